@@ -1,0 +1,234 @@
+/*
+ * sivf.h -- C ABI of the streaming IVF index for AMD Instinct MI355X (gfx950).
+ *
+ * The index keeps every inverted list in fixed-capacity device slabs and
+ * mutates them in place (Sec. 3 of "SIVF: GPU-Resident IVF Index for
+ * Streaming Vector Search"): insertion takes slabs from a device free stack
+ * (Sec. 3.1, Alg. 1; Sec. 3.2, Alg. 2), deletion finds an id's slot through an
+ * address translation table in O(1) (Sec. 3.4, Alg. 4), and search scans the
+ * slabs of the probed lists (Sec. 3.3, Alg. 3).  The operations follow the
+ * paper's statement of the problem: add_with_ids / remove_ids / search on a
+ * GPU-resident index (Sec. 1 and Sec. 4.1), plus the sliding-window step of
+ * Sec. 5.5.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Every function returns a sivf_status; nothing throws across the ABI.
+ *  - Memory: the library never allocates device memory.  The caller passes
+ *    one device workspace of sivf_workspace_bytes() bytes to sivf_create and
+ *    keeps it, and every input/output buffer, alive until the stream has
+ *    passed the call.  Pointers marked "device" are HIP device pointers;
+ *    pointers marked "host" are ordinary host memory.
+ *  - Streams: `stream` is a hipStream_t (NULL = the default stream).  Calls
+ *    enqueue work and return at once; only sivf_sync, sivf_stats, sivf_dump
+ *    and sivf_dump_info wait.
+ *  - Errors: argument errors are detected on the host and return
+ *    SIVF_ERR_ARG with nothing enqueued.  Errors that depend on device data
+ *    (pool exhausted, id out of range) are recorded in a device status word;
+ *    the failing call changes no index state, and sivf_sync returns the first
+ *    such error since the previous sivf_sync.
+ *  - Ids are int64 at the ABI and dense in [0, id_capacity) (Sec. 3, Data
+ *    Model).  Adding a live id replaces it (delete-then-insert, Sec. 3, Data
+ *    Model); if one add batch holds an id twice, the last occurrence wins.
+ *    Removing an absent id is a no-op (idempotent delete, Alg. 4, Theorem 3).
+ *  - Distances: squared L2 (ascending) or inner product (descending); ties
+ *    go to the smaller id.  Missing results are label -1 with +inf (L2) or
+ *    -inf (IP).  nprobe is clamped to nlist.
+ *  - Determinism: index membership and every search result are identical
+ *    to a sequential contiguous-array IVF with the same centroids; the slot
+ *    layout inside the slabs is implementation-defined.
+ *  - A handle is used from one host thread at a time.
+ */
+#ifndef SIVF_H
+#define SIVF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sivf_index sivf_index;
+
+typedef enum {
+    SIVF_OK = 0,
+    SIVF_ERR_ARG = -1,      /* invalid argument (host check; nothing enqueued)   */
+    SIVF_ERR_NOSPACE = -2,  /* slab pool too small for the add batch (Sec. 3.2)  */
+    SIVF_ERR_ID_RANGE = -3, /* an id outside [0, id_capacity)                    */
+    SIVF_ERR_DEVICE = -4,   /* a HIP runtime call failed                         */
+    SIVF_ERR_STATE = -5     /* handle unusable (e.g. after a device error)       */
+} sivf_status;
+
+typedef enum { SIVF_L2 = 0, SIVF_IP = 1 } sivf_metric;
+typedef enum { SIVF_F32 = 0, SIVF_BF16 = 1, SIVF_F16 = 2 } sivf_dtype;
+
+/* Index configuration.  The slab pool and id space are fixed at creation
+ * (the paper pre-allocates a monolithic slab pool, Sec. 3.1 and Sec. 4.1). */
+typedef struct {
+    int32_t dim;           /* vector dimension d, 1..2048                          */
+    int32_t nlist;         /* number of lists / centroids, 1..65536                */
+    int32_t slab_capacity; /* C, vectors per slab (Sec. 3.1): a power of two <= 128;
+                            * 32, 64 and 128 are the performance settings        */
+    int32_t metric;        /* sivf_metric                                          */
+    int32_t storage;       /* sivf_dtype of stored vectors; SIVF_F32 only          */
+    int32_t reserved0;     /* must be 0                                            */
+    int64_t num_slabs;     /* slabs in the pool, 1..2^31/C                         */
+    int64_t id_capacity;   /* N_max: ids are dense in [0, id_capacity), <= 2^31    */
+    int32_t max_batch;     /* largest n of one sivf_add / sivf_remove call         */
+    int32_t max_queries;   /* largest nq of one sivf_search call                   */
+    int32_t max_k;         /* largest k, 1..64                                     */
+    int32_t max_nprobe;    /* largest nprobe, 1..1024                              */
+} sivf_config;
+
+/* Bytes of device workspace the configuration needs (0 if invalid). */
+size_t sivf_workspace_bytes(const sivf_config *cfg);
+
+/* Create an index.  centroids: device, nlist x dim fp32 row-major, copied into
+ * the workspace (the caller may free its copy after the stream passes the
+ * call).  workspace: device, ws_bytes >= sivf_workspace_bytes(cfg), owned by
+ * the caller.  The pool starts empty with every slab on the free stack.
+ * Returns SIVF_ERR_ARG for an invalid configuration or a short workspace. */
+sivf_status sivf_create(const sivf_config *cfg, const float *centroids, void *workspace,
+                        size_t ws_bytes, void *stream, sivf_index **out);
+
+/* Release the host handle.  The workspace is not freed. */
+sivf_status sivf_destroy(sivf_index *ix);
+
+/* Insert n vectors (Sec. 3.2, Alg. 2; delete-then-insert for live ids, Sec. 3).
+ * x: device, n x dim fp32 row-major; ids: device, n int64.  Each vector goes
+ * to the list of its nearest centroid.  If any id is outside the id range
+ * (SIVF_ERR_ID_RANGE) or the final state would need more slabs than the pool
+ * holds (SIVF_ERR_NOSPACE), the whole batch is rejected and nothing changes.
+ * 0 <= n <= max_batch. */
+sivf_status sivf_add(sivf_index *ix, int64_t n, const float *x, const int64_t *ids, void *stream);
+
+/* Delete ids (Sec. 3.4, Alg. 4): O(1) address-table lookup per id; the hole
+ * is filled with the list's tail entry and emptied tail slabs return to the
+ * free stack.  ids: device, n int64; absent and repeated ids are no-ops.
+ * n_removed: device int64 scalar or NULL; receives the number of ids that
+ * were live.  An id outside the id range rejects the whole batch
+ * (SIVF_ERR_ID_RANGE).  0 <= n <= max_batch. */
+sivf_status sivf_remove(sivf_index *ix, int64_t n, const int64_t *ids, int64_t *n_removed,
+                        void *stream);
+
+/* k-nearest-neighbour search over the nprobe nearest lists (Sec. 3.3, Alg. 3).
+ * q: device, nq x dim fp32.  k: row stride of the outputs, 1 <= k <= max_k.
+ * k_per_query: device nq int32 in [0, k], or NULL (every query uses k).
+ * nprobe: 1..max_nprobe, used when nprobe_per_query is NULL; otherwise
+ * nprobe_per_query: device nq int32 in [1, max_nprobe].
+ * dist: device nq x k fp32; labels: device nq x k int64.  Row i holds query i's
+ * results best first; entries past the query's own k are padding.
+ * 0 <= nq <= max_queries. */
+sivf_status sivf_search(sivf_index *ix, int64_t nq, const float *q, int32_t k,
+                        const int32_t *k_per_query, int32_t nprobe,
+                        const int32_t *nprobe_per_query, float *dist, int64_t *labels,
+                        void *stream);
+
+/* One sliding-window step in the order of the paper's mixed loop
+ * (Sec. 5.5: insert, then search, then delete).  Any part with a zero count
+ * is skipped.  Same argument rules as the three calls. */
+typedef struct {
+    int64_t n_add;
+    const float *x;          /* device n_add x dim                  */
+    const int64_t *add_ids;  /* device n_add                        */
+    int64_t nq;
+    const float *q;          /* device nq x dim                     */
+    int32_t k, nprobe;
+    float *dist;             /* device nq x k                       */
+    int64_t *labels;         /* device nq x k                       */
+    int64_t n_remove;
+    const int64_t *remove_ids; /* device n_remove                   */
+    int64_t *n_removed;      /* device scalar or NULL               */
+} sivf_step_args;
+
+sivf_status sivf_step(sivf_index *ix, const sivf_step_args *args, void *stream);
+
+/* Nearest list of each vector (the coarse assignment used by sivf_add).
+ * x: device n x dim fp32; lists: device n int32.  n <= max(max_batch, max_queries). */
+sivf_status sivf_assign(sivf_index *ix, int64_t n, const float *x, int32_t *lists, void *stream);
+
+/* The nprobe nearest lists of each query (the probe set used by sivf_search),
+ * nearest first, ties to the smaller list id.  probes: device nq x nprobe
+ * int32; entries past nlist are -1.  1 <= nprobe <= max_nprobe. */
+sivf_status sivf_probe(sivf_index *ix, int64_t nq, const float *q, int32_t nprobe,
+                       int32_t *probes, void *stream);
+
+/* Approximate coarse distances of the quantizer's FP32 MFMA stage:
+ * |x|^2 + |c|^2 - 2 x.c (L2) or -x.c (IP), before the exact re-check.  For
+ * validating the error bound |approx - exact| <= (4d+16) 2^-24 (|x|+|c|)^2
+ * (L2) or (4d+16) 2^-24 |x||c| (IP) that the re-check relies on.
+ * x: device n x dim fp32; scores: device n x nlist fp32.
+ * n <= max(max_batch, max_queries). */
+sivf_status sivf_coarse_scores(sivf_index *ix, int64_t n, const float *x, float *scores, void *stream);
+
+/* Stored vectors of ids.  ids: device n int64; rows: device n x dim fp32.
+ * Rows of absent or out-of-range ids are filled with NaN.  n <= max_batch. */
+sivf_status sivf_get_rows(sivf_index *ix, int64_t n, const int64_t *ids, float *rows, void *stream);
+
+/* Wait for all work enqueued on the handle's streams; *device_status (may be
+ * NULL) receives the first data-dependent error since the previous
+ * sivf_sync (SIVF_OK if none), which is then cleared.  Returns
+ * SIVF_ERR_DEVICE if a HIP call fails. */
+sivf_status sivf_sync(sivf_index *ix, sivf_status *device_status);
+
+/* Counters (waits for the handle's last stream).  Any pointer may be NULL.
+ * live = entries in all lists; used = slabs held by lists; free = slabs on the
+ * free stack.  used + free = num_slabs. */
+sivf_status sivf_stats(sivf_index *ix, int64_t *live, int64_t *used_slabs, int64_t *free_slabs);
+
+/* Sizes of the arrays sivf_dump fills (waits for the handle's last stream). */
+typedef struct {
+    int64_t live;        /* sum of list lengths                          */
+    int64_t used_slabs;  /* sum over lists of ceil(len / C)              */
+    int64_t free_slabs;  /* entries on the free stack                    */
+    int64_t num_slabs;
+    int64_t id_capacity;
+    int32_t nlist;
+    int32_t slab_capacity;
+} sivf_dump_info;
+
+sivf_status sivf_dump_info_get(sivf_index *ix, sivf_dump_info *info);
+
+/* Copy the index state to host arrays for validation (waits).  All host.
+ *   list_len     [nlist]        entries per list
+ *   list_slabs   [used_slabs]   slab ids of list 0 by ordinal, then list 1, ...
+ *   ids_by_list  [live]         ids of list 0 by position, then list 1, ...
+ *   free_slabs   [free_slabs]   the free stack, bottom first
+ *   slab_owner   [num_slabs]    list holding each slab, or -1
+ *   slab_ordinal [num_slabs]    position of the slab in its list's table
+ *   att          [id_capacity]  address table: slab * C + slot, or 0xFFFFFFFF
+ * Any pointer may be NULL to skip that array. */
+sivf_status sivf_dump(sivf_index *ix, int32_t *list_len, int32_t *list_slabs, int64_t *ids_by_list,
+                      int32_t *free_slabs, int32_t *slab_owner, int32_t *slab_ordinal,
+                      uint32_t *att);
+
+/* Device time per operation class, from HIP events recorded on the call's
+ * stream around each class of work while profiling is on (in the spirit of
+ * the paper's GPU time breakdown, Sec. 5.6, Tab. 3). */
+typedef enum {
+    SIVF_PROF_ADD = 0,     /* a whole sivf_add                               */
+    SIVF_PROF_REMOVE = 1,  /* a whole sivf_remove                            */
+    SIVF_PROF_SEARCH = 2,  /* a whole sivf_search                            */
+    SIVF_PROF_COARSE = 3,  /* probe selection of a search (MFMA + re-check)  */
+    SIVF_PROF_SCAN = 4,    /* the slab scan kernel of a search               */
+    SIVF_PROF_MERGE = 5,   /* the final top-k merge kernel of a search       */
+    SIVF_PROF_KINDS = 6
+} sivf_prof_kind;
+
+/* Turn event recording on (on != 0) or off. */
+sivf_status sivf_profile_enable(sivf_index *ix, int on);
+
+/* Wait for the recorded work, then write the summed device milliseconds and
+ * the number of timed intervals of each class (host arrays of
+ * SIVF_PROF_KINDS entries, either may be NULL) and reset the sums. */
+sivf_status sivf_profile_read(sivf_index *ix, double *total_ms, int64_t *count);
+
+/* Static text for a status code. */
+const char *sivf_status_string(sivf_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SIVF_H */

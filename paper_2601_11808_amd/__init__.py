@@ -1,0 +1,333 @@
+"""Streaming IVF index on AMD Instinct MI355X: Python binding of libsivf.
+
+Thin ctypes layer over the C ABI in ``include/sivf.h``: every call marshals
+torch tensors (device memory) and a HIP stream into the library, whose HIP
+kernels do all of the work.  PyTorch only provides device memory and
+streams.  There is no fallback: if ``libsivf.so`` is not built, or no GPU is
+present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsivf.so")
+
+OK, ERR_ARG, ERR_NOSPACE, ERR_ID_RANGE, ERR_DEVICE, ERR_STATE = 0, -1, -2, -3, -4, -5
+L2, IP = 0, 1
+F32, BF16, F16 = 0, 1, 2
+
+
+class SivfError(RuntimeError):
+    def __init__(self, status, where=""):
+        self.status = status
+        super().__init__(f"{where}: {status_string(status)} ({status})")
+
+
+class SivfConfig(ct.Structure):
+    _fields_ = [("dim", ct.c_int32), ("nlist", ct.c_int32), ("slab_capacity", ct.c_int32),
+                ("metric", ct.c_int32), ("storage", ct.c_int32), ("reserved0", ct.c_int32),
+                ("num_slabs", ct.c_int64), ("id_capacity", ct.c_int64),
+                ("max_batch", ct.c_int32), ("max_queries", ct.c_int32),
+                ("max_k", ct.c_int32), ("max_nprobe", ct.c_int32)]
+
+
+class SivfStepArgs(ct.Structure):
+    _fields_ = [("n_add", ct.c_int64), ("x", ct.c_void_p), ("add_ids", ct.c_void_p),
+                ("nq", ct.c_int64), ("q", ct.c_void_p), ("k", ct.c_int32), ("nprobe", ct.c_int32),
+                ("dist", ct.c_void_p), ("labels", ct.c_void_p),
+                ("n_remove", ct.c_int64), ("remove_ids", ct.c_void_p), ("n_removed", ct.c_void_p)]
+
+
+class SivfDumpInfo(ct.Structure):
+    _fields_ = [("live", ct.c_int64), ("used_slabs", ct.c_int64), ("free_slabs", ct.c_int64),
+                ("num_slabs", ct.c_int64), ("id_capacity", ct.c_int64),
+                ("nlist", ct.c_int32), ("slab_capacity", ct.c_int32)]
+
+
+# (name, restype, argtypes) of every exported entry point of include/sivf.h
+_P, _I32, _I64 = ct.c_void_p, ct.c_int32, ct.c_int64
+SIGNATURES = [
+    ("sivf_workspace_bytes", ct.c_size_t, [ct.POINTER(SivfConfig)]),
+    ("sivf_create", ct.c_int, [ct.POINTER(SivfConfig), _P, _P, ct.c_size_t, _P, ct.POINTER(_P)]),
+    ("sivf_destroy", ct.c_int, [_P]),
+    ("sivf_add", ct.c_int, [_P, _I64, _P, _P, _P]),
+    ("sivf_remove", ct.c_int, [_P, _I64, _P, _P, _P]),
+    ("sivf_search", ct.c_int, [_P, _I64, _P, _I32, _P, _I32, _P, _P, _P, _P]),
+    ("sivf_step", ct.c_int, [_P, ct.POINTER(SivfStepArgs), _P]),
+    ("sivf_assign", ct.c_int, [_P, _I64, _P, _P, _P]),
+    ("sivf_probe", ct.c_int, [_P, _I64, _P, _I32, _P, _P]),
+    ("sivf_coarse_scores", ct.c_int, [_P, _I64, _P, _P, _P]),
+    ("sivf_get_rows", ct.c_int, [_P, _I64, _P, _P, _P]),
+    ("sivf_sync", ct.c_int, [_P, ct.POINTER(ct.c_int)]),
+    ("sivf_stats", ct.c_int, [_P, ct.POINTER(_I64), ct.POINTER(_I64), ct.POINTER(_I64)]),
+    ("sivf_dump_info_get", ct.c_int, [_P, ct.POINTER(SivfDumpInfo)]),
+    ("sivf_dump", ct.c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),
+    ("sivf_profile_enable", ct.c_int, [_P, ct.c_int]),
+    ("sivf_profile_read", ct.c_int, [_P, _P, _P]),
+    ("sivf_status_string", ct.c_char_p, [ct.c_int]),
+]
+
+_lib = None
+
+
+def lib():
+    """Load libsivf.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
+                               "python paper_2601_11808_amd/build.py")
+        L = ct.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def status_string(s: int) -> str:
+    try:
+        return lib().sivf_status_string(int(s)).decode()
+    except Exception:
+        return "status %d" % s
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev_tensor(a, dtype, device):
+    torch = _torch()
+    if isinstance(a, torch.Tensor):
+        t = a.to(device=device, dtype=dtype)
+    else:
+        t = torch.as_tensor(np.asarray(a), device=device).to(dtype)
+    return t.contiguous()
+
+
+def _ptr(t):
+    return ct.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _check(st, where):
+    if st != OK:
+        raise SivfError(st, where)
+
+
+class Index:
+    """A streaming IVF index held in one device workspace.
+
+    Arguments mirror ``sivf_config``; ``centroids`` is (nlist, dim) float32.
+    All methods take torch tensors (any device; they are moved to the index's
+    device) or numpy arrays and enqueue on ``stream`` (default: torch's
+    current stream of the device).
+    """
+
+    def __init__(self, dim, nlist, centroids, metric=L2, slab_capacity=64, num_slabs=1 << 16,
+                 id_capacity=1 << 20, max_batch=1 << 16, max_queries=1 << 14, max_k=64,
+                 max_nprobe=256, storage=F32, device="cuda:0", stream=None):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device is available")
+        self.device = torch.device(device)
+        self.cfg = SivfConfig(dim=dim, nlist=nlist, slab_capacity=slab_capacity, metric=metric,
+                              storage=storage, reserved0=0, num_slabs=num_slabs, id_capacity=id_capacity,
+                              max_batch=max_batch, max_queries=max_queries, max_k=max_k,
+                              max_nprobe=max_nprobe)
+        self.dim, self.nlist, self.metric, self.C = dim, nlist, metric, slab_capacity
+        nbytes = lib().sivf_workspace_bytes(ct.byref(self.cfg))
+        if nbytes == 0:
+            raise SivfError(ERR_ARG, "sivf_workspace_bytes (invalid configuration)")
+        self.workspace_bytes = nbytes
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        cent = _dev_tensor(centroids, torch.float32, self.device)
+        assert tuple(cent.shape) == (nlist, dim)
+        h = ct.c_void_p()
+        _check(lib().sivf_create(ct.byref(self.cfg), _ptr(cent), _ptr(self.workspace), nbytes,
+                                 self._stream(stream), ct.byref(h)), "sivf_create")
+        self._h = h
+        self._keep = [cent]
+        self._stream(stream)
+        self.sync()          # centroids copied: the caller's tensor may go
+
+    # -- helpers ---------------------------------------------------------
+    def _stream(self, stream):
+        torch = _torch()
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        return ct.c_void_p(s.cuda_stream)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().sivf_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- operations ------------------------------------------------------
+    def add(self, x, ids, stream=None):
+        torch = _torch()
+        x = _dev_tensor(x, torch.float32, self.device).reshape(-1, self.dim)
+        ids = _dev_tensor(ids, torch.int64, self.device).reshape(-1)
+        assert ids.shape[0] == x.shape[0]
+        _check(lib().sivf_add(self._h, x.shape[0], _ptr(x), _ptr(ids), self._stream(stream)), "sivf_add")
+        self._keep = [x, ids]
+        return self
+
+    def remove(self, ids, stream=None):
+        """Returns a device int64 scalar tensor with the number removed."""
+        torch = _torch()
+        ids = _dev_tensor(ids, torch.int64, self.device).reshape(-1)
+        nrem = torch.zeros(1, dtype=torch.int64, device=self.device)
+        _check(lib().sivf_remove(self._h, ids.shape[0], _ptr(ids), _ptr(nrem), self._stream(stream)),
+               "sivf_remove")
+        self._keep = [ids]
+        return nrem
+
+    def search(self, q, k, nprobe=1, k_per_query=None, nprobe_per_query=None, stream=None, out=None):
+        torch = _torch()
+        q = _dev_tensor(q, torch.float32, self.device).reshape(-1, self.dim)
+        nq = q.shape[0]
+        kpq = None if k_per_query is None else _dev_tensor(k_per_query, torch.int32, self.device)
+        npq = None if nprobe_per_query is None else _dev_tensor(nprobe_per_query, torch.int32, self.device)
+        if out is None:
+            dist = torch.empty((nq, k), dtype=torch.float32, device=self.device)
+            lab = torch.empty((nq, k), dtype=torch.int64, device=self.device)
+        else:
+            dist, lab = out
+        _check(lib().sivf_search(self._h, nq, _ptr(q), k, _ptr(kpq), nprobe, _ptr(npq), _ptr(dist), _ptr(lab),
+                                 self._stream(stream)), "sivf_search")
+        self._keep = [q, kpq, npq]
+        return dist, lab
+
+    def step(self, x=None, add_ids=None, q=None, k=10, nprobe=1, remove_ids=None, stream=None, out=None):
+        """add -> search -> remove; returns (dist, labels, n_removed)."""
+        torch = _torch()
+        a = SivfStepArgs()
+        keep = []
+        if x is not None:
+            x = _dev_tensor(x, torch.float32, self.device).reshape(-1, self.dim)
+            add_ids = _dev_tensor(add_ids, torch.int64, self.device).reshape(-1)
+            a.n_add, a.x, a.add_ids = x.shape[0], x.data_ptr(), add_ids.data_ptr()
+            keep += [x, add_ids]
+        dist = lab = None
+        if q is not None:
+            q = _dev_tensor(q, torch.float32, self.device).reshape(-1, self.dim)
+            if out is None:
+                dist = torch.empty((q.shape[0], k), dtype=torch.float32, device=self.device)
+                lab = torch.empty((q.shape[0], k), dtype=torch.int64, device=self.device)
+            else:
+                dist, lab = out
+            a.nq, a.q, a.k, a.nprobe = q.shape[0], q.data_ptr(), k, nprobe
+            a.dist, a.labels = dist.data_ptr(), lab.data_ptr()
+            keep += [q]
+        nrem = torch.zeros(1, dtype=torch.int64, device=self.device)
+        if remove_ids is not None:
+            remove_ids = _dev_tensor(remove_ids, torch.int64, self.device).reshape(-1)
+            a.n_remove, a.remove_ids = remove_ids.shape[0], remove_ids.data_ptr()
+            keep += [remove_ids]
+        a.n_removed = nrem.data_ptr()
+        _check(lib().sivf_step(self._h, ct.byref(a), self._stream(stream)), "sivf_step")
+        self._keep = keep
+        return dist, lab, nrem
+
+    def assign(self, x, stream=None):
+        torch = _torch()
+        x = _dev_tensor(x, torch.float32, self.device).reshape(-1, self.dim)
+        out = torch.empty(x.shape[0], dtype=torch.int32, device=self.device)
+        _check(lib().sivf_assign(self._h, x.shape[0], _ptr(x), _ptr(out), self._stream(stream)), "sivf_assign")
+        self._keep = [x]
+        return out
+
+    def probe(self, q, nprobe, stream=None):
+        torch = _torch()
+        q = _dev_tensor(q, torch.float32, self.device).reshape(-1, self.dim)
+        out = torch.empty((q.shape[0], nprobe), dtype=torch.int32, device=self.device)
+        _check(lib().sivf_probe(self._h, q.shape[0], _ptr(q), nprobe, _ptr(out), self._stream(stream)),
+               "sivf_probe")
+        self._keep = [q]
+        return out
+
+    def coarse_scores(self, x, stream=None):
+        torch = _torch()
+        x = _dev_tensor(x, torch.float32, self.device).reshape(-1, self.dim)
+        out = torch.empty((x.shape[0], self.nlist), dtype=torch.float32, device=self.device)
+        _check(lib().sivf_coarse_scores(self._h, x.shape[0], _ptr(x), _ptr(out), self._stream(stream)),
+               "sivf_coarse_scores")
+        self._keep = [x]
+        return out
+
+    def get_rows(self, ids, stream=None):
+        torch = _torch()
+        ids = _dev_tensor(ids, torch.int64, self.device).reshape(-1)
+        out = torch.empty((ids.shape[0], self.dim), dtype=torch.float32, device=self.device)
+        _check(lib().sivf_get_rows(self._h, ids.shape[0], _ptr(ids), _ptr(out), self._stream(stream)),
+               "sivf_get_rows")
+        self._keep = [ids]
+        return out
+
+    def sync(self) -> int:
+        """Wait; returns the first device-side status since the last sync."""
+        st = ct.c_int(0)
+        _check(lib().sivf_sync(self._h, ct.byref(st)), "sivf_sync")
+        return st.value
+
+    def check(self):
+        """sync() and raise SivfError on a device-side failure."""
+        st = self.sync()
+        if st != OK:
+            raise SivfError(st, "device")
+
+    def stats(self):
+        a, b, c = ct.c_int64(), ct.c_int64(), ct.c_int64()
+        _check(lib().sivf_stats(self._h, ct.byref(a), ct.byref(b), ct.byref(c)), "sivf_stats")
+        return {"live": a.value, "used_slabs": b.value, "free_slabs": c.value}
+
+    PROF_KINDS = ("add", "remove", "search", "coarse", "scan", "merge")
+
+    def profile(self, on=True):
+        _check(lib().sivf_profile_enable(self._h, 1 if on else 0), "sivf_profile_enable")
+
+    def profile_read(self):
+        """{class: (total device ms, intervals)} since the last read (waits)."""
+        ms = (ct.c_double * len(self.PROF_KINDS))()
+        cnt = (ct.c_int64 * len(self.PROF_KINDS))()
+        _check(lib().sivf_profile_read(self._h, ct.cast(ms, ct.c_void_p), ct.cast(cnt, ct.c_void_p)),
+               "sivf_profile_read")
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(self.PROF_KINDS)}
+
+    def dump(self):
+        """Host copy of the index state (numpy arrays), for validation."""
+        info = SivfDumpInfo()
+        _check(lib().sivf_dump_info_get(self._h, ct.byref(info)), "sivf_dump_info_get")
+        out = {
+            "list_len": np.empty(info.nlist, np.int32),
+            "list_slabs": np.empty(info.used_slabs, np.int32),
+            "ids_by_list": np.empty(info.live, np.int64),
+            "free_slabs": np.empty(info.free_slabs, np.int32),
+            "slab_owner": np.empty(info.num_slabs, np.int32),
+            "slab_ordinal": np.empty(info.num_slabs, np.int32),
+            "att": np.empty(info.id_capacity, np.uint32),
+        }
+        c = lambda a: a.ctypes.data_as(ct.c_void_p)
+        _check(lib().sivf_dump(self._h, c(out["list_len"]), c(out["list_slabs"]), c(out["ids_by_list"]),
+                               c(out["free_slabs"]), c(out["slab_owner"]), c(out["slab_ordinal"]),
+                               c(out["att"])), "sivf_dump")
+        out["info"] = {k: getattr(info, k) for k, _ in SivfDumpInfo._fields_}
+        return out
+
+    def membership(self):
+        """{list id: sorted id array} for non-empty lists (from a dump)."""
+        d = self.dump()
+        offs = np.concatenate([[0], np.cumsum(d["list_len"].astype(np.int64))])
+        return {l: np.sort(d["ids_by_list"][offs[l]:offs[l + 1]]) for l in range(self.nlist)
+                if d["list_len"][l] > 0}

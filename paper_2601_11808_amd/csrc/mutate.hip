@@ -1,0 +1,404 @@
+// In-place mutation of the slab-resident inverted lists.
+//
+// Insert (the paper's ingestion, Sec. 3.2 / Alg. 2, re-designed as a batch):
+//   prepare  validate ids, elect the last occurrence of each id in the batch
+//   count    per-list counts and ranks with wave-aggregated atomics (lanes of
+//            a wave that target the same list share one atomic) -- every
+//            vector gets a distinct position without a CAS retry loop
+//   admit    whole-batch check that the final state fits in the pool; else
+//            NOSPACE and no state change (fail-fast, Sec. 3.2)
+//   [delete  live ids of the batch are deleted first: delete-then-insert, Sec. 3]
+//   alloc    per list: slabs needed = ceil(new_len/C) - ceil(len/C); one
+//            atomic per block of 256 lists pops them from the free stack
+//            (the stack of Sec. 3.1 / Alg. 1), then the list tables are
+//            extended in parallel
+//   scatter  payload, id and address-table entry of every vector
+//
+// Delete (the paper's eviction, Sec. 3.4 / Alg. 4, with compaction instead of
+// a validity bitmap): the address table gives each id's slot in O(1); the
+// deleted set D of a list with n entries leaves n' = n - |D| entries; holes
+// below n' are refilled with the surviving entries of the tail window
+// [n', n), so the list stays dense, and the slabs past ceil(n'/C) return to
+// the free stack.  An id is deleted by exactly one thread: the one whose
+// atomic exchange on the address table sees it live (idempotent delete,
+// Theorem 3).
+#include "sivf_launch.h"
+
+namespace sivf {
+
+__device__ __forceinline__ int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+// ------------------------------------------------------------------ insert
+
+__global__ __launch_bounds__(256) void k_add_prepare(Dev S, int n, const int64_t *__restrict__ ids, uint32_t seq) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const int64_t u = ids[i];
+    if (u < 0 || u >= S.id_capacity)
+        fail_call(S.ctl, -3, seq);
+    else
+        atomicMax(&S.mark[u], i);
+}
+
+__global__ __launch_bounds__(256) void k_add_count(Dev S, int n, const int64_t *__restrict__ ids,
+                                                   const int32_t *__restrict__ assign, int32_t *__restrict__ rank,
+                                                   uint32_t seq) {
+    if (call_failed(S.ctl, seq)) return;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const bool active = i < n;
+    const int64_t u = active ? ids[i] : 0;
+    const bool win = active && S.mark[u] == i;
+    const int l = win ? assign[i] : 0;
+    const int r = wave_agg_inc(S.l_acnt, l, win);
+    if (active) rank[i] = win ? r : -1;
+    const uint32_t g = win ? S.att[u] : INVALID;
+    const bool live = g != INVALID;
+    const int lo = live ? S.sowner[g / (uint32_t)S.C] : 0;
+    wave_agg_inc(S.l_prem, lo, live);
+    if (ballot(live) && lane_id() == 0) atomicExch(&S.ctl[CTL_UPSERT], (int)seq);
+}
+
+// One block: does the final state fit in the pool?
+__global__ __launch_bounds__(1024) void k_add_admit(Dev S, uint32_t seq) {
+    __shared__ long long sred[16];
+    if (call_failed(S.ctl, seq)) return;
+    const int tid = threadIdx.x;
+    long long need = 0;
+    for (int l = tid; l < S.nlist; l += 1024) need += cdiv(S.len[l] - S.l_prem[l] + S.l_acnt[l], S.C);
+    for (int o = 32; o > 0; o >>= 1) need += __shfl_xor(need, o);
+    if (lane_id() == 0) sred[tid >> 6] = need;
+    __syncthreads();
+    long long tot = 0;
+    for (int w = 0; w < 16; w++) tot += sred[w];
+    const bool reject = tot > S.num_slabs;
+    if (reject && tid == 0) fail_call(S.ctl, -2, seq);
+    for (int l = tid; l < S.nlist; l += 1024) {
+        S.l_prem[l] = 0;
+        if (reject) S.l_acnt[l] = 0;
+    }
+}
+
+// Find the entry i of a block-local exclusive scan es[0..255] whose range
+// [es[i], es[i] + cnt[i]) holds s: the last index with es[i] <= s.
+__device__ __forceinline__ int owner_of(const int *es, int s) {
+    int lo = 0, hi = 255;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (es[mid] <= s)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void k_add_alloc(Dev S, uint32_t seq) {
+    __shared__ int s_es[256], s_nso[256], sbuf[4], s_base[2];
+    if (call_failed(S.ctl, seq)) return;
+    const int tid = threadIdx.x;
+    const int l = blockIdx.x * 256 + tid;
+    const bool valid = l < S.nlist;
+    const int cnt = valid ? S.l_acnt[l] : 0;
+    const int oldlen = valid ? S.len[l] : 0;
+    const int newlen = oldlen + cnt;
+    const int nso = cdiv(oldlen, S.C), nsn = cdiv(newlen, S.C);
+    const int pgo = cdiv(nso, PAGE), pgn = cdiv(nsn, PAGE);
+    int tot_s, tot_p;
+    const int es = block_excl_scan<256>(nsn - nso, sbuf, &tot_s);
+    const int ep = block_excl_scan<256>(pgn - pgo, sbuf, &tot_p);
+    if (tid == 0) {
+        s_base[0] = tot_s ? atomicSub(&S.ctl[CTL_SLAB_TOP], tot_s) - tot_s : 0;
+        s_base[1] = tot_p ? atomicSub(&S.ctl[CTL_PAGE_TOP], tot_p) - tot_p : 0;
+    }
+    s_es[tid] = es;
+    s_nso[tid] = nso;
+    __syncthreads();
+    if (cnt > 0) {
+        S.l_base[l] = oldlen;
+        S.len[l] = newlen;
+        S.l_acnt[l] = 0;
+        for (int j = 0; j < pgn - pgo; j++)
+            S.dir[(int64_t)l * S.dir_cap + pgo + j] = S.free_pages[s_base[1] + ep + j];
+    }
+    __syncthreads();
+    for (int s = tid; s < tot_s; s += 256) {
+        const int i = owner_of(s_es, s);
+        const int li = blockIdx.x * 256 + i;
+        const int ord = s_nso[i] + (s - s_es[i]);
+        const int slab = S.free_slabs[s_base[0] + s];
+        const int page = S.dir[(int64_t)li * S.dir_cap + ord / PAGE];
+        S.pages[(int64_t)page * PAGE + ord % PAGE] = slab;
+        S.sowner[slab] = li;
+        S.sord[slab] = ord;
+    }
+}
+
+// 16 lanes per vector; lane sub copies dimension chunks sub, sub+16, ...
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_add_scatter(Dev S, int n, const float *__restrict__ x,
+                                                     const int64_t *__restrict__ ids,
+                                                     const int32_t *__restrict__ assign,
+                                                     const int32_t *__restrict__ rank, uint32_t seq) {
+    if (call_failed(S.ctl, seq)) return;
+    const int gid = blockIdx.x * 256 + threadIdx.x;
+    const int i = gid >> 4, sub = gid & 15;
+    if (i >= n) return;
+    const int r = rank[i];
+    if (r < 0) return;
+    const int l = assign[i];
+    const int pos = S.l_base[l] + r;
+    const int slab = slab_of(S, l, pos / S.C);
+    const int slot = pos % S.C;
+    float4 *dst = S.data + (int64_t)slab * S.dp4 * S.C + slot;
+    const float *xr = x + (int64_t)i * S.d;
+    for (int c = sub; c < S.dp4; c += 16) {
+        float4 v;
+        if (VEC) {
+            v = reinterpret_cast<const float4 *>(xr)[c];
+        } else {
+            const int j = 4 * c;
+            v.x = j < S.d ? xr[j] : 0.f;
+            v.y = j + 1 < S.d ? xr[j + 1] : 0.f;
+            v.z = j + 2 < S.d ? xr[j + 2] : 0.f;
+            v.w = j + 3 < S.d ? xr[j + 3] : 0.f;
+        }
+        dst[(int64_t)c * S.C] = v;
+    }
+    if (sub == 0) {
+        const uint32_t g = (uint32_t)slab * (uint32_t)S.C + (uint32_t)slot;
+        const int64_t u = ids[i];
+        S.sids[g] = (uint32_t)u;
+        S.att[u] = g;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_add_cleanup(Dev S, int n, const int64_t *__restrict__ ids) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const int64_t u = ids[i];
+    if (u >= 0 && u < S.id_capacity) S.mark[u] = -1;
+}
+
+// ------------------------------------------------------------------ delete
+
+__device__ __forceinline__ bool rm_skip(const Dev &S, uint32_t seq, int mode) {
+    if (call_failed(S.ctl, seq)) return true;
+    return mode == 1 && S.ctl[CTL_UPSERT] != (int)seq;
+}
+
+__global__ __launch_bounds__(256) void k_rm_validate(Dev S, int n, const int64_t *__restrict__ ids, uint32_t seq) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const int64_t u = ids[i];
+    if (u < 0 || u >= S.id_capacity) fail_call(S.ctl, -3, seq);
+}
+
+__global__ __launch_bounds__(256) void k_rm_mark(Dev S, int n, const int64_t *__restrict__ ids,
+                                                 uint32_t *__restrict__ rec, uint32_t seq, int mode) {
+    if (rm_skip(S, seq, mode)) return;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const bool active = i < n;
+    const uint32_t g = active ? atomicExch(&S.att[ids[i]], INVALID) : INVALID;
+    const bool hit = g != INVALID;
+    int l = 0;
+    if (hit) {
+        S.sids[g] = INVALID;   // tombstone: this slot no longer holds a live entry
+        l = S.sowner[g / (uint32_t)S.C];
+    }
+    wave_agg_inc(S.l_m, l, hit);
+    if (active) rec[i] = g;
+}
+
+// One block: segment offsets of each list's survivor slots and new lengths.
+__global__ __launch_bounds__(1024) void k_rm_plan(Dev S, int64_t *n_removed, uint32_t seq, int mode) {
+    __shared__ int sbuf[16];
+    if (rm_skip(S, seq, mode)) {
+        if (n_removed && threadIdx.x == 0) *n_removed = 0;
+        return;
+    }
+    int carry = 0;
+    for (int base = 0; base < S.nlist; base += 1024) {
+        const int l = base + threadIdx.x;
+        const int m = l < S.nlist ? S.l_m[l] : 0;
+        int tot;
+        const int ex = block_excl_scan<1024>(m, sbuf, &tot);
+        if (l < S.nlist) {
+            S.l_off[l] = carry + ex;
+            S.l_newlen[l] = S.len[l] - m;
+            S.l_q[l] = 0;
+            S.l_s[l] = 0;
+            S.l_h[l] = 0;
+        }
+        carry += tot;
+    }
+    if (n_removed && threadIdx.x == 0) *n_removed = carry;
+}
+
+// Each deleted entry of list l inspects one position of the tail window
+// [n', n); positions still holding a live entry are the survivors to move.
+__global__ __launch_bounds__(256) void k_rm_survivors(Dev S, int n, const uint32_t *__restrict__ rec,
+                                                      int32_t *__restrict__ seg, uint32_t seq, int mode) {
+    if (rm_skip(S, seq, mode)) return;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const uint32_t g = i < n ? rec[i] : INVALID;
+    const bool hit = g != INVALID;
+    const int l = hit ? S.sowner[g / (uint32_t)S.C] : 0;
+    const int q = wave_agg_inc(S.l_q, l, hit);
+    bool surv = false;
+    uint32_t gt = 0;
+    if (hit) {
+        const int tp = S.l_newlen[l] + q;
+        const int slab = slab_of(S, l, tp / S.C);
+        gt = (uint32_t)slab * (uint32_t)S.C + (uint32_t)(tp % S.C);
+        surv = S.sids[gt] != INVALID;
+    }
+    const int r = wave_agg_inc(S.l_s, l, surv);
+    if (surv) seg[S.l_off[l] + r] = (int32_t)gt;
+}
+
+// Holes below n' take the survivors: the r-th hole of a list pairs with its
+// r-th survivor.  The payload copy of each move is done by the whole wave.
+__global__ __launch_bounds__(256) void k_rm_move(Dev S, int n, const uint32_t *__restrict__ rec,
+                                                 const int32_t *__restrict__ seg, uint32_t seq, int mode) {
+    if (rm_skip(S, seq, mode)) return;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const uint32_t g = i < n ? rec[i] : INVALID;
+    const bool hit = g != INVALID;
+    int l = 0;
+    bool hole = false;
+    if (hit) {
+        const uint32_t slab = g / (uint32_t)S.C;
+        l = S.sowner[slab];
+        const int pos = S.sord[slab] * S.C + (int)(g % (uint32_t)S.C);
+        hole = pos < S.l_newlen[l];
+    }
+    const int r = wave_agg_inc(S.l_h, l, hole);
+    const uint32_t src = hole ? (uint32_t)seg[S.l_off[l] + r] : 0u;
+    uint64_t mask = ballot(hole);
+    while (mask) {
+        const int j = __builtin_ctzll(mask);
+        mask &= mask - 1;
+        const uint32_t sg = (uint32_t)readlane_i((int)src, j);
+        const uint32_t dg = (uint32_t)readlane_i((int)g, j);
+        const float4 *sp = S.data + (int64_t)(sg / S.C) * S.dp4 * S.C + sg % S.C;
+        float4 *dp = S.data + (int64_t)(dg / S.C) * S.dp4 * S.C + dg % S.C;
+        for (int c = lane_id(); c < S.dp4; c += 64) dp[(int64_t)c * S.C] = sp[(int64_t)c * S.C];
+    }
+    if (hole) {
+        const uint32_t id = S.sids[src];
+        S.sids[g] = id;
+        S.att[id] = g;
+    }
+}
+
+// Per list: new length, and the tail slabs (and table pages) past the new
+// end go back to the free stacks.
+__global__ __launch_bounds__(256) void k_rm_finalize(Dev S, uint32_t seq, int mode) {
+    __shared__ int s_es[256], s_nsn[256], sbuf[4], s_base[2];
+    if (rm_skip(S, seq, mode)) return;
+    const int tid = threadIdx.x;
+    const int l = blockIdx.x * 256 + tid;
+    const bool valid = l < S.nlist;
+    const int m = valid ? S.l_m[l] : 0;
+    const int oldlen = valid ? S.len[l] : 0;
+    const int nl = oldlen - m;
+    const int nso = cdiv(oldlen, S.C), nsn = cdiv(nl, S.C);
+    const int pgo = cdiv(nso, PAGE), pgn = cdiv(nsn, PAGE);
+    int tot_s, tot_p;
+    const int es = block_excl_scan<256>(nso - nsn, sbuf, &tot_s);
+    const int ep = block_excl_scan<256>(pgo - pgn, sbuf, &tot_p);
+    if (tid == 0) {
+        s_base[0] = tot_s ? atomicAdd(&S.ctl[CTL_SLAB_TOP], tot_s) : 0;
+        s_base[1] = tot_p ? atomicAdd(&S.ctl[CTL_PAGE_TOP], tot_p) : 0;
+    }
+    s_es[tid] = es;
+    s_nsn[tid] = nsn;
+    __syncthreads();
+    for (int s = tid; s < tot_s; s += 256) {
+        const int i = owner_of(s_es, s);
+        const int li = blockIdx.x * 256 + i;
+        const int ord = s_nsn[i] + (s - s_es[i]);
+        const int slab = slab_of(S, li, ord);
+        S.free_slabs[s_base[0] + s] = slab;
+        S.sowner[slab] = -1;
+    }
+    __syncthreads();
+    if (m > 0) {
+        for (int j = 0; j < pgo - pgn; j++)
+            S.free_pages[s_base[1] + ep + j] = S.dir[(int64_t)l * S.dir_cap + pgn + j];
+        S.len[l] = nl;
+        S.l_m[l] = 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_get_rows(Dev S, int n, const int64_t *__restrict__ ids,
+                                                  float *__restrict__ rows) {
+    const int gid = blockIdx.x * 256 + threadIdx.x;
+    const int i = gid >> 4, sub = gid & 15;
+    if (i >= n) return;
+    const int64_t u = ids[i];
+    const uint32_t g = (u >= 0 && u < S.id_capacity) ? S.att[u] : INVALID;
+    float *out = rows + (int64_t)i * S.d;
+    if (g == INVALID) {
+        for (int j = sub; j < S.d; j += 16) out[j] = __int_as_float(0x7FC00000);
+        return;
+    }
+    const float4 *src = S.data + (int64_t)(g / S.C) * S.dp4 * S.C + g % S.C;
+    for (int c = sub; c < S.dp4; c += 16) {
+        const float4 v = src[(int64_t)c * S.C];
+        const float e[4] = {v.x, v.y, v.z, v.w};
+        for (int t = 0; t < 4; t++)
+            if (4 * c + t < S.d) out[4 * c + t] = e[t];
+    }
+}
+
+// ------------------------------------------------------------------ launch
+
+static unsigned blocks(int64_t threads, int per = 256) { return (unsigned)((threads + per - 1) / per); }
+
+void launch_add_prepare(hipStream_t st, const Dev &S, int n, const int64_t *ids, uint32_t seq) {
+    hipLaunchKernelGGL(k_add_prepare, dim3(blocks(n)), dim3(256), 0, st, S, n, ids, seq);
+}
+
+void launch_add_count(hipStream_t st, const Dev &S, int n, const int64_t *ids, const Batch &B, uint32_t seq) {
+    hipLaunchKernelGGL(k_add_count, dim3(blocks(n)), dim3(256), 0, st, S, n, ids, B.assign, B.rank, seq);
+}
+
+void launch_add_admit(hipStream_t st, const Dev &S, uint32_t seq) {
+    hipLaunchKernelGGL(k_add_admit, dim3(1), dim3(1024), 0, st, S, seq);
+}
+
+void launch_add_alloc(hipStream_t st, const Dev &S, uint32_t seq) {
+    hipLaunchKernelGGL(k_add_alloc, dim3(blocks(S.nlist)), dim3(256), 0, st, S, seq);
+}
+
+void launch_add_scatter(hipStream_t st, const Dev &S, int n, const float *x, const int64_t *ids, const Batch &B,
+                        uint32_t seq) {
+    const bool vec = (S.d % 4 == 0) && (((uintptr_t)x & 15) == 0);
+    if (vec)
+        hipLaunchKernelGGL(k_add_scatter<true>, dim3(blocks((int64_t)n * 16)), dim3(256), 0, st, S, n, x, ids,
+                           B.assign, B.rank, seq);
+    else
+        hipLaunchKernelGGL(k_add_scatter<false>, dim3(blocks((int64_t)n * 16)), dim3(256), 0, st, S, n, x, ids,
+                           B.assign, B.rank, seq);
+}
+
+void launch_add_cleanup(hipStream_t st, const Dev &S, int n, const int64_t *ids) {
+    hipLaunchKernelGGL(k_add_cleanup, dim3(blocks(n)), dim3(256), 0, st, S, n, ids);
+}
+
+void launch_remove(hipStream_t st, const Dev &S, int n, const int64_t *ids, int64_t *n_removed, const Batch &B,
+                   uint32_t seq, int mode) {
+    if (mode == 0) hipLaunchKernelGGL(k_rm_validate, dim3(blocks(n)), dim3(256), 0, st, S, n, ids, seq);
+    hipLaunchKernelGGL(k_rm_mark, dim3(blocks(n)), dim3(256), 0, st, S, n, ids, B.rec, seq, mode);
+    hipLaunchKernelGGL(k_rm_plan, dim3(1), dim3(1024), 0, st, S, n_removed, seq, mode);
+    hipLaunchKernelGGL(k_rm_survivors, dim3(blocks(n)), dim3(256), 0, st, S, n, B.rec, B.seg, seq, mode);
+    hipLaunchKernelGGL(k_rm_move, dim3(blocks(n)), dim3(256), 0, st, S, n, B.rec, B.seg, seq, mode);
+    hipLaunchKernelGGL(k_rm_finalize, dim3(blocks(S.nlist)), dim3(256), 0, st, S, seq, mode);
+}
+
+void launch_get_rows(hipStream_t st, const Dev &S, int n, const int64_t *ids, float *rows) {
+    hipLaunchKernelGGL(k_get_rows, dim3(blocks((int64_t)n * 16)), dim3(256), 0, st, S, n, ids, rows);
+}
+
+}  // namespace sivf

@@ -1,0 +1,311 @@
+// Search over the slab-resident lists (the paper's Sec. 3.3 / Alg. 3,
+// re-designed for wave64 and query batches).
+//
+// The paper gives one warp to one query and walks each probed chain per
+// query.  Here the (query, probed list) pairs of a whole batch are inverted
+// to list-major work items: an item is one list and a tile of up to T queries
+// that probe it.  One wave scans the list's slabs once per item (lane <->
+// slot, 64 slots per step, coalesced 1 KiB loads), computing the canonical
+// FP32 distance of every slot to all T queries of the tile, which sit in LDS.
+// Each query keeps its best kcap (distance, id) keys sorted across the lanes
+// of the wave; candidates below the current k-th key are inserted with
+// ballots and lane shifts.  A final kernel merges the per-list partial
+// results of each query.
+//
+//   k_inv_count   rank of each (query, probe) pair within its list
+//   k_inv_plan    per-list pair offsets; work items (list, tile)
+//   k_inv_scatter pair ids grouped by list
+//   k_scan        one wave per item: distances + per-query top-kcap
+//   k_merge       one wave per query: kcap-way merge of its probe partials
+#include "sivf_launch.h"
+
+namespace sivf {
+
+__device__ __forceinline__ int cdiv_s(int a, int b) { return (a + b - 1) / b; }
+
+__global__ __launch_bounds__(256) void k_inv_count(Dev S, int npairs, const int32_t *__restrict__ probes,
+                                                   int32_t *__restrict__ pair_rank) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    const bool active = p < npairs;
+    const int l = active ? probes[p] : -1;
+    const bool act = l >= 0;
+    const int r = wave_agg_inc(S.l_qc, act ? l : 0, act);
+    if (active) pair_rank[p] = act ? r : -1;
+}
+
+__global__ __launch_bounds__(1024) void k_inv_plan(Dev S, int T, int32_t *__restrict__ item_list,
+                                                   int32_t *__restrict__ item_tile) {
+    __shared__ int sbuf[16];
+    int carry_p = 0, carry_i = 0;
+    for (int base = 0; base < S.nlist; base += 1024) {
+        const int l = base + threadIdx.x;
+        const bool valid = l < S.nlist;
+        const int qc = valid ? S.l_qc[l] : 0;
+        const int ln = valid ? S.len[l] : 0;
+        const int nt = (qc > 0 && ln > 0) ? cdiv_s(qc, T) : 0;
+        int tp, ti;
+        const int ep = block_excl_scan<1024>(qc, sbuf, &tp);
+        const int ei = block_excl_scan<1024>(nt, sbuf, &ti);
+        if (valid) {
+            S.l_qoff[l] = carry_p + ep;
+            S.l_qcs[l] = qc;
+            S.l_qc[l] = 0;
+            for (int t = 0; t < nt; t++) {
+                item_list[carry_i + ei + t] = l;
+                item_tile[carry_i + ei + t] = t;
+            }
+        }
+        carry_p += tp;
+        carry_i += ti;
+    }
+    if (threadIdx.x == 0) S.ctl[CTL_NITEMS] = carry_i;
+}
+
+__global__ __launch_bounds__(256) void k_inv_scatter(Dev S, int npairs, const int32_t *__restrict__ probes,
+                                                     const int32_t *__restrict__ pair_rank,
+                                                     int32_t *__restrict__ list_pairs) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= npairs) return;
+    const int r = pair_rank[p];
+    if (r < 0) return;
+    list_pairs[S.l_qoff[probes[p]] + r] = p;
+}
+
+__device__ __forceinline__ uint64_t shfl_up1_u64(uint64_t v) {
+    const int lo = __shfl_up((int)(uint32_t)v, 1);
+    const int hi = __shfl_up((int)(uint32_t)(v >> 32), 1);
+    return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+// Insert the keys of all lanes that beat the current kcap-th best into the
+// sorted list held by lanes 0..kcap-1 (lanes >= kcap hold ~0).
+__device__ __forceinline__ void topk_insert(uint64_t &top, uint64_t key, int kcap) {
+    uint64_t thr = readlane_u64(top, kcap - 1);
+    uint64_t mask = ballot(key < thr);
+    const int ln = lane_id();
+    while (mask) {
+        const int src = __builtin_ctzll(mask);
+        mask &= mask - 1;
+        const uint64_t ck = readlane_u64(key, src);
+        if (ck >= thr) continue;
+        const int pos = __builtin_popcountll(ballot(top < ck));
+        const uint64_t up = shfl_up1_u64(top);
+        top = ln < pos ? top : (ln == pos ? ck : up);
+        if (ln >= kcap) top = ~0ull;
+        thr = readlane_u64(top, kcap - 1);
+    }
+}
+
+template <int T, int METRIC>
+__global__ __launch_bounds__(64) void k_scan(Dev S, const int32_t *__restrict__ item_list,
+                                             const int32_t *__restrict__ item_tile,
+                                             const int32_t *__restrict__ list_pairs, const float *__restrict__ q,
+                                             int np_stride, int kcap, uint64_t *__restrict__ partials,
+                                             int per_xcd) {
+    extern __shared__ float4 sq[];   // [T][dp4]
+    __shared__ int spair[T];
+    // Consecutive items (tiles of the same list) go to the same XCD, so a
+    // list's slabs are fetched once into that XCD's L2 and reused.
+    const int w = blockIdx.x;
+    const int item = (w & 7) * per_xcd + (w >> 3);
+    if (item >= S.ctl[CTL_NITEMS]) return;
+    const int lane = threadIdx.x;
+    const int l = item_list[item], tile = item_tile[item];
+    const int nt = min(T, S.l_qcs[l] - tile * T);
+    const int dp4 = S.dp4, C = S.C, d = S.d;
+    if (lane < T) spair[lane] = lane < nt ? list_pairs[S.l_qoff[l] + tile * T + lane] : -1;
+    __syncthreads();
+    for (int t = 0; t < T; t++) {
+        const int pr = spair[t];
+        const float *qr = q + (int64_t)(pr < 0 ? 0 : pr / np_stride) * d;
+        for (int c = lane; c < dp4; c += 64) {
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (pr >= 0) {
+                const int j = 4 * c;
+                v.x = j < d ? qr[j] : 0.f;
+                v.y = j + 1 < d ? qr[j + 1] : 0.f;
+                v.z = j + 2 < d ? qr[j + 2] : 0.f;
+                v.w = j + 3 < d ? qr[j + 3] : 0.f;
+            }
+            sq[t * dp4 + c] = v;
+        }
+    }
+    __syncthreads();
+
+    uint64_t top[T];
+#pragma unroll
+    for (int t = 0; t < T; t++) top[t] = ~0ull;
+    const int len = S.len[l];
+    const int nslab = cdiv_s(len, C);
+    int wbase = -(1 << 30), wslab = 0;   // lane j holds the slab of ordinal wbase + j
+    for (int base = 0; base < len; base += 64) {
+        const int p = base + lane;
+        const bool valid = p < len;
+        const int pc = valid ? p : len - 1;
+        const int last_ord = (min(base + 63, len - 1)) / C;
+        if (last_ord >= wbase + 64) {
+            wbase = base / C;
+            wslab = (wbase + lane < nslab) ? slab_of(S, l, wbase + lane) : 0;
+        }
+        const int slab = __shfl(wslab, pc / C - wbase);
+        const int slot = pc % C;
+        const float4 *xp = S.data + (int64_t)slab * dp4 * C + slot;
+        float acc[T];
+#pragma unroll
+        for (int t = 0; t < T; t++) acc[t] = 0.f;
+#pragma unroll 2
+        for (int c = 0; c < dp4; c++) {
+            const float4 xv = xp[(int64_t)c * C];
+#pragma unroll
+            for (int t = 0; t < T; t++) {
+                const float4 qv = sq[t * dp4 + c];
+                if (METRIC == 0) {
+                    float e;
+                    e = qv.x - xv.x;
+                    acc[t] = __builtin_fmaf(e, e, acc[t]);
+                    e = qv.y - xv.y;
+                    acc[t] = __builtin_fmaf(e, e, acc[t]);
+                    e = qv.z - xv.z;
+                    acc[t] = __builtin_fmaf(e, e, acc[t]);
+                    e = qv.w - xv.w;
+                    acc[t] = __builtin_fmaf(e, e, acc[t]);
+                } else {
+                    acc[t] = __builtin_fmaf(qv.x, xv.x, acc[t]);
+                    acc[t] = __builtin_fmaf(qv.y, xv.y, acc[t]);
+                    acc[t] = __builtin_fmaf(qv.z, xv.z, acc[t]);
+                    acc[t] = __builtin_fmaf(qv.w, xv.w, acc[t]);
+                }
+            }
+        }
+        const uint32_t id = S.sids[(int64_t)slab * C + slot];
+#pragma unroll
+        for (int t = 0; t < T; t++) {
+            if (t < nt) {
+                const uint64_t key = valid ? make_key(acc[t], id, METRIC) : ~0ull;
+                topk_insert(top[t], key, kcap);
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < T; t++)
+        if (t < nt && lane < kcap) partials[(int64_t)spair[t] * kcap + lane] = top[t];
+}
+
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
+    const int lo = __shfl_xor((int)(uint32_t)v, m);
+    const int hi = __shfl_xor((int)(uint32_t)(v >> 32), m);
+    return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+// One wave per query: repeatedly take the smallest head among the query's
+// probe partial lists (each sorted, kcap long).
+__global__ __launch_bounds__(256) void k_merge(Dev S, int nq, int np_stride, const int32_t *__restrict__ probes,
+                                               const uint64_t *__restrict__ partials, int kcap, int k,
+                                               const int32_t *__restrict__ kpq, float *__restrict__ dist,
+                                               int64_t *__restrict__ labels) {
+    __shared__ unsigned char heads[4][1024];
+    const int w = threadIdx.x >> 6, lane = lane_id();
+    const int qi = blockIdx.x * 4 + w;
+    if (qi >= nq) return;
+    int kq = kpq ? kpq[qi] : k;
+    kq = kq < 0 ? 0 : (kq > k ? k : kq);
+    const int32_t *prow = probes + (int64_t)qi * np_stride;
+    const uint64_t *part = partials + (int64_t)qi * np_stride * kcap;
+    auto head_key = [&](int p) -> uint64_t {
+        const int l = prow[p];
+        if (l < 0 || S.len[l] == 0) return ~0ull;
+        const int h = heads[w][p];
+        return h < kcap ? part[(int64_t)p * kcap + h] : ~0ull;
+    };
+    uint64_t best = ~0ull;
+    int bestp = -1;
+    for (int p = lane; p < np_stride; p += 64) {
+        heads[w][p] = 0;
+        const uint64_t kk = head_key(p);
+        if (kk < best) {
+            best = kk;
+            bestp = p;
+        }
+    }
+    uint64_t res = ~0ull;
+    for (int r = 0; r < kq; r++) {
+        uint64_t m = best;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const uint64_t u = shfl_xor_u64(m, o);
+            m = u < m ? u : m;
+        }
+        if (m == ~0ull) break;
+        if (lane == r) res = m;
+        if (best == m) {
+            heads[w][bestp]++;
+            best = ~0ull;
+            bestp = -1;
+            for (int p = lane; p < np_stride; p += 64) {
+                const uint64_t kk = head_key(p);
+                if (kk < best) {
+                    best = kk;
+                    bestp = p;
+                }
+            }
+        }
+    }
+    if (lane < k) {
+        const int64_t o = (int64_t)qi * k + lane;
+        if (lane < kq && res != ~0ull) {
+            dist[o] = key_value(res, S.metric);
+            labels[o] = (int64_t)(uint32_t)res;
+        } else {
+            dist[o] = S.metric == 0 ? __int_as_float(0x7F800000) : __int_as_float((int)0xFF800000);
+            labels[o] = -1;
+        }
+    }
+}
+
+// Queries per tile: LDS holds T * ceil(d/4) * 16 bytes, kept within 32 KiB.
+int search_tile(int d) { return d <= 512 ? 16 : (d <= 1024 ? 8 : 4); }
+
+template <int T>
+static void launch_scan_t(hipStream_t st, const Dev &S, const SearchBufs &W, const float *q, int np_stride,
+                          int kcap, unsigned grid, int per_xcd) {
+    const size_t smem = (size_t)T * S.dp4 * sizeof(float4);
+    if (S.metric == 0)
+        hipLaunchKernelGGL((k_scan<T, 0>), dim3(grid), dim3(64), smem, st, S, W.item_list, W.item_tile,
+                           W.list_pairs, q, np_stride, kcap, W.partials, per_xcd);
+    else
+        hipLaunchKernelGGL((k_scan<T, 1>), dim3(grid), dim3(64), smem, st, S, W.item_list, W.item_tile,
+                           W.list_pairs, q, np_stride, kcap, W.partials, per_xcd);
+}
+
+void launch_search_plan(hipStream_t st, const Dev &S, const SearchBufs &W, int nq, int np_stride) {
+    const int npairs = nq * np_stride;
+    const unsigned pb = (unsigned)((npairs + 255) / 256);
+    hipLaunchKernelGGL(k_inv_count, dim3(pb), dim3(256), 0, st, S, npairs, W.probes, W.pair_rank);
+    hipLaunchKernelGGL(k_inv_plan, dim3(1), dim3(1024), 0, st, S, search_tile(S.d), W.item_list, W.item_tile);
+    hipLaunchKernelGGL(k_inv_scatter, dim3(pb), dim3(256), 0, st, S, npairs, W.probes, W.pair_rank,
+                       W.list_pairs);
+}
+
+void launch_search_scan(hipStream_t st, const Dev &S, const SearchBufs &W, int nq, const float *q, int np_stride,
+                        int kcap) {
+    const int npairs = nq * np_stride;
+    const int T = search_tile(S.d);
+    // items <= sum over lists of ceil(pairs_l / T) <= npairs / T + min(nlist, npairs)
+    const int64_t bound = (int64_t)npairs / T + (npairs < S.nlist ? npairs : S.nlist);
+    const int per_xcd = (int)((bound + 7) / 8);
+    const unsigned grid = (unsigned)(8 * per_xcd);
+    if (T == 16)
+        launch_scan_t<16>(st, S, W, q, np_stride, kcap, grid, per_xcd);
+    else if (T == 8)
+        launch_scan_t<8>(st, S, W, q, np_stride, kcap, grid, per_xcd);
+    else
+        launch_scan_t<4>(st, S, W, q, np_stride, kcap, grid, per_xcd);
+}
+
+void launch_search_merge(hipStream_t st, const Dev &S, const SearchBufs &W, int nq, int np_stride, int kcap,
+                         int k, const int32_t *k_per_query, float *dist, int64_t *labels) {
+    hipLaunchKernelGGL(k_merge, dim3((nq + 3) / 4), dim3(256), 0, st, S, nq, np_stride, W.probes, W.partials,
+                       kcap, k, k_per_query, dist, labels);
+}
+
+}  // namespace sivf

@@ -1,0 +1,561 @@
+// Host runtime of libsivf: workspace layout, argument checks and the order in
+// which each C-ABI call enqueues its kernels.  All index state lives in the
+// caller's device workspace; the host handle holds pointers, sizes and a call
+// sequence number (data-dependent failures are recorded on the device against
+// the sequence number of the failing call, so the rest of that call's kernels
+// skip their work and the index is left unchanged).
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "../../include/sivf.h"
+#include "sivf_launch.h"
+
+using namespace sivf;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+constexpr int64_t COARSE_BYTES = 256ll << 20;   // scratch for approximate coarse distances
+
+size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+int kcap_for(int k) { return k <= 16 ? 16 : (k <= 32 ? 32 : 64); }
+
+struct Layout {
+    int dp4, kcap, coarse_rows;
+    int64_t num_pages, dir_cap, max_items;
+    size_t total;
+    size_t cent, cn2, cnorm, cmax, data, sids, sowner, sord, free_slabs, free_pages, pages, dir, len, att, mark,
+        ctl, lists, b_assign, b_rank, b_rec, b_seg, dt, probes, pair_rank, list_pairs, item_list, item_tile,
+        partials;
+};
+
+bool config_ok(const sivf_config *c) {
+    if (!c) return false;
+    if (c->dim < 1 || c->dim > 2048) return false;
+    if (c->nlist < 1 || c->nlist > 65536) return false;
+    if (c->slab_capacity < 1 || c->slab_capacity > 128 || (c->slab_capacity & (c->slab_capacity - 1))) return false;
+    if (c->metric != SIVF_L2 && c->metric != SIVF_IP) return false;
+    if (c->storage != SIVF_F32 || c->reserved0 != 0) return false;
+    if (c->num_slabs < 1 || c->num_slabs * (int64_t)c->slab_capacity >= (1ll << 31)) return false;
+    if (c->id_capacity < 1 || c->id_capacity >= (1ll << 31)) return false;
+    if (c->max_batch < 1 || c->max_queries < 1) return false;
+    if (c->max_k < 1 || c->max_k > 64) return false;
+    if (c->max_nprobe < 1 || c->max_nprobe > 1024) return false;
+    if ((int64_t)c->max_queries * c->max_nprobe >= (1ll << 31) / 64) return false;
+    return true;
+}
+
+Layout make_layout(const sivf_config *c) {
+    Layout L{};
+    L.dp4 = (c->dim + 3) / 4;
+    L.kcap = kcap_for(c->max_k);
+    const int64_t nl = c->nlist, ns = c->num_slabs, C = c->slab_capacity;
+    L.dir_cap = (ns + PAGE - 1) / PAGE + 1;
+    L.num_pages = (ns + PAGE - 1) / PAGE + nl;
+    const int64_t rows_cap = COARSE_BYTES / (4 * nl) > 64 ? COARSE_BYTES / (4 * nl) : 64;
+    const int64_t rows_need = c->max_batch > c->max_queries ? c->max_batch : c->max_queries;
+    L.coarse_rows = (int)(rows_need < rows_cap ? rows_need : rows_cap);
+    const int64_t npairs = (int64_t)c->max_queries * c->max_nprobe;
+    L.max_items = npairs + nl;
+    size_t cur = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = cur;
+        cur = align_up(cur + (bytes ? bytes : 1));
+        return o;
+    };
+    L.cent = take((size_t)nl * L.dp4 * 16);
+    L.cn2 = take((size_t)nl * 4);
+    L.cnorm = take((size_t)nl * 8);
+    L.cmax = take(8);
+    L.data = take((size_t)ns * L.dp4 * C * 16);
+    L.sids = take((size_t)ns * C * 4);
+    L.sowner = take((size_t)ns * 4);
+    L.sord = take((size_t)ns * 4);
+    L.free_slabs = take((size_t)ns * 4);
+    L.free_pages = take((size_t)L.num_pages * 4);
+    L.pages = take((size_t)L.num_pages * PAGE * 4);
+    L.dir = take((size_t)nl * L.dir_cap * 4);
+    L.len = take((size_t)nl * 4);
+    L.att = take((size_t)c->id_capacity * 4);
+    L.mark = take((size_t)c->id_capacity * 4);
+    L.ctl = take(CTL_WORDS * 4);
+    L.lists = take((size_t)12 * nl * 4);
+    L.b_assign = take((size_t)c->max_batch * 4);
+    L.b_rank = take((size_t)c->max_batch * 4);
+    L.b_rec = take((size_t)c->max_batch * 4);
+    L.b_seg = take((size_t)c->max_batch * 4);
+    L.dt = take((size_t)L.coarse_rows * nl * 4);
+    L.probes = take((size_t)npairs * 4);
+    L.pair_rank = take((size_t)npairs * 4);
+    L.list_pairs = take((size_t)npairs * 4);
+    L.item_list = take((size_t)L.max_items * 4);
+    L.item_tile = take((size_t)L.max_items * 4);
+    L.partials = take((size_t)npairs * L.kcap * 8);
+    L.total = cur;
+    return L;
+}
+
+bool dev_ok(hipError_t e) { return e == hipSuccess; }
+
+}  // namespace
+
+// Event pairs recorded around one class of work while profiling is on.
+struct ProfClass {
+    std::vector<hipEvent_t> start, stop;
+    size_t used = 0;
+    double ms = 0.0;
+    int64_t count = 0;
+};
+
+struct sivf_index {
+    sivf_config cfg{};
+    Layout L{};
+    Dev S{};
+    Batch B{};
+    SearchBufs W{};
+    float *dt = nullptr;
+    char *ws = nullptr;
+    uint32_t seq = 0;
+    hipStream_t last = nullptr;
+    bool broken = false;
+    bool prof = false;
+    ProfClass pc[SIVF_PROF_KINDS];
+};
+
+namespace {
+
+hipStream_t as_stream(void *s) { return (hipStream_t)s; }
+
+uint32_t next_seq(sivf_index *ix) {
+    ix->seq = ix->seq == 0x7FFFFFFF ? 1 : ix->seq + 1;
+    return ix->seq;
+}
+
+sivf_status launched(sivf_index *ix) {
+    if (!dev_ok(hipGetLastError())) {
+        ix->broken = true;
+        return SIVF_ERR_DEVICE;
+    }
+    return SIVF_OK;
+}
+
+// Fold finished intervals of one class into its sum.
+bool prof_fold(sivf_index *ix, ProfClass &c) {
+    for (size_t i = 0; i < c.used; i++) {
+        if (!dev_ok(hipEventSynchronize(c.stop[i]))) return false;
+        float ms = 0.f;
+        if (!dev_ok(hipEventElapsedTime(&ms, c.start[i], c.stop[i]))) return false;
+        c.ms += ms;
+        c.count++;
+    }
+    c.used = 0;
+    return true;
+}
+
+// Returns the slot of an interval whose start was recorded, or -1.
+int prof_begin(sivf_index *ix, int kind, hipStream_t st) {
+    if (!ix->prof) return -1;
+    ProfClass &c = ix->pc[kind];
+    if (c.used == 4096 && !prof_fold(ix, c)) return -1;
+    if (c.used == c.start.size()) {
+        hipEvent_t a, b;
+        if (!dev_ok(hipEventCreate(&a))) return -1;
+        if (!dev_ok(hipEventCreate(&b))) {
+            (void)hipEventDestroy(a);
+            return -1;
+        }
+        c.start.push_back(a);
+        c.stop.push_back(b);
+    }
+    if (!dev_ok(hipEventRecord(c.start[c.used], st))) return -1;
+    return (int)c.used++;
+}
+
+void prof_end(sivf_index *ix, int kind, int slot, hipStream_t st) {
+    if (slot < 0) return;
+    if (!dev_ok(hipEventRecord(ix->pc[kind].stop[slot], st))) ix->pc[kind].used = (size_t)slot;
+}
+
+// Coarse selection over rows [0, n) in chunks that fit the scratch.
+void coarse(sivf_index *ix, hipStream_t st, const float *x, int64_t n, int m, const int32_t *m_per_row, int mmax,
+            int32_t *out, int out_stride, uint32_t seq) {
+    const Dev &S = ix->S;
+    const int dpad = S.dp4 * 4;
+    for (int64_t r0 = 0; r0 < n; r0 += ix->L.coarse_rows) {
+        const int nr = (int)((n - r0) < ix->L.coarse_rows ? (n - r0) : ix->L.coarse_rows);
+        const float *xr = x + r0 * S.d;
+        launch_coarse_gemm(st, xr, nr, S.d, S.cent, dpad, S.cn2, S.nlist, S.metric, ix->dt, S.ctl, seq);
+        launch_coarse_select(st, ix->dt, xr, nr, S.d, S.cent, dpad, S.cnorm, S.cmax, S.nlist, S.metric, m,
+                             m_per_row ? m_per_row + r0 : nullptr, mmax, out + r0 * out_stride, out_stride,
+                             S.ctl, seq);
+    }
+}
+
+sivf_status do_add(sivf_index *ix, int64_t n, const float *x, const int64_t *ids, hipStream_t st) {
+    if (n < 0 || n > ix->cfg.max_batch) return SIVF_ERR_ARG;
+    if (n > 0 && (!x || !ids)) return SIVF_ERR_ARG;
+    if (n == 0) return SIVF_OK;
+    const Dev &S = ix->S;
+    const int nn = (int)n;
+    const uint32_t seq = next_seq(ix);
+    const int ps = prof_begin(ix, SIVF_PROF_ADD, st);
+    launch_add_prepare(st, S, nn, ids, seq);
+    coarse(ix, st, x, n, 1, nullptr, 1, ix->B.assign, 1, seq);
+    launch_add_count(st, S, nn, ids, ix->B, seq);
+    launch_add_admit(st, S, seq);
+    launch_remove(st, S, nn, ids, nullptr, ix->B, seq, 1);
+    launch_add_alloc(st, S, seq);
+    launch_add_scatter(st, S, nn, x, ids, ix->B, seq);
+    launch_add_cleanup(st, S, nn, ids);
+    prof_end(ix, SIVF_PROF_ADD, ps, st);
+    return launched(ix);
+}
+
+sivf_status do_remove(sivf_index *ix, int64_t n, const int64_t *ids, int64_t *n_removed, hipStream_t st) {
+    if (n < 0 || n > ix->cfg.max_batch) return SIVF_ERR_ARG;
+    if (n > 0 && !ids) return SIVF_ERR_ARG;
+    if (n == 0) {
+        if (n_removed) launch_fill_i64(st, n_removed, 1, 0);
+        return launched(ix);
+    }
+    const uint32_t seq = next_seq(ix);
+    const int ps = prof_begin(ix, SIVF_PROF_REMOVE, st);
+    launch_remove(st, ix->S, (int)n, ids, n_removed, ix->B, seq, 0);
+    prof_end(ix, SIVF_PROF_REMOVE, ps, st);
+    return launched(ix);
+}
+
+sivf_status do_search(sivf_index *ix, int64_t nq, const float *q, int32_t k, const int32_t *kpq, int32_t nprobe,
+                      const int32_t *npq, float *dist, int64_t *labels, hipStream_t st) {
+    const sivf_config &c = ix->cfg;
+    if (nq < 0 || nq > c.max_queries) return SIVF_ERR_ARG;
+    if (k < 1 || k > c.max_k) return SIVF_ERR_ARG;
+    if (!npq && (nprobe < 1 || nprobe > c.max_nprobe)) return SIVF_ERR_ARG;
+    if (nq == 0) return SIVF_OK;
+    if (!q || !dist || !labels) return SIVF_ERR_ARG;
+    const int mmax = npq ? c.max_nprobe : nprobe;
+    const int stride = mmax < c.nlist ? mmax : c.nlist;
+    const int ps = prof_begin(ix, SIVF_PROF_SEARCH, st);
+    const int pc = prof_begin(ix, SIVF_PROF_COARSE, st);
+    coarse(ix, st, q, nq, npq ? 0 : stride, npq, stride, ix->W.probes, stride, 0);
+    prof_end(ix, SIVF_PROF_COARSE, pc, st);
+    launch_search_plan(st, ix->S, ix->W, (int)nq, stride);
+    const int pk = prof_begin(ix, SIVF_PROF_SCAN, st);
+    launch_search_scan(st, ix->S, ix->W, (int)nq, q, stride, ix->L.kcap);
+    prof_end(ix, SIVF_PROF_SCAN, pk, st);
+    const int pm = prof_begin(ix, SIVF_PROF_MERGE, st);
+    launch_search_merge(st, ix->S, ix->W, (int)nq, stride, ix->L.kcap, k, kpq, dist, labels);
+    prof_end(ix, SIVF_PROF_MERGE, pm, st);
+    prof_end(ix, SIVF_PROF_SEARCH, ps, st);
+    return launched(ix);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t sivf_workspace_bytes(const sivf_config *cfg) {
+    if (!config_ok(cfg)) return 0;
+    return make_layout(cfg).total;
+}
+
+sivf_status sivf_create(const sivf_config *cfg, const float *centroids, void *workspace, size_t ws_bytes,
+                        void *stream, sivf_index **out) {
+    if (!out) return SIVF_ERR_ARG;
+    *out = nullptr;
+    if (!config_ok(cfg) || !centroids || !workspace) return SIVF_ERR_ARG;
+    const Layout L = make_layout(cfg);
+    if (ws_bytes < L.total || ((uintptr_t)workspace % ALIGN) != 0) return SIVF_ERR_ARG;
+    sivf_index *ix = new (std::nothrow) sivf_index();
+    if (!ix) return SIVF_ERR_STATE;
+    ix->cfg = *cfg;
+    ix->L = L;
+    ix->ws = (char *)workspace;
+    char *w = ix->ws;
+    Dev &S = ix->S;
+    S.d = cfg->dim;
+    S.dp4 = L.dp4;
+    S.nlist = cfg->nlist;
+    S.C = cfg->slab_capacity;
+    S.metric = cfg->metric;
+    S.num_slabs = cfg->num_slabs;
+    S.num_pages = L.num_pages;
+    S.dir_cap = L.dir_cap;
+    S.id_capacity = cfg->id_capacity;
+    S.cent = (const float *)(w + L.cent);
+    S.cn2 = (const float *)(w + L.cn2);
+    S.cnorm = (const double *)(w + L.cnorm);
+    S.cmax = (const double *)(w + L.cmax);
+    S.data = (float4 *)(w + L.data);
+    S.sids = (uint32_t *)(w + L.sids);
+    S.sowner = (int32_t *)(w + L.sowner);
+    S.sord = (int32_t *)(w + L.sord);
+    S.free_slabs = (int32_t *)(w + L.free_slabs);
+    S.free_pages = (int32_t *)(w + L.free_pages);
+    S.pages = (int32_t *)(w + L.pages);
+    S.dir = (int32_t *)(w + L.dir);
+    S.len = (int32_t *)(w + L.len);
+    S.att = (uint32_t *)(w + L.att);
+    S.mark = (int32_t *)(w + L.mark);
+    S.ctl = (int32_t *)(w + L.ctl);
+    int32_t *lists = (int32_t *)(w + L.lists);
+    int32_t **lp[] = {&S.l_acnt, &S.l_prem, &S.l_base, &S.l_m, &S.l_off, &S.l_newlen,
+                      &S.l_q, &S.l_s, &S.l_h, &S.l_qc, &S.l_qcs, &S.l_qoff};
+    for (int i = 0; i < 12; i++) *lp[i] = lists + (size_t)i * cfg->nlist;
+    ix->B.assign = (int32_t *)(w + L.b_assign);
+    ix->B.rank = (int32_t *)(w + L.b_rank);
+    ix->B.rec = (uint32_t *)(w + L.b_rec);
+    ix->B.seg = (int32_t *)(w + L.b_seg);
+    ix->dt = (float *)(w + L.dt);
+    ix->W.probes = (int32_t *)(w + L.probes);
+    ix->W.pair_rank = (int32_t *)(w + L.pair_rank);
+    ix->W.list_pairs = (int32_t *)(w + L.list_pairs);
+    ix->W.item_list = (int32_t *)(w + L.item_list);
+    ix->W.item_tile = (int32_t *)(w + L.item_tile);
+    ix->W.partials = (uint64_t *)(w + L.partials);
+    ix->seq = 0;
+    ix->last = as_stream(stream);
+    launch_init_state(as_stream(stream), S, centroids);
+    if (!dev_ok(hipGetLastError())) {
+        delete ix;
+        return SIVF_ERR_DEVICE;
+    }
+    *out = ix;
+    return SIVF_OK;
+}
+
+sivf_status sivf_destroy(sivf_index *ix) {
+    if (!ix) return SIVF_ERR_ARG;
+    for (ProfClass &c : ix->pc) {
+        for (hipEvent_t e : c.start) (void)hipEventDestroy(e);
+        for (hipEvent_t e : c.stop) (void)hipEventDestroy(e);
+    }
+    delete ix;
+    return SIVF_OK;
+}
+
+sivf_status sivf_profile_enable(sivf_index *ix, int on) {
+    if (!ix) return SIVF_ERR_ARG;
+    ix->prof = on != 0;
+    return SIVF_OK;
+}
+
+sivf_status sivf_profile_read(sivf_index *ix, double *total_ms, int64_t *count) {
+    if (!ix) return SIVF_ERR_ARG;
+    for (int k = 0; k < SIVF_PROF_KINDS; k++) {
+        ProfClass &c = ix->pc[k];
+        if (!prof_fold(ix, c)) return SIVF_ERR_DEVICE;
+        if (total_ms) total_ms[k] = c.ms;
+        if (count) count[k] = c.count;
+        c.ms = 0.0;
+        c.count = 0;
+    }
+    return SIVF_OK;
+}
+
+sivf_status sivf_add(sivf_index *ix, int64_t n, const float *x, const int64_t *ids, void *stream) {
+    if (!ix) return SIVF_ERR_ARG;
+    if (ix->broken) return SIVF_ERR_STATE;
+    ix->last = as_stream(stream);
+    return do_add(ix, n, x, ids, as_stream(stream));
+}
+
+sivf_status sivf_remove(sivf_index *ix, int64_t n, const int64_t *ids, int64_t *n_removed, void *stream) {
+    if (!ix) return SIVF_ERR_ARG;
+    if (ix->broken) return SIVF_ERR_STATE;
+    ix->last = as_stream(stream);
+    return do_remove(ix, n, ids, n_removed, as_stream(stream));
+}
+
+sivf_status sivf_search(sivf_index *ix, int64_t nq, const float *q, int32_t k, const int32_t *k_per_query,
+                        int32_t nprobe, const int32_t *nprobe_per_query, float *dist, int64_t *labels,
+                        void *stream) {
+    if (!ix) return SIVF_ERR_ARG;
+    if (ix->broken) return SIVF_ERR_STATE;
+    ix->last = as_stream(stream);
+    return do_search(ix, nq, q, k, k_per_query, nprobe, nprobe_per_query, dist, labels, as_stream(stream));
+}
+
+sivf_status sivf_step(sivf_index *ix, const sivf_step_args *a, void *stream) {
+    if (!ix || !a) return SIVF_ERR_ARG;
+    if (ix->broken) return SIVF_ERR_STATE;
+    const sivf_config &c = ix->cfg;
+    if (a->n_add < 0 || a->n_add > c.max_batch || a->n_remove < 0 || a->n_remove > c.max_batch) return SIVF_ERR_ARG;
+    if (a->nq < 0 || a->nq > c.max_queries) return SIVF_ERR_ARG;
+    if (a->nq > 0 && (a->k < 1 || a->k > c.max_k || a->nprobe < 1 || a->nprobe > c.max_nprobe))
+        return SIVF_ERR_ARG;
+    hipStream_t st = as_stream(stream);
+    ix->last = st;
+    sivf_status s = do_add(ix, a->n_add, a->x, a->add_ids, st);
+    if (s != SIVF_OK) return s;
+    if (a->nq > 0) {
+        s = do_search(ix, a->nq, a->q, a->k, nullptr, a->nprobe, nullptr, a->dist, a->labels, st);
+        if (s != SIVF_OK) return s;
+    }
+    return do_remove(ix, a->n_remove, a->remove_ids, a->n_removed, st);
+}
+
+sivf_status sivf_assign(sivf_index *ix, int64_t n, const float *x, int32_t *lists, void *stream) {
+    if (!ix || n < 0 || (n > 0 && (!x || !lists))) return SIVF_ERR_ARG;
+    if (ix->broken) return SIVF_ERR_STATE;
+    const int64_t cap = ix->cfg.max_batch > ix->cfg.max_queries ? ix->cfg.max_batch : ix->cfg.max_queries;
+    if (n > cap) return SIVF_ERR_ARG;
+    ix->last = as_stream(stream);
+    if (n == 0) return SIVF_OK;
+    coarse(ix, as_stream(stream), x, n, 1, nullptr, 1, lists, 1, 0);
+    return launched(ix);
+}
+
+sivf_status sivf_probe(sivf_index *ix, int64_t nq, const float *q, int32_t nprobe, int32_t *probes, void *stream) {
+    if (!ix || nq < 0 || (nq > 0 && (!q || !probes))) return SIVF_ERR_ARG;
+    if (ix->broken) return SIVF_ERR_STATE;
+    if (nprobe < 1 || nprobe > ix->cfg.max_nprobe) return SIVF_ERR_ARG;
+    const int64_t cap = ix->cfg.max_batch > ix->cfg.max_queries ? ix->cfg.max_batch : ix->cfg.max_queries;
+    if (nq > cap) return SIVF_ERR_ARG;
+    ix->last = as_stream(stream);
+    if (nq == 0) return SIVF_OK;
+    const int m = nprobe < ix->cfg.nlist ? nprobe : ix->cfg.nlist;
+    coarse(ix, as_stream(stream), q, nq, m, nullptr, nprobe, probes, nprobe, 0);
+    return launched(ix);
+}
+
+sivf_status sivf_coarse_scores(sivf_index *ix, int64_t n, const float *x, float *scores, void *stream) {
+    if (!ix || n < 0 || (n > 0 && (!x || !scores))) return SIVF_ERR_ARG;
+    if (ix->broken) return SIVF_ERR_STATE;
+    const int64_t cap = ix->cfg.max_batch > ix->cfg.max_queries ? ix->cfg.max_batch : ix->cfg.max_queries;
+    if (n > cap) return SIVF_ERR_ARG;
+    ix->last = as_stream(stream);
+    if (n == 0) return SIVF_OK;
+    const Dev &S = ix->S;
+    launch_coarse_gemm(as_stream(stream), x, (int)n, S.d, S.cent, S.dp4 * 4, S.cn2, S.nlist, S.metric, scores,
+                       S.ctl, 0);
+    return launched(ix);
+}
+
+sivf_status sivf_get_rows(sivf_index *ix, int64_t n, const int64_t *ids, float *rows, void *stream) {
+    if (!ix || n < 0 || n > ix->cfg.max_batch || (n > 0 && (!ids || !rows))) return SIVF_ERR_ARG;
+    if (ix->broken) return SIVF_ERR_STATE;
+    ix->last = as_stream(stream);
+    if (n == 0) return SIVF_OK;
+    launch_get_rows(as_stream(stream), ix->S, (int)n, ids, rows);
+    return launched(ix);
+}
+
+sivf_status sivf_sync(sivf_index *ix, sivf_status *device_status) {
+    if (!ix) return SIVF_ERR_ARG;
+    if (!dev_ok(hipStreamSynchronize(ix->last))) return SIVF_ERR_DEVICE;
+    int32_t st = 0, zero = 0;
+    if (!dev_ok(hipMemcpyAsync(&st, ix->S.ctl + CTL_STATUS, 4, hipMemcpyDeviceToHost, ix->last))) return SIVF_ERR_DEVICE;
+    if (!dev_ok(hipMemcpyAsync(ix->S.ctl + CTL_STATUS, &zero, 4, hipMemcpyHostToDevice, ix->last)))
+        return SIVF_ERR_DEVICE;
+    if (!dev_ok(hipStreamSynchronize(ix->last))) return SIVF_ERR_DEVICE;
+    if (device_status) *device_status = (sivf_status)st;
+    return SIVF_OK;
+}
+
+static sivf_status read_counts(sivf_index *ix, std::vector<int32_t> &len, int32_t *ctl) {
+    len.resize(ix->cfg.nlist);
+    if (!dev_ok(hipStreamSynchronize(ix->last))) return SIVF_ERR_DEVICE;
+    if (!dev_ok(hipMemcpy(len.data(), ix->S.len, sizeof(int32_t) * len.size(), hipMemcpyDeviceToHost)))
+        return SIVF_ERR_DEVICE;
+    if (!dev_ok(hipMemcpy(ctl, ix->S.ctl, sizeof(int32_t) * CTL_WORDS, hipMemcpyDeviceToHost))) return SIVF_ERR_DEVICE;
+    return SIVF_OK;
+}
+
+sivf_status sivf_dump_info_get(sivf_index *ix, sivf_dump_info *info) {
+    if (!ix || !info) return SIVF_ERR_ARG;
+    std::vector<int32_t> len;
+    int32_t ctl[CTL_WORDS];
+    sivf_status s = read_counts(ix, len, ctl);
+    if (s != SIVF_OK) return s;
+    int64_t live = 0, used = 0;
+    const int C = ix->cfg.slab_capacity;
+    for (int32_t v : len) {
+        live += v;
+        used += (v + C - 1) / C;
+    }
+    info->live = live;
+    info->used_slabs = used;
+    info->free_slabs = ctl[CTL_SLAB_TOP];
+    info->num_slabs = ix->cfg.num_slabs;
+    info->id_capacity = ix->cfg.id_capacity;
+    info->nlist = ix->cfg.nlist;
+    info->slab_capacity = C;
+    return SIVF_OK;
+}
+
+sivf_status sivf_stats(sivf_index *ix, int64_t *live, int64_t *used_slabs, int64_t *free_slabs) {
+    sivf_dump_info info;
+    sivf_status s = sivf_dump_info_get(ix, &info);
+    if (s != SIVF_OK) return s;
+    if (live) *live = info.live;
+    if (used_slabs) *used_slabs = info.used_slabs;
+    if (free_slabs) *free_slabs = info.free_slabs;
+    return SIVF_OK;
+}
+
+sivf_status sivf_dump(sivf_index *ix, int32_t *list_len, int32_t *list_slabs, int64_t *ids_by_list,
+                      int32_t *free_slabs, int32_t *slab_owner, int32_t *slab_ordinal, uint32_t *att) {
+    if (!ix) return SIVF_ERR_ARG;
+    std::vector<int32_t> len;
+    int32_t ctl[CTL_WORDS];
+    sivf_status s = read_counts(ix, len, ctl);
+    if (s != SIVF_OK) return s;
+    const sivf_config &c = ix->cfg;
+    const int C = c.slab_capacity;
+    const Dev &S = ix->S;
+    auto d2h = [&](void *dst, const void *src, size_t bytes) { return dev_ok(hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost)); };
+    if (list_len) memcpy(list_len, len.data(), sizeof(int32_t) * len.size());
+    if (list_slabs || ids_by_list) {
+        std::vector<int32_t> dir((size_t)c.nlist * S.dir_cap), pages((size_t)S.num_pages * PAGE);
+        std::vector<uint32_t> sids;
+        if (!d2h(dir.data(), S.dir, dir.size() * 4) || !d2h(pages.data(), S.pages, pages.size() * 4))
+            return SIVF_ERR_DEVICE;
+        if (ids_by_list) {
+            sids.resize((size_t)c.num_slabs * C);
+            if (!d2h(sids.data(), S.sids, sids.size() * 4)) return SIVF_ERR_DEVICE;
+        }
+        int64_t so = 0, io = 0;
+        for (int l = 0; l < c.nlist; l++) {
+            const int ns = (len[l] + C - 1) / C;
+            for (int o = 0; o < ns; o++) {
+                const int page = dir[(size_t)l * S.dir_cap + o / PAGE];
+                if (page < 0 || page >= S.num_pages) return SIVF_ERR_STATE;
+                const int slab = pages[(size_t)page * PAGE + o % PAGE];
+                if (list_slabs) list_slabs[so++] = slab;
+                if (ids_by_list) {
+                    if (slab < 0 || slab >= c.num_slabs) return SIVF_ERR_STATE;
+                    const int cnt = (o == ns - 1) ? len[l] - o * C : C;
+                    for (int t = 0; t < cnt; t++) {
+                        const uint32_t v = sids[(size_t)slab * C + t];
+                        ids_by_list[io++] = v == INVALID ? -1 : (int64_t)v;
+                    }
+                }
+            }
+        }
+    }
+    if (free_slabs && ctl[CTL_SLAB_TOP] > 0 && !d2h(free_slabs, S.free_slabs, (size_t)ctl[CTL_SLAB_TOP] * 4))
+        return SIVF_ERR_DEVICE;
+    if (slab_owner && !d2h(slab_owner, S.sowner, (size_t)c.num_slabs * 4)) return SIVF_ERR_DEVICE;
+    if (slab_ordinal && !d2h(slab_ordinal, S.sord, (size_t)c.num_slabs * 4)) return SIVF_ERR_DEVICE;
+    if (att && !d2h(att, S.att, (size_t)c.id_capacity * 4)) return SIVF_ERR_DEVICE;
+    return SIVF_OK;
+}
+
+const char *sivf_status_string(sivf_status s) {
+    switch (s) {
+        case SIVF_OK: return "ok";
+        case SIVF_ERR_ARG: return "invalid argument";
+        case SIVF_ERR_NOSPACE: return "slab pool exhausted";
+        case SIVF_ERR_ID_RANGE: return "id outside [0, id_capacity)";
+        case SIVF_ERR_DEVICE: return "HIP runtime error";
+        case SIVF_ERR_STATE: return "index state unusable";
+    }
+    return "unknown status";
+}
+
+}  // extern "C"

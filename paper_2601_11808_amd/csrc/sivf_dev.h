@@ -1,0 +1,169 @@
+// Device-side definitions shared by the SIVF kernels (gfx950, wave64).
+//
+// Index state in the caller's workspace (all offsets 256-byte aligned):
+//   slab pool     data   [num_slabs][dp4][C] float4   (dp4 = ceil(d / 4))
+//                 sids   [num_slabs][C]      uint32   (id of each slot)
+//                 sowner [num_slabs]         int32    (list holding the slab, -1 = free)
+//                 sord   [num_slabs]         int32    (ordinal of the slab in its list)
+//   free stacks   free_slabs[num_slabs], free_pages[num_pages]; tops in ctl[]
+//   list tables   dir[nlist][dir_cap] -> page id; pages[num_pages][PAGE] -> slab id
+//                 len[nlist]: entries of each list; a list of n entries holds
+//                 ceil(n / C) slabs and its entries sit densely at positions 0..n-1
+//   address table att[id_capacity] = slab * C + slot, or INVALID
+//
+// Within a slab, slot s keeps dimension chunk c (4 floats) at data[slab][c][s]:
+// 64 lanes mapped to 64 consecutive slots load one contiguous KiB per chunk.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sivf {
+
+constexpr uint32_t INVALID = 0xFFFFFFFFu;   // empty address-table entry / tombstoned slot
+constexpr int PAGE = 256;                   // slab ids per page of a list table
+constexpr int WAVE = 64;
+
+// Slots of the control block (int32).
+enum Ctl {
+    CTL_SLAB_TOP = 0,   // entries on the free slab stack
+    CTL_PAGE_TOP = 1,   // entries on the free page stack
+    CTL_STATUS = 2,     // first data-dependent error since the last sync
+    CTL_GATE = 3,       // sequence number of the call that failed (its later kernels skip)
+    CTL_UPSERT = 4,     // sequence number of the add call that holds live ids
+    CTL_NITEMS = 5,     // search: work items of the current call
+    CTL_WORDS = 64
+};
+
+struct Dev {
+    int d, dp4, nlist, C, metric;
+    int64_t num_slabs, num_pages, dir_cap, id_capacity;
+    const float *cent;    // [nlist][dp4*4], zero padded
+    const float *cn2;     // [nlist] fp32 squared norms
+    const double *cnorm;  // [nlist] fp64 norms
+    const double *cmax;   // [1] largest centroid norm
+    float4 *data;
+    uint32_t *sids;
+    int32_t *sowner, *sord;
+    int32_t *free_slabs, *free_pages, *pages, *dir;
+    int32_t *len;
+    uint32_t *att;
+    int32_t *mark;
+    int32_t *ctl;
+    // per-list scratch (nlist each)
+    int32_t *l_acnt, *l_prem, *l_base;               // add
+    int32_t *l_m, *l_off, *l_newlen, *l_q, *l_s, *l_h; // remove
+    int32_t *l_qc, *l_qcs, *l_qoff;                  // search
+};
+
+__device__ __forceinline__ int slab_of(const Dev &S, int l, int ord) {
+    int page = S.dir[(int64_t)l * S.dir_cap + ord / PAGE];
+    return S.pages[(int64_t)page * PAGE + ord % PAGE];
+}
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    const int l = lane_id();
+    return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ int readlane_i(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int l) {
+    uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src) {
+    int lo = __shfl((int)(uint32_t)v, src);
+    int hi = __shfl((int)(uint32_t)(v >> 32), src);
+    return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+// Order-preserving map float -> uint32 (larger float, larger code).
+__device__ __forceinline__ uint32_t ord_bits(float f) {
+    uint32_t b = __float_as_uint(f);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ float from_ord(uint32_t o) {
+    uint32_t b = (o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o;
+    return __uint_as_float(b);
+}
+
+// Result ranking key: smaller key = better result; ties broken by smaller id.
+// L2 ranks by ascending distance, IP by descending score.
+__device__ __forceinline__ uint64_t make_key(float v, uint32_t id, int metric) {
+    uint32_t hi = metric == 0 ? ord_bits(v) : ~ord_bits(v);
+    return ((uint64_t)hi << 32) | id;
+}
+__device__ __forceinline__ float key_value(uint64_t key, int metric) {
+    uint32_t hi = (uint32_t)(key >> 32);
+    return metric == 0 ? from_ord(hi) : from_ord(~hi);
+}
+
+// Wave-aggregated atomicAdd of 1 per active lane on counters[key]: lanes with
+// equal keys share one atomic; each lane gets a distinct old value.  Every
+// lane of the wave must call it (active may be false).
+__device__ __forceinline__ int wave_agg_inc(int32_t *counters, int key, bool active) {
+    uint64_t act = ballot(active);
+    int result = 0;
+    const uint64_t lt = lanemask_lt();
+    while (act) {
+        const int leader = __builtin_ctzll(act);
+        const int lkey = readlane_i(key, leader);
+        const uint64_t grp = ballot(active && key == lkey) & act;
+        int base = 0;
+        if (lane_id() == leader) base = atomicAdd(&counters[lkey], (int)__builtin_popcountll(grp));
+        base = readlane_i(base, leader);
+        if ((grp >> lane_id()) & 1ull) result = base + (int)__builtin_popcountll(grp & lt);
+        act &= ~grp;
+    }
+    return result;
+}
+
+// Record the first data-dependent error of a call and stop its later kernels.
+__device__ __forceinline__ void fail_call(int32_t *ctl, int status, uint32_t seq) {
+    atomicCAS(&ctl[CTL_STATUS], 0, status);
+    atomicExch(&ctl[CTL_GATE], (int)seq);
+}
+
+__device__ __forceinline__ bool call_failed(const int32_t *ctl, uint32_t seq) {
+    return __builtin_nontemporal_load(&ctl[CTL_GATE]) == (int)seq;
+}
+
+// Inclusive sum over the 64 lanes of a wave.
+__device__ __forceinline__ int wave_incl_scan(int v) {
+    const int l = lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int u = __shfl_up(v, o);
+        if (l >= o) v += u;
+    }
+    return v;
+}
+
+// Exclusive sum over a block of NT threads (NT multiple of 64, <= 1024);
+// *total receives the block sum.  Uses sbuf[NT/64] of shared memory.
+template <int NT>
+__device__ __forceinline__ int block_excl_scan(int v, int *sbuf, int *total) {
+    const int w = threadIdx.x / 64, l = lane_id();
+    int incl = wave_incl_scan(v);
+    if (l == 63) sbuf[w] = incl;
+    __syncthreads();
+    int before = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < NT / 64; i++) {
+        int s = sbuf[i];
+        if (i < w) before += s;
+        tot += s;
+    }
+    __syncthreads();
+    *total = tot;
+    return before + incl - v;
+}
+
+}  // namespace sivf

@@ -1,0 +1,63 @@
+"""Structural invariants of a device-state dump (host-side check, numpy).
+
+Checks the properties the paper's correctness argument rests on, restated
+for dense slab lists (Sec. 3.1 slab pool and free stack; Theorem 1: each
+inserted entry owns a unique slot; Theorem 3: a deleted id is absent; the
+address table of Sec. 3.4 maps each live id to its slot):
+  - each list of n entries holds ceil(n/C) slabs, each slab is held by at most
+    one list, and a held slab records its owner and ordinal;
+  - used + free = pool size, and no slab is both free and held;
+  - every live position holds a real id (no tombstone), each id once;
+  - the address table maps exactly the live ids, each to its own slot.
+"""
+import numpy as np
+
+INVALID = 0xFFFFFFFF
+
+
+def check_dump(d, C, num_slabs):
+    ln = d["list_len"].astype(np.int64)
+    assert (ln >= 0).all()
+    ns = (ln + C - 1) // C
+    slabs = d["list_slabs"].astype(np.int64)
+    assert slabs.shape[0] == ns.sum()
+    assert ((slabs >= 0) & (slabs < num_slabs)).all(), "slab id out of range"
+    assert np.unique(slabs).shape[0] == slabs.shape[0], "a slab is held twice"
+    free = d["free_slabs"].astype(np.int64)
+    assert np.unique(free).shape[0] == free.shape[0], "free stack holds a slab twice"
+    assert slabs.shape[0] + free.shape[0] == num_slabs, "used + free != pool"
+    assert np.intersect1d(slabs, free).shape[0] == 0, "slab both free and held"
+    owner, ordn = d["slab_owner"], d["slab_ordinal"]
+    lst = np.repeat(np.arange(ln.shape[0]), ns)
+    ordinal = np.arange(slabs.shape[0]) - np.repeat(np.cumsum(ns) - ns, ns)
+    assert (owner[slabs] == lst).all(), "slab owner mismatch"
+    assert (ordn[slabs] == ordinal).all(), "slab ordinal mismatch"
+    assert (owner[free] == -1).all(), "free slab still owned"
+    ids = d["ids_by_list"]
+    assert ids.shape[0] == ln.sum()
+    assert (ids >= 0).all(), "tombstone inside a live range"
+    assert np.unique(ids).shape[0] == ids.shape[0], "an id is stored twice"
+    att = d["att"]
+    valid = att != INVALID
+    assert valid.sum() == ids.shape[0], "address table size != live"
+    assert valid[ids].all(), "live id missing from the address table"
+    # expected slot of each live entry
+    pos = np.arange(ids.shape[0]) - np.repeat(np.cumsum(ln) - ln, ln)
+    list_of_entry = np.repeat(np.arange(ln.shape[0]), ln)
+    slab_base = np.cumsum(ns) - ns
+    slab_of_entry = slabs[slab_base[list_of_entry] + pos // C]
+    want = slab_of_entry * C + pos % C
+    assert (att[ids].astype(np.int64) == want).all(), "address table points to the wrong slot"
+    return True
+
+
+def membership_of(d):
+    ln = d["list_len"].astype(np.int64)
+    offs = np.concatenate([[0], np.cumsum(ln)])
+    return {l: np.sort(d["ids_by_list"][offs[l]:offs[l + 1]]) for l in range(ln.shape[0]) if ln[l] > 0}
+
+
+def same_membership(a, b):
+    if a.keys() != b.keys():
+        return False
+    return all(np.array_equal(a[k], b[k]) for k in a)

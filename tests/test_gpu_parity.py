@@ -1,0 +1,271 @@
+"""GPU parity: the HIP library against the CPU oracle on seeded inputs.
+
+Membership after every operation must be bit-exact (same ids in the same
+lists), device-state invariants must hold, and FP32 search must return the
+oracle's ids with distances within 1e-5 relative.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from tests.gpu_common import Pair, compare_results, say
+from tests.invariants import check_dump
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    say(f"\n[gpu] {request.node.name}")
+    yield
+
+
+# ------------------------------------------------------------ coarse stage
+
+@pytest.mark.parametrize("kind,d,nlist", [("normal", 32, 16), ("int", 128, 1024), ("scaled", 96, 300),
+                                          ("unit", 96, 256), ("odd", 30, 77)])
+def test_coarse_mfma_error_bound(kind, d, nlist):
+    """The approximate FP32-MFMA distances stay inside the bound the exact
+    re-check assumes: |approx - exact| <= (4d+16) 2^-24 (|x|+|c|)^2."""
+    rng = np.random.default_rng([7, d, nlist])
+    if kind == "int":
+        cent = rng.uniform(0, 255, (nlist, d)).astype(np.float32)
+        x = rng.integers(0, 256, (3000, d)).astype(np.float32)
+    elif kind == "scaled":
+        cent = (rng.standard_normal((nlist, d)) * 1e3).astype(np.float32)
+        x = (rng.standard_normal((3000, d)) * 1e3 + 5e3).astype(np.float32)
+    elif kind == "unit":
+        cent = rng.standard_normal((nlist, d))
+        cent = (cent / np.linalg.norm(cent, axis=1, keepdims=True)).astype(np.float32)
+        x = rng.standard_normal((3000, d))
+        x = (x / np.linalg.norm(x, axis=1, keepdims=True)).astype(np.float32)
+    else:
+        cent = rng.standard_normal((nlist, d)).astype(np.float32)
+        x = rng.standard_normal((3000, d)).astype(np.float32)
+    for metric in (0, 1):
+        p = Pair(d, nlist, cent, metric=metric, max_batch=4096)
+        s = p.gpu.coarse_scores(x).cpu().numpy().astype(np.float64)
+        xd, cd = x.astype(np.float64), cent.astype(np.float64)
+        nx, nc = np.linalg.norm(xd, axis=1), np.linalg.norm(cd, axis=1)
+        coef = (4 * d + 16) * 2.0 ** -24
+        if metric == 0:
+            exact = ((xd[:, None, :] - cd[None]) ** 2).sum(-1)
+            bound = coef * (nx[:, None] + nc[None]) ** 2
+        else:
+            exact = -(xd @ cd.T)
+            bound = coef * nx[:, None] * nc[None]
+        ratio = np.abs(s - exact) / bound
+        say(f"  metric {metric}: max |approx-exact|/bound = {ratio.max():.3e}")
+        assert ratio.max() <= 0.5
+
+
+def _tie_data(seed, d, nlist, n):
+    rng = np.random.default_rng(seed)
+    cent = rng.standard_normal((nlist, d)).astype(np.float32)
+    cent[5] = cent[2]                       # exact duplicates: ties -> lower id
+    cent[nlist - 1] = cent[0]
+    x = rng.standard_normal((n, d)).astype(np.float32)
+    a = rng.integers(0, nlist, n // 3)
+    b = rng.integers(0, nlist, n // 3)
+    x[: n // 3] = (cent[a] + cent[b]) * np.float32(0.5)   # near-equidistant points
+    x[n // 3: n // 3 + 8] = cent[[0, 2, 5, 7, 9, nlist - 1, 3, 4]]
+    return cent, x
+
+
+@pytest.mark.parametrize("metric", [0, 1])
+def test_assign_and_probe_exact(metric):
+    """Coarse decisions equal the oracle's (FP64 canonical distance, ties to
+    the smaller list id) on inputs full of near-ties and exact ties."""
+    for d, nlist in [(16, 64), (128, 1024), (7, 13)]:
+        cent, x = _tie_data(d * 1000 + nlist, d, nlist, 6000)
+        p = Pair(d, nlist, cent, metric=metric, max_batch=8192, max_nprobe=64)
+        ga = p.gpu.assign(x).cpu().numpy()
+        ra = oracle.assign(x, cent, metric)
+        np.testing.assert_array_equal(ga, ra)
+        for m in (1, 5, 32, 64):
+            gp = p.gpu.probe(x[:1500], m).cpu().numpy()
+            rp = oracle.probe(x[:1500], cent, m, metric)
+            np.testing.assert_array_equal(gp, rp)
+
+
+# --------------------------------------------------------- golden sequence
+
+def test_golden_mutation_sequence_gpu():
+    g = json.load(open(os.path.join(GOLD, "mutation_small.json")))
+    cent = np.array(g["centroids"], np.float32)
+    p = Pair(g["dim"], len(cent), cent, g["metric"], g["slab_capacity"], g["num_slabs"], g["id_capacity"],
+             max_batch=64, max_queries=8, max_k=8, max_nprobe=4)
+    for n, st in enumerate(g["steps"]):
+        if st["op"] == "add":
+            status = p.add(np.array(st["x"], np.float32), np.array(st["ids"], np.int64))
+        else:
+            status = p.remove(np.array(st["ids"], np.int64))
+        assert status == st["status"], n
+        d = p.check_state()
+        mem = {str(l): v.tolist() for l, v in p.ref.membership().items()}
+        assert mem == {k: sorted(v) for k, v in st["lists"].items()}, n
+        assert int(((d["list_len"] + 1) // 2).sum()) == st["used_slabs"]
+        for idk, row in st.get("rows", {}).items():
+            got = p.gpu.get_rows(np.array([int(idk)])).cpu().numpy()[0]
+            np.testing.assert_array_equal(got, np.array(row, np.float32))
+    s = g["searches_after_last_step"]
+    for case in s["cases"]:
+        gd, gl = p.gpu.search(np.array([s["query"]], np.float32), case["k"], case["nprobe"])
+        assert gl.cpu().numpy()[0].tolist() == case["ids"]
+        assert gd.cpu().numpy()[0].tolist() == [float(v) for v in case["dist"]]
+
+
+def test_golden_search_ip_gpu():
+    g = json.load(open(os.path.join(GOLD, "search_ip_small.json")))
+    cent = np.array(g["centroids"], np.float32)
+    p = Pair(g["dim"], len(cent), cent, g["metric"], g["slab_capacity"], g["num_slabs"], g["id_capacity"],
+             max_batch=16, max_queries=4, max_k=8, max_nprobe=4)
+    assert p.add(np.array(g["add"]["x"], np.float32), np.array(g["add"]["ids"])) == 0
+    p.check_state()
+    for case in g["cases"]:
+        gd, gl = p.gpu.search(np.array([g["query"]], np.float32), case["k"], case["nprobe"])
+        assert gl.cpu().numpy()[0].tolist() == case["ids"]
+        assert gd.cpu().numpy()[0].tolist() == [float(v) for v in case["dist"]]
+
+
+# -------------------------------------------------------- tiny workload
+
+def test_tiny_window_workload():
+    """Tiny plain FP32 workload: 4,096 base vectors, d=32, 16 lists, slab 32,
+    four window steps of +256 / -256 oldest, 64 queries, nprobe 4, k 10."""
+    w = workloads.tiny()
+    x, ids = w.base()
+    q = w.queries()
+    p = Pair(w.dim, w.nlist, w.centroids, w.metric, w.slab, num_slabs=400, id_capacity=8192,
+             max_batch=4096, max_queries=64, max_k=16, max_nprobe=16)
+    assert p.add(x, ids) == 0
+    p.check_state()
+    nbit = p.check_search(q, w.k, w.nprobe)
+    for t in range(1, 5):
+        xb, idb = w.stream_batch(t)
+        assert p.add(xb, idb) == 0
+        nbit += p.check_search(q, w.k, w.nprobe)
+        assert p.remove(w.oldest_ids(t)) == 0
+        p.check_state()
+        nbit += p.check_search(q, 10, 16)       # all lists
+    say(f"  distances differing in any bit: {nbit}")
+
+
+def test_step_call_matches_separate_calls():
+    w = workloads.tiny()
+    x, ids = w.base()
+    q = w.queries()
+    p = Pair(w.dim, w.nlist, w.centroids, w.metric, w.slab, num_slabs=400, id_capacity=8192,
+             max_batch=4096, max_queries=64, max_k=16, max_nprobe=16)
+    assert p.add(x, ids) == 0
+    for t in range(1, 4):
+        xb, idb = w.stream_batch(t)
+        old = w.oldest_ids(t)
+        gd, gl, nrem = p.gpu.step(xb, idb, q, w.k, w.nprobe, old)
+        assert p.gpu.sync() == 0
+        assert p.ref.add(xb, idb) == 0
+        st, rd, rl = p.ref.search(q, w.k, w.nprobe)
+        st, rn = p.ref.remove(old)
+        compare_results(gd.cpu().numpy(), gl.cpu().numpy(), rd, rl)
+        assert int(nrem.item()) == rn
+        p.check_state()
+
+
+# -------------------------------------------------------- random op stress
+
+@pytest.mark.parametrize("C,d,metric,seed", [(32, 5, 0, 1), (64, 32, 0, 2), (128, 17, 0, 3), (64, 24, 1, 4),
+                                             (32, 64, 1, 5)])
+def test_random_ops_vs_oracle(C, d, metric, seed):
+    """Random batches of adds (fresh, upserts, duplicates within a batch) and
+    removes (live, absent, repeated) on a small id space; state and search
+    compared after every operation."""
+    rng = np.random.default_rng([seed, 99])
+    nlist = 11
+    cent = rng.standard_normal((nlist, d)).astype(np.float32)
+    cap = 3000
+    p = Pair(d, nlist, cent, metric, C, num_slabs=2000, id_capacity=cap, max_batch=1024, max_queries=64,
+             max_k=40, max_nprobe=16)
+    q = rng.standard_normal((50, d)).astype(np.float32)
+    for step in range(25):
+        n = int(rng.integers(0, 700))
+        ids = rng.integers(0, cap, n)
+        x = rng.standard_normal((n, d)).astype(np.float32)
+        if n > 10:
+            x[:5] = x[5:10]                     # equal rows, different ids: equal distances
+        assert p.add(x, ids) == 0
+        p.check_state()
+        rm = rng.integers(0, cap, int(rng.integers(0, 600)))
+        assert p.remove(rm) == 0
+        p.check_state()
+        k = int(rng.integers(1, 41))
+        p.check_search(q, k, int(rng.integers(1, 16)))
+    kpq = rng.integers(0, 41, 50).astype(np.int32)
+    npq = rng.integers(1, 17, 50).astype(np.int32)
+    p.check_search(q, 40, 0, kpq=kpq, npq=npq)
+
+
+def test_single_list_contention_and_drain():
+    """Every vector lands in one list (maximum contention on one list's
+    counters), then the list is drained to empty and refilled."""
+    d, nlist = 16, 8
+    rng = np.random.default_rng(5)
+    cent = rng.standard_normal((nlist, d)).astype(np.float32) * 10
+    p = Pair(d, nlist, cent, 0, 64, num_slabs=600, id_capacity=40000, max_batch=20000, max_queries=16,
+             max_k=16, max_nprobe=8)
+    x = np.tile(cent[3], (20000, 1)) + rng.standard_normal((20000, d)).astype(np.float32) * 0.01
+    assert p.add(x, np.arange(20000)) == 0
+    d0 = p.check_state()
+    assert d0["list_len"][3] == 20000
+    q = x[:16]
+    p.check_search(q, 16, 2)
+    order = rng.permutation(20000)
+    for part in np.array_split(order, 5):
+        assert p.remove(part) == 0
+        p.check_state()
+    assert p.gpu.stats()["live"] == 0 and p.gpu.stats()["used_slabs"] == 0
+    assert p.add(x[:5000], np.arange(20000, 25000)) == 0
+    p.check_state()
+    p.check_search(q, 16, 8)
+
+
+def test_errors_leave_state_unchanged():
+    d, nlist = 8, 4
+    rng = np.random.default_rng(6)
+    cent = (np.eye(4, 8) * 10).astype(np.float32)
+    p = Pair(d, nlist, cent, 0, 32, num_slabs=10, id_capacity=1000, max_batch=512, max_queries=8,
+             max_k=8, max_nprobe=4)
+    x = np.tile(cent[0], (330, 1)) + rng.standard_normal((330, 8)).astype(np.float32) * 0.1
+    assert p.add(x[:320], np.arange(320)) == 0         # list 0: 10 full slabs = whole pool
+    before = p.check_state()
+    assert p.add(x[320:321], np.array([320])) == -2    # one more vector: NOSPACE
+    assert p.add(x[:2], np.array([5, 1000])) == -3      # id out of range
+    assert p.remove(np.array([1, -1])) == -3
+    after = p.check_state()
+    for k in ("list_len", "ids_by_list", "att"):
+        np.testing.assert_array_equal(before[k], after[k])
+    assert p.remove(np.array([7, 7, 7, 999, 998])) == 0   # duplicates and absent ids
+    assert p.add(x[320:321], np.array([320])) == 0     # room again after the delete
+    p.check_state()
+
+
+def test_empty_and_padding_cases():
+    d, nlist = 12, 6
+    rng = np.random.default_rng(7)
+    cent = rng.standard_normal((nlist, d)).astype(np.float32)
+    for metric in (0, 1):
+        p = Pair(d, nlist, cent, metric, 64, num_slabs=64, id_capacity=100, max_batch=100, max_queries=16,
+                 max_k=64, max_nprobe=64)
+        q = rng.standard_normal((5, d)).astype(np.float32)
+        p.check_search(q, 10, 3)                         # empty index: all padding
+        x = rng.standard_normal((7, d)).astype(np.float32)
+        assert p.add(x, np.arange(7)) == 0
+        p.check_search(q, 64, 64)                         # k > live, nprobe > nlist
+        p.check_search(q, 1, 1)
+        assert p.remove(np.arange(7)) == 0
+        p.check_search(q, 5, 6)
+        p.check_state()
