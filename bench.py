@@ -214,7 +214,7 @@ def main():
     }
     if not a.no_cpu_baseline:
         t0 = time.time()
-        xb, idb = w.stream_batch(T + 1)
+        xb, idb = w.stream_batch(1)
         res["cpu_baseline"] = cpu_baseline(w, x, ids, q, (xb, idb, w.oldest_ids(1)), nprobe, k,
                                            n_sample_q=200 if a.workload == "window" else nq)
         log(f"[bench] cpu baseline in {time.time() - t0:.1f} s")

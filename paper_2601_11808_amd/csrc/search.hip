@@ -71,9 +71,10 @@ __global__ __launch_bounds__(256) void k_inv_scatter(Dev S, int npairs, const in
     list_pairs[S.l_qoff[probes[p]] + r] = p;
 }
 
+// Lane i receives lane i-1's value (DPP wave_shr:1; lane 0 receives 0).
 __device__ __forceinline__ uint64_t shfl_up1_u64(uint64_t v) {
-    const int lo = __shfl_up((int)(uint32_t)v, 1);
-    const int hi = __shfl_up((int)(uint32_t)(v >> 32), 1);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, 0x138, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), 0x138, 0xF, 0xF, false);
     return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
 }
 
@@ -94,6 +95,89 @@ __device__ __forceinline__ void topk_insert(uint64_t &top, uint64_t key, int kca
         if (ln >= kcap) top = ~0ull;
         thr = readlane_u64(top, kcap - 1);
     }
+}
+
+// Queries come straight from the caller's rows with wave-uniform addresses,
+// so the compiler reads them through the scalar cache into SGPRs and every
+// VALU op takes its query operand from an SGPR (no LDS traffic).  Needs
+// d % 4 == 0 and 16-byte aligned rows.
+template <int T, int METRIC>
+__global__ __launch_bounds__(64) void k_scan_sq(Dev S, const int32_t *__restrict__ item_list,
+                                                const int32_t *__restrict__ item_tile,
+                                                const int32_t *__restrict__ list_pairs,
+                                                const float *__restrict__ q, int np_stride, int kcap,
+                                                uint64_t *__restrict__ partials, int per_xcd) {
+    const int w = blockIdx.x;
+    const int item = (w & 7) * per_xcd + (w >> 3);
+    if (item >= S.ctl[CTL_NITEMS]) return;
+    const int lane = threadIdx.x;
+    const int l = item_list[item], tile = item_tile[item];
+    const int nt = min(T, S.l_qcs[l] - tile * T);
+    const int dp4 = S.dp4, C = S.C;
+    const int32_t *pairs = list_pairs + S.l_qoff[l] + tile * T;
+    const float4 *qrow[T];
+#pragma unroll
+    for (int t = 0; t < T; t++) {
+        const int pr = pairs[t < nt ? t : 0];
+        qrow[t] = reinterpret_cast<const float4 *>(q + (int64_t)(pr / np_stride) * S.d);
+    }
+    uint64_t top[T];
+#pragma unroll
+    for (int t = 0; t < T; t++) top[t] = ~0ull;
+    const int len = S.len[l];
+    const int nslab = cdiv_s(len, C);
+    int wbase = -(1 << 30), wslab = 0;   // lane j holds the slab of ordinal wbase + j
+    for (int base = 0; base < len; base += 64) {
+        const int p = base + lane;
+        const bool valid = p < len;
+        const int pc = valid ? p : len - 1;
+        const int last_ord = (min(base + 63, len - 1)) / C;
+        if (last_ord >= wbase + 64) {
+            wbase = base / C;
+            wslab = (wbase + lane < nslab) ? slab_of(S, l, wbase + lane) : 0;
+        }
+        const int slab = __shfl(wslab, pc / C - wbase);
+        const int slot = pc % C;
+        const float4 *xp = S.data + (int64_t)slab * dp4 * C + slot;
+        float acc[T];
+#pragma unroll
+        for (int t = 0; t < T; t++) acc[t] = 0.f;
+#pragma unroll 2
+        for (int c = 0; c < dp4; c++) {
+            const float4 xv = xp[(int64_t)c * C];
+#pragma unroll
+            for (int t = 0; t < T; t++) {
+                const float4 qv = qrow[t][c];
+                if (METRIC == 0) {
+                    float e;
+                    e = qv.x - xv.x;
+                    acc[t] = __builtin_fmaf(e, e, acc[t]);
+                    e = qv.y - xv.y;
+                    acc[t] = __builtin_fmaf(e, e, acc[t]);
+                    e = qv.z - xv.z;
+                    acc[t] = __builtin_fmaf(e, e, acc[t]);
+                    e = qv.w - xv.w;
+                    acc[t] = __builtin_fmaf(e, e, acc[t]);
+                } else {
+                    acc[t] = __builtin_fmaf(qv.x, xv.x, acc[t]);
+                    acc[t] = __builtin_fmaf(qv.y, xv.y, acc[t]);
+                    acc[t] = __builtin_fmaf(qv.z, xv.z, acc[t]);
+                    acc[t] = __builtin_fmaf(qv.w, xv.w, acc[t]);
+                }
+            }
+        }
+        const uint32_t id = S.sids[(int64_t)slab * C + slot];
+#pragma unroll
+        for (int t = 0; t < T; t++) {
+            if (t < nt) {
+                const uint64_t key = valid ? make_key(acc[t], id, METRIC) : ~0ull;
+                topk_insert(top[t], key, kcap);
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < T; t++)
+        if (t < nt && lane < kcap) partials[(int64_t)pairs[t] * kcap + lane] = top[t];
 }
 
 template <int T, int METRIC>
@@ -269,6 +353,16 @@ template <int T>
 static void launch_scan_t(hipStream_t st, const Dev &S, const SearchBufs &W, const float *q, int np_stride,
                           int kcap, unsigned grid, int per_xcd) {
     const size_t smem = (size_t)T * S.dp4 * sizeof(float4);
+    const bool sq = (S.d % 4 == 0) && (((uintptr_t)q & 15) == 0);
+    if (sq) {
+        if (S.metric == 0)
+            hipLaunchKernelGGL((k_scan_sq<T, 0>), dim3(grid), dim3(64), 0, st, S, W.item_list, W.item_tile,
+                               W.list_pairs, q, np_stride, kcap, W.partials, per_xcd);
+        else
+            hipLaunchKernelGGL((k_scan_sq<T, 1>), dim3(grid), dim3(64), 0, st, S, W.item_list, W.item_tile,
+                               W.list_pairs, q, np_stride, kcap, W.partials, per_xcd);
+        return;
+    }
     if (S.metric == 0)
         hipLaunchKernelGGL((k_scan<T, 0>), dim3(grid), dim3(64), smem, st, S, W.item_list, W.item_tile,
                            W.list_pairs, q, np_stride, kcap, W.partials, per_xcd);

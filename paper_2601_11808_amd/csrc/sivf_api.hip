@@ -10,7 +10,7 @@
 #include <new>
 #include <vector>
 
-#include "../../include/sivf.h"
+#include "sivf.h"
 #include "sivf_launch.h"
 
 using namespace sivf;
