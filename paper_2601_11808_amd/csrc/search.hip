@@ -29,7 +29,7 @@ __global__ __launch_bounds__(256) void k_inv_count(Dev S, int npairs, const int3
     const bool active = p < npairs;
     const int l = active ? probes[p] : -1;
     const bool act = l >= 0;
-    const int r = wave_agg_inc(S.l_qc, act ? l : 0, act);
+    const int r = act ? atomicAdd(&S.l_qc[l], 1) : 0;   // a wave's 64 pairs hit ~64 distinct lists
     if (active) pair_rank[p] = act ? r : -1;
 }
 
@@ -346,8 +346,10 @@ __global__ __launch_bounds__(256) void k_merge(Dev S, int nq, int np_stride, con
     }
 }
 
-// Queries per tile: LDS holds T * ceil(d/4) * 16 bytes, kept within 32 KiB.
-int search_tile(int d) { return d <= 512 ? 16 : (d <= 1024 ? 8 : 4); }
+// Queries per tile (the LDS path holds T * ceil(d/4) * 16 bytes, within 32
+// KiB).  Measured on the window workload: T=8 with two dimension chunks in
+// flight beats T=16, whose query operands no longer fit the SGPR file.
+int search_tile(int d) { return d <= 1024 ? 8 : 4; }
 
 template <int T>
 static void launch_scan_t(hipStream_t st, const Dev &S, const SearchBufs &W, const float *q, int np_stride,
@@ -388,9 +390,7 @@ void launch_search_scan(hipStream_t st, const Dev &S, const SearchBufs &W, int n
     const int64_t bound = (int64_t)npairs / T + (npairs < S.nlist ? npairs : S.nlist);
     const int per_xcd = (int)((bound + 7) / 8);
     const unsigned grid = (unsigned)(8 * per_xcd);
-    if (T == 16)
-        launch_scan_t<16>(st, S, W, q, np_stride, kcap, grid, per_xcd);
-    else if (T == 8)
+    if (T == 8)
         launch_scan_t<8>(st, S, W, q, np_stride, kcap, grid, per_xcd);
     else
         launch_scan_t<4>(st, S, W, q, np_stride, kcap, grid, per_xcd);
