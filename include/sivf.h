@@ -144,6 +144,20 @@ typedef struct {
 
 sivf_status sivf_step(sivf_index *ix, const sivf_step_args *args, void *stream);
 
+/* A window step captured once as a HIP graph and replayed: the ~30 kernel
+ * launches of a step are recorded once and replayed as one graph launch
+ * (the paper finds that amortising kernel-launch overhead is a key driver of
+ * mutation latency, Sec. 5.2.3).  The graph records the pointers in `args`:
+ * before each launch, write the new batch into the same buffers.  Counts
+ * (n_add, nq, k, nprobe, n_remove) are fixed per graph, so create one graph
+ * per shape.  Profiling events are not recorded inside a graph.  The capture
+ * uses a private stream of default priority; `sivf_graph_launch` enqueues the
+ * whole step on `stream`.  A graph must be destroyed before its index. */
+typedef struct sivf_graph sivf_graph;
+sivf_status sivf_graph_create(sivf_index *ix, const sivf_step_args *args, sivf_graph **out);
+sivf_status sivf_graph_launch(sivf_graph *g, void *stream);
+sivf_status sivf_graph_destroy(sivf_graph *g);
+
 /* Nearest list of each vector (the coarse assignment used by sivf_add).
  * x: device n x dim fp32; lists: device n int32.  n <= max(max_batch, max_queries). */
 sivf_status sivf_assign(sivf_index *ix, int64_t n, const float *x, int32_t *lists, void *stream);

@@ -58,6 +58,9 @@ SIGNATURES = [
     ("sivf_remove", ct.c_int, [_P, _I64, _P, _P, _P]),
     ("sivf_search", ct.c_int, [_P, _I64, _P, _I32, _P, _I32, _P, _P, _P, _P]),
     ("sivf_step", ct.c_int, [_P, ct.POINTER(SivfStepArgs), _P]),
+    ("sivf_graph_create", ct.c_int, [_P, ct.POINTER(SivfStepArgs), ct.POINTER(_P)]),
+    ("sivf_graph_launch", ct.c_int, [_P, _P]),
+    ("sivf_graph_destroy", ct.c_int, [_P]),
     ("sivf_assign", ct.c_int, [_P, _I64, _P, _P, _P]),
     ("sivf_probe", ct.c_int, [_P, _I64, _P, _I32, _P, _P]),
     ("sivf_coarse_scores", ct.c_int, [_P, _I64, _P, _P, _P]),
@@ -240,6 +243,11 @@ class Index:
         self._keep = keep
         return dist, lab, nrem
 
+    def step_graph(self, x, add_ids, q, k, nprobe, remove_ids, dist, labels, n_removed):
+        """Capture add -> search -> remove on these device buffers as a graph.
+        Refill the buffers in place, then call ``launch()`` on the result."""
+        return StepGraph(self, x, add_ids, q, k, nprobe, remove_ids, dist, labels, n_removed)
+
     def assign(self, x, stream=None):
         torch = _torch()
         x = _dev_tensor(x, torch.float32, self.device).reshape(-1, self.dim)
@@ -331,3 +339,35 @@ class Index:
         offs = np.concatenate([[0], np.cumsum(d["list_len"].astype(np.int64))])
         return {l: np.sort(d["ids_by_list"][offs[l]:offs[l + 1]]) for l in range(self.nlist)
                 if d["list_len"][l] > 0}
+
+
+class StepGraph:
+    """A window step captured as a HIP graph over fixed device buffers."""
+
+    def __init__(self, index, x, add_ids, q, k, nprobe, remove_ids, dist, labels, n_removed):
+        for t in (x, add_ids, q, remove_ids, dist, labels, n_removed):
+            assert t.is_cuda and t.is_contiguous()
+        a = SivfStepArgs()
+        a.n_add, a.x, a.add_ids = add_ids.shape[0], x.data_ptr(), add_ids.data_ptr()
+        a.nq, a.q, a.k, a.nprobe = q.shape[0], q.data_ptr(), k, nprobe
+        a.dist, a.labels = dist.data_ptr(), labels.data_ptr()
+        a.n_remove, a.remove_ids, a.n_removed = remove_ids.shape[0], remove_ids.data_ptr(), n_removed.data_ptr()
+        self.index = index
+        self._bufs = (x, add_ids, q, remove_ids, dist, labels, n_removed)
+        h = ct.c_void_p()
+        _check(lib().sivf_graph_create(index._h, ct.byref(a), ct.byref(h)), "sivf_graph_create")
+        self._h = h
+
+    def launch(self, stream=None):
+        _check(lib().sivf_graph_launch(self._h, self.index._stream(stream)), "sivf_graph_launch")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().sivf_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -24,12 +24,12 @@ __global__ __launch_bounds__(256) void k_coarse_gemm(const float *__restrict__ X
                                                      const float *__restrict__ cent, int dpad,
                                                      const float *__restrict__ cn2, int nlist,
                                                      float *__restrict__ out, const int32_t *ctl,
-                                                     uint32_t seq) {
+                                                     int gated) {
     constexpr int BM = 64, BN = 64, BK = 32;
     __shared__ float sA[BM][BK + 1];
     __shared__ float sB[BN][BK + 1];
     __shared__ float sqn[BM];
-    if (seq && call_failed(ctl, seq)) return;
+    if (gated && call_failed(ctl)) return;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int r0 = blockIdx.x * BM, c0 = blockIdx.y * BN;
     const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
@@ -109,13 +109,13 @@ __global__ __launch_bounds__(256) void k_coarse_select(
     const float *__restrict__ dt, const float *__restrict__ X, int n, int d, const float *__restrict__ cent,
     int dpad, const double *__restrict__ cnorm, const double *__restrict__ cmax, int nlist, int metric,
     int m_uniform, const int32_t *__restrict__ m_per_row, int mmax, int32_t *__restrict__ out,
-    int out_stride, const int32_t *ctl, uint32_t seq) {
+    int out_stride, const int32_t *ctl, int gated) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int hist[256];
     __shared__ int sbuf[8];
     __shared__ double sred[4];
     __shared__ int sdig[2];
-    if (seq && call_failed(ctl, seq)) return;
+    if (gated && call_failed(ctl)) return;
     const int row = blockIdx.x;
     if (row >= n) return;
     const int tid = threadIdx.x;
@@ -230,24 +230,24 @@ size_t coarse_select_smem(int dpad, int mmax) {
 
 void launch_coarse_gemm(hipStream_t st, const float *X, int n, int d, const float *cent, int dpad,
                         const float *cn2, int nlist, int metric, float *out, const int32_t *ctl,
-                        uint32_t seq) {
+                        int gated) {
     dim3 grid((n + 63) / 64, (nlist + 63) / 64);
     if (metric == 0)
         hipLaunchKernelGGL(k_coarse_gemm<0>, grid, dim3(256), 0, st, X, n, d, cent, dpad, cn2, nlist, out,
-                           ctl, seq);
+                           ctl, gated);
     else
         hipLaunchKernelGGL(k_coarse_gemm<1>, grid, dim3(256), 0, st, X, n, d, cent, dpad, cn2, nlist, out,
-                           ctl, seq);
+                           ctl, gated);
 }
 
 void launch_coarse_select(hipStream_t st, const float *dt, const float *X, int n, int d, const float *cent,
                           int dpad, const double *cnorm, const double *cmax, int nlist, int metric,
                           int m_uniform, const int32_t *m_per_row, int mmax, int32_t *out, int out_stride,
-                          const int32_t *ctl, uint32_t seq) {
+                          const int32_t *ctl, int gated) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_coarse_select, dim3(n), dim3(256), coarse_select_smem(dpad, mmax), st, dt, X, n, d,
                        cent, dpad, cnorm, cmax, nlist, metric, m_uniform, m_per_row, mmax, out, out_stride,
-                       ctl, seq);
+                       ctl, gated);
 }
 
 }  // namespace sivf

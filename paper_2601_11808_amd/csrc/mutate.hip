@@ -30,20 +30,19 @@ __device__ __forceinline__ int cdiv(int a, int b) { return (a + b - 1) / b; }
 
 // ------------------------------------------------------------------ insert
 
-__global__ __launch_bounds__(256) void k_add_prepare(Dev S, int n, const int64_t *__restrict__ ids, uint32_t seq) {
+__global__ __launch_bounds__(256) void k_add_prepare(Dev S, int n, const int64_t *__restrict__ ids) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
     const int64_t u = ids[i];
     if (u < 0 || u >= S.id_capacity)
-        fail_call(S.ctl, -3, seq);
+        fail_call(S.ctl, -3);
     else
         atomicMax(&S.mark[u], i);
 }
 
 __global__ __launch_bounds__(256) void k_add_count(Dev S, int n, const int64_t *__restrict__ ids,
-                                                   const int32_t *__restrict__ assign, int32_t *__restrict__ rank,
-                                                   uint32_t seq) {
-    if (call_failed(S.ctl, seq)) return;
+                                                   const int32_t *__restrict__ assign, int32_t *__restrict__ rank) {
+    if (call_failed(S.ctl)) return;
     const int i = blockIdx.x * 256 + threadIdx.x;
     const bool active = i < n;
     const int64_t u = active ? ids[i] : 0;
@@ -55,13 +54,13 @@ __global__ __launch_bounds__(256) void k_add_count(Dev S, int n, const int64_t *
     const bool live = g != INVALID;
     const int lo = live ? S.sowner[g / (uint32_t)S.C] : 0;
     wave_agg_inc(S.l_prem, lo, live);
-    if (ballot(live) && lane_id() == 0) atomicExch(&S.ctl[CTL_UPSERT], (int)seq);
+    if (ballot(live) && lane_id() == 0) atomicExch(&S.ctl[CTL_UPSERT], S.ctl[CTL_SEQ]);
 }
 
 // One block: does the final state fit in the pool?
-__global__ __launch_bounds__(1024) void k_add_admit(Dev S, uint32_t seq) {
+__global__ __launch_bounds__(1024) void k_add_admit(Dev S) {
     __shared__ long long sred[16];
-    if (call_failed(S.ctl, seq)) return;
+    if (call_failed(S.ctl)) return;
     const int tid = threadIdx.x;
     long long need = 0;
     for (int l = tid; l < S.nlist; l += 1024) need += cdiv(S.len[l] - S.l_prem[l] + S.l_acnt[l], S.C);
@@ -71,7 +70,7 @@ __global__ __launch_bounds__(1024) void k_add_admit(Dev S, uint32_t seq) {
     long long tot = 0;
     for (int w = 0; w < 16; w++) tot += sred[w];
     const bool reject = tot > S.num_slabs;
-    if (reject && tid == 0) fail_call(S.ctl, -2, seq);
+    if (reject && tid == 0) fail_call(S.ctl, -2);
     for (int l = tid; l < S.nlist; l += 1024) {
         S.l_prem[l] = 0;
         if (reject) S.l_acnt[l] = 0;
@@ -92,9 +91,9 @@ __device__ __forceinline__ int owner_of(const int *es, int s) {
     return lo;
 }
 
-__global__ __launch_bounds__(256) void k_add_alloc(Dev S, uint32_t seq) {
+__global__ __launch_bounds__(256) void k_add_alloc(Dev S) {
     __shared__ int s_es[256], s_nso[256], sbuf[4], s_base[2];
-    if (call_failed(S.ctl, seq)) return;
+    if (call_failed(S.ctl)) return;
     const int tid = threadIdx.x;
     const int l = blockIdx.x * 256 + tid;
     const bool valid = l < S.nlist;
@@ -138,8 +137,8 @@ template <bool VEC>
 __global__ __launch_bounds__(256) void k_add_scatter(Dev S, int n, const float *__restrict__ x,
                                                      const int64_t *__restrict__ ids,
                                                      const int32_t *__restrict__ assign,
-                                                     const int32_t *__restrict__ rank, uint32_t seq) {
-    if (call_failed(S.ctl, seq)) return;
+                                                     const int32_t *__restrict__ rank) {
+    if (call_failed(S.ctl)) return;
     const int gid = blockIdx.x * 256 + threadIdx.x;
     const int i = gid >> 4, sub = gid & 15;
     if (i >= n) return;
@@ -181,21 +180,21 @@ __global__ __launch_bounds__(256) void k_add_cleanup(Dev S, int n, const int64_t
 
 // ------------------------------------------------------------------ delete
 
-__device__ __forceinline__ bool rm_skip(const Dev &S, uint32_t seq, int mode) {
-    if (call_failed(S.ctl, seq)) return true;
-    return mode == 1 && S.ctl[CTL_UPSERT] != (int)seq;
+__device__ __forceinline__ bool rm_skip(const Dev &S, int mode) {
+    if (call_failed(S.ctl)) return true;
+    return mode == 1 && S.ctl[CTL_UPSERT] != S.ctl[CTL_SEQ];
 }
 
-__global__ __launch_bounds__(256) void k_rm_validate(Dev S, int n, const int64_t *__restrict__ ids, uint32_t seq) {
+__global__ __launch_bounds__(256) void k_rm_validate(Dev S, int n, const int64_t *__restrict__ ids) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
     const int64_t u = ids[i];
-    if (u < 0 || u >= S.id_capacity) fail_call(S.ctl, -3, seq);
+    if (u < 0 || u >= S.id_capacity) fail_call(S.ctl, -3);
 }
 
 __global__ __launch_bounds__(256) void k_rm_mark(Dev S, int n, const int64_t *__restrict__ ids,
-                                                 uint32_t *__restrict__ rec, uint32_t seq, int mode) {
-    if (rm_skip(S, seq, mode)) return;
+                                                 uint32_t *__restrict__ rec, int mode) {
+    if (rm_skip(S, mode)) return;
     const int i = blockIdx.x * 256 + threadIdx.x;
     const bool active = i < n;
     const uint32_t g = active ? atomicExch(&S.att[ids[i]], INVALID) : INVALID;
@@ -210,9 +209,9 @@ __global__ __launch_bounds__(256) void k_rm_mark(Dev S, int n, const int64_t *__
 }
 
 // One block: segment offsets of each list's survivor slots and new lengths.
-__global__ __launch_bounds__(1024) void k_rm_plan(Dev S, int64_t *n_removed, uint32_t seq, int mode) {
+__global__ __launch_bounds__(1024) void k_rm_plan(Dev S, int64_t *n_removed, int mode) {
     __shared__ int sbuf[16];
-    if (rm_skip(S, seq, mode)) {
+    if (rm_skip(S, mode)) {
         if (n_removed && threadIdx.x == 0) *n_removed = 0;
         return;
     }
@@ -237,8 +236,8 @@ __global__ __launch_bounds__(1024) void k_rm_plan(Dev S, int64_t *n_removed, uin
 // Each deleted entry of list l inspects one position of the tail window
 // [n', n); positions still holding a live entry are the survivors to move.
 __global__ __launch_bounds__(256) void k_rm_survivors(Dev S, int n, const uint32_t *__restrict__ rec,
-                                                      int32_t *__restrict__ seg, uint32_t seq, int mode) {
-    if (rm_skip(S, seq, mode)) return;
+                                                      int32_t *__restrict__ seg, int mode) {
+    if (rm_skip(S, mode)) return;
     const int i = blockIdx.x * 256 + threadIdx.x;
     const uint32_t g = i < n ? rec[i] : INVALID;
     const bool hit = g != INVALID;
@@ -259,8 +258,8 @@ __global__ __launch_bounds__(256) void k_rm_survivors(Dev S, int n, const uint32
 // Holes below n' take the survivors: the r-th hole of a list pairs with its
 // r-th survivor.  The payload copy of each move is done by the whole wave.
 __global__ __launch_bounds__(256) void k_rm_move(Dev S, int n, const uint32_t *__restrict__ rec,
-                                                 const int32_t *__restrict__ seg, uint32_t seq, int mode) {
-    if (rm_skip(S, seq, mode)) return;
+                                                 const int32_t *__restrict__ seg, int mode) {
+    if (rm_skip(S, mode)) return;
     const int i = blockIdx.x * 256 + threadIdx.x;
     const uint32_t g = i < n ? rec[i] : INVALID;
     const bool hit = g != INVALID;
@@ -293,9 +292,9 @@ __global__ __launch_bounds__(256) void k_rm_move(Dev S, int n, const uint32_t *_
 
 // Per list: new length, and the tail slabs (and table pages) past the new
 // end go back to the free stacks.
-__global__ __launch_bounds__(256) void k_rm_finalize(Dev S, uint32_t seq, int mode) {
+__global__ __launch_bounds__(256) void k_rm_finalize(Dev S, int mode) {
     __shared__ int s_es[256], s_nsn[256], sbuf[4], s_base[2];
-    if (rm_skip(S, seq, mode)) return;
+    if (rm_skip(S, mode)) return;
     const int tid = threadIdx.x;
     const int l = blockIdx.x * 256 + tid;
     const bool valid = l < S.nlist;
@@ -352,49 +351,56 @@ __global__ __launch_bounds__(256) void k_get_rows(Dev S, int n, const int64_t *_
     }
 }
 
+// Last kernel of an add or remove call: the next call gets a new sequence number.
+__global__ void k_call_end(int32_t *ctl) {
+    if (threadIdx.x == 0) ctl[CTL_SEQ] = ctl[CTL_SEQ] + 1;
+}
+
 // ------------------------------------------------------------------ launch
 
 static unsigned blocks(int64_t threads, int per = 256) { return (unsigned)((threads + per - 1) / per); }
 
-void launch_add_prepare(hipStream_t st, const Dev &S, int n, const int64_t *ids, uint32_t seq) {
-    hipLaunchKernelGGL(k_add_prepare, dim3(blocks(n)), dim3(256), 0, st, S, n, ids, seq);
+void launch_add_prepare(hipStream_t st, const Dev &S, int n, const int64_t *ids) {
+    hipLaunchKernelGGL(k_add_prepare, dim3(blocks(n)), dim3(256), 0, st, S, n, ids);
 }
 
-void launch_add_count(hipStream_t st, const Dev &S, int n, const int64_t *ids, const Batch &B, uint32_t seq) {
-    hipLaunchKernelGGL(k_add_count, dim3(blocks(n)), dim3(256), 0, st, S, n, ids, B.assign, B.rank, seq);
+void launch_add_count(hipStream_t st, const Dev &S, int n, const int64_t *ids, const Batch &B) {
+    hipLaunchKernelGGL(k_add_count, dim3(blocks(n)), dim3(256), 0, st, S, n, ids, B.assign, B.rank);
 }
 
-void launch_add_admit(hipStream_t st, const Dev &S, uint32_t seq) {
-    hipLaunchKernelGGL(k_add_admit, dim3(1), dim3(1024), 0, st, S, seq);
+void launch_add_admit(hipStream_t st, const Dev &S) {
+    hipLaunchKernelGGL(k_add_admit, dim3(1), dim3(1024), 0, st, S);
 }
 
-void launch_add_alloc(hipStream_t st, const Dev &S, uint32_t seq) {
-    hipLaunchKernelGGL(k_add_alloc, dim3(blocks(S.nlist)), dim3(256), 0, st, S, seq);
+void launch_add_alloc(hipStream_t st, const Dev &S) {
+    hipLaunchKernelGGL(k_add_alloc, dim3(blocks(S.nlist)), dim3(256), 0, st, S);
 }
 
-void launch_add_scatter(hipStream_t st, const Dev &S, int n, const float *x, const int64_t *ids, const Batch &B,
-                        uint32_t seq) {
+void launch_add_scatter(hipStream_t st, const Dev &S, int n, const float *x, const int64_t *ids, const Batch &B) {
     const bool vec = (S.d % 4 == 0) && (((uintptr_t)x & 15) == 0);
     if (vec)
         hipLaunchKernelGGL(k_add_scatter<true>, dim3(blocks((int64_t)n * 16)), dim3(256), 0, st, S, n, x, ids,
-                           B.assign, B.rank, seq);
+                           B.assign, B.rank);
     else
         hipLaunchKernelGGL(k_add_scatter<false>, dim3(blocks((int64_t)n * 16)), dim3(256), 0, st, S, n, x, ids,
-                           B.assign, B.rank, seq);
+                           B.assign, B.rank);
 }
 
 void launch_add_cleanup(hipStream_t st, const Dev &S, int n, const int64_t *ids) {
     hipLaunchKernelGGL(k_add_cleanup, dim3(blocks(n)), dim3(256), 0, st, S, n, ids);
 }
 
-void launch_remove(hipStream_t st, const Dev &S, int n, const int64_t *ids, int64_t *n_removed, const Batch &B,
-                   uint32_t seq, int mode) {
-    if (mode == 0) hipLaunchKernelGGL(k_rm_validate, dim3(blocks(n)), dim3(256), 0, st, S, n, ids, seq);
-    hipLaunchKernelGGL(k_rm_mark, dim3(blocks(n)), dim3(256), 0, st, S, n, ids, B.rec, seq, mode);
-    hipLaunchKernelGGL(k_rm_plan, dim3(1), dim3(1024), 0, st, S, n_removed, seq, mode);
-    hipLaunchKernelGGL(k_rm_survivors, dim3(blocks(n)), dim3(256), 0, st, S, n, B.rec, B.seg, seq, mode);
-    hipLaunchKernelGGL(k_rm_move, dim3(blocks(n)), dim3(256), 0, st, S, n, B.rec, B.seg, seq, mode);
-    hipLaunchKernelGGL(k_rm_finalize, dim3(blocks(S.nlist)), dim3(256), 0, st, S, seq, mode);
+void launch_remove(hipStream_t st, const Dev &S, int n, const int64_t *ids, int64_t *n_removed, const Batch &B, int mode) {
+    if (mode == 0) hipLaunchKernelGGL(k_rm_validate, dim3(blocks(n)), dim3(256), 0, st, S, n, ids);
+    hipLaunchKernelGGL(k_rm_mark, dim3(blocks(n)), dim3(256), 0, st, S, n, ids, B.rec, mode);
+    hipLaunchKernelGGL(k_rm_plan, dim3(1), dim3(1024), 0, st, S, n_removed, mode);
+    hipLaunchKernelGGL(k_rm_survivors, dim3(blocks(n)), dim3(256), 0, st, S, n, B.rec, B.seg, mode);
+    hipLaunchKernelGGL(k_rm_move, dim3(blocks(n)), dim3(256), 0, st, S, n, B.rec, B.seg, mode);
+    hipLaunchKernelGGL(k_rm_finalize, dim3(blocks(S.nlist)), dim3(256), 0, st, S, mode);
+}
+
+void launch_call_end(hipStream_t st, const Dev &S) {
+    hipLaunchKernelGGL(k_call_end, dim3(1), dim3(64), 0, st, S.ctl);
 }
 
 void launch_get_rows(hipStream_t st, const Dev &S, int n, const int64_t *ids, float *rows) {

@@ -71,30 +71,174 @@ __global__ __launch_bounds__(256) void k_inv_scatter(Dev S, int npairs, const in
     list_pairs[S.l_qoff[probes[p]] + r] = p;
 }
 
-// Lane i receives lane i-1's value (DPP wave_shr:1; lane 0 receives 0).
-__device__ __forceinline__ uint64_t shfl_up1_u64(uint64_t v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, 0x138, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), 0x138, 0xF, 0xF, false);
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
+    const int lo = __shfl_xor((int)(uint32_t)v, m);
+    const int hi = __shfl_xor((int)(uint32_t)(v >> 32), m);
     return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
 }
 
-// Insert the keys of all lanes that beat the current kcap-th best into the
-// sorted list held by lanes 0..kcap-1 (lanes >= kcap hold ~0).
-__device__ __forceinline__ void topk_insert(uint64_t &top, uint64_t key, int kcap) {
-    uint64_t thr = readlane_u64(top, kcap - 1);
-    uint64_t mask = ballot(key < thr);
+// ---------------------------------------------------------------- top-k
+//
+// Per query, the wave keeps its best keys sorted across the lanes (lane i
+// holds the i-th best, lanes >= kcap hold ~0).  A key enters only if it beats
+// the query's current k-th best (the threshold); such keys are appended to a
+// 64-entry LDS buffer with one ballot.  When the buffer is full, and at the
+// end of the list, the wave merges it into the sorted list: a bitonic sort of
+// the buffer (descending), an element-wise min against the list (the 64
+// smallest of both, as a bitonic sequence), and a bitonic merge.
+
+// Sort the wave's 64 keys across lanes, ascending or descending.
+__device__ __forceinline__ uint64_t wave_sort64(uint64_t v, bool asc) {
     const int ln = lane_id();
-    while (mask) {
-        const int src = __builtin_ctzll(mask);
-        mask &= mask - 1;
-        const uint64_t ck = readlane_u64(key, src);
-        if (ck >= thr) continue;
-        const int pos = __builtin_popcountll(ballot(top < ck));
-        const uint64_t up = shfl_up1_u64(top);
-        top = ln < pos ? top : (ln == pos ? ck : up);
-        if (ln >= kcap) top = ~0ull;
-        thr = readlane_u64(top, kcap - 1);
+#pragma unroll
+    for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const uint64_t p = shfl_xor_u64(v, j);
+            const bool up = ((ln & k) == 0) == asc;
+            const bool keep_min = ((ln & j) == 0) == up;
+            const uint64_t lo = p < v ? p : v, hi = p < v ? v : p;
+            v = keep_min ? lo : hi;
+        }
     }
+    return v;
+}
+
+// The 64 smallest keys of a (sorted ascending across lanes) and b (any
+// order), sorted ascending.
+__device__ __forceinline__ uint64_t merge_sorted_with(uint64_t a, uint64_t b) {
+    b = wave_sort64(b, false);
+    uint64_t c = a < b ? a : b;
+    const int ln = lane_id();
+#pragma unroll
+    for (int j = 32; j > 0; j >>= 1) {
+        const uint64_t p = shfl_xor_u64(c, j);
+        const uint64_t lo = p < c ? p : c, hi = p < c ? c : p;
+        c = (ln & j) == 0 ? lo : hi;
+    }
+    return c;
+}
+
+template <int T>
+struct TopK {
+    uint64_t top[T];   // sorted keys, per query
+    uint32_t thr[T];   // high word of the query's k-th best key (wave-uniform)
+    int cnt[T];        // keys waiting in the LDS buffer (wave-uniform)
+};
+
+// kq: LDS array with each query's k (0 = no results wanted).
+template <int T>
+__device__ __forceinline__ void topk_init(TopK<T> &K, const int *kq) {
+#pragma unroll
+    for (int t = 0; t < T; t++) {
+        K.top[t] = ~0ull;
+        K.thr[t] = kq[t] > 0 ? 0xFFFFFFFFu : 0u;
+        K.cnt[t] = 0;
+    }
+}
+
+template <int T>
+__device__ __forceinline__ void topk_flush(TopK<T> &K, int t, uint64_t *buf, const int *kq, int kcap) {
+    __syncthreads();
+    const int ln = lane_id();
+    const uint64_t b = ln < K.cnt[t] ? buf[t * 64 + ln] : ~0ull;
+    uint64_t c = merge_sorted_with(K.top[t], b);
+    c = ln < kcap ? c : ~0ull;
+    K.top[t] = c;
+    K.thr[t] = (uint32_t)(readlane_u64(c, kq[t] - 1) >> 32);
+    K.cnt[t] = 0;
+    __syncthreads();
+}
+
+// Offer one candidate per lane to query t: hi is the high word of its key
+// (ordered distance), id its low word.  Keys whose high word is at most the
+// threshold's are buffered (a superset of those that beat the k-th key; the
+// merge orders them exactly).
+template <int T>
+__device__ __forceinline__ void topk_offer(TopK<T> &K, int t, bool valid, uint32_t hi, uint32_t id,
+                                           uint64_t *buf, const int *kq, int kcap) {
+    bool pass = valid && hi <= K.thr[t];
+    uint64_t mask = ballot(pass);
+    if (mask) {
+        int n = __builtin_popcountll(mask);
+        if (K.cnt[t] + n > 64) {   // no room: merge first, then re-test against the new threshold
+            topk_flush(K, t, buf, kq, kcap);
+            pass = valid && hi <= K.thr[t];
+            mask = ballot(pass);
+            n = __builtin_popcountll(mask);
+        }
+        if (pass)
+            buf[t * 64 + K.cnt[t] + (int)__builtin_popcountll(mask & lanemask_lt())] = ((uint64_t)hi << 32) | id;
+        K.cnt[t] += n;
+        if (K.cnt[t] == 64) topk_flush(K, t, buf, kq, kcap);
+    }
+}
+
+// High word of a result key: L2 distances are never negative (the canonical
+// sum starts at +0 and adds squares), so their order bits are bits | sign.
+template <int METRIC>
+__device__ __forceinline__ uint32_t key_hi(float v) {
+    return METRIC == 0 ? (__float_as_uint(v) | 0x80000000u) : ~ord_bits(v);
+}
+
+// Distances of 64 consecutive list positions (lane <-> slot) to the T queries
+// of a tile, in the canonical order (dimensions ascending, one fma each), then
+// offered to each query's top-k.  QV(t, c) gives query t's dimension chunk c.
+#define SIVF_SCAN_BODY(QV)                                                                       \
+    const int len = S.len[l];                                                                    \
+    const int nslab = cdiv_s(len, C);                                                            \
+    int wbase = -(1 << 30), wslab = 0; /* lane j holds the slab of ordinal wbase + j */          \
+    for (int base = 0; base < len; base += 64) {                                                 \
+        const int p = base + lane;                                                               \
+        const bool valid = p < len;                                                              \
+        const int pc = valid ? p : len - 1;                                                      \
+        const int last_ord = (min(base + 63, len - 1)) / C;                                      \
+        if (last_ord >= wbase + 64) {                                                            \
+            wbase = base / C;                                                                    \
+            wslab = (wbase + lane < nslab) ? slab_of(S, l, wbase + lane) : 0;                    \
+        }                                                                                        \
+        const int slab = __shfl(wslab, pc / C - wbase);                                          \
+        const int slot = pc % C;                                                                 \
+        const float4 *xp = S.data + (int64_t)slab * dp4 * C + slot;                              \
+        float acc[T];                                                                            \
+        _Pragma("unroll") for (int t = 0; t < T; t++) acc[t] = 0.f;                              \
+        _Pragma("unroll 2") for (int c = 0; c < dp4; c++) {                                      \
+            const float4 xv = xp[(int64_t)c * C];                                                \
+            _Pragma("unroll") for (int t = 0; t < T; t++) {                                      \
+                const float4 qv = QV(t, c);                                                      \
+                if (METRIC == 0) {                                                               \
+                    float e;                                                                     \
+                    e = qv.x - xv.x;                                                             \
+                    acc[t] = __builtin_fmaf(e, e, acc[t]);                                       \
+                    e = qv.y - xv.y;                                                             \
+                    acc[t] = __builtin_fmaf(e, e, acc[t]);                                       \
+                    e = qv.z - xv.z;                                                             \
+                    acc[t] = __builtin_fmaf(e, e, acc[t]);                                       \
+                    e = qv.w - xv.w;                                                             \
+                    acc[t] = __builtin_fmaf(e, e, acc[t]);                                       \
+                } else {                                                                         \
+                    acc[t] = __builtin_fmaf(qv.x, xv.x, acc[t]);                                 \
+                    acc[t] = __builtin_fmaf(qv.y, xv.y, acc[t]);                                 \
+                    acc[t] = __builtin_fmaf(qv.z, xv.z, acc[t]);                                 \
+                    acc[t] = __builtin_fmaf(qv.w, xv.w, acc[t]);                                 \
+                }                                                                                \
+            }                                                                                    \
+        }                                                                                        \
+        const uint32_t id = S.sids[(int64_t)slab * C + slot];                                    \
+        _Pragma("unroll") for (int t = 0; t < T; t++) {                                          \
+            if (t < nt) topk_offer(K, t, valid, key_hi<METRIC>(acc[t]), id, buf, skq, kcap);     \
+        }                                                                                        \
+    }                                                                                            \
+    _Pragma("unroll") for (int t = 0; t < T; t++) {                                              \
+        if (t < nt) {                                                                            \
+            if (K.cnt[t] > 0) topk_flush(K, t, buf, skq, kcap);                                  \
+            if (lane < kcap) partials[(int64_t)pairs[t] * kcap + lane] = K.top[t];               \
+        }                                                                                        \
+    }
+
+__device__ __forceinline__ int query_k(const int32_t *kpq, int k, int qi) {
+    int kq = kpq ? kpq[qi] : k;
+    return kq < 0 ? 0 : (kq > k ? k : kq);
 }
 
 // Queries come straight from the caller's rows with wave-uniform addresses,
@@ -105,8 +249,13 @@ template <int T, int METRIC>
 __global__ __launch_bounds__(64) void k_scan_sq(Dev S, const int32_t *__restrict__ item_list,
                                                 const int32_t *__restrict__ item_tile,
                                                 const int32_t *__restrict__ list_pairs,
-                                                const float *__restrict__ q, int np_stride, int kcap,
+                                                const float *__restrict__ q, int np_stride, int kcap, int k,
+                                                const int32_t *__restrict__ kpq,
                                                 uint64_t *__restrict__ partials, int per_xcd) {
+    __shared__ uint64_t buf[T * 64];
+    __shared__ int skq[T];
+    // Consecutive items (tiles of the same list) go to the same XCD, so a
+    // list's slabs are fetched once into that XCD's L2 and reused.
     const int w = blockIdx.x;
     const int item = (w & 7) * per_xcd + (w >> 3);
     if (item >= S.ctl[CTL_NITEMS]) return;
@@ -116,80 +265,30 @@ __global__ __launch_bounds__(64) void k_scan_sq(Dev S, const int32_t *__restrict
     const int dp4 = S.dp4, C = S.C;
     const int32_t *pairs = list_pairs + S.l_qoff[l] + tile * T;
     const float4 *qrow[T];
+    TopK<T> K;
 #pragma unroll
     for (int t = 0; t < T; t++) {
         const int pr = pairs[t < nt ? t : 0];
         qrow[t] = reinterpret_cast<const float4 *>(q + (int64_t)(pr / np_stride) * S.d);
     }
-    uint64_t top[T];
-#pragma unroll
-    for (int t = 0; t < T; t++) top[t] = ~0ull;
-    const int len = S.len[l];
-    const int nslab = cdiv_s(len, C);
-    int wbase = -(1 << 30), wslab = 0;   // lane j holds the slab of ordinal wbase + j
-    for (int base = 0; base < len; base += 64) {
-        const int p = base + lane;
-        const bool valid = p < len;
-        const int pc = valid ? p : len - 1;
-        const int last_ord = (min(base + 63, len - 1)) / C;
-        if (last_ord >= wbase + 64) {
-            wbase = base / C;
-            wslab = (wbase + lane < nslab) ? slab_of(S, l, wbase + lane) : 0;
-        }
-        const int slab = __shfl(wslab, pc / C - wbase);
-        const int slot = pc % C;
-        const float4 *xp = S.data + (int64_t)slab * dp4 * C + slot;
-        float acc[T];
-#pragma unroll
-        for (int t = 0; t < T; t++) acc[t] = 0.f;
-#pragma unroll 2
-        for (int c = 0; c < dp4; c++) {
-            const float4 xv = xp[(int64_t)c * C];
-#pragma unroll
-            for (int t = 0; t < T; t++) {
-                const float4 qv = qrow[t][c];
-                if (METRIC == 0) {
-                    float e;
-                    e = qv.x - xv.x;
-                    acc[t] = __builtin_fmaf(e, e, acc[t]);
-                    e = qv.y - xv.y;
-                    acc[t] = __builtin_fmaf(e, e, acc[t]);
-                    e = qv.z - xv.z;
-                    acc[t] = __builtin_fmaf(e, e, acc[t]);
-                    e = qv.w - xv.w;
-                    acc[t] = __builtin_fmaf(e, e, acc[t]);
-                } else {
-                    acc[t] = __builtin_fmaf(qv.x, xv.x, acc[t]);
-                    acc[t] = __builtin_fmaf(qv.y, xv.y, acc[t]);
-                    acc[t] = __builtin_fmaf(qv.z, xv.z, acc[t]);
-                    acc[t] = __builtin_fmaf(qv.w, xv.w, acc[t]);
-                }
-            }
-        }
-        const uint32_t id = S.sids[(int64_t)slab * C + slot];
-#pragma unroll
-        for (int t = 0; t < T; t++) {
-            if (t < nt) {
-                const uint64_t key = valid ? make_key(acc[t], id, METRIC) : ~0ull;
-                topk_insert(top[t], key, kcap);
-            }
-        }
-    }
-#pragma unroll
-    for (int t = 0; t < T; t++)
-        if (t < nt && lane < kcap) partials[(int64_t)pairs[t] * kcap + lane] = top[t];
+    if (lane < T) skq[lane] = lane < nt ? query_k(kpq, k, pairs[lane] / np_stride) : 0;
+    __syncthreads();
+    topk_init(K, skq);
+#define SIVF_QV_SQ(t, c) qrow[t][c]
+    SIVF_SCAN_BODY(SIVF_QV_SQ)
+#undef SIVF_QV_SQ
 }
 
+// General path: query rows of any alignment or dimension, staged in LDS.
 template <int T, int METRIC>
 __global__ __launch_bounds__(64) void k_scan(Dev S, const int32_t *__restrict__ item_list,
                                              const int32_t *__restrict__ item_tile,
                                              const int32_t *__restrict__ list_pairs, const float *__restrict__ q,
-                                             int np_stride, int kcap, uint64_t *__restrict__ partials,
-                                             int per_xcd) {
+                                             int np_stride, int kcap, int k, const int32_t *__restrict__ kpq,
+                                             uint64_t *__restrict__ partials, int per_xcd) {
     extern __shared__ float4 sq[];   // [T][dp4]
-    __shared__ int spair[T];
-    // Consecutive items (tiles of the same list) go to the same XCD, so a
-    // list's slabs are fetched once into that XCD's L2 and reused.
+    __shared__ uint64_t buf[T * 64];
+    __shared__ int skq[T];
     const int w = blockIdx.x;
     const int item = (w & 7) * per_xcd + (w >> 3);
     if (item >= S.ctl[CTL_NITEMS]) return;
@@ -197,10 +296,10 @@ __global__ __launch_bounds__(64) void k_scan(Dev S, const int32_t *__restrict__ 
     const int l = item_list[item], tile = item_tile[item];
     const int nt = min(T, S.l_qcs[l] - tile * T);
     const int dp4 = S.dp4, C = S.C, d = S.d;
-    if (lane < T) spair[lane] = lane < nt ? list_pairs[S.l_qoff[l] + tile * T + lane] : -1;
-    __syncthreads();
+    const int32_t *pairs = list_pairs + S.l_qoff[l] + tile * T;
+    TopK<T> K;
     for (int t = 0; t < T; t++) {
-        const int pr = spair[t];
+        const int pr = t < nt ? pairs[t] : -1;
         const float *qr = q + (int64_t)(pr < 0 ? 0 : pr / np_stride) * d;
         for (int c = lane; c < dp4; c += 64) {
             float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -214,72 +313,15 @@ __global__ __launch_bounds__(64) void k_scan(Dev S, const int32_t *__restrict__ 
             sq[t * dp4 + c] = v;
         }
     }
+    if (lane < T) skq[lane] = lane < nt ? query_k(kpq, k, pairs[lane] / np_stride) : 0;
     __syncthreads();
-
-    uint64_t top[T];
-#pragma unroll
-    for (int t = 0; t < T; t++) top[t] = ~0ull;
-    const int len = S.len[l];
-    const int nslab = cdiv_s(len, C);
-    int wbase = -(1 << 30), wslab = 0;   // lane j holds the slab of ordinal wbase + j
-    for (int base = 0; base < len; base += 64) {
-        const int p = base + lane;
-        const bool valid = p < len;
-        const int pc = valid ? p : len - 1;
-        const int last_ord = (min(base + 63, len - 1)) / C;
-        if (last_ord >= wbase + 64) {
-            wbase = base / C;
-            wslab = (wbase + lane < nslab) ? slab_of(S, l, wbase + lane) : 0;
-        }
-        const int slab = __shfl(wslab, pc / C - wbase);
-        const int slot = pc % C;
-        const float4 *xp = S.data + (int64_t)slab * dp4 * C + slot;
-        float acc[T];
-#pragma unroll
-        for (int t = 0; t < T; t++) acc[t] = 0.f;
-#pragma unroll 2
-        for (int c = 0; c < dp4; c++) {
-            const float4 xv = xp[(int64_t)c * C];
-#pragma unroll
-            for (int t = 0; t < T; t++) {
-                const float4 qv = sq[t * dp4 + c];
-                if (METRIC == 0) {
-                    float e;
-                    e = qv.x - xv.x;
-                    acc[t] = __builtin_fmaf(e, e, acc[t]);
-                    e = qv.y - xv.y;
-                    acc[t] = __builtin_fmaf(e, e, acc[t]);
-                    e = qv.z - xv.z;
-                    acc[t] = __builtin_fmaf(e, e, acc[t]);
-                    e = qv.w - xv.w;
-                    acc[t] = __builtin_fmaf(e, e, acc[t]);
-                } else {
-                    acc[t] = __builtin_fmaf(qv.x, xv.x, acc[t]);
-                    acc[t] = __builtin_fmaf(qv.y, xv.y, acc[t]);
-                    acc[t] = __builtin_fmaf(qv.z, xv.z, acc[t]);
-                    acc[t] = __builtin_fmaf(qv.w, xv.w, acc[t]);
-                }
-            }
-        }
-        const uint32_t id = S.sids[(int64_t)slab * C + slot];
-#pragma unroll
-        for (int t = 0; t < T; t++) {
-            if (t < nt) {
-                const uint64_t key = valid ? make_key(acc[t], id, METRIC) : ~0ull;
-                topk_insert(top[t], key, kcap);
-            }
-        }
-    }
-#pragma unroll
-    for (int t = 0; t < T; t++)
-        if (t < nt && lane < kcap) partials[(int64_t)spair[t] * kcap + lane] = top[t];
+    topk_init(K, skq);
+#define SIVF_QV_LDS(t, c) sq[(t) * dp4 + (c)]
+    SIVF_SCAN_BODY(SIVF_QV_LDS)
+#undef SIVF_QV_LDS
 }
 
-__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
-    const int lo = __shfl_xor((int)(uint32_t)v, m);
-    const int hi = __shfl_xor((int)(uint32_t)(v >> 32), m);
-    return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
-}
+#undef SIVF_SCAN_BODY
 
 // One wave per query: repeatedly take the smallest head among the query's
 // probe partial lists (each sorted, kcap long).
@@ -353,24 +395,24 @@ int search_tile(int d) { return d <= 1024 ? 8 : 4; }
 
 template <int T>
 static void launch_scan_t(hipStream_t st, const Dev &S, const SearchBufs &W, const float *q, int np_stride,
-                          int kcap, unsigned grid, int per_xcd) {
-    const size_t smem = (size_t)T * S.dp4 * sizeof(float4);
+                          int kcap, int k, const int32_t *kpq, unsigned grid, int per_xcd) {
     const bool sq = (S.d % 4 == 0) && (((uintptr_t)q & 15) == 0);
     if (sq) {
         if (S.metric == 0)
             hipLaunchKernelGGL((k_scan_sq<T, 0>), dim3(grid), dim3(64), 0, st, S, W.item_list, W.item_tile,
-                               W.list_pairs, q, np_stride, kcap, W.partials, per_xcd);
+                               W.list_pairs, q, np_stride, kcap, k, kpq, W.partials, per_xcd);
         else
             hipLaunchKernelGGL((k_scan_sq<T, 1>), dim3(grid), dim3(64), 0, st, S, W.item_list, W.item_tile,
-                               W.list_pairs, q, np_stride, kcap, W.partials, per_xcd);
+                               W.list_pairs, q, np_stride, kcap, k, kpq, W.partials, per_xcd);
         return;
     }
+    const size_t smem = (size_t)T * S.dp4 * sizeof(float4);
     if (S.metric == 0)
         hipLaunchKernelGGL((k_scan<T, 0>), dim3(grid), dim3(64), smem, st, S, W.item_list, W.item_tile,
-                           W.list_pairs, q, np_stride, kcap, W.partials, per_xcd);
+                           W.list_pairs, q, np_stride, kcap, k, kpq, W.partials, per_xcd);
     else
         hipLaunchKernelGGL((k_scan<T, 1>), dim3(grid), dim3(64), smem, st, S, W.item_list, W.item_tile,
-                           W.list_pairs, q, np_stride, kcap, W.partials, per_xcd);
+                           W.list_pairs, q, np_stride, kcap, k, kpq, W.partials, per_xcd);
 }
 
 void launch_search_plan(hipStream_t st, const Dev &S, const SearchBufs &W, int nq, int np_stride) {
@@ -383,7 +425,7 @@ void launch_search_plan(hipStream_t st, const Dev &S, const SearchBufs &W, int n
 }
 
 void launch_search_scan(hipStream_t st, const Dev &S, const SearchBufs &W, int nq, const float *q, int np_stride,
-                        int kcap) {
+                        int kcap, int k, const int32_t *k_per_query) {
     const int npairs = nq * np_stride;
     const int T = search_tile(S.d);
     // items <= sum over lists of ceil(pairs_l / T) <= npairs / T + min(nlist, npairs)
@@ -391,9 +433,9 @@ void launch_search_scan(hipStream_t st, const Dev &S, const SearchBufs &W, int n
     const int per_xcd = (int)((bound + 7) / 8);
     const unsigned grid = (unsigned)(8 * per_xcd);
     if (T == 8)
-        launch_scan_t<8>(st, S, W, q, np_stride, kcap, grid, per_xcd);
+        launch_scan_t<8>(st, S, W, q, np_stride, kcap, k, k_per_query, grid, per_xcd);
     else
-        launch_scan_t<4>(st, S, W, q, np_stride, kcap, grid, per_xcd);
+        launch_scan_t<4>(st, S, W, q, np_stride, kcap, k, k_per_query, grid, per_xcd);
 }
 
 void launch_search_merge(hipStream_t st, const Dev &S, const SearchBufs &W, int nq, int np_stride, int kcap,

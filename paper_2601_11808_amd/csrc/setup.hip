@@ -59,6 +59,7 @@ __global__ __launch_bounds__(256) void k_init_cent(float *cent, float *cn2, doub
 __global__ void k_init_ctl(int32_t *ctl, int64_t num_slabs, int64_t num_pages) {
     const int i = threadIdx.x;
     if (i < CTL_WORDS) ctl[i] = 0;
+    if (i == CTL_GATE || i == CTL_UPSERT) ctl[i] = -1;
     if (i == CTL_SLAB_TOP) ctl[i] = (int32_t)num_slabs;
     if (i == CTL_PAGE_TOP) ctl[i] = (int32_t)num_pages;
 }

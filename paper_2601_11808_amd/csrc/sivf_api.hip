@@ -119,7 +119,6 @@ struct sivf_index {
     SearchBufs W{};
     float *dt = nullptr;
     char *ws = nullptr;
-    uint32_t seq = 0;
     hipStream_t last = nullptr;
     bool broken = false;
     bool prof = false;
@@ -129,11 +128,6 @@ struct sivf_index {
 namespace {
 
 hipStream_t as_stream(void *s) { return (hipStream_t)s; }
-
-uint32_t next_seq(sivf_index *ix) {
-    ix->seq = ix->seq == 0x7FFFFFFF ? 1 : ix->seq + 1;
-    return ix->seq;
-}
 
 sivf_status launched(sivf_index *ix) {
     if (!dev_ok(hipGetLastError())) {
@@ -182,16 +176,16 @@ void prof_end(sivf_index *ix, int kind, int slot, hipStream_t st) {
 
 // Coarse selection over rows [0, n) in chunks that fit the scratch.
 void coarse(sivf_index *ix, hipStream_t st, const float *x, int64_t n, int m, const int32_t *m_per_row, int mmax,
-            int32_t *out, int out_stride, uint32_t seq) {
+            int32_t *out, int out_stride, int gated) {
     const Dev &S = ix->S;
     const int dpad = S.dp4 * 4;
     for (int64_t r0 = 0; r0 < n; r0 += ix->L.coarse_rows) {
         const int nr = (int)((n - r0) < ix->L.coarse_rows ? (n - r0) : ix->L.coarse_rows);
         const float *xr = x + r0 * S.d;
-        launch_coarse_gemm(st, xr, nr, S.d, S.cent, dpad, S.cn2, S.nlist, S.metric, ix->dt, S.ctl, seq);
+        launch_coarse_gemm(st, xr, nr, S.d, S.cent, dpad, S.cn2, S.nlist, S.metric, ix->dt, S.ctl, gated);
         launch_coarse_select(st, ix->dt, xr, nr, S.d, S.cent, dpad, S.cnorm, S.cmax, S.nlist, S.metric, m,
                              m_per_row ? m_per_row + r0 : nullptr, mmax, out + r0 * out_stride, out_stride,
-                             S.ctl, seq);
+                             S.ctl, gated);
     }
 }
 
@@ -201,16 +195,16 @@ sivf_status do_add(sivf_index *ix, int64_t n, const float *x, const int64_t *ids
     if (n == 0) return SIVF_OK;
     const Dev &S = ix->S;
     const int nn = (int)n;
-    const uint32_t seq = next_seq(ix);
     const int ps = prof_begin(ix, SIVF_PROF_ADD, st);
-    launch_add_prepare(st, S, nn, ids, seq);
-    coarse(ix, st, x, n, 1, nullptr, 1, ix->B.assign, 1, seq);
-    launch_add_count(st, S, nn, ids, ix->B, seq);
-    launch_add_admit(st, S, seq);
-    launch_remove(st, S, nn, ids, nullptr, ix->B, seq, 1);
-    launch_add_alloc(st, S, seq);
-    launch_add_scatter(st, S, nn, x, ids, ix->B, seq);
+    launch_add_prepare(st, S, nn, ids);
+    coarse(ix, st, x, n, 1, nullptr, 1, ix->B.assign, 1, 1);
+    launch_add_count(st, S, nn, ids, ix->B);
+    launch_add_admit(st, S);
+    launch_remove(st, S, nn, ids, nullptr, ix->B, 1);
+    launch_add_alloc(st, S);
+    launch_add_scatter(st, S, nn, x, ids, ix->B);
     launch_add_cleanup(st, S, nn, ids);
+    launch_call_end(st, S);
     prof_end(ix, SIVF_PROF_ADD, ps, st);
     return launched(ix);
 }
@@ -222,9 +216,9 @@ sivf_status do_remove(sivf_index *ix, int64_t n, const int64_t *ids, int64_t *n_
         if (n_removed) launch_fill_i64(st, n_removed, 1, 0);
         return launched(ix);
     }
-    const uint32_t seq = next_seq(ix);
     const int ps = prof_begin(ix, SIVF_PROF_REMOVE, st);
-    launch_remove(st, ix->S, (int)n, ids, n_removed, ix->B, seq, 0);
+    launch_remove(st, ix->S, (int)n, ids, n_removed, ix->B, 0);
+    launch_call_end(st, ix->S);
     prof_end(ix, SIVF_PROF_REMOVE, ps, st);
     return launched(ix);
 }
@@ -245,7 +239,7 @@ sivf_status do_search(sivf_index *ix, int64_t nq, const float *q, int32_t k, con
     prof_end(ix, SIVF_PROF_COARSE, pc, st);
     launch_search_plan(st, ix->S, ix->W, (int)nq, stride);
     const int pk = prof_begin(ix, SIVF_PROF_SCAN, st);
-    launch_search_scan(st, ix->S, ix->W, (int)nq, q, stride, ix->L.kcap);
+    launch_search_scan(st, ix->S, ix->W, (int)nq, q, stride, ix->L.kcap, k, kpq);
     prof_end(ix, SIVF_PROF_SCAN, pk, st);
     const int pm = prof_begin(ix, SIVF_PROF_MERGE, st);
     launch_search_merge(st, ix->S, ix->W, (int)nq, stride, ix->L.kcap, k, kpq, dist, labels);
@@ -317,7 +311,6 @@ sivf_status sivf_create(const sivf_config *cfg, const float *centroids, void *wo
     ix->W.item_list = (int32_t *)(w + L.item_list);
     ix->W.item_tile = (int32_t *)(w + L.item_tile);
     ix->W.partials = (uint64_t *)(w + L.partials);
-    ix->seq = 0;
     ix->last = as_stream(stream);
     launch_init_state(as_stream(stream), S, centroids);
     if (!dev_ok(hipGetLastError())) {
@@ -380,16 +373,15 @@ sivf_status sivf_search(sivf_index *ix, int64_t nq, const float *q, int32_t k, c
     return do_search(ix, nq, q, k, k_per_query, nprobe, nprobe_per_query, dist, labels, as_stream(stream));
 }
 
-sivf_status sivf_step(sivf_index *ix, const sivf_step_args *a, void *stream) {
-    if (!ix || !a) return SIVF_ERR_ARG;
-    if (ix->broken) return SIVF_ERR_STATE;
+static bool step_args_ok(const sivf_index *ix, const sivf_step_args *a) {
     const sivf_config &c = ix->cfg;
-    if (a->n_add < 0 || a->n_add > c.max_batch || a->n_remove < 0 || a->n_remove > c.max_batch) return SIVF_ERR_ARG;
-    if (a->nq < 0 || a->nq > c.max_queries) return SIVF_ERR_ARG;
-    if (a->nq > 0 && (a->k < 1 || a->k > c.max_k || a->nprobe < 1 || a->nprobe > c.max_nprobe))
-        return SIVF_ERR_ARG;
-    hipStream_t st = as_stream(stream);
-    ix->last = st;
+    if (a->n_add < 0 || a->n_add > c.max_batch || a->n_remove < 0 || a->n_remove > c.max_batch) return false;
+    if (a->nq < 0 || a->nq > c.max_queries) return false;
+    if (a->nq > 0 && (a->k < 1 || a->k > c.max_k || a->nprobe < 1 || a->nprobe > c.max_nprobe)) return false;
+    return true;
+}
+
+static sivf_status enqueue_step(sivf_index *ix, const sivf_step_args *a, hipStream_t st) {
     sivf_status s = do_add(ix, a->n_add, a->x, a->add_ids, st);
     if (s != SIVF_OK) return s;
     if (a->nq > 0) {
@@ -397,6 +389,74 @@ sivf_status sivf_step(sivf_index *ix, const sivf_step_args *a, void *stream) {
         if (s != SIVF_OK) return s;
     }
     return do_remove(ix, a->n_remove, a->remove_ids, a->n_removed, st);
+}
+
+struct sivf_graph {
+    sivf_index *ix;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+sivf_status sivf_graph_create(sivf_index *ix, const sivf_step_args *a, sivf_graph **out) {
+    if (!ix || !a || !out) return SIVF_ERR_ARG;
+    *out = nullptr;
+    if (ix->broken) return SIVF_ERR_STATE;
+    if (!step_args_ok(ix, a)) return SIVF_ERR_ARG;
+    hipStream_t cs;
+    if (!dev_ok(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking))) return SIVF_ERR_DEVICE;
+    const bool prof = ix->prof;
+    ix->prof = false;
+    hipGraph_t graph = nullptr;
+    sivf_status s = SIVF_OK;
+    if (!dev_ok(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal))) {
+        s = SIVF_ERR_DEVICE;
+    } else {
+        s = enqueue_step(ix, a, cs);
+        if (!dev_ok(hipStreamEndCapture(cs, &graph)) && s == SIVF_OK) s = SIVF_ERR_DEVICE;
+    }
+    ix->prof = prof;
+    (void)hipStreamDestroy(cs);
+    if (s != SIVF_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return s;
+    }
+    hipGraphExec_t exec;
+    if (!dev_ok(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0))) {
+        (void)hipGraphDestroy(graph);
+        return SIVF_ERR_DEVICE;
+    }
+    sivf_graph *g = new (std::nothrow) sivf_graph{ix, graph, exec};
+    if (!g) {
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(graph);
+        return SIVF_ERR_STATE;
+    }
+    *out = g;
+    return SIVF_OK;
+}
+
+sivf_status sivf_graph_launch(sivf_graph *g, void *stream) {
+    if (!g) return SIVF_ERR_ARG;
+    if (g->ix->broken) return SIVF_ERR_STATE;
+    g->ix->last = as_stream(stream);
+    return dev_ok(hipGraphLaunch(g->exec, as_stream(stream))) ? SIVF_OK : SIVF_ERR_DEVICE;
+}
+
+sivf_status sivf_graph_destroy(sivf_graph *g) {
+    if (!g) return SIVF_ERR_ARG;
+    (void)hipGraphExecDestroy(g->exec);
+    (void)hipGraphDestroy(g->graph);
+    delete g;
+    return SIVF_OK;
+}
+
+sivf_status sivf_step(sivf_index *ix, const sivf_step_args *a, void *stream) {
+    if (!ix || !a) return SIVF_ERR_ARG;
+    if (ix->broken) return SIVF_ERR_STATE;
+    if (!step_args_ok(ix, a)) return SIVF_ERR_ARG;
+    hipStream_t st = as_stream(stream);
+    ix->last = st;
+    return enqueue_step(ix, a, st);
 }
 
 sivf_status sivf_assign(sivf_index *ix, int64_t n, const float *x, int32_t *lists, void *stream) {

@@ -32,6 +32,7 @@ enum Ctl {
     CTL_GATE = 3,       // sequence number of the call that failed (its later kernels skip)
     CTL_UPSERT = 4,     // sequence number of the add call that holds live ids
     CTL_NITEMS = 5,     // search: work items of the current call
+    CTL_SEQ = 6,        // sequence number of the current add/remove call; its last kernel bumps it
     CTL_WORDS = 64
 };
 
@@ -126,14 +127,14 @@ __device__ __forceinline__ int wave_agg_inc(int32_t *counters, int key, bool act
 }
 
 // Record the first data-dependent error of a call and stop its later kernels.
-__device__ __forceinline__ void fail_call(int32_t *ctl, int status, uint32_t seq) {
+// The call's sequence number lives on the device, so a call replayed from a
+// captured graph gets a fresh one each time.
+__device__ __forceinline__ void fail_call(int32_t *ctl, int status) {
     atomicCAS(&ctl[CTL_STATUS], 0, status);
-    atomicExch(&ctl[CTL_GATE], (int)seq);
+    atomicExch(&ctl[CTL_GATE], ctl[CTL_SEQ]);
 }
 
-__device__ __forceinline__ bool call_failed(const int32_t *ctl, uint32_t seq) {
-    return __builtin_nontemporal_load(&ctl[CTL_GATE]) == (int)seq;
-}
+__device__ __forceinline__ bool call_failed(const int32_t *ctl) { return ctl[CTL_GATE] == ctl[CTL_SEQ]; }
 
 // Inclusive sum over the 64 lanes of a wave.
 __device__ __forceinline__ int wave_incl_scan(int v) {

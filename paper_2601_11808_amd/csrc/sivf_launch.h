@@ -15,27 +15,28 @@ void launch_init_state(hipStream_t st, const Dev &S, const float *centroids);
 size_t coarse_select_smem(int dpad, int mmax);
 void launch_coarse_gemm(hipStream_t st, const float *X, int n, int d, const float *cent, int dpad,
                         const float *cn2, int nlist, int metric, float *out, const int32_t *ctl,
-                        uint32_t seq);
+                        int gated);
 void launch_coarse_select(hipStream_t st, const float *dt, const float *X, int n, int d, const float *cent,
                           int dpad, const double *cnorm, const double *cmax, int nlist, int metric,
                           int m_uniform, const int32_t *m_per_row, int mmax, int32_t *out, int out_stride,
-                          const int32_t *ctl, uint32_t seq);
+                          const int32_t *ctl, int gated);
 
 // ---- mutation (mutate.hip)
 struct Batch {
     int32_t *assign, *rank, *seg;
     uint32_t *rec;
 };
-void launch_add_prepare(hipStream_t st, const Dev &S, int n, const int64_t *ids, uint32_t seq);
-void launch_add_count(hipStream_t st, const Dev &S, int n, const int64_t *ids, const Batch &B, uint32_t seq);
-void launch_add_admit(hipStream_t st, const Dev &S, uint32_t seq);
-void launch_add_alloc(hipStream_t st, const Dev &S, uint32_t seq);
+void launch_add_prepare(hipStream_t st, const Dev &S, int n, const int64_t *ids);
+void launch_add_count(hipStream_t st, const Dev &S, int n, const int64_t *ids, const Batch &B);
+void launch_add_admit(hipStream_t st, const Dev &S);
+void launch_add_alloc(hipStream_t st, const Dev &S);
 void launch_add_scatter(hipStream_t st, const Dev &S, int n, const float *x, const int64_t *ids,
-                        const Batch &B, uint32_t seq);
+                        const Batch &B);
 void launch_add_cleanup(hipStream_t st, const Dev &S, int n, const int64_t *ids);
 // mode 0: a remove call; mode 1: the delete half of an upsert inside an add call
 void launch_remove(hipStream_t st, const Dev &S, int n, const int64_t *ids, int64_t *n_removed,
-                   const Batch &B, uint32_t seq, int mode);
+                   const Batch &B, int mode);
+void launch_call_end(hipStream_t st, const Dev &S);
 void launch_get_rows(hipStream_t st, const Dev &S, int n, const int64_t *ids, float *rows);
 void launch_fill_i64(hipStream_t st, int64_t *p, int64_t n, int64_t v);
 
@@ -47,7 +48,7 @@ struct SearchBufs {
 int search_tile(int d);
 void launch_search_plan(hipStream_t st, const Dev &S, const SearchBufs &W, int nq, int np_stride);
 void launch_search_scan(hipStream_t st, const Dev &S, const SearchBufs &W, int nq, const float *q, int np_stride,
-                        int kcap);
+                        int kcap, int k, const int32_t *k_per_query);
 void launch_search_merge(hipStream_t st, const Dev &S, const SearchBufs &W, int nq, int np_stride, int kcap,
                          int k, const int32_t *k_per_query, float *dist, int64_t *labels);
 

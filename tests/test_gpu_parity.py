@@ -269,3 +269,40 @@ def test_empty_and_padding_cases():
         assert p.remove(np.arange(7)) == 0
         p.check_search(q, 5, 6)
         p.check_state()
+
+
+def test_graph_replay_matches_oracle():
+    """A window step captured once as a HIP graph and replayed on refilled
+    buffers gives the oracle's results on every replay, with eager calls of
+    the program between replays."""
+    import torch
+    w = workloads.tiny()
+    x, ids = w.base()
+    q = w.queries()
+    p = Pair(w.dim, w.nlist, w.centroids, w.metric, w.slab, num_slabs=400, id_capacity=8192,
+             max_batch=4096, max_queries=64, max_k=16, max_nprobe=16)
+    assert p.add(x, ids) == 0
+    dev = torch.device("cuda:0")
+    xb = torch.empty((w.batch, w.dim), dtype=torch.float32, device=dev)
+    ib = torch.empty(w.batch, dtype=torch.int64, device=dev)
+    rb = torch.empty(w.batch, dtype=torch.int64, device=dev)
+    qb = torch.from_numpy(q).to(dev)
+    dist = torch.empty((q.shape[0], w.k), dtype=torch.float32, device=dev)
+    lab = torch.empty((q.shape[0], w.k), dtype=torch.int64, device=dev)
+    nrem = torch.zeros(1, dtype=torch.int64, device=dev)
+    g = p.gpu.step_graph(xb, ib, qb, w.k, w.nprobe, rb, dist, lab, nrem)
+    for t in range(1, 6):
+        xt, it = w.stream_batch(t)
+        xb.copy_(torch.from_numpy(xt))
+        ib.copy_(torch.from_numpy(it))
+        rb.copy_(torch.from_numpy(w.oldest_ids(t)))
+        g.launch()
+        assert p.gpu.sync() == 0
+        assert p.ref.add(xt, it) == 0
+        st, rd, rl = p.ref.search(q, w.k, w.nprobe)
+        st, rn = p.ref.remove(w.oldest_ids(t))
+        compare_results(dist.cpu().numpy(), lab.cpu().numpy(), rd, rl)
+        assert int(nrem.item()) == rn
+        p.check_state()
+        p.check_search(q[:7], 12, 3)            # eager work between replays
+    g.close()
