@@ -38,6 +38,9 @@ def parse():
     ap.add_argument("--workload", default="window", choices=["window", "tiny"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--recall-queries", type=int, default=1000)
+    ap.add_argument("--no-sweep", action="store_true", help="skip the nprobe / recall sweep")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (scale for DRAM byte counters)")
     return ap.parse_args()
 
 
@@ -114,7 +117,7 @@ def main():
     log(f"[bench] workload {w.name}: N={w.n_base} d={w.dim} nlist={w.nlist} C={w.slab} B={B} nq={nq} "
         f"(generated in {time.time() - t0:.1f} s)")
     num_slabs = int(1.15 * (w.n_base + 2 * B) / w.slab) + w.nlist
-    id_cap = w.n_base + B * (T + 2)
+    id_cap = w.n_base + B * (T + a.steps + 2)   # timed loop, then as many graph-mode steps
     chunk = 65536
     ix = sivf.Index(w.dim, w.nlist, w.centroids, metric=w.metric, slab_capacity=w.slab, num_slabs=num_slabs,
                     id_capacity=id_cap, max_batch=max(chunk, B), max_queries=nq, max_k=16,
@@ -160,26 +163,80 @@ def main():
     prof = ix.profile_read()
     ix.profile(False)
     assert ix.sync() == 0
-    log(f"[bench] {a.steps} steps in {elapsed:.3f} s; device ms per class: "
-        + ", ".join(f"{kk}={v[0] / max(v[1], 1):.3f}" for kk, v in prof.items()))
-
-    # recall@10 of the last step's search against exact kNN over its window
-    t_last = T  # window during the last search: base ids >= B*(T-1) plus batches 1..T
-    lab_np = lab.cpu().numpy()
-    nrq = min(a.recall_queries, nq)
-    keep = ids >= B * (t_last - 1)
-    xw = np.concatenate([x[keep]] + [w.stream_batch(t)[0] for t in range(1, T + 1)])
-    idw = np.concatenate([ids[keep]] + [w.stream_batch(t)[1] for t in range(1, T + 1)])
-    gt = exact_topk(xw, idw, q[:nrq], k)
-    recall = float(np.mean([len(set(gt[i]) & set(lab_np[i])) / k for i in range(nrq)]))
-    log(f"[bench] recall@{k} on {nrq} queries: {recall:.4f}")
-
     # scan roofline: distance evaluations of one search = sum over (query,
     # probe) of the probed list's length; 3 flops per dimension (sub + fma)
     probes = ix.probe(qd, nprobe).cpu().numpy()
-    d = ix.dump()
+    d = ix.dump()   # window state at the end of the timed region
     evals = int(d["list_len"].astype(np.int64)[probes[probes >= 0]].sum())
     scan_ms = prof["scan"][0] / max(prof["scan"][1], 1)
+    log(f"[bench] {a.steps} steps in {elapsed:.3f} s; device ms per class: "
+        + ", ".join(f"{kk}={v[0] / max(v[1], 1):.3f}" for kk, v in prof.items()))
+
+    # graph mode: the same step captured once and replayed on refilled buffers
+    T2 = T + a.steps
+    gx = torch.empty_like(bx[0])
+    gi = torch.empty_like(bi[0])
+    go = torch.empty_like(bo[0])
+    nrem = torch.zeros(1, dtype=torch.int64, device=dev)
+    g = ix.step_graph(gx, gi, qd, k, nprobe, go, dist, lab, nrem)
+    gsteps = []
+    for t in range(T, T2):
+        xb, idb = w.stream_batch(t + 1)
+        bxt, bit = torch.from_numpy(xb).to(dev), torch.from_numpy(idb).to(dev)
+        bot = torch.from_numpy(w.oldest_ids(t + 1)).to(dev)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        gx.copy_(bxt)
+        gi.copy_(bit)
+        go.copy_(bot)
+        g.launch()
+        torch.cuda.synchronize()
+        gsteps.append((time.perf_counter() - ts) * 1e3)
+    g.close()
+    assert ix.sync() == 0
+    gsm = np.sort(np.array(gsteps))
+    log(f"[bench] graph steps: p50 {np.percentile(gsm, 50):.3f} ms, p99 {np.percentile(gsm, 99):.3f} ms")
+
+    # recall@10 and the nprobe sweep on the final window (base ids >= B*T2
+    # plus batches 1..T2) against exact kNN (float64)
+    nrq = min(a.recall_queries, nq)
+    keep = ids >= B * T2
+    xw = np.concatenate([x[keep]] + [w.stream_batch(t)[0] for t in range(1, T2 + 1)])
+    idw = np.concatenate([ids[keep]] + [w.stream_batch(t)[1] for t in range(1, T2 + 1)])
+    gt = exact_topk(xw, idw, q[:nrq], k)
+
+    def recall_of(labels):
+        return float(np.mean([len(set(gt[i]) & set(labels[i])) / k for i in range(nrq)]))
+
+    sweep = []
+    ix.profile(True)
+    for npb in ([1, 2, 4, 8, 16, 32, 64] if not a.no_sweep else [nprobe]):
+        ix.search(qd, k, npb, out=(dist, lab))
+        ix.sync()
+        ix.profile_read()
+        for _ in range(3):
+            ix.search(qd, k, npb, out=(dist, lab))
+        pr = ix.profile_read()
+        sms = pr["search"][0] / max(pr["search"][1], 1)
+        sweep.append({"nprobe": npb, "recall_at_10": round(recall_of(lab.cpu().numpy()), 4),
+                      "search_qps": round(nq / (sms * 1e-3), 1)})
+    ix.profile(False)
+    recall = [r for r in sweep if r["nprobe"] == nprobe][0]["recall_at_10"]
+    ok95 = [r for r in sweep if r["recall_at_10"] >= 0.95]
+    best95 = max(ok95, key=lambda r: r["search_qps"]) if ok95 else None
+    log(f"[bench] recall@{k} at nprobe {nprobe}: {recall:.4f}; sweep {sweep}")
+
+    copy_info = None
+    if a.copy_calibration:
+        nbytes = 1 << 30
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        copy_info = {"bytes_read": nbytes, "bytes_written": nbytes}
+        del src, dst
+
     flops = evals * 3.0 * w.dim
     achieved = flops / (scan_ms * 1e-3) / 1e12
     # per-operation device rates
@@ -198,7 +255,11 @@ def main():
         "config": {"workload": f"{w.name}: sliding window N={w.n_base}, d={w.dim}, nlist={w.nlist}, slab={w.slab}, "
                                f"+{B}/-{B} per step, {nq} queries, nprobe={nprobe}, k={k}, L2",
                    "global_batch": nq, "parallelism": "single GPU"},
-        "recall_at_10": round(recall, 4),
+        "recall_at_10": recall,
+        "qps_at_recall95": best95,
+        "nprobe_sweep": sweep,
+        "graph_p50_step_ms": round(float(np.percentile(gsm, 50)), 4),
+        "graph_p99_step_ms": round(float(np.percentile(gsm, 99)), 4),
         "search_qps": round(nq / (se_ms * 1e-3), 1),
         "insert_vec_per_s": round(B / (add_ms * 1e-3), 1),
         "delete_vec_per_s": round(B / (rm_ms * 1e-3), 1),
