@@ -30,6 +30,21 @@ HBM_PEAK_GBS = 8000.0
 ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
 
+def recorded_traffic():
+    """DRAM bytes per scan launch from the committed counter summary, or None
+    when the scan source changed since the counters were taken."""
+    import hashlib
+    prof = os.path.join(ROOT, "profiles", "k_scan_window_1M.md")
+    src = os.path.join(ROOT, "paper_2601_11808_amd", "csrc", "search.hip")
+    try:
+        kv = dict(l.split(": ", 1) for l in open(prof).read().splitlines() if l.startswith(("traffic_", "search_hip")))
+        if hashlib.sha256(open(src, "rb").read()).hexdigest() != kv["search_hip_sha256"].strip():
+            return None
+        return int(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -270,7 +285,9 @@ def main():
         "device_ms": {kk: round(v[0] / max(v[1], 1), 4) for kk, v in prof.items()},
         "roofline": {"bound": "alu", "kernel": "k_scan", "achieved": round(achieved, 3),
                      "peak": round(ALU_PEAK_TFLOPS, 2), "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TFLOPS, 4),
-                     "traffic": None, "evals_per_launch": evals, "flops_per_eval": 3 * w.dim,
+                     "traffic": recorded_traffic() if a.workload == "window" else None,
+                     "traffic_unit": "bytes per launch (DRAM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "evals_per_launch": evals, "flops_per_eval": 3 * w.dim,
                      "avg_launch_ms": round(scan_ms, 4)},
     }
     if not a.no_cpu_baseline:
