@@ -71,8 +71,14 @@ typedef struct {
     int32_t slab_capacity; /* C, vectors per slab (Sec. 3.1): a power of two <= 128;
                             * 32, 64 and 128 are the performance settings        */
     int32_t metric;        /* sivf_metric                                          */
-    int32_t storage;       /* sivf_dtype of stored vectors; SIVF_F32 only          */
-    int32_t reserved0;     /* must be 0                                            */
+    int32_t storage;       /* sivf_dtype of the scanned copy of each vector: with
+                            * SIVF_BF16 / SIVF_F16 the slabs hold a rounded copy
+                            * (round to nearest even) scanned on MFMA, beside the
+                            * exact fp32 copy used for the final re-rank; dim <= 256 */
+    int32_t rerank_factor; /* R: reduced precision keeps the best R * k candidates
+                            * per query by approximate distance, then re-ranks them
+                            * by the exact fp32 distance; R * max_k <= 64.  Must be
+                            * 0 with SIVF_F32                                      */
     int64_t num_slabs;     /* slabs in the pool, 1..2^31/C                         */
     int64_t id_capacity;   /* N_max: ids are dense in [0, id_capacity), <= 2^31    */
     int32_t max_batch;     /* largest n of one sivf_add / sivf_remove call         */

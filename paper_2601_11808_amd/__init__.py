@@ -29,7 +29,7 @@ class SivfError(RuntimeError):
 
 class SivfConfig(ct.Structure):
     _fields_ = [("dim", ct.c_int32), ("nlist", ct.c_int32), ("slab_capacity", ct.c_int32),
-                ("metric", ct.c_int32), ("storage", ct.c_int32), ("reserved0", ct.c_int32),
+                ("metric", ct.c_int32), ("storage", ct.c_int32), ("rerank_factor", ct.c_int32),
                 ("num_slabs", ct.c_int64), ("id_capacity", ct.c_int64),
                 ("max_batch", ct.c_int32), ("max_queries", ct.c_int32),
                 ("max_k", ct.c_int32), ("max_nprobe", ct.c_int32)]
@@ -134,13 +134,14 @@ class Index:
 
     def __init__(self, dim, nlist, centroids, metric=L2, slab_capacity=64, num_slabs=1 << 16,
                  id_capacity=1 << 20, max_batch=1 << 16, max_queries=1 << 14, max_k=64,
-                 max_nprobe=256, storage=F32, device="cuda:0", stream=None):
+                 max_nprobe=256, storage=F32, rerank_factor=0, device="cuda:0", stream=None):
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device is available")
         self.device = torch.device(device)
         self.cfg = SivfConfig(dim=dim, nlist=nlist, slab_capacity=slab_capacity, metric=metric,
-                              storage=storage, reserved0=0, num_slabs=num_slabs, id_capacity=id_capacity,
+                              storage=storage, rerank_factor=rerank_factor, num_slabs=num_slabs,
+                              id_capacity=id_capacity,
                               max_batch=max_batch, max_queries=max_queries, max_k=max_k,
                               max_nprobe=max_nprobe)
         self.dim, self.nlist, self.metric, self.C = dim, nlist, metric, slab_capacity

@@ -163,8 +163,34 @@ __global__ __launch_bounds__(256) void k_add_scatter(Dev S, int n, const float *
         }
         dst[(int64_t)c * S.C] = v;
     }
+    const uint32_t g = (uint32_t)slab * (uint32_t)S.C + (uint32_t)slot;
+    if (S.storage != 0) {
+        // reduced-precision copy (round to nearest even), 8 dims per chunk,
+        // and the fp32 squared norm of the rounded row (L2 scan epilogue)
+        uint4 *hdst = S.hdata + (int64_t)slab * S.dp8 * S.C + slot;
+        float nrm = 0.f;
+        for (int c = sub; c < S.dp8; c += 16) {
+            uint32_t h[8];
+#pragma unroll
+            for (int e = 0; e < 8; e++) {
+                const int j = 8 * c + e;
+                const float v = j < S.d ? xr[j] : 0.f;
+                h[e] = S.storage == 1 ? to_bf16_bits(v) : to_f16_bits(v);
+                const float r = S.storage == 1 ? bf16_bits_to_float(h[e]) : f16_bits_to_float(h[e]);
+                nrm = fmaf(r, r, nrm);
+            }
+            hdst[(int64_t)c * S.C] = make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16),
+                                                h[6] | (h[7] << 16));
+        }
+        if (S.xnorm) {
+            nrm += __shfl_xor(nrm, 8, 16);
+            nrm += __shfl_xor(nrm, 4, 16);
+            nrm += __shfl_xor(nrm, 2, 16);
+            nrm += __shfl_xor(nrm, 1, 16);
+            if (sub == 0) S.xnorm[g] = nrm;
+        }
+    }
     if (sub == 0) {
-        const uint32_t g = (uint32_t)slab * (uint32_t)S.C + (uint32_t)slot;
         const int64_t u = ids[i];
         S.sids[g] = (uint32_t)u;
         S.att[u] = g;
@@ -282,6 +308,12 @@ __global__ __launch_bounds__(256) void k_rm_move(Dev S, int n, const uint32_t *_
         const float4 *sp = S.data + (int64_t)(sg / S.C) * S.dp4 * S.C + sg % S.C;
         float4 *dp = S.data + (int64_t)(dg / S.C) * S.dp4 * S.C + dg % S.C;
         for (int c = lane_id(); c < S.dp4; c += 64) dp[(int64_t)c * S.C] = sp[(int64_t)c * S.C];
+        if (S.storage != 0) {
+            const uint4 *hs = S.hdata + (int64_t)(sg / S.C) * S.dp8 * S.C + sg % S.C;
+            uint4 *hd = S.hdata + (int64_t)(dg / S.C) * S.dp8 * S.C + dg % S.C;
+            for (int c = lane_id(); c < S.dp8; c += 64) hd[(int64_t)c * S.C] = hs[(int64_t)c * S.C];
+            if (S.xnorm && lane_id() == 0) S.xnorm[dg] = S.xnorm[sg];
+        }
     }
     if (hole) {
         const uint32_t id = S.sids[src];

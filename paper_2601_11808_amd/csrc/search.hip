@@ -325,16 +325,19 @@ __global__ __launch_bounds__(64) void k_scan(Dev S, const int32_t *__restrict__ 
 
 // One wave per query: repeatedly take the smallest head among the query's
 // probe partial lists (each sorted, kcap long).
+// k: the call's k; each query keeps kmul * (its k) results, at most
+// out_stride (the row stride of dist / labels).
 __global__ __launch_bounds__(256) void k_merge(Dev S, int nq, int np_stride, const int32_t *__restrict__ probes,
-                                               const uint64_t *__restrict__ partials, int kcap, int k,
-                                               const int32_t *__restrict__ kpq, float *__restrict__ dist,
-                                               int64_t *__restrict__ labels) {
+                                               const uint64_t *__restrict__ partials, int kcap, int out_stride,
+                                               int k, int kmul, const int32_t *__restrict__ kpq,
+                                               float *__restrict__ dist, int64_t *__restrict__ labels) {
     __shared__ unsigned char heads[4][1024];
     const int w = threadIdx.x >> 6, lane = lane_id();
     const int qi = blockIdx.x * 4 + w;
     if (qi >= nq) return;
     int kq = kpq ? kpq[qi] : k;
     kq = kq < 0 ? 0 : (kq > k ? k : kq);
+    kq = min(kq * kmul, out_stride);
     const int32_t *prow = probes + (int64_t)qi * np_stride;
     const uint64_t *part = partials + (int64_t)qi * np_stride * kcap;
     auto head_key = [&](int p) -> uint64_t {
@@ -376,8 +379,8 @@ __global__ __launch_bounds__(256) void k_merge(Dev S, int nq, int np_stride, con
             }
         }
     }
-    if (lane < k) {
-        const int64_t o = (int64_t)qi * k + lane;
+    if (lane < out_stride) {
+        const int64_t o = (int64_t)qi * out_stride + lane;
         if (lane < kq && res != ~0ull) {
             dist[o] = key_value(res, S.metric);
             labels[o] = (int64_t)(uint32_t)res;
@@ -391,7 +394,249 @@ __global__ __launch_bounds__(256) void k_merge(Dev S, int nq, int np_stride, con
 // Queries per tile (the LDS path holds T * ceil(d/4) * 16 bytes, within 32
 // KiB).  Measured on the window workload: T=8 with two dimension chunks in
 // flight beats T=16, whose query operands no longer fit the SGPR file.
-int search_tile(int d) { return d <= 1024 ? 8 : 4; }
+int search_tile(const Dev &S) {
+    if (S.storage != 0) return 16;   // the MFMA scan's tile is one 16-column operand
+    return S.d <= 1024 ? 8 : 4;
+}
+
+// ------------------------------------------------ reduced-precision scan
+//
+// Slabs in bf16 / fp16 ([slab][8-dim chunk][slot], 16 bytes per slot and
+// chunk).  One wave scans a list for a tile of 16 queries with
+// v_mfma_f32_16x16x32_{bf16,f16}: the A operand is 16 slots x 32 dims (lane l:
+// slot l % 16, dims 8 (l / 16) .. +8 of the k-block), B the 16 queries
+// rounded the same way, C the 16 x 16 fp32 scores (lane l: slots
+// 4 (l / 16) .. +4, query l % 16).  Approximate distances:
+// |x~|^2 + |q~|^2 - 2 x~.q~ (L2) or x~.q~ (IP), with FP32 accumulation.  Each
+// query keeps its best kmul * k approximate candidates; the exact FP32
+// re-rank over the shadow rows (k_rerank) decides the final order.
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+template <int DT>
+__device__ __forceinline__ f32x4_t mfma_16x16x32(uint4 a, uint4 b, f32x4_t c) {
+    if constexpr (DT == 1)
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, a), __builtin_bit_cast(bf16x8_t, b),
+                                                      c, 0, 0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8_t, a), __builtin_bit_cast(f16x8_t, b),
+                                                     c, 0, 0, 0);
+}
+
+constexpr int MQ = 16;       // queries per MFMA tile
+constexpr int MKB = 8;       // k-blocks of 32 dims: d <= 256
+constexpr int MBUF = 128;    // candidate buffer per query
+
+template <int METRIC, int DT>
+__global__ __launch_bounds__(64) void k_scan_mfma(Dev S, const int32_t *__restrict__ item_list,
+                                                  const int32_t *__restrict__ item_tile,
+                                                  const int32_t *__restrict__ list_pairs,
+                                                  const float *__restrict__ q, int np_stride, int kcap, int k,
+                                                  int kmul, const int32_t *__restrict__ kpq,
+                                                  uint64_t *__restrict__ partials, int per_xcd) {
+    __shared__ uint64_t buf[MQ * MBUF];
+    __shared__ int scnt[MQ], skq[MQ];
+    __shared__ uint32_t sid[64];
+    __shared__ float sxn[64];
+    const int w = blockIdx.x;
+    const int item = (w & 7) * per_xcd + (w >> 3);
+    if (item >= S.ctl[CTL_NITEMS]) return;
+    const int lane = threadIdx.x, qcol = lane & 15, kgrp = lane >> 4;
+    const int l = item_list[item], tile = item_tile[item];
+    const int nt = min(MQ, S.l_qcs[l] - tile * MQ);
+    const int d = S.d, C = S.C, dp8 = S.dp8;
+    const int nkb = (d + 31) / 32;
+    const int32_t *pairs = list_pairs + S.l_qoff[l] + tile * MQ;
+    if (lane < MQ) {
+        skq[lane] = lane < nt ? min(kmul * query_k(kpq, k, pairs[lane] / np_stride), kcap) : 0;
+        scnt[lane] = 0;
+    }
+    // B operand: query qcol, dims 32 kb + 8 kgrp .. +8, rounded like the slabs
+    const float *qr = q + (int64_t)(pairs[qcol < nt ? qcol : 0] / np_stride) * d;
+    uint4 bq[MKB];
+    float qn = 0.f;
+#pragma unroll
+    for (int kb = 0; kb < MKB; kb++) {
+        uint32_t h[8];
+#pragma unroll
+        for (int e = 0; e < 8; e++) {
+            const int j = 32 * kb + 8 * kgrp + e;
+            const float v = (kb < nkb && j < d) ? qr[j] : 0.f;
+            h[e] = DT == 1 ? to_bf16_bits(v) : to_f16_bits(v);
+            const float r = DT == 1 ? bf16_bits_to_float(h[e]) : f16_bits_to_float(h[e]);
+            qn = fmaf(r, r, qn);
+        }
+        bq[kb] = make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16));
+    }
+    qn += __shfl_xor(qn, 16);
+    qn += __shfl_xor(qn, 32);
+    __syncthreads();
+    uint32_t thr = skq[qcol] > 0 ? 0xFFFFFFFFu : 0u;   // threshold of query qcol
+    uint64_t top[MQ];
+#pragma unroll
+    for (int t = 0; t < MQ; t++) top[t] = ~0ull;
+
+    const int len = S.len[l];
+    const int nslab = cdiv_s(len, C);
+    int wbase = -(1 << 30), wslab = 0;
+    for (int base = 0; base < len; base += 64) {
+        const int last_ord = (min(base + 63, len - 1)) / C;
+        if (last_ord >= wbase + 64) {
+            wbase = base / C;
+            wslab = (wbase + lane < nslab) ? slab_of(S, l, wbase + lane) : 0;
+        }
+        {   // ids and norms of the 64 positions of this step, one per lane
+            const int p = base + lane;
+            const int pc = p < len ? p : len - 1;
+            const int slab = __shfl(wslab, pc / C - wbase);
+            const int64_t g = (int64_t)slab * C + pc % C;
+            sid[lane] = S.sids[g];
+            sxn[lane] = (METRIC == 0 && S.xnorm) ? S.xnorm[g] : 0.f;
+        }
+        f32x4_t acc[4];
+#pragma unroll
+        for (int rg = 0; rg < 4; rg++) {
+            const int p = base + 16 * rg + qcol;
+            const int pc = p < len ? p : len - 1;
+            const int slab = __shfl(wslab, pc / C - wbase);
+            const uint4 *hp = S.hdata + (int64_t)slab * dp8 * C + pc % C;
+            acc[rg] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kb = 0; kb < MKB; kb++) {
+                if (kb < nkb) {
+                    const int c8 = 4 * kb + kgrp;
+                    const uint4 a = (c8 < dp8 && p < len) ? hp[(int64_t)c8 * C] : make_uint4(0, 0, 0, 0);
+                    acc[rg] = mfma_16x16x32<DT>(a, bq[kb], acc[rg]);
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int rg = 0; rg < 4; rg++) {
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const int r = 16 * rg + 4 * kgrp + j;   // position base + r
+                const float v = METRIC == 0 ? (qn + sxn[r]) - 2.f * acc[rg][j] : acc[rg][j];
+                const uint32_t hi = METRIC == 0 ? ord_bits(v) : ~ord_bits(v);
+                if (base + r < len && qcol < nt && hi <= thr) {
+                    const int at = atomicAdd(&scnt[qcol], 1);
+                    buf[qcol * MBUF + at] = ((uint64_t)hi << 32) | sid[r];
+                }
+            }
+        }
+        __syncthreads();
+        // merge buffers that could overflow on the next step, and fill each
+        // query's list as soon as it has k candidates (sets its threshold)
+#pragma unroll
+        for (int t = 0; t < MQ; t++) {
+            const int cnt = scnt[t];
+            const bool unset = __builtin_amdgcn_readlane((int)thr, t) == (int)0xFFFFFFFFu;
+            if (cnt > MBUF - 64 || (unset && cnt >= skq[t] && cnt > 0)) {
+                const uint64_t b0 = lane < cnt ? buf[t * MBUF + lane] : ~0ull;
+                const uint64_t b1 = lane + 64 < cnt ? buf[t * MBUF + 64 + lane] : ~0ull;
+                uint64_t c = merge_sorted_with(top[t], b0);
+                if (cnt > 64) c = merge_sorted_with(c, b1);
+                c = lane < kcap ? c : ~0ull;
+                top[t] = c;
+                const uint32_t nthr = skq[t] > 0 ? (uint32_t)(readlane_u64(c, skq[t] - 1) >> 32) : 0u;
+                if (qcol == t) thr = nthr;
+                __syncthreads();
+                if (lane == 0) scnt[t] = 0;
+                __syncthreads();
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < MQ; t++) {
+        if (t < nt) {
+            const int cnt = scnt[t];
+            if (cnt > 0) {
+                const uint64_t b0 = lane < cnt ? buf[t * MBUF + lane] : ~0ull;
+                const uint64_t b1 = lane + 64 < cnt ? buf[t * MBUF + 64 + lane] : ~0ull;
+                uint64_t c = merge_sorted_with(top[t], b0);
+                if (cnt > 64) c = merge_sorted_with(c, b1);
+                top[t] = lane < kcap ? c : ~0ull;
+            }
+            if (lane < kcap) partials[(int64_t)pairs[t] * kcap + lane] = top[t];
+        }
+    }
+}
+
+// Exact FP32 re-rank: one wave per query; lane i recomputes the canonical
+// FP32 distance of candidate i from the fp32 shadow row, then the wave sorts
+// the keys and keeps the query's k best.
+__global__ __launch_bounds__(256) void k_rerank(Dev S, int nq, const float *__restrict__ q, int kc,
+                                                const int64_t *__restrict__ cand, int k, int kmul,
+                                                const int32_t *__restrict__ kpq, float *__restrict__ dist,
+                                                int64_t *__restrict__ labels) {
+    const int w = threadIdx.x >> 6, lane = lane_id();
+    const int qi = blockIdx.x * 4 + w;
+    if (qi >= nq) return;
+    const int kq = query_k(kpq, k, qi);
+    const int nc = min(kq * kmul, kc);
+    const int d = S.d, C = S.C;
+    uint64_t key = ~0ull;
+    if (lane < nc) {
+        const int64_t id = cand[(int64_t)qi * kc + lane];
+        const uint32_t g = id >= 0 ? S.att[id] : INVALID;
+        if (g != INVALID) {
+            const float4 *xp = S.data + (int64_t)(g / C) * S.dp4 * C + g % C;
+            const float *qr = q + (int64_t)qi * d;
+            float r = 0.f;
+            for (int c = 0; c < S.dp4; c++) {
+                const float4 xv = xp[(int64_t)c * C];
+                const float xs[4] = {xv.x, xv.y, xv.z, xv.w};
+                for (int e = 0; e < 4; e++) {
+                    const int j = 4 * c + e;
+                    if (j < d) {
+                        if (S.metric == 0) {
+                            const float t = qr[j] - xs[e];
+                            r = __builtin_fmaf(t, t, r);
+                        } else {
+                            r = __builtin_fmaf(qr[j], xs[e], r);
+                        }
+                    }
+                }
+            }
+            key = make_key(r, (uint32_t)id, S.metric);
+        }
+    }
+    key = wave_sort64(key, true);
+    if (lane < k) {
+        const int64_t o = (int64_t)qi * k + lane;
+        if (lane < kq && key != ~0ull) {
+            dist[o] = key_value(key, S.metric);
+            labels[o] = (int64_t)(uint32_t)key;
+        } else {
+            dist[o] = S.metric == 0 ? __int_as_float(0x7F800000) : __int_as_float((int)0xFF800000);
+            labels[o] = -1;
+        }
+    }
+}
+
+void launch_search_scan_mfma(hipStream_t st, const Dev &S, const SearchBufs &W, int nq, const float *q,
+                             int np_stride, int kcap, int k, int kmul, const int32_t *k_per_query) {
+    const int npairs = nq * np_stride;
+    const int64_t bound = (int64_t)npairs / MQ + (npairs < S.nlist ? npairs : S.nlist);
+    const int per_xcd = (int)((bound + 7) / 8);
+    const unsigned grid = (unsigned)(8 * per_xcd);
+#define SIVF_LAUNCH_MFMA(M, D)                                                                               \
+    hipLaunchKernelGGL((k_scan_mfma<M, D>), dim3(grid), dim3(64), 0, st, S, W.item_list, W.item_tile,         \
+                       W.list_pairs, q, np_stride, kcap, k, kmul, k_per_query, W.partials, per_xcd)
+    if (S.metric == 0 && S.storage == 1) SIVF_LAUNCH_MFMA(0, 1);
+    else if (S.metric == 0) SIVF_LAUNCH_MFMA(0, 2);
+    else if (S.storage == 1) SIVF_LAUNCH_MFMA(1, 1);
+    else SIVF_LAUNCH_MFMA(1, 2);
+#undef SIVF_LAUNCH_MFMA
+}
+
+void launch_rerank(hipStream_t st, const Dev &S, int nq, const float *q, int kc, const int64_t *cand, int k,
+                   int kmul, const int32_t *k_per_query, float *dist, int64_t *labels) {
+    hipLaunchKernelGGL(k_rerank, dim3((nq + 3) / 4), dim3(256), 0, st, S, nq, q, kc, cand, k, kmul, k_per_query,
+                       dist, labels);
+}
 
 template <int T>
 static void launch_scan_t(hipStream_t st, const Dev &S, const SearchBufs &W, const float *q, int np_stride,
@@ -419,7 +664,7 @@ void launch_search_plan(hipStream_t st, const Dev &S, const SearchBufs &W, int n
     const int npairs = nq * np_stride;
     const unsigned pb = (unsigned)((npairs + 255) / 256);
     hipLaunchKernelGGL(k_inv_count, dim3(pb), dim3(256), 0, st, S, npairs, W.probes, W.pair_rank);
-    hipLaunchKernelGGL(k_inv_plan, dim3(1), dim3(1024), 0, st, S, search_tile(S.d), W.item_list, W.item_tile);
+    hipLaunchKernelGGL(k_inv_plan, dim3(1), dim3(1024), 0, st, S, search_tile(S), W.item_list, W.item_tile);
     hipLaunchKernelGGL(k_inv_scatter, dim3(pb), dim3(256), 0, st, S, npairs, W.probes, W.pair_rank,
                        W.list_pairs);
 }
@@ -427,7 +672,7 @@ void launch_search_plan(hipStream_t st, const Dev &S, const SearchBufs &W, int n
 void launch_search_scan(hipStream_t st, const Dev &S, const SearchBufs &W, int nq, const float *q, int np_stride,
                         int kcap, int k, const int32_t *k_per_query) {
     const int npairs = nq * np_stride;
-    const int T = search_tile(S.d);
+    const int T = search_tile(S);
     // items <= sum over lists of ceil(pairs_l / T) <= npairs / T + min(nlist, npairs)
     const int64_t bound = (int64_t)npairs / T + (npairs < S.nlist ? npairs : S.nlist);
     const int per_xcd = (int)((bound + 7) / 8);
@@ -439,9 +684,10 @@ void launch_search_scan(hipStream_t st, const Dev &S, const SearchBufs &W, int n
 }
 
 void launch_search_merge(hipStream_t st, const Dev &S, const SearchBufs &W, int nq, int np_stride, int kcap,
-                         int k, const int32_t *k_per_query, float *dist, int64_t *labels) {
+                         int out_stride, int k, int kmul, const int32_t *k_per_query, float *dist,
+                         int64_t *labels) {
     hipLaunchKernelGGL(k_merge, dim3((nq + 3) / 4), dim3(256), 0, st, S, nq, np_stride, W.probes, W.partials,
-                       kcap, k, k_per_query, dist, labels);
+                       kcap, out_stride, k, kmul, k_per_query, dist, labels);
 }
 
 }  // namespace sivf

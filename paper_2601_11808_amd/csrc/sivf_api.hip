@@ -30,7 +30,7 @@ struct Layout {
     size_t total;
     size_t cent, cn2, cnorm, cmax, data, sids, sowner, sord, free_slabs, free_pages, pages, dir, len, att, mark,
         ctl, lists, b_assign, b_rank, b_rec, b_seg, dt, probes, pair_rank, list_pairs, item_list, item_tile,
-        partials;
+        partials, hdata, xnorm, rr_dist, rr_lab;
 };
 
 bool config_ok(const sivf_config *c) {
@@ -39,7 +39,11 @@ bool config_ok(const sivf_config *c) {
     if (c->nlist < 1 || c->nlist > 65536) return false;
     if (c->slab_capacity < 1 || c->slab_capacity > 128 || (c->slab_capacity & (c->slab_capacity - 1))) return false;
     if (c->metric != SIVF_L2 && c->metric != SIVF_IP) return false;
-    if (c->storage != SIVF_F32 || c->reserved0 != 0) return false;
+    if (c->storage != SIVF_F32 && c->storage != SIVF_BF16 && c->storage != SIVF_F16) return false;
+    if (c->storage == SIVF_F32 && c->rerank_factor != 0) return false;
+    if (c->storage != SIVF_F32 &&
+        (c->dim > 256 || c->rerank_factor < 1 || (int64_t)c->rerank_factor * c->max_k > 64))
+        return false;
     if (c->num_slabs < 1 || c->num_slabs * (int64_t)c->slab_capacity >= (1ll << 31)) return false;
     if (c->id_capacity < 1 || c->id_capacity >= (1ll << 31)) return false;
     if (c->max_batch < 1 || c->max_queries < 1) return false;
@@ -52,7 +56,7 @@ bool config_ok(const sivf_config *c) {
 Layout make_layout(const sivf_config *c) {
     Layout L{};
     L.dp4 = (c->dim + 3) / 4;
-    L.kcap = kcap_for(c->max_k);
+    L.kcap = kcap_for(c->storage == SIVF_F32 ? c->max_k : c->rerank_factor * c->max_k);
     const int64_t nl = c->nlist, ns = c->num_slabs, C = c->slab_capacity;
     L.dir_cap = (ns + PAGE - 1) / PAGE + 1;
     L.num_pages = (ns + PAGE - 1) / PAGE + nl;
@@ -95,6 +99,11 @@ Layout make_layout(const sivf_config *c) {
     L.item_list = take((size_t)L.max_items * 4);
     L.item_tile = take((size_t)L.max_items * 4);
     L.partials = take((size_t)npairs * L.kcap * 8);
+    const bool reduced = c->storage != SIVF_F32;
+    L.hdata = take(reduced ? (size_t)ns * ((c->dim + 7) / 8) * C * 16 : 0);
+    L.xnorm = take(reduced && c->metric == SIVF_L2 ? (size_t)ns * C * 4 : 0);
+    L.rr_dist = take(reduced ? (size_t)c->max_queries * L.kcap * 4 : 0);
+    L.rr_lab = take(reduced ? (size_t)c->max_queries * L.kcap * 8 : 0);
     L.total = cur;
     return L;
 }
@@ -239,10 +248,21 @@ sivf_status do_search(sivf_index *ix, int64_t nq, const float *q, int32_t k, con
     prof_end(ix, SIVF_PROF_COARSE, pc, st);
     launch_search_plan(st, ix->S, ix->W, (int)nq, stride);
     const int pk = prof_begin(ix, SIVF_PROF_SCAN, st);
-    launch_search_scan(st, ix->S, ix->W, (int)nq, q, stride, ix->L.kcap, k, kpq);
+    if (c.storage == SIVF_F32)
+        launch_search_scan(st, ix->S, ix->W, (int)nq, q, stride, ix->L.kcap, k, kpq);
+    else
+        launch_search_scan_mfma(st, ix->S, ix->W, (int)nq, q, stride, ix->L.kcap, k, c.rerank_factor, kpq);
     prof_end(ix, SIVF_PROF_SCAN, pk, st);
     const int pm = prof_begin(ix, SIVF_PROF_MERGE, st);
-    launch_search_merge(st, ix->S, ix->W, (int)nq, stride, ix->L.kcap, k, kpq, dist, labels);
+    if (c.storage == SIVF_F32) {
+        launch_search_merge(st, ix->S, ix->W, (int)nq, stride, ix->L.kcap, k, k, 1, kpq, dist, labels);
+    } else {
+        // approximate candidates, then the exact fp32 re-rank of R * k per query
+        const int kc = c.rerank_factor * k;
+        launch_search_merge(st, ix->S, ix->W, (int)nq, stride, ix->L.kcap, kc, k, c.rerank_factor, kpq,
+                            ix->W.rr_dist, ix->W.rr_lab);
+        launch_rerank(st, ix->S, (int)nq, q, kc, ix->W.rr_lab, k, c.rerank_factor, kpq, dist, labels);
+    }
     prof_end(ix, SIVF_PROF_MERGE, pm, st);
     prof_end(ix, SIVF_PROF_SEARCH, ps, st);
     return launched(ix);
@@ -276,6 +296,12 @@ sivf_status sivf_create(const sivf_config *cfg, const float *centroids, void *wo
     S.nlist = cfg->nlist;
     S.C = cfg->slab_capacity;
     S.metric = cfg->metric;
+    S.storage = cfg->storage;
+    S.dp8 = (cfg->dim + 7) / 8;
+    S.hdata = cfg->storage != SIVF_F32 ? (uint4 *)(w + L.hdata) : nullptr;
+    S.xnorm = (cfg->storage != SIVF_F32 && cfg->metric == SIVF_L2) ? (float *)(w + L.xnorm) : nullptr;
+    ix->W.rr_dist = cfg->storage != SIVF_F32 ? (float *)(w + L.rr_dist) : nullptr;
+    ix->W.rr_lab = cfg->storage != SIVF_F32 ? (int64_t *)(w + L.rr_lab) : nullptr;
     S.num_slabs = cfg->num_slabs;
     S.num_pages = L.num_pages;
     S.dir_cap = L.dir_cap;

@@ -38,12 +38,16 @@ enum Ctl {
 
 struct Dev {
     int d, dp4, nlist, C, metric;
+    int storage;          // 0 = fp32 slabs; 1 = bf16, 2 = fp16 slabs with the fp32 pool as shadow
+    int dp8;              // ceil(d / 8): 16-byte chunks of a reduced-precision row
     int64_t num_slabs, num_pages, dir_cap, id_capacity;
     const float *cent;    // [nlist][dp4*4], zero padded
     const float *cn2;     // [nlist] fp32 squared norms
     const double *cnorm;  // [nlist] fp64 norms
     const double *cmax;   // [1] largest centroid norm
-    float4 *data;
+    float4 *data;         // fp32 rows (the stored vectors, or the exact shadow)
+    uint4 *hdata;         // [num_slabs][dp8][C] 8 x 16-bit (reduced-precision storage only)
+    float *xnorm;         // [num_slabs * C] squared norm of the rounded row (reduced precision, L2)
     uint32_t *sids;
     int32_t *sowner, *sord;
     int32_t *free_slabs, *free_pages, *pages, *dir;
@@ -83,6 +87,21 @@ __device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src) {
     int lo = __shfl((int)(uint32_t)v, src);
     int hi = __shfl((int)(uint32_t)(v >> 32), src);
     return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+// fp32 -> bf16 / fp16 bits, round to nearest even.
+__device__ __forceinline__ uint32_t to_bf16_bits(float f) {
+    const uint32_t u = __float_as_uint(f);
+    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x7FFFFFu)) return 0x7FC0u;   // NaN stays NaN
+    return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+__device__ __forceinline__ uint32_t to_f16_bits(float f) {
+    const _Float16 h = (_Float16)f;   // v_cvt_f16_f32: round to nearest even
+    return (uint32_t)__builtin_bit_cast(uint16_t, h);
+}
+__device__ __forceinline__ float bf16_bits_to_float(uint32_t b) { return __uint_as_float(b << 16); }
+__device__ __forceinline__ float f16_bits_to_float(uint32_t b) {
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)b);
 }
 
 // Order-preserving map float -> uint32 (larger float, larger code).

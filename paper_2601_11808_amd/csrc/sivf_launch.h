@@ -44,12 +44,19 @@ void launch_fill_i64(hipStream_t st, int64_t *p, int64_t n, int64_t v);
 struct SearchBufs {
     int32_t *probes, *pair_rank, *list_pairs, *item_list, *item_tile;
     uint64_t *partials;
+    float *rr_dist;      // reduced precision: approximate candidates per query
+    int64_t *rr_lab;
 };
-int search_tile(int d);
+int search_tile(const Dev &S);
 void launch_search_plan(hipStream_t st, const Dev &S, const SearchBufs &W, int nq, int np_stride);
 void launch_search_scan(hipStream_t st, const Dev &S, const SearchBufs &W, int nq, const float *q, int np_stride,
                         int kcap, int k, const int32_t *k_per_query);
 void launch_search_merge(hipStream_t st, const Dev &S, const SearchBufs &W, int nq, int np_stride, int kcap,
-                         int k, const int32_t *k_per_query, float *dist, int64_t *labels);
+                         int out_stride, int k, int kmul, const int32_t *k_per_query, float *dist,
+                         int64_t *labels);
+void launch_search_scan_mfma(hipStream_t st, const Dev &S, const SearchBufs &W, int nq, const float *q,
+                             int np_stride, int kcap, int k, int kmul, const int32_t *k_per_query);
+void launch_rerank(hipStream_t st, const Dev &S, int nq, const float *q, int kc, const int64_t *cand, int k,
+                   int kmul, const int32_t *k_per_query, float *dist, int64_t *labels);
 
 }  // namespace sivf

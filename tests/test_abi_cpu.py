@@ -44,7 +44,7 @@ def test_struct_layouts_match_header():
 
 
 def _cfg(**kw):
-    base = dict(dim=128, nlist=1024, slab_capacity=64, metric=0, storage=0, reserved0=0,
+    base = dict(dim=128, nlist=1024, slab_capacity=64, metric=0, storage=0, rerank_factor=0,
                 num_slabs=20000, id_capacity=1 << 21, max_batch=65536, max_queries=10000,
                 max_k=16, max_nprobe=64)
     base.update(kw)
@@ -56,7 +56,8 @@ def test_workspace_bytes_and_config_validation(lib):
     nb = lib.sivf_workspace_bytes(ct.byref(c))
     pool = 20000 * 64 * (128 * 4 + 4)
     assert nb > pool and nb < pool + (1 << 30)
-    bad = [dict(dim=0), dict(nlist=0), dict(slab_capacity=48), dict(slab_capacity=256), dict(slab_capacity=0), dict(metric=2), dict(storage=1),
+    bad = [dict(dim=0), dict(nlist=0), dict(slab_capacity=48), dict(slab_capacity=256), dict(slab_capacity=0), dict(metric=2), dict(storage=3), dict(storage=1), dict(rerank_factor=2),
+           dict(storage=1, rerank_factor=8, max_k=16), dict(storage=1, rerank_factor=4, dim=512),
            dict(num_slabs=0), dict(id_capacity=0), dict(max_k=65), dict(max_k=0), dict(max_nprobe=0),
            dict(max_nprobe=2000), dict(num_slabs=1 << 30)]
     for b in bad:
