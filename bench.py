@@ -1,19 +1,27 @@
 """Benchmark: sliding-window streaming IVF on one MI355X.
 
-Workload (default): the sliding-window plain FP32 configuration - a window of
-1,000,000 vectors, d=128, integer values 0..255 stored as fp32, 1,024 lists
-(k-means centroids), slabs of 64; each step inserts 10,000 new vectors,
-searches 10,000 queries (nprobe 32, k 10) and evicts the oldest 10,000
-(the paper's insert -> search -> delete loop).  All inputs are generated on
-the host, copied to HBM before timing, and synthetic (the paper's datasets are
-not available).
+Default workload: the sliding-window plain FP32 configuration.  The window
+holds 1,000,000 vectors (d=128, integer values 0..255 stored as fp32) in 1,024
+lists (k-means centroids) with slabs of 64.  Each step inserts 10,000 new
+vectors, searches 10,000 queries (nprobe 32, k 10) and evicts the oldest
+10,000 -- the paper's insert -> search -> delete loop.  All inputs are
+synthetic, generated on the host and copied to HBM before timing (the
+paper's datasets are not available).
 
 Prints one JSON line.  value = queries answered per second of window-step
-time (every step also inserts and deletes 10,000 vectors); per-operation
-device rates, step-latency percentiles, recall@10, the roofline of the scan
-kernel and the CPU oracle's rate on a bounded sample are reported beside it.
+time (every step also inserts and deletes 10,000 vectors).  Reported beside
+it: per-operation device rates, step-latency percentiles (eager and
+HIP-graph steps), recall@10 and an nprobe sweep against exact kNN, the
+roofline of the scan kernel, and the CPU oracle's rate on a bounded sample.
+
+Other modes (not the headline line):
+  --storage bf16|f16   the precision form on the same window data
+  --workload precision 10M unit vectors, d=96, inner product, bf16 slabs,
+                       4,096 lists, slab 128, 16k queries, nprobe 64,
+                       re-rank of the top 40
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -24,25 +32,11 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0
 # FP32 VALU peak with packed FP32 off: 256 CUs x 4 SIMD x 16 lanes x 2 flop
-# (fma) x 2.4 GHz.
+# (fma) x 2.4 GHz.  Dense BF16/FP16 MFMA peak: 2.5 PFLOP/s.
 ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
-
-
-def recorded_traffic():
-    """DRAM bytes per scan launch from the committed counter summary, or None
-    when the scan source changed since the counters were taken."""
-    import hashlib
-    prof = os.path.join(ROOT, "profiles", "k_scan_window_1M.md")
-    src = os.path.join(ROOT, "paper_2601_11808_amd", "csrc", "search.hip")
-    try:
-        kv = dict(l.split(": ", 1) for l in open(prof).read().splitlines() if l.startswith(("traffic_", "search_hip")))
-        if hashlib.sha256(open(src, "rb").read()).hexdigest() != kv["search_hip_sha256"].strip():
-            return None
-        return int(kv["traffic_bytes_per_launch"])
-    except (OSError, KeyError, ValueError):
-        return None
+MFMA16_PEAK_TFLOPS = 2500.0
+STORAGE = {"f32": 0, "bf16": 1, "f16": 2}
 
 
 def parse():
@@ -50,7 +44,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="window", choices=["window", "tiny"])
+    ap.add_argument("--workload", default="window", choices=["window", "tiny", "precision"])
+    ap.add_argument("--storage", default=None, choices=list(STORAGE))
+    ap.add_argument("--rerank", type=int, default=4, help="re-rank factor R for bf16/f16 storage")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--recall-queries", type=int, default=1000)
     ap.add_argument("--no-sweep", action="store_true", help="skip the nprobe / recall sweep")
@@ -63,25 +59,44 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def exact_topk(xw, idw, q, k):
-    """Exact squared-L2 top-k (float64) of q against the window, ties by id."""
-    xd = xw.astype(np.float64)
-    x2 = (xd * xd).sum(1)
-    out = np.empty((q.shape[0], k), np.int64)
-    for s in range(0, q.shape[0], 64):
-        qq = q[s:s + 64].astype(np.float64)
-        dd = x2[None, :] - 2.0 * (qq @ xd.T) + (qq * qq).sum(1)[:, None]
-        part = np.argpartition(dd, k, axis=1)[:, :k + 8]
-        for i in range(qq.shape[0]):
-            c = part[i]
-            o = np.lexsort((idw[c], dd[i, c]))[:k]
-            out[s + i] = idw[c[o]]
-    return out
+def recorded_traffic():
+    """DRAM bytes per scan launch from the committed counter summary, or None
+    when the scan source changed since the counters were taken."""
+    prof = os.path.join(ROOT, "profiles", "k_scan_window_1M.md")
+    src = os.path.join(ROOT, "paper_2601_11808_amd", "csrc", "search.hip")
+    try:
+        kv = dict(l.split(": ", 1) for l in open(prof).read().splitlines() if l.startswith(("traffic_", "search_hip")))
+        if hashlib.sha256(open(src, "rb").read()).hexdigest() != kv["search_hip_sha256"].strip():
+            return None
+        return int(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def exact_topk(xw, idw, q, k, metric, chunk=1 << 18):
+    """Exact top-k (float64) of q over the window rows, ties by smaller id:
+    squared L2 ascending, or inner product descending."""
+    qd = q.astype(np.float64)
+    best_s = np.full((q.shape[0], k), np.inf)
+    best_i = np.full((q.shape[0], k), np.iinfo(np.int64).max, dtype=np.int64)
+    for s in range(0, xw.shape[0], chunk):
+        xd = xw[s:s + chunk].astype(np.float64)
+        if metric == 0:
+            sc = (xd * xd).sum(1)[None, :] - 2.0 * (qd @ xd.T) + (qd * qd).sum(1)[:, None]
+        else:
+            sc = -(qd @ xd.T)
+        kk = min(k, sc.shape[1])
+        part = np.argpartition(sc, kk - 1, axis=1)[:, :kk]
+        cs = np.concatenate([best_s, np.take_along_axis(sc, part, 1)], 1)
+        ci = np.concatenate([best_i, idw[s:s + chunk][part]], 1)
+        o = np.lexsort((ci, cs), axis=1)[:, :k]
+        best_s, best_i = np.take_along_axis(cs, o, 1), np.take_along_axis(ci, o, 1)
+    return best_i
 
 
 def cpu_baseline(w, x, ids, q, batches, nprobe, k, n_sample_q):
     """The CPU oracle on a bounded sample of the same workload: one window
-    step (insert 10k, search a query sample, delete 10k) on the full
+    step (insert a batch, search a query sample, delete a batch) on the full
     window; the search time is scaled to the full query batch."""
     import oracle
     ix = oracle.OracleIndex(w.dim, w.nlist, w.centroids, w.metric, w.slab, 1 << 26, ids.shape[0] + 4 * w.batch)
@@ -124,31 +139,39 @@ def main():
         raise SystemExit("libsivf.so is not built: run python -c 'import __graft_entry__ as g; g.build()'")
     dev = torch.device("cuda:0")
     t0 = time.time()
-    w = workloads.window() if a.workload == "window" else workloads.tiny()
+    w = {"window": workloads.window, "tiny": workloads.tiny, "precision": workloads.precision}[a.workload]()
+    storage = a.storage or ("bf16" if a.workload == "precision" else "f32")
+    st_code = STORAGE[storage]
+    rerank = a.rerank if st_code else 0
     x, ids = w.base()
     q = w.queries()
     B, nq, k, nprobe = w.batch, q.shape[0], w.k, w.nprobe
     T = a.warmup + a.steps
+    T2 = T + a.steps
     log(f"[bench] workload {w.name}: N={w.n_base} d={w.dim} nlist={w.nlist} C={w.slab} B={B} nq={nq} "
-        f"(generated in {time.time() - t0:.1f} s)")
+        f"storage={storage} (generated in {time.time() - t0:.1f} s)")
     num_slabs = int(1.15 * (w.n_base + 2 * B) / w.slab) + w.nlist
-    id_cap = w.n_base + B * (T + a.steps + 2)   # timed loop, then as many graph-mode steps
+    id_cap = w.n_base + B * (T2 + 2)   # timed loop, then as many graph-mode steps
     chunk = 65536
     ix = sivf.Index(w.dim, w.nlist, w.centroids, metric=w.metric, slab_capacity=w.slab, num_slabs=num_slabs,
                     id_capacity=id_cap, max_batch=max(chunk, B), max_queries=nq, max_k=16,
-                    max_nprobe=max(128, nprobe), device="cuda:0")
+                    max_nprobe=max(128, nprobe), storage=st_code, rerank_factor=rerank, device="cuda:0")
     log(f"[bench] workspace {ix.workspace_bytes / 2**30:.2f} GiB")
     # bulk load (device time of the whole load)
-    xd = torch.from_numpy(x).to(dev)
-    idd = torch.from_numpy(ids).to(dev)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for s in range(0, x.shape[0], chunk):
-        ix.add(xd[s:s + chunk], idd[s:s + chunk])
-    e1.record()
-    assert ix.sync() == 0
-    bulk_ms = e0.elapsed_time(e1)
+    bulk_ms = 0.0
+    for s in range(0, x.shape[0], 1 << 20):
+        xd = torch.from_numpy(x[s:s + (1 << 20)]).to(dev)
+        idd = torch.from_numpy(ids[s:s + (1 << 20)]).to(dev)
+        torch.cuda.synchronize()
+        e0.record()
+        for c in range(0, xd.shape[0], chunk):
+            ix.add(xd[c:c + chunk], idd[c:c + chunk])
+        e1.record()
+        assert ix.sync() == 0
+        bulk_ms += e0.elapsed_time(e1)
+    del xd, idd
     log(f"[bench] bulk load {x.shape[0]} vectors: {bulk_ms:.1f} ms ({x.shape[0] / bulk_ms * 1e3 / 1e6:.2f} M vec/s)")
     # stream batches, resident in HBM before timing
     bx, bi, bo = [], [], []
@@ -179,19 +202,19 @@ def main():
     ix.profile(False)
     assert ix.sync() == 0
     # scan roofline: distance evaluations of one search = sum over (query,
-    # probe) of the probed list's length; 3 flops per dimension (sub + fma)
+    # probe) of the probed list's length
     probes = ix.probe(qd, nprobe).cpu().numpy()
     d = ix.dump()   # window state at the end of the timed region
     evals = int(d["list_len"].astype(np.int64)[probes[probes >= 0]].sum())
+    del d, bx, bi, bo
     scan_ms = prof["scan"][0] / max(prof["scan"][1], 1)
     log(f"[bench] {a.steps} steps in {elapsed:.3f} s; device ms per class: "
         + ", ".join(f"{kk}={v[0] / max(v[1], 1):.3f}" for kk, v in prof.items()))
 
     # graph mode: the same step captured once and replayed on refilled buffers
-    T2 = T + a.steps
-    gx = torch.empty_like(bx[0])
-    gi = torch.empty_like(bi[0])
-    go = torch.empty_like(bo[0])
+    gx = torch.empty((B, w.dim), dtype=torch.float32, device=dev)
+    gi = torch.empty(B, dtype=torch.int64, device=dev)
+    go = torch.empty(B, dtype=torch.int64, device=dev)
     nrem = torch.zeros(1, dtype=torch.int64, device=dev)
     g = ix.step_graph(gx, gi, qd, k, nprobe, go, dist, lab, nrem)
     gsteps = []
@@ -218,14 +241,18 @@ def main():
     keep = ids >= B * T2
     xw = np.concatenate([x[keep]] + [w.stream_batch(t)[0] for t in range(1, T2 + 1)])
     idw = np.concatenate([ids[keep]] + [w.stream_batch(t)[1] for t in range(1, T2 + 1)])
-    gt = exact_topk(xw, idw, q[:nrq], k)
+    t0 = time.time()
+    gt = exact_topk(xw, idw, q[:nrq], k, w.metric)
+    del xw, idw
+    log(f"[bench] exact kNN of {nrq} queries in {time.time() - t0:.1f} s")
 
     def recall_of(labels):
         return float(np.mean([len(set(gt[i]) & set(labels[i])) / k for i in range(nrq)]))
 
     sweep = []
     ix.profile(True)
-    for npb in ([1, 2, 4, 8, 16, 32, 64] if not a.no_sweep else [nprobe]):
+    grid = [1, 2, 4, 8, 16, 32, 64] + ([128] if nprobe > 64 else [])
+    for npb in (grid if not a.no_sweep else [nprobe]):
         ix.search(qd, k, npb, out=(dist, lab))
         ix.sync()
         ix.profile_read()
@@ -241,7 +268,6 @@ def main():
     best95 = max(ok95, key=lambda r: r["search_qps"]) if ok95 else None
     log(f"[bench] recall@{k} at nprobe {nprobe}: {recall:.4f}; sweep {sweep}")
 
-    copy_info = None
     if a.copy_calibration:
         nbytes = 1 << 30
         src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
@@ -249,32 +275,43 @@ def main():
         torch.cuda.synchronize()
         dst.copy_(src)
         torch.cuda.synchronize()
-        copy_info = {"bytes_read": nbytes, "bytes_written": nbytes}
         del src, dst
 
-    flops = evals * 3.0 * w.dim
-    achieved = flops / (scan_ms * 1e-3) / 1e12
-    # per-operation device rates
     add_ms = prof["add"][0] / max(prof["add"][1], 1)
     rm_ms = prof["remove"][0] / max(prof["remove"][1], 1)
     se_ms = prof["search"][0] / max(prof["search"][1], 1)
     sm = np.sort(np.array(step_ms))
+    if st_code == 0:
+        flops = evals * 3.0 * w.dim   # sub + fma per dimension
+        achieved = flops / (scan_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "kernel": "k_scan_sq", "achieved": round(achieved, 3),
+                "peak": round(ALU_PEAK_TFLOPS, 2), "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TFLOPS, 4),
+                "traffic": recorded_traffic() if a.workload == "window" else None,
+                "traffic_unit": "bytes per launch (DRAM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                "evals_per_launch": evals, "flops_per_eval": 3 * w.dim, "avg_launch_ms": round(scan_ms, 4)}
+    else:
+        flops = evals * 2.0 * 32 * ((w.dim + 31) // 32)   # MFMA work incl. padding to 32-dim blocks
+        achieved = flops / (scan_ms * 1e-3) / 1e12
+        roof = {"bound": "mfma", "kernel": "k_scan_mfma", "achieved": round(achieved, 3),
+                "peak": MFMA16_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / MFMA16_PEAK_TFLOPS, 4),
+                "traffic": None, "evals_per_launch": evals, "avg_launch_ms": round(scan_ms, 4)}
     res = {
         "metric": "insert/delete vectors/s; search QPS at recall@10>=0.95; p99 window-step ms",
         "value": round(nq * a.steps / elapsed, 1),
-        "unit": "queries/s (window step: +10k insert, 10k-query search, -10k delete)",
+        "unit": f"queries/s (window step: +{B} insert, {nq}-query search, -{B} delete)",
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": round(elapsed / a.steps * 1e3, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"f32": "f32", "bf16": "bf16 scan + f32 re-rank", "f16": "f16 scan + f32 re-rank"}[storage],
         "data": "synthetic",
         "config": {"workload": f"{w.name}: sliding window N={w.n_base}, d={w.dim}, nlist={w.nlist}, slab={w.slab}, "
-                               f"+{B}/-{B} per step, {nq} queries, nprobe={nprobe}, k={k}, L2",
+                               f"+{B}/-{B} per step, {nq} queries, nprobe={nprobe}, k={k}, "
+                               f"{'L2' if w.metric == 0 else 'IP'}, storage={storage}"
+                               + (f", re-rank top {rerank * k}" if rerank else ""),
                    "global_batch": nq, "parallelism": "single GPU"},
         "recall_at_10": recall,
         "qps_at_recall95": best95,
         "nprobe_sweep": sweep,
-        "graph_p50_step_ms": round(float(np.percentile(gsm, 50)), 4),
-        "graph_p99_step_ms": round(float(np.percentile(gsm, 99)), 4),
         "search_qps": round(nq / (se_ms * 1e-3), 1),
         "insert_vec_per_s": round(B / (add_ms * 1e-3), 1),
         "delete_vec_per_s": round(B / (rm_ms * 1e-3), 1),
@@ -282,15 +319,13 @@ def main():
         "p50_step_ms": round(float(np.percentile(sm, 50)), 4),
         "p99_step_ms": round(float(np.percentile(sm, 99)), 4),
         "max_step_ms": round(float(sm[-1]), 4),
+        "graph_p50_step_ms": round(float(np.percentile(gsm, 50)), 4),
+        "graph_p99_step_ms": round(float(np.percentile(gsm, 99)), 4),
         "device_ms": {kk: round(v[0] / max(v[1], 1), 4) for kk, v in prof.items()},
-        "roofline": {"bound": "alu", "kernel": "k_scan", "achieved": round(achieved, 3),
-                     "peak": round(ALU_PEAK_TFLOPS, 2), "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TFLOPS, 4),
-                     "traffic": recorded_traffic() if a.workload == "window" else None,
-                     "traffic_unit": "bytes per launch (DRAM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                     "evals_per_launch": evals, "flops_per_eval": 3 * w.dim,
-                     "avg_launch_ms": round(scan_ms, 4)},
+        "roofline": roof,
+        "cpu_baseline": None,
     }
-    if not a.no_cpu_baseline:
+    if not a.no_cpu_baseline and a.workload != "precision":
         t0 = time.time()
         xb, idb = w.stream_batch(1)
         res["cpu_baseline"] = cpu_baseline(w, x, ids, q, (xb, idb, w.oldest_ids(1)), nprobe, k,
