@@ -87,35 +87,85 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
 // the buffer (descending), an element-wise min against the list (the 64
 // smallest of both, as a bitonic sequence), and a bitonic merge.
 
+// Lane i receives lane (i ^ J)'s value.  Strides 1, 2, 4, 8 stay inside a
+// 16-lane row and use DPP (quad_perm, row_shl/row_shr, row_ror); 16 uses a
+// ds_swizzle xor pattern and 32 a ds_bpermute.
+template <int J>
+__device__ __forceinline__ uint32_t xor_lane(uint32_t v) {
+    const int x = (int)v;
+    if constexpr (J == 1) {
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+    } else if constexpr (J == 2) {
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+    } else if constexpr (J == 4) {
+        const int up = __builtin_amdgcn_update_dpp(0, x, 0x104, 0xF, 0xF, false);    // row_shl:4 (from i+4)
+        const int dn = __builtin_amdgcn_update_dpp(0, x, 0x114, 0xF, 0xF, false);    // row_shr:4 (from i-4)
+        return (uint32_t)((lane_id() & 4) ? dn : up);
+    } else if constexpr (J == 8) {
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, x, 0x128, 0xF, 0xF, false);  // row_ror:8
+    } else if constexpr (J == 16) {
+        return (uint32_t)__builtin_amdgcn_ds_swizzle(x, 0x401F);                     // xor 16 within 32
+    } else {
+        return (uint32_t)__shfl_xor(x, J);
+    }
+}
+
+template <int J>
+__device__ __forceinline__ uint64_t xor_lane_u64(uint64_t v) {
+    const uint32_t lo = xor_lane<J>((uint32_t)v), hi = xor_lane<J>((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// One compare-exchange step of a bitonic network over the 64 lanes: blocks
+// of K lanes, partner distance J; `asc` is the direction of the final order.
+template <int K, int J>
+__device__ __forceinline__ uint64_t bitonic_step(uint64_t v, bool asc) {
+    const int ln = lane_id();
+    const uint64_t p = xor_lane_u64<J>(v);
+    const bool up = ((ln & K) == 0) == asc;
+    const bool keep_min = ((ln & J) == 0) == up;
+    const uint64_t lo = p < v ? p : v, hi = p < v ? v : p;
+    return keep_min ? lo : hi;
+}
+
 // Sort the wave's 64 keys across lanes, ascending or descending.
 __device__ __forceinline__ uint64_t wave_sort64(uint64_t v, bool asc) {
-    const int ln = lane_id();
-#pragma unroll
-    for (int k = 2; k <= 64; k <<= 1) {
-#pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            const uint64_t p = shfl_xor_u64(v, j);
-            const bool up = ((ln & k) == 0) == asc;
-            const bool keep_min = ((ln & j) == 0) == up;
-            const uint64_t lo = p < v ? p : v, hi = p < v ? v : p;
-            v = keep_min ? lo : hi;
-        }
-    }
+    v = bitonic_step<2, 1>(v, asc);
+    v = bitonic_step<4, 2>(v, asc);
+    v = bitonic_step<4, 1>(v, asc);
+    v = bitonic_step<8, 4>(v, asc);
+    v = bitonic_step<8, 2>(v, asc);
+    v = bitonic_step<8, 1>(v, asc);
+    v = bitonic_step<16, 8>(v, asc);
+    v = bitonic_step<16, 4>(v, asc);
+    v = bitonic_step<16, 2>(v, asc);
+    v = bitonic_step<16, 1>(v, asc);
+    v = bitonic_step<32, 16>(v, asc);
+    v = bitonic_step<32, 8>(v, asc);
+    v = bitonic_step<32, 4>(v, asc);
+    v = bitonic_step<32, 2>(v, asc);
+    v = bitonic_step<32, 1>(v, asc);
+    v = bitonic_step<64, 32>(v, asc);
+    v = bitonic_step<64, 16>(v, asc);
+    v = bitonic_step<64, 8>(v, asc);
+    v = bitonic_step<64, 4>(v, asc);
+    v = bitonic_step<64, 2>(v, asc);
+    v = bitonic_step<64, 1>(v, asc);
     return v;
 }
 
 // The 64 smallest keys of a (sorted ascending across lanes) and b (any
-// order), sorted ascending.
+// order), sorted ascending: sort b descending; the element-wise min of a and
+// b holds the 64 smallest as a bitonic sequence; half-cleaners sort it.
 __device__ __forceinline__ uint64_t merge_sorted_with(uint64_t a, uint64_t b) {
     b = wave_sort64(b, false);
     uint64_t c = a < b ? a : b;
-    const int ln = lane_id();
-#pragma unroll
-    for (int j = 32; j > 0; j >>= 1) {
-        const uint64_t p = shfl_xor_u64(c, j);
-        const uint64_t lo = p < c ? p : c, hi = p < c ? c : p;
-        c = (ln & j) == 0 ? lo : hi;
-    }
+    c = bitonic_step<64, 32>(c, true);
+    c = bitonic_step<64, 16>(c, true);
+    c = bitonic_step<64, 8>(c, true);
+    c = bitonic_step<64, 4>(c, true);
+    c = bitonic_step<64, 2>(c, true);
+    c = bitonic_step<64, 1>(c, true);
     return c;
 }
 
@@ -429,7 +479,23 @@ constexpr int MQ = 16;       // queries per MFMA tile
 constexpr int MKB = 8;       // k-blocks of 32 dims: d <= 256
 constexpr int MBUF = 128;    // candidate buffer per query
 
-template <int METRIC, int DT>
+// Merge query t's buffered candidates into its sorted list (held in LDS,
+// lane i = i-th best) and return the list's kq-th key's high word.
+__device__ __forceinline__ uint32_t mfma_flush(uint64_t *stop, int t, const uint64_t *buf, int cnt, int kq,
+                                               int kcap) {
+    const int lane = lane_id();
+    const uint64_t b0 = lane < cnt ? buf[t * MBUF + lane] : ~0ull;
+    uint64_t c = merge_sorted_with(stop[t * 64 + lane], b0);
+    if (cnt > 64) {
+        const uint64_t b1 = lane + 64 < cnt ? buf[t * MBUF + 64 + lane] : ~0ull;
+        c = merge_sorted_with(c, b1);
+    }
+    c = lane < kcap ? c : ~0ull;
+    stop[t * 64 + lane] = c;
+    return kq > 0 ? (uint32_t)(readlane_u64(c, kq - 1) >> 32) : 0u;
+}
+
+template <int METRIC, int DT, int NKB>
 __global__ __launch_bounds__(64) void k_scan_mfma(Dev S, const int32_t *__restrict__ item_list,
                                                   const int32_t *__restrict__ item_tile,
                                                   const int32_t *__restrict__ list_pairs,
@@ -437,6 +503,7 @@ __global__ __launch_bounds__(64) void k_scan_mfma(Dev S, const int32_t *__restri
                                                   int kmul, const int32_t *__restrict__ kpq,
                                                   uint64_t *__restrict__ partials, int per_xcd) {
     __shared__ uint64_t buf[MQ * MBUF];
+    __shared__ uint64_t stop[MQ * 64];   // per query: sorted best keys
     __shared__ int scnt[MQ], skq[MQ];
     __shared__ uint32_t sid[64];
     __shared__ float sxn[64];
@@ -447,7 +514,6 @@ __global__ __launch_bounds__(64) void k_scan_mfma(Dev S, const int32_t *__restri
     const int l = item_list[item], tile = item_tile[item];
     const int nt = min(MQ, S.l_qcs[l] - tile * MQ);
     const int d = S.d, C = S.C, dp8 = S.dp8;
-    const int nkb = (d + 31) / 32;
     const int32_t *pairs = list_pairs + S.l_qoff[l] + tile * MQ;
     if (lane < MQ) {
         skq[lane] = lane < nt ? min(kmul * query_k(kpq, k, pairs[lane] / np_stride), kcap) : 0;
@@ -455,15 +521,15 @@ __global__ __launch_bounds__(64) void k_scan_mfma(Dev S, const int32_t *__restri
     }
     // B operand: query qcol, dims 32 kb + 8 kgrp .. +8, rounded like the slabs
     const float *qr = q + (int64_t)(pairs[qcol < nt ? qcol : 0] / np_stride) * d;
-    uint4 bq[MKB];
+    uint4 bq[NKB];
     float qn = 0.f;
 #pragma unroll
-    for (int kb = 0; kb < MKB; kb++) {
+    for (int kb = 0; kb < NKB; kb++) {
         uint32_t h[8];
 #pragma unroll
         for (int e = 0; e < 8; e++) {
             const int j = 32 * kb + 8 * kgrp + e;
-            const float v = (kb < nkb && j < d) ? qr[j] : 0.f;
+            const float v = j < d ? qr[j] : 0.f;
             h[e] = DT == 1 ? to_bf16_bits(v) : to_f16_bits(v);
             const float r = DT == 1 ? bf16_bits_to_float(h[e]) : f16_bits_to_float(h[e]);
             qn = fmaf(r, r, qn);
@@ -474,9 +540,8 @@ __global__ __launch_bounds__(64) void k_scan_mfma(Dev S, const int32_t *__restri
     qn += __shfl_xor(qn, 32);
     __syncthreads();
     uint32_t thr = skq[qcol] > 0 ? 0xFFFFFFFFu : 0u;   // threshold of query qcol
-    uint64_t top[MQ];
 #pragma unroll
-    for (int t = 0; t < MQ; t++) top[t] = ~0ull;
+    for (int t = 0; t < MQ; t++) stop[t * 64 + lane] = ~0ull;
 
     const int len = S.len[l];
     const int nslab = cdiv_s(len, C);
@@ -493,7 +558,7 @@ __global__ __launch_bounds__(64) void k_scan_mfma(Dev S, const int32_t *__restri
             const int slab = __shfl(wslab, pc / C - wbase);
             const int64_t g = (int64_t)slab * C + pc % C;
             sid[lane] = S.sids[g];
-            sxn[lane] = (METRIC == 0 && S.xnorm) ? S.xnorm[g] : 0.f;
+            if (METRIC == 0) sxn[lane] = S.xnorm[g];
         }
         f32x4_t acc[4];
 #pragma unroll
@@ -504,63 +569,73 @@ __global__ __launch_bounds__(64) void k_scan_mfma(Dev S, const int32_t *__restri
             const uint4 *hp = S.hdata + (int64_t)slab * dp8 * C + pc % C;
             acc[rg] = f32x4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int kb = 0; kb < MKB; kb++) {
-                if (kb < nkb) {
-                    const int c8 = 4 * kb + kgrp;
-                    const uint4 a = (c8 < dp8 && p < len) ? hp[(int64_t)c8 * C] : make_uint4(0, 0, 0, 0);
-                    acc[rg] = mfma_16x16x32<DT>(a, bq[kb], acc[rg]);
-                }
+            for (int kb = 0; kb < NKB; kb++) {
+                const int c8 = 4 * kb + kgrp;
+                const uint4 a = (c8 < dp8 && p < len) ? hp[(int64_t)c8 * C] : make_uint4(0, 0, 0, 0);
+                acc[rg] = mfma_16x16x32<DT>(a, bq[kb], acc[rg]);
             }
         }
         __syncthreads();
+        // lane holds query qcol's scores of positions base + 16 rg + 4 kgrp + j
+        uint32_t hiv[16];
+        uint32_t pmask = 0;
 #pragma unroll
         for (int rg = 0; rg < 4; rg++) {
 #pragma unroll
             for (int j = 0; j < 4; j++) {
-                const int r = 16 * rg + 4 * kgrp + j;   // position base + r
+                const int r = 16 * rg + 4 * kgrp + j;
                 const float v = METRIC == 0 ? (qn + sxn[r]) - 2.f * acc[rg][j] : acc[rg][j];
                 const uint32_t hi = METRIC == 0 ? ord_bits(v) : ~ord_bits(v);
-                if (base + r < len && qcol < nt && hi <= thr) {
-                    const int at = atomicAdd(&scnt[qcol], 1);
-                    buf[qcol * MBUF + at] = ((uint64_t)hi << 32) | sid[r];
-                }
+                hiv[4 * rg + j] = hi;
+                if (base + r < len && qcol < nt && hi <= thr) pmask |= 1u << (4 * rg + j);
             }
         }
-        __syncthreads();
-        // merge buffers that could overflow on the next step, and fill each
-        // query's list as soon as it has k candidates (sets its threshold)
+        if (ballot(pmask != 0)) {
+            // offsets of this lane's candidates among the 4 lanes of its query
+            const int np = __builtin_popcount(pmask);
+            int incl = np;
+            int u = __shfl_up(incl, 16);
+            if (kgrp >= 1) incl += u;
+            u = __shfl_up(incl, 32);
+            if (kgrp >= 2) incl += u;
+            const int at0 = scnt[qcol] + incl - np;
+            int at = at0;
 #pragma unroll
-        for (int t = 0; t < MQ; t++) {
-            const int cnt = scnt[t];
-            const bool unset = __builtin_amdgcn_readlane((int)thr, t) == (int)0xFFFFFFFFu;
-            if (cnt > MBUF - 64 || (unset && cnt >= skq[t] && cnt > 0)) {
-                const uint64_t b0 = lane < cnt ? buf[t * MBUF + lane] : ~0ull;
-                const uint64_t b1 = lane + 64 < cnt ? buf[t * MBUF + 64 + lane] : ~0ull;
-                uint64_t c = merge_sorted_with(top[t], b0);
-                if (cnt > 64) c = merge_sorted_with(c, b1);
-                c = lane < kcap ? c : ~0ull;
-                top[t] = c;
-                const uint32_t nthr = skq[t] > 0 ? (uint32_t)(readlane_u64(c, skq[t] - 1) >> 32) : 0u;
-                if (qcol == t) thr = nthr;
-                __syncthreads();
-                if (lane == 0) scnt[t] = 0;
+            for (int b = 0; b < 16; b++) {
+                if ((pmask >> b) & 1u) {
+                    const int r = 16 * (b >> 2) + 4 * kgrp + (b & 3);
+                    buf[qcol * MBUF + at] = ((uint64_t)hiv[b] << 32) | sid[r];
+                    at++;
+                }
+            }
+            __syncthreads();
+            if (kgrp == 3) scnt[qcol] = at;   // the last lane of the query holds the new count
+            __syncthreads();
+            // merge buffers that could overflow on the next step, and fill a
+            // query's list as soon as it has k candidates (sets its threshold)
+            bool need = false;
+            if (lane < MQ) {
+                const int cnt = scnt[lane];
+                need = cnt > MBUF - 64 || (thr == 0xFFFFFFFFu && cnt > 0 && cnt >= skq[lane]);
+            }
+            uint64_t fm = ballot(need);
+            if (fm) {
+                while (fm) {
+                    const int t = __builtin_ctzll(fm);
+                    fm &= fm - 1;
+                    const uint32_t nthr = mfma_flush(stop, t, buf, scnt[t], skq[t], kcap);
+                    if (qcol == t) thr = nthr;
+                    __syncthreads();
+                    if (lane == 0) scnt[t] = 0;
+                }
                 __syncthreads();
             }
         }
     }
-#pragma unroll
-    for (int t = 0; t < MQ; t++) {
-        if (t < nt) {
-            const int cnt = scnt[t];
-            if (cnt > 0) {
-                const uint64_t b0 = lane < cnt ? buf[t * MBUF + lane] : ~0ull;
-                const uint64_t b1 = lane + 64 < cnt ? buf[t * MBUF + 64 + lane] : ~0ull;
-                uint64_t c = merge_sorted_with(top[t], b0);
-                if (cnt > 64) c = merge_sorted_with(c, b1);
-                top[t] = lane < kcap ? c : ~0ull;
-            }
-            if (lane < kcap) partials[(int64_t)pairs[t] * kcap + lane] = top[t];
-        }
+    for (int t = 0; t < nt; t++) {
+        const int cnt = scnt[t];
+        if (cnt > 0) mfma_flush(stop, t, buf, cnt, skq[t], kcap);
+        if (lane < kcap) partials[(int64_t)pairs[t] * kcap + lane] = stop[t * 64 + lane];
     }
 }
 
@@ -622,13 +697,23 @@ void launch_search_scan_mfma(hipStream_t st, const Dev &S, const SearchBufs &W, 
     const int64_t bound = (int64_t)npairs / MQ + (npairs < S.nlist ? npairs : S.nlist);
     const int per_xcd = (int)((bound + 7) / 8);
     const unsigned grid = (unsigned)(8 * per_xcd);
-#define SIVF_LAUNCH_MFMA(M, D)                                                                               \
-    hipLaunchKernelGGL((k_scan_mfma<M, D>), dim3(grid), dim3(64), 0, st, S, W.item_list, W.item_tile,         \
+    // k-blocks of 32 dimensions held as B operands: 2, 3, 4 or 8 (d <= 256)
+    const int nkb = (S.d + 31) / 32;
+#define SIVF_LAUNCH_MFMA(M, D, K)                                                                            \
+    hipLaunchKernelGGL((k_scan_mfma<M, D, K>), dim3(grid), dim3(64), 0, st, S, W.item_list, W.item_tile,     \
                        W.list_pairs, q, np_stride, kcap, k, kmul, k_per_query, W.partials, per_xcd)
-    if (S.metric == 0 && S.storage == 1) SIVF_LAUNCH_MFMA(0, 1);
-    else if (S.metric == 0) SIVF_LAUNCH_MFMA(0, 2);
-    else if (S.storage == 1) SIVF_LAUNCH_MFMA(1, 1);
-    else SIVF_LAUNCH_MFMA(1, 2);
+#define SIVF_LAUNCH_MFMA_K(M, D)                                                                             \
+    do {                                                                                                     \
+        if (nkb <= 2) SIVF_LAUNCH_MFMA(M, D, 2);                                                             \
+        else if (nkb == 3) SIVF_LAUNCH_MFMA(M, D, 3);                                                        \
+        else if (nkb == 4) SIVF_LAUNCH_MFMA(M, D, 4);                                                        \
+        else SIVF_LAUNCH_MFMA(M, D, 8);                                                                      \
+    } while (0)
+    if (S.metric == 0 && S.storage == 1) SIVF_LAUNCH_MFMA_K(0, 1);
+    else if (S.metric == 0) SIVF_LAUNCH_MFMA_K(0, 2);
+    else if (S.storage == 1) SIVF_LAUNCH_MFMA_K(1, 1);
+    else SIVF_LAUNCH_MFMA_K(1, 2);
+#undef SIVF_LAUNCH_MFMA_K
 #undef SIVF_LAUNCH_MFMA
 }
 
