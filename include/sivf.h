@@ -74,7 +74,8 @@ typedef struct {
     int32_t storage;       /* sivf_dtype of the scanned copy of each vector: with
                             * SIVF_BF16 / SIVF_F16 the slabs hold a rounded copy
                             * (round to nearest even) scanned on MFMA, beside the
-                            * exact fp32 copy used for the final re-rank; dim <= 256 */
+                            * exact fp32 copy used for the final re-rank; needs
+                            * dim <= 256 and slab_capacity >= 16               */
     int32_t rerank_factor; /* R: reduced precision keeps the best R * k candidates
                             * per query by approximate distance, then re-ranks them
                             * by the exact fp32 distance; R * max_k <= 64.  Must be

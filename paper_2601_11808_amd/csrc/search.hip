@@ -477,21 +477,22 @@ __device__ __forceinline__ f32x4_t mfma_16x16x32(uint4 a, uint4 b, f32x4_t c) {
 
 constexpr int MQ = 16;       // queries per MFMA tile
 constexpr int MKB = 8;       // k-blocks of 32 dims: d <= 256
-constexpr int MBUF = 128;    // candidate buffer per query
+constexpr int MBUF = 96;     // candidate buffer per query (a step adds at most 64)
 
-// Merge query t's buffered candidates into its sorted list (held in LDS,
-// lane i = i-th best) and return the list's kq-th key's high word.
-__device__ __forceinline__ uint32_t mfma_flush(uint64_t *stop, int t, const uint64_t *buf, int cnt, int kq,
+// Merge query t's buffered candidates into its sorted list (lane i = i-th
+// best) and return the list's kq-th key's high word.
+template <int NQ>
+__device__ __forceinline__ uint32_t mfma_flush(uint64_t (&top)[NQ], int t, const uint64_t *buf, int cnt, int kq,
                                                int kcap) {
     const int lane = lane_id();
     const uint64_t b0 = lane < cnt ? buf[t * MBUF + lane] : ~0ull;
-    uint64_t c = merge_sorted_with(stop[t * 64 + lane], b0);
+    uint64_t c = merge_sorted_with(top[t], b0);
     if (cnt > 64) {
         const uint64_t b1 = lane + 64 < cnt ? buf[t * MBUF + 64 + lane] : ~0ull;
         c = merge_sorted_with(c, b1);
     }
     c = lane < kcap ? c : ~0ull;
-    stop[t * 64 + lane] = c;
+    top[t] = c;
     return kq > 0 ? (uint32_t)(readlane_u64(c, kq - 1) >> 32) : 0u;
 }
 
@@ -503,10 +504,7 @@ __global__ __launch_bounds__(64) void k_scan_mfma(Dev S, const int32_t *__restri
                                                   int kmul, const int32_t *__restrict__ kpq,
                                                   uint64_t *__restrict__ partials, int per_xcd) {
     __shared__ uint64_t buf[MQ * MBUF];
-    __shared__ uint64_t stop[MQ * 64];   // per query: sorted best keys
     __shared__ int scnt[MQ], skq[MQ];
-    __shared__ uint32_t sid[64];
-    __shared__ float sxn[64];
     const int w = blockIdx.x;
     const int item = (w & 7) * per_xcd + (w >> 3);
     if (item >= S.ctl[CTL_NITEMS]) return;
@@ -540,8 +538,9 @@ __global__ __launch_bounds__(64) void k_scan_mfma(Dev S, const int32_t *__restri
     qn += __shfl_xor(qn, 32);
     __syncthreads();
     uint32_t thr = skq[qcol] > 0 ? 0xFFFFFFFFu : 0u;   // threshold of query qcol
+    uint64_t top[MQ];
 #pragma unroll
-    for (int t = 0; t < MQ; t++) stop[t * 64 + lane] = ~0ull;
+    for (int t = 0; t < MQ; t++) top[t] = ~0ull;
 
     const int len = S.len[l];
     const int nslab = cdiv_s(len, C);
@@ -552,13 +551,19 @@ __global__ __launch_bounds__(64) void k_scan_mfma(Dev S, const int32_t *__restri
             wbase = base / C;
             wslab = (wbase + lane < nslab) ? slab_of(S, l, wbase + lane) : 0;
         }
-        {   // ids and norms of the 64 positions of this step, one per lane
-            const int p = base + lane;
-            const int pc = p < len ? p : len - 1;
-            const int slab = __shfl(wslab, pc / C - wbase);
-            const int64_t g = (int64_t)slab * C + pc % C;
-            sid[lane] = S.sids[g];
-            if (METRIC == 0) sxn[lane] = S.xnorm[g];
+        // the 4 result rows of this lane in row group rg are positions
+        // base + 16 rg + 4 kgrp .. +3: one slab (C >= 4), 16-byte aligned slots
+        int64_t g4[4];
+#pragma unroll
+        for (int rg = 0; rg < 4; rg++) {
+            const int p = base + 16 * rg + 4 * kgrp;
+            const int pc = p < len ? p : ((len - 1) & ~3);
+            g4[rg] = (int64_t)__shfl(wslab, pc / C - wbase) * C + pc % C;
+        }
+        float4 xn4[4] = {};
+        if (METRIC == 0) {
+#pragma unroll
+            for (int rg = 0; rg < 4; rg++) xn4[rg] = *reinterpret_cast<const float4 *>(S.xnorm + g4[rg]);
         }
         f32x4_t acc[4];
 #pragma unroll
@@ -575,16 +580,15 @@ __global__ __launch_bounds__(64) void k_scan_mfma(Dev S, const int32_t *__restri
                 acc[rg] = mfma_16x16x32<DT>(a, bq[kb], acc[rg]);
             }
         }
-        __syncthreads();
-        // lane holds query qcol's scores of positions base + 16 rg + 4 kgrp + j
         uint32_t hiv[16];
         uint32_t pmask = 0;
 #pragma unroll
         for (int rg = 0; rg < 4; rg++) {
+            const float xs[4] = {xn4[rg].x, xn4[rg].y, xn4[rg].z, xn4[rg].w};
 #pragma unroll
             for (int j = 0; j < 4; j++) {
                 const int r = 16 * rg + 4 * kgrp + j;
-                const float v = METRIC == 0 ? (qn + sxn[r]) - 2.f * acc[rg][j] : acc[rg][j];
+                const float v = METRIC == 0 ? (qn + xs[j]) - 2.f * acc[rg][j] : acc[rg][j];
                 const uint32_t hi = METRIC == 0 ? ord_bits(v) : ~ord_bits(v);
                 hiv[4 * rg + j] = hi;
                 if (base + r < len && qcol < nt && hi <= thr) pmask |= 1u << (4 * rg + j);
@@ -598,14 +602,19 @@ __global__ __launch_bounds__(64) void k_scan_mfma(Dev S, const int32_t *__restri
             if (kgrp >= 1) incl += u;
             u = __shfl_up(incl, 32);
             if (kgrp >= 2) incl += u;
-            const int at0 = scnt[qcol] + incl - np;
-            int at = at0;
+            int at = scnt[qcol] + incl - np;
 #pragma unroll
-            for (int b = 0; b < 16; b++) {
-                if ((pmask >> b) & 1u) {
-                    const int r = 16 * (b >> 2) + 4 * kgrp + (b & 3);
-                    buf[qcol * MBUF + at] = ((uint64_t)hiv[b] << 32) | sid[r];
-                    at++;
+            for (int rg = 0; rg < 4; rg++) {
+                if ((pmask >> (4 * rg)) & 0xFu) {
+                    const uint4 id4 = *reinterpret_cast<const uint4 *>(S.sids + g4[rg]);
+                    const uint32_t ids[4] = {id4.x, id4.y, id4.z, id4.w};
+#pragma unroll
+                    for (int j = 0; j < 4; j++) {
+                        if ((pmask >> (4 * rg + j)) & 1u) {
+                            buf[qcol * MBUF + at] = ((uint64_t)hiv[4 * rg + j] << 32) | ids[j];
+                            at++;
+                        }
+                    }
                 }
             }
             __syncthreads();
@@ -618,24 +627,28 @@ __global__ __launch_bounds__(64) void k_scan_mfma(Dev S, const int32_t *__restri
                 const int cnt = scnt[lane];
                 need = cnt > MBUF - 64 || (thr == 0xFFFFFFFFu && cnt > 0 && cnt >= skq[lane]);
             }
-            uint64_t fm = ballot(need);
+            const uint64_t fm = ballot(need);
             if (fm) {
-                while (fm) {
-                    const int t = __builtin_ctzll(fm);
-                    fm &= fm - 1;
-                    const uint32_t nthr = mfma_flush(stop, t, buf, scnt[t], skq[t], kcap);
-                    if (qcol == t) thr = nthr;
-                    __syncthreads();
-                    if (lane == 0) scnt[t] = 0;
+#pragma unroll
+                for (int t = 0; t < MQ; t++) {
+                    if ((fm >> t) & 1ull) {
+                        const uint32_t nthr = mfma_flush<MQ>(top, t, buf, scnt[t], skq[t], kcap);
+                        if (qcol == t) thr = nthr;
+                    }
                 }
+                __syncthreads();
+                if (lane < MQ && ((fm >> lane) & 1ull)) scnt[lane] = 0;
                 __syncthreads();
             }
         }
     }
-    for (int t = 0; t < nt; t++) {
-        const int cnt = scnt[t];
-        if (cnt > 0) mfma_flush(stop, t, buf, cnt, skq[t], kcap);
-        if (lane < kcap) partials[(int64_t)pairs[t] * kcap + lane] = stop[t * 64 + lane];
+#pragma unroll
+    for (int t = 0; t < MQ; t++) {
+        if (t < nt) {
+            const int cnt = scnt[t];
+            if (cnt > 0) mfma_flush<MQ>(top, t, buf, cnt, skq[t], kcap);
+            if (lane < kcap) partials[(int64_t)pairs[t] * kcap + lane] = top[t];
+        }
     }
 }
 

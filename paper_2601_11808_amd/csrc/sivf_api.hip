@@ -42,7 +42,8 @@ bool config_ok(const sivf_config *c) {
     if (c->storage != SIVF_F32 && c->storage != SIVF_BF16 && c->storage != SIVF_F16) return false;
     if (c->storage == SIVF_F32 && c->rerank_factor != 0) return false;
     if (c->storage != SIVF_F32 &&
-        (c->dim > 256 || c->rerank_factor < 1 || (int64_t)c->rerank_factor * c->max_k > 64))
+        (c->dim > 256 || c->slab_capacity < 16 || c->rerank_factor < 1 ||
+         (int64_t)c->rerank_factor * c->max_k > 64))
         return false;
     if (c->num_slabs < 1 || c->num_slabs * (int64_t)c->slab_capacity >= (1ll << 31)) return false;
     if (c->id_capacity < 1 || c->id_capacity >= (1ll << 31)) return false;
