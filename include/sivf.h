@@ -57,7 +57,8 @@ typedef enum {
     SIVF_ERR_NOSPACE = -2,  /* slab pool too small for the add batch (Sec. 3.2)  */
     SIVF_ERR_ID_RANGE = -3, /* an id outside [0, id_capacity)                    */
     SIVF_ERR_DEVICE = -4,   /* a HIP runtime call failed                         */
-    SIVF_ERR_STATE = -5     /* handle unusable (e.g. after a device error)       */
+    SIVF_ERR_STATE = -5,    /* handle unusable (e.g. after a device error)       */
+    SIVF_ERR_LIVE_ID = -6   /* a server insert named an id that is live          */
 } sivf_status;
 
 typedef enum { SIVF_L2 = 0, SIVF_IP = 1 } sivf_metric;
@@ -244,6 +245,38 @@ sivf_status sivf_profile_enable(sivf_index *ix, int on);
  * the number of timed intervals of each class (host arrays of
  * SIVF_PROF_KINDS entries, either may be NULL) and reset the sums. */
 sivf_status sivf_profile_read(sivf_index *ix, double *total_ms, int64_t *count);
+
+/* Serving: a request loop over one index whose requests overlap on the GPU
+ * (the paper's mixed workload, Sec. 5.5, as continuous batching).  Searches
+ * run on one stream and inserts/removes on another:
+ *   - a search waits for every mutation submitted before it, then records
+ *     the length of every list and scans only those entries;
+ *   - an insert waits only until the most recent earlier search has recorded
+ *     the lengths: inserts append past them, so the two overlap;
+ *   - a remove (it moves entries inside lists) waits for every earlier search.
+ * Each request therefore returns what it returns when the requests run one
+ * at a time in submission order.  Server inserts must use ids that are not
+ * live (else the call fails with SIVF_ERR_LIVE_ID and changes nothing).
+ * Admission: an insert of n vectors is refused at once with SIVF_ERR_NOSPACE
+ * (nothing enqueued) unless the host's view of the free-slab count, minus
+ * the slabs reserved by inserts in flight, covers ceil(n/C) + min(n, nlist)
+ * slabs.  The free-slab count is copied back after every mutation without
+ * blocking.  Every submit returns a ticket; sivf_server_poll (non-blocking)
+ * and sivf_server_wait (blocking) observe its completion.  Buffers stay owned
+ * by the caller until the ticket completes.  One host thread per server; do
+ * not use the index directly while a server is in use. */
+typedef struct sivf_server sivf_server;
+sivf_status sivf_server_create(sivf_index *ix, sivf_server **out);
+sivf_status sivf_server_destroy(sivf_server *s);   /* waits for every request */
+sivf_status sivf_server_add(sivf_server *s, int64_t n, const float *x, const int64_t *ids, int64_t *ticket);
+sivf_status sivf_server_remove(sivf_server *s, int64_t n, const int64_t *ids, int64_t *n_removed,
+                               int64_t *ticket);
+sivf_status sivf_server_search(sivf_server *s, int64_t nq, const float *q, int32_t k, int32_t nprobe,
+                               float *dist, int64_t *labels, int64_t *ticket);
+sivf_status sivf_server_poll(sivf_server *s, int64_t ticket, int *done);
+sivf_status sivf_server_wait(sivf_server *s, int64_t ticket);
+/* Host view of free slabs and the slabs reserved by inserts in flight. */
+sivf_status sivf_server_free_slabs(sivf_server *s, int64_t *free_slabs, int64_t *reserved);
 
 /* Static text for a status code. */
 const char *sivf_status_string(sivf_status s);

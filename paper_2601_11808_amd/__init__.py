@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsivf.so")
 
-OK, ERR_ARG, ERR_NOSPACE, ERR_ID_RANGE, ERR_DEVICE, ERR_STATE = 0, -1, -2, -3, -4, -5
+OK, ERR_ARG, ERR_NOSPACE, ERR_ID_RANGE, ERR_DEVICE, ERR_STATE, ERR_LIVE_ID = 0, -1, -2, -3, -4, -5, -6
 L2, IP = 0, 1
 F32, BF16, F16 = 0, 1, 2
 
@@ -71,6 +71,14 @@ SIGNATURES = [
     ("sivf_dump", ct.c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),
     ("sivf_profile_enable", ct.c_int, [_P, ct.c_int]),
     ("sivf_profile_read", ct.c_int, [_P, _P, _P]),
+    ("sivf_server_create", ct.c_int, [_P, ct.POINTER(_P)]),
+    ("sivf_server_destroy", ct.c_int, [_P]),
+    ("sivf_server_add", ct.c_int, [_P, _I64, _P, _P, ct.POINTER(_I64)]),
+    ("sivf_server_remove", ct.c_int, [_P, _I64, _P, _P, ct.POINTER(_I64)]),
+    ("sivf_server_search", ct.c_int, [_P, _I64, _P, _I32, _I32, _P, _P, ct.POINTER(_I64)]),
+    ("sivf_server_poll", ct.c_int, [_P, _I64, ct.POINTER(ct.c_int)]),
+    ("sivf_server_wait", ct.c_int, [_P, _I64]),
+    ("sivf_server_free_slabs", ct.c_int, [_P, ct.POINTER(_I64), ct.POINTER(_I64)]),
     ("sivf_status_string", ct.c_char_p, [ct.c_int]),
 ]
 
@@ -372,3 +380,83 @@ class StepGraph:
             self.close()
         except Exception:
             pass
+
+
+class Server:
+    """Overlapping request loop over one index (see sivf_server_* in
+    include/sivf.h).  Submit methods return a ticket, or None when an insert
+    is refused for lack of free slabs (nothing was enqueued; retry later).
+    Device tensors of a request are kept alive until its ticket completes."""
+
+    def __init__(self, index):
+        self.index = index
+        h = ct.c_void_p()
+        _check(lib().sivf_server_create(index._h, ct.byref(h)), "sivf_server_create")
+        self._h = h
+        self._keep = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().sivf_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add(self, x, ids):
+        torch = _torch()
+        x = _dev_tensor(x, torch.float32, self.index.device).reshape(-1, self.index.dim)
+        ids = _dev_tensor(ids, torch.int64, self.index.device).reshape(-1)
+        t = ct.c_int64(0)
+        st = lib().sivf_server_add(self._h, x.shape[0], _ptr(x), _ptr(ids), ct.byref(t))
+        if st == ERR_NOSPACE:
+            return None
+        _check(st, "sivf_server_add")
+        self._keep[t.value] = (x, ids)
+        return t.value
+
+    def remove(self, ids):
+        """Returns (ticket, device int64 scalar with the number removed)."""
+        torch = _torch()
+        ids = _dev_tensor(ids, torch.int64, self.index.device).reshape(-1)
+        nrem = torch.zeros(1, dtype=torch.int64, device=self.index.device)
+        t = ct.c_int64(0)
+        _check(lib().sivf_server_remove(self._h, ids.shape[0], _ptr(ids), _ptr(nrem), ct.byref(t)),
+               "sivf_server_remove")
+        self._keep[t.value] = (ids, nrem)
+        return t.value, nrem
+
+    def search(self, q, k, nprobe, out=None):
+        """Returns (ticket, dist, labels); read them after the ticket completes."""
+        torch = _torch()
+        q = _dev_tensor(q, torch.float32, self.index.device).reshape(-1, self.index.dim)
+        if out is None:
+            dist = torch.empty((q.shape[0], k), dtype=torch.float32, device=self.index.device)
+            lab = torch.empty((q.shape[0], k), dtype=torch.int64, device=self.index.device)
+        else:
+            dist, lab = out
+        t = ct.c_int64(0)
+        _check(lib().sivf_server_search(self._h, q.shape[0], _ptr(q), k, nprobe, _ptr(dist), _ptr(lab),
+                                        ct.byref(t)), "sivf_server_search")
+        self._keep[t.value] = (q, dist, lab)
+        return t.value, dist, lab
+
+    def poll(self, ticket):
+        d = ct.c_int(0)
+        _check(lib().sivf_server_poll(self._h, ticket, ct.byref(d)), "sivf_server_poll")
+        if d.value:
+            self._keep.pop(ticket, None)
+        return bool(d.value)
+
+    def wait(self, ticket):
+        _check(lib().sivf_server_wait(self._h, ticket), "sivf_server_wait")
+        self._keep.pop(ticket, None)
+
+    def free_slabs(self):
+        f, r = ct.c_int64(), ct.c_int64()
+        _check(lib().sivf_server_free_slabs(self._h, ct.byref(f), ct.byref(r)), "sivf_server_free_slabs")
+        return f.value, r.value

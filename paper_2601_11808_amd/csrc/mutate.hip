@@ -40,8 +40,10 @@ __global__ __launch_bounds__(256) void k_add_prepare(Dev S, int n, const int64_t
         atomicMax(&S.mark[u], i);
 }
 
+// fresh_only: the call may not hold live ids (SIVF_ERR_LIVE_ID otherwise).
 __global__ __launch_bounds__(256) void k_add_count(Dev S, int n, const int64_t *__restrict__ ids,
-                                                   const int32_t *__restrict__ assign, int32_t *__restrict__ rank) {
+                                                   const int32_t *__restrict__ assign, int32_t *__restrict__ rank,
+                                                   int fresh_only) {
     if (call_failed(S.ctl)) return;
     const int i = blockIdx.x * 256 + threadIdx.x;
     const bool active = i < n;
@@ -54,7 +56,12 @@ __global__ __launch_bounds__(256) void k_add_count(Dev S, int n, const int64_t *
     const bool live = g != INVALID;
     const int lo = live ? S.sowner[g / (uint32_t)S.C] : 0;
     wave_agg_inc(S.l_prem, lo, live);
-    if (ballot(live) && lane_id() == 0) atomicExch(&S.ctl[CTL_UPSERT], S.ctl[CTL_SEQ]);
+    if (ballot(live) && lane_id() == 0) {
+        if (fresh_only)
+            fail_call(S.ctl, -6);
+        else
+            atomicExch(&S.ctl[CTL_UPSERT], S.ctl[CTL_SEQ]);
+    }
 }
 
 // One block: does the final state fit in the pool?
@@ -396,8 +403,8 @@ void launch_add_prepare(hipStream_t st, const Dev &S, int n, const int64_t *ids)
     hipLaunchKernelGGL(k_add_prepare, dim3(blocks(n)), dim3(256), 0, st, S, n, ids);
 }
 
-void launch_add_count(hipStream_t st, const Dev &S, int n, const int64_t *ids, const Batch &B) {
-    hipLaunchKernelGGL(k_add_count, dim3(blocks(n)), dim3(256), 0, st, S, n, ids, B.assign, B.rank);
+void launch_add_count(hipStream_t st, const Dev &S, int n, const int64_t *ids, const Batch &B, int fresh_only) {
+    hipLaunchKernelGGL(k_add_count, dim3(blocks(n)), dim3(256), 0, st, S, n, ids, B.assign, B.rank, fresh_only);
 }
 
 void launch_add_admit(hipStream_t st, const Dev &S) {

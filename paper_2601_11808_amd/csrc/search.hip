@@ -42,6 +42,7 @@ __global__ __launch_bounds__(1024) void k_inv_plan(Dev S, int T, int32_t *__rest
         const bool valid = l < S.nlist;
         const int qc = valid ? S.l_qc[l] : 0;
         const int ln = valid ? S.len[l] : 0;
+        if (valid) S.l_snap[l] = ln;
         const int nt = (qc > 0 && ln > 0) ? cdiv_s(qc, T) : 0;
         int tp, ti;
         const int ep = block_excl_scan<1024>(qc, sbuf, &tp);
@@ -235,7 +236,7 @@ __device__ __forceinline__ uint32_t key_hi(float v) {
 // of a tile, in the canonical order (dimensions ascending, one fma each), then
 // offered to each query's top-k.  QV(t, c) gives query t's dimension chunk c.
 #define SIVF_SCAN_BODY(QV)                                                                       \
-    const int len = S.len[l];                                                                    \
+    const int len = S.l_snap[l];                                                                 \
     const int nslab = cdiv_s(len, C);                                                            \
     int wbase = -(1 << 30), wslab = 0; /* lane j holds the slab of ordinal wbase + j */          \
     for (int base = 0; base < len; base += 64) {                                                 \
@@ -392,7 +393,7 @@ __global__ __launch_bounds__(256) void k_merge(Dev S, int nq, int np_stride, con
     const uint64_t *part = partials + (int64_t)qi * np_stride * kcap;
     auto head_key = [&](int p) -> uint64_t {
         const int l = prow[p];
-        if (l < 0 || S.len[l] == 0) return ~0ull;
+        if (l < 0 || S.l_snap[l] == 0) return ~0ull;
         const int h = heads[w][p];
         return h < kcap ? part[(int64_t)p * kcap + h] : ~0ull;
     };
@@ -542,7 +543,7 @@ __global__ __launch_bounds__(64) void k_scan_mfma(Dev S, const int32_t *__restri
 #pragma unroll
     for (int t = 0; t < MQ; t++) top[t] = ~0ull;
 
-    const int len = S.len[l];
+    const int len = S.l_snap[l];
     const int nslab = cdiv_s(len, C);
     int wbase = -(1 << 30), wslab = 0;
     for (int base = 0; base < len; base += 64) {

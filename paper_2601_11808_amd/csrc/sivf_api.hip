@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <new>
+#include <unordered_map>
 #include <vector>
 
 #include "sivf.h"
@@ -30,7 +31,7 @@ struct Layout {
     size_t total;
     size_t cent, cn2, cnorm, cmax, data, sids, sowner, sord, free_slabs, free_pages, pages, dir, len, att, mark,
         ctl, lists, b_assign, b_rank, b_rec, b_seg, dt, probes, pair_rank, list_pairs, item_list, item_tile,
-        partials, hdata, xnorm, rr_dist, rr_lab;
+        partials, hdata, xnorm, rr_dist, rr_lab, dt_s;
 };
 
 bool config_ok(const sivf_config *c) {
@@ -88,12 +89,13 @@ Layout make_layout(const sivf_config *c) {
     L.att = take((size_t)c->id_capacity * 4);
     L.mark = take((size_t)c->id_capacity * 4);
     L.ctl = take(CTL_WORDS * 4);
-    L.lists = take((size_t)12 * nl * 4);
+    L.lists = take((size_t)13 * nl * 4);
     L.b_assign = take((size_t)c->max_batch * 4);
     L.b_rank = take((size_t)c->max_batch * 4);
     L.b_rec = take((size_t)c->max_batch * 4);
     L.b_seg = take((size_t)c->max_batch * 4);
-    L.dt = take((size_t)L.coarse_rows * nl * 4);
+    L.dt = take((size_t)L.coarse_rows * nl * 4);     // coarse scratch of inserts
+    L.dt_s = take((size_t)L.coarse_rows * nl * 4);   // coarse scratch of searches (they may overlap inserts)
     L.probes = take((size_t)npairs * 4);
     L.pair_rank = take((size_t)npairs * 4);
     L.list_pairs = take((size_t)npairs * 4);
@@ -127,7 +129,8 @@ struct sivf_index {
     Dev S{};
     Batch B{};
     SearchBufs W{};
-    float *dt = nullptr;
+    float *dt = nullptr;     // coarse scratch: inserts
+    float *dt_s = nullptr;   // coarse scratch: searches
     char *ws = nullptr;
     hipStream_t last = nullptr;
     bool broken = false;
@@ -185,21 +188,22 @@ void prof_end(sivf_index *ix, int kind, int slot, hipStream_t st) {
 }
 
 // Coarse selection over rows [0, n) in chunks that fit the scratch.
-void coarse(sivf_index *ix, hipStream_t st, const float *x, int64_t n, int m, const int32_t *m_per_row, int mmax,
-            int32_t *out, int out_stride, int gated) {
+void coarse(sivf_index *ix, hipStream_t st, float *dt, const float *x, int64_t n, int m, const int32_t *m_per_row,
+            int mmax, int32_t *out, int out_stride, int gated) {
     const Dev &S = ix->S;
     const int dpad = S.dp4 * 4;
     for (int64_t r0 = 0; r0 < n; r0 += ix->L.coarse_rows) {
         const int nr = (int)((n - r0) < ix->L.coarse_rows ? (n - r0) : ix->L.coarse_rows);
         const float *xr = x + r0 * S.d;
-        launch_coarse_gemm(st, xr, nr, S.d, S.cent, dpad, S.cn2, S.nlist, S.metric, ix->dt, S.ctl, gated);
-        launch_coarse_select(st, ix->dt, xr, nr, S.d, S.cent, dpad, S.cnorm, S.cmax, S.nlist, S.metric, m,
+        launch_coarse_gemm(st, xr, nr, S.d, S.cent, dpad, S.cn2, S.nlist, S.metric, dt, S.ctl, gated);
+        launch_coarse_select(st, dt, xr, nr, S.d, S.cent, dpad, S.cnorm, S.cmax, S.nlist, S.metric, m,
                              m_per_row ? m_per_row + r0 : nullptr, mmax, out + r0 * out_stride, out_stride,
                              S.ctl, gated);
     }
 }
 
-sivf_status do_add(sivf_index *ix, int64_t n, const float *x, const int64_t *ids, hipStream_t st) {
+sivf_status do_add(sivf_index *ix, int64_t n, const float *x, const int64_t *ids, hipStream_t st,
+                   bool fresh_only = false) {
     if (n < 0 || n > ix->cfg.max_batch) return SIVF_ERR_ARG;
     if (n > 0 && (!x || !ids)) return SIVF_ERR_ARG;
     if (n == 0) return SIVF_OK;
@@ -207,10 +211,10 @@ sivf_status do_add(sivf_index *ix, int64_t n, const float *x, const int64_t *ids
     const int nn = (int)n;
     const int ps = prof_begin(ix, SIVF_PROF_ADD, st);
     launch_add_prepare(st, S, nn, ids);
-    coarse(ix, st, x, n, 1, nullptr, 1, ix->B.assign, 1, 1);
-    launch_add_count(st, S, nn, ids, ix->B);
+    coarse(ix, st, ix->dt, x, n, 1, nullptr, 1, ix->B.assign, 1, 1);
+    launch_add_count(st, S, nn, ids, ix->B, fresh_only ? 1 : 0);
     launch_add_admit(st, S);
-    launch_remove(st, S, nn, ids, nullptr, ix->B, 1);
+    if (!fresh_only) launch_remove(st, S, nn, ids, nullptr, ix->B, 1);   // delete half of an upsert
     launch_add_alloc(st, S);
     launch_add_scatter(st, S, nn, x, ids, ix->B);
     launch_add_cleanup(st, S, nn, ids);
@@ -234,7 +238,8 @@ sivf_status do_remove(sivf_index *ix, int64_t n, const int64_t *ids, int64_t *n_
 }
 
 sivf_status do_search(sivf_index *ix, int64_t nq, const float *q, int32_t k, const int32_t *kpq, int32_t nprobe,
-                      const int32_t *npq, float *dist, int64_t *labels, hipStream_t st) {
+                      const int32_t *npq, float *dist, int64_t *labels, hipStream_t st,
+                      hipEvent_t snapshot_taken = nullptr) {
     const sivf_config &c = ix->cfg;
     if (nq < 0 || nq > c.max_queries) return SIVF_ERR_ARG;
     if (k < 1 || k > c.max_k) return SIVF_ERR_ARG;
@@ -245,9 +250,10 @@ sivf_status do_search(sivf_index *ix, int64_t nq, const float *q, int32_t k, con
     const int stride = mmax < c.nlist ? mmax : c.nlist;
     const int ps = prof_begin(ix, SIVF_PROF_SEARCH, st);
     const int pc = prof_begin(ix, SIVF_PROF_COARSE, st);
-    coarse(ix, st, q, nq, npq ? 0 : stride, npq, stride, ix->W.probes, stride, 0);
+    coarse(ix, st, ix->dt_s, q, nq, npq ? 0 : stride, npq, stride, ix->W.probes, stride, 0);
     prof_end(ix, SIVF_PROF_COARSE, pc, st);
-    launch_search_plan(st, ix->S, ix->W, (int)nq, stride);
+    launch_search_plan(st, ix->S, ix->W, (int)nq, stride);   // records the list lengths it will scan
+    if (snapshot_taken && !dev_ok(hipEventRecord(snapshot_taken, st))) return SIVF_ERR_DEVICE;
     const int pk = prof_begin(ix, SIVF_PROF_SCAN, st);
     if (c.storage == SIVF_F32)
         launch_search_scan(st, ix->S, ix->W, (int)nq, q, stride, ix->L.kcap, k, kpq);
@@ -325,13 +331,14 @@ sivf_status sivf_create(const sivf_config *cfg, const float *centroids, void *wo
     S.ctl = (int32_t *)(w + L.ctl);
     int32_t *lists = (int32_t *)(w + L.lists);
     int32_t **lp[] = {&S.l_acnt, &S.l_prem, &S.l_base, &S.l_m, &S.l_off, &S.l_newlen,
-                      &S.l_q, &S.l_s, &S.l_h, &S.l_qc, &S.l_qcs, &S.l_qoff};
-    for (int i = 0; i < 12; i++) *lp[i] = lists + (size_t)i * cfg->nlist;
+                      &S.l_q, &S.l_s, &S.l_h, &S.l_qc, &S.l_qcs, &S.l_qoff, &S.l_snap};
+    for (int i = 0; i < 13; i++) *lp[i] = lists + (size_t)i * cfg->nlist;
     ix->B.assign = (int32_t *)(w + L.b_assign);
     ix->B.rank = (int32_t *)(w + L.b_rank);
     ix->B.rec = (uint32_t *)(w + L.b_rec);
     ix->B.seg = (int32_t *)(w + L.b_seg);
     ix->dt = (float *)(w + L.dt);
+    ix->dt_s = (float *)(w + L.dt_s);
     ix->W.probes = (int32_t *)(w + L.probes);
     ix->W.pair_rank = (int32_t *)(w + L.pair_rank);
     ix->W.list_pairs = (int32_t *)(w + L.list_pairs);
@@ -493,7 +500,7 @@ sivf_status sivf_assign(sivf_index *ix, int64_t n, const float *x, int32_t *list
     if (n > cap) return SIVF_ERR_ARG;
     ix->last = as_stream(stream);
     if (n == 0) return SIVF_OK;
-    coarse(ix, as_stream(stream), x, n, 1, nullptr, 1, lists, 1, 0);
+    coarse(ix, as_stream(stream), ix->dt, x, n, 1, nullptr, 1, lists, 1, 0);
     return launched(ix);
 }
 
@@ -506,7 +513,7 @@ sivf_status sivf_probe(sivf_index *ix, int64_t nq, const float *q, int32_t nprob
     ix->last = as_stream(stream);
     if (nq == 0) return SIVF_OK;
     const int m = nprobe < ix->cfg.nlist ? nprobe : ix->cfg.nlist;
-    coarse(ix, as_stream(stream), q, nq, m, nullptr, nprobe, probes, nprobe, 0);
+    coarse(ix, as_stream(stream), ix->dt_s, q, nq, m, nullptr, nprobe, probes, nprobe, 0);
     return launched(ix);
 }
 
@@ -633,6 +640,179 @@ sivf_status sivf_dump(sivf_index *ix, int32_t *list_len, int32_t *list_slabs, in
     return SIVF_OK;
 }
 
+// ------------------------------------------------------------------ server
+
+struct ServerReq {
+    hipEvent_t done;
+    int64_t reserve;     // slabs reserved by an insert until it completes
+    bool mutation;
+};
+
+struct sivf_server {
+    sivf_index *ix = nullptr;
+    hipStream_t s_search = nullptr, s_mut = nullptr;
+    hipEvent_t last_mut = nullptr, last_snap = nullptr, last_search = nullptr;
+    bool any_mut = false, any_search = false;
+    std::vector<hipEvent_t> pool;
+    std::unordered_map<int64_t, ServerReq> inflight;
+    int32_t *mirror = nullptr;     // pinned: free-slab count copied after each mutation
+    int64_t free_view = 0, reserved = 0, next_ticket = 1;
+    bool failed = false;
+};
+
+static hipEvent_t server_event(sivf_server *s) {
+    if (!s->pool.empty()) {
+        hipEvent_t e = s->pool.back();
+        s->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (!dev_ok(hipEventCreateWithFlags(&e, hipEventDisableTiming))) return nullptr;
+    return e;
+}
+
+// Retire completed requests: recycle events, release reservations, refresh
+// the host view of free slabs from the last completed copy.
+static void server_reap(sivf_server *s) {
+    bool mut_done = false;
+    for (auto it = s->inflight.begin(); it != s->inflight.end();) {
+        if (hipEventQuery(it->second.done) == hipSuccess) {
+            s->reserved -= it->second.reserve;
+            mut_done |= it->second.mutation;
+            s->pool.push_back(it->second.done);
+            it = s->inflight.erase(it);
+        } else {
+            ++it;
+        }
+    }
+    if (mut_done) s->free_view = *(volatile int32_t *)s->mirror;
+}
+
+static sivf_status server_finish(sivf_server *s, hipStream_t st, bool mutation, int64_t reserve, int64_t *ticket) {
+    if (mutation) {
+        if (!dev_ok(hipMemcpyAsync(s->mirror, s->ix->S.ctl + CTL_SLAB_TOP, sizeof(int32_t), hipMemcpyDeviceToHost,
+                                   st)))
+            return SIVF_ERR_DEVICE;
+    }
+    hipEvent_t e = server_event(s);
+    if (!e || !dev_ok(hipEventRecord(e, st))) return SIVF_ERR_DEVICE;
+    if (mutation) {
+        if (!dev_ok(hipEventRecord(s->last_mut, st))) return SIVF_ERR_DEVICE;
+        s->any_mut = true;
+    }
+    const int64_t t = s->next_ticket++;
+    s->inflight[t] = ServerReq{e, reserve, mutation};
+    s->reserved += reserve;
+    if (ticket) *ticket = t;
+    return SIVF_OK;
+}
+
+sivf_status sivf_server_create(sivf_index *ix, sivf_server **out) {
+    if (!ix || !out) return SIVF_ERR_ARG;
+    *out = nullptr;
+    if (ix->broken) return SIVF_ERR_STATE;
+    if (!dev_ok(hipStreamSynchronize(ix->last))) return SIVF_ERR_DEVICE;
+    sivf_server *s = new (std::nothrow) sivf_server();
+    if (!s) return SIVF_ERR_STATE;
+    s->ix = ix;
+    bool ok = dev_ok(hipStreamCreateWithFlags(&s->s_search, hipStreamNonBlocking)) &&
+              dev_ok(hipStreamCreateWithFlags(&s->s_mut, hipStreamNonBlocking)) &&
+              dev_ok(hipEventCreateWithFlags(&s->last_mut, hipEventDisableTiming)) &&
+              dev_ok(hipEventCreateWithFlags(&s->last_snap, hipEventDisableTiming)) &&
+              dev_ok(hipEventCreateWithFlags(&s->last_search, hipEventDisableTiming)) &&
+              dev_ok(hipHostMalloc((void **)&s->mirror, sizeof(int32_t), hipHostMallocDefault));
+    if (ok) {
+        ok = dev_ok(hipMemcpy(s->mirror, ix->S.ctl + CTL_SLAB_TOP, sizeof(int32_t), hipMemcpyDeviceToHost));
+        s->free_view = *s->mirror;
+    }
+    if (!ok) {
+        sivf_server_destroy(s);
+        return SIVF_ERR_DEVICE;
+    }
+    *out = s;
+    return SIVF_OK;
+}
+
+sivf_status sivf_server_destroy(sivf_server *s) {
+    if (!s) return SIVF_ERR_ARG;
+    if (s->s_search) (void)hipStreamSynchronize(s->s_search);
+    if (s->s_mut) (void)hipStreamSynchronize(s->s_mut);
+    for (auto &kv : s->inflight) (void)hipEventDestroy(kv.second.done);
+    for (hipEvent_t e : s->pool) (void)hipEventDestroy(e);
+    for (hipEvent_t e : {s->last_mut, s->last_snap, s->last_search})
+        if (e) (void)hipEventDestroy(e);
+    if (s->s_search) (void)hipStreamDestroy(s->s_search);
+    if (s->s_mut) (void)hipStreamDestroy(s->s_mut);
+    if (s->mirror) (void)hipHostFree(s->mirror);
+    delete s;
+    return SIVF_OK;
+}
+
+sivf_status sivf_server_add(sivf_server *s, int64_t n, const float *x, const int64_t *ids, int64_t *ticket) {
+    if (!s) return SIVF_ERR_ARG;
+    sivf_index *ix = s->ix;
+    if (ix->broken) return SIVF_ERR_STATE;
+    if (n < 0 || n > ix->cfg.max_batch || (n > 0 && (!x || !ids))) return SIVF_ERR_ARG;
+    server_reap(s);
+    const int64_t C = ix->cfg.slab_capacity;
+    const int64_t need = (n + C - 1) / C + (n < ix->cfg.nlist ? n : ix->cfg.nlist);
+    if (need > s->free_view - s->reserved) return SIVF_ERR_NOSPACE;
+    if (s->any_search && !dev_ok(hipStreamWaitEvent(s->s_mut, s->last_snap, 0))) return SIVF_ERR_DEVICE;
+    sivf_status st = do_add(ix, n, x, ids, s->s_mut, true);
+    if (st != SIVF_OK) return st;
+    return server_finish(s, s->s_mut, true, need, ticket);
+}
+
+sivf_status sivf_server_remove(sivf_server *s, int64_t n, const int64_t *ids, int64_t *n_removed,
+                               int64_t *ticket) {
+    if (!s) return SIVF_ERR_ARG;
+    sivf_index *ix = s->ix;
+    if (ix->broken) return SIVF_ERR_STATE;
+    if (n < 0 || n > ix->cfg.max_batch || (n > 0 && !ids)) return SIVF_ERR_ARG;
+    server_reap(s);
+    if (s->any_search && !dev_ok(hipStreamWaitEvent(s->s_mut, s->last_search, 0))) return SIVF_ERR_DEVICE;
+    sivf_status st = do_remove(ix, n, ids, n_removed, s->s_mut);
+    if (st != SIVF_OK) return st;
+    return server_finish(s, s->s_mut, true, 0, ticket);
+}
+
+sivf_status sivf_server_search(sivf_server *s, int64_t nq, const float *q, int32_t k, int32_t nprobe,
+                               float *dist, int64_t *labels, int64_t *ticket) {
+    if (!s) return SIVF_ERR_ARG;
+    sivf_index *ix = s->ix;
+    if (ix->broken) return SIVF_ERR_STATE;
+    server_reap(s);
+    if (s->any_mut && !dev_ok(hipStreamWaitEvent(s->s_search, s->last_mut, 0))) return SIVF_ERR_DEVICE;
+    sivf_status st = do_search(ix, nq, q, k, nullptr, nprobe, nullptr, dist, labels, s->s_search, s->last_snap);
+    if (st != SIVF_OK) return st;
+    if (!dev_ok(hipEventRecord(s->last_search, s->s_search))) return SIVF_ERR_DEVICE;
+    s->any_search = true;
+    return server_finish(s, s->s_search, false, 0, ticket);
+}
+
+sivf_status sivf_server_poll(sivf_server *s, int64_t ticket, int *done) {
+    if (!s || !done) return SIVF_ERR_ARG;
+    server_reap(s);
+    *done = (ticket > 0 && ticket < s->next_ticket && s->inflight.find(ticket) == s->inflight.end()) ? 1 : 0;
+    return SIVF_OK;
+}
+
+sivf_status sivf_server_wait(sivf_server *s, int64_t ticket) {
+    if (!s) return SIVF_ERR_ARG;
+    auto it = s->inflight.find(ticket);
+    if (it != s->inflight.end() && !dev_ok(hipEventSynchronize(it->second.done))) return SIVF_ERR_DEVICE;
+    server_reap(s);
+    return SIVF_OK;
+}
+
+sivf_status sivf_server_free_slabs(sivf_server *s, int64_t *free_slabs, int64_t *reserved) {
+    if (!s) return SIVF_ERR_ARG;
+    server_reap(s);
+    if (free_slabs) *free_slabs = s->free_view;
+    if (reserved) *reserved = s->reserved;
+    return SIVF_OK;
+}
+
 const char *sivf_status_string(sivf_status s) {
     switch (s) {
         case SIVF_OK: return "ok";
@@ -641,6 +821,7 @@ const char *sivf_status_string(sivf_status s) {
         case SIVF_ERR_ID_RANGE: return "id outside [0, id_capacity)";
         case SIVF_ERR_DEVICE: return "HIP runtime error";
         case SIVF_ERR_STATE: return "index state unusable";
+        case SIVF_ERR_LIVE_ID: return "a server insert named a live id";
     }
     return "unknown status";
 }

@@ -59,6 +59,7 @@ struct Dev {
     int32_t *l_acnt, *l_prem, *l_base;               // add
     int32_t *l_m, *l_off, *l_newlen, *l_q, *l_s, *l_h; // remove
     int32_t *l_qc, *l_qcs, *l_qoff;                  // search
+    int32_t *l_snap;   // search: list lengths when the search was planned (it scans only these)
 };
 
 __device__ __forceinline__ int slab_of(const Dev &S, int l, int ord) {

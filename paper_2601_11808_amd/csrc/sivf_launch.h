@@ -27,7 +27,7 @@ struct Batch {
     uint32_t *rec;
 };
 void launch_add_prepare(hipStream_t st, const Dev &S, int n, const int64_t *ids);
-void launch_add_count(hipStream_t st, const Dev &S, int n, const int64_t *ids, const Batch &B);
+void launch_add_count(hipStream_t st, const Dev &S, int n, const int64_t *ids, const Batch &B, int fresh_only);
 void launch_add_admit(hipStream_t st, const Dev &S);
 void launch_add_alloc(hipStream_t st, const Dev &S);
 void launch_add_scatter(hipStream_t st, const Dev &S, int n, const float *x, const int64_t *ids,
