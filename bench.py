@@ -15,6 +15,10 @@ HIP-graph steps), recall@10 and an nprobe sweep against exact kNN, the
 roofline of the scan kernel, and the CPU oracle's rate on a bounded sample.
 
 Other modes (not the headline line):
+  --workload serve     the serving form: a 50M-vector fp16 window (d=128,
+                       16,384 lists, slab 128) under a Poisson stream of
+                       searches, inserts and deletes through the
+                       overlapping request server; p50/p99 per request type
   --storage bf16|f16   the precision form on the same window data
   --workload precision 10M unit vectors, d=96, inner product, bf16 slabs,
                        4,096 lists, slab 128, 16k queries, nprobe 64,
@@ -44,7 +48,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="window", choices=["window", "tiny", "precision"])
+    ap.add_argument("--workload", default="window", choices=["window", "tiny", "precision", "serve"])
+    ap.add_argument("--serve-seconds", type=float, default=5.0, help="serve: length of the arrival stream")
+    ap.add_argument("--serve-rate", type=float, default=2000.0, help="serve: Poisson arrival rate (req/s)")
+    ap.add_argument("--serve-n", type=int, default=50_000_000, help="serve: steady-state window size")
     ap.add_argument("--storage", default=None, choices=list(STORAGE))
     ap.add_argument("--rerank", type=int, default=4, help="re-rank factor R for bf16/f16 storage")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -131,6 +138,8 @@ def main():
         print("bench.py runs on one GPU only: every GPU box here has a single MI355X, so --gpus must be 1 "
               "(multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
         sys.exit(2)
+    if a.workload == "serve":
+        return serve_main(a)
     import torch
     import paper_2601_11808_amd as sivf
     import workloads
@@ -331,6 +340,176 @@ def main():
         res["cpu_baseline"] = cpu_baseline(w, x, ids, q, (xb, idb, w.oldest_ids(1)), nprobe, k,
                                            n_sample_q=200 if a.workload == "window" else nq)
         log(f"[bench] cpu baseline in {time.time() - t0:.1f} s")
+    print(json.dumps(res), flush=True)
+
+
+def serve_main(a):
+    """Serving form: the steady-state window under an open-loop Poisson
+    request stream, every request submitted through the overlapping server
+    at its arrival time.  Latency = completion seen by the host - arrival."""
+    import torch
+    import paper_2601_11808_amd as sivf
+    import workloads
+
+    if not os.path.exists(sivf.LIB_PATH):
+        raise SystemExit("libsivf.so is not built: run python -c 'import __graft_entry__ as g; g.build()'")
+    dev = torch.device("cuda:0")
+    w = workloads.serving(n_base=a.serve_n)
+    N, C, k = w.n_base, w.slab, w.k
+    t0 = time.time()
+    reqs = workloads.serving_requests(a.serve_seconds, rate=a.serve_rate)
+    dels, live_end = workloads.serving_delete_ids(reqs, N)
+    n_ins = sum(r.n for r in reqs if r.kind == "insert")
+    id_cap = N + n_ins
+    log(f"[serve] {len(reqs)} requests over {a.serve_seconds} s at {a.serve_rate} req/s "
+        f"(+{n_ins} / -{sum(v.shape[0] for v in dels.values())} vectors) prepared in {time.time() - t0:.1f} s")
+    num_slabs = int(1.3 * max(N, int(np.count_nonzero(live_end))) / C) + 2 * w.nlist
+    ix = sivf.Index(w.dim, w.nlist, w.centroids, metric=w.metric, slab_capacity=C, num_slabs=num_slabs,
+                    id_capacity=id_cap, max_batch=100_000, max_queries=4096, max_k=16, max_nprobe=64,
+                    storage=STORAGE["f16"], rerank_factor=4, device="cuda:0")
+    log(f"[serve] workspace {ix.workspace_bytes / 2**30:.1f} GiB, {num_slabs} slabs")
+    means = torch.from_numpy(w.means).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    chunk = 100_000
+    for c, s0 in enumerate(range(0, N, chunk)):
+        n = min(chunk, N - s0)
+        xb = workloads.device_sample(w, n, 1000 + c, dev, means)
+        ix.add(xb, torch.arange(s0, s0 + n, device=dev))
+        if c % 50 == 49:
+            assert ix.sync() == 0
+            log(f"[serve] loaded {s0 + n} vectors")
+    assert ix.sync() == 0
+    load_s = time.perf_counter() - t0
+    log(f"[serve] bulk load {N} vectors in {load_s:.1f} s ({N / load_s / 1e6:.2f} M vec/s)")
+    # payloads resident before the stream starts
+    pool = workloads.device_sample(w, 2_000_000, 1, dev, means)
+    qpool = workloads.device_sample(w, 65536, 2, dev, means)
+    ins_ids = torch.arange(N, id_cap, device=dev)
+    del_all = torch.from_numpy(np.concatenate([dels[i] for i in sorted(dels)]) if dels else
+                               np.zeros(0, np.int64)).to(dev)
+    rng = np.random.default_rng([w.seed, 6, 0])
+    plan, ioff, doff = [], 0, 0
+    for i, r in enumerate(reqs):
+        if r.kind == "insert":
+            o = int(rng.integers(0, pool.shape[0] - r.n + 1))
+            plan.append((pool[o:o + r.n], ins_ids[ioff:ioff + r.n]))
+            ioff += r.n
+        elif r.kind == "delete":
+            m = dels[i].shape[0]
+            plan.append((del_all[doff:doff + m],))
+            doff += m
+        else:
+            o = int(rng.integers(0, qpool.shape[0] - r.n + 1))
+            plan.append((qpool[o:o + r.n],))
+    torch.cuda.synchronize()
+
+    srv = sivf.Server(ix)
+    queues = {"search": [], "mut": []}      # (request index, ticket) in submission order
+    heads = {"search": 0, "mut": 0}
+    done_t = np.zeros(len(reqs))
+    sub_t = np.zeros(len(reqs))
+    refused, refused_at = 0, -1
+    i = 0
+    start = time.perf_counter() + 0.05
+    while True:
+        now = time.perf_counter() - start
+        if i < len(reqs) and reqs[i].t <= now:
+            r, pl = reqs[i], plan[i]
+            if r.kind == "insert":
+                t = srv.add(pl[0], pl[1])
+                if t is None:           # not admitted yet: retry once something completes
+                    if refused_at != i:
+                        refused += 1
+                        refused_at = i
+                else:
+                    queues["mut"].append((i, t))
+            elif r.kind == "delete":
+                t, _ = srv.remove(pl[0])
+                queues["mut"].append((i, t))
+            else:
+                t, _, _ = srv.search(pl[0], k, r.nprobe)
+                queues["search"].append((i, t))
+            if t is not None:
+                sub_t[i] = time.perf_counter() - start
+                i += 1
+                continue
+        for kq in ("search", "mut"):
+            qq = queues[kq]
+            while heads[kq] < len(qq) and srv.poll(qq[heads[kq]][1]):
+                done_t[qq[heads[kq]][0]] = time.perf_counter() - start
+                heads[kq] += 1
+        if i == len(reqs) and all(heads[kq] == len(queues[kq]) for kq in queues):
+            break
+    end = time.perf_counter() - start
+    srv.close()
+    assert ix.sync() == 0
+    st = ix.stats()
+    log(f"[serve] stream done in {end:.2f} s; live {st['live']} (expected {int(np.count_nonzero(live_end))})")
+    assert st["live"] == int(np.count_nonzero(live_end))
+    assert st["used_slabs"] + st["free_slabs"] == num_slabs
+
+    arr = np.array([r.t for r in reqs])
+    lat = (done_t - arr) * 1e3
+    per = {}
+    for kind in ("search", "insert", "delete"):
+        sel = np.array([r.kind == kind for r in reqs])
+        if sel.any():
+            v = np.sort(lat[sel])
+            per[kind] = {"count": int(sel.sum()), "p50_ms": round(float(np.percentile(v, 50)), 3),
+                         "p99_ms": round(float(np.percentile(v, 99)), 3), "max_ms": round(float(v[-1]), 3),
+                         "mean_size": round(float(np.mean([r.n for r in reqs if r.kind == kind])), 1)}
+    last_arrival = float(arr[-1]) if len(reqs) else 0.0
+    # recall@10 on the final window for 256 pooled queries: exact top-10
+    # (fp32 candidate scoring over every live row, fp64 re-scoring of the best 32)
+    nrq = 256
+    qh = qpool[:nrq]
+    live_ids = np.flatnonzero(live_end).astype(np.int64)
+    q2 = (qh * qh).sum(1, keepdim=True)
+    best_s = torch.full((nrq, 32), float("inf"), device=dev)
+    best_i = torch.full((nrq, 32), -1, dtype=torch.int64, device=dev)
+    for s0 in range(0, live_ids.shape[0], 1 << 21):
+        idc = torch.from_numpy(live_ids[s0:s0 + (1 << 21)]).to(dev)
+        rows = ix.get_rows(idc)
+        sc = q2 + (rows * rows).sum(1)[None, :] - 2.0 * (qh @ rows.T)
+        s_c, o_c = torch.topk(sc, min(32, sc.shape[1]), dim=1, largest=False)
+        cs = torch.cat([best_s, s_c], 1)
+        ci = torch.cat([best_i, idc[o_c]], 1)
+        best_s, o = torch.topk(cs, 32, dim=1, largest=False)
+        best_i = torch.gather(ci, 1, o)
+        del rows, sc
+    cand = best_i.cpu().numpy()
+    rows = ix.get_rows(torch.from_numpy(cand.reshape(-1)).to(dev)).cpu().numpy().astype(np.float64)
+    qd = qh.cpu().numpy().astype(np.float64)
+    d64 = ((rows.reshape(nrq, 32, -1) - qd[:, None, :]) ** 2).sum(2)
+    gt = [cand[j][np.lexsort((cand[j], d64[j]))[:k]] for j in range(nrq)]
+    recall = {}
+    for npb in (16, 32, 64):
+        _, lab = ix.search(qh, k, npb)
+        lab = lab.cpu().numpy()
+        recall[str(npb)] = round(float(np.mean([len(set(gt[j]) & set(lab[j])) / k for j in range(nrq)])), 4)
+    log(f"[serve] recall@10 on the final window: {recall}")
+    nq_tot = sum(r.n for r in reqs if r.kind == "search")
+    n_del = int(sum(v.shape[0] for v in dels.values()))
+    res = {
+        "metric": "serving: completed requests/s with p50/p99 latency per request type",
+        "value": round(len(reqs) / end, 1), "unit": "requests/s",
+        "n_gpus": 1, "steps": len(reqs), "warmup": 0, "ms_per_step": round(end / max(len(reqs), 1) * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f16 scan + f32 re-rank", "data": "synthetic",
+        "config": {"workload": f"serving: steady window N={N}, d={w.dim}, nlist={w.nlist}, slab={C}, fp16 storage, "
+                               f"Poisson {a.serve_rate} req/s for {a.serve_seconds} s, mix search 1/2 "
+                               f"(1-4096 queries, nprobe 16-64, k=10), insert 1/3 (1k-50k), delete 1/6 (1k-100k)",
+                   "parallelism": "single GPU"},
+        "offered_req_per_s": round(len(reqs) / max(last_arrival, 1e-9), 1),
+        "drain_s_after_last_arrival": round(end - last_arrival, 3),
+        "latency": per,
+        "insert_vec_per_s": round(n_ins / end, 1), "delete_ids_per_s": round(n_del / end, 1),
+        "search_queries_per_s": round(nq_tot / end, 1),
+        "inserts_refused_then_retried": refused,
+        "recall_at_10_final_window": recall,
+        "bulk_load_vec_per_s": round(N / load_s, 1),
+    }
     print(json.dumps(res), flush=True)
 
 

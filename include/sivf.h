@@ -263,16 +263,20 @@ sivf_status sivf_profile_read(sivf_index *ix, double *total_ms, int64_t *count);
  * slabs.  The free-slab count is copied back after every mutation without
  * blocking.  Every submit returns a ticket; sivf_server_poll (non-blocking)
  * and sivf_server_wait (blocking) observe its completion.  Buffers stay owned
- * by the caller until the ticket completes.  One host thread per server; do
- * not use the index directly while a server is in use. */
+ * by the caller until the ticket completes; outputs are valid once it has.
+ * input_stream (a hipStream_t, NULL = the legacy default stream) is the
+ * stream whose work so far produces the request's device inputs: the request
+ * starts after it.  One host thread per server; do not use the index
+ * directly while a server is in use. */
 typedef struct sivf_server sivf_server;
 sivf_status sivf_server_create(sivf_index *ix, sivf_server **out);
 sivf_status sivf_server_destroy(sivf_server *s);   /* waits for every request */
-sivf_status sivf_server_add(sivf_server *s, int64_t n, const float *x, const int64_t *ids, int64_t *ticket);
+sivf_status sivf_server_add(sivf_server *s, int64_t n, const float *x, const int64_t *ids, void *input_stream,
+                            int64_t *ticket);
 sivf_status sivf_server_remove(sivf_server *s, int64_t n, const int64_t *ids, int64_t *n_removed,
-                               int64_t *ticket);
+                               void *input_stream, int64_t *ticket);
 sivf_status sivf_server_search(sivf_server *s, int64_t nq, const float *q, int32_t k, int32_t nprobe,
-                               float *dist, int64_t *labels, int64_t *ticket);
+                               float *dist, int64_t *labels, void *input_stream, int64_t *ticket);
 sivf_status sivf_server_poll(sivf_server *s, int64_t ticket, int *done);
 sivf_status sivf_server_wait(sivf_server *s, int64_t ticket);
 /* Host view of free slabs and the slabs reserved by inserts in flight. */

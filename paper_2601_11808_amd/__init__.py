@@ -73,9 +73,9 @@ SIGNATURES = [
     ("sivf_profile_read", ct.c_int, [_P, _P, _P]),
     ("sivf_server_create", ct.c_int, [_P, ct.POINTER(_P)]),
     ("sivf_server_destroy", ct.c_int, [_P]),
-    ("sivf_server_add", ct.c_int, [_P, _I64, _P, _P, ct.POINTER(_I64)]),
-    ("sivf_server_remove", ct.c_int, [_P, _I64, _P, _P, ct.POINTER(_I64)]),
-    ("sivf_server_search", ct.c_int, [_P, _I64, _P, _I32, _I32, _P, _P, ct.POINTER(_I64)]),
+    ("sivf_server_add", ct.c_int, [_P, _I64, _P, _P, _P, ct.POINTER(_I64)]),
+    ("sivf_server_remove", ct.c_int, [_P, _I64, _P, _P, _P, ct.POINTER(_I64)]),
+    ("sivf_server_search", ct.c_int, [_P, _I64, _P, _I32, _I32, _P, _P, _P, ct.POINTER(_I64)]),
     ("sivf_server_poll", ct.c_int, [_P, _I64, ct.POINTER(ct.c_int)]),
     ("sivf_server_wait", ct.c_int, [_P, _I64]),
     ("sivf_server_free_slabs", ct.c_int, [_P, ct.POINTER(_I64), ct.POINTER(_I64)]),
@@ -395,6 +395,10 @@ class Server:
         self._h = h
         self._keep = {}
 
+    def _in_stream(self):
+        # inputs are produced (copied, generated) on torch's current stream
+        return ct.c_void_p(_torch().cuda.current_stream(self.index.device).cuda_stream)
+
     def close(self):
         if getattr(self, "_h", None):
             lib().sivf_server_destroy(self._h)
@@ -412,7 +416,7 @@ class Server:
         x = _dev_tensor(x, torch.float32, self.index.device).reshape(-1, self.index.dim)
         ids = _dev_tensor(ids, torch.int64, self.index.device).reshape(-1)
         t = ct.c_int64(0)
-        st = lib().sivf_server_add(self._h, x.shape[0], _ptr(x), _ptr(ids), ct.byref(t))
+        st = lib().sivf_server_add(self._h, x.shape[0], _ptr(x), _ptr(ids), self._in_stream(), ct.byref(t))
         if st == ERR_NOSPACE:
             return None
         _check(st, "sivf_server_add")
@@ -425,7 +429,8 @@ class Server:
         ids = _dev_tensor(ids, torch.int64, self.index.device).reshape(-1)
         nrem = torch.zeros(1, dtype=torch.int64, device=self.index.device)
         t = ct.c_int64(0)
-        _check(lib().sivf_server_remove(self._h, ids.shape[0], _ptr(ids), _ptr(nrem), ct.byref(t)),
+        _check(lib().sivf_server_remove(self._h, ids.shape[0], _ptr(ids), _ptr(nrem), self._in_stream(),
+                                        ct.byref(t)),
                "sivf_server_remove")
         self._keep[t.value] = (ids, nrem)
         return t.value, nrem
@@ -441,7 +446,7 @@ class Server:
             dist, lab = out
         t = ct.c_int64(0)
         _check(lib().sivf_server_search(self._h, q.shape[0], _ptr(q), k, nprobe, _ptr(dist), _ptr(lab),
-                                        ct.byref(t)), "sivf_server_search")
+                                        self._in_stream(), ct.byref(t)), "sivf_server_search")
         self._keep[t.value] = (q, dist, lab)
         return t.value, dist, lab
 

@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <new>
+#include <deque>
 #include <unordered_map>
 #include <vector>
 
@@ -643,21 +644,23 @@ sivf_status sivf_dump(sivf_index *ix, int32_t *list_len, int32_t *list_slabs, in
 // ------------------------------------------------------------------ server
 
 struct ServerReq {
+    int64_t ticket;
     hipEvent_t done;
     int64_t reserve;     // slabs reserved by an insert until it completes
-    bool mutation;
 };
 
 struct sivf_server {
     sivf_index *ix = nullptr;
     hipStream_t s_search = nullptr, s_mut = nullptr;
-    hipEvent_t last_mut = nullptr, last_snap = nullptr, last_search = nullptr;
+    hipEvent_t last_mut = nullptr, last_snap = nullptr, last_search = nullptr, inputs = nullptr;
     bool any_mut = false, any_search = false;
     std::vector<hipEvent_t> pool;
-    std::unordered_map<int64_t, ServerReq> inflight;
+    // Requests in flight per stream, in submission order (they complete in
+    // that order, so only the oldest of each queue needs a query).
+    std::deque<ServerReq> q_search, q_mut;
+    std::unordered_map<int64_t, hipEvent_t> inflight;   // ticket -> completion event
     int32_t *mirror = nullptr;     // pinned: free-slab count copied after each mutation
     int64_t free_view = 0, reserved = 0, next_ticket = 1;
-    bool failed = false;
 };
 
 static hipEvent_t server_event(sivf_server *s) {
@@ -675,17 +678,22 @@ static hipEvent_t server_event(sivf_server *s) {
 // the host view of free slabs from the last completed copy.
 static void server_reap(sivf_server *s) {
     bool mut_done = false;
-    for (auto it = s->inflight.begin(); it != s->inflight.end();) {
-        if (hipEventQuery(it->second.done) == hipSuccess) {
-            s->reserved -= it->second.reserve;
-            mut_done |= it->second.mutation;
-            s->pool.push_back(it->second.done);
-            it = s->inflight.erase(it);
-        } else {
-            ++it;
+    for (std::deque<ServerReq> *q : {&s->q_search, &s->q_mut}) {
+        while (!q->empty() && hipEventQuery(q->front().done) == hipSuccess) {
+            const ServerReq &r = q->front();
+            s->reserved -= r.reserve;
+            mut_done |= (q == &s->q_mut);
+            s->pool.push_back(r.done);
+            s->inflight.erase(r.ticket);
+            q->pop_front();
         }
     }
     if (mut_done) s->free_view = *(volatile int32_t *)s->mirror;
+}
+
+// The request's inputs come from work enqueued on input_stream: start after it.
+static bool server_inputs(sivf_server *s, void *input_stream, hipStream_t st) {
+    return dev_ok(hipEventRecord(s->inputs, as_stream(input_stream))) && dev_ok(hipStreamWaitEvent(st, s->inputs, 0));
 }
 
 static sivf_status server_finish(sivf_server *s, hipStream_t st, bool mutation, int64_t reserve, int64_t *ticket) {
@@ -701,7 +709,8 @@ static sivf_status server_finish(sivf_server *s, hipStream_t st, bool mutation, 
         s->any_mut = true;
     }
     const int64_t t = s->next_ticket++;
-    s->inflight[t] = ServerReq{e, reserve, mutation};
+    (mutation ? s->q_mut : s->q_search).push_back(ServerReq{t, e, reserve});
+    s->inflight[t] = e;
     s->reserved += reserve;
     if (ticket) *ticket = t;
     return SIVF_OK;
@@ -720,6 +729,7 @@ sivf_status sivf_server_create(sivf_index *ix, sivf_server **out) {
               dev_ok(hipEventCreateWithFlags(&s->last_mut, hipEventDisableTiming)) &&
               dev_ok(hipEventCreateWithFlags(&s->last_snap, hipEventDisableTiming)) &&
               dev_ok(hipEventCreateWithFlags(&s->last_search, hipEventDisableTiming)) &&
+              dev_ok(hipEventCreateWithFlags(&s->inputs, hipEventDisableTiming)) &&
               dev_ok(hipHostMalloc((void **)&s->mirror, sizeof(int32_t), hipHostMallocDefault));
     if (ok) {
         ok = dev_ok(hipMemcpy(s->mirror, ix->S.ctl + CTL_SLAB_TOP, sizeof(int32_t), hipMemcpyDeviceToHost));
@@ -737,9 +747,9 @@ sivf_status sivf_server_destroy(sivf_server *s) {
     if (!s) return SIVF_ERR_ARG;
     if (s->s_search) (void)hipStreamSynchronize(s->s_search);
     if (s->s_mut) (void)hipStreamSynchronize(s->s_mut);
-    for (auto &kv : s->inflight) (void)hipEventDestroy(kv.second.done);
+    for (auto &kv : s->inflight) (void)hipEventDestroy(kv.second);
     for (hipEvent_t e : s->pool) (void)hipEventDestroy(e);
-    for (hipEvent_t e : {s->last_mut, s->last_snap, s->last_search})
+    for (hipEvent_t e : {s->last_mut, s->last_snap, s->last_search, s->inputs})
         if (e) (void)hipEventDestroy(e);
     if (s->s_search) (void)hipStreamDestroy(s->s_search);
     if (s->s_mut) (void)hipStreamDestroy(s->s_mut);
@@ -748,7 +758,8 @@ sivf_status sivf_server_destroy(sivf_server *s) {
     return SIVF_OK;
 }
 
-sivf_status sivf_server_add(sivf_server *s, int64_t n, const float *x, const int64_t *ids, int64_t *ticket) {
+sivf_status sivf_server_add(sivf_server *s, int64_t n, const float *x, const int64_t *ids, void *input_stream,
+                            int64_t *ticket) {
     if (!s) return SIVF_ERR_ARG;
     sivf_index *ix = s->ix;
     if (ix->broken) return SIVF_ERR_STATE;
@@ -758,31 +769,34 @@ sivf_status sivf_server_add(sivf_server *s, int64_t n, const float *x, const int
     const int64_t need = (n + C - 1) / C + (n < ix->cfg.nlist ? n : ix->cfg.nlist);
     if (need > s->free_view - s->reserved) return SIVF_ERR_NOSPACE;
     if (s->any_search && !dev_ok(hipStreamWaitEvent(s->s_mut, s->last_snap, 0))) return SIVF_ERR_DEVICE;
+    if (!server_inputs(s, input_stream, s->s_mut)) return SIVF_ERR_DEVICE;
     sivf_status st = do_add(ix, n, x, ids, s->s_mut, true);
     if (st != SIVF_OK) return st;
     return server_finish(s, s->s_mut, true, need, ticket);
 }
 
 sivf_status sivf_server_remove(sivf_server *s, int64_t n, const int64_t *ids, int64_t *n_removed,
-                               int64_t *ticket) {
+                               void *input_stream, int64_t *ticket) {
     if (!s) return SIVF_ERR_ARG;
     sivf_index *ix = s->ix;
     if (ix->broken) return SIVF_ERR_STATE;
     if (n < 0 || n > ix->cfg.max_batch || (n > 0 && !ids)) return SIVF_ERR_ARG;
     server_reap(s);
     if (s->any_search && !dev_ok(hipStreamWaitEvent(s->s_mut, s->last_search, 0))) return SIVF_ERR_DEVICE;
+    if (!server_inputs(s, input_stream, s->s_mut)) return SIVF_ERR_DEVICE;
     sivf_status st = do_remove(ix, n, ids, n_removed, s->s_mut);
     if (st != SIVF_OK) return st;
     return server_finish(s, s->s_mut, true, 0, ticket);
 }
 
 sivf_status sivf_server_search(sivf_server *s, int64_t nq, const float *q, int32_t k, int32_t nprobe,
-                               float *dist, int64_t *labels, int64_t *ticket) {
+                               float *dist, int64_t *labels, void *input_stream, int64_t *ticket) {
     if (!s) return SIVF_ERR_ARG;
     sivf_index *ix = s->ix;
     if (ix->broken) return SIVF_ERR_STATE;
     server_reap(s);
     if (s->any_mut && !dev_ok(hipStreamWaitEvent(s->s_search, s->last_mut, 0))) return SIVF_ERR_DEVICE;
+    if (!server_inputs(s, input_stream, s->s_search)) return SIVF_ERR_DEVICE;
     sivf_status st = do_search(ix, nq, q, k, nullptr, nprobe, nullptr, dist, labels, s->s_search, s->last_snap);
     if (st != SIVF_OK) return st;
     if (!dev_ok(hipEventRecord(s->last_search, s->s_search))) return SIVF_ERR_DEVICE;
@@ -800,7 +814,7 @@ sivf_status sivf_server_poll(sivf_server *s, int64_t ticket, int *done) {
 sivf_status sivf_server_wait(sivf_server *s, int64_t ticket) {
     if (!s) return SIVF_ERR_ARG;
     auto it = s->inflight.find(ticket);
-    if (it != s->inflight.end() && !dev_ok(hipEventSynchronize(it->second.done))) return SIVF_ERR_DEVICE;
+    if (it != s->inflight.end() && !dev_ok(hipEventSynchronize(it->second))) return SIVF_ERR_DEVICE;
     server_reap(s);
     return SIVF_OK;
 }

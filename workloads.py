@@ -182,3 +182,114 @@ def random_live_ids(live_ids, n, seed, t):
     """n distinct ids drawn uniformly from the live id array (step t)."""
     rng = np.random.default_rng([seed, 3, t])
     return rng.choice(live_ids, size=n, replace=False).astype(np.int64)
+
+
+def serving(seed=5, n_base=50_000_000):
+    """Serving form inputs: d=128, 16,384 equal-weight clusters (means
+    U[0,255]^128, sigma 48), L2, nlist 16,384 with the means as centroids,
+    slab 128 (fp16 storage).  The base set and the payload pools are drawn on
+    the device (``device_sample``): 50M host-side draws would take minutes."""
+    rng = np.random.default_rng([seed, 0, 0])
+    means = rng.uniform(0.0, 255.0, size=(16384, 128)).astype(np.float32)
+    w = Workload("serving", dim=128, nlist=16384, metric=L2, slab=128, n_base=n_base, batch=0,
+                 n_queries=4096, nprobe=64, k=10, seed=seed, means=means,
+                 weights=np.full(16384, 1.0 / 16384), sigma=48.0, kind="gauss")
+    w.centroids = means.copy()
+    return w
+
+
+def device_sample(w, n, tag, device, means=None):
+    """n rows of the mixture drawn with torch's device generator (Philox),
+    seeded by (w.seed, tag): float32 [n, dim] on ``device``.  Pass ``means``
+    (the mixture means already on the device) to skip the copy."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(w.seed * 1_000_003 + tag)
+    if means is None:
+        means = torch.from_numpy(w.means).to(device)
+    comp = torch.randint(0, w.means.shape[0], (n,), generator=g, device=device)
+    x = torch.randn((n, w.dim), generator=g, device=device, dtype=torch.float32)
+    x.mul_(w.sigma).add_(means[comp])
+    return x
+
+
+@dataclass
+class Request:
+    t: float            # arrival time (s) from the start of the stream
+    kind: str           # "search" | "insert" | "delete"
+    n: int              # queries, vectors or ids
+    nprobe: int = 0
+    oldest: bool = False
+
+
+def serving_requests(duration_s, rate=2000.0, seed=5, mix=(0.5, 1 / 3, 1 / 6), insert_range=(1000, 50_000),
+                     delete_range=(1000, 100_000), search_range=(1, 4096), nprobe_range=(16, 64)):
+    """Poisson arrivals (exponential gaps, mean 1/rate) over duration_s with
+    the serving mix: searches of log-uniform size with nprobe uniform,
+    inserts and deletes of uniform size, deletes half oldest / half random."""
+    rng = np.random.default_rng([seed, 4, 0])
+    n_est = int(duration_s * rate * 1.2) + 64
+    t = np.cumsum(rng.exponential(1.0 / rate, size=n_est))
+    t = t[t < duration_s]
+    kinds = rng.choice(3, size=t.shape[0], p=np.asarray(mix) / np.sum(mix))
+    lo, hi = np.log(search_range[0]), np.log(search_range[1] + 1)
+    sq = np.minimum(np.floor(np.exp(rng.uniform(lo, hi, size=t.shape[0]))), search_range[1]).astype(int)
+    sp = rng.integers(nprobe_range[0], nprobe_range[1] + 1, size=t.shape[0])
+    si = rng.integers(insert_range[0], insert_range[1] + 1, size=t.shape[0])
+    sd = rng.integers(delete_range[0], delete_range[1] + 1, size=t.shape[0])
+    old = rng.random(t.shape[0]) < 0.5
+    out = []
+    for i in range(t.shape[0]):
+        if kinds[i] == 0:
+            out.append(Request(float(t[i]), "search", int(sq[i]), nprobe=int(sp[i])))
+        elif kinds[i] == 1:
+            out.append(Request(float(t[i]), "insert", int(si[i])))
+        else:
+            out.append(Request(float(t[i]), "delete", int(sd[i]), oldest=bool(old[i])))
+    return out
+
+
+def serving_delete_ids(reqs, n_base, seed=5):
+    """Resolve every delete of a request stream to concrete ids, walking the
+    stream in order (inserts take the next fresh ids).  Oldest deletes take
+    the smallest live ids; random deletes draw ids uniformly from the live
+    range (about as many as the request size are live) and keep the first
+    r.n that are live at that point (a repeated draw stays in the request:
+    removing an id twice is a no-op).  Returns {request index:
+    int64 ids} and the number of ids live at the end."""
+    rng = np.random.default_rng([seed, 3, 0])
+    total = n_base + sum(r.n for r in reqs if r.kind == "insert")
+    live = np.zeros(total, dtype=bool)
+    live[:n_base] = True
+    nxt, low, nlive = n_base, 0, n_base    # nlive: running estimate (repeated draws count twice)
+    out = {}
+    for i, r in enumerate(reqs):
+        if r.kind == "insert":
+            live[nxt:nxt + r.n] = True
+            nxt += r.n
+            nlive += r.n
+        elif r.kind == "delete":
+            if r.oldest:
+                got, need = [], r.n
+                while need > 0 and low < nxt:
+                    seg = np.flatnonzero(live[low:min(nxt, low + max(2 * need, 4096))]) + low
+                    take = seg[:need]
+                    got.append(take)
+                    need -= take.shape[0]
+                    low = int(take[-1]) + 1 if take.shape[0] == seg.shape[0] and take.shape[0] else (
+                        int(take[-1]) + 1 if take.shape[0] else min(nxt, low + max(2 * need, 4096)))
+                ids = np.concatenate(got) if got else np.zeros(0, np.int64)
+            else:
+                # draw enough that about r.n of the draws are live
+                frac = max(nlive, 1) / max(nxt - low, 1)
+                cand = rng.integers(low, nxt, size=int(r.n / frac * 1.05) + 16) if nxt > low else \
+                    np.zeros(0, np.int64)
+                cand.sort()             # monotone addresses: far fewer cache and TLB misses
+                ids = cand[live[cand]]
+                if ids.shape[0] > r.n:
+                    ids = ids[rng.permutation(ids.shape[0])[:r.n]]
+                    ids.sort()
+            live[ids] = False
+            nlive -= ids.shape[0]
+            out[i] = ids.astype(np.int64)
+    return out, live
