@@ -106,9 +106,10 @@ sivf_status sivf_destroy(sivf_index *ix);
 /* Insert n vectors (Sec. 3.2, Alg. 2; delete-then-insert for live ids, Sec. 3).
  * x: device, n x dim fp32 row-major; ids: device, n int64.  Each vector goes
  * to the list of its nearest centroid.  If any id is outside the id range
- * (SIVF_ERR_ID_RANGE) or the final state would need more slabs than the pool
- * holds (SIVF_ERR_NOSPACE), the whole batch is rejected and nothing changes.
- * 0 <= n <= max_batch. */
+ * (SIVF_ERR_ID_RANGE), the final state would need more slabs than the pool
+ * holds (SIVF_ERR_NOSPACE) or a vector has a non-finite coordinate
+ * (SIVF_ERR_ARG, as the device status), the whole batch is rejected and
+ * nothing changes.  0 <= n <= max_batch. */
 sivf_status sivf_add(sivf_index *ix, int64_t n, const float *x, const int64_t *ids, void *stream);
 
 /* Delete ids (Sec. 3.4, Alg. 4): O(1) address-table lookup per id; the hole

@@ -19,72 +19,135 @@ namespace sivf {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-template <int METRIC>
+// Block tile: 128 rows x 128 centroids, 256 threads; each wave owns a 64x64
+// quarter as 4x4 accumulators of v_mfma_f32_16x16x4_f32.  K advances 32 per
+// step: the next 32-wide slice of both operands is fetched into registers
+// (float4 loads) while the current one, stored k-major in LDS, feeds the
+// MFMAs.  The LDS row stride of 144 floats puts the two 16-lane k-groups of a
+// half-wave read in disjoint banks.
+constexpr int GM = 128, GN = 128, GK = 32, GLD = GM + 16;
+constexpr int GROUP = 16;   // lists per group minimum (insert path)
+
+// GMIN = 0: write Dt[r][l] for every list (out row stride ldo = nlist).
+// GMIN = 1: write only the minimum of each group of 16 consecutive lists,
+//           out[r][l / 16] (ldo = ceil(nlist / 16)); a NaN counts as +inf.
+template <int METRIC, int GMIN, bool VEC>
 __global__ __launch_bounds__(256) void k_coarse_gemm(const float *__restrict__ X, int n, int d,
                                                      const float *__restrict__ cent, int dpad,
                                                      const float *__restrict__ cn2, int nlist,
-                                                     float *__restrict__ out, const int32_t *ctl,
+                                                     float *__restrict__ out, int ldo, const int32_t *ctl,
                                                      int gated) {
-    constexpr int BM = 64, BN = 64, BK = 32;
-    __shared__ float sA[BM][BK + 1];
-    __shared__ float sB[BN][BK + 1];
-    __shared__ float sqn[BM];
+    __shared__ float sA[GK][GLD];
+    __shared__ float sB[GK][GLD];
+    __shared__ float sqn[GM];
     if (gated && call_failed(ctl)) return;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int r0 = blockIdx.x * BM, c0 = blockIdx.y * BN;
-    const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
-    floatx4 acc[2][2];
+    const int r0 = blockIdx.x * GM, c0 = blockIdx.y * GN;
+    const int wr = (w >> 1) * 64, wc = (w & 1) * 64;
+    const int lrow = tid >> 3, lk = (tid & 7) * 4;   // loader: 8 threads x float4 per row, 32 rows per pass
+    floatx4 acc[4][4];
 #pragma unroll
-    for (int i = 0; i < 2; i++)
+    for (int i = 0; i < 4; i++)
 #pragma unroll
-        for (int j = 0; j < 2; j++) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-    float qn = 0.f;
-    const int lr = tid >> 2, lk = (tid & 3) * 8;
-    const int ar = r0 + lr, bc = c0 + lr;
-    for (int k0 = 0; k0 < dpad; k0 += BK) {
+        for (int j = 0; j < 4; j++) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    float4 ra[4], rb[4];
+    float qp[4] = {0.f, 0.f, 0.f, 0.f};
+    const int kend = (dpad + GK - 1) / GK * GK;
+
+    auto gload = [&](int k0) {
+        const int kk = k0 + lk;
 #pragma unroll
-        for (int e = 0; e < 8; e++) {
-            const int kk = k0 + lk + e;
-            float va = (ar < n && kk < d) ? X[(int64_t)ar * d + kk] : 0.f;
-            float vb = (bc < nlist && kk < dpad) ? cent[(int64_t)bc * dpad + kk] : 0.f;
-            sA[lr][lk + e] = va;
-            sB[lr][lk + e] = vb;
-            qn = fmaf(va, va, qn);
+        for (int i = 0; i < 4; i++) {
+            const int r = r0 + lrow + 32 * i;
+            if (VEC) {   // d % 4 == 0: kk < d covers all four
+                ra[i] = (r < n && kk < d) ? *(const float4 *)(X + (int64_t)r * d + kk) : make_float4(0.f, 0.f, 0.f, 0.f);
+            } else {
+                const float *p = X + (int64_t)r * d;
+                ra[i].x = (r < n && kk + 0 < d) ? p[kk + 0] : 0.f;
+                ra[i].y = (r < n && kk + 1 < d) ? p[kk + 1] : 0.f;
+                ra[i].z = (r < n && kk + 2 < d) ? p[kk + 2] : 0.f;
+                ra[i].w = (r < n && kk + 3 < d) ? p[kk + 3] : 0.f;
+            }
+            const int c = c0 + lrow + 32 * i;   // centroid rows are zero-padded to dpad (a multiple of 4)
+            rb[i] = (c < nlist && kk < dpad) ? *(const float4 *)(cent + (int64_t)c * dpad + kk)
+                                             : make_float4(0.f, 0.f, 0.f, 0.f);
         }
-        __syncthreads();
+    };
+    auto lstore = [&]() {
 #pragma unroll
-        for (int kk = 0; kk < BK; kk += 4) {
-            float a[2], b[2];
-#pragma unroll
-            for (int i = 0; i < 2; i++) a[i] = sA[wr + 16 * i + (lane & 15)][kk + (lane >> 4)];
-#pragma unroll
-            for (int j = 0; j < 2; j++) b[j] = sB[wc + 16 * j + (lane & 15)][kk + (lane >> 4)];
-#pragma unroll
-            for (int i = 0; i < 2; i++)
-#pragma unroll
-                for (int j = 0; j < 2; j++)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+        for (int i = 0; i < 4; i++) {
+            const int rr = lrow + 32 * i;
+            sA[lk + 0][rr] = ra[i].x;
+            sA[lk + 1][rr] = ra[i].y;
+            sA[lk + 2][rr] = ra[i].z;
+            sA[lk + 3][rr] = ra[i].w;
+            sB[lk + 0][rr] = rb[i].x;
+            sB[lk + 1][rr] = rb[i].y;
+            sB[lk + 2][rr] = rb[i].z;
+            sB[lk + 3][rr] = rb[i].w;
+            qp[i] = fmaf(ra[i].x, ra[i].x, qp[i]);
+            qp[i] = fmaf(ra[i].y, ra[i].y, qp[i]);
+            qp[i] = fmaf(ra[i].z, ra[i].z, qp[i]);
+            qp[i] = fmaf(ra[i].w, ra[i].w, qp[i]);
         }
+    };
+    gload(0);
+    for (int k0 = 0; k0 < kend; k0 += GK) {
         __syncthreads();
+        lstore();
+        __syncthreads();
+        if (k0 + GK < kend) gload(k0 + GK);
+#pragma unroll
+        for (int s = 0; s < GK / 4; s++) {
+            const int kr = 4 * s + (lane >> 4);
+            float av[4], bv[4];
+#pragma unroll
+            for (int i = 0; i < 4; i++) av[i] = sA[kr][wr + 16 * i + (lane & 15)];
+#pragma unroll
+            for (int j = 0; j < 4; j++) bv[j] = sB[kr][wc + 16 * j + (lane & 15)];
+#pragma unroll
+            for (int i = 0; i < 4; i++)
+#pragma unroll
+                for (int j = 0; j < 4; j++)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+        }
     }
-    qn += __shfl_xor(qn, 1);
-    qn += __shfl_xor(qn, 2);
-    if ((tid & 3) == 0) sqn[lr] = qn;
+    // |x|^2 of each row: the 8 loader threads of a row are adjacent lanes
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        float v = qp[i];
+        v += __shfl_xor(v, 1);
+        v += __shfl_xor(v, 2);
+        v += __shfl_xor(v, 4);
+        if ((tid & 7) == 0) sqn[lrow + 32 * i] = v;
+    }
     __syncthreads();
+    // lane holds C[4 * (lane / 16) + r][lane % 16] of each 16x16 block
 #pragma unroll
-    for (int i = 0; i < 2; i++)
+    for (int j = 0; j < 4; j++) {
+        const int gc0 = c0 + wc + 16 * j;
+        const int gc = gc0 + (lane & 15);
+        const float c2 = (METRIC == 0 && gc < nlist) ? cn2[gc] : 0.f;
 #pragma unroll
-        for (int j = 0; j < 2; j++)
+        for (int i = 0; i < 4; i++)
 #pragma unroll
-            for (int rr = 0; rr < 4; rr++) {
-                const int row = wr + 16 * i + 4 * (lane >> 4) + rr;
-                const int gr = r0 + row, gc = c0 + wc + 16 * j + (lane & 15);
-                if (gr < n && gc < nlist) {
-                    const float dot = acc[i][j][rr];
-                    out[(int64_t)gr * nlist + gc] =
-                        METRIC == 0 ? (sqn[row] + cn2[gc]) - 2.0f * dot : -dot;
+            for (int r = 0; r < 4; r++) {
+                const int row = wr + 16 * i + 4 * (lane >> 4) + r;
+                const int gr = r0 + row;
+                const float dot = acc[i][j][r];
+                float v = METRIC == 0 ? (sqn[row] + c2) - 2.0f * dot : -dot;
+                if (!GMIN) {
+                    if (gr < n && gc < nlist) out[(int64_t)gr * ldo + gc] = v;
+                } else {
+                    v = (gc < nlist && v == v) ? v : __builtin_inff();
+                    v = fminf(v, __shfl_xor(v, 1));
+                    v = fminf(v, __shfl_xor(v, 2));
+                    v = fminf(v, __shfl_xor(v, 4));
+                    v = fminf(v, __shfl_xor(v, 8));
+                    if ((lane & 15) == 0 && gr < n && gc0 < nlist) out[(int64_t)gr * ldo + gc0 / GROUP] = v;
                 }
             }
+    }
 }
 
 __device__ __forceinline__ double canon_dist(const float *sx, const float *__restrict__ c, int d,
@@ -223,21 +286,129 @@ __global__ __launch_bounds__(256) void k_coarse_select(
     for (int p = tid; p < out_stride; p += 256) orow[p] = p < nk ? kl[p] : -1;
 }
 
+// Nearest list per row (m = 1) from the group minima of k_coarse_gemm<.., 1>.
+// tau = the smallest approximate distance; every list whose certified
+// interval can reach below the best one lies in a group whose minimum is at
+// most tau + 2 max E, so those groups are re-checked exactly (canonical FP64
+// distance, ties to the lower list).  Rows with a non-finite coordinate get
+// -1 (the insert then fails); rows or centroids so large that fp32 squares
+// could overflow are re-checked against every list.  One wave per row.
+__global__ __launch_bounds__(256) void k_coarse_argmin(const float *__restrict__ gmin, int ldg,
+                                                       const float *__restrict__ X, int n, int d,
+                                                       const float *__restrict__ cent, int dpad,
+                                                       const double *__restrict__ cmax, int nlist, int metric,
+                                                       int32_t *__restrict__ out, int out_stride,
+                                                       const int32_t *ctl, int gated) {
+    if (gated && call_failed(ctl)) return;
+    const int lane = threadIdx.x & 63;
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= n) return;
+    const float *xr = X + (int64_t)row * d;
+    double q2 = 0.0;
+    bool fin = true;
+    for (int j = lane; j < d; j += 64) {
+        const float v = xr[j];
+        fin = fin && __builtin_isfinite(v);
+        q2 = __fma_rn((double)v, (double)v, q2);
+    }
+    if (ballot(!fin)) {
+        if (lane == 0) out[(int64_t)row * out_stride] = -1;
+        return;
+    }
+    for (int o = 32; o > 0; o >>= 1) q2 += __shfl_xor(q2, o);
+    const double qn = sqrt(q2) * (1.0 + 0x1p-50);
+    const double cm = *cmax;
+    const double coef = (4.0 * d + 16.0) * 0x1p-24;
+    const double eabs = (double)d * 0x1p-120;
+    const double emax = metric == 0 ? coef * (qn + cm) * (qn + cm) + eabs : coef * qn * cm + eabs;
+    const bool every = !(qn + cm < 0x1p60);
+    const float *g = gmin + (int64_t)row * ldg;
+    float t = __builtin_inff();
+    for (int gi = lane; gi < ldg; gi += 64) t = fminf(t, g[gi]);
+    for (int o = 32; o > 0; o >>= 1) t = fminf(t, __shfl_xor(t, o));
+    const double ub = (double)t + 2.0 * emax;
+    double best = __builtin_inf();
+    int bestl = 0x7fffffff;
+    for (int g0 = 0; g0 < ldg; g0 += 64) {
+        const int gi = g0 + lane;
+        uint64_t mask = ballot(gi < ldg && (every || (double)g[gi] <= ub));
+        while (mask) {
+            // up to 4 qualifying groups per pass, 16 lanes (lists) each
+            int sel = -1;
+            for (int s = 0; s < 4 && mask; s++) {
+                const int b = __builtin_ctzll(mask);
+                mask &= mask - 1;
+                if ((lane >> 4) == s) sel = g0 + b;
+            }
+            const int l = sel * GROUP + (lane & 15);
+            if (sel >= 0 && l < nlist) {
+                const float *c = cent + (int64_t)l * dpad;
+                double r = 0.0;
+                if (metric == 0) {
+                    for (int j = 0; j < d; j++) {
+                        const double u = (double)xr[j] - (double)c[j];
+                        r = __fma_rn(u, u, r);
+                    }
+                } else {
+                    for (int j = 0; j < d; j++) r = __fma_rn((double)xr[j], (double)c[j], r);
+                    r = -r;
+                }
+                if (r < best || (r == best && l < bestl)) {
+                    best = r;
+                    bestl = l;
+                }
+            }
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(best, o);
+        const int ol = __shfl_xor(bestl, o);
+        if (ob < best || (ob == best && ol < bestl)) {
+            best = ob;
+            bestl = ol;
+        }
+    }
+    if (lane == 0) out[(int64_t)row * out_stride] = bestl < nlist ? bestl : -1;
+}
+
 size_t coarse_select_smem(int dpad, int mmax) {
     return (size_t)(2 * mmax + SEL_CAP) * sizeof(double) + (size_t)(2 * mmax + SEL_CAP) * sizeof(int) +
            (size_t)dpad * sizeof(float) + 16;
 }
 
+template <int GMIN>
+static void coarse_gemm_t(hipStream_t st, const float *X, int n, int d, const float *cent, int dpad,
+                          const float *cn2, int nlist, int metric, float *out, int ldo, const int32_t *ctl,
+                          int gated) {
+    const dim3 grid((n + GM - 1) / GM, (nlist + GN - 1) / GN);
+    const bool vec = (d % 4 == 0) && (((uintptr_t)X & 15) == 0);
+#define SIVF_GEMM(M, V)                                                                                         \
+    hipLaunchKernelGGL((k_coarse_gemm<M, GMIN, V>), grid, dim3(256), 0, st, X, n, d, cent, dpad, cn2, nlist,  \
+                       out, ldo, ctl, gated)
+    if (metric == 0) {
+        if (vec) SIVF_GEMM(0, true); else SIVF_GEMM(0, false);
+    } else {
+        if (vec) SIVF_GEMM(1, true); else SIVF_GEMM(1, false);
+    }
+#undef SIVF_GEMM
+}
+
 void launch_coarse_gemm(hipStream_t st, const float *X, int n, int d, const float *cent, int dpad,
                         const float *cn2, int nlist, int metric, float *out, const int32_t *ctl,
                         int gated) {
-    dim3 grid((n + 63) / 64, (nlist + 63) / 64);
-    if (metric == 0)
-        hipLaunchKernelGGL(k_coarse_gemm<0>, grid, dim3(256), 0, st, X, n, d, cent, dpad, cn2, nlist, out,
-                           ctl, gated);
-    else
-        hipLaunchKernelGGL(k_coarse_gemm<1>, grid, dim3(256), 0, st, X, n, d, cent, dpad, cn2, nlist, out,
-                           ctl, gated);
+    if (n > 0) coarse_gemm_t<0>(st, X, n, d, cent, dpad, cn2, nlist, metric, out, nlist, ctl, gated);
+}
+
+int coarse_groups(int nlist) { return (nlist + GROUP - 1) / GROUP; }
+
+void launch_coarse_assign(hipStream_t st, float *scratch, const float *X, int n, int d, const float *cent,
+                          int dpad, const float *cn2, const double *cmax, int nlist, int metric, int32_t *out,
+                          int out_stride, const int32_t *ctl, int gated) {
+    if (n <= 0) return;
+    const int ldg = coarse_groups(nlist);
+    coarse_gemm_t<1>(st, X, n, d, cent, dpad, cn2, nlist, metric, scratch, ldg, ctl, gated);
+    hipLaunchKernelGGL(k_coarse_argmin, dim3((n + 3) / 4), dim3(256), 0, st, scratch, ldg, X, n, d, cent, dpad,
+                       cmax, nlist, metric, out, out_stride, ctl, gated);
 }
 
 void launch_coarse_select(hipStream_t st, const float *dt, const float *X, int n, int d, const float *cent,

@@ -48,8 +48,15 @@ __global__ __launch_bounds__(256) void k_add_count(Dev S, int n, const int64_t *
     const int i = blockIdx.x * 256 + threadIdx.x;
     const bool active = i < n;
     const int64_t u = active ? ids[i] : 0;
-    const bool win = active && S.mark[u] == i;
-    const int l = win ? assign[i] : 0;
+    bool win = active && S.mark[u] == i;
+    int l = win ? assign[i] : 0;
+    // a row with no valid list (non-finite input) fails the whole call
+    const bool bad = win && (unsigned)l >= (unsigned)S.nlist;
+    if (ballot(bad) && lane_id() == 0) fail_call(S.ctl, -1);
+    if (bad) {
+        win = false;
+        l = 0;
+    }
     const int r = wave_agg_inc(S.l_acnt, l, win);
     if (active) rank[i] = win ? r : -1;
     const uint32_t g = win ? S.att[u] : INVALID;
@@ -64,11 +71,19 @@ __global__ __launch_bounds__(256) void k_add_count(Dev S, int n, const int64_t *
     }
 }
 
-// One block: does the final state fit in the pool?
+// One block: does the final state fit in the pool?  Also clears the per-list
+// counts of a call that already failed (k_add_count may have counted part of
+// the batch before the failure was raised).
 __global__ __launch_bounds__(1024) void k_add_admit(Dev S) {
     __shared__ long long sred[16];
-    if (call_failed(S.ctl)) return;
     const int tid = threadIdx.x;
+    if (call_failed(S.ctl)) {
+        for (int l = tid; l < S.nlist; l += 1024) {
+            S.l_prem[l] = 0;
+            S.l_acnt[l] = 0;
+        }
+        return;
+    }
     long long need = 0;
     for (int l = tid; l < S.nlist; l += 1024) need += cdiv(S.len[l] - S.l_prem[l] + S.l_acnt[l], S.C);
     for (int o = 32; o > 0; o >>= 1) need += __shfl_xor(need, o);

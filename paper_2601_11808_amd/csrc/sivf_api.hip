@@ -196,6 +196,11 @@ void coarse(sivf_index *ix, hipStream_t st, float *dt, const float *x, int64_t n
     for (int64_t r0 = 0; r0 < n; r0 += ix->L.coarse_rows) {
         const int nr = (int)((n - r0) < ix->L.coarse_rows ? (n - r0) : ix->L.coarse_rows);
         const float *xr = x + r0 * S.d;
+        if (m == 1 && !m_per_row && mmax == 1) {
+            launch_coarse_assign(st, dt, xr, nr, S.d, S.cent, dpad, S.cn2, S.cmax, S.nlist, S.metric,
+                                 out + r0 * out_stride, out_stride, S.ctl, gated);
+            continue;
+        }
         launch_coarse_gemm(st, xr, nr, S.d, S.cent, dpad, S.cn2, S.nlist, S.metric, dt, S.ctl, gated);
         launch_coarse_select(st, dt, xr, nr, S.d, S.cent, dpad, S.cnorm, S.cmax, S.nlist, S.metric, m,
                              m_per_row ? m_per_row + r0 : nullptr, mmax, out + r0 * out_stride, out_stride,

@@ -93,6 +93,29 @@ def test_assign_and_probe_exact(metric):
             np.testing.assert_array_equal(gp, rp)
 
 
+@pytest.mark.parametrize("metric", [0, 1])
+def test_assign_many_lists_and_extremes(metric):
+    """Nearest-list decisions at the serving shape (d=128, 16,384 lists), with
+    a ragged last group of lists (4,100 lists), and at magnitudes where fp32
+    squares overflow (every list is then re-checked in FP64)."""
+    w = workloads.serving(n_base=0)
+    rng = np.random.default_rng([11, metric])
+    x = (w.means[rng.integers(0, 16384, 3000)] + 48 * rng.standard_normal((3000, 128))).astype(np.float32)
+    p = Pair(128, 16384, w.centroids, metric=metric, max_batch=4096, max_nprobe=64)
+    np.testing.assert_array_equal(p.gpu.assign(x).cpu().numpy(), oracle.assign(x, w.centroids, metric))
+    gp = p.gpu.probe(x[:500], 64).cpu().numpy()
+    np.testing.assert_array_equal(gp, oracle.probe(x[:500], w.centroids, 64, metric))
+    cent, xt = _tie_data(4100 + metric, 128, 4100, 3000)
+    p = Pair(128, 4100, cent, metric=metric, max_batch=4096, max_nprobe=64)
+    np.testing.assert_array_equal(p.gpu.assign(xt).cpu().numpy(), oracle.assign(xt, cent, metric))
+    big_c = (rng.standard_normal((300, 33)) * 1e19).astype(np.float32)
+    big_x = (big_c[rng.integers(0, 300, 2000)] * np.float32(1.0001)
+             + (rng.standard_normal((2000, 33)) * 1e17).astype(np.float32)).astype(np.float32)
+    assert np.isfinite(big_x).all()
+    p = Pair(33, 300, big_c, metric=metric, max_batch=4096, max_nprobe=64)
+    np.testing.assert_array_equal(p.gpu.assign(big_x).cpu().numpy(), oracle.assign(big_x, big_c, metric))
+
+
 # --------------------------------------------------------- golden sequence
 
 def test_golden_mutation_sequence_gpu():

@@ -127,3 +127,40 @@ def test_server_admission_and_live_ids():
     srv.close()
     assert a.sync() == sivf.ERR_LIVE_ID
     assert same_membership(membership_of(a.dump()), before)
+    # ... and leaves no partial counts behind: later calls still match the oracle
+    ref = oracle.OracleIndex(w.dim, w.nlist, w.centroids, 0, 32, 160, 9000)
+    assert ref.add(x, ids) == 0
+    xb, idb = w.stream_batch(2, 300)
+    a.add(xb, idb)
+    assert a.sync() == 0
+    assert ref.add(xb, idb) == 0
+    check_dump(a.dump(), 32, 160)
+    assert same_membership(membership_of(a.dump()), ref.membership())
+    q = w.queries()
+    gd, gl = a.search(q, 10, 4)
+    assert a.sync() == 0
+    st, rd, rl = ref.search(q, 10, 4)
+    compare_results(gd.cpu().numpy(), gl.cpu().numpy(), rd, rl)
+
+
+def test_non_finite_vector_rejects_batch():
+    w = workloads.tiny()
+    x, ids = w.base()
+    a = sivf.Index(w.dim, w.nlist, w.centroids, metric=0, slab_capacity=32, num_slabs=400, id_capacity=9000,
+                   max_batch=4096, max_queries=64, max_k=16, max_nprobe=16)
+    a.add(x, ids)
+    assert a.sync() == 0
+    before = membership_of(a.dump())
+    xb, idb = w.stream_batch(1, 100)
+    for bad in (np.nan, np.inf, -np.inf):
+        xx = xb.copy()
+        xx[37, 5] = bad
+        a.add(xx, idb)
+        assert a.sync() == sivf.ERR_ARG
+        assert same_membership(membership_of(a.dump()), before)
+    a.add(xb, idb)
+    assert a.sync() == 0
+    ref = oracle.OracleIndex(w.dim, w.nlist, w.centroids, 0, 32, 400, 9000)
+    assert ref.add(x, ids) == 0 and ref.add(xb, idb) == 0
+    check_dump(a.dump(), 32, 400)
+    assert same_membership(membership_of(a.dump()), ref.membership())
