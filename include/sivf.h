@@ -85,7 +85,7 @@ typedef struct {
     int64_t id_capacity;   /* N_max: ids are dense in [0, id_capacity), <= 2^31    */
     int32_t max_batch;     /* largest n of one sivf_add / sivf_remove call         */
     int32_t max_queries;   /* largest nq of one sivf_search call                   */
-    int32_t max_k;         /* largest k, 1..64                                     */
+    int32_t max_k;         /* largest k, 1..128 (fp32 storage)                     */
     int32_t max_nprobe;    /* largest nprobe, 1..1024                              */
 } sivf_config;
 

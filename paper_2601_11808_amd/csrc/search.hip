@@ -33,33 +33,110 @@ __global__ __launch_bounds__(256) void k_inv_count(Dev S, int npairs, const int3
     if (active) pair_rank[p] = act ? r : -1;
 }
 
-__global__ __launch_bounds__(1024) void k_inv_plan(Dev S, int T, int32_t *__restrict__ item_list,
-                                                   int32_t *__restrict__ item_tile) {
+// Block sums of two int64 values (every thread gets both totals).
+__device__ __forceinline__ void block_sum2(long long &a, long long &b, long long *sred) {
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o);
+        b += __shfl_xor(b, o);
+    }
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __syncthreads();
+    if (lane_id() == 0) {
+        sred[w] = a;
+        sred[16 + w] = b;
+    }
+    __syncthreads();
+    a = 0;
+    b = 0;
+    for (int i = 0; i < nw; i++) {
+        a += sred[i];
+        b += sred[16 + i];
+    }
+}
+
+__device__ __forceinline__ int list_chunks(int len, int sh) {
+    return len > 0 ? (int)(((int64_t)len + (1ll << sh) - 1) >> sh) : 0;
+}
+
+// One block plans the whole search:
+//  1. snapshot every list's length (the scan reads only these entries) and
+//     lay out the (query, probe) pairs list by list;
+//  2. split lists into chunks of 2^sh positions, with the smallest sh >= sh0
+//     whose partial results (one per pair and chunk) and work items (one per
+//     tile of T pairs and chunk) fit their buffers -- a long list is scanned
+//     by many waves at once instead of one;
+//  3. per-list offsets of partial slots and items; reset the work counters.
+__global__ __launch_bounds__(1024) void k_inv_plan(Dev S, int T, int sh0, int64_t slot_cap, int64_t item_cap) {
     __shared__ int sbuf[16];
-    int carry_p = 0, carry_i = 0;
+    __shared__ long long sred[32];
+    int carry_p = 0;
     for (int base = 0; base < S.nlist; base += 1024) {
         const int l = base + threadIdx.x;
         const bool valid = l < S.nlist;
         const int qc = valid ? S.l_qc[l] : 0;
-        const int ln = valid ? S.len[l] : 0;
-        if (valid) S.l_snap[l] = ln;
-        const int nt = (qc > 0 && ln > 0) ? cdiv_s(qc, T) : 0;
-        int tp, ti;
+        int tp;
         const int ep = block_excl_scan<1024>(qc, sbuf, &tp);
-        const int ei = block_excl_scan<1024>(nt, sbuf, &ti);
         if (valid) {
+            S.l_snap[l] = S.len[l];
             S.l_qoff[l] = carry_p + ep;
             S.l_qcs[l] = qc;
             S.l_qc[l] = 0;
-            for (int t = 0; t < nt; t++) {
-                item_list[carry_i + ei + t] = l;
-                item_tile[carry_i + ei + t] = t;
-            }
         }
         carry_p += tp;
+    }
+    // each thread re-reads only the lists it wrote above
+    int sh = sh0;
+    for (;;) {
+        long long slots = 0, items = 0;
+        for (int l = threadIdx.x; l < S.nlist; l += 1024) {
+            const int qc = S.l_qcs[l];
+            const int nc = qc > 0 ? list_chunks(S.l_snap[l], sh) : 0;
+            slots += (long long)qc * nc;
+            items += (long long)cdiv_s(qc, T) * nc;
+        }
+        block_sum2(slots, items, sred);
+        if ((slots <= slot_cap && items <= item_cap) || sh >= 31) break;   // sh = 31: one chunk per list
+        sh++;
+    }
+    int carry_s = 0, carry_i = 0;
+    for (int base = 0; base < S.nlist; base += 1024) {
+        const int l = base + threadIdx.x;
+        const bool valid = l < S.nlist;
+        const int qc = valid ? S.l_qcs[l] : 0;
+        const int nc = qc > 0 ? list_chunks(S.l_snap[l], sh) : 0;
+        int ts, ti;
+        const int es = block_excl_scan<1024>(qc * nc, sbuf, &ts);
+        const int ei = block_excl_scan<1024>(cdiv_s(qc, T) * nc, sbuf, &ti);
+        if (valid) {
+            S.l_pbase[l] = carry_s + es;
+            S.l_ioff[l] = carry_i + ei;
+        }
+        carry_s += ts;
         carry_i += ti;
     }
-    if (threadIdx.x == 0) S.ctl[CTL_NITEMS] = carry_i;
+    if (threadIdx.x == 0) {
+        S.ctl[CTL_NITEMS] = carry_i;
+        S.ctl[CTL_CHUNK] = sh;
+    }
+    if (threadIdx.x < 8) S.ctl[CTL_WORK0 + threadIdx.x] = 0;
+}
+
+// Work items of each list, chunk-major (consecutive items read the same
+// slabs for different query tiles).  One wave per list.
+__global__ __launch_bounds__(256) void k_inv_items(Dev S, int T, int32_t *__restrict__ item_list,
+                                                   int32_t *__restrict__ item_tile, int32_t *__restrict__ item_chunk) {
+    const int l = blockIdx.x * 4 + (threadIdx.x >> 6), lane = lane_id();
+    if (l >= S.nlist) return;
+    const int qc = S.l_qcs[l];
+    if (qc == 0) return;
+    const int nc = list_chunks(S.l_snap[l], S.ctl[CTL_CHUNK]);
+    const int nt = cdiv_s(qc, T);
+    const int base = S.l_ioff[l];
+    for (int i = lane; i < nt * nc; i += 64) {
+        item_list[base + i] = l;
+        item_chunk[base + i] = i / nt;
+        item_tile[base + i] = i % nt;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_inv_scatter(Dev S, int npairs, const int32_t *__restrict__ probes,
@@ -170,33 +247,68 @@ __device__ __forceinline__ uint64_t merge_sorted_with(uint64_t a, uint64_t b) {
     return c;
 }
 
-template <int T>
+// Half-cleaners: sort a bitonic sequence across the 64 lanes.
+__device__ __forceinline__ uint64_t bitonic_clean(uint64_t v, bool asc) {
+    v = bitonic_step<64, 32>(v, asc);
+    v = bitonic_step<64, 16>(v, asc);
+    v = bitonic_step<64, 8>(v, asc);
+    v = bitonic_step<64, 4>(v, asc);
+    v = bitonic_step<64, 2>(v, asc);
+    v = bitonic_step<64, 1>(v, asc);
+    return v;
+}
+
+// 128-key lists (k > 64): a holds ranks 0..63 and a2 ranks 64..127 (each
+// sorted ascending across lanes).  Merge 64 unsorted keys b into them.  With
+// b sorted descending, min(a, b) holds the 64 smallest of a and b and
+// max(a, b) the rest; none of the former exceeds any key of a2, so the new
+// ranks 64..127 are the 64 smallest of max(a, b) and a2.
+__device__ __forceinline__ void merge128_with(uint64_t &a, uint64_t &a2, uint64_t b) {
+    b = wave_sort64(b, false);
+    const uint64_t lo = a < b ? a : b;
+    const uint64_t hi = a < b ? b : a;
+    a = bitonic_clean(lo, true);
+    const uint64_t h = bitonic_clean(hi, false);
+    a2 = bitonic_clean(a2 < h ? a2 : h, true);
+}
+
+// WIDE: kcap = 128 (two keys per lane).
+template <int T, bool WIDE>
 struct TopK {
-    uint64_t top[T];   // sorted keys, per query
-    uint32_t thr[T];   // high word of the query's k-th best key (wave-uniform)
-    int cnt[T];        // keys waiting in the LDS buffer (wave-uniform)
+    uint64_t top[T];              // sorted keys, per query (ranks 0..63)
+    uint64_t top2[WIDE ? T : 1];  // ranks 64..127
+    uint32_t thr[T];              // high word of the query's k-th best key (wave-uniform)
+    int cnt[T];                   // keys waiting in the LDS buffer (wave-uniform)
 };
 
 // kq: LDS array with each query's k (0 = no results wanted).
-template <int T>
-__device__ __forceinline__ void topk_init(TopK<T> &K, const int *kq) {
+template <int T, bool WIDE>
+__device__ __forceinline__ void topk_init(TopK<T, WIDE> &K, const int *kq) {
 #pragma unroll
     for (int t = 0; t < T; t++) {
         K.top[t] = ~0ull;
+        if (WIDE) K.top2[t] = ~0ull;
         K.thr[t] = kq[t] > 0 ? 0xFFFFFFFFu : 0u;
         K.cnt[t] = 0;
     }
 }
 
-template <int T>
-__device__ __forceinline__ void topk_flush(TopK<T> &K, int t, uint64_t *buf, const int *kq, int kcap) {
+template <int T, bool WIDE>
+__device__ __forceinline__ void topk_flush(TopK<T, WIDE> &K, int t, uint64_t *buf, const int *kq, int kcap) {
     __syncthreads();
     const int ln = lane_id();
     const uint64_t b = ln < K.cnt[t] ? buf[t * 64 + ln] : ~0ull;
-    uint64_t c = merge_sorted_with(K.top[t], b);
-    c = ln < kcap ? c : ~0ull;
-    K.top[t] = c;
-    K.thr[t] = (uint32_t)(readlane_u64(c, kq[t] - 1) >> 32);
+    if (WIDE) {
+        merge128_with(K.top[t], K.top2[t], b);
+        K.top2[t] = ln + 64 < kcap ? K.top2[t] : ~0ull;
+        const int r = kq[t] - 1;
+        K.thr[t] = (uint32_t)((r < 64 ? readlane_u64(K.top[t], r) : readlane_u64(K.top2[t], r - 64)) >> 32);
+    } else {
+        uint64_t c = merge_sorted_with(K.top[t], b);
+        c = ln < kcap ? c : ~0ull;
+        K.top[t] = c;
+        K.thr[t] = (uint32_t)(readlane_u64(c, kq[t] - 1) >> 32);
+    }
     K.cnt[t] = 0;
     __syncthreads();
 }
@@ -205,8 +317,8 @@ __device__ __forceinline__ void topk_flush(TopK<T> &K, int t, uint64_t *buf, con
 // (ordered distance), id its low word.  Keys whose high word is at most the
 // threshold's are buffered (a superset of those that beat the k-th key; the
 // merge orders them exactly).
-template <int T>
-__device__ __forceinline__ void topk_offer(TopK<T> &K, int t, bool valid, uint32_t hi, uint32_t id,
+template <int T, bool WIDE>
+__device__ __forceinline__ void topk_offer(TopK<T, WIDE> &K, int t, bool valid, uint32_t hi, uint32_t id,
                                            uint64_t *buf, const int *kq, int kcap) {
     bool pass = valid && hi <= K.thr[t];
     uint64_t mask = ballot(pass);
@@ -232,18 +344,50 @@ __device__ __forceinline__ uint32_t key_hi(float v) {
     return METRIC == 0 ? (__float_as_uint(v) | 0x80000000u) : ~ord_bits(v);
 }
 
+// Persistent scan: a fixed grid of waves pulls work items until none are
+// left.  The items are cut into 8 contiguous ranges, one per XCD (blocks are
+// dealt to the XCDs round robin); a wave takes items from its own XCD's range
+// first -- consecutive items share a list, so its slabs stay in that XCD's
+// L2 -- and then helps the other ranges.  Every wave ends once all 8
+// counters have passed their range.
+#define SIVF_ITEM_LOOP_BEGIN                                                                     \
+    const int nitems = S.ctl[CTL_NITEMS];                                                        \
+    const int per = (nitems + 7) >> 3;                                                           \
+    for (int xs = 0; xs < 8; xs++) {                                                             \
+        const int xx = (int)((blockIdx.x + xs) & 7);                                             \
+        const int lo = xx * per, hi = min(nitems, lo + per);                                     \
+        for (;;) {                                                                               \
+            int item = 0;                                                                        \
+            if (threadIdx.x == 0) item = atomicAdd(&S.ctl[CTL_WORK0 + xx], 1);                   \
+            item = __builtin_amdgcn_readfirstlane(item) + lo; /* uniform: scalar addressing */   \
+            if (item >= hi) break;
+#define SIVF_ITEM_LOOP_END \
+        }                  \
+    }
+
+// Decode a work item: list l, query tile, chunk of positions [p0, p1).
+#define SIVF_ITEM_DECODE(TT)                                                                     \
+    const int l = item_list[item], tile = item_tile[item], chunk = item_chunk[item];             \
+    const int nt = min(TT, S.l_qcs[l] - tile * TT);                                              \
+    const int len = S.l_snap[l];                                                                 \
+    const int nc = list_chunks(len, sh);                                                         \
+    const int p0 = (int)((int64_t)chunk << sh);                                                  \
+    const int p1 = (int)min((int64_t)len, ((int64_t)chunk << sh) + (1ll << sh));                 \
+    const int32_t *pairs = list_pairs + S.l_qoff[l] + tile * TT;                                 \
+    /* partial slot of query t of the tile: slot0 + t * nc */                                    \
+    const int64_t slot0 = (int64_t)S.l_pbase[l] + (int64_t)tile * TT * nc + chunk;
+
 // Distances of 64 consecutive list positions (lane <-> slot) to the T queries
 // of a tile, in the canonical order (dimensions ascending, one fma each), then
 // offered to each query's top-k.  QV(t, c) gives query t's dimension chunk c.
-#define SIVF_SCAN_BODY(QV)                                                                       \
-    const int len = S.l_snap[l];                                                                 \
+#define SIVF_SCAN_RANGE(QV)                                                                      \
     const int nslab = cdiv_s(len, C);                                                            \
     int wbase = -(1 << 30), wslab = 0; /* lane j holds the slab of ordinal wbase + j */          \
-    for (int base = 0; base < len; base += 64) {                                                 \
+    for (int base = p0; base < p1; base += 64) {                                                 \
         const int p = base + lane;                                                               \
-        const bool valid = p < len;                                                              \
-        const int pc = valid ? p : len - 1;                                                      \
-        const int last_ord = (min(base + 63, len - 1)) / C;                                      \
+        const bool valid = p < p1;                                                               \
+        const int pc = valid ? p : p1 - 1;                                                       \
+        const int last_ord = (min(base + 63, p1 - 1)) / C;                                       \
         if (last_ord >= wbase + 64) {                                                            \
             wbase = base / C;                                                                    \
             wslab = (wbase + lane < nslab) ? slab_of(S, l, wbase + lane) : 0;                    \
@@ -283,7 +427,9 @@ __device__ __forceinline__ uint32_t key_hi(float v) {
     _Pragma("unroll") for (int t = 0; t < T; t++) {                                              \
         if (t < nt) {                                                                            \
             if (K.cnt[t] > 0) topk_flush(K, t, buf, skq, kcap);                                  \
-            if (lane < kcap) partials[(int64_t)pairs[t] * kcap + lane] = K.top[t];               \
+            uint64_t *dst = partials + (slot0 + (int64_t)t * nc) * kcap;                         \
+            if (lane < kcap) dst[lane] = K.top[t];                                               \
+            if (WIDE && lane + 64 < kcap) dst[64 + lane] = K.top2[WIDE ? t : 0];                 \
         }                                                                                        \
     }
 
@@ -296,59 +442,53 @@ __device__ __forceinline__ int query_k(const int32_t *kpq, int k, int qi) {
 // so the compiler reads them through the scalar cache into SGPRs and every
 // VALU op takes its query operand from an SGPR (no LDS traffic).  Needs
 // d % 4 == 0 and 16-byte aligned rows.
-template <int T, int METRIC>
+template <int T, int METRIC, bool WIDE>
 __global__ __launch_bounds__(64) void k_scan_sq(Dev S, const int32_t *__restrict__ item_list,
                                                 const int32_t *__restrict__ item_tile,
+                                                const int32_t *__restrict__ item_chunk,
                                                 const int32_t *__restrict__ list_pairs,
                                                 const float *__restrict__ q, int np_stride, int kcap, int k,
-                                                const int32_t *__restrict__ kpq,
-                                                uint64_t *__restrict__ partials, int per_xcd) {
+                                                const int32_t *__restrict__ kpq, uint64_t *__restrict__ partials) {
     __shared__ uint64_t buf[T * 64];
     __shared__ int skq[T];
-    // Consecutive items (tiles of the same list) go to the same XCD, so a
-    // list's slabs are fetched once into that XCD's L2 and reused.
-    const int w = blockIdx.x;
-    const int item = (w & 7) * per_xcd + (w >> 3);
-    if (item >= S.ctl[CTL_NITEMS]) return;
     const int lane = threadIdx.x;
-    const int l = item_list[item], tile = item_tile[item];
-    const int nt = min(T, S.l_qcs[l] - tile * T);
-    const int dp4 = S.dp4, C = S.C;
-    const int32_t *pairs = list_pairs + S.l_qoff[l] + tile * T;
+    const int dp4 = S.dp4, C = S.C, sh = S.ctl[CTL_CHUNK];
+    SIVF_ITEM_LOOP_BEGIN
+    SIVF_ITEM_DECODE(T)
     const float4 *qrow[T];
-    TopK<T> K;
+    TopK<T, WIDE> K;
 #pragma unroll
     for (int t = 0; t < T; t++) {
         const int pr = pairs[t < nt ? t : 0];
         qrow[t] = reinterpret_cast<const float4 *>(q + (int64_t)(pr / np_stride) * S.d);
     }
+    __syncthreads();
     if (lane < T) skq[lane] = lane < nt ? query_k(kpq, k, pairs[lane] / np_stride) : 0;
     __syncthreads();
     topk_init(K, skq);
 #define SIVF_QV_SQ(t, c) qrow[t][c]
-    SIVF_SCAN_BODY(SIVF_QV_SQ)
+    SIVF_SCAN_RANGE(SIVF_QV_SQ)
 #undef SIVF_QV_SQ
+    SIVF_ITEM_LOOP_END
 }
 
 // General path: query rows of any alignment or dimension, staged in LDS.
-template <int T, int METRIC>
+template <int T, int METRIC, bool WIDE>
 __global__ __launch_bounds__(64) void k_scan(Dev S, const int32_t *__restrict__ item_list,
                                              const int32_t *__restrict__ item_tile,
+                                             const int32_t *__restrict__ item_chunk,
                                              const int32_t *__restrict__ list_pairs, const float *__restrict__ q,
                                              int np_stride, int kcap, int k, const int32_t *__restrict__ kpq,
-                                             uint64_t *__restrict__ partials, int per_xcd) {
+                                             uint64_t *__restrict__ partials) {
     extern __shared__ float4 sq[];   // [T][dp4]
     __shared__ uint64_t buf[T * 64];
     __shared__ int skq[T];
-    const int w = blockIdx.x;
-    const int item = (w & 7) * per_xcd + (w >> 3);
-    if (item >= S.ctl[CTL_NITEMS]) return;
     const int lane = threadIdx.x;
-    const int l = item_list[item], tile = item_tile[item];
-    const int nt = min(T, S.l_qcs[l] - tile * T);
-    const int dp4 = S.dp4, C = S.C, d = S.d;
-    const int32_t *pairs = list_pairs + S.l_qoff[l] + tile * T;
-    TopK<T> K;
+    const int dp4 = S.dp4, C = S.C, d = S.d, sh = S.ctl[CTL_CHUNK];
+    SIVF_ITEM_LOOP_BEGIN
+    SIVF_ITEM_DECODE(T)
+    TopK<T, WIDE> K;
+    __syncthreads();
     for (int t = 0; t < T; t++) {
         const int pr = t < nt ? pairs[t] : -1;
         const float *qr = q + (int64_t)(pr < 0 ? 0 : pr / np_stride) * d;
@@ -368,17 +508,56 @@ __global__ __launch_bounds__(64) void k_scan(Dev S, const int32_t *__restrict__ 
     __syncthreads();
     topk_init(K, skq);
 #define SIVF_QV_LDS(t, c) sq[(t) * dp4 + (c)]
-    SIVF_SCAN_BODY(SIVF_QV_LDS)
+    SIVF_SCAN_RANGE(SIVF_QV_LDS)
 #undef SIVF_QV_LDS
+    SIVF_ITEM_LOOP_END
 }
 
-#undef SIVF_SCAN_BODY
+#undef SIVF_SCAN_RANGE
+
+// A pair whose list was split into chunks has one partial list per chunk:
+// merge them into the first.  One thread per pair finds the split ones; the
+// wave merges them one at a time.
+template <bool WIDE>
+__global__ __launch_bounds__(256) void k_chunk_merge(Dev S, int npairs, const int32_t *__restrict__ probes,
+                                                     const int32_t *__restrict__ pair_rank,
+                                                     uint64_t *__restrict__ partials, int kcap) {
+    const int p = blockIdx.x * 256 + threadIdx.x, lane = lane_id();
+    const int sh = S.ctl[CTL_CHUNK];
+    const int l = p < npairs ? probes[p] : -1;
+    const int nc = l >= 0 ? list_chunks(S.l_snap[l], sh) : 0;
+    const int64_t slot = nc > 1 ? (int64_t)S.l_pbase[l] + (int64_t)pair_rank[p] * nc : 0;
+    uint64_t mask = ballot(nc > 1);
+    while (mask) {
+        const int src = __builtin_ctzll(mask);
+        mask &= mask - 1;
+        const int m = __shfl(nc, src);
+        const int64_t s0 = ((int64_t)__shfl((int)(slot >> 32), src) << 32) | (uint32_t)__shfl((int)slot, src);
+        uint64_t *dst = partials + s0 * kcap;
+        uint64_t a = lane < kcap ? dst[lane] : ~0ull;
+        uint64_t a2 = (WIDE && lane + 64 < kcap) ? dst[64 + lane] : ~0ull;
+        for (int c = 1; c < m; c++) {
+            const uint64_t *src_c = dst + (int64_t)c * kcap;
+            const uint64_t b0 = lane < kcap ? src_c[lane] : ~0ull;
+            if (WIDE) {
+                merge128_with(a, a2, b0);
+                const uint64_t b1 = lane + 64 < kcap ? src_c[64 + lane] : ~0ull;
+                merge128_with(a, a2, b1);
+            } else {
+                a = merge_sorted_with(a, b0);
+            }
+        }
+        if (lane < kcap) dst[lane] = a;
+        if (WIDE && lane + 64 < kcap) dst[64 + lane] = a2;
+    }
+}
 
 // One wave per query: repeatedly take the smallest head among the query's
-// probe partial lists (each sorted, kcap long).
-// k: the call's k; each query keeps kmul * (its k) results, at most
-// out_stride (the row stride of dist / labels).
+// probe partial lists (each sorted, kcap long; a split list's chunks were
+// merged into its first slot).  k: the call's k; each query keeps kmul * (its
+// k) results, at most out_stride (the row stride of dist / labels, <= 128).
 __global__ __launch_bounds__(256) void k_merge(Dev S, int nq, int np_stride, const int32_t *__restrict__ probes,
+                                               const int32_t *__restrict__ pair_rank,
                                                const uint64_t *__restrict__ partials, int kcap, int out_stride,
                                                int k, int kmul, const int32_t *__restrict__ kpq,
                                                float *__restrict__ dist, int64_t *__restrict__ labels) {
@@ -386,16 +565,20 @@ __global__ __launch_bounds__(256) void k_merge(Dev S, int nq, int np_stride, con
     const int w = threadIdx.x >> 6, lane = lane_id();
     const int qi = blockIdx.x * 4 + w;
     if (qi >= nq) return;
+    const int sh = S.ctl[CTL_CHUNK];
     int kq = kpq ? kpq[qi] : k;
     kq = kq < 0 ? 0 : (kq > k ? k : kq);
     kq = min(kq * kmul, out_stride);
     const int32_t *prow = probes + (int64_t)qi * np_stride;
-    const uint64_t *part = partials + (int64_t)qi * np_stride * kcap;
+    const int32_t *rrow = pair_rank + (int64_t)qi * np_stride;
     auto head_key = [&](int p) -> uint64_t {
         const int l = prow[p];
-        if (l < 0 || S.l_snap[l] == 0) return ~0ull;
+        if (l < 0) return ~0ull;
+        const int len = S.l_snap[l];
+        if (len == 0) return ~0ull;
         const int h = heads[w][p];
-        return h < kcap ? part[(int64_t)p * kcap + h] : ~0ull;
+        const int64_t slot = (int64_t)S.l_pbase[l] + (int64_t)rrow[p] * list_chunks(len, sh);
+        return h < kcap ? partials[slot * kcap + h] : ~0ull;
     };
     uint64_t best = ~0ull;
     int bestp = -1;
@@ -407,7 +590,7 @@ __global__ __launch_bounds__(256) void k_merge(Dev S, int nq, int np_stride, con
             bestp = p;
         }
     }
-    uint64_t res = ~0ull;
+    uint64_t res = ~0ull, res2 = ~0ull;   // result r sits in lane r (r < 64) or lane r - 64 of res2
     for (int r = 0; r < kq; r++) {
         uint64_t m = best;
 #pragma unroll
@@ -417,6 +600,7 @@ __global__ __launch_bounds__(256) void k_merge(Dev S, int nq, int np_stride, con
         }
         if (m == ~0ull) break;
         if (lane == r) res = m;
+        if (lane + 64 == r) res2 = m;
         if (best == m) {
             heads[w][bestp]++;
             best = ~0ull;
@@ -430,14 +614,18 @@ __global__ __launch_bounds__(256) void k_merge(Dev S, int nq, int np_stride, con
             }
         }
     }
-    if (lane < out_stride) {
-        const int64_t o = (int64_t)qi * out_stride + lane;
-        if (lane < kq && res != ~0ull) {
-            dist[o] = key_value(res, S.metric);
-            labels[o] = (int64_t)(uint32_t)res;
-        } else {
-            dist[o] = S.metric == 0 ? __int_as_float(0x7F800000) : __int_as_float((int)0xFF800000);
-            labels[o] = -1;
+    for (int h = 0; h < 2; h++) {
+        const int r = lane + 64 * h;
+        if (r < out_stride) {
+            const uint64_t key = h ? res2 : res;
+            const int64_t o = (int64_t)qi * out_stride + r;
+            if (r < kq && key != ~0ull) {
+                dist[o] = key_value(key, S.metric);
+                labels[o] = (int64_t)(uint32_t)key;
+            } else {
+                dist[o] = S.metric == 0 ? __int_as_float(0x7F800000) : __int_as_float((int)0xFF800000);
+                labels[o] = -1;
+            }
         }
     }
 }
@@ -498,22 +686,20 @@ __device__ __forceinline__ uint32_t mfma_flush(uint64_t (&top)[NQ], int t, const
 }
 
 template <int METRIC, int DT, int NKB>
-__global__ __launch_bounds__(64) void k_scan_mfma(Dev S, const int32_t *__restrict__ item_list,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_scan_mfma(Dev S, const int32_t *__restrict__ item_list,
                                                   const int32_t *__restrict__ item_tile,
+                                                  const int32_t *__restrict__ item_chunk,
                                                   const int32_t *__restrict__ list_pairs,
                                                   const float *__restrict__ q, int np_stride, int kcap, int k,
                                                   int kmul, const int32_t *__restrict__ kpq,
-                                                  uint64_t *__restrict__ partials, int per_xcd) {
+                                                  uint64_t *__restrict__ partials) {
     __shared__ uint64_t buf[MQ * MBUF];
     __shared__ int scnt[MQ], skq[MQ];
-    const int w = blockIdx.x;
-    const int item = (w & 7) * per_xcd + (w >> 3);
-    if (item >= S.ctl[CTL_NITEMS]) return;
     const int lane = threadIdx.x, qcol = lane & 15, kgrp = lane >> 4;
-    const int l = item_list[item], tile = item_tile[item];
-    const int nt = min(MQ, S.l_qcs[l] - tile * MQ);
-    const int d = S.d, C = S.C, dp8 = S.dp8;
-    const int32_t *pairs = list_pairs + S.l_qoff[l] + tile * MQ;
+    const int d = S.d, C = S.C, dp8 = S.dp8, sh = S.ctl[CTL_CHUNK];
+    SIVF_ITEM_LOOP_BEGIN
+    SIVF_ITEM_DECODE(MQ)
+    __syncthreads();
     if (lane < MQ) {
         skq[lane] = lane < nt ? min(kmul * query_k(kpq, k, pairs[lane] / np_stride), kcap) : 0;
         scnt[lane] = 0;
@@ -543,11 +729,10 @@ __global__ __launch_bounds__(64) void k_scan_mfma(Dev S, const int32_t *__restri
 #pragma unroll
     for (int t = 0; t < MQ; t++) top[t] = ~0ull;
 
-    const int len = S.l_snap[l];
     const int nslab = cdiv_s(len, C);
     int wbase = -(1 << 30), wslab = 0;
-    for (int base = 0; base < len; base += 64) {
-        const int last_ord = (min(base + 63, len - 1)) / C;
+    for (int base = p0; base < p1; base += 64) {
+        const int last_ord = (min(base + 63, p1 - 1)) / C;
         if (last_ord >= wbase + 64) {
             wbase = base / C;
             wslab = (wbase + lane < nslab) ? slab_of(S, l, wbase + lane) : 0;
@@ -558,7 +743,7 @@ __global__ __launch_bounds__(64) void k_scan_mfma(Dev S, const int32_t *__restri
 #pragma unroll
         for (int rg = 0; rg < 4; rg++) {
             const int p = base + 16 * rg + 4 * kgrp;
-            const int pc = p < len ? p : ((len - 1) & ~3);
+            const int pc = p < p1 ? p : ((p1 - 1) & ~3);
             g4[rg] = (int64_t)__shfl(wslab, pc / C - wbase) * C + pc % C;
         }
         float4 xn4[4] = {};
@@ -570,14 +755,14 @@ __global__ __launch_bounds__(64) void k_scan_mfma(Dev S, const int32_t *__restri
 #pragma unroll
         for (int rg = 0; rg < 4; rg++) {
             const int p = base + 16 * rg + qcol;
-            const int pc = p < len ? p : len - 1;
+            const int pc = p < p1 ? p : p1 - 1;
             const int slab = __shfl(wslab, pc / C - wbase);
             const uint4 *hp = S.hdata + (int64_t)slab * dp8 * C + pc % C;
             acc[rg] = f32x4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int kb = 0; kb < NKB; kb++) {
                 const int c8 = 4 * kb + kgrp;
-                const uint4 a = (c8 < dp8 && p < len) ? hp[(int64_t)c8 * C] : make_uint4(0, 0, 0, 0);
+                const uint4 a = (c8 < dp8 && p < p1) ? hp[(int64_t)c8 * C] : make_uint4(0, 0, 0, 0);
                 acc[rg] = mfma_16x16x32<DT>(a, bq[kb], acc[rg]);
             }
         }
@@ -592,7 +777,7 @@ __global__ __launch_bounds__(64) void k_scan_mfma(Dev S, const int32_t *__restri
                 const float v = METRIC == 0 ? (qn + xs[j]) - 2.f * acc[rg][j] : acc[rg][j];
                 const uint32_t hi = METRIC == 0 ? ord_bits(v) : ~ord_bits(v);
                 hiv[4 * rg + j] = hi;
-                if (base + r < len && qcol < nt && hi <= thr) pmask |= 1u << (4 * rg + j);
+                if (base + r < p1 && qcol < nt && hi <= thr) pmask |= 1u << (4 * rg + j);
             }
         }
         if (ballot(pmask != 0)) {
@@ -648,9 +833,10 @@ __global__ __launch_bounds__(64) void k_scan_mfma(Dev S, const int32_t *__restri
         if (t < nt) {
             const int cnt = scnt[t];
             if (cnt > 0) mfma_flush<MQ>(top, t, buf, cnt, skq[t], kcap);
-            if (lane < kcap) partials[(int64_t)pairs[t] * kcap + lane] = top[t];
+            if (lane < kcap) partials[(slot0 + (int64_t)t * nc) * kcap + lane] = top[t];
         }
     }
+    SIVF_ITEM_LOOP_END
 }
 
 // Exact FP32 re-rank: one wave per query; lane i recomputes the canonical
@@ -705,17 +891,22 @@ __global__ __launch_bounds__(256) void k_rerank(Dev S, int nq, const float *__re
     }
 }
 
+// Waves of the persistent scans: 32 per CU on 256 CUs (more than can be
+// resident; the surplus finds the counters exhausted and exits).
+constexpr unsigned SCAN_WAVES = 256 * 32;
+
+static unsigned scan_grid(const SearchBufs &W) {
+    return (unsigned)(W.item_cap < (int64_t)SCAN_WAVES ? (W.item_cap < 1 ? 1 : W.item_cap) : SCAN_WAVES);
+}
+
 void launch_search_scan_mfma(hipStream_t st, const Dev &S, const SearchBufs &W, int nq, const float *q,
                              int np_stride, int kcap, int k, int kmul, const int32_t *k_per_query) {
-    const int npairs = nq * np_stride;
-    const int64_t bound = (int64_t)npairs / MQ + (npairs < S.nlist ? npairs : S.nlist);
-    const int per_xcd = (int)((bound + 7) / 8);
-    const unsigned grid = (unsigned)(8 * per_xcd);
+    const unsigned grid = scan_grid(W);
     // k-blocks of 32 dimensions held as B operands: 2, 3, 4 or 8 (d <= 256)
     const int nkb = (S.d + 31) / 32;
 #define SIVF_LAUNCH_MFMA(M, D, K)                                                                            \
     hipLaunchKernelGGL((k_scan_mfma<M, D, K>), dim3(grid), dim3(64), 0, st, S, W.item_list, W.item_tile,     \
-                       W.list_pairs, q, np_stride, kcap, k, kmul, k_per_query, W.partials, per_xcd)
+                       W.item_chunk, W.list_pairs, q, np_stride, kcap, k, kmul, k_per_query, W.partials)
 #define SIVF_LAUNCH_MFMA_K(M, D)                                                                             \
     do {                                                                                                     \
         if (nkb <= 2) SIVF_LAUNCH_MFMA(M, D, 2);                                                             \
@@ -737,56 +928,70 @@ void launch_rerank(hipStream_t st, const Dev &S, int nq, const float *q, int kc,
                        dist, labels);
 }
 
-template <int T>
+template <int T, bool WIDE>
 static void launch_scan_t(hipStream_t st, const Dev &S, const SearchBufs &W, const float *q, int np_stride,
-                          int kcap, int k, const int32_t *kpq, unsigned grid, int per_xcd) {
+                          int kcap, int k, const int32_t *kpq) {
+    const unsigned grid = scan_grid(W);
     const bool sq = (S.d % 4 == 0) && (((uintptr_t)q & 15) == 0);
     if (sq) {
         if (S.metric == 0)
-            hipLaunchKernelGGL((k_scan_sq<T, 0>), dim3(grid), dim3(64), 0, st, S, W.item_list, W.item_tile,
-                               W.list_pairs, q, np_stride, kcap, k, kpq, W.partials, per_xcd);
+            hipLaunchKernelGGL((k_scan_sq<T, 0, WIDE>), dim3(grid), dim3(64), 0, st, S, W.item_list, W.item_tile,
+                               W.item_chunk, W.list_pairs, q, np_stride, kcap, k, kpq, W.partials);
         else
-            hipLaunchKernelGGL((k_scan_sq<T, 1>), dim3(grid), dim3(64), 0, st, S, W.item_list, W.item_tile,
-                               W.list_pairs, q, np_stride, kcap, k, kpq, W.partials, per_xcd);
+            hipLaunchKernelGGL((k_scan_sq<T, 1, WIDE>), dim3(grid), dim3(64), 0, st, S, W.item_list, W.item_tile,
+                               W.item_chunk, W.list_pairs, q, np_stride, kcap, k, kpq, W.partials);
         return;
     }
     const size_t smem = (size_t)T * S.dp4 * sizeof(float4);
     if (S.metric == 0)
-        hipLaunchKernelGGL((k_scan<T, 0>), dim3(grid), dim3(64), smem, st, S, W.item_list, W.item_tile,
-                           W.list_pairs, q, np_stride, kcap, k, kpq, W.partials, per_xcd);
+        hipLaunchKernelGGL((k_scan<T, 0, WIDE>), dim3(grid), dim3(64), smem, st, S, W.item_list, W.item_tile,
+                           W.item_chunk, W.list_pairs, q, np_stride, kcap, k, kpq, W.partials);
     else
-        hipLaunchKernelGGL((k_scan<T, 1>), dim3(grid), dim3(64), smem, st, S, W.item_list, W.item_tile,
-                           W.list_pairs, q, np_stride, kcap, k, kpq, W.partials, per_xcd);
+        hipLaunchKernelGGL((k_scan<T, 1, WIDE>), dim3(grid), dim3(64), smem, st, S, W.item_list, W.item_tile,
+                           W.item_chunk, W.list_pairs, q, np_stride, kcap, k, kpq, W.partials);
 }
+
+// Default chunk: 2^14 positions per work item (a list is split only when
+// the plan's buffers allow; longer chunks otherwise).
+constexpr int CHUNK_SHIFT = 14;
 
 void launch_search_plan(hipStream_t st, const Dev &S, const SearchBufs &W, int nq, int np_stride) {
     const int npairs = nq * np_stride;
     const unsigned pb = (unsigned)((npairs + 255) / 256);
+    const int T = search_tile(S);
     hipLaunchKernelGGL(k_inv_count, dim3(pb), dim3(256), 0, st, S, npairs, W.probes, W.pair_rank);
-    hipLaunchKernelGGL(k_inv_plan, dim3(1), dim3(1024), 0, st, S, search_tile(S), W.item_list, W.item_tile);
+    hipLaunchKernelGGL(k_inv_plan, dim3(1), dim3(1024), 0, st, S, T, CHUNK_SHIFT, W.slot_cap, W.item_cap);
+    hipLaunchKernelGGL(k_inv_items, dim3((S.nlist + 3) / 4), dim3(256), 0, st, S, T, W.item_list, W.item_tile,
+                       W.item_chunk);
     hipLaunchKernelGGL(k_inv_scatter, dim3(pb), dim3(256), 0, st, S, npairs, W.probes, W.pair_rank,
                        W.list_pairs);
 }
 
 void launch_search_scan(hipStream_t st, const Dev &S, const SearchBufs &W, int nq, const float *q, int np_stride,
                         int kcap, int k, const int32_t *k_per_query) {
-    const int npairs = nq * np_stride;
     const int T = search_tile(S);
-    // items <= sum over lists of ceil(pairs_l / T) <= npairs / T + min(nlist, npairs)
-    const int64_t bound = (int64_t)npairs / T + (npairs < S.nlist ? npairs : S.nlist);
-    const int per_xcd = (int)((bound + 7) / 8);
-    const unsigned grid = (unsigned)(8 * per_xcd);
-    if (T == 8)
-        launch_scan_t<8>(st, S, W, q, np_stride, kcap, k, k_per_query, grid, per_xcd);
-    else
-        launch_scan_t<4>(st, S, W, q, np_stride, kcap, k, k_per_query, grid, per_xcd);
+    if (kcap > 64) {
+        if (T == 8) launch_scan_t<8, true>(st, S, W, q, np_stride, kcap, k, k_per_query);
+        else launch_scan_t<4, true>(st, S, W, q, np_stride, kcap, k, k_per_query);
+    } else {
+        if (T == 8) launch_scan_t<8, false>(st, S, W, q, np_stride, kcap, k, k_per_query);
+        else launch_scan_t<4, false>(st, S, W, q, np_stride, kcap, k, k_per_query);
+    }
 }
 
 void launch_search_merge(hipStream_t st, const Dev &S, const SearchBufs &W, int nq, int np_stride, int kcap,
                          int out_stride, int k, int kmul, const int32_t *k_per_query, float *dist,
                          int64_t *labels) {
-    hipLaunchKernelGGL(k_merge, dim3((nq + 3) / 4), dim3(256), 0, st, S, nq, np_stride, W.probes, W.partials,
-                       kcap, out_stride, k, kmul, k_per_query, dist, labels);
+    const int npairs = nq * np_stride;
+    const unsigned pb = (unsigned)((npairs + 255) / 256);
+    if (kcap > 64)
+        hipLaunchKernelGGL(k_chunk_merge<true>, dim3(pb), dim3(256), 0, st, S, npairs, W.probes, W.pair_rank,
+                           W.partials, kcap);
+    else
+        hipLaunchKernelGGL(k_chunk_merge<false>, dim3(pb), dim3(256), 0, st, S, npairs, W.probes, W.pair_rank,
+                           W.partials, kcap);
+    hipLaunchKernelGGL(k_merge, dim3((nq + 3) / 4), dim3(256), 0, st, S, nq, np_stride, W.probes, W.pair_rank,
+                       W.partials, kcap, out_stride, k, kmul, k_per_query, dist, labels);
 }
 
 }  // namespace sivf

@@ -24,15 +24,15 @@ constexpr int64_t COARSE_BYTES = 256ll << 20;   // scratch for approximate coars
 
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
-int kcap_for(int k) { return k <= 16 ? 16 : (k <= 32 ? 32 : 64); }
+int kcap_for(int k) { return k <= 16 ? 16 : (k <= 32 ? 32 : (k <= 64 ? 64 : 128)); }
 
 struct Layout {
     int dp4, kcap, coarse_rows;
-    int64_t num_pages, dir_cap, max_items;
+    int64_t num_pages, dir_cap, max_items, slot_cap;
     size_t total;
     size_t cent, cn2, cnorm, cmax, data, sids, sowner, sord, free_slabs, free_pages, pages, dir, len, att, mark,
         ctl, lists, b_assign, b_rank, b_rec, b_seg, dt, probes, pair_rank, list_pairs, item_list, item_tile,
-        partials, hdata, xnorm, rr_dist, rr_lab, dt_s;
+        item_chunk, partials, hdata, xnorm, rr_dist, rr_lab, dt_s;
 };
 
 bool config_ok(const sivf_config *c) {
@@ -50,7 +50,7 @@ bool config_ok(const sivf_config *c) {
     if (c->num_slabs < 1 || c->num_slabs * (int64_t)c->slab_capacity >= (1ll << 31)) return false;
     if (c->id_capacity < 1 || c->id_capacity >= (1ll << 31)) return false;
     if (c->max_batch < 1 || c->max_queries < 1) return false;
-    if (c->max_k < 1 || c->max_k > 64) return false;
+    if (c->max_k < 1 || c->max_k > 128) return false;
     if (c->max_nprobe < 1 || c->max_nprobe > 1024) return false;
     if ((int64_t)c->max_queries * c->max_nprobe >= (1ll << 31) / 64) return false;
     return true;
@@ -68,6 +68,7 @@ Layout make_layout(const sivf_config *c) {
     L.coarse_rows = (int)(rows_need < rows_cap ? rows_need : rows_cap);
     const int64_t npairs = (int64_t)c->max_queries * c->max_nprobe;
     L.max_items = npairs + nl;
+    L.slot_cap = npairs + npairs / 2;   // partial results: one per (pair, list chunk)
     size_t cur = 0;
     auto take = [&](size_t bytes) {
         size_t o = cur;
@@ -90,7 +91,7 @@ Layout make_layout(const sivf_config *c) {
     L.att = take((size_t)c->id_capacity * 4);
     L.mark = take((size_t)c->id_capacity * 4);
     L.ctl = take(CTL_WORDS * 4);
-    L.lists = take((size_t)13 * nl * 4);
+    L.lists = take((size_t)15 * nl * 4);
     L.b_assign = take((size_t)c->max_batch * 4);
     L.b_rank = take((size_t)c->max_batch * 4);
     L.b_rec = take((size_t)c->max_batch * 4);
@@ -102,7 +103,8 @@ Layout make_layout(const sivf_config *c) {
     L.list_pairs = take((size_t)npairs * 4);
     L.item_list = take((size_t)L.max_items * 4);
     L.item_tile = take((size_t)L.max_items * 4);
-    L.partials = take((size_t)npairs * L.kcap * 8);
+    L.item_chunk = take((size_t)L.max_items * 4);
+    L.partials = take((size_t)L.slot_cap * L.kcap * 8);
     const bool reduced = c->storage != SIVF_F32;
     L.hdata = take(reduced ? (size_t)ns * ((c->dim + 7) / 8) * C * 16 : 0);
     L.xnorm = take(reduced && c->metric == SIVF_L2 ? (size_t)ns * C * 4 : 0);
@@ -337,8 +339,8 @@ sivf_status sivf_create(const sivf_config *cfg, const float *centroids, void *wo
     S.ctl = (int32_t *)(w + L.ctl);
     int32_t *lists = (int32_t *)(w + L.lists);
     int32_t **lp[] = {&S.l_acnt, &S.l_prem, &S.l_base, &S.l_m, &S.l_off, &S.l_newlen,
-                      &S.l_q, &S.l_s, &S.l_h, &S.l_qc, &S.l_qcs, &S.l_qoff, &S.l_snap};
-    for (int i = 0; i < 13; i++) *lp[i] = lists + (size_t)i * cfg->nlist;
+                      &S.l_q, &S.l_s, &S.l_h, &S.l_qc, &S.l_qcs, &S.l_qoff, &S.l_snap, &S.l_pbase, &S.l_ioff};
+    for (int i = 0; i < 15; i++) *lp[i] = lists + (size_t)i * cfg->nlist;
     ix->B.assign = (int32_t *)(w + L.b_assign);
     ix->B.rank = (int32_t *)(w + L.b_rank);
     ix->B.rec = (uint32_t *)(w + L.b_rec);
@@ -350,7 +352,10 @@ sivf_status sivf_create(const sivf_config *cfg, const float *centroids, void *wo
     ix->W.list_pairs = (int32_t *)(w + L.list_pairs);
     ix->W.item_list = (int32_t *)(w + L.item_list);
     ix->W.item_tile = (int32_t *)(w + L.item_tile);
+    ix->W.item_chunk = (int32_t *)(w + L.item_chunk);
     ix->W.partials = (uint64_t *)(w + L.partials);
+    ix->W.slot_cap = L.slot_cap;
+    ix->W.item_cap = L.max_items;
     ix->last = as_stream(stream);
     launch_init_state(as_stream(stream), S, centroids);
     if (!dev_ok(hipGetLastError())) {

@@ -33,6 +33,8 @@ enum Ctl {
     CTL_UPSERT = 4,     // sequence number of the add call that holds live ids
     CTL_NITEMS = 5,     // search: work items of the current call
     CTL_SEQ = 6,        // sequence number of the current add/remove call; its last kernel bumps it
+    CTL_CHUNK = 7,      // search: log2 of the positions per work item (a list's chunk)
+    CTL_WORK0 = 8,      // search: 8 work counters, one per XCD range of items (words 8..15)
     CTL_WORDS = 64
 };
 
@@ -60,6 +62,8 @@ struct Dev {
     int32_t *l_m, *l_off, *l_newlen, *l_q, *l_s, *l_h; // remove
     int32_t *l_qc, *l_qcs, *l_qoff;                  // search
     int32_t *l_snap;   // search: list lengths when the search was planned (it scans only these)
+    int32_t *l_pbase;  // search: first partial-result slot of the list's (pair, chunk) results
+    int32_t *l_ioff;   // search: first work item of the list
 };
 
 __device__ __forceinline__ int slab_of(const Dev &S, int l, int ord) {

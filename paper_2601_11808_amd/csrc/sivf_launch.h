@@ -48,8 +48,10 @@ void launch_fill_i64(hipStream_t st, int64_t *p, int64_t n, int64_t v);
 
 // ---- search (search.hip)
 struct SearchBufs {
-    int32_t *probes, *pair_rank, *list_pairs, *item_list, *item_tile;
+    int32_t *probes, *pair_rank, *list_pairs, *item_list, *item_tile, *item_chunk;
     uint64_t *partials;
+    int64_t slot_cap;    // partial-result slots (kcap keys each) in partials
+    int64_t item_cap;    // entries of item_list / item_tile / item_chunk
     float *rr_dist;      // reduced precision: approximate candidates per query
     int64_t *rr_lab;
 };

@@ -59,7 +59,7 @@ def test_workspace_bytes_and_config_validation(lib):
     bad = [dict(dim=0), dict(nlist=0), dict(slab_capacity=48), dict(slab_capacity=256), dict(slab_capacity=0), dict(metric=2), dict(storage=3), dict(storage=1), dict(rerank_factor=2),
            dict(storage=1, rerank_factor=8, max_k=16), dict(storage=1, rerank_factor=4, dim=512),
            dict(storage=1, rerank_factor=4, slab_capacity=8),
-           dict(num_slabs=0), dict(id_capacity=0), dict(max_k=65), dict(max_k=0), dict(max_nprobe=0),
+           dict(num_slabs=0), dict(id_capacity=0), dict(max_k=129), dict(max_k=0), dict(storage=1, rerank_factor=1, max_k=65), dict(max_nprobe=0),
            dict(max_nprobe=2000), dict(num_slabs=1 << 30)]
     for b in bad:
         assert lib.sivf_workspace_bytes(ct.byref(_cfg(**b))) == 0, b
