@@ -15,6 +15,10 @@ HIP-graph steps), recall@10 and an nprobe sweep against exact kNN, the
 roofline of the scan kernel, and the CPU oracle's rate on a bounded sample.
 
 Other modes (not the headline line):
+  --workload batched   the batched uneven form: 5M vectors over 2,048 Zipf-
+                       skewed lists, 32k queries with per-query nprobe
+                       U[8,128] and k in {1,10,100}, +20k / -20k random ids
+                       per step, autotuned schedule, eager and graph steps
   --workload serve     the serving form: a 50M-vector fp16 window (d=128,
                        16,384 lists, slab 128) under a Poisson stream of
                        searches, inserts and deletes through the
@@ -48,7 +52,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="window", choices=["window", "tiny", "precision", "serve"])
+    ap.add_argument("--workload", default="window", choices=["window", "tiny", "precision", "serve", "batched"])
     ap.add_argument("--serve-seconds", type=float, default=5.0, help="serve: length of the arrival stream")
     ap.add_argument("--serve-rate", type=float, default=2000.0, help="serve: Poisson arrival rate (req/s)")
     ap.add_argument("--serve-n", type=int, default=50_000_000, help="serve: steady-state window size")
@@ -140,6 +144,8 @@ def main():
         sys.exit(2)
     if a.workload == "serve":
         return serve_main(a)
+    if a.workload == "batched":
+        return batched_main(a)
     import torch
     import paper_2601_11808_amd as sivf
     import workloads
@@ -343,6 +349,169 @@ def main():
     print(json.dumps(res), flush=True)
 
 
+def exact_knn_device(ix, live_ids, q, k, metric, dev, cand=None):
+    """Exact top-k over the live rows (fetched from the index in 2M-row
+    chunks): candidates by fp32 scores on the device, the best `cand` of them
+    re-scored in float64 on the host, ties by smaller id."""
+    import torch
+    cand = cand or max(32, 2 * k)
+    nq = q.shape[0]
+    q2 = (q * q).sum(1, keepdim=True)
+    best_s = torch.full((nq, cand), float("inf"), device=dev)
+    best_i = torch.full((nq, cand), -1, dtype=torch.int64, device=dev)
+    for s0 in range(0, live_ids.shape[0], 1 << 21):
+        idc = torch.from_numpy(live_ids[s0:s0 + (1 << 21)]).to(dev)
+        rows = ix.get_rows(idc)
+        sc = (q2 + (rows * rows).sum(1)[None, :] - 2.0 * (q @ rows.T)) if metric == 0 else -(q @ rows.T)
+        s_c, o_c = torch.topk(sc, min(cand, sc.shape[1]), dim=1, largest=False)
+        cs = torch.cat([best_s, s_c], 1)
+        ci = torch.cat([best_i, idc[o_c]], 1)
+        best_s, o = torch.topk(cs, cand, dim=1, largest=False)
+        best_i = torch.gather(ci, 1, o)
+        del rows, sc
+    ci = best_i.cpu().numpy()
+    rows = ix.get_rows(torch.from_numpy(ci.reshape(-1)).to(dev)).cpu().numpy().astype(np.float64)
+    qd = q.cpu().numpy().astype(np.float64)
+    rows = rows.reshape(nq, cand, -1)
+    d64 = ((rows - qd[:, None, :]) ** 2).sum(2) if metric == 0 else -(rows * qd[:, None, :]).sum(2)
+    return [ci[j][np.lexsort((ci[j], d64[j]))[:k]] for j in range(nq)]
+
+
+def batched_main(a):
+    """Batched uneven form: skewed lists, per-query nprobe and k, random
+    deletes; window steps eager and as HIP graphs, after the autotuner."""
+    import torch
+    import paper_2601_11808_amd as sivf
+    import workloads
+
+    if not os.path.exists(sivf.LIB_PATH):
+        raise SystemExit("libsivf.so is not built: run python -c 'import __graft_entry__ as g; g.build()'")
+    dev = torch.device("cuda:0")
+    w = workloads.batched()
+    N, B, C, nq = w.n_base, w.batch, w.slab, w.n_queries
+    steps, warm = a.steps, a.warmup
+    T = warm + 2 * steps
+    npq, kpq = workloads.per_query_params(nq)
+    kmax = int(kpq.max())
+    id_cap = N + B * (T + 2)
+    num_slabs = int(1.1 * (N + 2 * B) / C) + 2 * w.nlist
+    ix = sivf.Index(w.dim, w.nlist, w.centroids, metric=w.metric, slab_capacity=C, num_slabs=num_slabs,
+                    id_capacity=id_cap, max_batch=1 << 16, max_queries=nq, max_k=kmax, max_nprobe=int(npq.max()),
+                    device="cuda:0")
+    log(f"[batched] N={N} d={w.dim} nlist={w.nlist} C={C}; {nq} queries, nprobe U[{npq.min()},{npq.max()}], "
+        f"k in {sorted(set(kpq.tolist()))}; workspace {ix.workspace_bytes / 2**30:.1f} GiB")
+    means = torch.from_numpy(w.means).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c, s0 in enumerate(range(0, N, 1 << 16)):
+        n = min(1 << 16, N - s0)
+        ix.add(workloads.device_sample(w, n, 1000 + c, dev, means), torch.arange(s0, s0 + n, device=dev))
+    assert ix.sync() == 0
+    load_s = time.perf_counter() - t0
+    lens = ix.dump()["list_len"]
+    log(f"[batched] bulk load {load_s:.1f} s; list lengths min {lens.min()} median {int(np.median(lens))} "
+        f"max {lens.max()}")
+    qd = workloads.device_sample(w, nq, 2, dev, means)
+    kpq_d = torch.from_numpy(kpq).to(dev)
+    npq_d = torch.from_numpy(npq).to(dev)
+    t0 = time.perf_counter()
+    tile, sh = ix.tune_search(qd, kmax, int(npq.max()), k_per_query=kpq_d, nprobe_per_query=npq_d)
+    log(f"[batched] autotuner: {tile} queries x 2^{sh} positions per work item ({time.perf_counter() - t0:.1f} s)")
+    # per step: B fresh vectors in, B uniformly random live ids out
+    rng = np.random.default_rng([w.seed, 3, 1])
+    live = np.arange(N, dtype=np.int64)
+    bx, bi, bo = [], [], []
+    for t in range(T):
+        ids = np.arange(N + B * t, N + B * (t + 1), dtype=np.int64)
+        idx = rng.choice(live.shape[0], B, replace=False)
+        out = live[idx]
+        live = np.concatenate([np.delete(live, idx), ids])
+        bx.append(workloads.device_sample(w, B, 100 + t, dev, means))
+        bi.append(torch.from_numpy(ids).to(dev))
+        bo.append(torch.from_numpy(out).to(dev))
+    dist = torch.empty((nq, kmax), dtype=torch.float32, device=dev)
+    lab = torch.empty((nq, kmax), dtype=torch.int64, device=dev)
+    np_max = int(npq.max())
+    for t in range(warm):
+        ix.step(bx[t], bi[t], qd, kmax, np_max, bo[t], out=(dist, lab), k_per_query=kpq_d, nprobe_per_query=npq_d)
+    assert ix.sync() == 0
+    ix.profile_read()
+    ix.profile(True)
+    step_ms = []
+    torch.cuda.synchronize()
+    t_all = time.perf_counter()
+    for t in range(warm, warm + steps):
+        ts = time.perf_counter()
+        ix.step(bx[t], bi[t], qd, kmax, np_max, bo[t], out=(dist, lab), k_per_query=kpq_d, nprobe_per_query=npq_d)
+        torch.cuda.synchronize()
+        step_ms.append((time.perf_counter() - ts) * 1e3)
+    elapsed = time.perf_counter() - t_all
+    prof = ix.profile_read()
+    ix.profile(False)
+    assert ix.sync() == 0
+    # graph mode on refilled buffers
+    gx = torch.empty((B, w.dim), dtype=torch.float32, device=dev)
+    gi = torch.empty(B, dtype=torch.int64, device=dev)
+    go = torch.empty(B, dtype=torch.int64, device=dev)
+    nrem = torch.zeros(1, dtype=torch.int64, device=dev)
+    g = ix.step_graph(gx, gi, qd, kmax, np_max, go, dist, lab, nrem, k_per_query=kpq_d, nprobe_per_query=npq_d)
+    gsteps = []
+    for t in range(warm + steps, T):
+        gx.copy_(bx[t])
+        gi.copy_(bi[t])
+        go.copy_(bo[t])
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        g.launch()
+        torch.cuda.synchronize()
+        gsteps.append((time.perf_counter() - ts) * 1e3)
+    g.close()
+    assert ix.sync() == 0
+    st = ix.stats()
+    assert st["live"] == live.shape[0], (st["live"], live.shape[0])
+    # recall@10 of queries with k >= 10 (their own nprobe) on the final window
+    sel = np.flatnonzero(kpq >= 10)[:500]
+    qs = qd[torch.from_numpy(sel).to(dev)]
+    gt = exact_knn_device(ix, live, qs, 10, w.metric, dev)
+    _, lab_s = ix.search(qs, kmax, np_max, k_per_query=kpq_d[torch.from_numpy(sel).to(dev)],
+                         nprobe_per_query=npq_d[torch.from_numpy(sel).to(dev)])
+    lab_s = lab_s.cpu().numpy()
+    rec = float(np.mean([len(set(gt[j]) & set(lab_s[j][:10])) / 10 for j in range(sel.shape[0])]))
+    # scan roofline: distance evaluations = sum over (query, probe) of the probed list's length
+    probes = ix.probe(qd, np_max).cpu().numpy()
+    probes = np.where(np.arange(np_max)[None, :] < npq[:, None], probes, -1)
+    lens = ix.dump()["list_len"].astype(np.int64)
+    evals = int(lens[probes[probes >= 0]].sum())
+    scan_ms = prof["scan"][0] / max(prof["scan"][1], 1)
+    flops = evals * 3.0 * w.dim
+    achieved = flops / (scan_ms * 1e-3) / 1e12
+    sm, gsm = np.sort(np.array(step_ms)), np.sort(np.array(gsteps))
+    se_ms = prof["search"][0] / max(prof["search"][1], 1)
+    res = {
+        "metric": "batched uneven form: queries/s of window steps (per-query nprobe and k), p50/p99 step ms",
+        "value": round(nq * steps / elapsed, 1), "unit": f"queries/s (window step: +{B} insert, {nq}-query "
+                                                         f"search, -{B} random delete)",
+        "n_gpus": 1, "steps": steps, "warmup": warm, "ms_per_step": round(elapsed / steps * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"batched: N={N}, d={w.dim}, Zipf(1.1) over {w.nlist} clusters, nlist={w.nlist}, "
+                               f"slab={C}, {nq} queries, nprobe U[8,128], k in {{1,10,100}}, +{B}/-{B} random",
+                   "parallelism": "single GPU"},
+        "schedule": {"tile": tile, "chunk_positions": 1 << sh},
+        "recall_at_10_k_ge_10": round(rec, 4),
+        "search_qps": round(nq / (se_ms * 1e-3), 1),
+        "p50_step_ms": round(float(np.percentile(sm, 50)), 3), "p99_step_ms": round(float(np.percentile(sm, 99)), 3),
+        "graph_p50_step_ms": round(float(np.percentile(gsm, 50)), 3),
+        "graph_p99_step_ms": round(float(np.percentile(gsm, 99)), 3),
+        "device_ms": {kk: round(v[0] / max(v[1], 1), 4) for kk, v in prof.items()},
+        "list_len": {"min": int(lens.min()), "median": int(np.median(lens)), "max": int(lens.max())},
+        "roofline": {"bound": "alu", "kernel": "k_scan_sq", "achieved": round(achieved, 3),
+                     "peak": round(ALU_PEAK_TFLOPS, 2), "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TFLOPS, 4),
+                     "evals_per_launch": evals, "avg_launch_ms": round(scan_ms, 4)},
+        "bulk_load_vec_per_s": round(N / load_s, 1),
+    }
+    print(json.dumps(res), flush=True)
+
+
 def serve_main(a):
     """Serving form: the steady-state window under an open-loop Poisson
     request stream, every request submitted through the overlapping server
@@ -460,29 +629,10 @@ def serve_main(a):
                          "p99_ms": round(float(np.percentile(v, 99)), 3), "max_ms": round(float(v[-1]), 3),
                          "mean_size": round(float(np.mean([r.n for r in reqs if r.kind == kind])), 1)}
     last_arrival = float(arr[-1]) if len(reqs) else 0.0
-    # recall@10 on the final window for 256 pooled queries: exact top-10
-    # (fp32 candidate scoring over every live row, fp64 re-scoring of the best 32)
+    # recall@10 on the final window for 256 pooled queries
     nrq = 256
     qh = qpool[:nrq]
-    live_ids = np.flatnonzero(live_end).astype(np.int64)
-    q2 = (qh * qh).sum(1, keepdim=True)
-    best_s = torch.full((nrq, 32), float("inf"), device=dev)
-    best_i = torch.full((nrq, 32), -1, dtype=torch.int64, device=dev)
-    for s0 in range(0, live_ids.shape[0], 1 << 21):
-        idc = torch.from_numpy(live_ids[s0:s0 + (1 << 21)]).to(dev)
-        rows = ix.get_rows(idc)
-        sc = q2 + (rows * rows).sum(1)[None, :] - 2.0 * (qh @ rows.T)
-        s_c, o_c = torch.topk(sc, min(32, sc.shape[1]), dim=1, largest=False)
-        cs = torch.cat([best_s, s_c], 1)
-        ci = torch.cat([best_i, idc[o_c]], 1)
-        best_s, o = torch.topk(cs, 32, dim=1, largest=False)
-        best_i = torch.gather(ci, 1, o)
-        del rows, sc
-    cand = best_i.cpu().numpy()
-    rows = ix.get_rows(torch.from_numpy(cand.reshape(-1)).to(dev)).cpu().numpy().astype(np.float64)
-    qd = qh.cpu().numpy().astype(np.float64)
-    d64 = ((rows.reshape(nrq, 32, -1) - qd[:, None, :]) ** 2).sum(2)
-    gt = [cand[j][np.lexsort((cand[j], d64[j]))[:k]] for j in range(nrq)]
+    gt = exact_knn_device(ix, np.flatnonzero(live_end).astype(np.int64), qh, k, w.metric, dev)
     recall = {}
     for npb in (16, 32, 64):
         _, lab = ix.search(qh, k, npb)

@@ -134,9 +134,24 @@ sivf_status sivf_search(sivf_index *ix, int64_t nq, const float *q, int32_t k,
                         const int32_t *nprobe_per_query, float *dist, int64_t *labels,
                         void *stream);
 
+/* Search schedule autotuner (for uneven batches: skewed list lengths,
+ * per-query nprobe and k).  Runs sivf_search on this sample batch once per
+ * candidate schedule -- queries per work item (fp32 storage: 8 and 4; the
+ * reduced-precision scan always takes 16) x positions per work item (2^12
+ * .. 2^17; longer lists are split into chunks scanned in parallel) -- times
+ * each with HIP events and keeps the fastest for every later search of this
+ * index (and graphs captured afterwards).  Results do not depend on the
+ * schedule.  Arguments as sivf_search; dist/labels receive the last run's
+ * results.  Blocks until done.  tile, chunk_shift: host int32 or NULL,
+ * receive the chosen values. */
+sivf_status sivf_tune_search(sivf_index *ix, int64_t nq, const float *q, int32_t k, const int32_t *k_per_query,
+                             int32_t nprobe, const int32_t *nprobe_per_query, float *dist, int64_t *labels,
+                             void *stream, int32_t *tile, int32_t *chunk_shift);
+
 /* One sliding-window step in the order of the paper's mixed loop
  * (Sec. 5.5: insert, then search, then delete).  Any part with a zero count
- * is skipped.  Same argument rules as the three calls. */
+ * is skipped.  Same argument rules as the three calls (k_per_query and
+ * nprobe_per_query as in sivf_search, NULL for uniform values). */
 typedef struct {
     int64_t n_add;
     const float *x;          /* device n_add x dim                  */
@@ -146,6 +161,8 @@ typedef struct {
     int32_t k, nprobe;
     float *dist;             /* device nq x k                       */
     int64_t *labels;         /* device nq x k                       */
+    const int32_t *k_per_query;      /* device nq or NULL           */
+    const int32_t *nprobe_per_query; /* device nq or NULL           */
     int64_t n_remove;
     const int64_t *remove_ids; /* device n_remove                   */
     int64_t *n_removed;      /* device scalar or NULL               */

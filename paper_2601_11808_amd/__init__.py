@@ -39,6 +39,7 @@ class SivfStepArgs(ct.Structure):
     _fields_ = [("n_add", ct.c_int64), ("x", ct.c_void_p), ("add_ids", ct.c_void_p),
                 ("nq", ct.c_int64), ("q", ct.c_void_p), ("k", ct.c_int32), ("nprobe", ct.c_int32),
                 ("dist", ct.c_void_p), ("labels", ct.c_void_p),
+                ("k_per_query", ct.c_void_p), ("nprobe_per_query", ct.c_void_p),
                 ("n_remove", ct.c_int64), ("remove_ids", ct.c_void_p), ("n_removed", ct.c_void_p)]
 
 
@@ -57,6 +58,8 @@ SIGNATURES = [
     ("sivf_add", ct.c_int, [_P, _I64, _P, _P, _P]),
     ("sivf_remove", ct.c_int, [_P, _I64, _P, _P, _P]),
     ("sivf_search", ct.c_int, [_P, _I64, _P, _I32, _P, _I32, _P, _P, _P, _P]),
+    ("sivf_tune_search", ct.c_int, [_P, _I64, _P, _I32, _P, _I32, _P, _P, _P, _P, ct.POINTER(_I32),
+                                    ct.POINTER(_I32)]),
     ("sivf_step", ct.c_int, [_P, ct.POINTER(SivfStepArgs), _P]),
     ("sivf_graph_create", ct.c_int, [_P, ct.POINTER(SivfStepArgs), ct.POINTER(_P)]),
     ("sivf_graph_launch", ct.c_int, [_P, _P]),
@@ -221,7 +224,23 @@ class Index:
         self._keep = [q, kpq, npq]
         return dist, lab
 
-    def step(self, x=None, add_ids=None, q=None, k=10, nprobe=1, remove_ids=None, stream=None, out=None):
+    def tune_search(self, q, k, nprobe=1, k_per_query=None, nprobe_per_query=None, stream=None):
+        """Pick the fastest search schedule for batches like this one; returns
+        (queries per work item, log2 positions per work item)."""
+        torch = _torch()
+        q = _dev_tensor(q, torch.float32, self.device).reshape(-1, self.dim)
+        kpq = None if k_per_query is None else _dev_tensor(k_per_query, torch.int32, self.device)
+        npq = None if nprobe_per_query is None else _dev_tensor(nprobe_per_query, torch.int32, self.device)
+        dist = torch.empty((q.shape[0], k), dtype=torch.float32, device=self.device)
+        lab = torch.empty((q.shape[0], k), dtype=torch.int64, device=self.device)
+        t, sh = ct.c_int32(0), ct.c_int32(0)
+        _check(lib().sivf_tune_search(self._h, q.shape[0], _ptr(q), k, _ptr(kpq), nprobe, _ptr(npq), _ptr(dist),
+                                      _ptr(lab), self._stream(stream), ct.byref(t), ct.byref(sh)),
+               "sivf_tune_search")
+        return t.value, sh.value
+
+    def step(self, x=None, add_ids=None, q=None, k=10, nprobe=1, remove_ids=None, stream=None, out=None,
+             k_per_query=None, nprobe_per_query=None):
         """add -> search -> remove; returns (dist, labels, n_removed)."""
         torch = _torch()
         a = SivfStepArgs()
@@ -242,6 +261,11 @@ class Index:
             a.nq, a.q, a.k, a.nprobe = q.shape[0], q.data_ptr(), k, nprobe
             a.dist, a.labels = dist.data_ptr(), lab.data_ptr()
             keep += [q]
+            for name, v in (("k_per_query", k_per_query), ("nprobe_per_query", nprobe_per_query)):
+                if v is not None:
+                    v = _dev_tensor(v, torch.int32, self.device).reshape(-1)
+                    setattr(a, name, v.data_ptr())
+                    keep.append(v)
         nrem = torch.zeros(1, dtype=torch.int64, device=self.device)
         if remove_ids is not None:
             remove_ids = _dev_tensor(remove_ids, torch.int64, self.device).reshape(-1)
@@ -252,10 +276,12 @@ class Index:
         self._keep = keep
         return dist, lab, nrem
 
-    def step_graph(self, x, add_ids, q, k, nprobe, remove_ids, dist, labels, n_removed):
+    def step_graph(self, x, add_ids, q, k, nprobe, remove_ids, dist, labels, n_removed, k_per_query=None,
+                   nprobe_per_query=None):
         """Capture add -> search -> remove on these device buffers as a graph.
         Refill the buffers in place, then call ``launch()`` on the result."""
-        return StepGraph(self, x, add_ids, q, k, nprobe, remove_ids, dist, labels, n_removed)
+        return StepGraph(self, x, add_ids, q, k, nprobe, remove_ids, dist, labels, n_removed, k_per_query,
+                         nprobe_per_query)
 
     def assign(self, x, stream=None):
         torch = _torch()
@@ -353,16 +379,24 @@ class Index:
 class StepGraph:
     """A window step captured as a HIP graph over fixed device buffers."""
 
-    def __init__(self, index, x, add_ids, q, k, nprobe, remove_ids, dist, labels, n_removed):
-        for t in (x, add_ids, q, remove_ids, dist, labels, n_removed):
+    def __init__(self, index, x, add_ids, q, k, nprobe, remove_ids, dist, labels, n_removed, k_per_query=None,
+                 nprobe_per_query=None):
+        extra = tuple(t for t in (k_per_query, nprobe_per_query) if t is not None)
+        for t in (x, add_ids, q, remove_ids, dist, labels, n_removed) + extra:
             assert t.is_cuda and t.is_contiguous()
         a = SivfStepArgs()
         a.n_add, a.x, a.add_ids = add_ids.shape[0], x.data_ptr(), add_ids.data_ptr()
         a.nq, a.q, a.k, a.nprobe = q.shape[0], q.data_ptr(), k, nprobe
         a.dist, a.labels = dist.data_ptr(), labels.data_ptr()
+        if k_per_query is not None:
+            assert k_per_query.dtype == _torch().int32
+            a.k_per_query = k_per_query.data_ptr()
+        if nprobe_per_query is not None:
+            assert nprobe_per_query.dtype == _torch().int32
+            a.nprobe_per_query = nprobe_per_query.data_ptr()
         a.n_remove, a.remove_ids, a.n_removed = remove_ids.shape[0], remove_ids.data_ptr(), n_removed.data_ptr()
         self.index = index
-        self._bufs = (x, add_ids, q, remove_ids, dist, labels, n_removed)
+        self._bufs = (x, add_ids, q, remove_ids, dist, labels, n_removed) + extra
         h = ct.c_void_p()
         _check(lib().sivf_graph_create(index._h, ct.byref(a), ct.byref(h)), "sivf_graph_create")
         self._h = h

@@ -630,13 +630,16 @@ __global__ __launch_bounds__(256) void k_merge(Dev S, int nq, int np_stride, con
     }
 }
 
-// Queries per tile (the LDS path holds T * ceil(d/4) * 16 bytes, within 32
-// KiB).  Measured on the window workload: T=8 with two dimension chunks in
-// flight beats T=16, whose query operands no longer fit the SGPR file.
-int search_tile(const Dev &S) {
-    if (S.storage != 0) return 16;   // the MFMA scan's tile is one 16-column operand
-    return S.d <= 1024 ? 8 : 4;
+// Default queries per tile (the LDS path holds T * ceil(d/4) * 16 bytes,
+// within 32 KiB).  Measured on the window workload: T=8 with two dimension
+// chunks in flight beats T=16, whose query operands no longer fit the SGPR
+// file.  The MFMA scan's tile is one 16-column operand.
+int default_tile(int storage, int d) {
+    if (storage != 0) return 16;
+    return d <= 1024 ? 8 : 4;
 }
+
+int search_tile(const Dev &S) { return S.tile; }
 
 // ------------------------------------------------ reduced-precision scan
 //
@@ -951,16 +954,12 @@ static void launch_scan_t(hipStream_t st, const Dev &S, const SearchBufs &W, con
                            W.item_chunk, W.list_pairs, q, np_stride, kcap, k, kpq, W.partials);
 }
 
-// Default chunk: 2^14 positions per work item (a list is split only when
-// the plan's buffers allow; longer chunks otherwise).
-constexpr int CHUNK_SHIFT = 14;
-
 void launch_search_plan(hipStream_t st, const Dev &S, const SearchBufs &W, int nq, int np_stride) {
     const int npairs = nq * np_stride;
     const unsigned pb = (unsigned)((npairs + 255) / 256);
     const int T = search_tile(S);
     hipLaunchKernelGGL(k_inv_count, dim3(pb), dim3(256), 0, st, S, npairs, W.probes, W.pair_rank);
-    hipLaunchKernelGGL(k_inv_plan, dim3(1), dim3(1024), 0, st, S, T, CHUNK_SHIFT, W.slot_cap, W.item_cap);
+    hipLaunchKernelGGL(k_inv_plan, dim3(1), dim3(1024), 0, st, S, T, S.chunk_shift, W.slot_cap, W.item_cap);
     hipLaunchKernelGGL(k_inv_items, dim3((S.nlist + 3) / 4), dim3(256), 0, st, S, T, W.item_list, W.item_tile,
                        W.item_chunk);
     hipLaunchKernelGGL(k_inv_scatter, dim3(pb), dim3(256), 0, st, S, npairs, W.probes, W.pair_rank,

@@ -313,6 +313,8 @@ sivf_status sivf_create(const sivf_config *cfg, const float *centroids, void *wo
     S.metric = cfg->metric;
     S.storage = cfg->storage;
     S.dp8 = (cfg->dim + 7) / 8;
+    S.tile = default_tile(cfg->storage, cfg->dim);
+    S.chunk_shift = DEFAULT_CHUNK_SHIFT;
     S.hdata = cfg->storage != SIVF_F32 ? (uint4 *)(w + L.hdata) : nullptr;
     S.xnorm = (cfg->storage != SIVF_F32 && cfg->metric == SIVF_L2) ? (float *)(w + L.xnorm) : nullptr;
     ix->W.rr_dist = cfg->storage != SIVF_F32 ? (float *)(w + L.rr_dist) : nullptr;
@@ -418,11 +420,63 @@ sivf_status sivf_search(sivf_index *ix, int64_t nq, const float *q, int32_t k, c
     return do_search(ix, nq, q, k, k_per_query, nprobe, nprobe_per_query, dist, labels, as_stream(stream));
 }
 
+sivf_status sivf_tune_search(sivf_index *ix, int64_t nq, const float *q, int32_t k, const int32_t *k_per_query,
+                             int32_t nprobe, const int32_t *nprobe_per_query, float *dist, int64_t *labels,
+                             void *stream, int32_t *tile, int32_t *chunk_shift) {
+    if (!ix) return SIVF_ERR_ARG;
+    if (ix->broken) return SIVF_ERR_STATE;
+    hipStream_t st = as_stream(stream);
+    ix->last = st;
+    std::vector<int> tiles;
+    if (ix->cfg.storage != SIVF_F32) tiles = {16};
+    else if (ix->cfg.dim <= 1024) tiles = {8, 4};
+    else tiles = {4};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (!dev_ok(hipEventCreate(&e0)) || !dev_ok(hipEventCreate(&e1))) {
+        if (e0) (void)hipEventDestroy(e0);
+        return SIVF_ERR_DEVICE;
+    }
+    const bool prof = ix->prof;
+    ix->prof = false;
+    int bt = ix->S.tile, bs = ix->S.chunk_shift;
+    float best = -1.f;
+    sivf_status s = SIVF_OK;
+    for (int T : tiles) {
+        for (int sh = 12; sh <= 17 && s == SIVF_OK; sh++) {
+            ix->S.tile = T;
+            ix->S.chunk_shift = sh;
+            s = do_search(ix, nq, q, k, k_per_query, nprobe, nprobe_per_query, dist, labels, st);   // warm-up
+            if (s != SIVF_OK) break;
+            if (!dev_ok(hipEventRecord(e0, st))) s = SIVF_ERR_DEVICE;
+            for (int r = 0; r < 2 && s == SIVF_OK; r++)
+                s = do_search(ix, nq, q, k, k_per_query, nprobe, nprobe_per_query, dist, labels, st);
+            float ms = 0.f;
+            if (s == SIVF_OK && (!dev_ok(hipEventRecord(e1, st)) || !dev_ok(hipEventSynchronize(e1)) ||
+                                 !dev_ok(hipEventElapsedTime(&ms, e0, e1))))
+                s = SIVF_ERR_DEVICE;
+            if (s == SIVF_OK && (best < 0.f || ms < best)) {
+                best = ms;
+                bt = T;
+                bs = sh;
+            }
+        }
+    }
+    ix->S.tile = bt;
+    ix->S.chunk_shift = bs;
+    ix->prof = prof;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (tile) *tile = bt;
+    if (chunk_shift) *chunk_shift = bs;
+    return s;
+}
+
 static bool step_args_ok(const sivf_index *ix, const sivf_step_args *a) {
     const sivf_config &c = ix->cfg;
     if (a->n_add < 0 || a->n_add > c.max_batch || a->n_remove < 0 || a->n_remove > c.max_batch) return false;
     if (a->nq < 0 || a->nq > c.max_queries) return false;
-    if (a->nq > 0 && (a->k < 1 || a->k > c.max_k || a->nprobe < 1 || a->nprobe > c.max_nprobe)) return false;
+    if (a->nq > 0 && (a->k < 1 || a->k > c.max_k)) return false;
+    if (a->nq > 0 && !a->nprobe_per_query && (a->nprobe < 1 || a->nprobe > c.max_nprobe)) return false;
     return true;
 }
 
@@ -430,7 +484,8 @@ static sivf_status enqueue_step(sivf_index *ix, const sivf_step_args *a, hipStre
     sivf_status s = do_add(ix, a->n_add, a->x, a->add_ids, st);
     if (s != SIVF_OK) return s;
     if (a->nq > 0) {
-        s = do_search(ix, a->nq, a->q, a->k, nullptr, a->nprobe, nullptr, a->dist, a->labels, st);
+        s = do_search(ix, a->nq, a->q, a->k, a->k_per_query, a->nprobe, a->nprobe_per_query, a->dist, a->labels,
+                      st);
         if (s != SIVF_OK) return s;
     }
     return do_remove(ix, a->n_remove, a->remove_ids, a->n_removed, st);

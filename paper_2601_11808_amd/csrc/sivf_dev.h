@@ -42,6 +42,8 @@ struct Dev {
     int d, dp4, nlist, C, metric;
     int storage;          // 0 = fp32 slabs; 1 = bf16, 2 = fp16 slabs with the fp32 pool as shadow
     int dp8;              // ceil(d / 8): 16-byte chunks of a reduced-precision row
+    int tile;             // search schedule: queries per work item (fp32 scan: 4 or 8; MFMA scan: 16)
+    int chunk_shift;      // search schedule: a work item covers at most 2^chunk_shift list positions
     int64_t num_slabs, num_pages, dir_cap, id_capacity;
     const float *cent;    // [nlist][dp4*4], zero padded
     const float *cn2;     // [nlist] fp32 squared norms

@@ -56,6 +56,10 @@ struct SearchBufs {
     int64_t *rr_lab;
 };
 int search_tile(const Dev &S);
+int default_tile(int storage, int d);
+// Default search chunk: 2^14 positions per work item (a list is split only
+// when the plan's buffers allow; into longer chunks otherwise).
+constexpr int DEFAULT_CHUNK_SHIFT = 14;
 void launch_search_plan(hipStream_t st, const Dev &S, const SearchBufs &W, int nq, int np_stride);
 void launch_search_scan(hipStream_t st, const Dev &S, const SearchBufs &W, int nq, const float *q, int np_stride,
                         int kcap, int k, const int32_t *k_per_query);

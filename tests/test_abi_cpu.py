@@ -39,7 +39,7 @@ def test_every_declared_symbol_is_exported(lib):
 def test_struct_layouts_match_header():
     # sizes follow from the field lists in include/sivf.h (natural alignment)
     assert ct.sizeof(sivf.SivfConfig) == 6 * 4 + 2 * 8 + 4 * 4
-    assert ct.sizeof(sivf.SivfStepArgs) == 8 + 8 + 8 + 8 + 8 + 4 + 4 + 8 + 8 + 8 + 8 + 8
+    assert ct.sizeof(sivf.SivfStepArgs) == 8 + 8 + 8 + 8 + 8 + 4 + 4 + 8 + 8 + 8 + 8 + 8 + 8 + 8
     assert ct.sizeof(sivf.SivfDumpInfo) == 5 * 8 + 2 * 4
 
 

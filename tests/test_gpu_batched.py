@@ -40,7 +40,7 @@ def test_split_lists_wide_k_per_query(metric, max_queries):
     cent, x, ids, q = _skewed([5, metric], d, sizes)
     q = q[:nq]
     ix = sivf.Index(d, len(sizes), cent, metric=metric, slab_capacity=C, num_slabs=1800, id_capacity=x.shape[0],
-                    max_batch=1 << 16, max_queries=max_queries, max_k=128, max_nprobe=nprobe)
+                    max_batch=1 << 17, max_queries=max_queries, max_k=128, max_nprobe=nprobe)
     ref = oracle.OracleIndex(d, len(sizes), cent, metric, C, 1800, x.shape[0])
     ix.add(x, ids)
     assert ix.sync() == 0
@@ -66,6 +66,14 @@ def test_split_lists_wide_k_per_query(metric, max_queries):
         say(f"  k={k} per-query={'yes' if kp is not None else 'no'}: ids identical, {nd} distances differ in "
             f"some bit; slots at 2^14-position chunks {slots14} vs capacity {cap} "
             f"({'longer chunks' if slots14 > cap else 'split'})")
+    # the autotuner changes only the schedule: results stay identical
+    t, sh = ix.tune_search(q, 128, nprobe, k_per_query=kpq, nprobe_per_query=npq)
+    assert ix.sync() == 0
+    say(f"  tuned schedule: {t} queries x 2^{sh} positions per work item")
+    gd, gl = ix.search(q, 128, nprobe, k_per_query=kpq, nprobe_per_query=npq)
+    assert ix.sync() == 0
+    st, rd, rl = ref.search(q, 128, nprobe, k_per_query=kpq, nprobe_per_query=npq)
+    compare_results(gd.cpu().numpy(), gl.cpu().numpy(), rd, rl)
     # a window step on the split lists, then search again
     rm = ids[::3]
     nr = ix.remove(rm)

@@ -207,7 +207,13 @@ def device_sample(w, n, tag, device, means=None):
     g.manual_seed(w.seed * 1_000_003 + tag)
     if means is None:
         means = torch.from_numpy(w.means).to(device)
-    comp = torch.randint(0, w.means.shape[0], (n,), generator=g, device=device)
+    if np.allclose(w.weights, w.weights[0]):
+        comp = torch.randint(0, w.means.shape[0], (n,), generator=g, device=device)
+    else:   # skewed cluster weights (the batched form's Zipf mixture)
+        wt = torch.from_numpy(w.weights).to(device=device, dtype=torch.float64)
+        comp = torch.cat([torch.multinomial(wt, min(1 << 22, n - s), replacement=True, generator=g)
+                          for s in range(0, n, 1 << 22)]) if n > 0 else torch.zeros(0, dtype=torch.int64,
+                                                                                        device=device)
     x = torch.randn((n, w.dim), generator=g, device=device, dtype=torch.float32)
     x.mul_(w.sigma).add_(means[comp])
     return x
