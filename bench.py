@@ -415,8 +415,9 @@ def batched_main(a):
     kpq_d = torch.from_numpy(kpq).to(dev)
     npq_d = torch.from_numpy(npq).to(dev)
     t0 = time.perf_counter()
-    tile, sh = ix.tune_search(qd, kmax, int(npq.max()), k_per_query=kpq_d, nprobe_per_query=npq_d)
-    log(f"[batched] autotuner: {tile} queries x 2^{sh} positions per work item ({time.perf_counter() - t0:.1f} s)")
+    tile, sh, pers = ix.tune_search(qd, kmax, int(npq.max()), k_per_query=kpq_d, nprobe_per_query=npq_d)
+    log(f"[batched] autotuner: {tile} queries x 2^{sh} positions per work item, persistent={pers} "
+        f"({time.perf_counter() - t0:.1f} s)")
     # per step: B fresh vectors in, B uniformly random live ids out
     rng = np.random.default_rng([w.seed, 3, 1])
     live = np.arange(N, dtype=np.int64)
@@ -496,7 +497,7 @@ def batched_main(a):
         "config": {"workload": f"batched: N={N}, d={w.dim}, Zipf(1.1) over {w.nlist} clusters, nlist={w.nlist}, "
                                f"slab={C}, {nq} queries, nprobe U[8,128], k in {{1,10,100}}, +{B}/-{B} random",
                    "parallelism": "single GPU"},
-        "schedule": {"tile": tile, "chunk_positions": 1 << sh},
+        "schedule": {"tile": tile, "chunk_positions": 1 << sh, "persistent_waves": bool(pers)},
         "recall_at_10_k_ge_10": round(rec, 4),
         "search_qps": round(nq / (se_ms * 1e-3), 1),
         "p50_step_ms": round(float(np.percentile(sm, 50)), 3), "p99_step_ms": round(float(np.percentile(sm, 99)), 3),

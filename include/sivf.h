@@ -138,15 +138,16 @@ sivf_status sivf_search(sivf_index *ix, int64_t nq, const float *q, int32_t k,
  * per-query nprobe and k).  Runs sivf_search on this sample batch once per
  * candidate schedule -- queries per work item (fp32 storage: 8 and 4; the
  * reduced-precision scan always takes 16) x positions per work item (2^12
- * .. 2^17; longer lists are split into chunks scanned in parallel) -- times
- * each with HIP events and keeps the fastest for every later search of this
- * index (and graphs captured afterwards).  Results do not depend on the
- * schedule.  Arguments as sivf_search; dist/labels receive the last run's
- * results.  Blocks until done.  tile, chunk_shift: host int32 or NULL,
- * receive the chosen values. */
+ * .. 2^17; longer lists are split into chunks scanned in parallel) x wave
+ * schedule (one wave per work item, or resident waves pulling items from
+ * per-XCD counters) -- times each with HIP events and keeps the fastest for
+ * every later search of this index (and graphs captured afterwards).
+ * Results do not depend on the schedule.  Arguments as sivf_search;
+ * dist/labels receive the last run's results.  Blocks until done.  tile,
+ * chunk_shift, persistent: host int32 or NULL, receive the chosen values. */
 sivf_status sivf_tune_search(sivf_index *ix, int64_t nq, const float *q, int32_t k, const int32_t *k_per_query,
                              int32_t nprobe, const int32_t *nprobe_per_query, float *dist, int64_t *labels,
-                             void *stream, int32_t *tile, int32_t *chunk_shift);
+                             void *stream, int32_t *tile, int32_t *chunk_shift, int32_t *persistent);
 
 /* One sliding-window step in the order of the paper's mixed loop
  * (Sec. 5.5: insert, then search, then delete).  Any part with a zero count
@@ -203,7 +204,7 @@ sivf_status sivf_probe(sivf_index *ix, int64_t nq, const float *q, int32_t nprob
 sivf_status sivf_coarse_scores(sivf_index *ix, int64_t n, const float *x, float *scores, void *stream);
 
 /* Stored vectors of ids.  ids: device n int64; rows: device n x dim fp32.
- * Rows of absent or out-of-range ids are filled with NaN.  n <= max_batch. */
+ * Rows of absent or out-of-range ids are filled with NaN.  n <= 2^26. */
 sivf_status sivf_get_rows(sivf_index *ix, int64_t n, const int64_t *ids, float *rows, void *stream);
 
 /* Wait for all work enqueued on the handle's streams; *device_status (may be

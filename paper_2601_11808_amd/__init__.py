@@ -59,7 +59,7 @@ SIGNATURES = [
     ("sivf_remove", ct.c_int, [_P, _I64, _P, _P, _P]),
     ("sivf_search", ct.c_int, [_P, _I64, _P, _I32, _P, _I32, _P, _P, _P, _P]),
     ("sivf_tune_search", ct.c_int, [_P, _I64, _P, _I32, _P, _I32, _P, _P, _P, _P, ct.POINTER(_I32),
-                                    ct.POINTER(_I32)]),
+                                    ct.POINTER(_I32), ct.POINTER(_I32)]),
     ("sivf_step", ct.c_int, [_P, ct.POINTER(SivfStepArgs), _P]),
     ("sivf_graph_create", ct.c_int, [_P, ct.POINTER(SivfStepArgs), ct.POINTER(_P)]),
     ("sivf_graph_launch", ct.c_int, [_P, _P]),
@@ -226,18 +226,18 @@ class Index:
 
     def tune_search(self, q, k, nprobe=1, k_per_query=None, nprobe_per_query=None, stream=None):
         """Pick the fastest search schedule for batches like this one; returns
-        (queries per work item, log2 positions per work item)."""
+        (queries per work item, log2 positions per work item, persistent waves)."""
         torch = _torch()
         q = _dev_tensor(q, torch.float32, self.device).reshape(-1, self.dim)
         kpq = None if k_per_query is None else _dev_tensor(k_per_query, torch.int32, self.device)
         npq = None if nprobe_per_query is None else _dev_tensor(nprobe_per_query, torch.int32, self.device)
         dist = torch.empty((q.shape[0], k), dtype=torch.float32, device=self.device)
         lab = torch.empty((q.shape[0], k), dtype=torch.int64, device=self.device)
-        t, sh = ct.c_int32(0), ct.c_int32(0)
+        t, sh, pm = ct.c_int32(0), ct.c_int32(0), ct.c_int32(0)
         _check(lib().sivf_tune_search(self._h, q.shape[0], _ptr(q), k, _ptr(kpq), nprobe, _ptr(npq), _ptr(dist),
-                                      _ptr(lab), self._stream(stream), ct.byref(t), ct.byref(sh)),
+                                      _ptr(lab), self._stream(stream), ct.byref(t), ct.byref(sh), ct.byref(pm)),
                "sivf_tune_search")
-        return t.value, sh.value
+        return t.value, sh.value, pm.value
 
     def step(self, x=None, add_ids=None, q=None, k=10, nprobe=1, remove_ids=None, stream=None, out=None,
              k_per_query=None, nprobe_per_query=None):

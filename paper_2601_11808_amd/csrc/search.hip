@@ -118,7 +118,7 @@ __global__ __launch_bounds__(1024) void k_inv_plan(Dev S, int T, int sh0, int64_
         S.ctl[CTL_NITEMS] = carry_i;
         S.ctl[CTL_CHUNK] = sh;
     }
-    if (threadIdx.x < 8) S.ctl[CTL_WORK0 + threadIdx.x] = 0;
+    if (threadIdx.x < 8) S.ctl[CTL_WORK0 + CTL_WORK_STRIDE * threadIdx.x] = 0;
 }
 
 // Work items of each list, chunk-major (consecutive items read the same
@@ -344,22 +344,32 @@ __device__ __forceinline__ uint32_t key_hi(float v) {
     return METRIC == 0 ? (__float_as_uint(v) | 0x80000000u) : ~ord_bits(v);
 }
 
-// Persistent scan: a fixed grid of waves pulls work items until none are
-// left.  The items are cut into 8 contiguous ranges, one per XCD (blocks are
-// dealt to the XCDs round robin); a wave takes items from its own XCD's range
-// first -- consecutive items share a list, so its slabs stay in that XCD's
-// L2 -- and then helps the other ranges.  Every wave ends once all 8
-// counters have passed their range.
+// Work items are cut into 8 contiguous ranges, one per XCD (blocks are
+// dealt to the XCDs round robin): consecutive items share a list, so its
+// slabs stay in that XCD's L2.  Two schedules:
+//  - dispatch (persistent = 0): one wave per item; block b takes item
+//    (b mod 8) * ceil(items / 8) + b / 8, and the grid is the host's upper
+//    bound on the item count (surplus waves exit at once);
+//  - persistent (1): a grid of resident waves pulls items from its XCD's
+//    counter, then helps the other ranges; every wave ends once all 8
+//    counters have passed their range.
 #define SIVF_ITEM_LOOP_BEGIN                                                                     \
     const int nitems = S.ctl[CTL_NITEMS];                                                        \
     const int per = (nitems + 7) >> 3;                                                           \
-    for (int xs = 0; xs < 8; xs++) {                                                             \
+    const int nrange = persistent ? 8 : 1;                                                       \
+    for (int xs = 0; xs < nrange; xs++) {                                                        \
         const int xx = (int)((blockIdx.x + xs) & 7);                                             \
         const int lo = xx * per, hi = min(nitems, lo + per);                                     \
-        for (;;) {                                                                               \
-            int item = 0;                                                                        \
-            if (threadIdx.x == 0) item = atomicAdd(&S.ctl[CTL_WORK0 + xx], 1);                   \
-            item = __builtin_amdgcn_readfirstlane(item) + lo; /* uniform: scalar addressing */   \
+        for (int it = 0;; it++) {                                                                \
+            int item;                                                                            \
+            if (persistent) {                                                                    \
+                item = 0;                                                                        \
+                if (threadIdx.x == 0) item = atomicAdd(&S.ctl[CTL_WORK0 + CTL_WORK_STRIDE * xx], 1); \
+                item = __builtin_amdgcn_readfirstlane(item) + lo; /* uniform: scalar addressing */ \
+            } else {                                                                             \
+                if (it > 0) break;                                                               \
+                item = lo + (int)(blockIdx.x >> 3);                                              \
+            }                                                                                    \
             if (item >= hi) break;
 #define SIVF_ITEM_LOOP_END \
         }                  \
@@ -448,7 +458,8 @@ __global__ __launch_bounds__(64) void k_scan_sq(Dev S, const int32_t *__restrict
                                                 const int32_t *__restrict__ item_chunk,
                                                 const int32_t *__restrict__ list_pairs,
                                                 const float *__restrict__ q, int np_stride, int kcap, int k,
-                                                const int32_t *__restrict__ kpq, uint64_t *__restrict__ partials) {
+                                                const int32_t *__restrict__ kpq, uint64_t *__restrict__ partials,
+                                                int persistent) {
     __shared__ uint64_t buf[T * 64];
     __shared__ int skq[T];
     const int lane = threadIdx.x;
@@ -479,7 +490,7 @@ __global__ __launch_bounds__(64) void k_scan(Dev S, const int32_t *__restrict__ 
                                              const int32_t *__restrict__ item_chunk,
                                              const int32_t *__restrict__ list_pairs, const float *__restrict__ q,
                                              int np_stride, int kcap, int k, const int32_t *__restrict__ kpq,
-                                             uint64_t *__restrict__ partials) {
+                                             uint64_t *__restrict__ partials, int persistent) {
     extern __shared__ float4 sq[];   // [T][dp4]
     __shared__ uint64_t buf[T * 64];
     __shared__ int skq[T];
@@ -695,7 +706,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
                                                   const int32_t *__restrict__ list_pairs,
                                                   const float *__restrict__ q, int np_stride, int kcap, int k,
                                                   int kmul, const int32_t *__restrict__ kpq,
-                                                  uint64_t *__restrict__ partials) {
+                                                  uint64_t *__restrict__ partials, int persistent) {
     __shared__ uint64_t buf[MQ * MBUF];
     __shared__ int scnt[MQ], skq[MQ];
     const int lane = threadIdx.x, qcol = lane & 15, kgrp = lane >> 4;
@@ -894,22 +905,49 @@ __global__ __launch_bounds__(256) void k_rerank(Dev S, int nq, const float *__re
     }
 }
 
-// Waves of the persistent scans: 32 per CU on 256 CUs (more than can be
-// resident; the surplus finds the counters exhausted and exits).
-constexpr unsigned SCAN_WAVES = 256 * 32;
+// Upper bound on a call's work items, which sizes the dispatch grid: twice
+// the unsplit count (tiles of T pairs per list); the plan lengthens chunks
+// until the items fit.
+static int64_t item_limit(const Dev &S, const SearchBufs &W, int npairs) {
+    const int T = search_tile(S);
+    const int64_t unsplit = (npairs + T - 1) / T + (npairs < S.nlist ? npairs : S.nlist);
+    const int64_t lim = 2 * unsplit;
+    return lim < W.item_cap ? lim : W.item_cap;
+}
 
-static unsigned scan_grid(const SearchBufs &W) {
-    return (unsigned)(W.item_cap < (int64_t)SCAN_WAVES ? (W.item_cap < 1 ? 1 : W.item_cap) : SCAN_WAVES);
+// Grid of a scan launch: the item bound (dispatch) or the waves that fit on
+// the chip at the kernel's occupancy (persistent).
+// (Dispatch: block b takes item (b mod 8) * ceil(n / 8) + b / 8, so the grid
+// is the bound rounded up to a multiple of 8, which covers every item.)
+template <typename K>
+static unsigned scan_grid(K kernel, const Dev &S, const SearchBufs &W, int npairs, size_t smem) {
+    if (!S.persistent) {
+        const int64_t g = (item_limit(S, W, npairs) + 7) / 8 * 8;
+        return (unsigned)(g < 8 ? 8 : g);
+    }
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 64, smem) != hipSuccess || per_cu < 1)
+        per_cu = 8;
+    static int cus = 0;   // compute units of the first device used (all GPUs of a node are one part)
+    if (cus == 0) {
+        int dev = 0, n = 0;
+        cus = (hipGetDevice(&dev) == hipSuccess &&
+               hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+                  ? n
+                  : 256;
+    }
+    return (unsigned)(per_cu * cus);
 }
 
 void launch_search_scan_mfma(hipStream_t st, const Dev &S, const SearchBufs &W, int nq, const float *q,
                              int np_stride, int kcap, int k, int kmul, const int32_t *k_per_query) {
-    const unsigned grid = scan_grid(W);
+    const int npairs = nq * np_stride;
     // k-blocks of 32 dimensions held as B operands: 2, 3, 4 or 8 (d <= 256)
     const int nkb = (S.d + 31) / 32;
 #define SIVF_LAUNCH_MFMA(M, D, K)                                                                            \
-    hipLaunchKernelGGL((k_scan_mfma<M, D, K>), dim3(grid), dim3(64), 0, st, S, W.item_list, W.item_tile,     \
-                       W.item_chunk, W.list_pairs, q, np_stride, kcap, k, kmul, k_per_query, W.partials)
+    hipLaunchKernelGGL((k_scan_mfma<M, D, K>), dim3(scan_grid(k_scan_mfma<M, D, K>, S, W, npairs, 0)), dim3(64), \
+                       0, st, S, W.item_list, W.item_tile, W.item_chunk, W.list_pairs, q, np_stride, kcap, k, kmul, \
+                       k_per_query, W.partials, S.persistent)
 #define SIVF_LAUNCH_MFMA_K(M, D)                                                                             \
     do {                                                                                                     \
         if (nkb <= 2) SIVF_LAUNCH_MFMA(M, D, 2);                                                             \
@@ -933,25 +971,21 @@ void launch_rerank(hipStream_t st, const Dev &S, int nq, const float *q, int kc,
 
 template <int T, bool WIDE>
 static void launch_scan_t(hipStream_t st, const Dev &S, const SearchBufs &W, const float *q, int np_stride,
-                          int kcap, int k, const int32_t *kpq) {
-    const unsigned grid = scan_grid(W);
+                          int kcap, int k, const int32_t *kpq, int npairs) {
     const bool sq = (S.d % 4 == 0) && (((uintptr_t)q & 15) == 0);
+#define SIVF_LAUNCH_SCAN(KERN, SMEM)                                                                         \
+    hipLaunchKernelGGL(KERN, dim3(scan_grid(KERN, S, W, npairs, SMEM)), dim3(64), SMEM, st, S, W.item_list,   \
+                       W.item_tile, W.item_chunk, W.list_pairs, q, np_stride, kcap, k, kpq, W.partials,       \
+                       S.persistent)
     if (sq) {
-        if (S.metric == 0)
-            hipLaunchKernelGGL((k_scan_sq<T, 0, WIDE>), dim3(grid), dim3(64), 0, st, S, W.item_list, W.item_tile,
-                               W.item_chunk, W.list_pairs, q, np_stride, kcap, k, kpq, W.partials);
-        else
-            hipLaunchKernelGGL((k_scan_sq<T, 1, WIDE>), dim3(grid), dim3(64), 0, st, S, W.item_list, W.item_tile,
-                               W.item_chunk, W.list_pairs, q, np_stride, kcap, k, kpq, W.partials);
+        if (S.metric == 0) SIVF_LAUNCH_SCAN((k_scan_sq<T, 0, WIDE>), 0);
+        else SIVF_LAUNCH_SCAN((k_scan_sq<T, 1, WIDE>), 0);
         return;
     }
     const size_t smem = (size_t)T * S.dp4 * sizeof(float4);
-    if (S.metric == 0)
-        hipLaunchKernelGGL((k_scan<T, 0, WIDE>), dim3(grid), dim3(64), smem, st, S, W.item_list, W.item_tile,
-                           W.item_chunk, W.list_pairs, q, np_stride, kcap, k, kpq, W.partials);
-    else
-        hipLaunchKernelGGL((k_scan<T, 1, WIDE>), dim3(grid), dim3(64), smem, st, S, W.item_list, W.item_tile,
-                           W.item_chunk, W.list_pairs, q, np_stride, kcap, k, kpq, W.partials);
+    if (S.metric == 0) SIVF_LAUNCH_SCAN((k_scan<T, 0, WIDE>), smem);
+    else SIVF_LAUNCH_SCAN((k_scan<T, 1, WIDE>), smem);
+#undef SIVF_LAUNCH_SCAN
 }
 
 void launch_search_plan(hipStream_t st, const Dev &S, const SearchBufs &W, int nq, int np_stride) {
@@ -959,7 +993,8 @@ void launch_search_plan(hipStream_t st, const Dev &S, const SearchBufs &W, int n
     const unsigned pb = (unsigned)((npairs + 255) / 256);
     const int T = search_tile(S);
     hipLaunchKernelGGL(k_inv_count, dim3(pb), dim3(256), 0, st, S, npairs, W.probes, W.pair_rank);
-    hipLaunchKernelGGL(k_inv_plan, dim3(1), dim3(1024), 0, st, S, T, S.chunk_shift, W.slot_cap, W.item_cap);
+    hipLaunchKernelGGL(k_inv_plan, dim3(1), dim3(1024), 0, st, S, T, S.chunk_shift, W.slot_cap,
+                       item_limit(S, W, npairs));
     hipLaunchKernelGGL(k_inv_items, dim3((S.nlist + 3) / 4), dim3(256), 0, st, S, T, W.item_list, W.item_tile,
                        W.item_chunk);
     hipLaunchKernelGGL(k_inv_scatter, dim3(pb), dim3(256), 0, st, S, npairs, W.probes, W.pair_rank,
@@ -969,12 +1004,13 @@ void launch_search_plan(hipStream_t st, const Dev &S, const SearchBufs &W, int n
 void launch_search_scan(hipStream_t st, const Dev &S, const SearchBufs &W, int nq, const float *q, int np_stride,
                         int kcap, int k, const int32_t *k_per_query) {
     const int T = search_tile(S);
+    const int npairs = nq * np_stride;
     if (kcap > 64) {
-        if (T == 8) launch_scan_t<8, true>(st, S, W, q, np_stride, kcap, k, k_per_query);
-        else launch_scan_t<4, true>(st, S, W, q, np_stride, kcap, k, k_per_query);
+        if (T == 8) launch_scan_t<8, true>(st, S, W, q, np_stride, kcap, k, k_per_query, npairs);
+        else launch_scan_t<4, true>(st, S, W, q, np_stride, kcap, k, k_per_query, npairs);
     } else {
-        if (T == 8) launch_scan_t<8, false>(st, S, W, q, np_stride, kcap, k, k_per_query);
-        else launch_scan_t<4, false>(st, S, W, q, np_stride, kcap, k, k_per_query);
+        if (T == 8) launch_scan_t<8, false>(st, S, W, q, np_stride, kcap, k, k_per_query, npairs);
+        else launch_scan_t<4, false>(st, S, W, q, np_stride, kcap, k, k_per_query, npairs);
     }
 }
 

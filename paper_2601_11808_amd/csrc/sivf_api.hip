@@ -315,6 +315,7 @@ sivf_status sivf_create(const sivf_config *cfg, const float *centroids, void *wo
     S.dp8 = (cfg->dim + 7) / 8;
     S.tile = default_tile(cfg->storage, cfg->dim);
     S.chunk_shift = DEFAULT_CHUNK_SHIFT;
+    S.persistent = 0;
     S.hdata = cfg->storage != SIVF_F32 ? (uint4 *)(w + L.hdata) : nullptr;
     S.xnorm = (cfg->storage != SIVF_F32 && cfg->metric == SIVF_L2) ? (float *)(w + L.xnorm) : nullptr;
     ix->W.rr_dist = cfg->storage != SIVF_F32 ? (float *)(w + L.rr_dist) : nullptr;
@@ -422,7 +423,7 @@ sivf_status sivf_search(sivf_index *ix, int64_t nq, const float *q, int32_t k, c
 
 sivf_status sivf_tune_search(sivf_index *ix, int64_t nq, const float *q, int32_t k, const int32_t *k_per_query,
                              int32_t nprobe, const int32_t *nprobe_per_query, float *dist, int64_t *labels,
-                             void *stream, int32_t *tile, int32_t *chunk_shift) {
+                             void *stream, int32_t *tile, int32_t *chunk_shift, int32_t *persistent) {
     if (!ix) return SIVF_ERR_ARG;
     if (ix->broken) return SIVF_ERR_STATE;
     hipStream_t st = as_stream(stream);
@@ -438,13 +439,15 @@ sivf_status sivf_tune_search(sivf_index *ix, int64_t nq, const float *q, int32_t
     }
     const bool prof = ix->prof;
     ix->prof = false;
-    int bt = ix->S.tile, bs = ix->S.chunk_shift;
+    int bt = ix->S.tile, bs = ix->S.chunk_shift, bp = ix->S.persistent;
     float best = -1.f;
     sivf_status s = SIVF_OK;
+    for (int pm = 0; pm < 2; pm++)
     for (int T : tiles) {
         for (int sh = 12; sh <= 17 && s == SIVF_OK; sh++) {
             ix->S.tile = T;
             ix->S.chunk_shift = sh;
+            ix->S.persistent = pm;
             s = do_search(ix, nq, q, k, k_per_query, nprobe, nprobe_per_query, dist, labels, st);   // warm-up
             if (s != SIVF_OK) break;
             if (!dev_ok(hipEventRecord(e0, st))) s = SIVF_ERR_DEVICE;
@@ -458,16 +461,19 @@ sivf_status sivf_tune_search(sivf_index *ix, int64_t nq, const float *q, int32_t
                 best = ms;
                 bt = T;
                 bs = sh;
+                bp = pm;
             }
         }
     }
     ix->S.tile = bt;
     ix->S.chunk_shift = bs;
+    ix->S.persistent = bp;
     ix->prof = prof;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (tile) *tile = bt;
     if (chunk_shift) *chunk_shift = bs;
+    if (persistent) *persistent = bp;
     return s;
 }
 
@@ -597,7 +603,7 @@ sivf_status sivf_coarse_scores(sivf_index *ix, int64_t n, const float *x, float 
 }
 
 sivf_status sivf_get_rows(sivf_index *ix, int64_t n, const int64_t *ids, float *rows, void *stream) {
-    if (!ix || n < 0 || n > ix->cfg.max_batch || (n > 0 && (!ids || !rows))) return SIVF_ERR_ARG;
+    if (!ix || n < 0 || n > (1 << 26) || (n > 0 && (!ids || !rows))) return SIVF_ERR_ARG;   // no scratch used
     if (ix->broken) return SIVF_ERR_STATE;
     ix->last = as_stream(stream);
     if (n == 0) return SIVF_OK;

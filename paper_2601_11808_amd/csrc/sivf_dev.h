@@ -34,8 +34,9 @@ enum Ctl {
     CTL_NITEMS = 5,     // search: work items of the current call
     CTL_SEQ = 6,        // sequence number of the current add/remove call; its last kernel bumps it
     CTL_CHUNK = 7,      // search: log2 of the positions per work item (a list's chunk)
-    CTL_WORK0 = 8,      // search: 8 work counters, one per XCD range of items (words 8..15)
-    CTL_WORDS = 64
+    CTL_WORK0 = 64,     // search, persistent schedule: 8 work counters, one per XCD range of items,
+    CTL_WORK_STRIDE = 32,  // each on its own 128-byte line (words 64, 96, .., 288)
+    CTL_WORDS = 320
 };
 
 struct Dev {
@@ -44,6 +45,7 @@ struct Dev {
     int dp8;              // ceil(d / 8): 16-byte chunks of a reduced-precision row
     int tile;             // search schedule: queries per work item (fp32 scan: 4 or 8; MFMA scan: 16)
     int chunk_shift;      // search schedule: a work item covers at most 2^chunk_shift list positions
+    int persistent;       // search schedule: 0 = one wave per work item; 1 = resident waves pull items
     int64_t num_slabs, num_pages, dir_cap, id_capacity;
     const float *cent;    // [nlist][dp4*4], zero padded
     const float *cn2;     // [nlist] fp32 squared norms

@@ -67,9 +67,9 @@ def test_split_lists_wide_k_per_query(metric, max_queries):
             f"some bit; slots at 2^14-position chunks {slots14} vs capacity {cap} "
             f"({'longer chunks' if slots14 > cap else 'split'})")
     # the autotuner changes only the schedule: results stay identical
-    t, sh = ix.tune_search(q, 128, nprobe, k_per_query=kpq, nprobe_per_query=npq)
+    t, sh, pm = ix.tune_search(q, 128, nprobe, k_per_query=kpq, nprobe_per_query=npq)
     assert ix.sync() == 0
-    say(f"  tuned schedule: {t} queries x 2^{sh} positions per work item")
+    say(f"  tuned schedule: {t} queries x 2^{sh} positions per work item, persistent={pm}")
     gd, gl = ix.search(q, 128, nprobe, k_per_query=kpq, nprobe_per_query=npq)
     assert ix.sync() == 0
     st, rd, rl = ref.search(q, 128, nprobe, k_per_query=kpq, nprobe_per_query=npq)
