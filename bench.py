@@ -198,6 +198,10 @@ def main():
     qd = torch.from_numpy(q).to(dev)
     dist = torch.empty((nq, k), dtype=torch.float32, device=dev)
     lab = torch.empty((nq, k), dtype=torch.int64, device=dev)
+    t0 = time.perf_counter()
+    tile, sh, pers = ix.tune_search(qd, k, nprobe)   # search schedule for this batch shape (untimed)
+    log(f"[bench] autotuner: {tile} queries x 2^{sh} positions per work item, persistent={pers} "
+        f"({time.perf_counter() - t0:.1f} s)")
     torch.cuda.synchronize()
     for t in range(a.warmup):
         ix.step(bx[t], bi[t], qd, k, nprobe, bo[t], out=(dist, lab))
@@ -324,6 +328,7 @@ def main():
                                f"{'L2' if w.metric == 0 else 'IP'}, storage={storage}"
                                + (f", re-rank top {rerank * k}" if rerank else ""),
                    "global_batch": nq, "parallelism": "single GPU"},
+        "schedule": {"tile": tile, "chunk_positions": 1 << sh, "persistent_waves": bool(pers)},
         "recall_at_10": recall,
         "qps_at_recall95": best95,
         "nprobe_sweep": sweep,
@@ -574,6 +579,8 @@ def serve_main(a):
             plan.append((qpool[o:o + r.n],))
     torch.cuda.synchronize()
 
+    ix.profile_read()
+    ix.profile(True)
     srv = sivf.Server(ix)
     queues = {"search": [], "mut": []}      # (request index, ticket) in submission order
     heads = {"search": 0, "mut": 0}
@@ -614,6 +621,8 @@ def serve_main(a):
     end = time.perf_counter() - start
     srv.close()
     assert ix.sync() == 0
+    prof = ix.profile_read()
+    ix.profile(False)
     st = ix.stats()
     log(f"[serve] stream done in {end:.2f} s; live {st['live']} (expected {int(np.count_nonzero(live_end))})")
     assert st["live"] == int(np.count_nonzero(live_end))
@@ -658,6 +667,10 @@ def serve_main(a):
         "insert_vec_per_s": round(n_ins / end, 1), "delete_ids_per_s": round(n_del / end, 1),
         "search_queries_per_s": round(nq_tot / end, 1),
         "inserts_refused_then_retried": refused,
+        # device time per request class (HIP events on the server's streams; searches and inserts overlap,
+        # so the sums can exceed the wall time)
+        "device_ms_mean": {kk: round(v[0] / max(v[1], 1), 3) for kk, v in prof.items()},
+        "device_ms_total": {kk: round(v[0], 1) for kk, v in prof.items()},
         "recall_at_10_final_window": recall,
         "bulk_load_vec_per_s": round(N / load_s, 1),
     }

@@ -137,7 +137,7 @@ sivf_status sivf_search(sivf_index *ix, int64_t nq, const float *q, int32_t k,
 /* Search schedule autotuner (for uneven batches: skewed list lengths,
  * per-query nprobe and k).  Runs sivf_search on this sample batch once per
  * candidate schedule -- queries per work item (fp32 storage: 8 and 4; the
- * reduced-precision scan always takes 16) x positions per work item (2^12
+ * reduced-precision scan always takes 16) x positions per work item (2^10
  * .. 2^17; longer lists are split into chunks scanned in parallel) x wave
  * schedule (one wave per work item, or resident waves pulling items from
  * per-XCD counters) -- times each with HIP events and keeps the fastest for

@@ -65,10 +65,17 @@ __device__ __forceinline__ int list_chunks(int len, int sh) {
 //     whose partial results (one per pair and chunk) and work items (one per
 //     tile of T pairs and chunk) fit their buffers -- a long list is scanned
 //     by many waves at once instead of one;
-//  3. per-list offsets of partial slots and items; reset the work counters.
-__global__ __launch_bounds__(1024) void k_inv_plan(Dev S, int T, int sh0, int64_t slot_cap, int64_t item_cap) {
+//  3. per-list offsets of partial slots and items; reset the work counters;
+//  4. cut the items into 8 ranges, one per XCD, of equal scan cost (list
+//     positions x query tiles) -- equal item counts leave XCDs idle while
+//     others finish long lists -- each at most xcd_cap items (the blocks an
+//     XCD receives in the dispatch schedule).
+__global__ __launch_bounds__(1024) void k_inv_plan(Dev S, int T, int sh0, int64_t slot_cap, int64_t item_cap,
+                                                   int xcd_cap) {
     __shared__ int sbuf[16];
     __shared__ long long sred[32];
+    __shared__ long long scost[16];
+    __shared__ int sxb[9];
     int carry_p = 0;
     for (int base = 0; base < S.nlist; base += 1024) {
         const int l = base + threadIdx.x;
@@ -98,24 +105,63 @@ __global__ __launch_bounds__(1024) void k_inv_plan(Dev S, int T, int sh0, int64_
         if ((slots <= slot_cap && items <= item_cap) || sh >= 31) break;   // sh = 31: one chunk per list
         sh++;
     }
+    // total scan cost first, so that each list can tell which XCD boundaries fall in it
+    long long wsum = 0, wdummy = 0;
+    for (int l = threadIdx.x; l < S.nlist; l += 1024) {
+        const int qc = S.l_qcs[l];
+        if (qc > 0) wsum += (long long)cdiv_s(qc, T) * S.l_snap[l];
+    }
+    block_sum2(wsum, wdummy, sred);
+    if (threadIdx.x < 9) sxb[threadIdx.x] = -1;
+    __syncthreads();
     int carry_s = 0, carry_i = 0;
+    long long carry_w = 0;
     for (int base = 0; base < S.nlist; base += 1024) {
         const int l = base + threadIdx.x;
         const bool valid = l < S.nlist;
         const int qc = valid ? S.l_qcs[l] : 0;
-        const int nc = qc > 0 ? list_chunks(S.l_snap[l], sh) : 0;
+        const int len = valid ? S.l_snap[l] : 0;
+        const int nc = qc > 0 ? list_chunks(len, sh) : 0;
+        const int ni = cdiv_s(qc, T) * nc;
+        const long long wl = nc > 0 ? (long long)cdiv_s(qc, T) * len : 0;
         int ts, ti;
+        long long tw;
         const int es = block_excl_scan<1024>(qc * nc, sbuf, &ts);
-        const int ei = block_excl_scan<1024>(cdiv_s(qc, T) * nc, sbuf, &ti);
+        const int ei = block_excl_scan<1024>(ni, sbuf, &ti);
+        const long long ew = block_excl_scan64<1024>(wl, scost, &tw);
         if (valid) {
             S.l_pbase[l] = carry_s + es;
             S.l_ioff[l] = carry_i + ei;
+            // XCD boundary x (1..7) at cost x * W / 8 falls in this list's [w0, w0 + wl)
+            const long long w0 = carry_w + ew;
+            for (int x = 1; x < 8 && wl > 0; x++) {
+                const long long target = wsum * x / 8;
+                if (target >= w0 && target < w0 + wl)
+                    sxb[x] = carry_i + ei + (int)((double)(target - w0) / (double)wl * ni);
+            }
         }
         carry_s += ts;
         carry_i += ti;
+        carry_w += tw;
     }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        S.ctl[CTL_NITEMS] = carry_i;
+        const int n = carry_i;
+        // boundaries not hit (zero-cost tail) follow the previous one; then cap every range
+        int b = 0;
+        S.ctl[CTL_XB] = 0;
+        for (int x = 1; x < 8; x++) {
+            int t = sxb[x] < 0 ? b : sxb[x];
+            t = t < b ? b : t;
+            t = t > b + xcd_cap ? b + xcd_cap : t;               // this range fits its XCD's blocks
+            const int rest = n - (8 - x) * xcd_cap;               // the later ranges must fit too
+            t = t < rest ? rest : t;
+            t = t > n ? n : t;
+            S.ctl[CTL_XB + x] = t;
+            b = t;
+        }
+        S.ctl[CTL_XB + 8] = n;
+        S.ctl[CTL_NITEMS] = n;
         S.ctl[CTL_CHUNK] = sh;
     }
     if (threadIdx.x < 8) S.ctl[CTL_WORK0 + CTL_WORK_STRIDE * threadIdx.x] = 0;
@@ -346,28 +392,26 @@ __device__ __forceinline__ uint32_t key_hi(float v) {
 
 // Work items are cut into 8 contiguous ranges, one per XCD (blocks are
 // dealt to the XCDs round robin): consecutive items share a list, so its
-// slabs stay in that XCD's L2.  Two schedules:
-//  - dispatch (persistent = 0): one wave per item; block b takes item
-//    (b mod 8) * ceil(items / 8) + b / 8, and the grid is the host's upper
-//    bound on the item count (surplus waves exit at once);
-//  - persistent (1): a grid of resident waves pulls items from its XCD's
-//    counter, then helps the other ranges; every wave ends once all 8
+// slabs stay in that XCD's L2.  Two schedules (a template parameter: a loop
+// around the scan body costs the hot loop scalar registers):
+//  - dispatch (PERS = false): one wave per item; block b takes item b / 8
+//    of XCD (b mod 8)'s range; the grid is the host's bound on the item
+//    count rounded up to a multiple of 8, and the plan keeps every range
+//    within grid / 8 items (surplus waves exit at once);
+//  - persistent (PERS = true): a grid of resident waves pulls items from its
+//    XCD's counter, then helps the other ranges; every wave ends once all 8
 //    counters have passed their range.
 #define SIVF_ITEM_LOOP_BEGIN                                                                     \
-    const int nitems = S.ctl[CTL_NITEMS];                                                        \
-    const int per = (nitems + 7) >> 3;                                                           \
-    const int nrange = persistent ? 8 : 1;                                                       \
-    for (int xs = 0; xs < nrange; xs++) {                                                        \
+    for (int xs = 0; xs < (PERS ? 8 : 1); xs++) {                                                \
         const int xx = (int)((blockIdx.x + xs) & 7);                                             \
-        const int lo = xx * per, hi = min(nitems, lo + per);                                     \
-        for (int it = 0;; it++) {                                                                \
+        const int lo = S.ctl[CTL_XB + xx], hi = S.ctl[CTL_XB + xx + 1];                          \
+        for (int it = 0; PERS || it < 1; it++) {                                                 \
             int item;                                                                            \
-            if (persistent) {                                                                    \
+            if (PERS) {                                                                          \
                 item = 0;                                                                        \
                 if (threadIdx.x == 0) item = atomicAdd(&S.ctl[CTL_WORK0 + CTL_WORK_STRIDE * xx], 1); \
                 item = __builtin_amdgcn_readfirstlane(item) + lo; /* uniform: scalar addressing */ \
             } else {                                                                             \
-                if (it > 0) break;                                                               \
                 item = lo + (int)(blockIdx.x >> 3);                                              \
             }                                                                                    \
             if (item >= hi) break;
@@ -377,15 +421,19 @@ __device__ __forceinline__ uint32_t key_hi(float v) {
 
 // Decode a work item: list l, query tile, chunk of positions [p0, p1).
 #define SIVF_ITEM_DECODE(TT)                                                                     \
-    const int l = item_list[item], tile = item_tile[item], chunk = item_chunk[item];             \
+    const int l = item_list[item], tile = item_tile[item];                                       \
     const int nt = min(TT, S.l_qcs[l] - tile * TT);                                              \
     const int len = S.l_snap[l];                                                                 \
-    const int nc = list_chunks(len, sh);                                                         \
-    const int p0 = (int)((int64_t)chunk << sh);                                                  \
-    const int p1 = (int)min((int64_t)len, ((int64_t)chunk << sh) + (1ll << sh));                 \
-    const int32_t *pairs = list_pairs + S.l_qoff[l] + tile * TT;                                 \
-    /* partial slot of query t of the tile: slot0 + t * nc */                                    \
-    const int64_t slot0 = (int64_t)S.l_pbase[l] + (int64_t)tile * TT * nc + chunk;
+    const int p0 = (int)((int64_t)item_chunk[item] << sh);                                       \
+    const int p1 = (int)min((int64_t)len, (int64_t)p0 + (1ll << sh));                            \
+    const int32_t *pairs = list_pairs + S.l_qoff[l] + tile * TT;
+
+// Partial slot of query t of the item's tile: slot0 + t * nc.  Computed after
+// the scan (re-reading the item) so that none of it holds a scalar register
+// across the distance loop.
+#define SIVF_ITEM_SLOT(TT)                                                                       \
+    const int nc = list_chunks(len, S.ctl[CTL_CHUNK]);                                           \
+    const int64_t slot0 = (int64_t)S.l_pbase[l] + (int64_t)tile * TT * nc + item_chunk[item];
 
 // Distances of 64 consecutive list positions (lane <-> slot) to the T queries
 // of a tile, in the canonical order (dimensions ascending, one fma each), then
@@ -434,6 +482,7 @@ __device__ __forceinline__ uint32_t key_hi(float v) {
             if (t < nt) topk_offer(K, t, valid, key_hi<METRIC>(acc[t]), id, buf, skq, kcap);     \
         }                                                                                        \
     }                                                                                            \
+    SIVF_ITEM_SLOT(T)                                                                            \
     _Pragma("unroll") for (int t = 0; t < T; t++) {                                              \
         if (t < nt) {                                                                            \
             if (K.cnt[t] > 0) topk_flush(K, t, buf, skq, kcap);                                  \
@@ -452,14 +501,13 @@ __device__ __forceinline__ int query_k(const int32_t *kpq, int k, int qi) {
 // so the compiler reads them through the scalar cache into SGPRs and every
 // VALU op takes its query operand from an SGPR (no LDS traffic).  Needs
 // d % 4 == 0 and 16-byte aligned rows.
-template <int T, int METRIC, bool WIDE>
+template <int T, int METRIC, bool WIDE, bool PERS>
 __global__ __launch_bounds__(64) void k_scan_sq(Dev S, const int32_t *__restrict__ item_list,
                                                 const int32_t *__restrict__ item_tile,
                                                 const int32_t *__restrict__ item_chunk,
                                                 const int32_t *__restrict__ list_pairs,
                                                 const float *__restrict__ q, int np_stride, int kcap, int k,
-                                                const int32_t *__restrict__ kpq, uint64_t *__restrict__ partials,
-                                                int persistent) {
+                                                const int32_t *__restrict__ kpq, uint64_t *__restrict__ partials) {
     __shared__ uint64_t buf[T * 64];
     __shared__ int skq[T];
     const int lane = threadIdx.x;
@@ -484,13 +532,13 @@ __global__ __launch_bounds__(64) void k_scan_sq(Dev S, const int32_t *__restrict
 }
 
 // General path: query rows of any alignment or dimension, staged in LDS.
-template <int T, int METRIC, bool WIDE>
+template <int T, int METRIC, bool WIDE, bool PERS>
 __global__ __launch_bounds__(64) void k_scan(Dev S, const int32_t *__restrict__ item_list,
                                              const int32_t *__restrict__ item_tile,
                                              const int32_t *__restrict__ item_chunk,
                                              const int32_t *__restrict__ list_pairs, const float *__restrict__ q,
                                              int np_stride, int kcap, int k, const int32_t *__restrict__ kpq,
-                                             uint64_t *__restrict__ partials, int persistent) {
+                                             uint64_t *__restrict__ partials) {
     extern __shared__ float4 sq[];   // [T][dp4]
     __shared__ uint64_t buf[T * 64];
     __shared__ int skq[T];
@@ -699,14 +747,14 @@ __device__ __forceinline__ uint32_t mfma_flush(uint64_t (&top)[NQ], int t, const
     return kq > 0 ? (uint32_t)(readlane_u64(c, kq - 1) >> 32) : 0u;
 }
 
-template <int METRIC, int DT, int NKB>
+template <int METRIC, int DT, int NKB, bool PERS>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_scan_mfma(Dev S, const int32_t *__restrict__ item_list,
                                                   const int32_t *__restrict__ item_tile,
                                                   const int32_t *__restrict__ item_chunk,
                                                   const int32_t *__restrict__ list_pairs,
                                                   const float *__restrict__ q, int np_stride, int kcap, int k,
                                                   int kmul, const int32_t *__restrict__ kpq,
-                                                  uint64_t *__restrict__ partials, int persistent) {
+                                                  uint64_t *__restrict__ partials) {
     __shared__ uint64_t buf[MQ * MBUF];
     __shared__ int scnt[MQ], skq[MQ];
     const int lane = threadIdx.x, qcol = lane & 15, kgrp = lane >> 4;
@@ -842,6 +890,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
             }
         }
     }
+    SIVF_ITEM_SLOT(MQ)
 #pragma unroll
     for (int t = 0; t < MQ; t++) {
         if (t < nt) {
@@ -905,20 +954,22 @@ __global__ __launch_bounds__(256) void k_rerank(Dev S, int nq, const float *__re
     }
 }
 
-// Upper bound on a call's work items, which sizes the dispatch grid: twice
-// the unsplit count (tiles of T pairs per list); the plan lengthens chunks
-// until the items fit.
-static int64_t item_limit(const Dev &S, const SearchBufs &W, int npairs) {
+// Work items of a call without splitting: tiles of T pairs per list.  The
+// plan may split long lists until the items reach twice this (or the
+// buffer); the dispatch grid stays at this size.
+static int64_t items_unsplit(const Dev &S, int npairs) {
     const int T = search_tile(S);
-    const int64_t unsplit = (npairs + T - 1) / T + (npairs < S.nlist ? npairs : S.nlist);
-    const int64_t lim = 2 * unsplit;
+    return (npairs + T - 1) / T + (npairs < S.nlist ? npairs : S.nlist);
+}
+
+static int64_t item_limit(const Dev &S, const SearchBufs &W, int npairs) {
+    const int64_t lim = 2 * items_unsplit(S, npairs);
     return lim < W.item_cap ? lim : W.item_cap;
 }
 
-// Grid of a scan launch: the item bound (dispatch) or the waves that fit on
-// the chip at the kernel's occupancy (persistent).
-// (Dispatch: block b takes item (b mod 8) * ceil(n / 8) + b / 8, so the grid
-// is the bound rounded up to a multiple of 8, which covers every item.)
+// Grid of a scan launch: the call's item bound rounded up to a multiple of 8
+// (dispatch), or the waves that fit on the chip at the kernel's occupancy
+// (persistent).
 template <typename K>
 static unsigned scan_grid(K kernel, const Dev &S, const SearchBufs &W, int npairs, size_t smem) {
     if (!S.persistent) {
@@ -944,10 +995,15 @@ void launch_search_scan_mfma(hipStream_t st, const Dev &S, const SearchBufs &W, 
     const int npairs = nq * np_stride;
     // k-blocks of 32 dimensions held as B operands: 2, 3, 4 or 8 (d <= 256)
     const int nkb = (S.d + 31) / 32;
+#define SIVF_LAUNCH_MFMA_P(M, D, K, P)                                                                       \
+    hipLaunchKernelGGL((k_scan_mfma<M, D, K, P>), dim3(scan_grid(k_scan_mfma<M, D, K, P>, S, W, npairs, 0)),    \
+                       dim3(64), 0, st, S, W.item_list, W.item_tile, W.item_chunk, W.list_pairs, q, np_stride,  \
+                       kcap, k, kmul, k_per_query, W.partials)
 #define SIVF_LAUNCH_MFMA(M, D, K)                                                                            \
-    hipLaunchKernelGGL((k_scan_mfma<M, D, K>), dim3(scan_grid(k_scan_mfma<M, D, K>, S, W, npairs, 0)), dim3(64), \
-                       0, st, S, W.item_list, W.item_tile, W.item_chunk, W.list_pairs, q, np_stride, kcap, k, kmul, \
-                       k_per_query, W.partials, S.persistent)
+    do {                                                                                                     \
+        if (S.persistent) SIVF_LAUNCH_MFMA_P(M, D, K, true);                                                 \
+        else SIVF_LAUNCH_MFMA_P(M, D, K, false);                                                             \
+    } while (0)
 #define SIVF_LAUNCH_MFMA_K(M, D)                                                                             \
     do {                                                                                                     \
         if (nkb <= 2) SIVF_LAUNCH_MFMA(M, D, 2);                                                             \
@@ -961,6 +1017,7 @@ void launch_search_scan_mfma(hipStream_t st, const Dev &S, const SearchBufs &W, 
     else SIVF_LAUNCH_MFMA_K(1, 2);
 #undef SIVF_LAUNCH_MFMA_K
 #undef SIVF_LAUNCH_MFMA
+#undef SIVF_LAUNCH_MFMA_P
 }
 
 void launch_rerank(hipStream_t st, const Dev &S, int nq, const float *q, int kc, const int64_t *cand, int k,
@@ -969,23 +1026,29 @@ void launch_rerank(hipStream_t st, const Dev &S, int nq, const float *q, int kc,
                        dist, labels);
 }
 
-template <int T, bool WIDE>
-static void launch_scan_t(hipStream_t st, const Dev &S, const SearchBufs &W, const float *q, int np_stride,
+template <int T, bool WIDE, bool PERS>
+static void launch_scan_p(hipStream_t st, const Dev &S, const SearchBufs &W, const float *q, int np_stride,
                           int kcap, int k, const int32_t *kpq, int npairs) {
     const bool sq = (S.d % 4 == 0) && (((uintptr_t)q & 15) == 0);
 #define SIVF_LAUNCH_SCAN(KERN, SMEM)                                                                         \
     hipLaunchKernelGGL(KERN, dim3(scan_grid(KERN, S, W, npairs, SMEM)), dim3(64), SMEM, st, S, W.item_list,   \
-                       W.item_tile, W.item_chunk, W.list_pairs, q, np_stride, kcap, k, kpq, W.partials,       \
-                       S.persistent)
+                       W.item_tile, W.item_chunk, W.list_pairs, q, np_stride, kcap, k, kpq, W.partials)
     if (sq) {
-        if (S.metric == 0) SIVF_LAUNCH_SCAN((k_scan_sq<T, 0, WIDE>), 0);
-        else SIVF_LAUNCH_SCAN((k_scan_sq<T, 1, WIDE>), 0);
+        if (S.metric == 0) SIVF_LAUNCH_SCAN((k_scan_sq<T, 0, WIDE, PERS>), 0);
+        else SIVF_LAUNCH_SCAN((k_scan_sq<T, 1, WIDE, PERS>), 0);
         return;
     }
     const size_t smem = (size_t)T * S.dp4 * sizeof(float4);
-    if (S.metric == 0) SIVF_LAUNCH_SCAN((k_scan<T, 0, WIDE>), smem);
-    else SIVF_LAUNCH_SCAN((k_scan<T, 1, WIDE>), smem);
+    if (S.metric == 0) SIVF_LAUNCH_SCAN((k_scan<T, 0, WIDE, PERS>), smem);
+    else SIVF_LAUNCH_SCAN((k_scan<T, 1, WIDE, PERS>), smem);
 #undef SIVF_LAUNCH_SCAN
+}
+
+template <int T, bool WIDE>
+static void launch_scan_t(hipStream_t st, const Dev &S, const SearchBufs &W, const float *q, int np_stride,
+                          int kcap, int k, const int32_t *kpq, int npairs) {
+    if (S.persistent) launch_scan_p<T, WIDE, true>(st, S, W, q, np_stride, kcap, k, kpq, npairs);
+    else launch_scan_p<T, WIDE, false>(st, S, W, q, np_stride, kcap, k, kpq, npairs);
 }
 
 void launch_search_plan(hipStream_t st, const Dev &S, const SearchBufs &W, int nq, int np_stride) {
@@ -993,8 +1056,9 @@ void launch_search_plan(hipStream_t st, const Dev &S, const SearchBufs &W, int n
     const unsigned pb = (unsigned)((npairs + 255) / 256);
     const int T = search_tile(S);
     hipLaunchKernelGGL(k_inv_count, dim3(pb), dim3(256), 0, st, S, npairs, W.probes, W.pair_rank);
-    hipLaunchKernelGGL(k_inv_plan, dim3(1), dim3(1024), 0, st, S, T, S.chunk_shift, W.slot_cap,
-                       item_limit(S, W, npairs));
+    const int64_t lim = item_limit(S, W, npairs);
+    hipLaunchKernelGGL(k_inv_plan, dim3(1), dim3(1024), 0, st, S, T, S.chunk_shift, W.slot_cap, lim,
+                       (int)((lim + 7) / 8));
     hipLaunchKernelGGL(k_inv_items, dim3((S.nlist + 3) / 4), dim3(256), 0, st, S, T, W.item_list, W.item_tile,
                        W.item_chunk);
     hipLaunchKernelGGL(k_inv_scatter, dim3(pb), dim3(256), 0, st, S, npairs, W.probes, W.pair_rank,

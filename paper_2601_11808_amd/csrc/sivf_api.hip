@@ -444,7 +444,7 @@ sivf_status sivf_tune_search(sivf_index *ix, int64_t nq, const float *q, int32_t
     sivf_status s = SIVF_OK;
     for (int pm = 0; pm < 2; pm++)
     for (int T : tiles) {
-        for (int sh = 12; sh <= 17 && s == SIVF_OK; sh++) {
+        for (int sh = 10; sh <= 17 && s == SIVF_OK; sh++) {
             ix->S.tile = T;
             ix->S.chunk_shift = sh;
             ix->S.persistent = pm;

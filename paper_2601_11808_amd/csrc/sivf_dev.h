@@ -34,6 +34,7 @@ enum Ctl {
     CTL_NITEMS = 5,     // search: work items of the current call
     CTL_SEQ = 6,        // sequence number of the current add/remove call; its last kernel bumps it
     CTL_CHUNK = 7,      // search: log2 of the positions per work item (a list's chunk)
+    CTL_XB = 16,        // search: first item of each XCD's range (words 16..24; word 24 = item count)
     CTL_WORK0 = 64,     // search, persistent schedule: 8 work counters, one per XCD range of items,
     CTL_WORK_STRIDE = 32,  // each on its own 128-byte line (words 64, 96, .., 288)
     CTL_WORDS = 320
@@ -187,6 +188,30 @@ __device__ __forceinline__ int block_excl_scan(int v, int *sbuf, int *total) {
 #pragma unroll
     for (int i = 0; i < NT / 64; i++) {
         int s = sbuf[i];
+        if (i < w) before += s;
+        tot += s;
+    }
+    __syncthreads();
+    *total = tot;
+    return before + incl - v;
+}
+
+// Exclusive prefix sum of 64-bit values over a block of NT threads.
+template <int NT>
+__device__ __forceinline__ long long block_excl_scan64(long long v, long long *sbuf, long long *total) {
+    const int w = threadIdx.x / 64, l = lane_id();
+    long long incl = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const long long u = __shfl_up(incl, o);
+        if (l >= o) incl += u;
+    }
+    if (l == 63) sbuf[w] = incl;
+    __syncthreads();
+    long long before = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < NT / 64; i++) {
+        const long long s = sbuf[i];
         if (i < w) before += s;
         tot += s;
     }
