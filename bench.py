@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--recall-queries", type=int, default=1000)
     ap.add_argument("--no-sweep", action="store_true", help="skip the nprobe / recall sweep")
+    ap.add_argument("--schedule", default=None,
+                    help="T,log2chunk,persistent: set the search schedule instead of running the autotuner")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (scale for DRAM byte counters)")
     return ap.parse_args()
@@ -199,9 +201,13 @@ def main():
     dist = torch.empty((nq, k), dtype=torch.float32, device=dev)
     lab = torch.empty((nq, k), dtype=torch.int64, device=dev)
     t0 = time.perf_counter()
-    tile, sh, pers = ix.tune_search(qd, k, nprobe)   # search schedule for this batch shape (untimed)
-    log(f"[bench] autotuner: {tile} queries x 2^{sh} positions per work item, persistent={pers} "
-        f"({time.perf_counter() - t0:.1f} s)")
+    if a.schedule:
+        tile, sh, pers = (int(v) for v in a.schedule.split(","))
+        ix.set_search_schedule(tile, sh, pers)
+    else:
+        tile, sh, pers = ix.tune_search(qd, k, nprobe)   # search schedule for this batch shape (untimed)
+    log(f"[bench] schedule: {tile} queries x 2^{sh} positions per work item, persistent={pers} "
+        f"({'given' if a.schedule else 'autotuned'}, {time.perf_counter() - t0:.1f} s)")
     torch.cuda.synchronize()
     for t in range(a.warmup):
         ix.step(bx[t], bi[t], qd, k, nprobe, bo[t], out=(dist, lab))

@@ -149,6 +149,13 @@ sivf_status sivf_tune_search(sivf_index *ix, int64_t nq, const float *q, int32_t
                              int32_t nprobe, const int32_t *nprobe_per_query, float *dist, int64_t *labels,
                              void *stream, int32_t *tile, int32_t *chunk_shift, int32_t *persistent);
 
+/* Set the search schedule directly (e.g. one found earlier by
+ * sivf_tune_search): tile = queries per work item (fp32 storage: 4, or 8
+ * when dim <= 1024; reduced precision: 16), 2^chunk_shift = positions per
+ * work item (6..31), persistent = 0 (one wave per item) or 1 (resident
+ * waves).  SIVF_ERR_ARG for other values.  Applies to later calls. */
+sivf_status sivf_set_search_schedule(sivf_index *ix, int32_t tile, int32_t chunk_shift, int32_t persistent);
+
 /* One sliding-window step in the order of the paper's mixed loop
  * (Sec. 5.5: insert, then search, then delete).  Any part with a zero count
  * is skipped.  Same argument rules as the three calls (k_per_query and

@@ -60,6 +60,7 @@ SIGNATURES = [
     ("sivf_search", ct.c_int, [_P, _I64, _P, _I32, _P, _I32, _P, _P, _P, _P]),
     ("sivf_tune_search", ct.c_int, [_P, _I64, _P, _I32, _P, _I32, _P, _P, _P, _P, ct.POINTER(_I32),
                                     ct.POINTER(_I32), ct.POINTER(_I32)]),
+    ("sivf_set_search_schedule", ct.c_int, [_P, _I32, _I32, _I32]),
     ("sivf_step", ct.c_int, [_P, ct.POINTER(SivfStepArgs), _P]),
     ("sivf_graph_create", ct.c_int, [_P, ct.POINTER(SivfStepArgs), ct.POINTER(_P)]),
     ("sivf_graph_launch", ct.c_int, [_P, _P]),
@@ -238,6 +239,10 @@ class Index:
                                       _ptr(lab), self._stream(stream), ct.byref(t), ct.byref(sh), ct.byref(pm)),
                "sivf_tune_search")
         return t.value, sh.value, pm.value
+
+    def set_search_schedule(self, tile, chunk_shift, persistent):
+        _check(lib().sivf_set_search_schedule(self._h, tile, chunk_shift, int(persistent)),
+               "sivf_set_search_schedule")
 
     def step(self, x=None, add_ids=None, q=None, k=10, nprobe=1, remove_ids=None, stream=None, out=None,
              k_per_query=None, nprobe_per_query=None):

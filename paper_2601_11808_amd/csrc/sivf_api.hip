@@ -477,6 +477,17 @@ sivf_status sivf_tune_search(sivf_index *ix, int64_t nq, const float *q, int32_t
     return s;
 }
 
+sivf_status sivf_set_search_schedule(sivf_index *ix, int32_t tile, int32_t chunk_shift, int32_t persistent) {
+    if (!ix) return SIVF_ERR_ARG;
+    const bool reduced = ix->cfg.storage != SIVF_F32;
+    if (reduced ? tile != 16 : (tile != 4 && (tile != 8 || ix->cfg.dim > 1024))) return SIVF_ERR_ARG;
+    if (chunk_shift < 6 || chunk_shift > 31 || (persistent != 0 && persistent != 1)) return SIVF_ERR_ARG;
+    ix->S.tile = tile;
+    ix->S.chunk_shift = chunk_shift;
+    ix->S.persistent = persistent;
+    return SIVF_OK;
+}
+
 static bool step_args_ok(const sivf_index *ix, const sivf_step_args *a) {
     const sivf_config &c = ix->cfg;
     if (a->n_add < 0 || a->n_add > c.max_batch || a->n_remove < 0 || a->n_remove > c.max_batch) return false;
