@@ -202,10 +202,12 @@ sivf_status sivf_assign(sivf_index *ix, int64_t n, const float *x, int32_t *list
 sivf_status sivf_probe(sivf_index *ix, int64_t nq, const float *q, int32_t nprobe,
                        int32_t *probes, void *stream);
 
-/* Approximate coarse distances of the quantizer's FP32 MFMA stage:
+/* Approximate coarse distances of the quantizer's MFMA stage:
  * |x|^2 + |c|^2 - 2 x.c (L2) or -x.c (IP), before the exact re-check.  For
  * validating the error bound |approx - exact| <= (4d+16) 2^-24 (|x|+|c|)^2
- * (L2) or (4d+16) 2^-24 |x||c| (IP) that the re-check relies on.
+ * (L2) or (4d+16) 2^-24 |x||c| (IP) that the re-check relies on.  Indexes
+ * with bf16/fp16 storage multiply bf16-rounded operands (bf16 MFMA); their
+ * bound adds 2 (2u + u^2) |x||c| (L2) or (2u + u^2) |x||c| (IP), u = 2^-8.
  * x: device n x dim fp32; scores: device n x nlist fp32.
  * n <= max(max_batch, max_queries). */
 sivf_status sivf_coarse_scores(sivf_index *ix, int64_t n, const float *x, float *scores, void *stream);

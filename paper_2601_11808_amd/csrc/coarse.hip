@@ -28,18 +28,30 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 constexpr int GM = 128, GN = 128, GK = 32, GLD = GM + 16;
 constexpr int GROUP = 16;   // lists per group minimum (insert path)
 
+constexpr int HLD = GK + 8;  // bf16 operands: row-major LDS rows of 32 + 8 halves (80 bytes)
+
+typedef __bf16 cbf16x8 __attribute__((ext_vector_type(8)));
+
 // GMIN = 0: write Dt[r][l] for every list (out row stride ldo = nlist).
 // GMIN = 1: write only the minimum of each group of 16 consecutive lists,
 //           out[r][l / 16] (ldo = ceil(nlist / 16)); a NaN counts as +inf.
-template <int METRIC, int GMIN, bool VEC>
+// BF = 1: both operands rounded to bf16 (round to nearest even) and
+//         multiplied on v_mfma_f32_16x16x32_bf16 (16 times the FP32 MFMA
+//         rate); |x|^2 and |c|^2 stay fp32 from the exact values.  The
+//         re-check bound then adds the operand rounding (coarse_err).
+template <int METRIC, int GMIN, bool VEC, int BF>
 __global__ __launch_bounds__(256) void k_coarse_gemm(const float *__restrict__ X, int n, int d,
                                                      const float *__restrict__ cent, int dpad,
                                                      const float *__restrict__ cn2, int nlist,
                                                      float *__restrict__ out, int ldo, const int32_t *ctl,
                                                      int gated) {
-    __shared__ float sA[GK][GLD];
-    __shared__ float sB[GK][GLD];
+    // fp32: k-major [GK][GLD] floats per operand; bf16: row-major [GM][HLD] halves per operand
+    __shared__ __align__(16) float sbuf[2][BF ? (GM * HLD / 2) : (GK * GLD)];
     __shared__ float sqn[GM];
+    float(*sA)[GLD] = reinterpret_cast<float(*)[GLD]>(sbuf[0]);
+    float(*sB)[GLD] = reinterpret_cast<float(*)[GLD]>(sbuf[1]);
+    uint16_t(*hA)[HLD] = reinterpret_cast<uint16_t(*)[HLD]>(sbuf[0]);
+    uint16_t(*hB)[HLD] = reinterpret_cast<uint16_t(*)[HLD]>(sbuf[1]);
     if (gated && call_failed(ctl)) return;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int r0 = blockIdx.x * GM, c0 = blockIdx.y * GN;
@@ -77,6 +89,19 @@ __global__ __launch_bounds__(256) void k_coarse_gemm(const float *__restrict__ X
 #pragma unroll
         for (int i = 0; i < 4; i++) {
             const int rr = lrow + 32 * i;
+            qp[i] = fmaf(ra[i].x, ra[i].x, qp[i]);
+            qp[i] = fmaf(ra[i].y, ra[i].y, qp[i]);
+            qp[i] = fmaf(ra[i].z, ra[i].z, qp[i]);
+            qp[i] = fmaf(ra[i].w, ra[i].w, qp[i]);
+            if (BF) {
+                *reinterpret_cast<uint2 *>(&hA[rr][lk]) =
+                    make_uint2(to_bf16_bits(ra[i].x) | (to_bf16_bits(ra[i].y) << 16),
+                               to_bf16_bits(ra[i].z) | (to_bf16_bits(ra[i].w) << 16));
+                *reinterpret_cast<uint2 *>(&hB[rr][lk]) =
+                    make_uint2(to_bf16_bits(rb[i].x) | (to_bf16_bits(rb[i].y) << 16),
+                               to_bf16_bits(rb[i].z) | (to_bf16_bits(rb[i].w) << 16));
+                continue;
+            }
             sA[lk + 0][rr] = ra[i].x;
             sA[lk + 1][rr] = ra[i].y;
             sA[lk + 2][rr] = ra[i].z;
@@ -85,10 +110,6 @@ __global__ __launch_bounds__(256) void k_coarse_gemm(const float *__restrict__ X
             sB[lk + 1][rr] = rb[i].y;
             sB[lk + 2][rr] = rb[i].z;
             sB[lk + 3][rr] = rb[i].w;
-            qp[i] = fmaf(ra[i].x, ra[i].x, qp[i]);
-            qp[i] = fmaf(ra[i].y, ra[i].y, qp[i]);
-            qp[i] = fmaf(ra[i].z, ra[i].z, qp[i]);
-            qp[i] = fmaf(ra[i].w, ra[i].w, qp[i]);
         }
     };
     gload(0);
@@ -97,6 +118,23 @@ __global__ __launch_bounds__(256) void k_coarse_gemm(const float *__restrict__ X
         lstore();
         __syncthreads();
         if (k0 + GK < kend) gload(k0 + GK);
+        if (BF) {
+            // lane l: row (or centroid) l % 16 of the block, halves 8 (l / 16) .. +8 of the step
+            const int kg = (lane >> 4) * 8;
+            uint4 av[4], bv[4];
+#pragma unroll
+            for (int i = 0; i < 4; i++) av[i] = *reinterpret_cast<const uint4 *>(&hA[wr + 16 * i + (lane & 15)][kg]);
+#pragma unroll
+            for (int j = 0; j < 4; j++) bv[j] = *reinterpret_cast<const uint4 *>(&hB[wc + 16 * j + (lane & 15)][kg]);
+#pragma unroll
+            for (int i = 0; i < 4; i++)
+#pragma unroll
+                for (int j = 0; j < 4; j++)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(cbf16x8, av[i]),
+                                                                       __builtin_bit_cast(cbf16x8, bv[j]),
+                                                                       acc[i][j], 0, 0, 0);
+            continue;
+        }
 #pragma unroll
         for (int s = 0; s < GK / 4; s++) {
             const int kr = 4 * s + (lane >> 4);
@@ -150,6 +188,21 @@ __global__ __launch_bounds__(256) void k_coarse_gemm(const float *__restrict__ X
     }
 }
 
+// Certified bound on |Dt - D| for a row of norm qn and a list of norm cn: the
+// FP32 arithmetic of the GEMM ((4d+16) 2^-24 (|x|+|c|)^2, IP: |x||c|, plus
+// an underflow term) and, with bf16 operands (bf = 1), their rounding:
+// |x.c - x~.c~| <= (2u + u^2)|x||c| with u = 2^-8 (Cauchy-Schwarz), counted
+// twice for L2's -2 x.c, plus the bf16 subnormal spacing.
+__device__ __forceinline__ double coarse_err(int metric, int d, int bf, double qn, double cn) {
+    const double coef = (4.0 * d + 16.0) * 0x1p-24;
+    double e = metric == 0 ? coef * (qn + cn) * (qn + cn) : coef * qn * cn;
+    if (bf) {
+        const double u = 0x1p-8, m = metric == 0 ? 2.0 : 1.0;
+        e += m * (2.0 * u + u * u) * 1.01 * qn * cn + m * 0x1p-132 * sqrt((double)d) * (qn + cn);
+    }
+    return e + (double)d * 0x1p-120;
+}
+
 __device__ __forceinline__ double canon_dist(const float *sx, const float *__restrict__ c, int d,
                                              int metric) {
     double r = 0.0;
@@ -172,7 +225,7 @@ __global__ __launch_bounds__(256) void k_coarse_select(
     const float *__restrict__ dt, const float *__restrict__ X, int n, int d, const float *__restrict__ cent,
     int dpad, const double *__restrict__ cnorm, const double *__restrict__ cmax, int nlist, int metric,
     int m_uniform, const int32_t *__restrict__ m_per_row, int mmax, int32_t *__restrict__ out,
-    int out_stride, const int32_t *ctl, int gated) {
+    int out_stride, const int32_t *ctl, int gated, int bf) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int hist[256];
     __shared__ int sbuf[8];
@@ -204,11 +257,9 @@ __global__ __launch_bounds__(256) void k_coarse_select(
     for (int o = 32; o > 0; o >>= 1) q2 += __shfl_xor(q2, o);
     if ((tid & 63) == 0) sred[tid >> 6] = q2;
     __syncthreads();
-    const double qn = sqrt(sred[0] + sred[1] + sred[2] + sred[3]);
-    const double coef = (4.0 * d + 16.0) * 0x1p-24;
-    const double eabs = (double)d * 0x1p-120;
+    const double qn = sqrt(sred[0] + sred[1] + sred[2] + sred[3]) * (1.0 + 0x1p-50);
     const double cm = *cmax;
-    const double emax = metric == 0 ? coef * (qn + cm) * (qn + cm) + eabs : coef * qn * cm + eabs;
+    const double emax = coarse_err(metric, d, bf, qn, cm);
     const float *drow = dt + (int64_t)row * nlist;
 
     // tau = m-th smallest approximate distance (radix select on ordered bits).
@@ -271,7 +322,7 @@ __global__ __launch_bounds__(256) void k_coarse_select(
         if (l < nlist) {
             const double dv = (double)drow[l];
             const double cn = cnorm[l];
-            const double el = metric == 0 ? coef * (qn + cn) * (qn + cn) + eabs : coef * qn * cn + eabs;
+            const double el = coarse_err(metric, d, bf, qn, cn);
             isc = (dv - el <= ub) ? 1 : 0;
         }
         int tot;
@@ -298,7 +349,7 @@ __global__ __launch_bounds__(256) void k_coarse_argmin(const float *__restrict__
                                                        const float *__restrict__ cent, int dpad,
                                                        const double *__restrict__ cmax, int nlist, int metric,
                                                        int32_t *__restrict__ out, int out_stride,
-                                                       const int32_t *ctl, int gated) {
+                                                       const int32_t *ctl, int gated, int bf) {
     if (gated && call_failed(ctl)) return;
     const int lane = threadIdx.x & 63;
     const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -318,9 +369,7 @@ __global__ __launch_bounds__(256) void k_coarse_argmin(const float *__restrict__
     for (int o = 32; o > 0; o >>= 1) q2 += __shfl_xor(q2, o);
     const double qn = sqrt(q2) * (1.0 + 0x1p-50);
     const double cm = *cmax;
-    const double coef = (4.0 * d + 16.0) * 0x1p-24;
-    const double eabs = (double)d * 0x1p-120;
-    const double emax = metric == 0 ? coef * (qn + cm) * (qn + cm) + eabs : coef * qn * cm + eabs;
+    const double emax = coarse_err(metric, d, bf, qn, cm);
     const bool every = !(qn + cm < 0x1p60);
     const float *g = gmin + (int64_t)row * ldg;
     float t = __builtin_inff();
@@ -379,46 +428,51 @@ size_t coarse_select_smem(int dpad, int mmax) {
 template <int GMIN>
 static void coarse_gemm_t(hipStream_t st, const float *X, int n, int d, const float *cent, int dpad,
                           const float *cn2, int nlist, int metric, float *out, int ldo, const int32_t *ctl,
-                          int gated) {
+                          int gated, int bf) {
     const dim3 grid((n + GM - 1) / GM, (nlist + GN - 1) / GN);
     const bool vec = (d % 4 == 0) && (((uintptr_t)X & 15) == 0);
-#define SIVF_GEMM(M, V)                                                                                         \
-    hipLaunchKernelGGL((k_coarse_gemm<M, GMIN, V>), grid, dim3(256), 0, st, X, n, d, cent, dpad, cn2, nlist,  \
+#define SIVF_GEMM(M, V, B)                                                                                      \
+    hipLaunchKernelGGL((k_coarse_gemm<M, GMIN, V, B>), grid, dim3(256), 0, st, X, n, d, cent, dpad, cn2, nlist, \
                        out, ldo, ctl, gated)
+#define SIVF_GEMM_B(M, V)                                                                                       \
+    do {                                                                                                        \
+        if (bf) SIVF_GEMM(M, V, 1); else SIVF_GEMM(M, V, 0);                                                    \
+    } while (0)
     if (metric == 0) {
-        if (vec) SIVF_GEMM(0, true); else SIVF_GEMM(0, false);
+        if (vec) SIVF_GEMM_B(0, true); else SIVF_GEMM_B(0, false);
     } else {
-        if (vec) SIVF_GEMM(1, true); else SIVF_GEMM(1, false);
+        if (vec) SIVF_GEMM_B(1, true); else SIVF_GEMM_B(1, false);
     }
+#undef SIVF_GEMM_B
 #undef SIVF_GEMM
 }
 
 void launch_coarse_gemm(hipStream_t st, const float *X, int n, int d, const float *cent, int dpad,
                         const float *cn2, int nlist, int metric, float *out, const int32_t *ctl,
-                        int gated) {
-    if (n > 0) coarse_gemm_t<0>(st, X, n, d, cent, dpad, cn2, nlist, metric, out, nlist, ctl, gated);
+                        int gated, int bf) {
+    if (n > 0) coarse_gemm_t<0>(st, X, n, d, cent, dpad, cn2, nlist, metric, out, nlist, ctl, gated, bf);
 }
 
 int coarse_groups(int nlist) { return (nlist + GROUP - 1) / GROUP; }
 
 void launch_coarse_assign(hipStream_t st, float *scratch, const float *X, int n, int d, const float *cent,
                           int dpad, const float *cn2, const double *cmax, int nlist, int metric, int32_t *out,
-                          int out_stride, const int32_t *ctl, int gated) {
+                          int out_stride, const int32_t *ctl, int gated, int bf) {
     if (n <= 0) return;
     const int ldg = coarse_groups(nlist);
-    coarse_gemm_t<1>(st, X, n, d, cent, dpad, cn2, nlist, metric, scratch, ldg, ctl, gated);
+    coarse_gemm_t<1>(st, X, n, d, cent, dpad, cn2, nlist, metric, scratch, ldg, ctl, gated, bf);
     hipLaunchKernelGGL(k_coarse_argmin, dim3((n + 3) / 4), dim3(256), 0, st, scratch, ldg, X, n, d, cent, dpad,
-                       cmax, nlist, metric, out, out_stride, ctl, gated);
+                       cmax, nlist, metric, out, out_stride, ctl, gated, bf);
 }
 
 void launch_coarse_select(hipStream_t st, const float *dt, const float *X, int n, int d, const float *cent,
                           int dpad, const double *cnorm, const double *cmax, int nlist, int metric,
                           int m_uniform, const int32_t *m_per_row, int mmax, int32_t *out, int out_stride,
-                          const int32_t *ctl, int gated) {
+                          const int32_t *ctl, int gated, int bf) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_coarse_select, dim3(n), dim3(256), coarse_select_smem(dpad, mmax), st, dt, X, n, d,
                        cent, dpad, cnorm, cmax, nlist, metric, m_uniform, m_per_row, mmax, out, out_stride,
-                       ctl, gated);
+                       ctl, gated, bf);
 }
 
 }  // namespace sivf

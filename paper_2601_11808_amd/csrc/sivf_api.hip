@@ -195,18 +195,19 @@ void coarse(sivf_index *ix, hipStream_t st, float *dt, const float *x, int64_t n
             int mmax, int32_t *out, int out_stride, int gated) {
     const Dev &S = ix->S;
     const int dpad = S.dp4 * 4;
+    const int bf = S.storage != SIVF_F32;   // reduced-precision indexes run the coarse GEMM on bf16 MFMA
     for (int64_t r0 = 0; r0 < n; r0 += ix->L.coarse_rows) {
         const int nr = (int)((n - r0) < ix->L.coarse_rows ? (n - r0) : ix->L.coarse_rows);
         const float *xr = x + r0 * S.d;
         if (m == 1 && !m_per_row && mmax == 1) {
             launch_coarse_assign(st, dt, xr, nr, S.d, S.cent, dpad, S.cn2, S.cmax, S.nlist, S.metric,
-                                 out + r0 * out_stride, out_stride, S.ctl, gated);
+                                 out + r0 * out_stride, out_stride, S.ctl, gated, bf);
             continue;
         }
-        launch_coarse_gemm(st, xr, nr, S.d, S.cent, dpad, S.cn2, S.nlist, S.metric, dt, S.ctl, gated);
+        launch_coarse_gemm(st, xr, nr, S.d, S.cent, dpad, S.cn2, S.nlist, S.metric, dt, S.ctl, gated, bf);
         launch_coarse_select(st, dt, xr, nr, S.d, S.cent, dpad, S.cnorm, S.cmax, S.nlist, S.metric, m,
                              m_per_row ? m_per_row + r0 : nullptr, mmax, out + r0 * out_stride, out_stride,
-                             S.ctl, gated);
+                             S.ctl, gated, bf);
     }
 }
 
@@ -609,7 +610,7 @@ sivf_status sivf_coarse_scores(sivf_index *ix, int64_t n, const float *x, float 
     if (n == 0) return SIVF_OK;
     const Dev &S = ix->S;
     launch_coarse_gemm(as_stream(stream), x, (int)n, S.d, S.cent, S.dp4 * 4, S.cn2, S.nlist, S.metric, scores,
-                       S.ctl, 0);
+                       S.ctl, 0, S.storage != SIVF_F32);
     return launched(ix);
 }
 

@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 import oracle
+import paper_2601_11808_amd as sivf
 import workloads
 from tests.gpu_common import Pair, compare_results, say
 from tests.invariants import check_dump
@@ -47,21 +48,26 @@ def test_coarse_mfma_error_bound(kind, d, nlist):
     else:
         cent = rng.standard_normal((nlist, d)).astype(np.float32)
         x = rng.standard_normal((3000, d)).astype(np.float32)
-    for metric in (0, 1):
-        p = Pair(d, nlist, cent, metric=metric, max_batch=4096)
-        s = p.gpu.coarse_scores(x).cpu().numpy().astype(np.float64)
+    for storage, metric in ((0, 0), (0, 1), (1, 0), (1, 1)):
+        if storage == 1 and d > 256:
+            continue
+        ix = sivf.Index(d, nlist, cent, metric=metric, slab_capacity=64, num_slabs=64, id_capacity=64,
+                        max_batch=4096, max_queries=64, max_k=16, max_nprobe=16, storage=storage,
+                        rerank_factor=4 if storage else 0)
+        s = ix.coarse_scores(x).cpu().numpy().astype(np.float64)
         xd, cd = x.astype(np.float64), cent.astype(np.float64)
         nx, nc = np.linalg.norm(xd, axis=1), np.linalg.norm(cd, axis=1)
         coef = (4 * d + 16) * 2.0 ** -24
+        u = 2.0 ** -8     # bf16 operands on reduced-storage indexes: |x.c - x~.c~| <= (2u + u^2)|x||c|
         if metric == 0:
             exact = ((xd[:, None, :] - cd[None]) ** 2).sum(-1)
-            bound = coef * (nx[:, None] + nc[None]) ** 2
+            bound = coef * (nx[:, None] + nc[None]) ** 2 + storage * 2 * (2 * u + u * u) * nx[:, None] * nc[None]
         else:
             exact = -(xd @ cd.T)
-            bound = coef * nx[:, None] * nc[None]
+            bound = coef * nx[:, None] * nc[None] + storage * (2 * u + u * u) * nx[:, None] * nc[None]
         ratio = np.abs(s - exact) / bound
-        say(f"  metric {metric}: max |approx-exact|/bound = {ratio.max():.3e}")
-        assert ratio.max() <= 0.5
+        say(f"  storage {storage} metric {metric}: max |approx-exact|/bound = {ratio.max():.3e}")
+        assert ratio.max() <= (0.5 if storage == 0 else 1.0)
 
 
 def _tie_data(seed, d, nlist, n):
@@ -91,6 +97,27 @@ def test_assign_and_probe_exact(metric):
             gp = p.gpu.probe(x[:1500], m).cpu().numpy()
             rp = oracle.probe(x[:1500], cent, m, metric)
             np.testing.assert_array_equal(gp, rp)
+
+
+@pytest.mark.parametrize("metric", [0, 1])
+def test_assign_and_probe_exact_bf16_coarse(metric):
+    """Reduced-storage indexes run the coarse GEMM on bf16 MFMA; with the
+    wider certified bound the decisions still equal the oracle's exactly."""
+    for d, nlist in [(16, 64), (128, 1024), (7, 13), (96, 4100)]:
+        cent, x = _tie_data(d * 1000 + nlist + 7, d, nlist, 4000)
+        ix = sivf.Index(d, nlist, cent, metric=metric, slab_capacity=64, num_slabs=64, id_capacity=64,
+                        max_batch=4096, max_queries=4096, max_k=16, max_nprobe=64, storage=1, rerank_factor=4)
+        np.testing.assert_array_equal(ix.assign(x).cpu().numpy(), oracle.assign(x, cent, metric))
+        for m in (1, 7, 64):
+            gp = ix.probe(x[:1000], m).cpu().numpy()
+            np.testing.assert_array_equal(gp, oracle.probe(x[:1000], cent, m, metric))
+    w = workloads.serving(n_base=0)
+    rng = np.random.default_rng([12, metric])
+    x = (w.means[rng.integers(0, 16384, 3000)] + 48 * rng.standard_normal((3000, 128))).astype(np.float32)
+    ix = sivf.Index(128, 16384, w.centroids, metric=metric, slab_capacity=128, num_slabs=64, id_capacity=64,
+                    max_batch=4096, max_queries=4096, max_k=16, max_nprobe=64, storage=2, rerank_factor=4)
+    np.testing.assert_array_equal(ix.assign(x).cpu().numpy(), oracle.assign(x, w.centroids, metric))
+    np.testing.assert_array_equal(ix.probe(x[:300], 64).cpu().numpy(), oracle.probe(x[:300], w.centroids, 64, metric))
 
 
 @pytest.mark.parametrize("metric", [0, 1])
