@@ -41,10 +41,11 @@ typedef __bf16 cbf16x8 __attribute__((ext_vector_type(8)));
 //         re-check bound then adds the operand rounding (coarse_err).
 template <int METRIC, int GMIN, bool VEC, int BF>
 __global__ __launch_bounds__(256) void k_coarse_gemm(const float *__restrict__ X, int n, int d,
-                                                     const float *__restrict__ cent, int dpad,
+                                                     const float *__restrict__ cent,
+                                                     const uint16_t *__restrict__ cent_h, int dpad,
                                                      const float *__restrict__ cn2, int nlist,
                                                      float *__restrict__ out, int ldo, const int32_t *ctl,
-                                                     int gated) {
+                                                     int gated, int xcd_map) {
     // fp32: k-major [GK][GLD] floats per operand; bf16: row-major [GM][HLD] halves per operand
     __shared__ __align__(16) float sbuf[2][BF ? (GM * HLD / 2) : (GK * GLD)];
     __shared__ float sqn[GM];
@@ -54,7 +55,22 @@ __global__ __launch_bounds__(256) void k_coarse_gemm(const float *__restrict__ X
     uint16_t(*hB)[HLD] = reinterpret_cast<uint16_t(*)[HLD]>(sbuf[1]);
     if (gated && call_failed(ctl)) return;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int r0 = blockIdx.x * GM, c0 = blockIdx.y * GN;
+    // Block -> (row block, centroid block).  With xcd_map each XCD (blocks are
+    // dealt round robin) owns a contiguous range of centroid blocks and walks
+    // every row block for one before the next, so a centroid tile is fetched
+    // into one L2 and reused by all row blocks.
+    const int nrb = (n + GM - 1) / GM, ncb = (nlist + GN - 1) / GN;
+    int rb, cb;
+    if (xcd_map) {
+        const int per = (ncb + 7) >> 3, j = (int)(blockIdx.x >> 3);
+        cb = (int)(blockIdx.x & 7) * per + j / nrb;
+        rb = j % nrb;
+        if (cb >= ncb || j / nrb >= per) return;
+    } else {
+        rb = (int)blockIdx.x % nrb;
+        cb = (int)blockIdx.x / nrb;
+    }
+    const int r0 = rb * GM, c0 = cb * GN;
     const int wr = (w >> 1) * 64, wc = (w & 1) * 64;
     const int lrow = tid >> 3, lk = (tid & 7) * 4;   // loader: 8 threads x float4 per row, 32 rows per pass
     floatx4 acc[4][4];
@@ -62,7 +78,8 @@ __global__ __launch_bounds__(256) void k_coarse_gemm(const float *__restrict__ X
     for (int i = 0; i < 4; i++)
 #pragma unroll
         for (int j = 0; j < 4; j++) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-    float4 ra[4], rb[4];
+    float4 ra[4], rbf[4];
+    uint2 rbh[4];   // bf16 centroid halves (BF)
     float qp[4] = {0.f, 0.f, 0.f, 0.f};
     const int kend = (dpad + GK - 1) / GK * GK;
 
@@ -81,8 +98,12 @@ __global__ __launch_bounds__(256) void k_coarse_gemm(const float *__restrict__ X
                 ra[i].w = (r < n && kk + 3 < d) ? p[kk + 3] : 0.f;
             }
             const int c = c0 + lrow + 32 * i;   // centroid rows are zero-padded to dpad (a multiple of 4)
-            rb[i] = (c < nlist && kk < dpad) ? *(const float4 *)(cent + (int64_t)c * dpad + kk)
-                                             : make_float4(0.f, 0.f, 0.f, 0.f);
+            if (BF)
+                rbh[i] = (c < nlist && kk < dpad) ? *(const uint2 *)(cent_h + (int64_t)c * dpad + kk)
+                                                  : make_uint2(0u, 0u);
+            else
+                rbf[i] = (c < nlist && kk < dpad) ? *(const float4 *)(cent + (int64_t)c * dpad + kk)
+                                                  : make_float4(0.f, 0.f, 0.f, 0.f);
         }
     };
     auto lstore = [&]() {
@@ -97,19 +118,17 @@ __global__ __launch_bounds__(256) void k_coarse_gemm(const float *__restrict__ X
                 *reinterpret_cast<uint2 *>(&hA[rr][lk]) =
                     make_uint2(to_bf16_bits(ra[i].x) | (to_bf16_bits(ra[i].y) << 16),
                                to_bf16_bits(ra[i].z) | (to_bf16_bits(ra[i].w) << 16));
-                *reinterpret_cast<uint2 *>(&hB[rr][lk]) =
-                    make_uint2(to_bf16_bits(rb[i].x) | (to_bf16_bits(rb[i].y) << 16),
-                               to_bf16_bits(rb[i].z) | (to_bf16_bits(rb[i].w) << 16));
+                *reinterpret_cast<uint2 *>(&hB[rr][lk]) = rbh[i];
                 continue;
             }
             sA[lk + 0][rr] = ra[i].x;
             sA[lk + 1][rr] = ra[i].y;
             sA[lk + 2][rr] = ra[i].z;
             sA[lk + 3][rr] = ra[i].w;
-            sB[lk + 0][rr] = rb[i].x;
-            sB[lk + 1][rr] = rb[i].y;
-            sB[lk + 2][rr] = rb[i].z;
-            sB[lk + 3][rr] = rb[i].w;
+            sB[lk + 0][rr] = rbf[i].x;
+            sB[lk + 1][rr] = rbf[i].y;
+            sB[lk + 2][rr] = rbf[i].z;
+            sB[lk + 3][rr] = rbf[i].w;
         }
     };
     gload(0);
@@ -426,14 +445,17 @@ size_t coarse_select_smem(int dpad, int mmax) {
 }
 
 template <int GMIN>
-static void coarse_gemm_t(hipStream_t st, const float *X, int n, int d, const float *cent, int dpad,
+static void coarse_gemm_t(hipStream_t st, const float *X, int n, int d, const float *cent,
+                          const uint16_t *cent_h, int dpad,
                           const float *cn2, int nlist, int metric, float *out, int ldo, const int32_t *ctl,
                           int gated, int bf) {
-    const dim3 grid((n + GM - 1) / GM, (nlist + GN - 1) / GN);
+    const int nrb = (n + GM - 1) / GM, ncb = (nlist + GN - 1) / GN;
+    const int xcd_map = ncb >= 8 ? 1 : 0;   // fewer centroid blocks than XCDs: plain order
+    const unsigned grid = xcd_map ? (unsigned)(8 * ((ncb + 7) / 8) * nrb) : (unsigned)(nrb * ncb);
     const bool vec = (d % 4 == 0) && (((uintptr_t)X & 15) == 0);
 #define SIVF_GEMM(M, V, B)                                                                                      \
-    hipLaunchKernelGGL((k_coarse_gemm<M, GMIN, V, B>), grid, dim3(256), 0, st, X, n, d, cent, dpad, cn2, nlist, \
-                       out, ldo, ctl, gated)
+    hipLaunchKernelGGL((k_coarse_gemm<M, GMIN, V, B>), dim3(grid), dim3(256), 0, st, X, n, d, cent, cent_h, dpad, \
+                       cn2, nlist, out, ldo, ctl, gated, xcd_map)
 #define SIVF_GEMM_B(M, V)                                                                                       \
     do {                                                                                                        \
         if (bf) SIVF_GEMM(M, V, 1); else SIVF_GEMM(M, V, 0);                                                    \
@@ -447,20 +469,20 @@ static void coarse_gemm_t(hipStream_t st, const float *X, int n, int d, const fl
 #undef SIVF_GEMM
 }
 
-void launch_coarse_gemm(hipStream_t st, const float *X, int n, int d, const float *cent, int dpad,
+void launch_coarse_gemm(hipStream_t st, const float *X, int n, int d, const float *cent, const uint16_t *cent_h, int dpad,
                         const float *cn2, int nlist, int metric, float *out, const int32_t *ctl,
                         int gated, int bf) {
-    if (n > 0) coarse_gemm_t<0>(st, X, n, d, cent, dpad, cn2, nlist, metric, out, nlist, ctl, gated, bf);
+    if (n > 0) coarse_gemm_t<0>(st, X, n, d, cent, cent_h, dpad, cn2, nlist, metric, out, nlist, ctl, gated, bf);
 }
 
 int coarse_groups(int nlist) { return (nlist + GROUP - 1) / GROUP; }
 
 void launch_coarse_assign(hipStream_t st, float *scratch, const float *X, int n, int d, const float *cent,
-                          int dpad, const float *cn2, const double *cmax, int nlist, int metric, int32_t *out,
+                          const uint16_t *cent_h, int dpad, const float *cn2, const double *cmax, int nlist, int metric, int32_t *out,
                           int out_stride, const int32_t *ctl, int gated, int bf) {
     if (n <= 0) return;
     const int ldg = coarse_groups(nlist);
-    coarse_gemm_t<1>(st, X, n, d, cent, dpad, cn2, nlist, metric, scratch, ldg, ctl, gated, bf);
+    coarse_gemm_t<1>(st, X, n, d, cent, cent_h, dpad, cn2, nlist, metric, scratch, ldg, ctl, gated, bf);
     hipLaunchKernelGGL(k_coarse_argmin, dim3((n + 3) / 4), dim3(256), 0, st, scratch, ldg, X, n, d, cent, dpad,
                        cmax, nlist, metric, out, out_stride, ctl, gated, bf);
 }

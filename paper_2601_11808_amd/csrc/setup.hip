@@ -24,7 +24,7 @@ __global__ void k_fill_i64_kernel(int64_t *p, int64_t n, int64_t v) {
 // One block per centroid: zero-padded copy, fp32 squared norm, fp64 norm and
 // the running maximum norm (non-negative doubles order like their bits).
 __global__ __launch_bounds__(256) void k_init_cent(float *cent, float *cn2, double *cnorm, double *cmax,
-                                                   const float *src, int d, int dpad) {
+                                                   uint16_t *cent_h, const float *src, int d, int dpad) {
     __shared__ float s32[4];
     __shared__ double s64[4];
     const int l = blockIdx.x, tid = threadIdx.x;
@@ -33,6 +33,7 @@ __global__ __launch_bounds__(256) void k_init_cent(float *cent, float *cn2, doub
     for (int j = tid; j < dpad; j += 256) {
         const float v = j < d ? src[(int64_t)l * d + j] : 0.f;
         cent[(int64_t)l * dpad + j] = v;
+        if (cent_h) cent_h[(int64_t)l * dpad + j] = (uint16_t)to_bf16_bits(v);
         a = fmaf(v, v, a);
         b = __fma_rn((double)v, (double)v, b);
     }
@@ -82,7 +83,7 @@ void launch_init_state(hipStream_t st, const Dev &S, const float *centroids) {
     const int dpad = S.dp4 * 4;
     launch_fill_i64(st, (int64_t *)S.cmax, 1, 0);
     hipLaunchKernelGGL(k_init_cent, dim3(S.nlist), dim3(256), 0, st, (float *)S.cent, (float *)S.cn2,
-                       (double *)S.cnorm, (double *)S.cmax, centroids, S.d, dpad);
+                       (double *)S.cnorm, (double *)S.cmax, (uint16_t *)S.cent_h, centroids, S.d, dpad);
     hipLaunchKernelGGL(k_iota_i32, dim3(grid_for(S.num_slabs)), dim3(256), 0, st, S.free_slabs, S.num_slabs);
     hipLaunchKernelGGL(k_iota_i32, dim3(grid_for(S.num_pages)), dim3(256), 0, st, S.free_pages, S.num_pages);
     fill(st, S.sowner, S.num_slabs, -1);

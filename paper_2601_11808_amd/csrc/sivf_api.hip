@@ -30,7 +30,7 @@ struct Layout {
     int dp4, kcap, coarse_rows;
     int64_t num_pages, dir_cap, max_items, slot_cap;
     size_t total;
-    size_t cent, cn2, cnorm, cmax, data, sids, sowner, sord, free_slabs, free_pages, pages, dir, len, att, mark,
+    size_t cent, cent_h, cn2, cnorm, cmax, data, sids, sowner, sord, free_slabs, free_pages, pages, dir, len, att, mark,
         ctl, lists, b_assign, b_rank, b_rec, b_seg, dt, probes, pair_rank, list_pairs, item_list, item_tile,
         item_chunk, partials, hdata, xnorm, rr_dist, rr_lab, dt_s;
 };
@@ -76,6 +76,7 @@ Layout make_layout(const sivf_config *c) {
         return o;
     };
     L.cent = take((size_t)nl * L.dp4 * 16);
+    L.cent_h = take(c->storage != SIVF_F32 ? (size_t)nl * L.dp4 * 8 : 0);
     L.cn2 = take((size_t)nl * 4);
     L.cnorm = take((size_t)nl * 8);
     L.cmax = take(8);
@@ -200,11 +201,11 @@ void coarse(sivf_index *ix, hipStream_t st, float *dt, const float *x, int64_t n
         const int nr = (int)((n - r0) < ix->L.coarse_rows ? (n - r0) : ix->L.coarse_rows);
         const float *xr = x + r0 * S.d;
         if (m == 1 && !m_per_row && mmax == 1) {
-            launch_coarse_assign(st, dt, xr, nr, S.d, S.cent, dpad, S.cn2, S.cmax, S.nlist, S.metric,
+            launch_coarse_assign(st, dt, xr, nr, S.d, S.cent, S.cent_h, dpad, S.cn2, S.cmax, S.nlist, S.metric,
                                  out + r0 * out_stride, out_stride, S.ctl, gated, bf);
             continue;
         }
-        launch_coarse_gemm(st, xr, nr, S.d, S.cent, dpad, S.cn2, S.nlist, S.metric, dt, S.ctl, gated, bf);
+        launch_coarse_gemm(st, xr, nr, S.d, S.cent, S.cent_h, dpad, S.cn2, S.nlist, S.metric, dt, S.ctl, gated, bf);
         launch_coarse_select(st, dt, xr, nr, S.d, S.cent, dpad, S.cnorm, S.cmax, S.nlist, S.metric, m,
                              m_per_row ? m_per_row + r0 : nullptr, mmax, out + r0 * out_stride, out_stride,
                              S.ctl, gated, bf);
@@ -326,6 +327,7 @@ sivf_status sivf_create(const sivf_config *cfg, const float *centroids, void *wo
     S.dir_cap = L.dir_cap;
     S.id_capacity = cfg->id_capacity;
     S.cent = (const float *)(w + L.cent);
+    S.cent_h = cfg->storage != SIVF_F32 ? (const uint16_t *)(w + L.cent_h) : nullptr;
     S.cn2 = (const float *)(w + L.cn2);
     S.cnorm = (const double *)(w + L.cnorm);
     S.cmax = (const double *)(w + L.cmax);
@@ -609,7 +611,7 @@ sivf_status sivf_coarse_scores(sivf_index *ix, int64_t n, const float *x, float 
     ix->last = as_stream(stream);
     if (n == 0) return SIVF_OK;
     const Dev &S = ix->S;
-    launch_coarse_gemm(as_stream(stream), x, (int)n, S.d, S.cent, S.dp4 * 4, S.cn2, S.nlist, S.metric, scores,
+    launch_coarse_gemm(as_stream(stream), x, (int)n, S.d, S.cent, S.cent_h, S.dp4 * 4, S.cn2, S.nlist, S.metric, scores,
                        S.ctl, 0, S.storage != SIVF_F32);
     return launched(ix);
 }

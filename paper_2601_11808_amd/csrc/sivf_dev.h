@@ -49,6 +49,7 @@ struct Dev {
     int persistent;       // search schedule: 0 = one wave per work item; 1 = resident waves pull items
     int64_t num_slabs, num_pages, dir_cap, id_capacity;
     const float *cent;    // [nlist][dp4*4], zero padded
+    const uint16_t *cent_h;  // [nlist][dp4*4] bf16 copy (reduced-precision indexes: coarse GEMM operand)
     const float *cn2;     // [nlist] fp32 squared norms
     const double *cnorm;  // [nlist] fp64 norms
     const double *cmax;   // [1] largest centroid norm

@@ -13,14 +13,14 @@ void launch_init_state(hipStream_t st, const Dev &S, const float *centroids);
 
 // ---- coarse quantizer (coarse.hip)
 size_t coarse_select_smem(int dpad, int mmax);
-void launch_coarse_gemm(hipStream_t st, const float *X, int n, int d, const float *cent, int dpad,
+void launch_coarse_gemm(hipStream_t st, const float *X, int n, int d, const float *cent, const uint16_t *cent_h, int dpad,
                         const float *cn2, int nlist, int metric, float *out, const int32_t *ctl,
                         int gated, int bf);
 // m = 1 (nearest list per row): group-minimum GEMM into scratch (n x
 // ceil(nlist / 16) floats), then the exact argmin; rows with a non-finite
 // coordinate get -1.
 void launch_coarse_assign(hipStream_t st, float *scratch, const float *X, int n, int d, const float *cent,
-                          int dpad, const float *cn2, const double *cmax, int nlist, int metric, int32_t *out,
+                          const uint16_t *cent_h, int dpad, const float *cn2, const double *cmax, int nlist, int metric, int32_t *out,
                           int out_stride, const int32_t *ctl, int gated, int bf);
 void launch_coarse_select(hipStream_t st, const float *dt, const float *X, int n, int d, const float *cent,
                           int dpad, const double *cnorm, const double *cmax, int nlist, int metric,
