@@ -19,6 +19,8 @@ Other modes (not the headline line):
                        skewed lists, 32k queries with per-query nprobe
                        U[8,128] and k in {1,10,100}, +20k / -20k random ids
                        per step, autotuned schedule, eager and graph steps
+  --workload mutation  bulk mutation kernels: the 1M window inserted in one
+                       call, then half of it deleted (random ids) in one call
   --workload serve     the serving form: a 50M-vector fp16 window (d=128,
                        16,384 lists, slab 128) under a Poisson stream of
                        searches, inserts and deletes through the
@@ -52,11 +54,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="window", choices=["window", "tiny", "precision", "serve", "batched"])
+    ap.add_argument("--workload", default="window",
+                    choices=["window", "tiny", "precision", "serve", "batched", "mutation"])
     ap.add_argument("--serve-seconds", type=float, default=5.0, help="serve: length of the arrival stream")
     ap.add_argument("--serve-rate", type=float, default=2000.0, help="serve: Poisson arrival rate (req/s)")
     ap.add_argument("--serve-n", type=int, default=50_000_000, help="serve: steady-state window size")
     ap.add_argument("--storage", default=None, choices=list(STORAGE))
+    ap.add_argument("--batch", type=int, default=None, help="window/tiny: vectors inserted and evicted per step")
     ap.add_argument("--rerank", type=int, default=4, help="re-rank factor R for bf16/f16 storage")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--recall-queries", type=int, default=1000)
@@ -148,6 +152,8 @@ def main():
         return serve_main(a)
     if a.workload == "batched":
         return batched_main(a)
+    if a.workload == "mutation":
+        return mutation_main(a)
     import torch
     import paper_2601_11808_amd as sivf
     import workloads
@@ -157,6 +163,8 @@ def main():
     dev = torch.device("cuda:0")
     t0 = time.time()
     w = {"window": workloads.window, "tiny": workloads.tiny, "precision": workloads.precision}[a.workload]()
+    if a.batch:
+        w.batch = a.batch
     storage = a.storage or ("bf16" if a.workload == "precision" else "f32")
     st_code = STORAGE[storage]
     rerank = a.rerank if st_code else 0
@@ -263,9 +271,17 @@ def main():
     # recall@10 and the nprobe sweep on the final window (base ids >= B*T2
     # plus batches 1..T2) against exact kNN (float64)
     nrq = min(a.recall_queries, nq)
+    # live at the end: ids >= B * T2 (every step evicted the oldest B)
     keep = ids >= B * T2
-    xw = np.concatenate([x[keep]] + [w.stream_batch(t)[0] for t in range(1, T2 + 1)])
-    idw = np.concatenate([ids[keep]] + [w.stream_batch(t)[1] for t in range(1, T2 + 1)])
+    parts_x, parts_i = [x[keep]], [ids[keep]]
+    for t in range(1, T2 + 1):
+        xb, idb = w.stream_batch(t)
+        if idb[-1] >= B * T2:
+            sel = idb >= B * T2
+            parts_x.append(xb[sel])
+            parts_i.append(idb[sel])
+    xw, idw = np.concatenate(parts_x), np.concatenate(parts_i)
+    assert xw.shape[0] == w.n_base
     t0 = time.time()
     gt = exact_topk(xw, idw, q[:nrq], k, w.metric)
     del xw, idw
@@ -520,6 +536,68 @@ def batched_main(a):
                      "peak": round(ALU_PEAK_TFLOPS, 2), "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TFLOPS, 4),
                      "evals_per_launch": evals, "avg_launch_ms": round(scan_ms, 4)},
         "bulk_load_vec_per_s": round(N / load_s, 1),
+    }
+    print(json.dumps(res), flush=True)
+
+
+def mutation_main(a):
+    """Mutation kernels at bulk scale on the window data: one insert call of
+    the whole 1M-vector window (batch = window) and one delete call of half of
+    it (500k uniformly random ids), each timed by the library's HIP events.
+    Algorithmic bytes: insert 4d (read) + 4d (write) + 4 (id) + 4 (address
+    table) per vector; delete 4 (address table read) + 2 (4d + 4) (tail entry
+    moved into the hole) + 8 (two address-table writes) per removed id."""
+    import torch
+    import paper_2601_11808_amd as sivf
+    import workloads
+
+    if not os.path.exists(sivf.LIB_PATH):
+        raise SystemExit("libsivf.so is not built: run python -c 'import __graft_entry__ as g; g.build()'")
+    dev = torch.device("cuda:0")
+    w = workloads.window()
+    x, ids = w.base()
+    N, d = x.shape
+    num_slabs = int(1.15 * N / w.slab) + w.nlist
+    ix = sivf.Index(w.dim, w.nlist, w.centroids, metric=w.metric, slab_capacity=w.slab, num_slabs=num_slabs,
+                    id_capacity=N, max_batch=N, max_queries=16, max_k=16, max_nprobe=16, device="cuda:0")
+    xd, idd = torch.from_numpy(x).to(dev), torch.from_numpy(ids).to(dev)
+    rng = np.random.default_rng([w.seed, 7, 0])
+    reps = max(1, a.steps // 10)
+    add_ms, rm_ms = [], []
+    for r in range(reps + 1):
+        rm = torch.from_numpy(np.sort(rng.choice(N, N // 2, replace=False)).astype(np.int64)).to(dev)
+        torch.cuda.synchronize()
+        ix.profile_read()
+        ix.profile(True)
+        ix.add(xd, idd)
+        assert ix.sync() == 0
+        pa = ix.profile_read()
+        nr = ix.remove(rm)
+        assert ix.sync() == 0
+        pr = ix.profile_read()
+        ix.profile(False)
+        assert int(nr.item()) == N // 2
+        ix.remove(idd)                      # empty the index for the next repetition
+        assert ix.sync() == 0 and ix.stats()["live"] == 0
+        if r > 0:                           # the first repetition warms up
+            add_ms.append(pa["add"][0])
+            rm_ms.append(pr["remove"][0])
+    ins_b = N * (4 * d + 4 * d + 8)
+    del_b = (N // 2) * (4 + 2 * (4 * d + 4) + 8)
+    am, rmm = float(np.median(add_ms)), float(np.median(rm_ms))
+    res = {
+        "metric": "insert/delete vectors/s at bulk scale (whole-window insert, half-window delete)",
+        "value": round(N / (am * 1e-3), 1), "unit": "inserted vectors/s",
+        "n_gpus": 1, "steps": reps, "warmup": 1, "ms_per_step": round(am + rmm, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"mutation: window data N={N}, d={d}, nlist={w.nlist}, slab={w.slab}; insert {N} "
+                               f"in one call, delete {N // 2} random ids in one call", "parallelism": "single GPU"},
+        "insert_ms": round(am, 3), "insert_vec_per_s": round(N / (am * 1e-3), 1),
+        "insert_algorithmic_GBps": round(ins_b / (am * 1e-3) / 1e9, 1),
+        "delete_ms": round(rmm, 3), "delete_vec_per_s": round((N // 2) / (rmm * 1e-3), 1),
+        "delete_algorithmic_GBps": round(del_b / (rmm * 1e-3) / 1e9, 1),
+        "note": "insert time includes the exact coarse assignment (FP32 MFMA GEMM + FP64 re-check); "
+                "per-kernel bandwidth of the copy kernels comes from the kernel trace",
     }
     print(json.dumps(res), flush=True)
 

@@ -149,8 +149,8 @@ __global__ __launch_bounds__(256) void k_coarse_gemm(const float *__restrict__ X
             for (int i = 0; i < 4; i++)
 #pragma unroll
                 for (int j = 0; j < 4; j++)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(cbf16x8, av[i]),
-                                                                       __builtin_bit_cast(cbf16x8, bv[j]),
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(cbf16x8, bv[j]),
+                                                                       __builtin_bit_cast(cbf16x8, av[i]),
                                                                        acc[i][j], 0, 0, 0);
             continue;
         }
@@ -166,7 +166,7 @@ __global__ __launch_bounds__(256) void k_coarse_gemm(const float *__restrict__ X
             for (int i = 0; i < 4; i++)
 #pragma unroll
                 for (int j = 0; j < 4; j++)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[j], av[i], acc[i][j], 0, 0, 0);
         }
     }
     // |x|^2 of each row: the 8 loader threads of a row are adjacent lanes
@@ -179,31 +179,48 @@ __global__ __launch_bounds__(256) void k_coarse_gemm(const float *__restrict__ X
         if ((tid & 7) == 0) sqn[lrow + 32 * i] = v;
     }
     __syncthreads();
-    // lane holds C[4 * (lane / 16) + r][lane % 16] of each 16x16 block
+    // The MFMAs compute the transposed tile (centroids as rows): lane holds
+    // the dot of row wr + 16 i + lane % 16 with the 4 consecutive centroids
+    // wc + 16 j + 4 (lane / 16) .. +3, so a 16-list group minimum takes 3
+    // in-register mins and 2 lane exchanges, and full rows store 4 floats.
+    const bool vec4 = (ldo & 3) == 0;
 #pragma unroll
-    for (int j = 0; j < 4; j++) {
-        const int gc0 = c0 + wc + 16 * j;
-        const int gc = gc0 + (lane & 15);
-        const float c2 = (METRIC == 0 && gc < nlist) ? cn2[gc] : 0.f;
+    for (int i = 0; i < 4; i++) {
+        const int row = wr + 16 * i + (lane & 15);
+        const int gr = r0 + row;
+        const float sq = sqn[row];
 #pragma unroll
-        for (int i = 0; i < 4; i++)
+        for (int j = 0; j < 4; j++) {
+            const int gc0 = c0 + wc + 16 * j;
+            const int gcb = gc0 + 4 * (lane >> 4);
+            float v[4];
 #pragma unroll
             for (int r = 0; r < 4; r++) {
-                const int row = wr + 16 * i + 4 * (lane >> 4) + r;
-                const int gr = r0 + row;
+                const int gc = gcb + r;
+                const float c2 = (METRIC == 0 && gc < nlist) ? cn2[gc] : 0.f;
                 const float dot = acc[i][j][r];
-                float v = METRIC == 0 ? (sqn[row] + c2) - 2.0f * dot : -dot;
-                if (!GMIN) {
-                    if (gr < n && gc < nlist) out[(int64_t)gr * ldo + gc] = v;
-                } else {
-                    v = (gc < nlist && v == v) ? v : __builtin_inff();
-                    v = fminf(v, __shfl_xor(v, 1));
-                    v = fminf(v, __shfl_xor(v, 2));
-                    v = fminf(v, __shfl_xor(v, 4));
-                    v = fminf(v, __shfl_xor(v, 8));
-                    if ((lane & 15) == 0 && gr < n && gc0 < nlist) out[(int64_t)gr * ldo + gc0 / GROUP] = v;
-                }
+                v[r] = METRIC == 0 ? (sq + c2) - 2.0f * dot : -dot;
             }
+            if (!GMIN) {
+                if (gr < n) {
+                    float *o = out + (int64_t)gr * ldo + gcb;
+                    if (vec4 && gcb + 3 < nlist) {
+                        *reinterpret_cast<float4 *>(o) = make_float4(v[0], v[1], v[2], v[3]);
+                    } else {
+#pragma unroll
+                        for (int r = 0; r < 4; r++)
+                            if (gcb + r < nlist) o[r] = v[r];
+                    }
+                }
+            } else {
+                float m = __builtin_inff();
+#pragma unroll
+                for (int r = 0; r < 4; r++) m = (gcb + r < nlist && v[r] == v[r]) ? fminf(m, v[r]) : m;
+                m = fminf(m, __shfl_xor(m, 16));
+                m = fminf(m, __shfl_xor(m, 32));
+                if ((lane >> 4) == 0 && gr < n && gc0 < nlist) out[(int64_t)gr * ldo + gc0 / GROUP] = m;
+            }
+        }
     }
 }
 
@@ -222,18 +239,44 @@ __device__ __forceinline__ double coarse_err(int metric, int d, int bf, double q
     return e + (double)d * 0x1p-120;
 }
 
-__device__ __forceinline__ double canon_dist(const float *sx, const float *__restrict__ c, int d,
-                                             int metric) {
+// Canonical FP64 coarse distance (sequential fma over ascending dimensions;
+// IP: minus the dot product) of row x to centroid c.  c is 16-byte aligned
+// and zero-padded to a multiple of 4; x is read up to d (a padded x would add
+// exact zeros).  Centroid values are fetched 32 at a time (8 float4) ahead of
+// their fmas, so the loop is not one memory latency per dimension.
+__device__ __forceinline__ double canon_dist(const float *x, const float *__restrict__ c, int d, int metric) {
     double r = 0.0;
-    if (metric == 0) {
-        for (int j = 0; j < d; j++) {
-            const double t = (double)sx[j] - (double)c[j];
-            r = __fma_rn(t, t, r);
+    const float4 *c4 = reinterpret_cast<const float4 *>(c);
+    int j = 0;
+    for (; j + 32 <= d; j += 32) {
+        float4 cv[8];
+#pragma unroll
+        for (int e = 0; e < 8; e++) cv[e] = c4[(j >> 2) + e];
+#pragma unroll
+        for (int e = 0; e < 8; e++) {
+            const float cs[4] = {cv[e].x, cv[e].y, cv[e].z, cv[e].w};
+#pragma unroll
+            for (int f = 0; f < 4; f++) {
+                const double xv = (double)x[j + 4 * e + f];
+                if (metric == 0) {
+                    const double t = xv - (double)cs[f];
+                    r = __fma_rn(t, t, r);
+                } else {
+                    r = __fma_rn(xv, (double)cs[f], r);
+                }
+            }
         }
-        return r;
     }
-    for (int j = 0; j < d; j++) r = __fma_rn((double)sx[j], (double)c[j], r);
-    return -r;
+    for (; j < d; j++) {
+        const double xv = (double)x[j];
+        if (metric == 0) {
+            const double t = xv - (double)c[j];
+            r = __fma_rn(t, t, r);
+        } else {
+            r = __fma_rn(xv, (double)c[j], r);
+        }
+    }
+    return metric == 0 ? r : -r;
 }
 
 constexpr int SEL_CAP = 512;   // candidates buffered per exact re-check round
@@ -371,7 +414,8 @@ __global__ __launch_bounds__(256) void k_coarse_argmin(const float *__restrict__
                                                        const int32_t *ctl, int gated, int bf) {
     if (gated && call_failed(ctl)) return;
     const int lane = threadIdx.x & 63;
-    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    // wave-uniform row: its coordinates are read through the scalar cache
+    const int row = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
     if (row >= n) return;
     const float *xr = X + (int64_t)row * d;
     double q2 = 0.0;
@@ -410,17 +454,7 @@ __global__ __launch_bounds__(256) void k_coarse_argmin(const float *__restrict__
             }
             const int l = sel * GROUP + (lane & 15);
             if (sel >= 0 && l < nlist) {
-                const float *c = cent + (int64_t)l * dpad;
-                double r = 0.0;
-                if (metric == 0) {
-                    for (int j = 0; j < d; j++) {
-                        const double u = (double)xr[j] - (double)c[j];
-                        r = __fma_rn(u, u, r);
-                    }
-                } else {
-                    for (int j = 0; j < d; j++) r = __fma_rn((double)xr[j], (double)c[j], r);
-                    r = -r;
-                }
+                const double r = canon_dist(xr, cent + (int64_t)l * dpad, d, metric);
                 if (r < best || (r == best && l < bestl)) {
                     best = r;
                     bestl = l;
