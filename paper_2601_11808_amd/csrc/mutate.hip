@@ -93,6 +93,7 @@ __global__ __launch_bounds__(1024) void k_add_admit(Dev S) {
     for (int w = 0; w < 16; w++) tot += sred[w];
     const bool reject = tot > S.num_slabs;
     if (reject && tid == 0) fail_call(S.ctl, -2);
+    if (tid == 0) S.ctl[CTL_EBASE] = 0;
     for (int l = tid; l < S.nlist; l += 1024) {
         S.l_prem[l] = 0;
         if (reject) S.l_acnt[l] = 0;
@@ -114,7 +115,7 @@ __device__ __forceinline__ int owner_of(const int *es, int s) {
 }
 
 __global__ __launch_bounds__(256) void k_add_alloc(Dev S) {
-    __shared__ int s_es[256], s_nso[256], sbuf[4], s_base[2];
+    __shared__ int s_es[256], s_nso[256], sbuf[4], s_base[3];
     if (call_failed(S.ctl)) return;
     const int tid = threadIdx.x;
     const int l = blockIdx.x * 256 + tid;
@@ -124,18 +125,21 @@ __global__ __launch_bounds__(256) void k_add_alloc(Dev S) {
     const int newlen = oldlen + cnt;
     const int nso = cdiv(oldlen, S.C), nsn = cdiv(newlen, S.C);
     const int pgo = cdiv(nso, PAGE), pgn = cdiv(nsn, PAGE);
-    int tot_s, tot_p;
+    int tot_s, tot_p, tot_e;
     const int es = block_excl_scan<256>(nsn - nso, sbuf, &tot_s);
     const int ep = block_excl_scan<256>(pgn - pgo, sbuf, &tot_p);
+    const int ee = block_excl_scan<256>(cnt, sbuf, &tot_e);
     if (tid == 0) {
         s_base[0] = tot_s ? atomicSub(&S.ctl[CTL_SLAB_TOP], tot_s) - tot_s : 0;
         s_base[1] = tot_p ? atomicSub(&S.ctl[CTL_PAGE_TOP], tot_p) - tot_p : 0;
+        s_base[2] = tot_e ? atomicAdd(&S.ctl[CTL_EBASE], tot_e) : 0;   // this block's lists' new entries
     }
     s_es[tid] = es;
     s_nso[tid] = nso;
     __syncthreads();
     if (cnt > 0) {
         S.l_base[l] = oldlen;
+        S.l_eoff[l] = s_base[2] + ee;
         S.len[l] = newlen;
         S.l_acnt[l] = 0;
         for (int j = 0; j < pgn - pgo; j++)
@@ -154,25 +158,37 @@ __global__ __launch_bounds__(256) void k_add_alloc(Dev S) {
     }
 }
 
-// 16 lanes per vector; lane sub copies dimension chunks sub, sub+16, ...
-template <bool VEC>
-__global__ __launch_bounds__(256) void k_add_scatter(Dev S, int n, const float *__restrict__ x,
-                                                     const int64_t *__restrict__ ids,
-                                                     const int32_t *__restrict__ assign,
-                                                     const int32_t *__restrict__ rank) {
+// Entry order of the new entries: entry l_eoff[l] + rank is list l's rank-th
+// new position; inv[entry] = its source row.
+__global__ __launch_bounds__(256) void k_add_inv(Dev S, int n, const int32_t *__restrict__ assign,
+                                                 const int32_t *__restrict__ rank, int32_t *__restrict__ inv) {
     if (call_failed(S.ctl)) return;
-    const int gid = blockIdx.x * 256 + threadIdx.x;
-    const int i = gid >> 4, sub = gid & 15;
+    const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
     const int r = rank[i];
-    if (r < 0) return;
+    if (r >= 0) inv[S.l_eoff[assign[i]] + r] = i;
+}
+
+// One lane per new entry, in entry order: consecutive lanes fill consecutive
+// slots of a list, so each 16-byte dimension chunk of 64 entries is one
+// contiguous KiB write; the lane reads its source row in order.
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_add_scatter(Dev S, const float *__restrict__ x,
+                                                     const int64_t *__restrict__ ids,
+                                                     const int32_t *__restrict__ assign,
+                                                     const int32_t *__restrict__ rank,
+                                                     const int32_t *__restrict__ inv) {
+    if (call_failed(S.ctl)) return;
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= S.ctl[CTL_EBASE]) return;
+    const int i = inv[e];
     const int l = assign[i];
-    const int pos = S.l_base[l] + r;
+    const int pos = S.l_base[l] + rank[i];
     const int slab = slab_of(S, l, pos / S.C);
     const int slot = pos % S.C;
     float4 *dst = S.data + (int64_t)slab * S.dp4 * S.C + slot;
     const float *xr = x + (int64_t)i * S.d;
-    for (int c = sub; c < S.dp4; c += 16) {
+    for (int c = 0; c < S.dp4; c++) {
         float4 v;
         if (VEC) {
             v = reinterpret_cast<const float4 *>(xr)[c];
@@ -191,28 +207,22 @@ __global__ __launch_bounds__(256) void k_add_scatter(Dev S, int n, const float *
         // and the fp32 squared norm of the rounded row (L2 scan epilogue)
         uint4 *hdst = S.hdata + (int64_t)slab * S.dp8 * S.C + slot;
         float nrm = 0.f;
-        for (int c = sub; c < S.dp8; c += 16) {
+        for (int c = 0; c < S.dp8; c++) {
             uint32_t h[8];
 #pragma unroll
-            for (int e = 0; e < 8; e++) {
-                const int j = 8 * c + e;
+            for (int q = 0; q < 8; q++) {
+                const int j = 8 * c + q;
                 const float v = j < S.d ? xr[j] : 0.f;
-                h[e] = S.storage == 1 ? to_bf16_bits(v) : to_f16_bits(v);
-                const float r = S.storage == 1 ? bf16_bits_to_float(h[e]) : f16_bits_to_float(h[e]);
+                h[q] = S.storage == 1 ? to_bf16_bits(v) : to_f16_bits(v);
+                const float r = S.storage == 1 ? bf16_bits_to_float(h[q]) : f16_bits_to_float(h[q]);
                 nrm = fmaf(r, r, nrm);
             }
             hdst[(int64_t)c * S.C] = make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16),
                                                 h[6] | (h[7] << 16));
         }
-        if (S.xnorm) {
-            nrm += __shfl_xor(nrm, 8, 16);
-            nrm += __shfl_xor(nrm, 4, 16);
-            nrm += __shfl_xor(nrm, 2, 16);
-            nrm += __shfl_xor(nrm, 1, 16);
-            if (sub == 0) S.xnorm[g] = nrm;
-        }
+        if (S.xnorm) S.xnorm[g] = nrm;
     }
-    if (sub == 0) {
+    {
         const int64_t u = ids[i];
         S.sids[g] = (uint32_t)u;
         S.att[u] = g;
@@ -431,13 +441,14 @@ void launch_add_alloc(hipStream_t st, const Dev &S) {
 }
 
 void launch_add_scatter(hipStream_t st, const Dev &S, int n, const float *x, const int64_t *ids, const Batch &B) {
+    hipLaunchKernelGGL(k_add_inv, dim3(blocks(n)), dim3(256), 0, st, S, n, B.assign, B.rank, B.inv);
     const bool vec = (S.d % 4 == 0) && (((uintptr_t)x & 15) == 0);
     if (vec)
-        hipLaunchKernelGGL(k_add_scatter<true>, dim3(blocks((int64_t)n * 16)), dim3(256), 0, st, S, n, x, ids,
-                           B.assign, B.rank);
+        hipLaunchKernelGGL(k_add_scatter<true>, dim3(blocks(n)), dim3(256), 0, st, S, x, ids, B.assign, B.rank,
+                           B.inv);
     else
-        hipLaunchKernelGGL(k_add_scatter<false>, dim3(blocks((int64_t)n * 16)), dim3(256), 0, st, S, n, x, ids,
-                           B.assign, B.rank);
+        hipLaunchKernelGGL(k_add_scatter<false>, dim3(blocks(n)), dim3(256), 0, st, S, x, ids, B.assign, B.rank,
+                           B.inv);
 }
 
 void launch_add_cleanup(hipStream_t st, const Dev &S, int n, const int64_t *ids) {

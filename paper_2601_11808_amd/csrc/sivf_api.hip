@@ -31,7 +31,7 @@ struct Layout {
     int64_t num_pages, dir_cap, max_items, slot_cap;
     size_t total;
     size_t cent, cent_h, cn2, cnorm, cmax, data, sids, sowner, sord, free_slabs, free_pages, pages, dir, len, att, mark,
-        ctl, lists, b_assign, b_rank, b_rec, b_seg, dt, probes, pair_rank, list_pairs, item_list, item_tile,
+        ctl, lists, b_assign, b_rank, b_rec, b_seg, b_inv, dt, probes, pair_rank, list_pairs, item_list, item_tile,
         item_chunk, partials, hdata, xnorm, rr_dist, rr_lab, dt_s;
 };
 
@@ -92,11 +92,12 @@ Layout make_layout(const sivf_config *c) {
     L.att = take((size_t)c->id_capacity * 4);
     L.mark = take((size_t)c->id_capacity * 4);
     L.ctl = take(CTL_WORDS * 4);
-    L.lists = take((size_t)15 * nl * 4);
+    L.lists = take((size_t)16 * nl * 4);
     L.b_assign = take((size_t)c->max_batch * 4);
     L.b_rank = take((size_t)c->max_batch * 4);
     L.b_rec = take((size_t)c->max_batch * 4);
     L.b_seg = take((size_t)c->max_batch * 4);
+    L.b_inv = take((size_t)c->max_batch * 4);
     L.dt = take((size_t)L.coarse_rows * nl * 4);     // coarse scratch of inserts
     L.dt_s = take((size_t)L.coarse_rows * nl * 4);   // coarse scratch of searches (they may overlap inserts)
     L.probes = take((size_t)npairs * 4);
@@ -344,13 +345,14 @@ sivf_status sivf_create(const sivf_config *cfg, const float *centroids, void *wo
     S.mark = (int32_t *)(w + L.mark);
     S.ctl = (int32_t *)(w + L.ctl);
     int32_t *lists = (int32_t *)(w + L.lists);
-    int32_t **lp[] = {&S.l_acnt, &S.l_prem, &S.l_base, &S.l_m, &S.l_off, &S.l_newlen,
+    int32_t **lp[] = {&S.l_acnt, &S.l_prem, &S.l_base, &S.l_eoff, &S.l_m, &S.l_off, &S.l_newlen,
                       &S.l_q, &S.l_s, &S.l_h, &S.l_qc, &S.l_qcs, &S.l_qoff, &S.l_snap, &S.l_pbase, &S.l_ioff};
-    for (int i = 0; i < 15; i++) *lp[i] = lists + (size_t)i * cfg->nlist;
+    for (int i = 0; i < 16; i++) *lp[i] = lists + (size_t)i * cfg->nlist;
     ix->B.assign = (int32_t *)(w + L.b_assign);
     ix->B.rank = (int32_t *)(w + L.b_rank);
     ix->B.rec = (uint32_t *)(w + L.b_rec);
     ix->B.seg = (int32_t *)(w + L.b_seg);
+    ix->B.inv = (int32_t *)(w + L.b_inv);
     ix->dt = (float *)(w + L.dt);
     ix->dt_s = (float *)(w + L.dt_s);
     ix->W.probes = (int32_t *)(w + L.probes);

@@ -34,6 +34,7 @@ enum Ctl {
     CTL_NITEMS = 5,     // search: work items of the current call
     CTL_SEQ = 6,        // sequence number of the current add/remove call; its last kernel bumps it
     CTL_CHUNK = 7,      // search: log2 of the positions per work item (a list's chunk)
+    CTL_EBASE = 8,      // add: new entries handed out so far (per-list entry offsets)
     CTL_XB = 16,        // search: first item of each XCD's range (words 16..24; word 24 = item count)
     CTL_WORK0 = 64,     // search, persistent schedule: 8 work counters, one per XCD range of items,
     CTL_WORK_STRIDE = 32,  // each on its own 128-byte line (words 64, 96, .., 288)
@@ -64,7 +65,7 @@ struct Dev {
     int32_t *mark;
     int32_t *ctl;
     // per-list scratch (nlist each)
-    int32_t *l_acnt, *l_prem, *l_base;               // add
+    int32_t *l_acnt, *l_prem, *l_base, *l_eoff;      // add
     int32_t *l_m, *l_off, *l_newlen, *l_q, *l_s, *l_h; // remove
     int32_t *l_qc, *l_qcs, *l_qoff;                  // search
     int32_t *l_snap;   // search: list lengths when the search was planned (it scans only these)

@@ -29,7 +29,7 @@ void launch_coarse_select(hipStream_t st, const float *dt, const float *X, int n
 
 // ---- mutation (mutate.hip)
 struct Batch {
-    int32_t *assign, *rank, *seg;
+    int32_t *assign, *rank, *seg, *inv;   // inv: source row of each new entry, entry-major
     uint32_t *rec;
 };
 void launch_add_prepare(hipStream_t st, const Dev &S, int n, const int64_t *ids);
