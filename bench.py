@@ -76,10 +76,10 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def recorded_traffic():
+def recorded_traffic(name="k_scan_window_1M.md"):
     """DRAM bytes per scan launch from the committed counter summary, or None
     when the scan source changed since the counters were taken."""
-    prof = os.path.join(ROOT, "profiles", "k_scan_window_1M.md")
+    prof = os.path.join(ROOT, "profiles", name)
     src = os.path.join(ROOT, "paper_2601_11808_amd", "csrc", "search.hip")
     try:
         kv = dict(l.split(": ", 1) for l in open(prof).read().splitlines() if l.startswith(("traffic_", "search_hip")))
@@ -331,11 +331,20 @@ def main():
                 "traffic_unit": "bytes per launch (DRAM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 "evals_per_launch": evals, "flops_per_eval": 3 * w.dim, "avg_launch_ms": round(scan_ms, 4)}
     else:
+        # a list is read once per tile of 16 queries: rounded rows (2 B per dim), ids, and for L2 the
+        # norms of the rounded rows
+        per_eval = (2.0 * w.dim + 4 + (4 if w.metric == 0 else 0)) / 16
+        gbps = evals * per_eval / (scan_ms * 1e-3) / 1e9
         flops = evals * 2.0 * 32 * ((w.dim + 31) // 32)   # MFMA work incl. padding to 32-dim blocks
-        achieved = flops / (scan_ms * 1e-3) / 1e12
-        roof = {"bound": "mfma", "kernel": "k_scan_mfma", "achieved": round(achieved, 3),
-                "peak": MFMA16_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / MFMA16_PEAK_TFLOPS, 4),
-                "traffic": None, "evals_per_launch": evals, "avg_launch_ms": round(scan_ms, 4)}
+        mfma_tf = flops / (scan_ms * 1e-3) / 1e12
+        prof_name = "k_scan_mfma_precision_10M.md" if a.workload == "precision" else None
+        roof = {"bound": "hbm", "kernel": "k_scan_mfma", "achieved": round(gbps, 1), "peak": 8000.0,
+                "unit": "GB/s", "frac": round(gbps / 8000.0, 4),
+                "traffic": recorded_traffic(prof_name) if prof_name else None,
+                "traffic_unit": "bytes per launch (DRAM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                "algorithmic_bytes_per_launch": int(evals * per_eval), "evals_per_launch": evals,
+                "mfma_tflops": round(mfma_tf, 3), "mfma_frac": round(mfma_tf / MFMA16_PEAK_TFLOPS, 4),
+                "avg_launch_ms": round(scan_ms, 4)}
     res = {
         "metric": "insert/delete vectors/s; search QPS at recall@10>=0.95; p99 window-step ms",
         "value": round(nq * a.steps / elapsed, 1),
