@@ -136,8 +136,10 @@ sivf_status sivf_search(sivf_index *ix, int64_t nq, const float *q, int32_t k,
 
 /* Search schedule autotuner (for uneven batches: skewed list lengths,
  * per-query nprobe and k).  Runs sivf_search on this sample batch once per
- * candidate schedule -- queries per work item (fp32 storage: 8 and 4; the
- * reduced-precision scan always takes 16) x positions per work item (2^10
+ * candidate schedule -- queries per work item (fp32 storage: 8 and 4, and
+ * 16 where the certified matrix-core scan applies: dim <= 256, max_k <= 64,
+ * slab_capacity >= 4; the reduced-precision scan always takes 16) x
+ * positions per work item (2^10
  * .. 2^17; longer lists are split into chunks scanned in parallel) x wave
  * schedule (one wave per work item, or resident waves pulling items from
  * per-XCD counters) -- times each with HIP events and keeps the fastest for
@@ -150,8 +152,10 @@ sivf_status sivf_tune_search(sivf_index *ix, int64_t nq, const float *q, int32_t
                              void *stream, int32_t *tile, int32_t *chunk_shift, int32_t *persistent);
 
 /* Set the search schedule directly (e.g. one found earlier by
- * sivf_tune_search): tile = queries per work item (fp32 storage: 4, or 8
- * when dim <= 1024; reduced precision: 16), 2^chunk_shift = positions per
+ * sivf_tune_search): tile = queries per work item (fp32 storage: 4, 8
+ * when dim <= 1024, or 16 -- the certified matrix-core scan, identical
+ * results -- when dim <= 256, max_k <= 64 and slab_capacity >= 4; reduced
+ * precision: 16), 2^chunk_shift = positions per
  * work item (6..31), persistent = 0 (one wave per item) or 1 (resident
  * waves).  SIVF_ERR_ARG for other values.  Applies to later calls. */
 sivf_status sivf_set_search_schedule(sivf_index *ix, int32_t tile, int32_t chunk_shift, int32_t persistent);

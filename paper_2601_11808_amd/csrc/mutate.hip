@@ -188,6 +188,7 @@ __global__ __launch_bounds__(256) void k_add_scatter(Dev S, const float *__restr
     const int slot = pos % S.C;
     float4 *dst = S.data + (int64_t)slab * S.dp4 * S.C + slot;
     const float *xr = x + (int64_t)i * S.d;
+    float n32 = 0.f;   // fp32 squared norm (fp32 storage)
     for (int c = 0; c < S.dp4; c++) {
         float4 v;
         if (VEC) {
@@ -200,8 +201,13 @@ __global__ __launch_bounds__(256) void k_add_scatter(Dev S, const float *__restr
             v.w = j + 3 < S.d ? xr[j + 3] : 0.f;
         }
         dst[(int64_t)c * S.C] = v;
+        n32 = fmaf(v.x, v.x, n32);
+        n32 = fmaf(v.y, v.y, n32);
+        n32 = fmaf(v.z, v.z, n32);
+        n32 = fmaf(v.w, v.w, n32);
     }
     const uint32_t g = (uint32_t)slab * (uint32_t)S.C + (uint32_t)slot;
+    if (S.storage == 0) S.xnorm[g] = n32;
     if (S.storage != 0) {
         // reduced-precision copy (round to nearest even), 8 dims per chunk,
         // and the fp32 squared norm of the rounded row (L2 scan epilogue)
@@ -344,8 +350,8 @@ __global__ __launch_bounds__(256) void k_rm_move(Dev S, int n, const uint32_t *_
             const uint4 *hs = S.hdata + (int64_t)(sg / S.C) * S.dp8 * S.C + sg % S.C;
             uint4 *hd = S.hdata + (int64_t)(dg / S.C) * S.dp8 * S.C + dg % S.C;
             for (int c = lane_id(); c < S.dp8; c += 64) hd[(int64_t)c * S.C] = hs[(int64_t)c * S.C];
-            if (S.xnorm && lane_id() == 0) S.xnorm[dg] = S.xnorm[sg];
         }
+        if (S.xnorm && lane_id() == 0) S.xnorm[dg] = S.xnorm[sg];
     }
     if (hole) {
         const uint32_t id = S.sids[src];

@@ -786,7 +786,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
     qn += __shfl_xor(qn, 16);
     qn += __shfl_xor(qn, 32);
     __syncthreads();
-    uint32_t thr = skq[qcol] > 0 ? 0xFFFFFFFFu : 0u;   // threshold of query qcol
+    uint32_t thr = skq[qcol] > 0 ? 0xFFFFFFFFu : 0u;   // threshold of query qcol (high word of its k-th key)
+    // The same threshold as a float: a value passes when its key's high word is
+    // at most thr, i.e. (L2) !(v > thr_f) or (IP) !(v < thr_f).  thr = ~0
+    // (list not yet full) maps to NaN, which passes everything.
+    const bool live = qcol < nt && skq[qcol] > 0;
+    float thr_f = METRIC == 0 ? from_ord(thr) : from_ord(~thr);
     uint64_t top[MQ];
 #pragma unroll
     for (int t = 0; t < MQ; t++) top[t] = ~0ull;
@@ -828,19 +833,27 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
                 acc[rg] = mfma_16x16x32<DT>(a, bq[kb], acc[rg]);
             }
         }
-        uint32_t hiv[16];
+        float vv[16];
         uint32_t pmask = 0;
+        const int lim = p1 - base;   // positions of this step inside the item (64 except at its end)
 #pragma unroll
         for (int rg = 0; rg < 4; rg++) {
             const float xs[4] = {xn4[rg].x, xn4[rg].y, xn4[rg].z, xn4[rg].w};
 #pragma unroll
             for (int j = 0; j < 4; j++) {
-                const int r = 16 * rg + 4 * kgrp + j;
-                const float v = METRIC == 0 ? (qn + xs[j]) - 2.f * acc[rg][j] : acc[rg][j];
-                const uint32_t hi = METRIC == 0 ? ord_bits(v) : ~ord_bits(v);
-                hiv[4 * rg + j] = hi;
-                if (base + r < p1 && qcol < nt && hi <= thr) pmask |= 1u << (4 * rg + j);
+                const float v = METRIC == 0 ? fmaf(-2.f, acc[rg][j], qn + xs[j]) : acc[rg][j];
+                vv[4 * rg + j] = v;
+                const bool pass = METRIC == 0 ? !(v > thr_f) : !(v < thr_f);
+                pmask |= (pass ? 1u : 0u) << (4 * rg + j);
             }
+        }
+        if (!live) pmask = 0;
+        if (lim < 64) {
+#pragma unroll
+            for (int rg = 0; rg < 4; rg++)
+#pragma unroll
+                for (int j = 0; j < 4; j++)
+                    if (16 * rg + 4 * kgrp + j >= lim) pmask &= ~(1u << (4 * rg + j));
         }
         if (ballot(pmask != 0)) {
             // offsets of this lane's candidates among the 4 lanes of its query
@@ -859,7 +872,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
 #pragma unroll
                     for (int j = 0; j < 4; j++) {
                         if ((pmask >> (4 * rg + j)) & 1u) {
-                            buf[qcol * MBUF + at] = ((uint64_t)hiv[4 * rg + j] << 32) | ids[j];
+                            const float v = vv[4 * rg + j];
+                            const uint32_t hi = METRIC == 0 ? ord_bits(v) : ~ord_bits(v);
+                            buf[qcol * MBUF + at] = ((uint64_t)hi << 32) | ids[j];
                             at++;
                         }
                     }
@@ -881,7 +896,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
                 for (int t = 0; t < MQ; t++) {
                     if ((fm >> t) & 1ull) {
                         const uint32_t nthr = mfma_flush<MQ>(top, t, buf, scnt[t], skq[t], kcap);
-                        if (qcol == t) thr = nthr;
+                        if (qcol == t) {
+                            thr = nthr;
+                            thr_f = METRIC == 0 ? from_ord(thr) : from_ord(~thr);
+                        }
                     }
                 }
                 __syncthreads();
@@ -899,6 +917,309 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
             if (lane < kcap) partials[(slot0 + (int64_t)t * nc) * kcap + lane] = top[t];
         }
     }
+    SIVF_ITEM_LOOP_END
+}
+
+// Insert key c into a list sorted ascending across the lanes (lane i holds
+// the i-th smallest); the largest key drops out.  Keys are distinct.
+__device__ __forceinline__ uint64_t sorted_insert(uint64_t a, uint64_t c) {
+    const int lane = lane_id();
+    const uint32_t plo = (uint32_t)__shfl_up((int)(uint32_t)a, 1);
+    const uint32_t phi = (uint32_t)__shfl_up((int)(uint32_t)(a >> 32), 1);
+    const uint64_t prev = ((uint64_t)phi << 32) | plo;
+    return a < c ? a : ((lane == 0 || prev < c) ? c : prev);
+}
+
+// Canonical FP32 value of one (row, query) pair, exactly as the VALU scan
+// computes it (one fma per dimension, ascending, over the padded chunks);
+// four chunks of loads in flight.  qaln: d % 4 == 0 and 16-byte aligned rows.
+template <int METRIC>
+__device__ __forceinline__ void cert_chunk(float &r, float4 qv, float4 xv) {
+    if (METRIC == 0) {
+        float e;
+        e = qv.x - xv.x;
+        r = __builtin_fmaf(e, e, r);
+        e = qv.y - xv.y;
+        r = __builtin_fmaf(e, e, r);
+        e = qv.z - xv.z;
+        r = __builtin_fmaf(e, e, r);
+        e = qv.w - xv.w;
+        r = __builtin_fmaf(e, e, r);
+    } else {
+        r = __builtin_fmaf(qv.x, xv.x, r);
+        r = __builtin_fmaf(qv.y, xv.y, r);
+        r = __builtin_fmaf(qv.z, xv.z, r);
+        r = __builtin_fmaf(qv.w, xv.w, r);
+    }
+}
+
+__device__ __forceinline__ float4 cert_q(const float *__restrict__ qr, int c, int d, int qaln) {
+    if (qaln) return reinterpret_cast<const float4 *>(qr)[c];
+    const int j = 4 * c;
+    float4 v;
+    v.x = j < d ? qr[j] : 0.f;
+    v.y = j + 1 < d ? qr[j + 1] : 0.f;
+    v.z = j + 2 < d ? qr[j + 2] : 0.f;
+    v.w = j + 3 < d ? qr[j + 3] : 0.f;
+    return v;
+}
+
+template <int METRIC>
+__device__ __forceinline__ float cert_exact(const float4 *__restrict__ xp, int C, int dp4,
+                                            const float *__restrict__ qr, int d, int qaln) {
+    float r = 0.f;
+    int c0 = 0;
+    for (; c0 + 4 <= dp4; c0 += 4) {
+        float4 xv[4], qv[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            xv[u] = xp[(int64_t)(c0 + u) * C];
+            qv[u] = cert_q(qr, c0 + u, d, qaln);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++) cert_chunk<METRIC>(r, qv[u], xv[u]);
+    }
+    for (; c0 < dp4; c0++) cert_chunk<METRIC>(r, cert_q(qr, c0, d, qaln), xp[(int64_t)c0 * C]);
+    return r;
+}
+
+// ------------------------------------------------ certified FP32 MFMA scan
+//
+// FP32 slabs with results identical to the canonical scan.  v_mfma_f32_16x16x4_f32
+// (four times the FP32 VALU rate for this contraction) gives approximate values for
+// 16 slots x 16 queries: Dt = |x|^2 + |q|^2 - 2 x.q (IP: x.q).  A slot can be among a
+// query's k best only if its certified interval reaches the query's current k-th best
+// canonical value; only those slots get their canonical FP32 distance recomputed
+// (sequential fma over ascending dimensions, exactly as the VALU scan computes it) and
+// offered to the query's exact top-k.  The interval half-width bounds the MFMA
+// approximation and the canonical sum's own rounding together:
+// (5d + 32) 2^-24 (|x| + |q|)^2 for L2 and (4d + 32) 2^-24 |x||q| for IP (|x|, |q| from
+// the fp32 squared norms; the margin covers their rounding), plus
+// 2^-122 sqrt(d) (|x| + |q|) + 2^-120 d for underflow.  With rounding error at most
+// one unit 2^-24 per operation the two sums differ from the exact value by at most
+// (2d + 4) 2^-24 (|x| + |q|)^2 (MFMA form, norms included) and (d + 2) 2^-24 |q - x|^2
+// (canonical form); IP: 2d and d times 2^-24 |x||q|.  An overflowing value gives inf or
+// NaN in the test below, and both pass.
+//
+// A operand (lane l): slot l % 16 of the row group, the 4 dimensions of chunk
+// 4 b + l / 16 (one float4), fed to 4 consecutive MFMAs one component each; the B
+// operand holds the same dimensions of query l % 16, so every MFMA pairs equal
+// dimensions and the 4 x NB MFMAs of a row group cover all 16 NB dimensions.
+template <int METRIC, int NB, bool PERS>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_scan_cert(Dev S, const int32_t *__restrict__ item_list,
+                                                  const int32_t *__restrict__ item_tile,
+                                                  const int32_t *__restrict__ item_chunk,
+                                                  const int32_t *__restrict__ list_pairs,
+                                                  const float *__restrict__ q, int np_stride, int kcap, int k,
+                                                  const int32_t *__restrict__ kpq,
+                                                  uint64_t *__restrict__ partials, int qaln) {
+    __shared__ uint16_t pq[64 * MQ];   // passing pairs of a step: position << 4 | query
+    __shared__ int skq[MQ], sqi[MQ];
+    const int lane = threadIdx.x, qcol = lane & 15, kgrp = lane >> 4;
+    const int d = S.d, C = S.C, dp4 = S.dp4, sh = S.ctl[CTL_CHUNK];
+    // half-width e = e1 (|x|^2 + |q|^2) + e0, from (|x| + |q|)^2 <= 2 (|x|^2 + |q|^2),
+    // |x||q| <= (|x|^2 + |q|^2) / 2 and |x| + |q| <= 1 + (|x|^2 + |q|^2)
+    const float cf = METRIC == 0 ? (5.0f * d + 32.0f) * 0x1p-24f : (4.0f * d + 32.0f) * 0x1p-24f;
+    const float ca = sqrtf((float)d) * 0x1p-122f, cb = (float)d * 0x1p-120f;
+    const float e1 = (METRIC == 0 ? 2.f * cf : 0.5f * cf) + ca, e0 = ca + cb;
+    SIVF_ITEM_LOOP_BEGIN
+    SIVF_ITEM_DECODE(MQ)
+    __syncthreads();
+    if (lane < MQ) {
+        const int qi = pairs[lane < nt ? lane : 0] / np_stride;
+        skq[lane] = lane < nt ? min(query_k(kpq, k, qi), kcap) : 0;
+        sqi[lane] = qi;
+    }
+    const float *qr = q + (int64_t)(pairs[qcol < nt ? qcol : 0] / np_stride) * d;
+    float4 bq[NB];
+    float qn2 = 0.f;
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+        const int j = 4 * (4 * b + kgrp);
+        bq[b].x = j < d ? qr[j] : 0.f;
+        bq[b].y = j + 1 < d ? qr[j + 1] : 0.f;
+        bq[b].z = j + 2 < d ? qr[j + 2] : 0.f;
+        bq[b].w = j + 3 < d ? qr[j + 3] : 0.f;
+        qn2 = fmaf(bq[b].x, bq[b].x, qn2);
+        qn2 = fmaf(bq[b].y, bq[b].y, qn2);
+        qn2 = fmaf(bq[b].z, bq[b].z, qn2);
+        qn2 = fmaf(bq[b].w, bq[b].w, qn2);
+    }
+    qn2 += __shfl_xor(qn2, 16);
+    qn2 += __shfl_xor(qn2, 32);
+    __syncthreads();
+    uint32_t thr = skq[qcol] > 0 ? 0xFFFFFFFFu : 0u;   // high word of query qcol's k-th exact key
+    // the k-th exact value as a float (L2: distance, IP: score); ~0 maps to NaN, which passes all
+    const bool live = qcol < nt && skq[qcol] > 0;
+    float thr_f = METRIC == 0 ? from_ord(thr) : from_ord(~thr);
+    uint64_t top[MQ];
+#pragma unroll
+    for (int t = 0; t < MQ; t++) top[t] = ~0ull;
+
+    const int nslab = cdiv_s(len, C);
+    int wbase = -(1 << 30), wslab = 0;
+    for (int base = p0; base < p1; base += 64) {
+        const int last_ord = (min(base + 63, p1 - 1)) / C;
+        if (last_ord >= wbase + 64) {
+            wbase = base / C;
+            wslab = (wbase + lane < nslab) ? slab_of(S, l, wbase + lane) : 0;
+        }
+        // the 4 result rows of this lane in row group rg: positions base + 16 rg + 4 kgrp .. +3
+        int64_t g4[4];
+#pragma unroll
+        for (int rg = 0; rg < 4; rg++) {
+            const int p = base + 16 * rg + 4 * kgrp;
+            const int pc = p < p1 ? p : ((p1 - 1) & ~3);
+            g4[rg] = (int64_t)__shfl(wslab, pc / C - wbase) * C + pc % C;
+        }
+        float4 xn4[4];
+#pragma unroll
+        for (int rg = 0; rg < 4; rg++) xn4[rg] = *reinterpret_cast<const float4 *>(S.xnorm + g4[rg]);
+        f32x4_t acc[4];
+#pragma unroll
+        for (int rg = 0; rg < 4; rg++) {
+            const int p = base + 16 * rg + qcol;
+            const int pc = p < p1 ? p : p1 - 1;
+            const int slab = __shfl(wslab, pc / C - wbase);
+            const float4 *xp = S.data + (int64_t)slab * dp4 * C + pc % C;
+            acc[rg] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int b = 0; b < NB; b++) {
+                // chunks past the row repeat its last chunk: their B lanes are zero and the
+                // stored values are finite; positions past the item read its last row and
+                // are masked below
+                const int c = min(4 * b + kgrp, dp4 - 1);
+                const float4 a = xp[(int64_t)c * C];
+                acc[rg] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, bq[b].x, acc[rg], 0, 0, 0);
+                acc[rg] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bq[b].y, acc[rg], 0, 0, 0);
+                acc[rg] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, bq[b].z, acc[rg], 0, 0, 0);
+                acc[rg] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, bq[b].w, acc[rg], 0, 0, 0);
+            }
+        }
+        // distance space (L2: the distance; IP: minus the score): value v and
+        // certified half-width e of every (slot, query) pair of this lane
+        float vv[16], ee[16];
+        const int lim = p1 - base;   // positions of this step inside the item (64 except at its end)
+#pragma unroll
+        for (int rg = 0; rg < 4; rg++) {
+            const float xs[4] = {xn4[rg].x, xn4[rg].y, xn4[rg].z, xn4[rg].w};
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const float sq = qn2 + xs[j];
+                vv[4 * rg + j] = METRIC == 0 ? fmaf(-2.f, acc[rg][j], sq) : -acc[rg][j];
+                ee[4 * rg + j] = fmaf(e1, sq, e0);
+            }
+        }
+        // the query's k-th best value so far in distance space (NaN: none yet, all pass)
+        float thd = METRIC == 0 ? thr_f : -thr_f;
+        const bool warm = live && thr == 0xFFFFFFFFu;
+        if (ballot(warm)) {
+            // No k-th value yet: bound it by the k-th smallest upper bound v + e
+            // among this step's candidates of the query (lanes qcol + 16 i hold
+            // them): at least k candidates lie at or below it, so the k best
+            // do too.  Bisection keeps count(v + e <= hi) >= k.
+            int nv = 0;
+            float mn = __int_as_float(0x7F800000), mx = -__int_as_float(0x7F800000);
+#pragma unroll
+            for (int i = 0; i < 16; i++) {
+                float u = vv[i] + ee[i];
+                if (!(u <= __int_as_float(0x7F800000))) u = __int_as_float(0x7F800000);   // NaN: +inf
+                if (16 * (i >> 2) + 4 * kgrp + (i & 3) < lim) {
+                    nv++;
+                    mn = fminf(mn, u);
+                    mx = fmaxf(mx, u);
+                }
+            }
+            nv += __shfl_xor(nv, 16);
+            nv += __shfl_xor(nv, 32);
+            mn = fminf(mn, __shfl_xor(mn, 16));
+            mn = fminf(mn, __shfl_xor(mn, 32));
+            mx = fmaxf(mx, __shfl_xor(mx, 16));
+            mx = fmaxf(mx, __shfl_xor(mx, 32));
+            const int kq = skq[qcol];
+            float lo = mn, hi = mx;
+            for (int it = 0; it < 10; it++) {
+                const float mid = lo + 0.5f * (hi - lo);
+                int c = 0;
+#pragma unroll
+                for (int i = 0; i < 16; i++) {
+                    const float u = vv[i] + ee[i];
+                    c += (16 * (i >> 2) + 4 * kgrp + (i & 3) < lim && u <= mid) ? 1 : 0;
+                }
+                c += __shfl_xor(c, 16);
+                c += __shfl_xor(c, 32);
+                if (c >= kq) hi = mid;
+                else lo = mid;
+            }
+            if (warm && nv >= kq) thd = hi;
+        }
+        uint32_t pmask = 0;
+#pragma unroll
+        for (int i = 0; i < 16; i++) pmask |= (!(vv[i] - ee[i] > thd) ? 1u : 0u) << i;
+        if (!live) pmask = 0;
+        if (lim < 64) {
+#pragma unroll
+            for (int rg = 0; rg < 4; rg++)
+#pragma unroll
+                for (int j = 0; j < 4; j++)
+                    if (16 * rg + 4 * kgrp + j >= lim) pmask &= ~(1u << (4 * rg + j));
+        }
+        if (ballot(pmask != 0)) {
+            // queue the passing (position, query) pairs in lane order, then
+            // recompute them 64 at a time, one pair per lane
+            const int np = __builtin_popcount(pmask);
+            int incl = np;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int u = __shfl_up(incl, o);
+                if (lane >= o) incl += u;
+            }
+            const int total = __shfl(incl, 63);
+            int at = incl - np;
+            uint32_t m = pmask;
+            while (m) {
+                const int bit = __builtin_ctz(m);
+                m &= m - 1;
+                pq[at++] = (uint16_t)(((16 * (bit >> 2) + 4 * kgrp + (bit & 3)) << 4) | qcol);
+            }
+            __syncthreads();
+            for (int r0 = 0; r0 < total; r0 += 64) {
+                const bool act = r0 + lane < total;
+                const int e = pq[act ? r0 + lane : r0];
+                const int t = e & 15, pos = base + (e >> 4);
+                const int slab = __shfl(wslab, pos / C - wbase);
+                uint64_t key = ~0ull;
+                if (act) {
+                    const float r = cert_exact<METRIC>(S.data + (int64_t)slab * dp4 * C + pos % C, C, dp4,
+                                                       q + (int64_t)sqi[t] * d, d, qaln);
+                    key = ((uint64_t)key_hi<METRIC>(r) << 32) | S.sids[(int64_t)slab * C + pos % C];
+                }
+                // insert the exact keys into their queries' sorted lists, one at a time
+#pragma unroll
+                for (int t2 = 0; t2 < MQ; t2++) {
+                    uint64_t cm = ballot(act && t == t2);
+                    if (cm) {
+                        while (cm) {
+                            const int src = (int)__builtin_ctzll(cm);
+                            cm &= cm - 1;
+                            top[t2] = sorted_insert(top[t2], readlane_u64(key, src));
+                        }
+                        const int kq = skq[t2];   // > 0: only live queries have pairs
+                        const uint32_t nthr = kq > 0 ? (uint32_t)(readlane_u64(top[t2], kq - 1) >> 32) : 0u;
+                        if (qcol == t2) {
+                            thr = nthr;
+                            thr_f = METRIC == 0 ? from_ord(thr) : from_ord(~thr);
+                        }
+                    }
+                }
+            }
+            __syncthreads();   // the queue is rewritten by the next step
+        }
+    }
+    SIVF_ITEM_SLOT(MQ)
+#pragma unroll
+    for (int t = 0; t < MQ; t++)
+        if (t < nt && lane < kcap) partials[(slot0 + (int64_t)t * nc) * kcap + lane] = top[t];
     SIVF_ITEM_LOOP_END
 }
 
@@ -1065,10 +1386,41 @@ void launch_search_plan(hipStream_t st, const Dev &S, const SearchBufs &W, int n
                        W.list_pairs);
 }
 
+bool cert_ok(int storage, int d, int C, int kcap) { return storage == 0 && d <= 256 && C >= 4 && kcap <= 64; }
+
+template <int METRIC, int NB>
+static void launch_cert_nb(hipStream_t st, const Dev &S, const SearchBufs &W, const float *q, int np_stride,
+                           int kcap, int k, const int32_t *kpq, int npairs) {
+#define SIVF_LAUNCH_CERT(P)                                                                                  \
+    hipLaunchKernelGGL((k_scan_cert<METRIC, NB, P>), dim3(scan_grid(k_scan_cert<METRIC, NB, P>, S, W, npairs, 0)), \
+                       dim3(64), 0, st, S, W.item_list, W.item_tile, W.item_chunk, W.list_pairs, q, np_stride,  \
+                       kcap, k, kpq, W.partials, qaln)
+    const int qaln = (S.d % 4 == 0) && (((uintptr_t)q & 15) == 0);
+    if (S.persistent) SIVF_LAUNCH_CERT(true);
+    else SIVF_LAUNCH_CERT(false);
+#undef SIVF_LAUNCH_CERT
+}
+
+template <int METRIC>
+static void launch_cert(hipStream_t st, const Dev &S, const SearchBufs &W, const float *q, int np_stride, int kcap,
+                        int k, const int32_t *kpq, int npairs) {
+    // blocks of 16 dimensions held as B operands (d <= 256)
+    const int nb = (S.d + 15) / 16;
+    if (nb <= 2) launch_cert_nb<METRIC, 2>(st, S, W, q, np_stride, kcap, k, kpq, npairs);
+    else if (nb <= 4) launch_cert_nb<METRIC, 4>(st, S, W, q, np_stride, kcap, k, kpq, npairs);
+    else if (nb <= 8) launch_cert_nb<METRIC, 8>(st, S, W, q, np_stride, kcap, k, kpq, npairs);
+    else launch_cert_nb<METRIC, 16>(st, S, W, q, np_stride, kcap, k, kpq, npairs);
+}
+
 void launch_search_scan(hipStream_t st, const Dev &S, const SearchBufs &W, int nq, const float *q, int np_stride,
                         int kcap, int k, const int32_t *k_per_query) {
     const int T = search_tile(S);
     const int npairs = nq * np_stride;
+    if (T == 16) {   // the schedule setter admits tile 16 only where cert_ok holds
+        if (S.metric == 0) launch_cert<0>(st, S, W, q, np_stride, kcap, k, k_per_query, npairs);
+        else launch_cert<1>(st, S, W, q, np_stride, kcap, k, k_per_query, npairs);
+        return;
+    }
     if (kcap > 64) {
         if (T == 8) launch_scan_t<8, true>(st, S, W, q, np_stride, kcap, k, k_per_query, npairs);
         else launch_scan_t<4, true>(st, S, W, q, np_stride, kcap, k, k_per_query, npairs);

@@ -109,7 +109,9 @@ Layout make_layout(const sivf_config *c) {
     L.partials = take((size_t)L.slot_cap * L.kcap * 8);
     const bool reduced = c->storage != SIVF_F32;
     L.hdata = take(reduced ? (size_t)ns * ((c->dim + 7) / 8) * C * 16 : 0);
-    L.xnorm = take(reduced && c->metric == SIVF_L2 ? (size_t)ns * C * 4 : 0);
+    // squared row norms: the rounded rows' (reduced precision, L2 scan) or the fp32 rows' (the
+    // certified FP32 MFMA scan's error bound and approximate distance)
+    L.xnorm = take((reduced && c->metric == SIVF_L2) || !reduced ? (size_t)ns * C * 4 : 0);
     L.rr_dist = take(reduced ? (size_t)c->max_queries * L.kcap * 4 : 0);
     L.rr_lab = take(reduced ? (size_t)c->max_queries * L.kcap * 8 : 0);
     L.total = cur;
@@ -320,7 +322,7 @@ sivf_status sivf_create(const sivf_config *cfg, const float *centroids, void *wo
     S.chunk_shift = DEFAULT_CHUNK_SHIFT;
     S.persistent = 0;
     S.hdata = cfg->storage != SIVF_F32 ? (uint4 *)(w + L.hdata) : nullptr;
-    S.xnorm = (cfg->storage != SIVF_F32 && cfg->metric == SIVF_L2) ? (float *)(w + L.xnorm) : nullptr;
+    S.xnorm = (cfg->storage == SIVF_F32 || cfg->metric == SIVF_L2) ? (float *)(w + L.xnorm) : nullptr;
     ix->W.rr_dist = cfg->storage != SIVF_F32 ? (float *)(w + L.rr_dist) : nullptr;
     ix->W.rr_lab = cfg->storage != SIVF_F32 ? (int64_t *)(w + L.rr_lab) : nullptr;
     S.num_slabs = cfg->num_slabs;
@@ -437,6 +439,7 @@ sivf_status sivf_tune_search(sivf_index *ix, int64_t nq, const float *q, int32_t
     if (ix->cfg.storage != SIVF_F32) tiles = {16};
     else if (ix->cfg.dim <= 1024) tiles = {8, 4};
     else tiles = {4};
+    if (cert_ok(ix->cfg.storage, ix->cfg.dim, ix->cfg.slab_capacity, ix->L.kcap)) tiles.push_back(16);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (!dev_ok(hipEventCreate(&e0)) || !dev_ok(hipEventCreate(&e1))) {
         if (e0) (void)hipEventDestroy(e0);
@@ -485,7 +488,8 @@ sivf_status sivf_tune_search(sivf_index *ix, int64_t nq, const float *q, int32_t
 sivf_status sivf_set_search_schedule(sivf_index *ix, int32_t tile, int32_t chunk_shift, int32_t persistent) {
     if (!ix) return SIVF_ERR_ARG;
     const bool reduced = ix->cfg.storage != SIVF_F32;
-    if (reduced ? tile != 16 : (tile != 4 && (tile != 8 || ix->cfg.dim > 1024))) return SIVF_ERR_ARG;
+    const bool cert = tile == 16 && cert_ok(ix->cfg.storage, ix->cfg.dim, ix->cfg.slab_capacity, ix->L.kcap);
+    if (reduced ? tile != 16 : (tile != 4 && (tile != 8 || ix->cfg.dim > 1024) && !cert)) return SIVF_ERR_ARG;
     if (chunk_shift < 6 || chunk_shift > 31 || (persistent != 0 && persistent != 1)) return SIVF_ERR_ARG;
     ix->S.tile = tile;
     ix->S.chunk_shift = chunk_shift;

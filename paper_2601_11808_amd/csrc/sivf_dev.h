@@ -56,7 +56,8 @@ struct Dev {
     const double *cmax;   // [1] largest centroid norm
     float4 *data;         // fp32 rows (the stored vectors, or the exact shadow)
     uint4 *hdata;         // [num_slabs][dp8][C] 8 x 16-bit (reduced-precision storage only)
-    float *xnorm;         // [num_slabs * C] squared norm of the rounded row (reduced precision, L2)
+    float *xnorm;         // [num_slabs * C] squared norm of the stored row: the fp32 row (fp32 storage)
+                          // or the rounded row (reduced precision, L2); NULL otherwise
     uint32_t *sids;
     int32_t *sowner, *sord;
     int32_t *free_slabs, *free_pages, *pages, *dir;

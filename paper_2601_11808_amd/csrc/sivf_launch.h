@@ -57,6 +57,8 @@ struct SearchBufs {
 };
 int search_tile(const Dev &S);
 int default_tile(int storage, int d);
+// Whether the certified FP32 MFMA scan (tile 16 on fp32 slabs) applies.
+bool cert_ok(int storage, int d, int C, int kcap);
 // Default search chunk: 2^14 positions per work item (a list is split only
 // when the plan's buffers allow; into longer chunks otherwise).
 constexpr int DEFAULT_CHUNK_SHIFT = 14;

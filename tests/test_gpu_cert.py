@@ -1,0 +1,126 @@
+"""Certified FP32 MFMA scan (search tile 16 on fp32 slabs): the matrix-core
+values only decide which slots get their canonical FP32 distance recomputed,
+so results must be bit-identical to the VALU scan's and match the oracle
+(identical ids, distances within 1e-5 relative).  Cases that stress the
+error bound: near-ties, large common offsets (cancellation in
+|x|^2 + |q|^2 - 2 x.q), tiny magnitudes (underflow), equal rows."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2601_11808_amd as sivf
+from tests.gpu_common import Pair, compare_results, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    say(f"\n[gpu] {request.node.name}")
+    yield
+
+
+def _both(ix, q, k, nprobe, kpq=None, npq=None, sched=(16, 14, 0)):
+    """Search with the VALU scan (tile 8) and the certified scan; assert bit-identical results."""
+    ix.set_search_schedule(8, 14, 0)
+    d0, l0 = ix.search(q, k, nprobe, k_per_query=kpq, nprobe_per_query=npq)
+    assert ix.sync() == 0
+    ix.set_search_schedule(*sched)
+    d1, l1 = ix.search(q, k, nprobe, k_per_query=kpq, nprobe_per_query=npq)
+    assert ix.sync() == 0
+    d0, l0, d1, l1 = d0.cpu().numpy(), l0.cpu().numpy(), d1.cpu().numpy(), l1.cpu().numpy()
+    np.testing.assert_array_equal(l1, l0)
+    np.testing.assert_array_equal(d1.view(np.uint32), d0.view(np.uint32))
+    return d1, l1
+
+
+KINDS = ["normal", "offset", "tiny", "grid"]
+
+
+def _data(kind, rng, n, d):
+    if kind == "normal":
+        return rng.standard_normal((n, d)).astype(np.float32)
+    if kind == "offset":      # common offset 300 per dimension, unit noise: |x|^2 >> distances
+        return (300.0 + rng.standard_normal((n, d))).astype(np.float32)
+    if kind == "tiny":        # magnitudes near 1e-19: squared terms near the bottom of fp32's range
+        return (1e-19 * rng.standard_normal((n, d))).astype(np.float32)
+    if kind == "grid":        # small integers: many exact ties
+        return rng.integers(-2, 3, (n, d)).astype(np.float32)
+    raise ValueError(kind)
+
+
+@pytest.mark.parametrize("kind,d,metric,C", [("normal", 128, 0, 64), ("normal", 100, 1, 32), ("offset", 64, 0, 64),
+                                             ("offset", 32, 1, 16), ("tiny", 48, 0, 64), ("grid", 17, 0, 8),
+                                             ("grid", 24, 1, 4), ("normal", 256, 0, 128), ("normal", 5, 1, 64)])
+def test_cert_scan_matches_valu_and_oracle(kind, d, metric, C):
+    rng = np.random.default_rng([KINDS.index(kind), d, metric, C])
+    nlist, n = 13, 6000
+    cent = _data(kind, rng, nlist, d)
+    x = _data(kind, rng, n, d)
+    x[100:200] = x[:100]                       # equal rows under different ids
+    x[200:300] = np.nextafter(x[:100], np.float32(np.inf))   # one-ulp neighbours
+    ids = rng.permutation(n).astype(np.int64)
+    q = np.concatenate([_data(kind, rng, 150, d), x[:50]]).astype(np.float32)   # some queries on data rows
+    p = Pair(d, nlist, cent, metric, C, num_slabs=n // C + 4 * nlist + 8, id_capacity=n, max_batch=n,
+             max_queries=q.shape[0], max_k=64, max_nprobe=nlist)
+    assert p.add(x, ids) == 0
+    for k, nprobe in [(10, 3), (64, 13), (1, 1)]:
+        gd, gl = _both(p.gpu, q, k, nprobe)
+        st, rd, rl = p.ref.search(q, k, nprobe)
+        assert st == 0
+        compare_results(gd, gl, rd, rl)
+    kpq = rng.integers(0, 65, q.shape[0]).astype(np.int32)
+    npq = rng.integers(1, nlist + 1, q.shape[0]).astype(np.int32)
+    gd, gl = _both(p.gpu, q, 64, nlist, kpq, npq)
+    st, rd, rl = p.ref.search(q, 64, nlist, k_per_query=kpq, nprobe_per_query=npq)
+    compare_results(gd, gl, rd, rl)
+    # after deletes (tail-swap moves rows and their norms) and upserts
+    assert p.remove(ids[::4]) == 0
+    assert p.add(x[1::7] * np.float32(0.5), ids[1::7]) == 0
+    gd, gl = _both(p.gpu, q, 32, 5, sched=(16, 10, 1))
+    st, rd, rl = p.ref.search(q, 32, 5)
+    compare_results(gd, gl, rd, rl)
+    say(f"  {kind} d={d} metric={metric} C={C}: identical to the VALU scan and the oracle")
+
+
+@pytest.mark.parametrize("metric", [0, 1])
+def test_cert_scan_split_lists(metric):
+    """Long lists split into chunks, both schedules, ragged tails."""
+    rng = np.random.default_rng([77, metric])
+    sizes = [30001, 12000, 999, 65, 3, 0]
+    d = 64
+    cent = (rng.standard_normal((len(sizes), d)) * 8).astype(np.float32)
+    x = np.concatenate([cent[l] + rng.standard_normal((s, d)) for l, s in enumerate(sizes) if s]).astype(np.float32)
+    ids = rng.permutation(x.shape[0]).astype(np.int64)
+    q = (cent[rng.integers(0, len(sizes), 400)] + rng.standard_normal((400, d))).astype(np.float32)
+    ix = sivf.Index(d, len(sizes), cent, metric=metric, slab_capacity=64, num_slabs=800, id_capacity=x.shape[0],
+                    max_batch=1 << 16, max_queries=400, max_k=64, max_nprobe=4)
+    ref = oracle.OracleIndex(d, len(sizes), cent, metric, 64, 800, x.shape[0])
+    ix.add(x, ids)
+    assert ix.sync() == 0
+    assert ref.add(x, ids) == 0
+    st, rd, rl = ref.search(q, 50, 4)
+    for sched in [(16, 10, 0), (16, 10, 1), (16, 12, 0), (16, 17, 1)]:
+        gd, gl = _both(ix, q, 50, 4, sched=sched)
+        compare_results(gd, gl, rd, rl)
+    t, sh, pm = ix.tune_search(q, 50, 4)
+    assert ix.sync() == 0
+    gd, gl = ix.search(q, 50, 4)
+    assert ix.sync() == 0
+    compare_results(gd.cpu().numpy(), gl.cpu().numpy(), rd, rl)
+    say(f"  split lists: identical on 4 schedules; tuner chose tile {t}, 2^{sh}, persistent={pm}")
+
+
+def test_cert_schedule_limits():
+    """Tile 16 on fp32 slabs needs d <= 256, max_k <= 64 and slabs of >= 4 slots."""
+    rng = np.random.default_rng(5)
+
+    def mk(d, max_k, C):
+        cent = rng.standard_normal((4, d)).astype(np.float32)
+        return sivf.Index(d, 4, cent, slab_capacity=C, num_slabs=64, id_capacity=1024, max_batch=1024,
+                          max_queries=16, max_k=max_k, max_nprobe=4)
+
+    mk(256, 64, 4).set_search_schedule(16, 14, 0)
+    for d, max_k, C in [(257, 16, 64), (64, 65, 64), (64, 16, 2)]:
+        with pytest.raises(sivf.SivfError):
+            mk(d, max_k, C).set_search_schedule(16, 14, 0)
