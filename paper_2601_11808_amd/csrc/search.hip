@@ -439,19 +439,20 @@ __device__ __forceinline__ uint32_t key_hi(float v) {
 // of a tile, in the canonical order (dimensions ascending, one fma each), then
 // offered to each query's top-k.  QV(t, c) gives query t's dimension chunk c.
 #define SIVF_SCAN_RANGE(QV)                                                                      \
-    const int nslab = cdiv_s(len, C);                                                            \
+    const int cs_ = __builtin_ctz(C), cm_ = C - 1; /* slab capacities are powers of two */       \
+    const int nslab = (len + cm_) >> cs_;                                                        \
     int wbase = -(1 << 30), wslab = 0; /* lane j holds the slab of ordinal wbase + j */          \
     for (int base = p0; base < p1; base += 64) {                                                 \
         const int p = base + lane;                                                               \
         const bool valid = p < p1;                                                               \
         const int pc = valid ? p : p1 - 1;                                                       \
-        const int last_ord = (min(base + 63, p1 - 1)) / C;                                       \
+        const int last_ord = min(base + 63, p1 - 1) >> cs_;                                      \
         if (last_ord >= wbase + 64) {                                                            \
-            wbase = base / C;                                                                    \
+            wbase = base >> cs_;                                                                 \
             wslab = (wbase + lane < nslab) ? slab_of(S, l, wbase + lane) : 0;                    \
         }                                                                                        \
-        const int slab = __shfl(wslab, pc / C - wbase);                                          \
-        const int slot = pc % C;                                                                 \
+        const int slab = __shfl(wslab, (pc >> cs_) - wbase);                                     \
+        const int slot = pc & cm_;                                                               \
         const float4 *xp = S.data + (int64_t)slab * dp4 * C + slot;                              \
         float acc[T];                                                                            \
         _Pragma("unroll") for (int t = 0; t < T; t++) acc[t] = 0.f;                              \
@@ -759,6 +760,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
     __shared__ int scnt[MQ], skq[MQ];
     const int lane = threadIdx.x, qcol = lane & 15, kgrp = lane >> 4;
     const int d = S.d, C = S.C, dp8 = S.dp8, sh = S.ctl[CTL_CHUNK];
+    const int cs = __builtin_ctz(C), cm = C - 1;   // slab capacities are powers of two
     SIVF_ITEM_LOOP_BEGIN
     SIVF_ITEM_DECODE(MQ)
     __syncthreads();
@@ -796,12 +798,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
 #pragma unroll
     for (int t = 0; t < MQ; t++) top[t] = ~0ull;
 
-    const int nslab = cdiv_s(len, C);
+    const int nslab = (len + cm) >> cs;
     int wbase = -(1 << 30), wslab = 0;
     for (int base = p0; base < p1; base += 64) {
-        const int last_ord = (min(base + 63, p1 - 1)) / C;
+        const int last_ord = min(base + 63, p1 - 1) >> cs;
         if (last_ord >= wbase + 64) {
-            wbase = base / C;
+            wbase = base >> cs;
             wslab = (wbase + lane < nslab) ? slab_of(S, l, wbase + lane) : 0;
         }
         // the 4 result rows of this lane in row group rg are positions
@@ -811,7 +813,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
         for (int rg = 0; rg < 4; rg++) {
             const int p = base + 16 * rg + 4 * kgrp;
             const int pc = p < p1 ? p : ((p1 - 1) & ~3);
-            g4[rg] = (int64_t)__shfl(wslab, pc / C - wbase) * C + pc % C;
+            g4[rg] = (int64_t)__shfl(wslab, (pc >> cs) - wbase) * C + (pc & cm);
         }
         float4 xn4[4] = {};
         if (METRIC == 0) {
@@ -823,8 +825,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
         for (int rg = 0; rg < 4; rg++) {
             const int p = base + 16 * rg + qcol;
             const int pc = p < p1 ? p : p1 - 1;
-            const int slab = __shfl(wslab, pc / C - wbase);
-            const uint4 *hp = S.hdata + (int64_t)slab * dp8 * C + pc % C;
+            const int slab = __shfl(wslab, (pc >> cs) - wbase);
+            const uint4 *hp = S.hdata + (int64_t)slab * dp8 * C + (pc & cm);
             acc[rg] = f32x4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int kb = 0; kb < NKB; kb++) {
@@ -924,15 +926,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
 // the i-th smallest); the largest key drops out.  Keys are distinct.
 __device__ __forceinline__ uint64_t sorted_insert(uint64_t a, uint64_t c) {
     const int lane = lane_id();
-    const uint32_t plo = (uint32_t)__shfl_up((int)(uint32_t)a, 1);
-    const uint32_t phi = (uint32_t)__shfl_up((int)(uint32_t)(a >> 32), 1);
+    // previous lane's key: DPP wave_shr:1 (lane 0 keeps its own, unused)
+    const uint32_t plo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)a, (int)(uint32_t)a, 0x138, 0xf, 0xf, false);
+    const uint32_t phi = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(a >> 32), (int)(uint32_t)(a >> 32), 0x138,
+                                                                0xf, 0xf, false);
     const uint64_t prev = ((uint64_t)phi << 32) | plo;
     return a < c ? a : ((lane == 0 || prev < c) ? c : prev);
 }
 
 // Canonical FP32 value of one (row, query) pair, exactly as the VALU scan
 // computes it (one fma per dimension, ascending, over the padded chunks);
-// four chunks of loads in flight.  qaln: d % 4 == 0 and 16-byte aligned rows.
+// four chunks of loads in flight.  qv4: the query's zero-padded row in LDS.
 template <int METRIC>
 __device__ __forceinline__ void cert_chunk(float &r, float4 qv, float4 xv) {
     if (METRIC == 0) {
@@ -953,34 +957,42 @@ __device__ __forceinline__ void cert_chunk(float &r, float4 qv, float4 xv) {
     }
 }
 
-__device__ __forceinline__ float4 cert_q(const float *__restrict__ qr, int c, int d, int qaln) {
-    if (qaln) return reinterpret_cast<const float4 *>(qr)[c];
-    const int j = 4 * c;
-    float4 v;
-    v.x = j < d ? qr[j] : 0.f;
-    v.y = j + 1 < d ? qr[j + 1] : 0.f;
-    v.z = j + 2 < d ? qr[j + 2] : 0.f;
-    v.w = j + 3 < d ? qr[j + 3] : 0.f;
-    return v;
-}
-
 template <int METRIC>
-__device__ __forceinline__ float cert_exact(const float4 *__restrict__ xp, int C, int dp4,
-                                            const float *__restrict__ qr, int d, int qaln) {
+__device__ __forceinline__ float cert_exact(const float4 *__restrict__ xp, int C, int dp4, const float4 *qv4) {
     float r = 0.f;
     int c0 = 0;
     for (; c0 + 4 <= dp4; c0 += 4) {
-        float4 xv[4], qv[4];
+        float4 xv[4];
 #pragma unroll
-        for (int u = 0; u < 4; u++) {
-            xv[u] = xp[(int64_t)(c0 + u) * C];
-            qv[u] = cert_q(qr, c0 + u, d, qaln);
-        }
+        for (int u = 0; u < 4; u++) xv[u] = xp[(int64_t)(c0 + u) * C];
 #pragma unroll
-        for (int u = 0; u < 4; u++) cert_chunk<METRIC>(r, qv[u], xv[u]);
+        for (int u = 0; u < 4; u++) cert_chunk<METRIC>(r, qv4[c0 + u], xv[u]);
     }
-    for (; c0 < dp4; c0++) cert_chunk<METRIC>(r, cert_q(qr, c0, d, qaln), xp[(int64_t)c0 * C]);
+    for (; c0 < dp4; c0++) cert_chunk<METRIC>(r, qv4[c0], xp[(int64_t)c0 * C]);
     return r;
+}
+
+template <int NB>
+__device__ __forceinline__ void cert_load_a(float4 (&a)[NB], const float4 *__restrict__ xr, int C, int kgrp, int dp4) {
+#pragma unroll
+    for (int b = 0; b < NB; b++) a[b] = xr[(int64_t)min(4 * b + kgrp, dp4 - 1) * C];
+}
+
+// 16 slots x 16 queries over all dimensions; B operand (query l % 16, chunk
+// 4 b + l / 16) read from the LDS query rows.
+template <int NB>
+__device__ __forceinline__ f32x4_t cert_mfma(const float4 (&a)[NB], const float4 *qrow, int kgrp, int dp4) {
+    f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+        const int c = 4 * b + kgrp;
+        const float4 bv = c < dp4 ? qrow[c] : make_float4(0.f, 0.f, 0.f, 0.f);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[b].x, bv.x, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[b].y, bv.y, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[b].z, bv.z, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[b].w, bv.w, acc, 0, 0, 0);
+    }
+    return acc;
 }
 
 // ------------------------------------------------ certified FP32 MFMA scan
@@ -1012,11 +1024,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
                                                   const int32_t *__restrict__ list_pairs,
                                                   const float *__restrict__ q, int np_stride, int kcap, int k,
                                                   const int32_t *__restrict__ kpq,
-                                                  uint64_t *__restrict__ partials, int qaln) {
+                                                  uint64_t *__restrict__ partials) {
+    extern __shared__ float4 sqr[];    // the tile's 16 query rows, zero-padded to dp4 chunks, stride dp4 + 1
     __shared__ uint16_t pq[64 * MQ];   // passing pairs of a step: position << 4 | query
-    __shared__ int skq[MQ], sqi[MQ];
+    __shared__ int skq[MQ];
     const int lane = threadIdx.x, qcol = lane & 15, kgrp = lane >> 4;
     const int d = S.d, C = S.C, dp4 = S.dp4, sh = S.ctl[CTL_CHUNK];
+    const int qs = dp4 + 1;   // LDS row stride: rows start in different banks
+    const int cs = __builtin_ctz(C), cm = C - 1;   // slab capacities are powers of two
     // half-width e = e1 (|x|^2 + |q|^2) + e0, from (|x| + |q|)^2 <= 2 (|x|^2 + |q|^2),
     // |x||q| <= (|x|^2 + |q|^2) / 2 and |x| + |q| <= 1 + (|x|^2 + |q|^2)
     const float cf = METRIC == 0 ? (5.0f * d + 32.0f) * 0x1p-24f : (4.0f * d + 32.0f) * 0x1p-24f;
@@ -1028,22 +1043,27 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
     if (lane < MQ) {
         const int qi = pairs[lane < nt ? lane : 0] / np_stride;
         skq[lane] = lane < nt ? min(query_k(kpq, k, qi), kcap) : 0;
-        sqi[lane] = qi;
     }
-    const float *qr = q + (int64_t)(pairs[qcol < nt ? qcol : 0] / np_stride) * d;
-    float4 bq[NB];
-    float qn2 = 0.f;
+    for (int i = lane; i < MQ * dp4; i += 64) {
+        const int t = i / dp4, j = 4 * (i - t * dp4);
+        const float *qr = q + (int64_t)(pairs[t < nt ? t : 0] / np_stride) * d;
+        float4 v;
+        v.x = j < d ? qr[j] : 0.f;
+        v.y = j + 1 < d ? qr[j + 1] : 0.f;
+        v.z = j + 2 < d ? qr[j + 2] : 0.f;
+        v.w = j + 3 < d ? qr[j + 3] : 0.f;
+        sqr[t * qs + (j >> 2)] = v;
+    }
+    __syncthreads();
+    float qn2 = 0.f;   // |q|^2 of query qcol
 #pragma unroll
     for (int b = 0; b < NB; b++) {
-        const int j = 4 * (4 * b + kgrp);
-        bq[b].x = j < d ? qr[j] : 0.f;
-        bq[b].y = j + 1 < d ? qr[j + 1] : 0.f;
-        bq[b].z = j + 2 < d ? qr[j + 2] : 0.f;
-        bq[b].w = j + 3 < d ? qr[j + 3] : 0.f;
-        qn2 = fmaf(bq[b].x, bq[b].x, qn2);
-        qn2 = fmaf(bq[b].y, bq[b].y, qn2);
-        qn2 = fmaf(bq[b].z, bq[b].z, qn2);
-        qn2 = fmaf(bq[b].w, bq[b].w, qn2);
+        const int c = 4 * b + kgrp;
+        const float4 v = c < dp4 ? sqr[qcol * qs + c] : make_float4(0.f, 0.f, 0.f, 0.f);
+        qn2 = fmaf(v.x, v.x, qn2);
+        qn2 = fmaf(v.y, v.y, qn2);
+        qn2 = fmaf(v.z, v.z, qn2);
+        qn2 = fmaf(v.w, v.w, qn2);
     }
     qn2 += __shfl_xor(qn2, 16);
     qn2 += __shfl_xor(qn2, 32);
@@ -1056,12 +1076,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
 #pragma unroll
     for (int t = 0; t < MQ; t++) top[t] = ~0ull;
 
-    const int nslab = cdiv_s(len, C);
+    const int nslab = (len + cm) >> cs;
     int wbase = -(1 << 30), wslab = 0;
     for (int base = p0; base < p1; base += 64) {
-        const int last_ord = (min(base + 63, p1 - 1)) / C;
+        const int last_ord = min(base + 63, p1 - 1) >> cs;
         if (last_ord >= wbase + 64) {
-            wbase = base / C;
+            wbase = base >> cs;
             wslab = (wbase + lane < nslab) ? slab_of(S, l, wbase + lane) : 0;
         }
         // the 4 result rows of this lane in row group rg: positions base + 16 rg + 4 kgrp .. +3
@@ -1070,32 +1090,34 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
         for (int rg = 0; rg < 4; rg++) {
             const int p = base + 16 * rg + 4 * kgrp;
             const int pc = p < p1 ? p : ((p1 - 1) & ~3);
-            g4[rg] = (int64_t)__shfl(wslab, pc / C - wbase) * C + pc % C;
+            g4[rg] = (int64_t)__shfl(wslab, (pc >> cs) - wbase) * C + (pc & cm);
         }
         float4 xn4[4];
 #pragma unroll
         for (int rg = 0; rg < 4; rg++) xn4[rg] = *reinterpret_cast<const float4 *>(S.xnorm + g4[rg]);
-        f32x4_t acc[4];
+        // A operands of row group rg: slot 16 rg + qcol, chunks 4 b + kgrp; two
+        // row groups in flight (the loads of the next overlap this one's MFMAs).
+        // Chunks past the row repeat its last chunk (their B lanes are zero and
+        // stored values are finite); positions past the item read its last row
+        // and are masked below.
+        const float4 *xr[4];
 #pragma unroll
         for (int rg = 0; rg < 4; rg++) {
             const int p = base + 16 * rg + qcol;
             const int pc = p < p1 ? p : p1 - 1;
-            const int slab = __shfl(wslab, pc / C - wbase);
-            const float4 *xp = S.data + (int64_t)slab * dp4 * C + pc % C;
-            acc[rg] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int b = 0; b < NB; b++) {
-                // chunks past the row repeat its last chunk: their B lanes are zero and the
-                // stored values are finite; positions past the item read its last row and
-                // are masked below
-                const int c = min(4 * b + kgrp, dp4 - 1);
-                const float4 a = xp[(int64_t)c * C];
-                acc[rg] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, bq[b].x, acc[rg], 0, 0, 0);
-                acc[rg] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bq[b].y, acc[rg], 0, 0, 0);
-                acc[rg] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, bq[b].z, acc[rg], 0, 0, 0);
-                acc[rg] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, bq[b].w, acc[rg], 0, 0, 0);
-            }
+            const int slab = __shfl(wslab, (pc >> cs) - wbase);
+            xr[rg] = S.data + (int64_t)slab * dp4 * C + (pc & cm);
         }
+        f32x4_t acc[4];
+        float4 a0[NB], a1[NB];
+        cert_load_a<NB>(a0, xr[0], C, kgrp, dp4);
+        cert_load_a<NB>(a1, xr[1], C, kgrp, dp4);
+        acc[0] = cert_mfma<NB>(a0, sqr + qcol * qs, kgrp, dp4);
+        cert_load_a<NB>(a0, xr[2], C, kgrp, dp4);
+        acc[1] = cert_mfma<NB>(a1, sqr + qcol * qs, kgrp, dp4);
+        cert_load_a<NB>(a1, xr[3], C, kgrp, dp4);
+        acc[2] = cert_mfma<NB>(a0, sqr + qcol * qs, kgrp, dp4);
+        acc[3] = cert_mfma<NB>(a1, sqr + qcol * qs, kgrp, dp4);
         // distance space (L2: the distance; IP: minus the score): value v and
         // certified half-width e of every (slot, query) pair of this lane
         float vv[16], ee[16];
@@ -1187,12 +1209,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
                 const bool act = r0 + lane < total;
                 const int e = pq[act ? r0 + lane : r0];
                 const int t = e & 15, pos = base + (e >> 4);
-                const int slab = __shfl(wslab, pos / C - wbase);
+                const int slab = __shfl(wslab, (pos >> cs) - wbase);
                 uint64_t key = ~0ull;
                 if (act) {
-                    const float r = cert_exact<METRIC>(S.data + (int64_t)slab * dp4 * C + pos % C, C, dp4,
-                                                       q + (int64_t)sqi[t] * d, d, qaln);
-                    key = ((uint64_t)key_hi<METRIC>(r) << 32) | S.sids[(int64_t)slab * C + pos % C];
+                    const float r = cert_exact<METRIC>(S.data + (int64_t)slab * dp4 * C + (pos & cm), C, dp4,
+                                                       sqr + t * qs);
+                    key = ((uint64_t)key_hi<METRIC>(r) << 32) | S.sids[(int64_t)slab * C + (pos & cm)];
                 }
                 // insert the exact keys into their queries' sorted lists, one at a time
 #pragma unroll
@@ -1391,11 +1413,11 @@ bool cert_ok(int storage, int d, int C, int kcap) { return storage == 0 && d <= 
 template <int METRIC, int NB>
 static void launch_cert_nb(hipStream_t st, const Dev &S, const SearchBufs &W, const float *q, int np_stride,
                            int kcap, int k, const int32_t *kpq, int npairs) {
+    const size_t smem = (size_t)MQ * (S.dp4 + 1) * sizeof(float4);
 #define SIVF_LAUNCH_CERT(P)                                                                                  \
-    hipLaunchKernelGGL((k_scan_cert<METRIC, NB, P>), dim3(scan_grid(k_scan_cert<METRIC, NB, P>, S, W, npairs, 0)), \
-                       dim3(64), 0, st, S, W.item_list, W.item_tile, W.item_chunk, W.list_pairs, q, np_stride,  \
-                       kcap, k, kpq, W.partials, qaln)
-    const int qaln = (S.d % 4 == 0) && (((uintptr_t)q & 15) == 0);
+    hipLaunchKernelGGL((k_scan_cert<METRIC, NB, P>), dim3(scan_grid(k_scan_cert<METRIC, NB, P>, S, W, npairs, smem)), \
+                       dim3(64), smem, st, S, W.item_list, W.item_tile, W.item_chunk, W.list_pairs, q, np_stride, \
+                       kcap, k, kpq, W.partials)
     if (S.persistent) SIVF_LAUNCH_CERT(true);
     else SIVF_LAUNCH_CERT(false);
 #undef SIVF_LAUNCH_CERT
