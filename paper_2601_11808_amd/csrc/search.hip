@@ -694,8 +694,8 @@ __global__ __launch_bounds__(256) void k_merge(Dev S, int nq, int np_stride, con
 // within 32 KiB).  Measured on the window workload: T=8 with two dimension
 // chunks in flight beats T=16, whose query operands no longer fit the SGPR
 // file.  The MFMA scan's tile is one 16-column operand.
-int default_tile(int storage, int d) {
-    if (storage != 0) return 16;
+int default_tile(int storage, int d, int C, int kcap) {
+    if (storage != 0 || cert_ok(storage, d, C, kcap)) return 16;
     return d <= 1024 ? 8 : 4;
 }
 

@@ -318,7 +318,7 @@ sivf_status sivf_create(const sivf_config *cfg, const float *centroids, void *wo
     S.metric = cfg->metric;
     S.storage = cfg->storage;
     S.dp8 = (cfg->dim + 7) / 8;
-    S.tile = default_tile(cfg->storage, cfg->dim);
+    S.tile = default_tile(cfg->storage, cfg->dim, cfg->slab_capacity, L.kcap);
     S.chunk_shift = DEFAULT_CHUNK_SHIFT;
     S.persistent = 0;
     S.hdata = cfg->storage != SIVF_F32 ? (uint4 *)(w + L.hdata) : nullptr;

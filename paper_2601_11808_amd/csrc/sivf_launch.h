@@ -56,7 +56,9 @@ struct SearchBufs {
     int64_t *rr_lab;
 };
 int search_tile(const Dev &S);
-int default_tile(int storage, int d);
+// Default queries per work item: 16 (reduced precision, or the certified
+// matrix-core scan where it applies), else 8 (4 past 1024 dimensions).
+int default_tile(int storage, int d, int C, int kcap);
 // Whether the certified FP32 MFMA scan (tile 16 on fp32 slabs) applies.
 bool cert_ok(int storage, int d, int C, int kcap);
 // Default search chunk: 2^14 positions per work item (a list is split only
