@@ -922,16 +922,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
     SIVF_ITEM_LOOP_END
 }
 
-// Insert key c into a list sorted ascending across the lanes (lane i holds
-// the i-th smallest); the largest key drops out.  Keys are distinct.
-__device__ __forceinline__ uint64_t sorted_insert(uint64_t a, uint64_t c) {
+// Insert key c into a list sorted ascending across lanes s0 .. s0 + KC - 1
+// (lane s0 + i holds the i-th smallest); the largest key drops out and the
+// other lanes keep their keys.  Keys are distinct.
+template <int KC>
+__device__ __forceinline__ uint64_t sorted_insert(uint64_t a, uint64_t c, int s0) {
     const int lane = lane_id();
     // previous lane's key: DPP wave_shr:1 (lane 0 keeps its own, unused)
     const uint32_t plo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)a, (int)(uint32_t)a, 0x138, 0xf, 0xf, false);
     const uint32_t phi = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(a >> 32), (int)(uint32_t)(a >> 32), 0x138,
                                                                 0xf, 0xf, false);
     const uint64_t prev = ((uint64_t)phi << 32) | plo;
-    return a < c ? a : ((lane == 0 || prev < c) ? c : prev);
+    const uint64_t r = a < c ? a : ((lane == s0 || prev < c) ? c : prev);
+    return (KC == 64 || (lane >= s0 && lane < s0 + KC)) ? r : a;
 }
 
 // Canonical FP32 value of one (row, query) pair, exactly as the VALU scan
@@ -997,27 +1000,37 @@ __device__ __forceinline__ f32x4_t cert_mfma(const float4 (&a)[NB], const float4
 
 // ------------------------------------------------ certified FP32 MFMA scan
 //
-// FP32 slabs with results identical to the canonical scan.  v_mfma_f32_16x16x4_f32
-// (four times the FP32 VALU rate for this contraction) gives approximate values for
-// 16 slots x 16 queries: Dt = |x|^2 + |q|^2 - 2 x.q (IP: x.q).  A slot can be among a
-// query's k best only if its certified interval reaches the query's current k-th best
-// canonical value; only those slots get their canonical FP32 distance recomputed
-// (sequential fma over ascending dimensions, exactly as the VALU scan computes it) and
-// offered to the query's exact top-k.  The interval half-width bounds the MFMA
-// approximation and the canonical sum's own rounding together:
-// (5d + 32) 2^-24 (|x| + |q|)^2 for L2 and (4d + 32) 2^-24 |x||q| for IP (|x|, |q| from
-// the fp32 squared norms; the margin covers their rounding), plus
-// 2^-122 sqrt(d) (|x| + |q|) + 2^-120 d for underflow.  With rounding error at most
-// one unit 2^-24 per operation the two sums differ from the exact value by at most
-// (2d + 4) 2^-24 (|x| + |q|)^2 (MFMA form, norms included) and (d + 2) 2^-24 |q - x|^2
-// (canonical form); IP: 2d and d times 2^-24 |x||q|.  An overflowing value gives inf or
-// NaN in the test below, and both pass.
+// FP32 slabs with results identical to the canonical scan.  For this contraction
+// v_mfma_f32_16x16x4_f32 does four times the work per cycle of the sub + fma VALU
+// form; it gives approximate values for 16 slots x 16 queries:
+// Dt = |x|^2 + |q|^2 - 2 x.q (L2) or -x.q (IP, as a distance).  A slot can be
+// among a query's k best only if Dt - e is at most the query's current k-th best
+// canonical value; only those pairs get their canonical FP32 distance recomputed
+// (sequential fma over ascending dimensions, exactly as the VALU scan computes it)
+// and inserted into the query's exact sorted list.
 //
-// A operand (lane l): slot l % 16 of the row group, the 4 dimensions of chunk
-// 4 b + l / 16 (one float4), fed to 4 consecutive MFMAs one component each; the B
-// operand holds the same dimensions of query l % 16, so every MFMA pairs equal
-// dimensions and the 4 x NB MFMAs of a row group cover all 16 NB dimensions.
-template <int METRIC, int NB, bool PERS>
+// Half-width e.  With rounding error at most one unit 2^-24 per operation, the MFMA
+// form (norms included) differs from the exact value by at most (2d + 4) 2^-24
+// (|x| + |q|)^2 and the canonical sum by (d + 2) 2^-24 |q - x|^2; IP: 2d and d times
+// 2^-24 |x||q|.  The kernel uses cf (|x| + |q|)^2 with cf = (5d + 32) 2^-24 (IP:
+// (4d + 32) 2^-24 |x||q|), plus 2^-122 sqrt(d) (|x| + |q|) + 2^-120 d for underflow,
+// relaxed to e = e1 (|x|^2 + |q|^2) + e0 so that no square root is needed (the
+// margin covers the rounding of the fp32 norms and of e).  An overflowing value gives
+// inf or NaN in the test, and both pass.
+//
+// Before a query has k exact values (the first step of a work item), its threshold
+// is the k-th smallest upper bound Dt + e among the step's candidates, found by
+// bisection: at least k candidates lie at or below it, so the k best do too.
+//
+// Layout.  A operand (lane l): slot l % 16 of the row group, the 4 dimensions of
+// chunk 4 b + l / 16 (one float4), fed to 4 consecutive MFMAs one component each;
+// the B operand holds the same dimensions of query l % 16 (read from the tile's
+// query rows in LDS), so every MFMA pairs equal dimensions and the 4 x NB MFMAs of
+// a row group cover all 16 NB dimensions.  C (lane l): slots 4 (l / 16) .. +3,
+// query l % 16.  Passing pairs are queued in LDS and recomputed one per lane.
+// Exact lists: KC keys per query sorted across KC lanes, 64 / KC queries per
+// register (KC = 16 for kcap 16, else 64).
+template <int METRIC, int NB, bool PERS, int KC>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_scan_cert(Dev S, const int32_t *__restrict__ item_list,
                                                   const int32_t *__restrict__ item_tile,
                                                   const int32_t *__restrict__ item_chunk,
@@ -1072,9 +1085,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
     // the k-th exact value as a float (L2: distance, IP: score); ~0 maps to NaN, which passes all
     const bool live = qcol < nt && skq[qcol] > 0;
     float thr_f = METRIC == 0 ? from_ord(thr) : from_ord(~thr);
-    uint64_t top[MQ];
+    // sorted exact lists: query t in register t / QPR, lanes KC (t % QPR) .. +KC-1
+    constexpr int QPR = 64 / KC, NR = MQ / QPR;
+    uint64_t top[NR];
 #pragma unroll
-    for (int t = 0; t < MQ; t++) top[t] = ~0ull;
+    for (int r = 0; r < NR; r++) top[r] = ~0ull;
 
     const int nslab = (len + cm) >> cs;
     int wbase = -(1 << 30), wslab = 0;
@@ -1224,10 +1239,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
                         while (cm) {
                             const int src = (int)__builtin_ctzll(cm);
                             cm &= cm - 1;
-                            top[t2] = sorted_insert(top[t2], readlane_u64(key, src));
+                            top[t2 / QPR] = sorted_insert<KC>(top[t2 / QPR], readlane_u64(key, src), KC * (t2 % QPR));
                         }
                         const int kq = skq[t2];   // > 0: only live queries have pairs
-                        const uint32_t nthr = kq > 0 ? (uint32_t)(readlane_u64(top[t2], kq - 1) >> 32) : 0u;
+                        const uint32_t nthr =
+                            kq > 0 ? (uint32_t)(readlane_u64(top[t2 / QPR], KC * (t2 % QPR) + kq - 1) >> 32) : 0u;
                         if (qcol == t2) {
                             thr = nthr;
                             thr_f = METRIC == 0 ? from_ord(thr) : from_ord(~thr);
@@ -1241,7 +1257,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
     SIVF_ITEM_SLOT(MQ)
 #pragma unroll
     for (int t = 0; t < MQ; t++)
-        if (t < nt && lane < kcap) partials[(slot0 + (int64_t)t * nc) * kcap + lane] = top[t];
+        if (t < nt && (lane >> (KC == 64 ? 6 : 4)) == (KC == 64 ? 0 : t % QPR) && (lane & (KC - 1)) < kcap)
+            partials[(slot0 + (int64_t)t * nc) * kcap + (lane & (KC - 1))] = top[t / QPR];
     SIVF_ITEM_LOOP_END
 }
 
@@ -1410,12 +1427,12 @@ void launch_search_plan(hipStream_t st, const Dev &S, const SearchBufs &W, int n
 
 bool cert_ok(int storage, int d, int C, int kcap) { return storage == 0 && d <= 256 && C >= 4 && kcap <= 64; }
 
-template <int METRIC, int NB>
+template <int METRIC, int NB, int KC>
 static void launch_cert_nb(hipStream_t st, const Dev &S, const SearchBufs &W, const float *q, int np_stride,
                            int kcap, int k, const int32_t *kpq, int npairs) {
     const size_t smem = (size_t)MQ * (S.dp4 + 1) * sizeof(float4);
 #define SIVF_LAUNCH_CERT(P)                                                                                  \
-    hipLaunchKernelGGL((k_scan_cert<METRIC, NB, P>), dim3(scan_grid(k_scan_cert<METRIC, NB, P>, S, W, npairs, smem)), \
+    hipLaunchKernelGGL((k_scan_cert<METRIC, NB, P, KC>), dim3(scan_grid(k_scan_cert<METRIC, NB, P, KC>, S, W, npairs, smem)), \
                        dim3(64), smem, st, S, W.item_list, W.item_tile, W.item_chunk, W.list_pairs, q, np_stride, \
                        kcap, k, kpq, W.partials)
     if (S.persistent) SIVF_LAUNCH_CERT(true);
@@ -1427,11 +1444,18 @@ template <int METRIC>
 static void launch_cert(hipStream_t st, const Dev &S, const SearchBufs &W, const float *q, int np_stride, int kcap,
                         int k, const int32_t *kpq, int npairs) {
     // blocks of 16 dimensions held as B operands (d <= 256)
+    // sorted lists of 16 keys (kcap 16: four queries per register) or 64 (kcap 32, 64)
     const int nb = (S.d + 15) / 16;
-    if (nb <= 2) launch_cert_nb<METRIC, 2>(st, S, W, q, np_stride, kcap, k, kpq, npairs);
-    else if (nb <= 4) launch_cert_nb<METRIC, 4>(st, S, W, q, np_stride, kcap, k, kpq, npairs);
-    else if (nb <= 8) launch_cert_nb<METRIC, 8>(st, S, W, q, np_stride, kcap, k, kpq, npairs);
-    else launch_cert_nb<METRIC, 16>(st, S, W, q, np_stride, kcap, k, kpq, npairs);
+#define SIVF_CERT_NB(KC)                                                                                     \
+    do {                                                                                                     \
+        if (nb <= 2) launch_cert_nb<METRIC, 2, KC>(st, S, W, q, np_stride, kcap, k, kpq, npairs);            \
+        else if (nb <= 4) launch_cert_nb<METRIC, 4, KC>(st, S, W, q, np_stride, kcap, k, kpq, npairs);       \
+        else if (nb <= 8) launch_cert_nb<METRIC, 8, KC>(st, S, W, q, np_stride, kcap, k, kpq, npairs);       \
+        else launch_cert_nb<METRIC, 16, KC>(st, S, W, q, np_stride, kcap, k, kpq, npairs);                   \
+    } while (0)
+    if (kcap <= 16) SIVF_CERT_NB(16);
+    else SIVF_CERT_NB(64);
+#undef SIVF_CERT_NB
 }
 
 void launch_search_scan(hipStream_t st, const Dev &S, const SearchBufs &W, int nq, const float *q, int np_stride,

@@ -49,11 +49,15 @@ def _data(kind, rng, n, d):
     raise ValueError(kind)
 
 
-@pytest.mark.parametrize("kind,d,metric,C", [("normal", 128, 0, 64), ("normal", 100, 1, 32), ("offset", 64, 0, 64),
-                                             ("offset", 32, 1, 16), ("tiny", 48, 0, 64), ("grid", 17, 0, 8),
-                                             ("grid", 24, 1, 4), ("normal", 256, 0, 128), ("normal", 5, 1, 64)])
-def test_cert_scan_matches_valu_and_oracle(kind, d, metric, C):
-    rng = np.random.default_rng([KINDS.index(kind), d, metric, C])
+@pytest.mark.parametrize("kind,d,metric,C,mk", [("normal", 128, 0, 64, 64), ("normal", 100, 1, 32, 64),
+                                                ("offset", 64, 0, 64, 64), ("offset", 32, 1, 16, 16),
+                                                ("tiny", 48, 0, 64, 64), ("grid", 17, 0, 8, 64), ("grid", 24, 1, 4, 16),
+                                                ("normal", 256, 0, 128, 64), ("normal", 5, 1, 64, 64),
+                                                ("normal", 128, 0, 64, 16), ("tiny", 40, 1, 32, 16),
+                                                ("grid", 33, 0, 64, 32)])
+def test_cert_scan_matches_valu_and_oracle(kind, d, metric, C, mk):
+    """mk = max_k: 16 keeps four queries' lists per register, 32 and 64 one."""
+    rng = np.random.default_rng([KINDS.index(kind), d, metric, C, mk])
     nlist, n = 13, 6000
     cent = _data(kind, rng, nlist, d)
     x = _data(kind, rng, n, d)
@@ -62,31 +66,31 @@ def test_cert_scan_matches_valu_and_oracle(kind, d, metric, C):
     ids = rng.permutation(n).astype(np.int64)
     q = np.concatenate([_data(kind, rng, 150, d), x[:50]]).astype(np.float32)   # some queries on data rows
     p = Pair(d, nlist, cent, metric, C, num_slabs=n // C + 4 * nlist + 8, id_capacity=n, max_batch=n,
-             max_queries=q.shape[0], max_k=64, max_nprobe=nlist)
+             max_queries=q.shape[0], max_k=mk, max_nprobe=nlist)
     assert p.add(x, ids) == 0
-    for k, nprobe in [(10, 3), (64, 13), (1, 1)]:
+    for k, nprobe in [(10, 3), (mk, 13), (1, 1)]:
         gd, gl = _both(p.gpu, q, k, nprobe)
         st, rd, rl = p.ref.search(q, k, nprobe)
         assert st == 0
         compare_results(gd, gl, rd, rl)
-    kpq = rng.integers(0, 65, q.shape[0]).astype(np.int32)
+    kpq = rng.integers(0, mk + 1, q.shape[0]).astype(np.int32)
     npq = rng.integers(1, nlist + 1, q.shape[0]).astype(np.int32)
-    gd, gl = _both(p.gpu, q, 64, nlist, kpq, npq)
-    st, rd, rl = p.ref.search(q, 64, nlist, k_per_query=kpq, nprobe_per_query=npq)
+    gd, gl = _both(p.gpu, q, mk, nlist, kpq, npq)
+    st, rd, rl = p.ref.search(q, mk, nlist, k_per_query=kpq, nprobe_per_query=npq)
     compare_results(gd, gl, rd, rl)
     # after deletes (tail-swap moves rows and their norms) and upserts
     assert p.remove(ids[::4]) == 0
     assert p.add(x[1::7] * np.float32(0.5), ids[1::7]) == 0
-    gd, gl = _both(p.gpu, q, 32, 5, sched=(16, 10, 1))
-    st, rd, rl = p.ref.search(q, 32, 5)
+    gd, gl = _both(p.gpu, q, min(32, mk), 5, sched=(16, 10, 1))
+    st, rd, rl = p.ref.search(q, min(32, mk), 5)
     compare_results(gd, gl, rd, rl)
-    say(f"  {kind} d={d} metric={metric} C={C}: identical to the VALU scan and the oracle")
+    say(f"  {kind} d={d} metric={metric} C={C} max_k={mk}: identical to the VALU scan and the oracle")
 
 
-@pytest.mark.parametrize("metric", [0, 1])
-def test_cert_scan_split_lists(metric):
+@pytest.mark.parametrize("metric,mk", [(0, 64), (1, 64), (0, 16)])
+def test_cert_scan_split_lists(metric, mk):
     """Long lists split into chunks, both schedules, ragged tails."""
-    rng = np.random.default_rng([77, metric])
+    rng = np.random.default_rng([77, metric, mk])
     sizes = [30001, 12000, 999, 65, 3, 0]
     d = 64
     cent = (rng.standard_normal((len(sizes), d)) * 8).astype(np.float32)
@@ -94,18 +98,19 @@ def test_cert_scan_split_lists(metric):
     ids = rng.permutation(x.shape[0]).astype(np.int64)
     q = (cent[rng.integers(0, len(sizes), 400)] + rng.standard_normal((400, d))).astype(np.float32)
     ix = sivf.Index(d, len(sizes), cent, metric=metric, slab_capacity=64, num_slabs=800, id_capacity=x.shape[0],
-                    max_batch=1 << 16, max_queries=400, max_k=64, max_nprobe=4)
+                    max_batch=1 << 16, max_queries=400, max_k=mk, max_nprobe=4)
     ref = oracle.OracleIndex(d, len(sizes), cent, metric, 64, 800, x.shape[0])
     ix.add(x, ids)
     assert ix.sync() == 0
     assert ref.add(x, ids) == 0
-    st, rd, rl = ref.search(q, 50, 4)
+    k = min(50, mk)
+    st, rd, rl = ref.search(q, k, 4)
     for sched in [(16, 10, 0), (16, 10, 1), (16, 12, 0), (16, 17, 1)]:
-        gd, gl = _both(ix, q, 50, 4, sched=sched)
+        gd, gl = _both(ix, q, k, 4, sched=sched)
         compare_results(gd, gl, rd, rl)
-    t, sh, pm = ix.tune_search(q, 50, 4)
+    t, sh, pm = ix.tune_search(q, k, 4)
     assert ix.sync() == 0
-    gd, gl = ix.search(q, 50, 4)
+    gd, gl = ix.search(q, k, 4)
     assert ix.sync() == 0
     compare_results(gd.cpu().numpy(), gl.cpu().numpy(), rd, rl)
     say(f"  split lists: identical on 4 schedules; tuner chose tile {t}, 2^{sh}, persistent={pm}")
