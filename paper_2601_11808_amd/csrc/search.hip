@@ -12,7 +12,8 @@
 // ballots and lane shifts.  A final kernel merges the per-list partial
 // results of each query.
 //
-//   k_inv_count   rank of each (query, probe) pair within its list
+//   k_inv_count   rank of each (query, probe) pair within its list (or
+//                 k_inv_count_lds: block histograms, fewer global atomics)
 //   k_inv_plan    per-list pair offsets; work items (list, tile)
 //   k_inv_scatter pair ids grouped by list
 //   k_scan        one wave per item: distances + per-query top-kcap
@@ -31,6 +32,36 @@ __global__ __launch_bounds__(256) void k_inv_count(Dev S, int npairs, const int3
     const bool act = l >= 0;
     const int r = act ? atomicAdd(&S.l_qc[l], 1) : 0;   // a wave's 64 pairs hit ~64 distinct lists
     if (active) pair_rank[p] = act ? r : -1;
+}
+
+// The same ranks with one device-scope atomic per (block, list) instead of
+// one per pair: a block of 1024 threads takes INV_PB pairs, ranks them
+// within the block by LDS atomics on a per-list histogram (nlist ints of
+// dynamic LDS), reserves each list's block total with one atomic on l_qc,
+// and adds that base.  Used when the histogram fits in 64 KiB.
+constexpr int INV_PB = 8192;
+__global__ __launch_bounds__(1024) void k_inv_count_lds(Dev S, int npairs, const int32_t *__restrict__ probes,
+                                                        int32_t *__restrict__ pair_rank) {
+    extern __shared__ int32_t hist[];
+    const int tid = threadIdx.x;
+    const int64_t p0 = (int64_t)blockIdx.x * INV_PB;
+    const int n = (int)min((int64_t)INV_PB, (int64_t)npairs - p0);
+    for (int i = tid; i < S.nlist; i += 1024) hist[i] = 0;
+    __syncthreads();
+    for (int i = tid; i < n; i += 1024) {
+        const int l = probes[p0 + i];
+        pair_rank[p0 + i] = l >= 0 ? atomicAdd(&hist[l], 1) : -1;
+    }
+    __syncthreads();
+    for (int i = tid; i < S.nlist; i += 1024) {
+        const int c = hist[i];
+        if (c > 0) hist[i] = atomicAdd(&S.l_qc[i], c);
+    }
+    __syncthreads();
+    for (int i = tid; i < n; i += 1024) {
+        const int l = probes[p0 + i];
+        if (l >= 0) pair_rank[p0 + i] += hist[l];
+    }
 }
 
 // Block sums of two int64 values (every thread gets both totals).
@@ -1415,7 +1446,11 @@ void launch_search_plan(hipStream_t st, const Dev &S, const SearchBufs &W, int n
     const int npairs = nq * np_stride;
     const unsigned pb = (unsigned)((npairs + 255) / 256);
     const int T = search_tile(S);
-    hipLaunchKernelGGL(k_inv_count, dim3(pb), dim3(256), 0, st, S, npairs, W.probes, W.pair_rank);
+    if (S.nlist <= 16384)
+        hipLaunchKernelGGL(k_inv_count_lds, dim3((unsigned)((npairs + INV_PB - 1) / INV_PB)), dim3(1024),
+                           (size_t)S.nlist * 4, st, S, npairs, W.probes, W.pair_rank);
+    else
+        hipLaunchKernelGGL(k_inv_count, dim3(pb), dim3(256), 0, st, S, npairs, W.probes, W.pair_rank);
     const int64_t lim = item_limit(S, W, npairs);
     hipLaunchKernelGGL(k_inv_plan, dim3(1), dim3(1024), 0, st, S, T, S.chunk_shift, W.slot_cap, lim,
                        (int)((lim + 7) / 8));
