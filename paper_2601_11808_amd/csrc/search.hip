@@ -851,21 +851,38 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
 #pragma unroll
             for (int rg = 0; rg < 4; rg++) xn4[rg] = *reinterpret_cast<const float4 *>(S.xnorm + g4[rg]);
         }
-        f32x4_t acc[4];
+        // A operands of row group rg: slot 16 rg + qcol, 8-dim chunks 4 kb + kgrp;
+        // two row groups in flight.  Chunks past the row repeat its last chunk
+        // (their B lanes are zero); positions past the item read its last row
+        // and are masked below.
+        const uint4 *hr[4];
 #pragma unroll
         for (int rg = 0; rg < 4; rg++) {
             const int p = base + 16 * rg + qcol;
             const int pc = p < p1 ? p : p1 - 1;
             const int slab = __shfl(wslab, (pc >> cs) - wbase);
-            const uint4 *hp = S.hdata + (int64_t)slab * dp8 * C + (pc & cm);
-            acc[rg] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int kb = 0; kb < NKB; kb++) {
-                const int c8 = 4 * kb + kgrp;
-                const uint4 a = (c8 < dp8 && p < p1) ? hp[(int64_t)c8 * C] : make_uint4(0, 0, 0, 0);
-                acc[rg] = mfma_16x16x32<DT>(a, bq[kb], acc[rg]);
-            }
+            hr[rg] = S.hdata + (int64_t)slab * dp8 * C + (pc & cm);
         }
+        f32x4_t acc[4];
+        uint4 a0[NKB], a1[NKB];
+        auto load_a = [&](uint4 (&a)[NKB], const uint4 *h) {
+#pragma unroll
+            for (int kb = 0; kb < NKB; kb++) a[kb] = h[(int64_t)min(4 * kb + kgrp, dp8 - 1) * C];
+        };
+        auto mma = [&](const uint4 (&a)[NKB]) {
+            f32x4_t c = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kb = 0; kb < NKB; kb++) c = mfma_16x16x32<DT>(a[kb], bq[kb], c);
+            return c;
+        };
+        load_a(a0, hr[0]);
+        load_a(a1, hr[1]);
+        acc[0] = mma(a0);
+        load_a(a0, hr[2]);
+        acc[1] = mma(a1);
+        load_a(a1, hr[3]);
+        acc[2] = mma(a0);
+        acc[3] = mma(a1);
         float vv[16];
         uint32_t pmask = 0;
         const int lim = p1 - base;   // positions of this step inside the item (64 except at its end)
