@@ -1075,7 +1075,9 @@ __device__ __forceinline__ f32x4_t cert_mfma(const float4 (&a)[NB], const float4
 // the B operand holds the same dimensions of query l % 16 (read from the tile's
 // query rows in LDS), so every MFMA pairs equal dimensions and the 4 x NB MFMAs of
 // a row group cover all 16 NB dimensions.  C (lane l): slots 4 (l / 16) .. +3,
-// query l % 16.  Passing pairs are queued in LDS and recomputed one per lane.
+// query l % 16.  Passing pairs are queued in LDS and recomputed one per lane,
+// in full rounds of 64 (the queue drains early when a query has no k-th value
+// yet, before the slab window moves, and at the end of the item).
 // Exact lists: KC keys per query sorted across KC lanes, 64 / KC queries per
 // register (KC = 16 for kcap 16, else 64).
 template <int METRIC, int NB, bool PERS, int KC>
@@ -1087,7 +1089,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
                                                   const int32_t *__restrict__ kpq,
                                                   uint64_t *__restrict__ partials) {
     extern __shared__ float4 sqr[];    // the tile's 16 query rows, zero-padded to dp4 chunks, stride dp4 + 1
-    __shared__ uint16_t pq[64 * MQ];   // passing pairs of a step: position << 4 | query
+    __shared__ uint32_t pq[64 * MQ + 64];   // queued passing pairs: window position << 4 | query
     __shared__ int skq[MQ];
     const int lane = threadIdx.x, qcol = lane & 15, kgrp = lane >> 4;
     const int d = S.d, C = S.C, dp4 = S.dp4, sh = S.ctl[CTL_CHUNK];
@@ -1141,6 +1143,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
 
     const int nslab = (len + cm) >> cs;
     int wbase = -(1 << 30), wslab = 0;
+    int qn = 0;   // queued pairs (fewer than 64 carry over to the next step)
     for (int base = p0; base < p1; base += 64) {
         const int last_ord = min(base + 63, p1 - 1) >> cs;
         if (last_ord >= wbase + 64) {
@@ -1250,8 +1253,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
                     if (16 * rg + 4 * kgrp + j >= lim) pmask &= ~(1u << (4 * rg + j));
         }
         if (ballot(pmask != 0)) {
-            // queue the passing (position, query) pairs in lane order, then
-            // recompute them 64 at a time, one pair per lane
+            // queue the passing (position, query) pairs in lane order
             const int np = __builtin_popcount(pmask);
             int incl = np;
 #pragma unroll
@@ -1259,34 +1261,42 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
                 const int u = __shfl_up(incl, o);
                 if (lane >= o) incl += u;
             }
-            const int total = __shfl(incl, 63);
-            int at = incl - np;
+            int at = qn + incl - np;
+            qn += __shfl(incl, 63);
+            const int wpos = base - (wbase << cs);   // queued positions are relative to the slab window
             uint32_t m = pmask;
             while (m) {
                 const int bit = __builtin_ctz(m);
                 m &= m - 1;
-                pq[at++] = (uint16_t)(((16 * (bit >> 2) + 4 * kgrp + (bit & 3)) << 4) | qcol);
+                pq[at++] = ((uint32_t)(wpos + 16 * (bit >> 2) + 4 * kgrp + (bit & 3)) << 4) | (uint32_t)qcol;
             }
+        }
+        // Recompute full rounds of 64 pairs; everything when a query still waits
+        // for its first k-th value, before the slab window moves, and at the end.
+        const int nb = base + 64;
+        const bool drain = ballot(live && thr == 0xFFFFFFFFu) != 0 || nb >= p1 ||
+                           (min(nb + 63, p1 - 1) >> cs) >= wbase + 64;
+        const int nproc = drain ? qn : (qn & ~63);
+        if (nproc > 0) {
             __syncthreads();
-            for (int r0 = 0; r0 < total; r0 += 64) {
-                const bool act = r0 + lane < total;
-                const int e = pq[act ? r0 + lane : r0];
-                const int t = e & 15, pos = base + (e >> 4);
-                const int slab = __shfl(wslab, (pos >> cs) - wbase);
+            for (int r0 = 0; r0 < nproc; r0 += 64) {
+                const bool act = r0 + lane < nproc;
+                const uint32_t e = pq[act ? r0 + lane : r0];
+                const int t = (int)(e & 15), pw = (int)(e >> 4);
+                const int slab = __shfl(wslab, pw >> cs), slot = pw & cm;
                 uint64_t key = ~0ull;
                 if (act) {
-                    const float r = cert_exact<METRIC>(S.data + (int64_t)slab * dp4 * C + (pos & cm), C, dp4,
-                                                       sqr + t * qs);
-                    key = ((uint64_t)key_hi<METRIC>(r) << 32) | S.sids[(int64_t)slab * C + (pos & cm)];
+                    const float r = cert_exact<METRIC>(S.data + (int64_t)slab * dp4 * C + slot, C, dp4, sqr + t * qs);
+                    key = ((uint64_t)key_hi<METRIC>(r) << 32) | S.sids[(int64_t)slab * C + slot];
                 }
                 // insert the exact keys into their queries' sorted lists, one at a time
 #pragma unroll
                 for (int t2 = 0; t2 < MQ; t2++) {
-                    uint64_t cm = ballot(act && t == t2);
-                    if (cm) {
-                        while (cm) {
-                            const int src = (int)__builtin_ctzll(cm);
-                            cm &= cm - 1;
+                    uint64_t bm = ballot(act && t == t2);
+                    if (bm) {
+                        while (bm) {
+                            const int src = (int)__builtin_ctzll(bm);
+                            bm &= bm - 1;
                             top[t2 / QPR] = sorted_insert<KC>(top[t2 / QPR], readlane_u64(key, src), KC * (t2 % QPR));
                         }
                         const int kq = skq[t2];   // > 0: only live queries have pairs
@@ -1299,8 +1309,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
                     }
                 }
             }
-            __syncthreads();   // the queue is rewritten by the next step
+            // move the unprocessed tail (< 64 pairs) to the front
+            const int rest = qn - nproc;
+            const uint32_t v = lane < rest ? pq[nproc + lane] : 0u;
+            __syncthreads();
+            if (lane < rest) pq[lane] = v;
+            qn = rest;
         }
+        __syncthreads();   // queue writes of this step before the next step's appends
     }
     SIVF_ITEM_SLOT(MQ)
 #pragma unroll
