@@ -129,3 +129,47 @@ def test_cert_schedule_limits():
     for d, max_k, C in [(257, 16, 64), (64, 65, 64), (64, 16, 2)]:
         with pytest.raises(sivf.SivfError):
             mk(d, max_k, C).set_search_schedule(16, 14, 0)
+
+
+def test_cert_random_configs():
+    """150 seeded random configurations (d 1..256, C 4..128, L2/IP, max_k 16/32/64, data from 1e-25 to 1e18
+    in scale, repeated rows and one-ulp neighbours, random schedules): tile 16 and tile 8 agree bit for bit."""
+    rng = np.random.default_rng(2026)
+    for it in range(150):
+        d = int(rng.integers(1, 257))
+        C = int(rng.choice([4, 8, 16, 32, 64, 128]))
+        metric = int(rng.integers(0, 2))
+        mk = int(rng.choice([16, 32, 64]))
+        nlist = int(rng.integers(1, 30))
+        n = int(rng.integers(1, 6000))
+        kind = ["normal", "offset", "tiny", "grid", "mixed", "huge"][it % 6]
+        if kind == "normal":
+            x = rng.standard_normal((n, d))
+        elif kind == "offset":
+            x = float(10 ** rng.uniform(0, 4)) + rng.standard_normal((n, d))
+        elif kind == "tiny":
+            x = 10 ** rng.uniform(-25, -15) * rng.standard_normal((n, d))
+        elif kind == "grid":
+            x = rng.integers(-3, 4, (n, d)).astype(np.float64)
+        elif kind == "mixed":
+            x = rng.standard_normal((n, d)) * (10 ** rng.uniform(-3, 3, (n, 1)))
+        else:
+            x = 10 ** rng.uniform(10, 18) * rng.standard_normal((n, d))
+        x = x.astype(np.float32)
+        if n > 40:
+            x[n // 2:n // 2 + 10] = x[:10]
+            x[n // 2 + 10:n // 2 + 20] = np.nextafter(x[:10], np.float32(np.inf))
+        nq = int(rng.integers(1, 200))
+        q = np.concatenate([x[rng.integers(0, n, nq // 2)],
+                            x[rng.integers(0, n, nq - nq // 2)] +
+                            (np.float32(1e-3) * rng.standard_normal((nq - nq // 2, d))).astype(np.float32)])
+        q = q.astype(np.float32)
+        cent = (x[rng.integers(0, n, nlist)] + np.float32(0.1) * rng.standard_normal((nlist, d))).astype(np.float32)
+        ix = sivf.Index(d, nlist, cent, metric=metric, slab_capacity=C, num_slabs=n // C + 2 * nlist + 8,
+                        id_capacity=n, max_batch=n, max_queries=nq, max_k=mk, max_nprobe=nlist)
+        ix.add(x, rng.permutation(n).astype(np.int64))
+        assert ix.sync() == 0
+        k, nprobe = int(rng.integers(1, mk + 1)), int(rng.integers(1, nlist + 1))
+        _both(ix, q, k, nprobe, sched=(16, int(rng.integers(6, 18)), int(rng.integers(0, 2))))
+        del ix
+    say("  150 random configurations: identical")
