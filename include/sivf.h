@@ -184,7 +184,7 @@ sivf_status sivf_step(sivf_index *ix, const sivf_step_args *args, void *stream);
 
 /* A window step captured once as a HIP graph and replayed: the ~30 kernel
  * launches of a step are recorded once and replayed as one graph launch
- * (the paper finds that amortising kernel-launch overhead is a key driver of
+ * (the paper finds that amortising kernel-launch overhead is a major factor in
  * mutation latency, Sec. 5.2.3).  The graph records the pointers in `args`:
  * before each launch, write the new batch into the same buffers.  Counts
  * (n_add, nq, k, nprobe, n_remove) are fixed per graph, so create one graph
