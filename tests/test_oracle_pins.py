@@ -356,3 +356,40 @@ def test_deleted_never_returned_and_exact_knn():
     kd, ki = ix.knn_exact(q, 10)                       # FP64 exact, same ties
     np.testing.assert_array_equal(ki, wi)
     np.testing.assert_array_equal(kd, wd.astype(np.float64))
+
+
+def test_knn_exact_ip_bruteforce_before_and_after_deletes():
+    """The inner-product branch of the FP64 exact kNN (the recall ground truth
+    of the inner-product precision form): on integer data every product and
+    partial sum is exact, so numpy brute force ranked by descending score,
+    ties to the smaller id, is an independent reference.  Duplicated rows
+    give exact ties; signed values give negative scores (a sign slip in the
+    score, or an ascending order, fails)."""
+    rng = np.random.default_rng(48)
+    n, d, nlist = 1800, 9, 6
+    cent = rng.integers(-16, 17, (nlist, d)).astype(np.float32)
+    x = rng.integers(-16, 17, (n, d)).astype(np.float32)
+    x[n // 2: n // 2 + 30] = x[:30]
+    ix = oracle.OracleIndex(d, nlist, cent, oracle.IP, 8, num_slabs=100_000, id_capacity=n)
+    assert ix.add(x, np.arange(n)) == 0
+    q = rng.integers(-16, 17, (25, d)).astype(np.float32)
+    q[:4] = x[:4]
+    q[4] = -x[5]
+    for live in (np.arange(n), None):
+        if live is None:
+            rm = rng.choice(n, n // 3, replace=False)
+            st, nr = ix.remove(rm)
+            assert st == 0 and nr == len(rm)
+            live = np.setdiff1d(np.arange(n), rm)
+        kd, ki = ix.knn_exact(q, 12)
+        wd, wi = _brute_int(x[live], q, live.astype(np.int64), 12, metric=oracle.IP)
+        np.testing.assert_array_equal(ki, wi)
+        np.testing.assert_array_equal(kd, wd.astype(np.float64))
+        assert (np.diff(kd, axis=1) <= 0).all()          # scores descending
+    # more results asked for than live entries: padding with -1 and -inf
+    small = oracle.OracleIndex(d, nlist, cent, oracle.IP, 8, num_slabs=100, id_capacity=n)
+    assert small.add(x[:3], np.arange(3)) == 0
+    kd, ki = small.knn_exact(q[:2], 5)
+    wd, wi = _brute_int(x[:3], q[:2], np.arange(3), 3, metric=oracle.IP)
+    np.testing.assert_array_equal(ki[:, :3], wi)
+    assert (ki[:, 3:] == -1).all() and (kd[:, 3:] == -np.inf).all()
