@@ -49,26 +49,44 @@ MFMA32_PEAK_TFLOPS = 157.3
 MFMA16_PEAK_TFLOPS = 2500.0
 
 
+HBM_PEAK_GBPS = 8000.0
+
+
 def fp32_scan_roofline(evals, d, scan_ms, tile, traffic=None):
-    """Roofline of the FP32 scan that ran: the certified matrix-core scan (tile
-    16) is bounded by FP32 MFMA on its 2d-flop contraction per (query, row)
-    pair; the VALU scan by packed-off FP32 VALU on 3d flops (sub + fma per
-    dimension).  Both report the exact-distance rate (3d per pair) too."""
+    """Roofline of the FP32 scan that ran.
+
+    Bound: a list is read once per work item of `tile` queries, so one
+    (query, list entry) evaluation moves (4d + 4) / tile bytes of slab rows and
+    ids; at tile 16 that is 0.75 * 16 = 12 flop/B of exact-distance work
+    against a ridge of 157.3 / 8 = 19.7 flop/B, so the certified scan is
+    HBM-bound and is reported against the HBM peak.  The VALU scan (tiles 4
+    and 8) sits at 3d*tile/(4d+4) <= 6 flop/B, under its own ridge of 9.8 only
+    because packed FP32 is off, and is reported against the FP32 VALU peak on
+    its 3d flops per evaluation.  The matrix-core accounting of the certified
+    scan (2 * 4 * ceil(d / 4) flops per evaluation against the FP32 MFMA peak)
+    is kept beside it."""
     exact_tf = evals * 3.0 * d / (scan_ms * 1e-3) / 1e12
     if tile == 16:
+        per_eval = (4.0 * d + 4.0) / tile
+        gbps = evals * per_eval / (scan_ms * 1e-3) / 1e9
         tf = evals * 2.0 * 4 * ((d + 3) // 4) / (scan_ms * 1e-3) / 1e12
-        roof = {"bound": "mfma", "kernel": "k_scan_cert", "achieved": round(tf, 3),
-                "peak": MFMA32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(tf / MFMA32_PEAK_TFLOPS, 4),
-                "flops_per_eval": 2 * 4 * ((d + 3) // 4)}
+        roof = {"bound": "hbm", "kernel": "k_scan_cert", "achieved": round(gbps, 1), "peak": HBM_PEAK_GBPS,
+                "unit": "GB/s", "frac": round(gbps / HBM_PEAK_GBPS, 4),
+                "bytes_per_eval": per_eval, "algorithmic_bytes_per_launch": int(evals * per_eval),
+                "mfma": {"achieved_tflops": round(tf, 3), "peak_tflops": MFMA32_PEAK_TFLOPS,
+                         "frac": round(tf / MFMA32_PEAK_TFLOPS, 4), "flops_per_eval": 2 * 4 * ((d + 3) // 4)}}
     else:
         roof = {"bound": "alu", "kernel": "k_scan_sq", "achieved": round(exact_tf, 3),
                 "peak": round(ALU_PEAK_TFLOPS, 2), "unit": "TFLOP/s", "frac": round(exact_tf / ALU_PEAK_TFLOPS, 4),
                 "flops_per_eval": 3 * d}
     roof.update({"traffic": traffic,
-                 "traffic_unit": "bytes per launch (DRAM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                 "traffic_unit": "bytes per launch (DRAM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated; "
+                                 "taken from the committed counter summary while the scan source is unchanged)",
                  "evals_per_launch": evals, "exact_distance_tflops": round(exact_tf, 3),
                  "avg_launch_ms": round(scan_ms, 4)})
     return roof
+
+
 STORAGE = {"f32": 0, "bf16": 1, "f16": 2}
 
 
@@ -90,6 +108,10 @@ def parse():
     ap.add_argument("--no-sweep", action="store_true", help="skip the nprobe / recall sweep")
     ap.add_argument("--schedule", default=None,
                     help="T,log2chunk,persistent: set the search schedule instead of running the autotuner")
+    ap.add_argument("--latency-steps", type=int, default=1000,
+                    help="window: steady-state steps of each latency leg (at B and at B=1000); 0 skips them")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="window: skip the bf16 form and the bulk-mutation leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (scale for DRAM byte counters)")
     return ap.parse_args()
@@ -134,35 +156,197 @@ def exact_topk(xw, idw, q, k, metric, chunk=1 << 18):
     return best_i
 
 
-def cpu_baseline(w, x, ids, q, batches, nprobe, k, n_sample_q):
-    """The CPU oracle on a bounded sample of the same workload: one window
-    step (insert a batch, search a query sample, delete a batch) on the full
-    window; the search time is scaled to the full query batch."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, x, ids, q, nprobe, k, n_sample_q, reps=3):
+    """The CPU oracle on a bounded sample of the same workload: window steps
+    (insert a batch, search a query sample, delete the oldest batch) on the
+    full window, three steps, median; the search time is scaled to the full
+    query batch."""
     import oracle
     ix = oracle.OracleIndex(w.dim, w.nlist, w.centroids, w.metric, w.slab, 1 << 26, ids.shape[0] + 4 * w.batch)
     t0 = time.time()
     assert ix.add(x, ids) == 0
     build_s = time.time() - t0
-    xb, idb, old = batches
-    t0 = time.time()
-    assert ix.add(xb, idb) == 0
-    t_add = time.time() - t0
-    t0 = time.time()
-    st, _, _ = ix.search(q[:n_sample_q], k, nprobe)
-    t_search = time.time() - t0
-    t0 = time.time()
-    st, nr = ix.remove(old)
-    t_rm = time.time() - t0
-    step_s = t_add + t_search * (q.shape[0] / n_sample_q) + t_rm
+    rates, parts = [], []
+    for t in range(1, reps + 1):
+        xb, idb = w.stream_batch(t)
+        old = w.oldest_ids(t)
+        t0 = time.time()
+        assert ix.add(xb, idb) == 0
+        t_add = time.time() - t0
+        t0 = time.time()
+        st, _, _ = ix.search(q[:n_sample_q], k, nprobe)
+        t_search = time.time() - t0
+        t0 = time.time()
+        st, nr = ix.remove(old)
+        t_rm = time.time() - t0
+        step_s = t_add + t_search * (q.shape[0] / n_sample_q) + t_rm
+        rates.append(q.shape[0] / step_s)
+        parts.append((t_add, t_search, t_rm))
     ix.close()
+    med = int(np.argsort(rates)[len(rates) // 2])
+    t_add, t_search, t_rm = parts[med]
     return {
-        "value": q.shape[0] / step_s, "unit": "queries/s", "cores": oracle.num_threads(), "kind": "oracle",
-        "sample": (f"one window step on the full {ids.shape[0]}-vector window: insert {xb.shape[0]} "
-                   f"({t_add:.2f} s), search {n_sample_q} of {q.shape[0]} queries ({t_search:.2f} s, scaled "
-                   f"x{q.shape[0] / n_sample_q:.0f}), delete {old.shape[0]} ({t_rm:.3f} s); "
-                   f"untimed window build {build_s:.1f} s"),
-        "insert_vec_per_s": xb.shape[0] / t_add, "delete_vec_per_s": old.shape[0] / max(t_rm, 1e-9),
+        "value": round(float(rates[med]), 1), "unit": "queries/s", "cores": oracle.num_threads(), "kind": "oracle",
+        "cpu_model": cpu_model(), "host_cpus": os.cpu_count(), "repetitions": reps,
+        "all_values": [round(float(r), 1) for r in rates],
+        "sample": (f"median of {reps} window steps on the full {ids.shape[0]}-vector window; median step: insert "
+                   f"{w.batch} ({t_add:.2f} s), search {n_sample_q} of {q.shape[0]} queries ({t_search:.2f} s, "
+                   f"scaled x{q.shape[0] / n_sample_q:.0f}), delete {w.batch} ({t_rm:.3f} s); untimed window "
+                   f"build {build_s:.1f} s"),
+        "insert_vec_per_s": round(w.batch / t_add, 1), "delete_vec_per_s": round(w.batch / max(t_rm, 1e-9), 1),
     }
+
+
+def latency_leg(ix, pool, q, k, nprobe, first_add_id, first_old_id, n_base, B, steps, dist, lab):
+    """Host wall-clock per window step (add B, search, remove the oldest B;
+    synchronised at the end of each step) over `steps` steady-state steps.
+    Vectors come from a device-resident pool of earlier stream batches under
+    fresh ids, so the window keeps its size and distribution."""
+    import torch
+    dev = pool.device
+    ids = torch.arange(first_add_id, first_add_id + B * steps, device=dev)
+    olds = torch.arange(first_old_id, first_old_id + B * steps, device=dev)
+    npool = pool.shape[0] // B
+    times = []
+    torch.cuda.synchronize()
+    for s_ in range(steps):
+        xb = pool[(s_ % npool) * B:(s_ % npool + 1) * B]
+        ts = time.perf_counter()
+        ix.step(xb, ids[s_ * B:(s_ + 1) * B], q, k, nprobe, olds[s_ * B:(s_ + 1) * B], out=(dist, lab))
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - ts) * 1e3)
+    assert ix.sync() == 0
+    assert ix.stats()["live"] == n_base
+    v = np.sort(np.array(times))
+    return {"batch": B, "steps": steps, "p50_ms": round(float(np.percentile(v, 50)), 4),
+            "p99_ms": round(float(np.percentile(v, 99)), 4), "max_ms": round(float(v[-1]), 4),
+            "mean_ms": round(float(v.mean()), 4)}, first_add_id + B * steps, first_old_id + B * steps
+
+
+def bulk_mutation_leg(w, x, ids, reps=3):
+    """Mutation kernels at bulk scale on the window data: the whole window
+    inserted in one call, then half of it (uniformly random ids) deleted in
+    one call; device time of each call from the library's HIP events, median
+    of `reps` after one warm-up.  Algorithmic bytes per unit: insert 4d (read)
+    + 4d (write) + 4 (id) + 4 (address table) per vector; delete 4 (address
+    table read) + 2 (4d + 4) (a tail entry moved into the hole) + 8 (two
+    address-table writes) per removed id, the upper bound the method moves."""
+    import torch
+    import paper_2601_11808_amd as sivf
+    dev = torch.device("cuda:0")
+    N, d = x.shape
+    num_slabs = int(1.15 * N / w.slab) + w.nlist
+    ix = sivf.Index(w.dim, w.nlist, w.centroids, metric=w.metric, slab_capacity=w.slab, num_slabs=num_slabs,
+                    id_capacity=N, max_batch=N, max_queries=16, max_k=16, max_nprobe=16, device="cuda:0")
+    xd, idd = torch.from_numpy(x).to(dev), torch.from_numpy(ids).to(dev)
+    rng = np.random.default_rng([w.seed, 7, 0])
+    add_ms, rm_ms = [], []
+    for r in range(reps + 1):
+        rm = torch.from_numpy(np.sort(rng.choice(N, N // 2, replace=False)).astype(np.int64)).to(dev)
+        torch.cuda.synchronize()
+        ix.profile_read()
+        ix.profile(True)
+        ix.add(xd, idd)
+        assert ix.sync() == 0
+        pa = ix.profile_read()
+        nr = ix.remove(rm)
+        assert ix.sync() == 0
+        pr = ix.profile_read()
+        ix.profile(False)
+        assert int(nr.item()) == N // 2
+        ix.remove(idd)                      # empty the index for the next repetition
+        assert ix.sync() == 0 and ix.stats()["live"] == 0
+        if r > 0:
+            add_ms.append(pa["add"][0])
+            rm_ms.append(pr["remove"][0])
+    ix.close()
+    del ix, xd, idd
+    torch.cuda.empty_cache()
+    ins_b = N * (4 * d + 4 * d + 8)
+    del_b = (N // 2) * (4 + 2 * (4 * d + 4) + 8)
+    am, rmm = float(np.median(add_ms)), float(np.median(rm_ms))
+    ins_gbps, del_gbps = ins_b / (am * 1e-3) / 1e9, del_b / (rmm * 1e-3) / 1e9
+    return {
+        "insert": {"vectors": N, "ms": round(am, 4), "vec_per_s": round(N / (am * 1e-3), 1),
+                   "algorithmic_bytes": ins_b, "GBps": round(ins_gbps, 1), "frac": round(ins_gbps / HBM_PEAK_GBPS, 4),
+                   "bytes_per_vector": 8 * d + 8,
+                   "note": "the call includes the exact coarse assignment (FP32 MFMA GEMM + FP64 re-check)"},
+        "delete": {"ids": N // 2, "ms": round(rmm, 4), "vec_per_s": round((N // 2) / (rmm * 1e-3), 1),
+                   "algorithmic_bytes": del_b, "GBps": round(del_gbps, 1), "frac": round(del_gbps / HBM_PEAK_GBPS, 4),
+                   "bytes_per_id": 4 + 2 * (4 * d + 4) + 8},
+        "repetitions": reps,
+    }
+
+
+def build_window_index(sivf, w, x, ids, storage, rerank, id_cap, B, nq, nprobe, dev):
+    import torch
+    num_slabs = int(1.15 * (w.n_base + 2 * B) / w.slab) + w.nlist
+    chunk = 65536
+    ix = sivf.Index(w.dim, w.nlist, w.centroids, metric=w.metric, slab_capacity=w.slab, num_slabs=num_slabs,
+                    id_capacity=id_cap, max_batch=max(chunk, B), max_queries=nq, max_k=16,
+                    max_nprobe=max(128, nprobe), storage=storage, rerank_factor=rerank, device="cuda:0")
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    bulk_ms = 0.0
+    for s0 in range(0, x.shape[0], 1 << 20):
+        xd = torch.from_numpy(x[s0:s0 + (1 << 20)]).to(dev)
+        idd = torch.from_numpy(ids[s0:s0 + (1 << 20)]).to(dev)
+        torch.cuda.synchronize()
+        e0.record()
+        for c in range(0, xd.shape[0], chunk):
+            ix.add(xd[c:c + chunk], idd[c:c + chunk])
+        e1.record()
+        assert ix.sync() == 0
+        bulk_ms += e0.elapsed_time(e1)
+    return ix, bulk_ms
+
+
+def timed_steps(ix, bx, bi, bo, qd, k, nprobe, dist, lab, t_from, t_to):
+    import torch
+    ix.profile_read()
+    ix.profile(True)
+    step_ms = []
+    torch.cuda.synchronize()
+    t_all = time.perf_counter()
+    for t in range(t_from, t_to):
+        ts = time.perf_counter()
+        ix.step(bx[t], bi[t], qd, k, nprobe, bo[t], out=(dist, lab))
+        torch.cuda.synchronize()
+        step_ms.append((time.perf_counter() - ts) * 1e3)
+    elapsed = time.perf_counter() - t_all
+    prof = ix.profile_read()
+    ix.profile(False)
+    assert ix.sync() == 0
+    return elapsed, step_ms, prof
+
+
+def nprobe_sweep(ix, qd, k, nq, nprobe, grid, recall_of, dist, lab):
+    sweep = []
+    ix.profile(True)
+    for npb in grid:
+        ix.search(qd, k, npb, out=(dist, lab))
+        ix.sync()
+        ix.profile_read()
+        for _ in range(3):
+            ix.search(qd, k, npb, out=(dist, lab))
+        pr = ix.profile_read()
+        sms = pr["search"][0] / max(pr["search"][1], 1)
+        sweep.append({"nprobe": npb, "recall_at_10": round(recall_of(lab.cpu().numpy()), 4),
+                      "search_qps": round(nq / (sms * 1e-3), 1)})
+    ix.profile(False)
+    ok95 = [r for r in sweep if r["recall_at_10"] >= 0.95]
+    best95 = max(ok95, key=lambda r: r["search_qps"]) if ok95 else None
+    return sweep, best95
 
 
 def main():
@@ -196,34 +380,18 @@ def main():
     B, nq, k, nprobe = w.batch, q.shape[0], w.k, w.nprobe
     T = a.warmup + a.steps
     T2 = T + a.steps
+    lat_steps = a.latency_steps if a.workload == "window" else 0
+    B_small = 1000
     log(f"[bench] workload {w.name}: N={w.n_base} d={w.dim} nlist={w.nlist} C={w.slab} B={B} nq={nq} "
         f"storage={storage} (generated in {time.time() - t0:.1f} s)")
-    num_slabs = int(1.15 * (w.n_base + 2 * B) / w.slab) + w.nlist
-    id_cap = w.n_base + B * (T2 + 2)   # timed loop, then as many graph-mode steps
-    chunk = 65536
-    ix = sivf.Index(w.dim, w.nlist, w.centroids, metric=w.metric, slab_capacity=w.slab, num_slabs=num_slabs,
-                    id_capacity=id_cap, max_batch=max(chunk, B), max_queries=nq, max_k=16,
-                    max_nprobe=max(128, nprobe), storage=st_code, rerank_factor=rerank, device="cuda:0")
-    log(f"[bench] workspace {ix.workspace_bytes / 2**30:.2f} GiB")
-    # bulk load (device time of the whole load)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    bulk_ms = 0.0
-    for s in range(0, x.shape[0], 1 << 20):
-        xd = torch.from_numpy(x[s:s + (1 << 20)]).to(dev)
-        idd = torch.from_numpy(ids[s:s + (1 << 20)]).to(dev)
-        torch.cuda.synchronize()
-        e0.record()
-        for c in range(0, xd.shape[0], chunk):
-            ix.add(xd[c:c + chunk], idd[c:c + chunk])
-        e1.record()
-        assert ix.sync() == 0
-        bulk_ms += e0.elapsed_time(e1)
-    del xd, idd
-    log(f"[bench] bulk load {x.shape[0]} vectors: {bulk_ms:.1f} ms ({x.shape[0] / bulk_ms * 1e3 / 1e6:.2f} M vec/s)")
-    # stream batches, resident in HBM before timing
+    # ids: base, then T2 stream batches, then the latency legs (B and B_small per step)
+    id_cap = w.n_base + B * (T2 + 2) + lat_steps * (B + B_small)
+    ix, bulk_ms = build_window_index(sivf, w, x, ids, st_code, rerank, id_cap, B, nq, nprobe, dev)
+    log(f"[bench] workspace {ix.workspace_bytes / 2**30:.2f} GiB; bulk load {x.shape[0]} vectors: {bulk_ms:.1f} ms "
+        f"({x.shape[0] / bulk_ms * 1e3 / 1e6:.2f} M vec/s)")
+    # stream batches 1..T2, resident in HBM before timing
     bx, bi, bo = [], [], []
-    for t in range(1, T + 1):
+    for t in range(1, T2 + 1):
         xb, idb = w.stream_batch(t)
         bx.append(torch.from_numpy(xb).to(dev))
         bi.append(torch.from_numpy(idb).to(dev))
@@ -243,26 +411,13 @@ def main():
     for t in range(a.warmup):
         ix.step(bx[t], bi[t], qd, k, nprobe, bo[t], out=(dist, lab))
     assert ix.sync() == 0
-    ix.profile_read()
-    ix.profile(True)
-    step_ms = []
-    torch.cuda.synchronize()
-    t_all = time.perf_counter()
-    for t in range(a.warmup, T):
-        ts = time.perf_counter()
-        ix.step(bx[t], bi[t], qd, k, nprobe, bo[t], out=(dist, lab))
-        torch.cuda.synchronize()
-        step_ms.append((time.perf_counter() - ts) * 1e3)
-    elapsed = time.perf_counter() - t_all
-    prof = ix.profile_read()
-    ix.profile(False)
-    assert ix.sync() == 0
+    elapsed, step_ms, prof = timed_steps(ix, bx, bi, bo, qd, k, nprobe, dist, lab, a.warmup, T)
     # scan roofline: distance evaluations of one search = sum over (query,
     # probe) of the probed list's length
     probes = ix.probe(qd, nprobe).cpu().numpy()
-    d = ix.dump()   # window state at the end of the timed region
-    evals = int(d["list_len"].astype(np.int64)[probes[probes >= 0]].sum())
-    del d, bx, bi, bo
+    lens = ix.dump()["list_len"].astype(np.int64)
+    evals = int(lens[probes[probes >= 0]].sum())
+    balanced = nq * nprobe * w.n_base / w.nlist
     scan_ms = prof["scan"][0] / max(prof["scan"][1], 1)
     log(f"[bench] {a.steps} steps in {elapsed:.3f} s; device ms per class: "
         + ", ".join(f"{kk}={v[0] / max(v[1], 1):.3f}" for kk, v in prof.items()))
@@ -275,14 +430,11 @@ def main():
     g = ix.step_graph(gx, gi, qd, k, nprobe, go, dist, lab, nrem)
     gsteps = []
     for t in range(T, T2):
-        xb, idb = w.stream_batch(t + 1)
-        bxt, bit = torch.from_numpy(xb).to(dev), torch.from_numpy(idb).to(dev)
-        bot = torch.from_numpy(w.oldest_ids(t + 1)).to(dev)
         torch.cuda.synchronize()
         ts = time.perf_counter()
-        gx.copy_(bxt)
-        gi.copy_(bit)
-        go.copy_(bot)
+        gx.copy_(bx[t])
+        gi.copy_(bi[t])
+        go.copy_(bo[t])
         g.launch()
         torch.cuda.synchronize()
         gsteps.append((time.perf_counter() - ts) * 1e3)
@@ -291,10 +443,9 @@ def main():
     gsm = np.sort(np.array(gsteps))
     log(f"[bench] graph steps: p50 {np.percentile(gsm, 50):.3f} ms, p99 {np.percentile(gsm, 99):.3f} ms")
 
-    # recall@10 and the nprobe sweep on the final window (base ids >= B*T2
-    # plus batches 1..T2) against exact kNN (float64)
+    # recall@10 and the nprobe sweep on the window after T2 steps (base ids >=
+    # B*T2 plus the live part of batches 1..T2) against exact kNN (float64)
     nrq = min(a.recall_queries, nq)
-    # live at the end: ids >= B * T2 (every step evicted the oldest B)
     keep = ids >= B * T2
     parts_x, parts_i = [x[keep]], [ids[keep]]
     for t in range(1, T2 + 1):
@@ -313,24 +464,22 @@ def main():
     def recall_of(labels):
         return float(np.mean([len(set(gt[i]) & set(labels[i])) / k for i in range(nrq)]))
 
-    sweep = []
-    ix.profile(True)
     grid = [1, 2, 4, 8, 16, 32, 64] + ([128] if nprobe > 64 else [])
-    for npb in (grid if not a.no_sweep else [nprobe]):
-        ix.search(qd, k, npb, out=(dist, lab))
-        ix.sync()
-        ix.profile_read()
-        for _ in range(3):
-            ix.search(qd, k, npb, out=(dist, lab))
-        pr = ix.profile_read()
-        sms = pr["search"][0] / max(pr["search"][1], 1)
-        sweep.append({"nprobe": npb, "recall_at_10": round(recall_of(lab.cpu().numpy()), 4),
-                      "search_qps": round(nq / (sms * 1e-3), 1)})
-    ix.profile(False)
+    sweep, best95 = nprobe_sweep(ix, qd, k, nq, nprobe, grid if not a.no_sweep else [nprobe], recall_of, dist, lab)
     recall = [r for r in sweep if r["nprobe"] == nprobe][0]["recall_at_10"]
-    ok95 = [r for r in sweep if r["recall_at_10"] >= 0.95]
-    best95 = max(ok95, key=lambda r: r["search_qps"]) if ok95 else None
     log(f"[bench] recall@{k} at nprobe {nprobe}: {recall:.4f}; sweep {sweep}")
+
+    # latency legs: >= 1,000 steady-state steps at B, then at B = 1,000
+    latency = {}
+    if lat_steps:
+        pool = torch.cat(bx[:16])
+        nxt, old = w.n_base + B * T2, B * T2
+        latency[f"B{B}"], nxt, old = latency_leg(ix, pool, qd, k, nprobe, nxt, old, w.n_base, B, lat_steps, dist, lab)
+        log(f"[bench] latency at B={B}: {latency[f'B{B}']}")
+        latency[f"B{B_small}"], nxt, old = latency_leg(ix, pool, qd, k, nprobe, nxt, old, w.n_base, B_small,
+                                                       lat_steps, dist, lab)
+        log(f"[bench] latency at B={B_small}: {latency[f'B{B_small}']}")
+        del pool
 
     if a.copy_calibration:
         nbytes = 1 << 30
@@ -357,13 +506,14 @@ def main():
         flops = evals * 2.0 * 32 * ((w.dim + 31) // 32)   # MFMA work incl. padding to 32-dim blocks
         mfma_tf = flops / (scan_ms * 1e-3) / 1e12
         prof_name = "k_scan_mfma_precision_10M.md" if a.workload == "precision" else None
-        roof = {"bound": "hbm", "kernel": "k_scan_mfma", "achieved": round(gbps, 1), "peak": 8000.0,
-                "unit": "GB/s", "frac": round(gbps / 8000.0, 4),
+        roof = {"bound": "hbm", "kernel": "k_scan_mfma", "achieved": round(gbps, 1), "peak": HBM_PEAK_GBPS,
+                "unit": "GB/s", "frac": round(gbps / HBM_PEAK_GBPS, 4),
                 "traffic": recorded_traffic(prof_name) if prof_name else None,
                 "traffic_unit": "bytes per launch (DRAM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 "algorithmic_bytes_per_launch": int(evals * per_eval), "evals_per_launch": evals,
                 "mfma_tflops": round(mfma_tf, 3), "mfma_frac": round(mfma_tf / MFMA16_PEAK_TFLOPS, 4),
                 "avg_launch_ms": round(scan_ms, 4)}
+    roof["probed_list_imbalance"] = round(evals / balanced, 3)
     res = {
         "metric": "insert/delete vectors/s; search QPS at recall@10>=0.95; p99 window-step ms",
         "value": round(nq * a.steps / elapsed, 1),
@@ -386,19 +536,59 @@ def main():
         "insert_vec_per_s": round(B / (add_ms * 1e-3), 1),
         "delete_vec_per_s": round(B / (rm_ms * 1e-3), 1),
         "bulk_insert_vec_per_s": round(x.shape[0] / (bulk_ms * 1e-3), 1),
-        "p50_step_ms": round(float(np.percentile(sm, 50)), 4),
-        "p99_step_ms": round(float(np.percentile(sm, 99)), 4),
-        "max_step_ms": round(float(sm[-1]), 4),
+        "timed_steps_p50_ms": round(float(np.percentile(sm, 50)), 4),
+        "timed_steps_max_ms": round(float(sm[-1]), 4),
         "graph_p50_step_ms": round(float(np.percentile(gsm, 50)), 4),
         "graph_p99_step_ms": round(float(np.percentile(gsm, 99)), 4),
         "device_ms": {kk: round(v[0] / max(v[1], 1), 4) for kk, v in prof.items()},
         "roofline": roof,
         "cpu_baseline": None,
     }
+    if latency:
+        res["latency"] = latency
+        res["p50_step_ms"] = latency[f"B{B}"]["p50_ms"]
+        res["p99_step_ms"] = latency[f"B{B}"]["p99_ms"]
+        res["max_step_ms"] = latency[f"B{B}"]["max_ms"]
+    ix.close()
+    del ix
+    torch.cuda.empty_cache()
+
+    if a.workload == "window" and st_code == 0 and not a.no_forms:
+        # the reduced-precision form on the same window data, queries and steps
+        t0 = time.time()
+        ixb, bulk_b = build_window_index(sivf, w, x, ids, STORAGE["bf16"], a.rerank, id_cap, B, nq, nprobe, dev)
+        tb = ixb.tune_search(qd, k, nprobe)
+        for t in range(a.warmup):
+            ixb.step(bx[t], bi[t], qd, k, nprobe, bo[t], out=(dist, lab))
+        assert ixb.sync() == 0
+        el_b, st_b, prof_b = timed_steps(ixb, bx, bi, bo, qd, k, nprobe, dist, lab, a.warmup, T)
+        for t in range(T, T2):      # same window as the FP32 index had for the sweep
+            ixb.step(bx[t], bi[t], qd, k, nprobe, bo[t], out=(dist, lab))
+        assert ixb.sync() == 0
+        sweep_b, best95_b = nprobe_sweep(ixb, qd, k, nq, nprobe, grid, recall_of, dist, lab)
+        smb = np.sort(np.array(st_b))
+        res["bf16_form"] = {
+            "value": round(nq * a.steps / el_b, 1), "unit": res["unit"], "steps": a.steps,
+            "ms_per_step": round(el_b / a.steps * 1e3, 4), "p50_step_ms": round(float(np.percentile(smb, 50)), 4),
+            "schedule": {"tile": tb[0], "chunk_positions": 1 << tb[1], "persistent_waves": bool(tb[2])},
+            "recall_at_10": [r for r in sweep_b if r["nprobe"] == nprobe][0]["recall_at_10"],
+            "qps_at_recall95": best95_b, "nprobe_sweep": sweep_b,
+            "device_ms": {kk: round(v[0] / max(v[1], 1), 4) for kk, v in prof_b.items()},
+            "rerank_top": a.rerank * k,
+            "fp32_qps_at_recall95": best95,
+        }
+        log(f"[bench] bf16 form: {res['bf16_form']['value']} q/s, sweep {sweep_b} ({time.time() - t0:.1f} s)")
+        ixb.close()
+        del ixb
+        torch.cuda.empty_cache()
+        t0 = time.time()
+        res["bulk_mutation"] = bulk_mutation_leg(w, x, ids)
+        log(f"[bench] bulk mutation: {res['bulk_mutation']} ({time.time() - t0:.1f} s)")
+    del bx, bi, bo
+
     if not a.no_cpu_baseline and a.workload != "precision":
         t0 = time.time()
-        xb, idb = w.stream_batch(1)
-        res["cpu_baseline"] = cpu_baseline(w, x, ids, q, (xb, idb, w.oldest_ids(1)), nprobe, k,
+        res["cpu_baseline"] = cpu_baseline(w, x, ids, q, nprobe, k,
                                            n_sample_q=200 if a.workload == "window" else nq)
         log(f"[bench] cpu baseline in {time.time() - t0:.1f} s")
     print(json.dumps(res), flush=True)
@@ -565,63 +755,26 @@ def batched_main(a):
 
 
 def mutation_main(a):
-    """Mutation kernels at bulk scale on the window data: one insert call of
-    the whole 1M-vector window (batch = window) and one delete call of half of
-    it (500k uniformly random ids), each timed by the library's HIP events.
-    Algorithmic bytes: insert 4d (read) + 4d (write) + 4 (id) + 4 (address
-    table) per vector; delete 4 (address table read) + 2 (4d + 4) (tail entry
-    moved into the hole) + 8 (two address-table writes) per removed id."""
-    import torch
+    """Mutation kernels at bulk scale on the window data (the bulk-mutation leg
+    of the default run on its own, for kernel traces and counters)."""
     import paper_2601_11808_amd as sivf
     import workloads
 
     if not os.path.exists(sivf.LIB_PATH):
         raise SystemExit("libsivf.so is not built: run python -c 'import __graft_entry__ as g; g.build()'")
-    dev = torch.device("cuda:0")
     w = workloads.window()
     x, ids = w.base()
     N, d = x.shape
-    num_slabs = int(1.15 * N / w.slab) + w.nlist
-    ix = sivf.Index(w.dim, w.nlist, w.centroids, metric=w.metric, slab_capacity=w.slab, num_slabs=num_slabs,
-                    id_capacity=N, max_batch=N, max_queries=16, max_k=16, max_nprobe=16, device="cuda:0")
-    xd, idd = torch.from_numpy(x).to(dev), torch.from_numpy(ids).to(dev)
-    rng = np.random.default_rng([w.seed, 7, 0])
     reps = max(1, a.steps // 10)
-    add_ms, rm_ms = [], []
-    for r in range(reps + 1):
-        rm = torch.from_numpy(np.sort(rng.choice(N, N // 2, replace=False)).astype(np.int64)).to(dev)
-        torch.cuda.synchronize()
-        ix.profile_read()
-        ix.profile(True)
-        ix.add(xd, idd)
-        assert ix.sync() == 0
-        pa = ix.profile_read()
-        nr = ix.remove(rm)
-        assert ix.sync() == 0
-        pr = ix.profile_read()
-        ix.profile(False)
-        assert int(nr.item()) == N // 2
-        ix.remove(idd)                      # empty the index for the next repetition
-        assert ix.sync() == 0 and ix.stats()["live"] == 0
-        if r > 0:                           # the first repetition warms up
-            add_ms.append(pa["add"][0])
-            rm_ms.append(pr["remove"][0])
-    ins_b = N * (4 * d + 4 * d + 8)
-    del_b = (N // 2) * (4 + 2 * (4 * d + 4) + 8)
-    am, rmm = float(np.median(add_ms)), float(np.median(rm_ms))
+    m = bulk_mutation_leg(w, x, ids, reps=reps)
     res = {
         "metric": "insert/delete vectors/s at bulk scale (whole-window insert, half-window delete)",
-        "value": round(N / (am * 1e-3), 1), "unit": "inserted vectors/s",
-        "n_gpus": 1, "steps": reps, "warmup": 1, "ms_per_step": round(am + rmm, 4),
+        "value": m["insert"]["vec_per_s"], "unit": "inserted vectors/s",
+        "n_gpus": 1, "steps": reps, "warmup": 1, "ms_per_step": round(m["insert"]["ms"] + m["delete"]["ms"], 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"mutation: window data N={N}, d={d}, nlist={w.nlist}, slab={w.slab}; insert {N} "
                                f"in one call, delete {N // 2} random ids in one call", "parallelism": "single GPU"},
-        "insert_ms": round(am, 3), "insert_vec_per_s": round(N / (am * 1e-3), 1),
-        "insert_algorithmic_GBps": round(ins_b / (am * 1e-3) / 1e9, 1),
-        "delete_ms": round(rmm, 3), "delete_vec_per_s": round((N // 2) / (rmm * 1e-3), 1),
-        "delete_algorithmic_GBps": round(del_b / (rmm * 1e-3) / 1e9, 1),
-        "note": "insert time includes the exact coarse assignment (FP32 MFMA GEMM + FP64 re-check); "
-                "per-kernel bandwidth of the copy kernels comes from the kernel trace",
+        **m,
     }
     print(json.dumps(res), flush=True)
 

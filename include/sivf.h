@@ -289,6 +289,16 @@ sivf_status sivf_profile_read(sivf_index *ix, double *total_ms, int64_t *count);
  * Each request therefore returns what it returns when the requests run one
  * at a time in submission order.  Server inserts must use ids that are not
  * live (else the call fails with SIVF_ERR_LIVE_ID and changes nothing).
+ * Continuous batching: a search is not launched on its own while a search
+ * batch is in flight; it joins the pending batch, and the pending batch
+ * (every search submitted since the last launch, in submission order, with
+ * its own k and nprobe) goes out as one search launch as soon as the search
+ * stream is free -- checked by every server call (submit, poll, wait) -- or
+ * before the next insert or remove is enqueued, which therefore never
+ * overtakes an earlier search.  A batch holds at most max_queries rows
+ * (batch slots): a search that does not fit starts the next batch, and is
+ * refused with SIVF_ERR_NOSPACE (nothing enqueued; retry after a poll) while
+ * two batches are already in flight.
  * Admission: an insert of n vectors is refused at once with SIVF_ERR_NOSPACE
  * (nothing enqueued) unless the host's view of the free-slab count, minus
  * the slabs reserved by inserts in flight, covers ceil(n/C) + min(n, nlist)
@@ -313,6 +323,69 @@ sivf_status sivf_server_poll(sivf_server *s, int64_t ticket, int *done);
 sivf_status sivf_server_wait(sivf_server *s, int64_t ticket);
 /* Host view of free slabs and the slabs reserved by inserts in flight. */
 sivf_status sivf_server_free_slabs(sivf_server *s, int64_t *free_slabs, int64_t *reserved);
+/* Search batches launched so far and the search requests they carried
+ * (host int64, either may be NULL). */
+sivf_status sivf_server_batches(sivf_server *s, int64_t *batches, int64_t *requests);
+
+/* ------------------------------------------------------------ checkpoint
+ * Save the index to a file and load it into a new workspace (the paper keeps
+ * host and device views of its index consistent, Sec. 1 and Sec. 4.1; this
+ * is the persistent view).  The file holds the logical content: the
+ * configuration, the centroids, each list's length and, list after list in
+ * position order, every entry's id and exact fp32 row.  Rounded copies and
+ * norms are recomputed on load and the slab layout is not kept, so a
+ * checkpoint loads into any configuration with the same dim, nlist, metric,
+ * storage and rerank_factor whose pool, id range and batch limits hold it;
+ * the loaded index has the same lists, and every search returns what it
+ * returned before the save.  Both calls block; sivf_save waits for the
+ * handle's last stream and must not overlap other calls on the index.  File
+ * errors and a mismatched configuration return SIVF_ERR_ARG; a pool or id
+ * range too small returns SIVF_ERR_NOSPACE / SIVF_ERR_ID_RANGE (no index is
+ * created).  Staging goes through the index's own workspace. */
+sivf_status sivf_save(sivf_index *ix, const char *path);
+/* Configuration and live count stored in a checkpoint (live may be NULL). */
+sivf_status sivf_checkpoint_config(const char *path, sivf_config *cfg, int64_t *live);
+/* Create an index from a checkpoint: workspace and stream as sivf_create. */
+sivf_status sivf_load(const char *path, const sivf_config *cfg, void *workspace, size_t ws_bytes, void *stream,
+                      sivf_index **out);
+
+/* ------------------------------------------------------ external id registry
+ * Sparse 64-bit external ids (UUIDs, hashes) on top of the dense internal
+ * id range [0, id_capacity) (the paper maps them through a registry in front
+ * of its dense identifier space, Sec. 3, Data Model).  The registry lives in
+ * its own device workspace: a hash table (external -> internal), the reverse
+ * map (internal -> external) and a stack of free internal ids, so batches of
+ * external ids are resolved on the device with no host round trip.  While a
+ * registry is attached, use the index only through it (it owns the internal
+ * ids).  External ids may be any int64 except INT64_MIN and INT64_MIN + 1
+ * (reserved table markers; such an id fails the call with SIVF_ERR_ARG as the
+ * device status).  Semantics are those of the dense calls: add of a held id
+ * is an upsert, the last duplicate in a batch wins, removing an absent id is
+ * a no-op; a failed add maps no new id.  Search labels are external ids (-1
+ * for missing results).  Device status: sivf_registry_sync (the registry's
+ * first error, else the index's).  Workspace: device, caller-owned, of
+ * sivf_registry_workspace_bytes(ix) bytes, 256-byte aligned. */
+typedef struct sivf_registry sivf_registry;
+size_t sivf_registry_workspace_bytes(const sivf_index *ix);
+sivf_status sivf_registry_create(sivf_index *ix, void *workspace, size_t ws_bytes, void *stream,
+                                 sivf_registry **out);
+sivf_status sivf_registry_destroy(sivf_registry *r);   /* does not free the workspace */
+/* x: device n x dim fp32; ext_ids: device n int64.  n <= max_batch. */
+sivf_status sivf_registry_add(sivf_registry *r, int64_t n, const float *x, const int64_t *ext_ids, void *stream);
+/* ext_ids: device n int64; n_removed: device int64 scalar or NULL. */
+sivf_status sivf_registry_remove(sivf_registry *r, int64_t n, const int64_t *ext_ids, int64_t *n_removed,
+                                 void *stream);
+/* As sivf_search; labels (device nq x k int64) receive external ids. */
+sivf_status sivf_registry_search(sivf_registry *r, int64_t nq, const float *q, int32_t k, int32_t nprobe,
+                                 float *dist, int64_t *labels, void *stream);
+/* Internal id of each external id (device n int64 out; -1 if not held). */
+sivf_status sivf_registry_lookup(sivf_registry *r, int64_t n, const int64_t *ext_ids, int64_t *internal,
+                                 void *stream);
+sivf_status sivf_registry_sync(sivf_registry *r, sivf_status *device_status);
+/* The registry's reverse map to / from a file (blocks).  Load into a fresh
+ * registry created over the index loaded from the matching sivf_save. */
+sivf_status sivf_registry_save(sivf_registry *r, const char *path);
+sivf_status sivf_registry_load(sivf_registry *r, const char *path, void *stream);
 
 /* Static text for a status code. */
 const char *sivf_status_string(sivf_status s);

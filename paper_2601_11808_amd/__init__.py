@@ -83,6 +83,20 @@ SIGNATURES = [
     ("sivf_server_poll", ct.c_int, [_P, _I64, ct.POINTER(ct.c_int)]),
     ("sivf_server_wait", ct.c_int, [_P, _I64]),
     ("sivf_server_free_slabs", ct.c_int, [_P, ct.POINTER(_I64), ct.POINTER(_I64)]),
+    ("sivf_server_batches", ct.c_int, [_P, ct.POINTER(_I64), ct.POINTER(_I64)]),
+    ("sivf_save", ct.c_int, [_P, ct.c_char_p]),
+    ("sivf_checkpoint_config", ct.c_int, [ct.c_char_p, ct.POINTER(SivfConfig), ct.POINTER(_I64)]),
+    ("sivf_load", ct.c_int, [ct.c_char_p, ct.POINTER(SivfConfig), _P, ct.c_size_t, _P, ct.POINTER(_P)]),
+    ("sivf_registry_workspace_bytes", ct.c_size_t, [_P]),
+    ("sivf_registry_create", ct.c_int, [_P, _P, ct.c_size_t, _P, ct.POINTER(_P)]),
+    ("sivf_registry_destroy", ct.c_int, [_P]),
+    ("sivf_registry_add", ct.c_int, [_P, _I64, _P, _P, _P]),
+    ("sivf_registry_remove", ct.c_int, [_P, _I64, _P, _P, _P]),
+    ("sivf_registry_search", ct.c_int, [_P, _I64, _P, _I32, _I32, _P, _P, _P]),
+    ("sivf_registry_lookup", ct.c_int, [_P, _I64, _P, _P, _P]),
+    ("sivf_registry_sync", ct.c_int, [_P, ct.POINTER(ct.c_int)]),
+    ("sivf_registry_save", ct.c_int, [_P, ct.c_char_p]),
+    ("sivf_registry_load", ct.c_int, [_P, ct.c_char_p, _P]),
     ("sivf_status_string", ct.c_char_p, [ct.c_int]),
 ]
 
@@ -146,7 +160,8 @@ class Index:
 
     def __init__(self, dim, nlist, centroids, metric=L2, slab_capacity=64, num_slabs=1 << 16,
                  id_capacity=1 << 20, max_batch=1 << 16, max_queries=1 << 14, max_k=64,
-                 max_nprobe=256, storage=F32, rerank_factor=0, device="cuda:0", stream=None):
+                 max_nprobe=256, storage=F32, rerank_factor=0, device="cuda:0", stream=None,
+                 _checkpoint=None):
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device is available")
@@ -162,15 +177,35 @@ class Index:
             raise SivfError(ERR_ARG, "sivf_workspace_bytes (invalid configuration)")
         self.workspace_bytes = nbytes
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
-        cent = _dev_tensor(centroids, torch.float32, self.device)
-        assert tuple(cent.shape) == (nlist, dim)
         h = ct.c_void_p()
-        _check(lib().sivf_create(ct.byref(self.cfg), _ptr(cent), _ptr(self.workspace), nbytes,
-                                 self._stream(stream), ct.byref(h)), "sivf_create")
+        if _checkpoint is not None:
+            cent = None
+            _check(lib().sivf_load(str(_checkpoint).encode(), ct.byref(self.cfg), _ptr(self.workspace), nbytes,
+                                   self._stream(stream), ct.byref(h)), "sivf_load")
+        else:
+            cent = _dev_tensor(centroids, torch.float32, self.device)
+            assert tuple(cent.shape) == (nlist, dim)
+            _check(lib().sivf_create(ct.byref(self.cfg), _ptr(cent), _ptr(self.workspace), nbytes,
+                                     self._stream(stream), ct.byref(h)), "sivf_create")
         self._h = h
         self._keep = [cent]
         self._stream(stream)
         self.sync()          # centroids copied: the caller's tensor may go
+
+    @classmethod
+    def load(cls, path, device="cuda:0", stream=None, **overrides):
+        """An index from a checkpoint written by save().  Capacity arguments
+        (num_slabs, id_capacity, slab_capacity, max_batch, max_queries, max_k,
+        max_nprobe) may be overridden; the rest come from the file."""
+        cfg, live = checkpoint_config(path)
+        kw = {k: getattr(cfg, k) for k in ("metric", "slab_capacity", "num_slabs", "id_capacity", "max_batch",
+                                            "max_queries", "max_k", "max_nprobe", "storage", "rerank_factor")}
+        kw.update(overrides)
+        return cls(cfg.dim, cfg.nlist, None, device=device, stream=stream, _checkpoint=path, **kw)
+
+    def save(self, path):
+        """Write the index's logical content to a file (waits)."""
+        _check(lib().sivf_save(self._h, str(path).encode()), "sivf_save")
 
     # -- helpers ---------------------------------------------------------
     def _stream(self, stream):
@@ -381,6 +416,92 @@ class Index:
                 if d["list_len"][l] > 0}
 
 
+def checkpoint_config(path):
+    """(SivfConfig, live count) stored in a checkpoint file."""
+    cfg, live = SivfConfig(), ct.c_int64()
+    _check(lib().sivf_checkpoint_config(str(path).encode(), ct.byref(cfg), ct.byref(live)), "sivf_checkpoint_config")
+    return cfg, live.value
+
+
+class Registry:
+    """External 64-bit ids over an index (see sivf_registry_* in
+    include/sivf.h).  The index must be used only through the registry."""
+
+    def __init__(self, index, stream=None):
+        torch = _torch()
+        self.index = index
+        nbytes = lib().sivf_registry_workspace_bytes(index._h)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=index.device)
+        h = ct.c_void_p()
+        _check(lib().sivf_registry_create(index._h, _ptr(self.workspace), nbytes, index._stream(stream),
+                                          ct.byref(h)), "sivf_registry_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().sivf_registry_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add(self, x, ext_ids, stream=None):
+        torch = _torch()
+        ix = self.index
+        x = _dev_tensor(x, torch.float32, ix.device).reshape(-1, ix.dim)
+        ext_ids = _dev_tensor(ext_ids, torch.int64, ix.device).reshape(-1)
+        assert ext_ids.shape[0] == x.shape[0]
+        _check(lib().sivf_registry_add(self._h, x.shape[0], _ptr(x), _ptr(ext_ids), ix._stream(stream)),
+               "sivf_registry_add")
+        self._keep = (x, ext_ids)
+
+    def remove(self, ext_ids, stream=None):
+        torch = _torch()
+        ix = self.index
+        ext_ids = _dev_tensor(ext_ids, torch.int64, ix.device).reshape(-1)
+        nrem = torch.zeros(1, dtype=torch.int64, device=ix.device)
+        _check(lib().sivf_registry_remove(self._h, ext_ids.shape[0], _ptr(ext_ids), _ptr(nrem), ix._stream(stream)),
+               "sivf_registry_remove")
+        self._keep = (ext_ids,)
+        return nrem
+
+    def search(self, q, k, nprobe=1, stream=None):
+        torch = _torch()
+        ix = self.index
+        q = _dev_tensor(q, torch.float32, ix.device).reshape(-1, ix.dim)
+        dist = torch.empty((q.shape[0], k), dtype=torch.float32, device=ix.device)
+        lab = torch.empty((q.shape[0], k), dtype=torch.int64, device=ix.device)
+        _check(lib().sivf_registry_search(self._h, q.shape[0], _ptr(q), k, nprobe, _ptr(dist), _ptr(lab),
+                                          ix._stream(stream)), "sivf_registry_search")
+        self._keep = (q,)
+        return dist, lab
+
+    def lookup(self, ext_ids, stream=None):
+        torch = _torch()
+        ix = self.index
+        ext_ids = _dev_tensor(ext_ids, torch.int64, ix.device).reshape(-1)
+        out = torch.empty(ext_ids.shape[0], dtype=torch.int64, device=ix.device)
+        _check(lib().sivf_registry_lookup(self._h, ext_ids.shape[0], _ptr(ext_ids), _ptr(out), ix._stream(stream)),
+               "sivf_registry_lookup")
+        self._keep = (ext_ids,)
+        return out
+
+    def sync(self) -> int:
+        st = ct.c_int(0)
+        _check(lib().sivf_registry_sync(self._h, ct.byref(st)), "sivf_registry_sync")
+        return st.value
+
+    def save(self, path):
+        _check(lib().sivf_registry_save(self._h, str(path).encode()), "sivf_registry_save")
+
+    def load(self, path, stream=None):
+        _check(lib().sivf_registry_load(self._h, str(path).encode(), self.index._stream(stream)),
+               "sivf_registry_load")
+
+
 class StepGraph:
     """A window step captured as a HIP graph over fixed device buffers."""
 
@@ -475,7 +596,9 @@ class Server:
         return t.value, nrem
 
     def search(self, q, k, nprobe, out=None):
-        """Returns (ticket, dist, labels); read them after the ticket completes."""
+        """Returns (ticket, dist, labels); read them after the ticket completes.
+        ticket is None when the search slots are full (nothing was enqueued;
+        retry after a poll)."""
         torch = _torch()
         q = _dev_tensor(q, torch.float32, self.index.device).reshape(-1, self.index.dim)
         if out is None:
@@ -484,8 +607,11 @@ class Server:
         else:
             dist, lab = out
         t = ct.c_int64(0)
-        _check(lib().sivf_server_search(self._h, q.shape[0], _ptr(q), k, nprobe, _ptr(dist), _ptr(lab),
-                                        self._in_stream(), ct.byref(t)), "sivf_server_search")
+        st = lib().sivf_server_search(self._h, q.shape[0], _ptr(q), k, nprobe, _ptr(dist), _ptr(lab),
+                                      self._in_stream(), ct.byref(t))
+        if st == ERR_NOSPACE:
+            return None, dist, lab
+        _check(st, "sivf_server_search")
         self._keep[t.value] = (q, dist, lab)
         return t.value, dist, lab
 
@@ -504,3 +630,9 @@ class Server:
         f, r = ct.c_int64(), ct.c_int64()
         _check(lib().sivf_server_free_slabs(self._h, ct.byref(f), ct.byref(r)), "sivf_server_free_slabs")
         return f.value, r.value
+
+    def batches(self):
+        """(search batches launched, search requests they carried)."""
+        b, r = ct.c_int64(), ct.c_int64()
+        _check(lib().sivf_server_batches(self._h, ct.byref(b), ct.byref(r)), "sivf_server_batches")
+        return b.value, r.value

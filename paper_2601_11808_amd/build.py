@@ -22,7 +22,8 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libsivf.so")
 ARCH = "gfx950"
 
-SOURCES = ["sivf_api.hip", "setup.hip", "coarse.hip", "mutate.hip", "search.hip"]
+SOURCES = ["sivf_api.hip", "setup.hip", "coarse.hip", "mutate.hip", "search.hip", "serve.hip",
+           "registry.hip"]
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",

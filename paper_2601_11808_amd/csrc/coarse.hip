@@ -11,7 +11,9 @@
 //     tau = m-th smallest Dt and per-list error bounds E_l >= |Dt_l - D_l|,
 //     every list with Dt_l - E_l <= tau + max E is re-evaluated exactly; this
 //     set provably holds the true top-m, so the decision equals a plain
-//     argmin/argsort over exact D for any input.
+//     argmin/argsort over exact D for any input.  Rows or centroids large
+//     enough for an fp32 square to overflow are re-checked against every
+//     list, in both kernels.
 #include "sivf_dev.h"
 #include "sivf_launch.h"
 
@@ -322,6 +324,10 @@ __global__ __launch_bounds__(256) void k_coarse_select(
     const double qn = sqrt(sred[0] + sred[1] + sred[2] + sred[3]) * (1.0 + 0x1p-50);
     const double cm = *cmax;
     const double emax = coarse_err(metric, d, bf, qn, cm);
+    // Below 2^60 for |x| + max |c| no fp32 square, norm sum or dot product of
+    // the GEMM can overflow, so every approximation is finite and the bound
+    // holds; above it (or for a non-finite norm) every list is re-checked.
+    const bool every = !(qn + cm < 0x1p60);
     const float *drow = dt + (int64_t)row * nlist;
 
     // tau = m-th smallest approximate distance (radix select on ordered bits).
@@ -385,7 +391,9 @@ __global__ __launch_bounds__(256) void k_coarse_select(
             const double dv = (double)drow[l];
             const double cn = cnorm[l];
             const double el = coarse_err(metric, d, bf, qn, cn);
-            isc = (dv - el <= ub) ? 1 : 0;
+            // written as "not above" so that a NaN approximation (or a NaN
+            // tau) keeps the list as a candidate
+            isc = (every || !(dv - el > ub)) ? 1 : 0;
         }
         int tot;
         const int pos = block_excl_scan<256>(isc, sbuf, &tot);

@@ -19,7 +19,12 @@
 // deleted set D of a list with n entries leaves n' = n - |D| entries; holes
 // below n' are refilled with the surviving entries of the tail window
 // [n', n), so the list stays dense, and the slabs past ceil(n'/C) return to
-// the free stack.  An id is deleted by exactly one thread: the one whose
+// the free stack.
+//   mark      address-table exchange, tombstone, per-list deletion counts
+//   plan      per-list offsets of the tail windows, new lengths
+//   holes     deleted positions below n', numbered per list
+//   move      tail-window positions in list order; survivors fill the holes
+//   finalize  new lengths; emptied tail slabs and pages back to the stacks  An id is deleted by exactly one thread: the one whose
 // atomic exchange on the address table sees it live (idempotent delete,
 // Theorem 3).
 #include "sivf_launch.h"
@@ -235,6 +240,95 @@ __global__ __launch_bounds__(256) void k_add_scatter(Dev S, const float *__restr
     }
 }
 
+// LDS-staged form of the scatter (rows of at most 64 chunks, 16-byte aligned):
+// one wave per SENT consecutive new entries.  The wave first reads the
+// entries' source rows whole (consecutive lanes read consecutive chunks of a
+// row) into LDS, then writes chunk c of every entry (consecutive lanes,
+// consecutive slots), so reads and writes are both contiguous runs.
+constexpr int SENT = 32;
+
+__global__ __launch_bounds__(64) void k_add_scatter_lds(Dev S, const float *__restrict__ x,
+                                                         const int64_t *__restrict__ ids,
+                                                         const int32_t *__restrict__ assign,
+                                                         const int32_t *__restrict__ rank,
+                                                         const int32_t *__restrict__ inv) {
+    extern __shared__ __align__(16) float4 srow[];   // [SENT][dp4 + 1]
+    if (call_failed(S.ctl)) return;
+    const int lane = threadIdx.x;
+    const int e0 = blockIdx.x * SENT;
+    const int nent = S.ctl[CTL_EBASE];
+    if (e0 >= nent) return;
+    const int cnt = min(SENT, nent - e0);
+    const int dp4 = S.dp4, ld = dp4 + 1;
+    // entry lane (lane < cnt): source row, destination slab and slot
+    int i = 0, slab = 0, slot = 0;
+    if (lane < cnt) {
+        i = inv[e0 + lane];
+        const int l = assign[i];
+        const int pos = S.l_base[l] + rank[i];
+        slab = slab_of(S, l, pos / S.C);
+        slot = pos % S.C;
+    }
+    // rows into LDS
+    const int tot = cnt * dp4;
+    for (int f0 = 0; f0 < tot; f0 += 4 * WAVE) {
+        float4 v[4];
+        int rr[4], cc[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int f = f0 + u * WAVE + lane;
+            rr[u] = f / dp4;
+            cc[u] = f - rr[u] * dp4;
+            const int src = __shfl(i, rr[u] < SENT ? rr[u] : 0);
+            if (f < tot) v[u] = reinterpret_cast<const float4 *>(x + (int64_t)src * S.d)[cc[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+            if (f0 + u * WAVE + lane < tot) srow[rr[u] * ld + cc[u]] = v[u];
+    }
+    __syncthreads();
+    // chunk c of entry e: lanes e + SENT * h take chunks h, h + 2, ...
+    {
+        const int e = lane % SENT, h = lane / SENT;
+        const int sl = __shfl(slab, e), so = __shfl(slot, e);
+        if (e < cnt) {
+            float4 *dst = S.data + (int64_t)sl * dp4 * S.C + so;
+            for (int c = h; c < dp4; c += 2) dst[(int64_t)c * S.C] = srow[e * ld + c];
+        }
+    }
+    if (lane < cnt) {
+        const uint32_t g = (uint32_t)slab * (uint32_t)S.C + (uint32_t)slot;
+        const float *row = reinterpret_cast<const float *>(srow + lane * ld);
+        if (S.storage == 0) {
+            float n32 = 0.f;   // fp32 squared norm, sequential over ascending dimensions
+            for (int j = 0; j < 4 * dp4; j++) n32 = fmaf(row[j], row[j], n32);
+            S.xnorm[g] = n32;
+        } else {
+            // reduced-precision copy (round to nearest even), 8 dims per chunk,
+            // and the fp32 squared norm of the rounded row (L2 scan epilogue)
+            uint4 *hdst = S.hdata + (int64_t)slab * S.dp8 * S.C + slot;
+            float nrm = 0.f;
+            for (int c = 0; c < S.dp8; c++) {
+                uint32_t hb[8];
+#pragma unroll
+                for (int q = 0; q < 8; q++) {
+                    const int j = 8 * c + q;
+                    const float v = j < S.d ? row[j] : 0.f;
+                    hb[q] = S.storage == 1 ? to_bf16_bits(v) : to_f16_bits(v);
+                    const float r = S.storage == 1 ? bf16_bits_to_float(hb[q]) : f16_bits_to_float(hb[q]);
+                    nrm = fmaf(r, r, nrm);
+                }
+                hdst[(int64_t)c * S.C] = make_uint4(hb[0] | (hb[1] << 16), hb[2] | (hb[3] << 16),
+                                                    hb[4] | (hb[5] << 16), hb[6] | (hb[7] << 16));
+            }
+            if (S.xnorm) S.xnorm[g] = nrm;
+        }
+        const int64_t u = ids[i];
+        S.sids[g] = (uint32_t)u;
+        S.att[u] = g;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_add_cleanup(Dev S, int n, const int64_t *__restrict__ ids) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
@@ -260,8 +354,9 @@ __global__ __launch_bounds__(256) void k_rm_mark(Dev S, int n, const int64_t *__
                                                  uint32_t *__restrict__ rec, int mode) {
     if (rm_skip(S, mode)) return;
     const int i = blockIdx.x * 256 + threadIdx.x;
-    const bool active = i < n;
-    const uint32_t g = active ? atomicExch(&S.att[ids[i]], INVALID) : INVALID;
+    const int64_t u = i < n ? ids[i] : -1;
+    const bool active = u >= 0 && u < S.id_capacity;   // out-of-range ids: rejected before (mode 0) or skipped (mode 2)
+    const uint32_t g = active ? atomicExch(&S.att[u], INVALID) : INVALID;
     const bool hit = g != INVALID;
     int l = 0;
     if (hit) {
@@ -269,7 +364,7 @@ __global__ __launch_bounds__(256) void k_rm_mark(Dev S, int n, const int64_t *__
         l = S.sowner[g / (uint32_t)S.C];
     }
     wave_agg_inc(S.l_m, l, hit);
-    if (active) rec[i] = g;
+    if (i < n) rec[i] = g;
 }
 
 // One block: segment offsets of each list's survivor slots and new lengths.
@@ -294,35 +389,16 @@ __global__ __launch_bounds__(1024) void k_rm_plan(Dev S, int64_t *n_removed, int
         }
         carry += tot;
     }
-    if (n_removed && threadIdx.x == 0) *n_removed = carry;
-}
-
-// Each deleted entry of list l inspects one position of the tail window
-// [n', n); positions still holding a live entry are the survivors to move.
-__global__ __launch_bounds__(256) void k_rm_survivors(Dev S, int n, const uint32_t *__restrict__ rec,
-                                                      int32_t *__restrict__ seg, int mode) {
-    if (rm_skip(S, mode)) return;
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    const uint32_t g = i < n ? rec[i] : INVALID;
-    const bool hit = g != INVALID;
-    const int l = hit ? S.sowner[g / (uint32_t)S.C] : 0;
-    const int q = wave_agg_inc(S.l_q, l, hit);
-    bool surv = false;
-    uint32_t gt = 0;
-    if (hit) {
-        const int tp = S.l_newlen[l] + q;
-        const int slab = slab_of(S, l, tp / S.C);
-        gt = (uint32_t)slab * (uint32_t)S.C + (uint32_t)(tp % S.C);
-        surv = S.sids[gt] != INVALID;
+    if (threadIdx.x == 0) {
+        S.ctl[CTL_RMTOT] = carry;
+        if (n_removed) *n_removed = carry;
     }
-    const int r = wave_agg_inc(S.l_s, l, surv);
-    if (surv) seg[S.l_off[l] + r] = (int32_t)gt;
 }
 
-// Holes below n' take the survivors: the r-th hole of a list pairs with its
-// r-th survivor.  The payload copy of each move is done by the whole wave.
-__global__ __launch_bounds__(256) void k_rm_move(Dev S, int n, const uint32_t *__restrict__ rec,
-                                                 const int32_t *__restrict__ seg, int mode) {
+// Holes: deleted positions below the new length n' of their list.  The h-th
+// hole of list l (in any order) is stored at seg[l_off[l] + h].
+__global__ __launch_bounds__(256) void k_rm_holes(Dev S, int n, const uint32_t *__restrict__ rec,
+                                                  int32_t *__restrict__ seg, int mode) {
     if (rm_skip(S, mode)) return;
     const int i = blockIdx.x * 256 + threadIdx.x;
     const uint32_t g = i < n ? rec[i] : INVALID;
@@ -332,32 +408,66 @@ __global__ __launch_bounds__(256) void k_rm_move(Dev S, int n, const uint32_t *_
     if (hit) {
         const uint32_t slab = g / (uint32_t)S.C;
         l = S.sowner[slab];
-        const int pos = S.sord[slab] * S.C + (int)(g % (uint32_t)S.C);
-        hole = pos < S.l_newlen[l];
+        hole = S.sord[slab] * S.C + (int)(g % (uint32_t)S.C) < S.l_newlen[l];
     }
-    const int r = wave_agg_inc(S.l_h, l, hole);
-    const uint32_t src = hole ? (uint32_t)seg[S.l_off[l] + r] : 0u;
-    uint64_t mask = ballot(hole);
-    while (mask) {
-        const int j = __builtin_ctzll(mask);
-        mask &= mask - 1;
-        const uint32_t sg = (uint32_t)readlane_i((int)src, j);
-        const uint32_t dg = (uint32_t)readlane_i((int)g, j);
-        const float4 *sp = S.data + (int64_t)(sg / S.C) * S.dp4 * S.C + sg % S.C;
-        float4 *dp = S.data + (int64_t)(dg / S.C) * S.dp4 * S.C + dg % S.C;
-        for (int c = lane_id(); c < S.dp4; c += 64) dp[(int64_t)c * S.C] = sp[(int64_t)c * S.C];
-        if (S.storage != 0) {
-            const uint4 *hs = S.hdata + (int64_t)(sg / S.C) * S.dp8 * S.C + sg % S.C;
-            uint4 *hd = S.hdata + (int64_t)(dg / S.C) * S.dp8 * S.C + dg % S.C;
-            for (int c = lane_id(); c < S.dp8; c += 64) hd[(int64_t)c * S.C] = hs[(int64_t)c * S.C];
+    const int h = wave_agg_inc(S.l_h, l, hole);
+    if (hole) seg[S.l_off[l] + h] = (int32_t)g;
+}
+
+// The tail windows [n', n) of all lists with deletions, list after list, one
+// lane per position (the window of list l has l_m[l] positions and starts at
+// entry l_off[l]).  A position that still holds a live entry is a survivor;
+// the r-th survivor of a list moves into its r-th hole.  Consecutive lanes
+// read consecutive slots, so each 16-byte dimension chunk of a wave's
+// survivors is one contiguous read; the holes they fill are scattered.
+template <bool HALF>
+__global__ __launch_bounds__(256) void k_rm_move(Dev S, int n, const int32_t *__restrict__ seg, int mode) {
+    if (rm_skip(S, mode)) return;
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    const int total = S.ctl[CTL_RMTOT];
+    const bool active = e < total;
+    int l = 0;
+    if (active) {   // the last list whose window starts at or before e
+        int lo = 0, hi = S.nlist - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (S.l_off[mid] <= e)
+                lo = mid;
+            else
+                hi = mid - 1;
         }
-        if (S.xnorm && lane_id() == 0) S.xnorm[dg] = S.xnorm[sg];
+        l = lo;
     }
-    if (hole) {
-        const uint32_t id = S.sids[src];
-        S.sids[g] = id;
-        S.att[id] = g;
+    uint32_t src = 0, id = INVALID;
+    if (active) {
+        const int tp = S.l_newlen[l] + (e - S.l_off[l]);
+        src = (uint32_t)slab_of(S, l, tp / S.C) * (uint32_t)S.C + (uint32_t)(tp % S.C);
+        id = S.sids[src];
     }
+    const bool surv = id != INVALID;
+    const int r = wave_agg_inc(S.l_s, l, surv);
+    if (!surv) return;
+    const uint32_t dst = (uint32_t)seg[S.l_off[l] + r];
+    const int64_t ss = (int64_t)(src / S.C), sl = src % S.C, ds = (int64_t)(dst / S.C), dl = dst % S.C;
+    const float4 *sp = S.data + ss * S.dp4 * S.C + sl;
+    float4 *dp = S.data + ds * S.dp4 * S.C + dl;
+    int c = 0;
+    for (; c + 8 <= S.dp4; c += 8) {
+        float4 v[8];
+#pragma unroll
+        for (int j = 0; j < 8; j++) v[j] = sp[(int64_t)(c + j) * S.C];
+#pragma unroll
+        for (int j = 0; j < 8; j++) dp[(int64_t)(c + j) * S.C] = v[j];
+    }
+    for (; c < S.dp4; c++) dp[(int64_t)c * S.C] = sp[(int64_t)c * S.C];
+    if (HALF) {
+        const uint4 *hs = S.hdata + ss * S.dp8 * S.C + sl;
+        uint4 *hd = S.hdata + ds * S.dp8 * S.C + dl;
+        for (int c8 = 0; c8 < S.dp8; c8++) hd[(int64_t)c8 * S.C] = hs[(int64_t)c8 * S.C];
+    }
+    if (S.xnorm) S.xnorm[dst] = S.xnorm[src];
+    S.sids[dst] = id;
+    S.att[id] = dst;
 }
 
 // Per list: new length, and the tail slabs (and table pages) past the new
@@ -421,6 +531,35 @@ __global__ __launch_bounds__(256) void k_get_rows(Dev S, int n, const int64_t *_
     }
 }
 
+// Checkpoint packing: entries [e0, e0 + n) of all lists in list order (list
+// l's entries are e in [off[l], off[l] + len[l]), positions ascending) ->
+// fp32 rows (d floats each) and ids.  One wave per entry.
+__global__ __launch_bounds__(256) void k_pack(Dev S, const int32_t *__restrict__ off, int64_t e0, int n,
+                                              float *__restrict__ rows, uint32_t *__restrict__ ids) {
+    const int i = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+    if (i >= n) return;
+    const int64_t e = e0 + i;
+    int lo = 0, hi = S.nlist - 1;
+    while (lo < hi) {   // the last list whose entries start at or before e
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= e)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const int p = (int)(e - off[lo]);
+    const int slab = slab_of(S, lo, p / S.C), slot = p % S.C;
+    const float4 *src = S.data + (int64_t)slab * S.dp4 * S.C + slot;
+    float *out = rows + (int64_t)i * S.d;
+    for (int c = lane_id(); c < S.dp4; c += 64) {
+        const float4 v = src[(int64_t)c * S.C];
+        const float ev[4] = {v.x, v.y, v.z, v.w};
+        for (int t = 0; t < 4; t++)
+            if (4 * c + t < S.d) out[4 * c + t] = ev[t];
+    }
+    if (lane_id() == 0) ids[i] = S.sids[(int64_t)slab * S.C + slot];
+}
+
 // Last kernel of an add or remove call: the next call gets a new sequence number.
 __global__ void k_call_end(int32_t *ctl) {
     if (threadIdx.x == 0) ctl[CTL_SEQ] = ctl[CTL_SEQ] + 1;
@@ -449,7 +588,10 @@ void launch_add_alloc(hipStream_t st, const Dev &S) {
 void launch_add_scatter(hipStream_t st, const Dev &S, int n, const float *x, const int64_t *ids, const Batch &B) {
     hipLaunchKernelGGL(k_add_inv, dim3(blocks(n)), dim3(256), 0, st, S, n, B.assign, B.rank, B.inv);
     const bool vec = (S.d % 4 == 0) && (((uintptr_t)x & 15) == 0);
-    if (vec)
+    if (vec && S.dp4 <= 64)
+        hipLaunchKernelGGL(k_add_scatter_lds, dim3(blocks(n, SENT)), dim3(64),
+                           (size_t)SENT * (S.dp4 + 1) * sizeof(float4), st, S, x, ids, B.assign, B.rank, B.inv);
+    else if (vec)
         hipLaunchKernelGGL(k_add_scatter<true>, dim3(blocks(n)), dim3(256), 0, st, S, x, ids, B.assign, B.rank,
                            B.inv);
     else
@@ -465,13 +607,20 @@ void launch_remove(hipStream_t st, const Dev &S, int n, const int64_t *ids, int6
     if (mode == 0) hipLaunchKernelGGL(k_rm_validate, dim3(blocks(n)), dim3(256), 0, st, S, n, ids);
     hipLaunchKernelGGL(k_rm_mark, dim3(blocks(n)), dim3(256), 0, st, S, n, ids, B.rec, mode);
     hipLaunchKernelGGL(k_rm_plan, dim3(1), dim3(1024), 0, st, S, n_removed, mode);
-    hipLaunchKernelGGL(k_rm_survivors, dim3(blocks(n)), dim3(256), 0, st, S, n, B.rec, B.seg, mode);
-    hipLaunchKernelGGL(k_rm_move, dim3(blocks(n)), dim3(256), 0, st, S, n, B.rec, B.seg, mode);
+    hipLaunchKernelGGL(k_rm_holes, dim3(blocks(n)), dim3(256), 0, st, S, n, B.rec, B.seg, mode);
+    if (S.storage != 0)
+        hipLaunchKernelGGL(k_rm_move<true>, dim3(blocks(n)), dim3(256), 0, st, S, n, B.seg, mode);
+    else
+        hipLaunchKernelGGL(k_rm_move<false>, dim3(blocks(n)), dim3(256), 0, st, S, n, B.seg, mode);
     hipLaunchKernelGGL(k_rm_finalize, dim3(blocks(S.nlist)), dim3(256), 0, st, S, mode);
 }
 
 void launch_call_end(hipStream_t st, const Dev &S) {
     hipLaunchKernelGGL(k_call_end, dim3(1), dim3(64), 0, st, S.ctl);
+}
+
+void launch_pack(hipStream_t st, const Dev &S, const int32_t *off, int64_t e0, int n, float *rows, uint32_t *ids) {
+    if (n > 0) hipLaunchKernelGGL(k_pack, dim3((n + 3) / 4), dim3(256), 0, st, S, off, e0, n, rows, ids);
 }
 
 void launch_get_rows(hipStream_t st, const Dev &S, int n, const int64_t *ids, float *rows) {

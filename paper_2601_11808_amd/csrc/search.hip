@@ -415,10 +415,11 @@ __device__ __forceinline__ void topk_offer(TopK<T, WIDE> &K, int t, bool valid, 
 }
 
 // High word of a result key: L2 distances are never negative (the canonical
-// sum starts at +0 and adds squares), so their order bits are bits | sign.
+// sum starts at +0 and adds squares), so their order bits are bits | sign;
+// an IP score of -0 ranks as +0.
 template <int METRIC>
 __device__ __forceinline__ uint32_t key_hi(float v) {
-    return METRIC == 0 ? (__float_as_uint(v) | 0x80000000u) : ~ord_bits(v);
+    return METRIC == 0 ? (__float_as_uint(v) | 0x80000000u) : ~ord_bits(zero_sign(v));
 }
 
 // Work items are cut into 8 contiguous ranges, one per XCD (blocks are
@@ -923,7 +924,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
                     for (int j = 0; j < 4; j++) {
                         if ((pmask >> (4 * rg + j)) & 1u) {
                             const float v = vv[4 * rg + j];
-                            const uint32_t hi = METRIC == 0 ? ord_bits(v) : ~ord_bits(v);
+                            const uint32_t hi = METRIC == 0 ? ord_bits(v) : ~ord_bits(zero_sign(v));
                             buf[qcol * MBUF + at] = ((uint64_t)hi << 32) | ids[j];
                             at++;
                         }

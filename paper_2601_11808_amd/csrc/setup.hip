@@ -75,6 +75,8 @@ static void fill(hipStream_t st, int32_t *p, int64_t n, int32_t v) {
     if (n > 0) hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n)), dim3(256), 0, st, p, n, v);
 }
 
+void launch_fill_i32(hipStream_t st, int32_t *p, int64_t n, int32_t v) { fill(st, p, n, v); }
+
 void launch_fill_i64(hipStream_t st, int64_t *p, int64_t n, int64_t v) {
     if (n > 0) hipLaunchKernelGGL(k_fill_i64_kernel, dim3(grid_for(n)), dim3(256), 0, st, p, n, v);
 }

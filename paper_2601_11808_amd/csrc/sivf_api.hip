@@ -4,6 +4,7 @@
 // sequence number (data-dependent failures are recorded on the device against
 // the sequence number of the failing call, so the rest of that call's kernels
 // skip their work and the index is left unchanged).
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -32,7 +33,8 @@ struct Layout {
     size_t total;
     size_t cent, cent_h, cn2, cnorm, cmax, data, sids, sowner, sord, free_slabs, free_pages, pages, dir, len, att, mark,
         ctl, lists, b_assign, b_rank, b_rec, b_seg, b_inv, dt, probes, pair_rank, list_pairs, item_list, item_tile,
-        item_chunk, partials, hdata, xnorm, rr_dist, rr_lab, dt_s;
+        item_chunk, partials, hdata, xnorm, rr_dist, rr_lab, dt_s, srv_q, srv_k, srv_np, srv_dist, srv_lab,
+        srv_seg;
 };
 
 bool config_ok(const sivf_config *c) {
@@ -114,6 +116,14 @@ Layout make_layout(const sivf_config *c) {
     L.xnorm = take((reduced && c->metric == SIVF_L2) || !reduced ? (size_t)ns * C * 4 : 0);
     L.rr_dist = take(reduced ? (size_t)c->max_queries * L.kcap * 4 : 0);
     L.rr_lab = take(reduced ? (size_t)c->max_queries * L.kcap * 8 : 0);
+    // serving: one coalesced search batch (query rows, per-row k and nprobe,
+    // results at stride max_k, one segment per request)
+    L.srv_q = take((size_t)c->max_queries * c->dim * 4);
+    L.srv_k = take((size_t)c->max_queries * 4);
+    L.srv_np = take((size_t)c->max_queries * 4);
+    L.srv_dist = take((size_t)c->max_queries * c->max_k * 4);
+    L.srv_lab = take((size_t)c->max_queries * c->max_k * 8);
+    L.srv_seg = take((size_t)c->max_queries * sizeof(SrvSeg));
     L.total = cur;
     return L;
 }
@@ -131,6 +141,7 @@ struct ProfClass {
 };
 
 struct sivf_index {
+    int device = 0;          // the device current at creation (the workspace's)
     sivf_config cfg{};
     Layout L{};
     Dev S{};
@@ -304,8 +315,11 @@ sivf_status sivf_create(const sivf_config *cfg, const float *centroids, void *wo
     if (!config_ok(cfg) || !centroids || !workspace) return SIVF_ERR_ARG;
     const Layout L = make_layout(cfg);
     if (ws_bytes < L.total || ((uintptr_t)workspace % ALIGN) != 0) return SIVF_ERR_ARG;
+    int device = 0;
+    if (!dev_ok(hipGetDevice(&device))) return SIVF_ERR_DEVICE;
     sivf_index *ix = new (std::nothrow) sivf_index();
     if (!ix) return SIVF_ERR_STATE;
+    ix->device = device;
     ix->cfg = *cfg;
     ix->L = L;
     ix->ws = (char *)workspace;
@@ -734,11 +748,23 @@ sivf_status sivf_dump(sivf_index *ix, int32_t *list_len, int32_t *list_slabs, in
 
 // ------------------------------------------------------------------ server
 
+// Work in flight on one server stream: a mutation (one ticket) or a
+// coalesced search batch (one ticket per request); it completes when `done`
+// has been reached.
 struct ServerReq {
-    int64_t ticket;
+    std::vector<int64_t> tickets;
     hipEvent_t done;
     int64_t reserve;     // slabs reserved by an insert until it completes
 };
+
+// A search request waiting for the next batch.
+struct PendingSearch {
+    int64_t ticket;
+    SrvSeg seg;
+    hipEvent_t inputs;   // recorded on the request's input stream at submission
+};
+
+constexpr int SRV_MAX_BATCHES = 2;   // search batches in flight before new searches are refused
 
 struct sivf_server {
     sivf_index *ix = nullptr;
@@ -746,10 +772,16 @@ struct sivf_server {
     hipEvent_t last_mut = nullptr, last_snap = nullptr, last_search = nullptr, inputs = nullptr;
     bool any_mut = false, any_search = false;
     std::vector<hipEvent_t> pool;
-    // Requests in flight per stream, in submission order (they complete in
-    // that order, so only the oldest of each queue needs a query).
+    // Work in flight per stream, in submission order (it completes in that
+    // order, so only the oldest entry of each queue needs a query).
     std::deque<ServerReq> q_search, q_mut;
-    std::unordered_map<int64_t, hipEvent_t> inflight;   // ticket -> completion event
+    std::unordered_map<int64_t, hipEvent_t> inflight;   // ticket -> completion event (null while pending)
+    std::vector<PendingSearch> pending;                  // the next search batch
+    int64_t pending_rows = 0;
+    SrvSeg *seg_host[2] = {nullptr, nullptr};            // pinned: segment tables, alternating
+    hipEvent_t seg_used[2] = {nullptr, nullptr};         // the copy out of each table has been done
+    int seg_next = 0;
+    int64_t batches = 0, batched_requests = 0;
     int32_t *mirror = nullptr;     // pinned: free-slab count copied after each mutation
     int64_t free_view = 0, reserved = 0, next_ticket = 1;
 };
@@ -765,8 +797,8 @@ static hipEvent_t server_event(sivf_server *s) {
     return e;
 }
 
-// Retire completed requests: recycle events, release reservations, refresh
-// the host view of free slabs from the last completed copy.
+// Retire completed work: recycle events, release reservations, refresh the
+// host view of free slabs from the last completed copy.
 static void server_reap(sivf_server *s) {
     bool mut_done = false;
     for (std::deque<ServerReq> *q : {&s->q_search, &s->q_mut}) {
@@ -775,7 +807,7 @@ static void server_reap(sivf_server *s) {
             s->reserved -= r.reserve;
             mut_done |= (q == &s->q_mut);
             s->pool.push_back(r.done);
-            s->inflight.erase(r.ticket);
+            for (int64_t t : r.tickets) s->inflight.erase(t);
             q->pop_front();
         }
     }
@@ -787,7 +819,8 @@ static bool server_inputs(sivf_server *s, void *input_stream, hipStream_t st) {
     return dev_ok(hipEventRecord(s->inputs, as_stream(input_stream))) && dev_ok(hipStreamWaitEvent(st, s->inputs, 0));
 }
 
-static sivf_status server_finish(sivf_server *s, hipStream_t st, bool mutation, int64_t reserve, int64_t *ticket) {
+static sivf_status server_finish(sivf_server *s, hipStream_t st, bool mutation, int64_t reserve,
+                                 std::vector<int64_t> tickets) {
     if (mutation) {
         if (!dev_ok(hipMemcpyAsync(s->mirror, s->ix->S.ctl + CTL_SLAB_TOP, sizeof(int32_t), hipMemcpyDeviceToHost,
                                    st)))
@@ -799,11 +832,65 @@ static sivf_status server_finish(sivf_server *s, hipStream_t st, bool mutation, 
         if (!dev_ok(hipEventRecord(s->last_mut, st))) return SIVF_ERR_DEVICE;
         s->any_mut = true;
     }
-    const int64_t t = s->next_ticket++;
-    (mutation ? s->q_mut : s->q_search).push_back(ServerReq{t, e, reserve});
-    s->inflight[t] = e;
+    for (int64_t t : tickets) s->inflight[t] = e;
+    (mutation ? s->q_mut : s->q_search).push_back(ServerReq{std::move(tickets), e, reserve});
     s->reserved += reserve;
-    if (ticket) *ticket = t;
+    return SIVF_OK;
+}
+
+// Launch the pending searches as one batch on the search stream: it starts
+// after every request's inputs and after the last mutation (every pending
+// search was submitted after it: a mutation flushes the pending batch before
+// it is enqueued), so each request sees the state of its submission.
+static sivf_status server_dispatch(sivf_server *s) {
+    if (s->pending.empty()) return SIVF_OK;
+    sivf_index *ix = s->ix;
+    hipStream_t st = s->s_search;
+    const int slot = s->seg_next;
+    s->seg_next ^= 1;
+    // the table in this pinned slot may still feed a copy two batches back
+    if (!dev_ok(hipEventSynchronize(s->seg_used[slot]))) return SIVF_ERR_DEVICE;
+    SrvSeg *tab = s->seg_host[slot];
+    const int nseg = (int)s->pending.size();
+    int kmax = 1;
+    std::vector<int64_t> tickets;
+    tickets.reserve(nseg);
+    for (int i = 0; i < nseg; i++) {
+        const PendingSearch &p = s->pending[i];
+        tab[i] = p.seg;
+        kmax = p.seg.k > kmax ? p.seg.k : kmax;
+        tickets.push_back(p.ticket);
+        if (!dev_ok(hipStreamWaitEvent(st, p.inputs, 0))) return SIVF_ERR_DEVICE;
+    }
+    const int nrows = (int)s->pending_rows;
+    for (PendingSearch &p : s->pending) s->pool.push_back(p.inputs);
+    s->pending.clear();
+    s->pending_rows = 0;
+    if (s->any_mut && !dev_ok(hipStreamWaitEvent(st, s->last_mut, 0))) return SIVF_ERR_DEVICE;
+    const Layout &L = ix->L;
+    char *w = ix->ws;
+    SrvSeg *dseg = (SrvSeg *)(w + L.srv_seg);
+    float *bq = (float *)(w + L.srv_q), *bdist = (float *)(w + L.srv_dist);
+    int32_t *bk = (int32_t *)(w + L.srv_k), *bnp = (int32_t *)(w + L.srv_np);
+    int64_t *blab = (int64_t *)(w + L.srv_lab);
+    if (!dev_ok(hipMemcpyAsync(dseg, tab, sizeof(SrvSeg) * nseg, hipMemcpyHostToDevice, st))) return SIVF_ERR_DEVICE;
+    if (!dev_ok(hipEventRecord(s->seg_used[slot], st))) return SIVF_ERR_DEVICE;
+    launch_srv_gather(st, dseg, nseg, nrows, ix->cfg.dim, bq, bk, bnp);
+    sivf_status r = do_search(ix, nrows, bq, kmax, bk, 0, bnp, bdist, blab, st, s->last_snap);
+    if (r != SIVF_OK) return r;
+    launch_srv_scatter(st, dseg, nseg, nrows, kmax, bdist, blab);
+    if (!dev_ok(hipGetLastError())) return SIVF_ERR_DEVICE;
+    if (!dev_ok(hipEventRecord(s->last_search, st))) return SIVF_ERR_DEVICE;
+    s->any_search = true;
+    s->batches++;
+    s->batched_requests += nseg;
+    return server_finish(s, st, false, 0, std::move(tickets));
+}
+
+// Dispatch the pending batch when no search batch is in flight.
+static sivf_status server_pump(sivf_server *s) {
+    server_reap(s);
+    if (!s->pending.empty() && s->q_search.empty()) return server_dispatch(s);
     return SIVF_OK;
 }
 
@@ -815,12 +902,17 @@ sivf_status sivf_server_create(sivf_index *ix, sivf_server **out) {
     sivf_server *s = new (std::nothrow) sivf_server();
     if (!s) return SIVF_ERR_STATE;
     s->ix = ix;
+    const size_t tab = sizeof(SrvSeg) * (size_t)ix->cfg.max_queries;
     bool ok = dev_ok(hipStreamCreateWithFlags(&s->s_search, hipStreamNonBlocking)) &&
               dev_ok(hipStreamCreateWithFlags(&s->s_mut, hipStreamNonBlocking)) &&
               dev_ok(hipEventCreateWithFlags(&s->last_mut, hipEventDisableTiming)) &&
               dev_ok(hipEventCreateWithFlags(&s->last_snap, hipEventDisableTiming)) &&
               dev_ok(hipEventCreateWithFlags(&s->last_search, hipEventDisableTiming)) &&
               dev_ok(hipEventCreateWithFlags(&s->inputs, hipEventDisableTiming)) &&
+              dev_ok(hipEventCreateWithFlags(&s->seg_used[0], hipEventDisableTiming)) &&
+              dev_ok(hipEventCreateWithFlags(&s->seg_used[1], hipEventDisableTiming)) &&
+              dev_ok(hipHostMalloc((void **)&s->seg_host[0], tab, hipHostMallocDefault)) &&
+              dev_ok(hipHostMalloc((void **)&s->seg_host[1], tab, hipHostMallocDefault)) &&
               dev_ok(hipHostMalloc((void **)&s->mirror, sizeof(int32_t), hipHostMallocDefault));
     if (ok) {
         ok = dev_ok(hipMemcpy(s->mirror, ix->S.ctl + CTL_SLAB_TOP, sizeof(int32_t), hipMemcpyDeviceToHost));
@@ -836,17 +928,23 @@ sivf_status sivf_server_create(sivf_index *ix, sivf_server **out) {
 
 sivf_status sivf_server_destroy(sivf_server *s) {
     if (!s) return SIVF_ERR_ARG;
+    sivf_status r = SIVF_OK;
+    if (!s->pending.empty() && s->s_search) r = server_dispatch(s);
     if (s->s_search) (void)hipStreamSynchronize(s->s_search);
     if (s->s_mut) (void)hipStreamSynchronize(s->s_mut);
-    for (auto &kv : s->inflight) (void)hipEventDestroy(kv.second);
+    for (auto &q : {&s->q_search, &s->q_mut})
+        for (ServerReq &e : *q) (void)hipEventDestroy(e.done);
+    for (PendingSearch &p : s->pending) (void)hipEventDestroy(p.inputs);
     for (hipEvent_t e : s->pool) (void)hipEventDestroy(e);
-    for (hipEvent_t e : {s->last_mut, s->last_snap, s->last_search, s->inputs})
+    for (hipEvent_t e : {s->last_mut, s->last_snap, s->last_search, s->inputs, s->seg_used[0], s->seg_used[1]})
         if (e) (void)hipEventDestroy(e);
     if (s->s_search) (void)hipStreamDestroy(s->s_search);
     if (s->s_mut) (void)hipStreamDestroy(s->s_mut);
+    for (SrvSeg *t : s->seg_host)
+        if (t) (void)hipHostFree(t);
     if (s->mirror) (void)hipHostFree(s->mirror);
     delete s;
-    return SIVF_OK;
+    return r;
 }
 
 sivf_status sivf_server_add(sivf_server *s, int64_t n, const float *x, const int64_t *ids, void *input_stream,
@@ -859,11 +957,15 @@ sivf_status sivf_server_add(sivf_server *s, int64_t n, const float *x, const int
     const int64_t C = ix->cfg.slab_capacity;
     const int64_t need = (n + C - 1) / C + (n < ix->cfg.nlist ? n : ix->cfg.nlist);
     if (need > s->free_view - s->reserved) return SIVF_ERR_NOSPACE;
+    sivf_status st = server_dispatch(s);   // earlier searches go first
+    if (st != SIVF_OK) return st;
     if (s->any_search && !dev_ok(hipStreamWaitEvent(s->s_mut, s->last_snap, 0))) return SIVF_ERR_DEVICE;
     if (!server_inputs(s, input_stream, s->s_mut)) return SIVF_ERR_DEVICE;
-    sivf_status st = do_add(ix, n, x, ids, s->s_mut, true);
+    st = do_add(ix, n, x, ids, s->s_mut, true);
     if (st != SIVF_OK) return st;
-    return server_finish(s, s->s_mut, true, need, ticket);
+    const int64_t t = s->next_ticket++;
+    if (ticket) *ticket = t;
+    return server_finish(s, s->s_mut, true, need, {t});
 }
 
 sivf_status sivf_server_remove(sivf_server *s, int64_t n, const int64_t *ids, int64_t *n_removed,
@@ -873,11 +975,15 @@ sivf_status sivf_server_remove(sivf_server *s, int64_t n, const int64_t *ids, in
     if (ix->broken) return SIVF_ERR_STATE;
     if (n < 0 || n > ix->cfg.max_batch || (n > 0 && !ids)) return SIVF_ERR_ARG;
     server_reap(s);
+    sivf_status st = server_dispatch(s);   // earlier searches go first
+    if (st != SIVF_OK) return st;
     if (s->any_search && !dev_ok(hipStreamWaitEvent(s->s_mut, s->last_search, 0))) return SIVF_ERR_DEVICE;
     if (!server_inputs(s, input_stream, s->s_mut)) return SIVF_ERR_DEVICE;
-    sivf_status st = do_remove(ix, n, ids, n_removed, s->s_mut);
+    st = do_remove(ix, n, ids, n_removed, s->s_mut);
     if (st != SIVF_OK) return st;
-    return server_finish(s, s->s_mut, true, 0, ticket);
+    const int64_t t = s->next_ticket++;
+    if (ticket) *ticket = t;
+    return server_finish(s, s->s_mut, true, 0, {t});
 }
 
 sivf_status sivf_server_search(sivf_server *s, int64_t nq, const float *q, int32_t k, int32_t nprobe,
@@ -885,29 +991,49 @@ sivf_status sivf_server_search(sivf_server *s, int64_t nq, const float *q, int32
     if (!s) return SIVF_ERR_ARG;
     sivf_index *ix = s->ix;
     if (ix->broken) return SIVF_ERR_STATE;
+    const sivf_config &c = ix->cfg;
+    if (nq < 0 || nq > c.max_queries || k < 1 || k > c.max_k || nprobe < 1 || nprobe > c.max_nprobe)
+        return SIVF_ERR_ARG;
+    if (nq > 0 && (!q || !dist || !labels)) return SIVF_ERR_ARG;
     server_reap(s);
-    if (s->any_mut && !dev_ok(hipStreamWaitEvent(s->s_search, s->last_mut, 0))) return SIVF_ERR_DEVICE;
-    if (!server_inputs(s, input_stream, s->s_search)) return SIVF_ERR_DEVICE;
-    sivf_status st = do_search(ix, nq, q, k, nullptr, nprobe, nullptr, dist, labels, s->s_search, s->last_snap);
-    if (st != SIVF_OK) return st;
-    if (!dev_ok(hipEventRecord(s->last_search, s->s_search))) return SIVF_ERR_DEVICE;
-    s->any_search = true;
-    return server_finish(s, s->s_search, false, 0, ticket);
+    if (s->pending_rows + nq > c.max_queries) {
+        // the pending batch is full: it goes out now unless the search slots are taken
+        if ((int)s->q_search.size() >= SRV_MAX_BATCHES) return SIVF_ERR_NOSPACE;
+        sivf_status st = server_dispatch(s);
+        if (st != SIVF_OK) return st;
+    }
+    const int64_t t = s->next_ticket++;
+    if (ticket) *ticket = t;
+    if (nq == 0) return SIVF_OK;   // nothing to do: complete at once
+    hipEvent_t in = server_event(s);
+    if (!in || !dev_ok(hipEventRecord(in, as_stream(input_stream)))) return SIVF_ERR_DEVICE;
+    PendingSearch p;
+    p.ticket = t;
+    p.seg = SrvSeg{q, dist, labels, (int32_t)s->pending_rows, (int32_t)nq, k, nprobe};
+    p.inputs = in;
+    s->pending.push_back(p);
+    s->pending_rows += nq;
+    s->inflight[t] = nullptr;
+    return server_pump(s);
 }
 
 sivf_status sivf_server_poll(sivf_server *s, int64_t ticket, int *done) {
     if (!s || !done) return SIVF_ERR_ARG;
-    server_reap(s);
+    sivf_status st = server_pump(s);
     *done = (ticket > 0 && ticket < s->next_ticket && s->inflight.find(ticket) == s->inflight.end()) ? 1 : 0;
-    return SIVF_OK;
+    return st;
 }
 
 sivf_status sivf_server_wait(sivf_server *s, int64_t ticket) {
     if (!s) return SIVF_ERR_ARG;
     auto it = s->inflight.find(ticket);
+    if (it != s->inflight.end() && it->second == nullptr) {   // still pending: launch its batch now
+        sivf_status st = server_dispatch(s);
+        if (st != SIVF_OK) return st;
+        it = s->inflight.find(ticket);
+    }
     if (it != s->inflight.end() && !dev_ok(hipEventSynchronize(it->second))) return SIVF_ERR_DEVICE;
-    server_reap(s);
-    return SIVF_OK;
+    return server_pump(s);
 }
 
 sivf_status sivf_server_free_slabs(sivf_server *s, int64_t *free_slabs, int64_t *reserved) {
@@ -915,6 +1041,446 @@ sivf_status sivf_server_free_slabs(sivf_server *s, int64_t *free_slabs, int64_t 
     server_reap(s);
     if (free_slabs) *free_slabs = s->free_view;
     if (reserved) *reserved = s->reserved;
+    return SIVF_OK;
+}
+
+sivf_status sivf_server_batches(sivf_server *s, int64_t *batches, int64_t *requests) {
+    if (!s) return SIVF_ERR_ARG;
+    if (batches) *batches = s->batches;
+    if (requests) *requests = s->batched_requests;
+    return SIVF_OK;
+}
+
+// ------------------------------------------------------------------ checkpoint
+//
+// A checkpoint holds the logical content of the index: its configuration,
+// the centroids, every list's length and, list after list in position order,
+// each entry's id and exact fp32 row.  Reduced-precision copies and norms
+// are derived data and are recomputed on load, and the slab layout is not
+// kept: a checkpoint loads into any pool large enough (num_slabs, slab
+// capacity, id and batch limits may change; dim, nlist, metric, storage and
+// re-rank factor may not), and the loaded index has the same lists, so every
+// search returns the same result as before the save.
+//
+// File layout (little-endian):
+//   header  CkptHeader (magic, version, configuration, live count, record size)
+//   float   centroids [nlist][dim]
+//   int32   list lengths [nlist]
+//   records of up to `record` entries: uint32 ids [m], then float rows [m][dim]
+
+namespace {
+
+struct CkptHeader {
+    char magic[8];        // "SIVFCKP1"
+    uint32_t version;     // 1
+    uint32_t header_bytes;
+    sivf_config cfg;
+    int64_t live;
+    int64_t record;       // entries per record
+};
+
+constexpr uint32_t CKPT_VERSION = 1;
+
+bool write_all(FILE *f, const void *p, size_t bytes) { return bytes == 0 || fwrite(p, 1, bytes, f) == bytes; }
+bool read_all(FILE *f, void *p, size_t bytes) { return bytes == 0 || fread(p, 1, bytes, f) == bytes; }
+
+struct FileCloser {
+    FILE *f;
+    ~FileCloser() {
+        if (f) fclose(f);
+    }
+};
+
+// Entries per record: what fits in the staging area (the insert coarse
+// scratch, idle between calls) and in one add batch.
+int64_t stage_entries(const sivf_index *ix) {
+    const int64_t bytes = (int64_t)ix->L.coarse_rows * ix->cfg.nlist * 4;
+    int64_t m = bytes / (4 * (int64_t)ix->cfg.dim + 8);
+    if (m > ix->cfg.max_batch) m = ix->cfg.max_batch;
+    return m;
+}
+
+bool same_shape(const sivf_config &a, const sivf_config &b) {
+    return a.dim == b.dim && a.nlist == b.nlist && a.metric == b.metric && a.storage == b.storage &&
+           a.rerank_factor == b.rerank_factor;
+}
+
+}  // namespace
+
+sivf_status sivf_save(sivf_index *ix, const char *path) {
+    if (!ix || !path) return SIVF_ERR_ARG;
+    if (ix->broken) return SIVF_ERR_STATE;
+    std::vector<int32_t> len;
+    int32_t ctl[CTL_WORDS];
+    sivf_status s = read_counts(ix, len, ctl);
+    if (s != SIVF_OK) return s;
+    const sivf_config &c = ix->cfg;
+    std::vector<int32_t> off(c.nlist);
+    int64_t live = 0;
+    for (int l = 0; l < c.nlist; l++) {
+        off[l] = (int32_t)live;
+        live += len[l];
+    }
+    FILE *f = fopen(path, "wb");
+    if (!f) return SIVF_ERR_ARG;
+    FileCloser fc{f};
+    const int64_t rec = stage_entries(ix);
+    if (rec < 1) return SIVF_ERR_STATE;
+    CkptHeader h{};
+    memcpy(h.magic, "SIVFCKP1", 8);
+    h.version = CKPT_VERSION;
+    h.header_bytes = sizeof(CkptHeader);
+    h.cfg = c;
+    h.live = live;
+    h.record = rec;
+    if (!write_all(f, &h, sizeof h)) return SIVF_ERR_ARG;
+    const int dpad = ix->S.dp4 * 4;
+    std::vector<float> cent((size_t)c.nlist * dpad);
+    if (!dev_ok(hipMemcpy(cent.data(), ix->S.cent, cent.size() * 4, hipMemcpyDeviceToHost))) return SIVF_ERR_DEVICE;
+    for (int l = 0; l < c.nlist; l++)
+        if (!write_all(f, cent.data() + (size_t)l * dpad, (size_t)c.dim * 4)) return SIVF_ERR_ARG;
+    if (!write_all(f, len.data(), (size_t)c.nlist * 4)) return SIVF_ERR_ARG;
+    // list offsets into the (idle) per-list scratch of removes, rows and ids into the insert coarse scratch
+    hipStream_t st = ix->last;
+    if (!dev_ok(hipMemcpy(ix->S.l_off, off.data(), (size_t)c.nlist * 4, hipMemcpyHostToDevice))) return SIVF_ERR_DEVICE;
+    float *rows_d = ix->dt;
+    uint32_t *ids_d = (uint32_t *)(rows_d + (size_t)rec * c.dim);
+    std::vector<float> rows((size_t)rec * c.dim);
+    std::vector<uint32_t> ids((size_t)rec);
+    for (int64_t e0 = 0; e0 < live; e0 += rec) {
+        const int n = (int)(live - e0 < rec ? live - e0 : rec);
+        launch_pack(st, ix->S, ix->S.l_off, e0, n, rows_d, ids_d);
+        if (!dev_ok(hipGetLastError()) || !dev_ok(hipStreamSynchronize(st))) return SIVF_ERR_DEVICE;
+        if (!dev_ok(hipMemcpy(ids.data(), ids_d, (size_t)n * 4, hipMemcpyDeviceToHost)) ||
+            !dev_ok(hipMemcpy(rows.data(), rows_d, (size_t)n * c.dim * 4, hipMemcpyDeviceToHost)))
+            return SIVF_ERR_DEVICE;
+        if (!write_all(f, ids.data(), (size_t)n * 4) || !write_all(f, rows.data(), (size_t)n * c.dim * 4))
+            return SIVF_ERR_ARG;
+    }
+    if (fflush(f) != 0) return SIVF_ERR_ARG;
+    return SIVF_OK;
+}
+
+sivf_status sivf_checkpoint_config(const char *path, sivf_config *cfg, int64_t *live) {
+    if (!path || !cfg) return SIVF_ERR_ARG;
+    FILE *f = fopen(path, "rb");
+    if (!f) return SIVF_ERR_ARG;
+    FileCloser fc{f};
+    CkptHeader h{};
+    if (!read_all(f, &h, sizeof h) || memcmp(h.magic, "SIVFCKP1", 8) != 0 || h.version != CKPT_VERSION ||
+        h.header_bytes != sizeof(CkptHeader))
+        return SIVF_ERR_ARG;
+    *cfg = h.cfg;
+    if (live) *live = h.live;
+    return SIVF_OK;
+}
+
+sivf_status sivf_load(const char *path, const sivf_config *cfg, void *workspace, size_t ws_bytes, void *stream,
+                      sivf_index **out) {
+    if (!path || !cfg || !out) return SIVF_ERR_ARG;
+    *out = nullptr;
+    FILE *f = fopen(path, "rb");
+    if (!f) return SIVF_ERR_ARG;
+    FileCloser fc{f};
+    CkptHeader h{};
+    if (!read_all(f, &h, sizeof h) || memcmp(h.magic, "SIVFCKP1", 8) != 0 || h.version != CKPT_VERSION ||
+        h.header_bytes != sizeof(CkptHeader) || h.record < 1 || h.live < 0)
+        return SIVF_ERR_ARG;
+    if (!config_ok(cfg) || !same_shape(h.cfg, *cfg) || !workspace) return SIVF_ERR_ARG;
+    const Layout L = make_layout(cfg);
+    if (ws_bytes < L.total || ((uintptr_t)workspace % ALIGN) != 0) return SIVF_ERR_ARG;
+    const int d = cfg->dim, nlist = cfg->nlist;
+    hipStream_t st = as_stream(stream);
+    // centroids go through the workspace's insert coarse scratch (not touched by creation)
+    std::vector<float> cent((size_t)nlist * d);
+    if (!read_all(f, cent.data(), cent.size() * 4)) return SIVF_ERR_ARG;
+    float *cent_d = (float *)((char *)workspace + L.dt);
+    if ((size_t)L.coarse_rows * nlist < cent.size()) return SIVF_ERR_STATE;
+    if (!dev_ok(hipMemcpyAsync(cent_d, cent.data(), cent.size() * 4, hipMemcpyHostToDevice, st)))
+        return SIVF_ERR_DEVICE;
+    sivf_index *ix = nullptr;
+    sivf_status s = sivf_create(cfg, cent_d, workspace, ws_bytes, stream, &ix);
+    if (s != SIVF_OK) return s;
+    if (!dev_ok(hipStreamSynchronize(st))) {
+        sivf_destroy(ix);
+        return SIVF_ERR_DEVICE;
+    }
+    std::vector<int32_t> len(nlist);
+    if (!read_all(f, len.data(), (size_t)nlist * 4)) {
+        sivf_destroy(ix);
+        return SIVF_ERR_ARG;
+    }
+    int64_t live = 0;
+    bool bad = false;
+    for (int32_t v : len) {
+        bad |= v < 0;
+        live += v;
+    }
+    if (bad || live != h.live) {
+        sivf_destroy(ix);
+        return SIVF_ERR_ARG;
+    }
+    // Entries are inserted in file order with their saved lists (no coarse
+    // step), staged through the insert coarse scratch.
+    const int64_t m = stage_entries(ix);
+    std::vector<uint32_t> ids((size_t)h.record);
+    std::vector<int64_t> ids64((size_t)h.record);
+    std::vector<float> rows((size_t)h.record * d);
+    std::vector<int32_t> lists((size_t)h.record);
+    float *rows_d = ix->dt;
+    int64_t *ids_d = (int64_t *)(rows_d + (size_t)m * d);
+    int lcur = 0;
+    int64_t lleft = nlist > 0 ? len[0] : 0;
+    for (int64_t e0 = 0; e0 < live && s == SIVF_OK; e0 += h.record) {
+        const int64_t n = live - e0 < h.record ? live - e0 : h.record;
+        if (!read_all(f, ids.data(), (size_t)n * 4) || !read_all(f, rows.data(), (size_t)n * d * 4)) {
+            s = SIVF_ERR_ARG;
+            break;
+        }
+        for (int64_t i = 0; i < n; i++) {
+            while (lleft == 0) lleft = len[++lcur];
+            lists[i] = lcur;
+            lleft--;
+            ids64[i] = ids[i];
+        }
+        for (int64_t p0 = 0; p0 < n && s == SIVF_OK; p0 += m) {
+            const int nn = (int)(n - p0 < m ? n - p0 : m);
+            if (!dev_ok(hipMemcpyAsync(rows_d, rows.data() + (size_t)p0 * d, (size_t)nn * d * 4, hipMemcpyHostToDevice,
+                                       st)) ||
+                !dev_ok(hipMemcpyAsync(ids_d, ids64.data() + p0, (size_t)nn * 8, hipMemcpyHostToDevice, st)) ||
+                !dev_ok(hipMemcpyAsync(ix->B.assign, lists.data() + p0, (size_t)nn * 4, hipMemcpyHostToDevice, st))) {
+                s = SIVF_ERR_DEVICE;
+                break;
+            }
+            const Dev &S = ix->S;
+            launch_add_prepare(st, S, nn, ids_d);
+            launch_add_count(st, S, nn, ids_d, ix->B, 1);
+            launch_add_admit(st, S);
+            launch_add_alloc(st, S);
+            launch_add_scatter(st, S, nn, rows_d, ids_d, ix->B);
+            launch_add_cleanup(st, S, nn, ids_d);
+            launch_call_end(st, S);
+            sivf_status ds = SIVF_OK;
+            if (!dev_ok(hipGetLastError())) s = SIVF_ERR_DEVICE;
+            else if ((s = sivf_sync(ix, &ds)) == SIVF_OK && ds != SIVF_OK) s = ds;
+        }
+    }
+    if (s != SIVF_OK) {
+        sivf_destroy(ix);
+        return s;
+    }
+    *out = ix;
+    return SIVF_OK;
+}
+
+// ------------------------------------------------------------------ registry
+
+struct sivf_registry {
+    sivf_index *ix = nullptr;
+    RegDev R{};
+    int32_t *ctl = nullptr;
+    int64_t *slot = nullptr;     // per batch row: table slot (-1 if none)
+    int32_t *fresh = nullptr;    // per batch row: this row claimed a new slot
+    int64_t *internal = nullptr; // per batch row: internal id (-1 if none)
+    int64_t used_bound = 0;      // upper bound on used table slots (live keys + tombstones)
+};
+
+namespace {
+
+struct RegLayout {
+    int64_t cap;
+    size_t keys, vals, ext_of, free_ids, ctl, slot, fresh, internal, total;
+};
+
+RegLayout reg_layout(const sivf_config &c) {
+    RegLayout L{};
+    int64_t cap = 1024;
+    while (cap < 4 * c.id_capacity) cap <<= 1;
+    L.cap = cap;
+    size_t cur = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = cur;
+        cur = align_up(cur + (bytes ? bytes : 1));
+        return o;
+    };
+    L.keys = take((size_t)cap * 8);
+    L.vals = take((size_t)cap * 4);
+    L.ext_of = take((size_t)c.id_capacity * 8);
+    L.free_ids = take((size_t)c.id_capacity * 4);
+    L.ctl = take(REG_CTL_WORDS * 4);
+    L.slot = take((size_t)c.max_batch * 8);
+    L.fresh = take((size_t)c.max_batch * 4);
+    L.internal = take((size_t)c.max_batch * 8);
+    L.total = cur;
+    return L;
+}
+
+// Rebuild the table from the reverse map when the used slots could pass half
+// of the table (tombstones are never reused, so they accumulate).
+void reg_maybe_rebuild(sivf_registry *r, hipStream_t st, int64_t n) {
+    if (r->used_bound + n <= r->R.cap / 2) return;
+    launch_reg_rebuild(st, r->R, r->ctl);
+    r->used_bound = r->ix->cfg.id_capacity;   // live keys after the rebuild: at most one per internal id
+}
+
+}  // namespace
+
+size_t sivf_registry_workspace_bytes(const sivf_index *ix) {
+    if (!ix) return 0;
+    return reg_layout(ix->cfg).total;
+}
+
+sivf_status sivf_registry_create(sivf_index *ix, void *workspace, size_t ws_bytes, void *stream,
+                                 sivf_registry **out) {
+    if (!ix || !workspace || !out) return SIVF_ERR_ARG;
+    *out = nullptr;
+    if (ix->broken) return SIVF_ERR_STATE;
+    const RegLayout L = reg_layout(ix->cfg);
+    if (ws_bytes < L.total || ((uintptr_t)workspace % ALIGN) != 0) return SIVF_ERR_ARG;
+    sivf_registry *r = new (std::nothrow) sivf_registry();
+    if (!r) return SIVF_ERR_STATE;
+    char *w = (char *)workspace;
+    r->ix = ix;
+    r->R.keys = (int64_t *)(w + L.keys);
+    r->R.vals = (int32_t *)(w + L.vals);
+    r->R.ext_of = (int64_t *)(w + L.ext_of);
+    r->R.free_ids = (int32_t *)(w + L.free_ids);
+    r->R.cap = L.cap;
+    r->R.id_cap = ix->cfg.id_capacity;
+    r->ctl = (int32_t *)(w + L.ctl);
+    r->slot = (int64_t *)(w + L.slot);
+    r->fresh = (int32_t *)(w + L.fresh);
+    r->internal = (int64_t *)(w + L.internal);
+    hipStream_t st = as_stream(stream);
+    ix->last = st;
+    launch_fill_i32(st, r->ctl, REG_CTL_WORDS, 0);
+    launch_fill_i64(st, r->R.ext_of, r->R.id_cap, REG_EMPTY);
+    launch_reg_rebuild(st, r->R, r->ctl);          // an empty table
+    launch_reg_free_stack(st, r->R, r->ctl);       // every internal id free
+    if (!dev_ok(hipGetLastError())) {
+        delete r;
+        return SIVF_ERR_DEVICE;
+    }
+    *out = r;
+    return SIVF_OK;
+}
+
+sivf_status sivf_registry_destroy(sivf_registry *r) {
+    if (!r) return SIVF_ERR_ARG;
+    delete r;
+    return SIVF_OK;
+}
+
+sivf_status sivf_registry_add(sivf_registry *r, int64_t n, const float *x, const int64_t *ext_ids, void *stream) {
+    if (!r) return SIVF_ERR_ARG;
+    sivf_index *ix = r->ix;
+    if (ix->broken) return SIVF_ERR_STATE;
+    if (n < 0 || n > ix->cfg.max_batch || (n > 0 && (!x || !ext_ids))) return SIVF_ERR_ARG;
+    if (n == 0) return SIVF_OK;
+    hipStream_t st = as_stream(stream);
+    ix->last = st;
+    reg_maybe_rebuild(r, st, n);
+    r->used_bound += n;
+    launch_reg_add_pre(st, r->R, (int)n, ext_ids, r->slot, r->fresh, r->internal, r->ctl);
+    if (!dev_ok(hipGetLastError())) return SIVF_ERR_DEVICE;
+    sivf_status s = do_add(ix, n, x, r->internal, st);
+    if (s != SIVF_OK) return s;
+    launch_reg_add_post(st, r->R, ix->S, (int)n, r->slot, r->fresh, r->ctl);
+    return launched(ix);
+}
+
+sivf_status sivf_registry_remove(sivf_registry *r, int64_t n, const int64_t *ext_ids, int64_t *n_removed,
+                                 void *stream) {
+    if (!r) return SIVF_ERR_ARG;
+    sivf_index *ix = r->ix;
+    if (ix->broken) return SIVF_ERR_STATE;
+    if (n < 0 || n > ix->cfg.max_batch || (n > 0 && !ext_ids)) return SIVF_ERR_ARG;
+    hipStream_t st = as_stream(stream);
+    ix->last = st;
+    if (n == 0) {
+        if (n_removed) launch_fill_i64(st, n_removed, 1, 0);
+        return launched(ix);
+    }
+    launch_reg_lookup(st, r->R, (int)n, ext_ids, r->slot, r->internal);
+    // unmapped keys carry internal id -1, which the remove skips
+    launch_remove(st, ix->S, (int)n, r->internal, n_removed, ix->B, 2);
+    launch_call_end(st, ix->S);
+    launch_reg_release(st, r->R, ix->S, (int)n, ext_ids, r->slot, r->ctl);
+    return launched(ix);
+}
+
+sivf_status sivf_registry_search(sivf_registry *r, int64_t nq, const float *q, int32_t k, int32_t nprobe,
+                                 float *dist, int64_t *labels, void *stream) {
+    if (!r) return SIVF_ERR_ARG;
+    sivf_index *ix = r->ix;
+    if (ix->broken) return SIVF_ERR_STATE;
+    hipStream_t st = as_stream(stream);
+    ix->last = st;
+    sivf_status s = do_search(ix, nq, q, k, nullptr, nprobe, nullptr, dist, labels, st);
+    if (s != SIVF_OK || nq == 0) return s;
+    launch_reg_labels(st, r->R, nq * k, labels);
+    return launched(ix);
+}
+
+sivf_status sivf_registry_lookup(sivf_registry *r, int64_t n, const int64_t *ext_ids, int64_t *internal,
+                                 void *stream) {
+    if (!r || n < 0 || (n > 0 && (!ext_ids || !internal))) return SIVF_ERR_ARG;
+    if (r->ix->broken) return SIVF_ERR_STATE;
+    hipStream_t st = as_stream(stream);
+    r->ix->last = st;
+    if (n == 0) return SIVF_OK;
+    launch_reg_lookup(st, r->R, (int)n, ext_ids, nullptr, internal);
+    return launched(r->ix);
+}
+
+sivf_status sivf_registry_sync(sivf_registry *r, sivf_status *device_status) {
+    if (!r) return SIVF_ERR_ARG;
+    sivf_status ixs = SIVF_OK;
+    sivf_status s = sivf_sync(r->ix, &ixs);
+    if (s != SIVF_OK) return s;
+    int32_t rs = 0, zero = 0;
+    if (!dev_ok(hipMemcpy(&rs, r->ctl + REG_CTL_STATUS, 4, hipMemcpyDeviceToHost)) ||
+        !dev_ok(hipMemcpy(r->ctl + REG_CTL_STATUS, &zero, 4, hipMemcpyHostToDevice)))
+        return SIVF_ERR_DEVICE;
+    if (device_status) *device_status = rs != 0 ? (sivf_status)rs : ixs;
+    return SIVF_OK;
+}
+
+sivf_status sivf_registry_save(sivf_registry *r, const char *path) {
+    if (!r || !path) return SIVF_ERR_ARG;
+    if (!dev_ok(hipStreamSynchronize(r->ix->last))) return SIVF_ERR_DEVICE;
+    std::vector<int64_t> ext((size_t)r->R.id_cap);
+    if (!dev_ok(hipMemcpy(ext.data(), r->R.ext_of, ext.size() * 8, hipMemcpyDeviceToHost))) return SIVF_ERR_DEVICE;
+    FILE *f = fopen(path, "wb");
+    if (!f) return SIVF_ERR_ARG;
+    FileCloser fc{f};
+    const char magic[8] = {'S', 'I', 'V', 'F', 'R', 'E', 'G', '1'};
+    const int64_t cap = r->R.id_cap;
+    if (!write_all(f, magic, 8) || !write_all(f, &cap, 8) || !write_all(f, ext.data(), ext.size() * 8))
+        return SIVF_ERR_ARG;
+    return fflush(f) == 0 ? SIVF_OK : SIVF_ERR_ARG;
+}
+
+sivf_status sivf_registry_load(sivf_registry *r, const char *path, void *stream) {
+    if (!r || !path) return SIVF_ERR_ARG;
+    FILE *f = fopen(path, "rb");
+    if (!f) return SIVF_ERR_ARG;
+    FileCloser fc{f};
+    char magic[8];
+    int64_t cap = 0;
+    if (!read_all(f, magic, 8) || memcmp(magic, "SIVFREG1", 8) != 0 || !read_all(f, &cap, 8) || cap < 1 ||
+        cap > r->R.id_cap)
+        return SIVF_ERR_ARG;
+    std::vector<int64_t> ext((size_t)r->R.id_cap, REG_EMPTY);
+    if (!read_all(f, ext.data(), (size_t)cap * 8)) return SIVF_ERR_ARG;
+    hipStream_t st = as_stream(stream);
+    r->ix->last = st;
+    if (!dev_ok(hipMemcpyAsync(r->R.ext_of, ext.data(), ext.size() * 8, hipMemcpyHostToDevice, st)))
+        return SIVF_ERR_DEVICE;
+    launch_reg_rebuild(st, r->R, r->ctl);
+    launch_reg_free_stack(st, r->R, r->ctl);
+    r->used_bound = r->R.id_cap;
+    if (!dev_ok(hipGetLastError()) || !dev_ok(hipStreamSynchronize(st))) return SIVF_ERR_DEVICE;
     return SIVF_OK;
 }
 

@@ -35,6 +35,7 @@ enum Ctl {
     CTL_SEQ = 6,        // sequence number of the current add/remove call; its last kernel bumps it
     CTL_CHUNK = 7,      // search: log2 of the positions per work item (a list's chunk)
     CTL_EBASE = 8,      // add: new entries handed out so far (per-list entry offsets)
+    CTL_RMTOT = 9,      // remove: entries deleted by the current call (positions of all tail windows)
     CTL_XB = 16,        // search: first item of each XCD's range (words 16..24; word 24 = item count)
     CTL_WORK0 = 64,     // search, persistent schedule: 8 work counters, one per XCD range of items,
     CTL_WORK_STRIDE = 32,  // each on its own 128-byte line (words 64, 96, .., 288)
@@ -127,10 +128,15 @@ __device__ __forceinline__ float from_ord(uint32_t o) {
     return __uint_as_float(b);
 }
 
+// -0 and +0 are the same score: both rank as +0 (an inner product of tiny
+// values whose sum rounds to zero from below is -0), so equal scores tie on
+// the id as for every other value.
+__device__ __forceinline__ float zero_sign(float v) { return v == 0.f ? 0.f : v; }
+
 // Result ranking key: smaller key = better result; ties broken by smaller id.
 // L2 ranks by ascending distance, IP by descending score.
 __device__ __forceinline__ uint64_t make_key(float v, uint32_t id, int metric) {
-    uint32_t hi = metric == 0 ? ord_bits(v) : ~ord_bits(v);
+    uint32_t hi = metric == 0 ? ord_bits(v) : ~ord_bits(zero_sign(v));
     return ((uint64_t)hi << 32) | id;
 }
 __device__ __forceinline__ float key_value(uint64_t key, int metric) {

@@ -13,6 +13,7 @@ void launch_init_state(hipStream_t st, const Dev &S, const float *centroids);
 
 // ---- coarse quantizer (coarse.hip)
 size_t coarse_select_smem(int dpad, int mmax);
+int coarse_groups(int nlist);   // group minima per row of the nearest-list GEMM: ceil(nlist / 16)
 void launch_coarse_gemm(hipStream_t st, const float *X, int n, int d, const float *cent, const uint16_t *cent_h, int dpad,
                         const float *cn2, int nlist, int metric, float *out, const int32_t *ctl,
                         int gated, int bf);
@@ -39,12 +40,17 @@ void launch_add_alloc(hipStream_t st, const Dev &S);
 void launch_add_scatter(hipStream_t st, const Dev &S, int n, const float *x, const int64_t *ids,
                         const Batch &B);
 void launch_add_cleanup(hipStream_t st, const Dev &S, int n, const int64_t *ids);
-// mode 0: a remove call; mode 1: the delete half of an upsert inside an add call
+// mode 0: a remove call; mode 1: the delete half of an upsert inside an add call;
+// mode 2: a remove call whose ids are not validated and skipped when outside
+// [0, id_capacity) (the registry passes -1 for keys it does not hold)
 void launch_remove(hipStream_t st, const Dev &S, int n, const int64_t *ids, int64_t *n_removed,
                    const Batch &B, int mode);
 void launch_call_end(hipStream_t st, const Dev &S);
 void launch_get_rows(hipStream_t st, const Dev &S, int n, const int64_t *ids, float *rows);
+// checkpoint: entries [e0, e0 + n) in list order (off = per-list first entry) -> rows and ids
+void launch_pack(hipStream_t st, const Dev &S, const int32_t *off, int64_t e0, int n, float *rows, uint32_t *ids);
 void launch_fill_i64(hipStream_t st, int64_t *p, int64_t n, int64_t v);
+void launch_fill_i32(hipStream_t st, int32_t *p, int64_t n, int32_t v);
 
 // ---- search (search.hip)
 struct SearchBufs {
@@ -74,5 +80,41 @@ void launch_search_scan_mfma(hipStream_t st, const Dev &S, const SearchBufs &W, 
                              int np_stride, int kcap, int k, int kmul, const int32_t *k_per_query);
 void launch_rerank(hipStream_t st, const Dev &S, int nq, const float *q, int kc, const int64_t *cand, int k,
                    int kmul, const int32_t *k_per_query, float *dist, int64_t *labels);
+
+// ---- external id registry (registry.hip)
+constexpr int64_t REG_EMPTY = (int64_t)0x8000000000000000ull;   // table marker: never used
+constexpr int64_t REG_TOMB = (int64_t)0x8000000000000001ull;    // table marker: key removed
+enum RegCtl { REG_CTL_STATUS = 0, REG_CTL_TOP = 1, REG_CTL_WORDS = 64 };
+struct RegDev {
+    int64_t *keys;      // [cap] external id, REG_EMPTY or REG_TOMB
+    int32_t *vals;      // [cap] internal id of the key
+    int64_t *ext_of;    // [id_cap] external id held by each internal id, or REG_EMPTY
+    int32_t *free_ids;  // [id_cap] stack of free internal ids (count in ctl[REG_CTL_TOP])
+    int64_t cap, id_cap;
+};
+void launch_reg_add_pre(hipStream_t st, const RegDev &R, int n, const int64_t *ext, int64_t *slot, int32_t *fresh,
+                        int64_t *internal, int32_t *ctl);
+void launch_reg_add_post(hipStream_t st, const RegDev &R, const Dev &S, int n, const int64_t *slot,
+                         const int32_t *fresh, int32_t *ctl);
+void launch_reg_lookup(hipStream_t st, const RegDev &R, int n, const int64_t *ext, int64_t *slot, int64_t *internal);
+void launch_reg_release(hipStream_t st, const RegDev &R, const Dev &S, int n, const int64_t *ext,
+                        const int64_t *slot, int32_t *ctl);
+void launch_reg_labels(hipStream_t st, const RegDev &R, int64_t n, int64_t *labels);
+void launch_reg_rebuild(hipStream_t st, const RegDev &R, int32_t *ctl);
+void launch_reg_free_stack(hipStream_t st, const RegDev &R, int32_t *ctl);
+
+// ---- serving, continuous batching (serve.hip)
+// One request of a coalesced search batch: its rows are batch rows
+// [row0, row0 + nq); q, dist and labels are the request's own buffers.
+struct SrvSeg {
+    const float *q;
+    float *dist;
+    int64_t *labels;
+    int32_t row0, nq, k, nprobe;
+};
+void launch_srv_gather(hipStream_t st, const SrvSeg *segs, int nseg, int nrows, int d, float *q, int32_t *kq,
+                       int32_t *npq);
+void launch_srv_scatter(hipStream_t st, const SrvSeg *segs, int nseg, int nrows, int kstride, const float *dist,
+                        const int64_t *labels);
 
 }  // namespace sivf

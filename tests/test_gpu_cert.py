@@ -10,6 +10,7 @@ import pytest
 import oracle
 import paper_2601_11808_amd as sivf
 from tests.gpu_common import Pair, compare_results, say
+from tests.invariants import membership_of, same_membership
 
 pytestmark = pytest.mark.gpu
 
@@ -133,7 +134,8 @@ def test_cert_schedule_limits():
 
 def test_cert_random_configs():
     """150 seeded random configurations (d 1..256, C 4..128, L2/IP, max_k 16/32/64, data from 1e-25 to 1e18
-    in scale, repeated rows and one-ulp neighbours, random schedules): tile 16 and tile 8 agree bit for bit."""
+    in scale, repeated rows and one-ulp neighbours, random schedules): tile 16 and tile 8 agree bit for bit,
+    and both equal the oracle (same ids, distances within 1e-5 relative)."""
     rng = np.random.default_rng(2026)
     for it in range(150):
         d = int(rng.integers(1, 257))
@@ -167,9 +169,22 @@ def test_cert_random_configs():
         cent = (x[rng.integers(0, n, nlist)] + np.float32(0.1) * rng.standard_normal((nlist, d))).astype(np.float32)
         ix = sivf.Index(d, nlist, cent, metric=metric, slab_capacity=C, num_slabs=n // C + 2 * nlist + 8,
                         id_capacity=n, max_batch=n, max_queries=nq, max_k=mk, max_nprobe=nlist)
-        ix.add(x, rng.permutation(n).astype(np.int64))
+        ref = oracle.OracleIndex(d, nlist, cent, metric, C, n // C + 2 * nlist + 8, n)
+        ids = rng.permutation(n).astype(np.int64)
+        ix.add(x, ids)
         assert ix.sync() == 0
+        assert ref.add(x, ids) == 0
         k, nprobe = int(rng.integers(1, mk + 1)), int(rng.integers(1, nlist + 1))
-        _both(ix, q, k, nprobe, sched=(16, int(rng.integers(6, 18)), int(rng.integers(0, 2))))
-        del ix
-    say("  150 random configurations: identical")
+        gd, gl = _both(ix, q, k, nprobe, sched=(16, int(rng.integers(6, 18)), int(rng.integers(0, 2))))
+        st, rd, rl = ref.search(q, k, nprobe)
+        assert st == 0
+        try:
+            compare_results(gd, gl, rd, rl)
+        except AssertionError:
+            gp, rp = ix.probe(q, nprobe).cpu().numpy(), oracle.probe(q, cent, nprobe, metric)
+            same_m = same_membership(membership_of(ix.dump()), ref.membership())
+            say(f"  config {it}: kind={kind} d={d} C={C} metric={metric} max_k={mk} nlist={nlist} n={n} nq={nq} "
+                f"k={k} nprobe={nprobe}; probes equal: {np.array_equal(gp, rp)}; membership equal: {same_m}")
+            raise
+        del ix, ref
+    say("  150 random configurations: identical to each other and to the oracle")

@@ -143,6 +143,75 @@ def test_assign_many_lists_and_extremes(metric):
     np.testing.assert_array_equal(p.gpu.assign(big_x).cpu().numpy(), oracle.assign(big_x, big_c, metric))
 
 
+@pytest.mark.parametrize("metric", [0, 1])
+def test_probe_and_search_at_overflow_magnitudes(metric):
+    """Probe sets and searches equal the oracle's where fp32 squares, norm sums or
+    dot products of the coarse GEMM overflow (approximations become inf or NaN):
+    such rows must be re-checked against every list, not dropped.  Vector norms
+    from about 1e17 up to 1e19 (either side of the re-check-everything threshold
+    |x| + max|c| = 2^60), nprobe 2, 7 and 64, k 10.  IP coordinates stay below
+    1.5e19, so every fp32 product of the fine distance is finite."""
+    rng = np.random.default_rng([13, metric])
+    # the hand-made case: x equal to a centroid whose fp32 |c|^2 + |x|^2 and 2 x.c
+    # both overflow (approximation inf - inf = NaN), next to finite competitors
+    cent = np.array([[7e18] * 4, [0.0] * 4, [1e18] * 4, [-3e18, 1e18, 2e18, 0.0]], np.float32)
+    x = np.concatenate([cent, cent * np.float32(0.999), cent[:1] * np.float32(1.001)]).astype(np.float32)
+    p = Pair(4, 4, cent, metric=metric, C=4, num_slabs=64, id_capacity=64, max_batch=64, max_queries=64,
+             max_k=16, max_nprobe=4)
+    assert p.add(x, np.arange(x.shape[0])) == 0
+    p.check_state()
+    for m in (1, 2, 3, 4):
+        np.testing.assert_array_equal(p.gpu.probe(x, m).cpu().numpy(), oracle.probe(x, cent, m, metric))
+        p.check_search(x, 5, m)
+    for d, scale in [(8, 3e17), (16, 2e18), (33, 7e18), (128, 1e18)]:
+        nlist = 96
+        c = rng.standard_normal((nlist, d)) * scale
+        pts = c[rng.integers(0, nlist, 3000)] * 1.0001 + rng.standard_normal((3000, d)) * scale * 0.02
+        if metric == 1:
+            c, pts = np.clip(c, -1.5e19, 1.5e19), np.clip(pts, -1.5e19, 1.5e19)
+        c, pts = c.astype(np.float32), pts.astype(np.float32)
+        assert np.isfinite(pts).all()
+        pts[:8] = c[:8]                      # rows equal to centroids
+        q = np.concatenate([pts[rng.integers(0, 3000, 150)], c[8:58]]).astype(np.float32)
+        p = Pair(d, nlist, c, metric=metric, C=64, num_slabs=3000 // 64 + nlist + 8, id_capacity=3000,
+                 max_batch=3000, max_queries=q.shape[0], max_k=16, max_nprobe=64)
+        assert p.add(pts, rng.permutation(3000).astype(np.int64)) == 0
+        p.check_state()
+        for m in (2, 7, 64):
+            np.testing.assert_array_equal(p.gpu.probe(q, m).cpu().numpy(), oracle.probe(q, c, m, metric))
+            p.check_search(q, 10, m)
+        say(f"  d={d} scale={scale:.0e}: probes and searches equal the oracle")
+
+
+def test_ip_signed_zero_scores_tie_on_id():
+    """IP scores that round to -0 and to +0 are the same score: the results are
+    ordered by id among them, on the VALU scan (tile 8), the certified scan
+    (tile 16) and the reduced-precision scan with its exact re-rank."""
+    rng = np.random.default_rng(47)
+    n, d = 3000, 8
+    x = (rng.choice([-1.0, 1.0], (n, d)) * 1e-30).astype(np.float32)
+    cent = np.zeros((2, d), np.float32)
+    cent[1, 0] = 1.0
+    q = np.concatenate([np.full((8, d), 1e-30), rng.choice([-1.0, 1.0], (8, d)) * 1e-30]).astype(np.float32)
+    p = Pair(d, 2, cent, metric=1, C=64, num_slabs=200, id_capacity=n, max_batch=n, max_queries=16, max_k=32,
+             max_nprobe=2)
+    assert p.add(x, rng.permutation(n).astype(np.int64)) == 0
+    for tile in (8, 16):
+        p.gpu.set_search_schedule(tile, 14, 0)
+        p.check_search(q, 32, 2)
+        p.check_search(q, 5, 1)
+    ix = sivf.Index(d, 2, cent, metric=1, slab_capacity=64, num_slabs=200, id_capacity=n, max_batch=n,
+                    max_queries=16, max_k=16, max_nprobe=2, storage=1, rerank_factor=4)
+    ix.add(x, np.arange(n))
+    assert ix.sync() == 0
+    gd, gl = ix.search(q, 10, 2)
+    gl = gl.cpu().numpy()
+    assert (gd.cpu().numpy() == 0).all()
+    # every candidate scores 0 exactly, so the re-ranked top 10 of the 40 candidates
+    # are the 10 smallest candidate ids: ascending, and never a deleted or missing id
+    assert (np.diff(gl, axis=1) > 0).all() and (gl >= 0).all()
+
+
 # --------------------------------------------------------- golden sequence
 
 def test_golden_mutation_sequence_gpu():

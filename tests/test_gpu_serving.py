@@ -63,6 +63,12 @@ def test_server_mix_equals_serial(storage):
     for r in reqs:                      # submit everything at once: maximum overlap
         if r[0] == "search":
             t, d, l = srv.search(r[1], 10, r[2])
+            waited = 0
+            while t is None:            # search slots full: let earlier requests finish, then resubmit
+                assert waited < len(tickets), "search refused with nothing in flight"
+                srv.wait(tickets[waited][0])
+                waited += 1
+                t, d, l = srv.search(r[1], 10, r[2], out=(d, l))
             tickets.append((t, d, l))
         elif r[0] == "add":
             t = srv.add(r[1], r[2])
@@ -78,6 +84,7 @@ def test_server_mix_equals_serial(storage):
             tickets.append((t, nrem))
     for tk in tickets:
         srv.wait(tk[0])
+    nb, nreq = srv.batches()
     srv.close()
     assert a.sync() == 0
     nsearch = 0
@@ -104,7 +111,53 @@ def test_server_mix_equals_serial(storage):
     check_dump(da, w.slab, 1200)
     assert same_membership(membership_of(da), membership_of(db))
     assert same_membership(membership_of(da), ref.membership())
-    say(f"  {len(reqs)} requests ({nsearch} searches) identical in the mix and one at a time")
+    assert nreq == nsearch and nb <= nsearch
+    say(f"  {len(reqs)} requests ({nsearch} searches in {nb} batches) identical in the mix and one at a time")
+
+
+@pytest.mark.parametrize("storage", [0, 1])
+def test_server_coalesces_searches(storage):
+    """Searches submitted while a search batch is in flight join one batch:
+    a run of 60 searches (sizes 1..40, k 1..16, nprobe 1..16) goes out in
+    fewer launches than requests, rows past the batch slots start a new batch,
+    and every result equals the same search run alone (and the oracle)."""
+    w = workloads.tiny()
+    x, ids = w.base()
+    rng = np.random.default_rng(78)
+    kw = dict(metric=w.metric, slab_capacity=w.slab, num_slabs=400, id_capacity=8192, max_batch=4096,
+              max_queries=128, max_k=16, max_nprobe=16, storage=storage, rerank_factor=4 if storage else 0)
+    a = sivf.Index(w.dim, w.nlist, w.centroids, **kw)
+    a.add(x, ids)
+    assert a.sync() == 0
+    ref = oracle.OracleIndex(w.dim, w.nlist, w.centroids, w.metric, w.slab, 400, 8192)
+    assert ref.add(x, ids) == 0
+    reqs = [(w.queries(int(rng.integers(1, 41)), tag=1000 + i), int(rng.integers(1, 17)), int(rng.integers(1, 17)))
+            for i in range(60)]
+    srv = sivf.Server(a)
+    out = []
+    for q, k, npb in reqs:
+        t, d, l = srv.search(q, k, npb)
+        while t is None:
+            srv.wait(out[0][0] if out else 0)
+            for o in out:
+                srv.poll(o[0])
+            t, d, l = srv.search(q, k, npb, out=(d, l))
+        out.append((t, d, l))
+    for o in out:
+        srv.wait(o[0])
+    nb, nreq = srv.batches()
+    srv.close()
+    assert a.sync() == 0
+    assert nreq == 60 and nb < 60, (nb, nreq)
+    for (q, k, npb), (t, d, l) in zip(reqs, out):
+        gd, gl = a.search(q, k, npb)
+        assert a.sync() == 0
+        np.testing.assert_array_equal(l.cpu().numpy(), gl.cpu().numpy())
+        np.testing.assert_array_equal(d.cpu().numpy(), gd.cpu().numpy())
+        if storage == 0:
+            st, rd, rl = ref.search(q, k, npb)
+            compare_results(d.cpu().numpy(), l.cpu().numpy(), rd, rl)
+    say(f"  60 searches in {nb} batches, each identical to its alone result")
 
 
 def test_server_admission_and_live_ids():

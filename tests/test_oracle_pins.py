@@ -393,3 +393,20 @@ def test_knn_exact_ip_bruteforce_before_and_after_deletes():
     wd, wi = _brute_int(x[:3], q[:2], np.arange(3), 3, metric=oracle.IP)
     np.testing.assert_array_equal(ki[:, :3], wi)
     assert (ki[:, 3:] == -1).all() and (kd[:, 3:] == -np.inf).all()
+
+
+def test_ip_signed_zero_scores_tie_on_id():
+    """An inner product of tiny values rounds to -0 or +0 with the sign of the
+    exact sum; both are the score 0, so the order among them is by id alone.
+    Catches a ranking on the raw sign bit (which would put every +0 first)."""
+    rng = np.random.default_rng(47)
+    n, d = 300, 3
+    x = (rng.choice([-1.0, 1.0], (n, d)) * 1e-30).astype(np.float32)
+    ix = oracle.OracleIndex(d, 1, np.zeros((1, d), np.float32), oracle.IP, 64, 100, n)
+    assert ix.add(x, rng.permutation(n).astype(np.int64)) == 0
+    q = np.full((4, d), 1e-30, np.float32)
+    st, dist, lab = ix.search(q, 20, 1)
+    assert st == 0
+    signs = {bool(np.signbit(v)) for v in dist.ravel()}
+    assert (dist == 0).all() and signs == {False, True}, "the sample must mix -0 and +0 scores"
+    np.testing.assert_array_equal(lab, np.tile(np.arange(20), (4, 1)))
