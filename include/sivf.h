@@ -58,7 +58,8 @@ typedef enum {
     SIVF_ERR_ID_RANGE = -3, /* an id outside [0, id_capacity)                    */
     SIVF_ERR_DEVICE = -4,   /* a HIP runtime call failed                         */
     SIVF_ERR_STATE = -5,    /* handle unusable (e.g. after a device error)       */
-    SIVF_ERR_LIVE_ID = -6   /* a server insert named an id that is live          */
+    SIVF_ERR_LIVE_ID = -6,  /* a server insert named an id that is live          */
+    SIVF_ERR_TOO_LARGE = -7 /* request exceeds the fixed scratch of sivf_probe_noalloc */
 } sivf_status;
 
 typedef enum { SIVF_L2 = 0, SIVF_IP = 1 } sivf_metric;
@@ -205,6 +206,22 @@ sivf_status sivf_assign(sivf_index *ix, int64_t n, const float *x, int32_t *list
  * int32; entries past nlist are -1.  1 <= nprobe <= max_nprobe. */
 sivf_status sivf_probe(sivf_index *ix, int64_t nq, const float *q, int32_t nprobe,
                        int32_t *probes, void *stream);
+
+/* sivf_probe for callers that cannot allocate device memory (code under
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same probe sets, with the approximate-distance scratch in a fixed 16 MiB
+ * device array of the library instead of the index workspace.  Each device
+ * holds one copy of that array until the process ends; every call on a
+ * device shares it and leaves its contents behind (nothing in it needs to
+ * start at zero), so calls that overlap on one device -- on two streams, or
+ * from two threads -- race and must not be issued.  nq x nlist floats
+ * (nq x ceil(nlist / 16) when nprobe == 1) must fit in 16 MiB and nq may not
+ * exceed max(max_batch, max_queries): larger requests return
+ * SIVF_ERR_TOO_LARGE with nothing enqueued.  The calling thread's device may
+ * differ from the index's; the kernels run on the stream given.  Allocates
+ * nothing, ever (the array is set up on the first call on a device). */
+sivf_status sivf_probe_noalloc(sivf_index *ix, int64_t nq, const float *q, int32_t nprobe,
+                               int32_t *probes, void *stream);
 
 /* Approximate coarse distances of the quantizer's MFMA stage:
  * |x|^2 + |c|^2 - 2 x.c (L2) or -x.c (IP), before the exact re-check.  For

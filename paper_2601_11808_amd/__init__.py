@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsivf.so")
 
-OK, ERR_ARG, ERR_NOSPACE, ERR_ID_RANGE, ERR_DEVICE, ERR_STATE, ERR_LIVE_ID = 0, -1, -2, -3, -4, -5, -6
+OK, ERR_ARG, ERR_NOSPACE, ERR_ID_RANGE, ERR_DEVICE, ERR_STATE, ERR_LIVE_ID, ERR_TOO_LARGE = 0, -1, -2, -3, -4, -5, -6, -7
 L2, IP = 0, 1
 F32, BF16, F16 = 0, 1, 2
 
@@ -67,6 +67,7 @@ SIGNATURES = [
     ("sivf_graph_destroy", ct.c_int, [_P]),
     ("sivf_assign", ct.c_int, [_P, _I64, _P, _P, _P]),
     ("sivf_probe", ct.c_int, [_P, _I64, _P, _I32, _P, _P]),
+    ("sivf_probe_noalloc", ct.c_int, [_P, _I64, _P, _I32, _P, _P]),
     ("sivf_coarse_scores", ct.c_int, [_P, _I64, _P, _P, _P]),
     ("sivf_get_rows", ct.c_int, [_P, _I64, _P, _P, _P]),
     ("sivf_sync", ct.c_int, [_P, ct.POINTER(ct.c_int)]),
@@ -338,6 +339,18 @@ class Index:
         _check(lib().sivf_probe(self._h, q.shape[0], _ptr(q), nprobe, _ptr(out), self._stream(stream)),
                "sivf_probe")
         self._keep = [q]
+        return out
+
+    def probe_noalloc(self, q, nprobe, out=None, stream=None):
+        """probe() whose scratch is the library's fixed device array (nothing is
+        allocated by the library; `out` may be passed to allocate nothing here
+        either)."""
+        torch = _torch()
+        q = _dev_tensor(q, torch.float32, self.device).reshape(-1, self.dim)
+        if out is None:
+            out = torch.empty((q.shape[0], nprobe), dtype=torch.int32, device=self.device)
+        _check(lib().sivf_probe_noalloc(self._h, q.shape[0], _ptr(q), nprobe, _ptr(out), self._stream(stream)),
+               "sivf_probe_noalloc")
         return out
 
     def coarse_scores(self, x, stream=None):

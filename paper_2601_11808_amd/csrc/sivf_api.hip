@@ -10,6 +10,7 @@
 
 #include <new>
 #include <deque>
+#include <mutex>
 #include <unordered_map>
 #include <vector>
 
@@ -620,6 +621,58 @@ sivf_status sivf_probe(sivf_index *ix, int64_t nq, const float *q, int32_t nprob
     if (nq == 0) return SIVF_OK;
     const int m = nprobe < ix->cfg.nlist ? nprobe : ix->cfg.nlist;
     coarse(ix, as_stream(stream), ix->dt_s, q, nq, m, nullptr, nprobe, probes, nprobe, 0);
+    return launched(ix);
+}
+
+// ------------------------------------------- probe without workspace scratch
+//
+// For callers that cannot allocate device memory per call (code under graph
+// capture, tight serving loops): the approximate-distance scratch of the
+// probe lives in a fixed device array of this library, one copy per device,
+// held until the process ends.  Host code never passes the array's name to a
+// kernel (in host code it is only a stand-in for the symbol): the device
+// address comes from hipGetSymbolAddress, once per device, with that device
+// current.
+constexpr size_t NOALLOC_SCRATCH_FLOATS = (size_t)(16u << 20) / sizeof(float);   // 16 MiB
+static __device__ __align__(256) float scratch[NOALLOC_SCRATCH_FLOATS];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+float *g_scratch_ptr[MAX_DEVICES] = {};
+
+float *scratch_on(int device) {
+    if (device < 0 || device >= MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        int cur = 0;
+        if (!dev_ok(hipGetDevice(&cur))) return nullptr;
+        if (cur != device && !dev_ok(hipSetDevice(device))) return nullptr;
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != device) (void)hipSetDevice(cur);
+        if (!dev_ok(e) || !p) return nullptr;
+        g_scratch_ptr[device] = (float *)p;
+    }
+    return g_scratch_ptr[device];
+}
+}  // namespace
+
+sivf_status sivf_probe_noalloc(sivf_index *ix, int64_t nq, const float *q, int32_t nprobe, int32_t *probes,
+                               void *stream) {
+    if (!ix || nq < 0 || (nq > 0 && (!q || !probes))) return SIVF_ERR_ARG;
+    if (ix->broken) return SIVF_ERR_STATE;
+    if (nprobe < 1 || nprobe > ix->cfg.max_nprobe) return SIVF_ERR_ARG;
+    const int m = nprobe < ix->cfg.nlist ? nprobe : ix->cfg.nlist;
+    const int per_row = (m == 1 && nprobe == 1) ? coarse_groups(ix->cfg.nlist) : ix->cfg.nlist;
+    if ((size_t)nq * (size_t)per_row > NOALLOC_SCRATCH_FLOATS) return SIVF_ERR_TOO_LARGE;
+    const int64_t cap = ix->cfg.max_batch > ix->cfg.max_queries ? ix->cfg.max_batch : ix->cfg.max_queries;
+    if (nq > cap) return SIVF_ERR_TOO_LARGE;
+    float *sp = scratch_on(ix->device);
+    if (!sp) return SIVF_ERR_DEVICE;
+    ix->last = as_stream(stream);
+    if (nq == 0) return SIVF_OK;
+    coarse(ix, as_stream(stream), sp, q, nq, m, nullptr, nprobe, probes, nprobe, 0);
     return launched(ix);
 }
 
@@ -1493,6 +1546,7 @@ const char *sivf_status_string(sivf_status s) {
         case SIVF_ERR_DEVICE: return "HIP runtime error";
         case SIVF_ERR_STATE: return "index state unusable";
         case SIVF_ERR_LIVE_ID: return "a server insert named a live id";
+        case SIVF_ERR_TOO_LARGE: return "request larger than the fixed scratch of the no-allocation entry point";
     }
     return "unknown status";
 }
