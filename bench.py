@@ -156,6 +156,19 @@ def exact_topk(xw, idw, q, k, metric, chunk=1 << 18):
     return best_i
 
 
+def copy_calibration():
+    """A plain 1 GiB device-to-device copy: its DRAM byte counters scale those
+    of the library's kernels (1 GiB read, 1 GiB written)."""
+    import torch
+    nbytes = 1 << 30
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -482,13 +495,7 @@ def main():
         del pool
 
     if a.copy_calibration:
-        nbytes = 1 << 30
-        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        copy_calibration()
 
     add_ms = prof["add"][0] / max(prof["add"][1], 1)
     rm_ms = prof["remove"][0] / max(prof["remove"][1], 1)
@@ -767,6 +774,8 @@ def mutation_main(a):
     N, d = x.shape
     reps = max(1, a.steps // 10)
     m = bulk_mutation_leg(w, x, ids, reps=reps)
+    if a.copy_calibration:
+        copy_calibration()
     res = {
         "metric": "insert/delete vectors/s at bulk scale (whole-window insert, half-window delete)",
         "value": m["insert"]["vec_per_s"], "unit": "inserted vectors/s",

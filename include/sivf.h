@@ -65,6 +65,17 @@ typedef enum {
 typedef enum { SIVF_L2 = 0, SIVF_IP = 1 } sivf_metric;
 typedef enum { SIVF_F32 = 0, SIVF_BF16 = 1, SIVF_F16 = 2 } sivf_dtype;
 
+/* How sivf_remove deletes (both give the same membership and search results):
+ *  SIVF_DELETE_COMPACT: the list's tail entry moves into the hole at once, so
+ *    lists stay dense and emptied tail slabs return to the pool in the call;
+ *  SIVF_DELETE_LAZY: the paper's eviction (Sec. 3.4, Alg. 4): a validity bit
+ *    per slot is cleared with an atomic AND (the 1 -> 0 transition counts the
+ *    removal exactly once, Theorem 3) and nothing moves, so a delete never
+ *    waits for searches; inserts publish their slots with a release fence and
+ *    an atomic OR (Alg. 2).  Dead slots keep their space until
+ *    sivf_compact. */
+typedef enum { SIVF_DELETE_COMPACT = 0, SIVF_DELETE_LAZY = 1 } sivf_delete_mode;
+
 /* Index configuration.  The slab pool and id space are fixed at creation
  * (the paper pre-allocates a monolithic slab pool, Sec. 3.1 and Sec. 4.1). */
 typedef struct {
@@ -88,6 +99,8 @@ typedef struct {
     int32_t max_queries;   /* largest nq of one sivf_search call                   */
     int32_t max_k;         /* largest k, 1..128 (fp32 storage)                     */
     int32_t max_nprobe;    /* largest nprobe, 1..1024                              */
+    int32_t delete_mode;   /* sivf_delete_mode                                     */
+    int32_t reserved;      /* must be 0                                            */
 } sivf_config;
 
 /* Bytes of device workspace the configuration needs (0 if invalid). */
@@ -197,6 +210,18 @@ sivf_status sivf_graph_create(sivf_index *ix, const sivf_step_args *args, sivf_g
 sivf_status sivf_graph_launch(sivf_graph *g, void *stream);
 sivf_status sivf_graph_destroy(sivf_graph *g);
 
+/* Reclaim the slots of lazy deletes (SIVF_DELETE_LAZY; a no-op otherwise):
+ * every list whose dead slots are at least min_dead_fraction of its length
+ * (0 = any dead slot) is compacted -- its tail entries move into the dead
+ * slots below the new length, as a dense delete does, and emptied tail slabs
+ * return to the pool with cleared validity words (reset before the push).
+ * The adaptive background compaction the paper plans (Sec. 6): call it when
+ * fragmentation passes a threshold.  Entries move, so no search may overlap
+ * the call (the server orders it after earlier searches).  At most max_batch
+ * dead slots are reclaimed per call; n_compacted (device int64 scalar or
+ * NULL) receives the number reclaimed; call again while it is positive. */
+sivf_status sivf_compact(sivf_index *ix, float min_dead_fraction, int64_t *n_compacted, void *stream);
+
 /* Nearest list of each vector (the coarse assignment used by sivf_add).
  * x: device n x dim fp32; lists: device n int32.  n <= max(max_batch, max_queries). */
 sivf_status sivf_assign(sivf_index *ix, int64_t n, const float *x, int32_t *lists, void *stream);
@@ -250,13 +275,14 @@ sivf_status sivf_stats(sivf_index *ix, int64_t *live, int64_t *used_slabs, int64
 
 /* Sizes of the arrays sivf_dump fills (waits for the handle's last stream). */
 typedef struct {
-    int64_t live;        /* sum of list lengths                          */
+    int64_t live;        /* entries in all lists                         */
     int64_t used_slabs;  /* sum over lists of ceil(len / C)              */
     int64_t free_slabs;  /* entries on the free stack                    */
     int64_t num_slabs;
     int64_t id_capacity;
     int32_t nlist;
     int32_t slab_capacity;
+    int64_t positions;   /* sum of list lengths: live plus dead slots (lazy deletes) */
 } sivf_dump_info;
 
 sivf_status sivf_dump_info_get(sivf_index *ix, sivf_dump_info *info);
@@ -264,7 +290,8 @@ sivf_status sivf_dump_info_get(sivf_index *ix, sivf_dump_info *info);
 /* Copy the index state to host arrays for validation (waits).  All host.
  *   list_len     [nlist]        entries per list
  *   list_slabs   [used_slabs]   slab ids of list 0 by ordinal, then list 1, ...
- *   ids_by_list  [live]         ids of list 0 by position, then list 1, ...
+ *   ids_by_list  [positions]    ids of list 0 by position, then list 1, ...
+ *                               (-1 for a slot deleted lazily, not yet compacted)
  *   free_slabs   [free_slabs]   the free stack, bottom first
  *   slab_owner   [num_slabs]    list holding each slab, or -1
  *   slab_ordinal [num_slabs]    position of the slab in its list's table

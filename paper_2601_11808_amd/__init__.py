@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libsivf.so")
 OK, ERR_ARG, ERR_NOSPACE, ERR_ID_RANGE, ERR_DEVICE, ERR_STATE, ERR_LIVE_ID, ERR_TOO_LARGE = 0, -1, -2, -3, -4, -5, -6, -7
 L2, IP = 0, 1
 F32, BF16, F16 = 0, 1, 2
+DELETE_COMPACT, DELETE_LAZY = 0, 1
 
 
 class SivfError(RuntimeError):
@@ -32,7 +33,8 @@ class SivfConfig(ct.Structure):
                 ("metric", ct.c_int32), ("storage", ct.c_int32), ("rerank_factor", ct.c_int32),
                 ("num_slabs", ct.c_int64), ("id_capacity", ct.c_int64),
                 ("max_batch", ct.c_int32), ("max_queries", ct.c_int32),
-                ("max_k", ct.c_int32), ("max_nprobe", ct.c_int32)]
+                ("max_k", ct.c_int32), ("max_nprobe", ct.c_int32),
+                ("delete_mode", ct.c_int32), ("reserved", ct.c_int32)]
 
 
 class SivfStepArgs(ct.Structure):
@@ -46,7 +48,7 @@ class SivfStepArgs(ct.Structure):
 class SivfDumpInfo(ct.Structure):
     _fields_ = [("live", ct.c_int64), ("used_slabs", ct.c_int64), ("free_slabs", ct.c_int64),
                 ("num_slabs", ct.c_int64), ("id_capacity", ct.c_int64),
-                ("nlist", ct.c_int32), ("slab_capacity", ct.c_int32)]
+                ("nlist", ct.c_int32), ("slab_capacity", ct.c_int32), ("positions", ct.c_int64)]
 
 
 # (name, restype, argtypes) of every exported entry point of include/sivf.h
@@ -66,6 +68,7 @@ SIGNATURES = [
     ("sivf_graph_launch", ct.c_int, [_P, _P]),
     ("sivf_graph_destroy", ct.c_int, [_P]),
     ("sivf_assign", ct.c_int, [_P, _I64, _P, _P, _P]),
+    ("sivf_compact", ct.c_int, [_P, ct.c_float, _P, _P]),
     ("sivf_probe", ct.c_int, [_P, _I64, _P, _I32, _P, _P]),
     ("sivf_probe_noalloc", ct.c_int, [_P, _I64, _P, _I32, _P, _P]),
     ("sivf_coarse_scores", ct.c_int, [_P, _I64, _P, _P, _P]),
@@ -162,7 +165,7 @@ class Index:
     def __init__(self, dim, nlist, centroids, metric=L2, slab_capacity=64, num_slabs=1 << 16,
                  id_capacity=1 << 20, max_batch=1 << 16, max_queries=1 << 14, max_k=64,
                  max_nprobe=256, storage=F32, rerank_factor=0, device="cuda:0", stream=None,
-                 _checkpoint=None):
+                 delete_mode=DELETE_COMPACT, _checkpoint=None):
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device is available")
@@ -171,8 +174,9 @@ class Index:
                               storage=storage, rerank_factor=rerank_factor, num_slabs=num_slabs,
                               id_capacity=id_capacity,
                               max_batch=max_batch, max_queries=max_queries, max_k=max_k,
-                              max_nprobe=max_nprobe)
+                              max_nprobe=max_nprobe, delete_mode=delete_mode, reserved=0)
         self.dim, self.nlist, self.metric, self.C = dim, nlist, metric, slab_capacity
+        self.lazy = delete_mode == DELETE_LAZY
         nbytes = lib().sivf_workspace_bytes(ct.byref(self.cfg))
         if nbytes == 0:
             raise SivfError(ERR_ARG, "sivf_workspace_bytes (invalid configuration)")
@@ -200,7 +204,8 @@ class Index:
         max_nprobe) may be overridden; the rest come from the file."""
         cfg, live = checkpoint_config(path)
         kw = {k: getattr(cfg, k) for k in ("metric", "slab_capacity", "num_slabs", "id_capacity", "max_batch",
-                                            "max_queries", "max_k", "max_nprobe", "storage", "rerank_factor")}
+                                            "max_queries", "max_k", "max_nprobe", "storage", "rerank_factor",
+                                            "delete_mode")}
         kw.update(overrides)
         return cls(cfg.dim, cfg.nlist, None, device=device, stream=stream, _checkpoint=path, **kw)
 
@@ -362,6 +367,14 @@ class Index:
         self._keep = [x]
         return out
 
+    def compact(self, min_dead_fraction=0.0, stream=None):
+        """Reclaim lazily deleted slots (see sivf_compact); returns a device
+        int64 scalar with the number reclaimed by this call."""
+        torch = _torch()
+        n = torch.zeros(1, dtype=torch.int64, device=self.device)
+        _check(lib().sivf_compact(self._h, float(min_dead_fraction), _ptr(n), self._stream(stream)), "sivf_compact")
+        return n
+
     def get_rows(self, ids, stream=None):
         torch = _torch()
         ids = _dev_tensor(ids, torch.int64, self.device).reshape(-1)
@@ -408,7 +421,7 @@ class Index:
         out = {
             "list_len": np.empty(info.nlist, np.int32),
             "list_slabs": np.empty(info.used_slabs, np.int32),
-            "ids_by_list": np.empty(info.live, np.int64),
+            "ids_by_list": np.empty(info.positions, np.int64),
             "free_slabs": np.empty(info.free_slabs, np.int32),
             "slab_owner": np.empty(info.num_slabs, np.int32),
             "slab_ordinal": np.empty(info.num_slabs, np.int32),
@@ -425,8 +438,13 @@ class Index:
         """{list id: sorted id array} for non-empty lists (from a dump)."""
         d = self.dump()
         offs = np.concatenate([[0], np.cumsum(d["list_len"].astype(np.int64))])
-        return {l: np.sort(d["ids_by_list"][offs[l]:offs[l + 1]]) for l in range(self.nlist)
-                if d["list_len"][l] > 0}
+        out = {}
+        for l in range(self.nlist):
+            v = d["ids_by_list"][offs[l]:offs[l + 1]]
+            v = v[v >= 0]                      # lazily deleted slots read -1
+            if v.shape[0]:
+                out[l] = np.sort(v)
+        return out
 
 
 def checkpoint_config(path):

@@ -33,6 +33,16 @@ namespace sivf {
 
 __device__ __forceinline__ int cdiv(int a, int b) { return (a + b - 1) / b; }
 
+// Lazy deletes: make a written slot visible (the paper's Alg. 2): a release
+// fence at agent scope orders the slot's payload, id and address-table writes
+// before the atomic OR that sets its validity bit, so a reader that sees the
+// bit (on any XCD) sees the entry.
+__device__ __forceinline__ void publish_slot(const Dev &S, int slab, int slot) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_fetch_or(S.bits + (int64_t)slab * S.bw + (slot >> 6), 1ull << (slot & 63), __ATOMIC_RELAXED,
+                          __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // ------------------------------------------------------------------ insert
 
 __global__ __launch_bounds__(256) void k_add_prepare(Dev S, int n, const int64_t *__restrict__ ids) {
@@ -46,12 +56,17 @@ __global__ __launch_bounds__(256) void k_add_prepare(Dev S, int n, const int64_t
 }
 
 // fresh_only: the call may not hold live ids (SIVF_ERR_LIVE_ID otherwise).
+template <bool BLK>
 __global__ __launch_bounds__(256) void k_add_count(Dev S, int n, const int64_t *__restrict__ ids,
                                                    const int32_t *__restrict__ assign, int32_t *__restrict__ rank,
                                                    int fresh_only) {
-    if (call_failed(S.ctl)) return;
+    extern __shared__ int32_t hist[];
+    // no early return: this kernel may fail the call while other waves of the
+    // block are still starting, and every thread must reach the block's
+    // barriers; a failed call's counts are cleared by the admission kernel
+    const bool failed = call_failed(S.ctl);
     const int i = blockIdx.x * 256 + threadIdx.x;
-    const bool active = i < n;
+    const bool active = i < n && !failed;
     const int64_t u = active ? ids[i] : 0;
     bool win = active && S.mark[u] == i;
     int l = win ? assign[i] : 0;
@@ -62,12 +77,13 @@ __global__ __launch_bounds__(256) void k_add_count(Dev S, int n, const int64_t *
         win = false;
         l = 0;
     }
-    const int r = wave_agg_inc(S.l_acnt, l, win);
+    const int r = list_agg_inc<BLK>(S.l_acnt, l, win, hist, S.nlist, true);
     if (active) rank[i] = win ? r : -1;
     const uint32_t g = win ? S.att[u] : INVALID;
     const bool live = g != INVALID;
     const int lo = live ? S.sowner[g / (uint32_t)S.C] : 0;
-    wave_agg_inc(S.l_prem, lo, live);
+    // an upsert frees a position only with compacting deletes (a lazy delete leaves a dead slot)
+    list_agg_inc<BLK>(S.l_prem, lo, live && !S.bits, hist, S.nlist, false);
     if (ballot(live) && lane_id() == 0) {
         if (fresh_only)
             fail_call(S.ctl, -6);
@@ -238,6 +254,7 @@ __global__ __launch_bounds__(256) void k_add_scatter(Dev S, const float *__restr
         S.sids[g] = (uint32_t)u;
         S.att[u] = g;
     }
+    if (S.bits) publish_slot(S, slab, slot);
 }
 
 // LDS-staged form of the scatter (rows of at most 64 chunks, 16-byte aligned):
@@ -269,13 +286,13 @@ __global__ __launch_bounds__(64) void k_add_scatter_lds(Dev S, const float *__re
         slab = slab_of(S, l, pos / S.C);
         slot = pos % S.C;
     }
-    // rows into LDS
+    // rows into LDS: up to 16 chunks per lane in flight (all of a 128-dim batch)
     const int tot = cnt * dp4;
-    for (int f0 = 0; f0 < tot; f0 += 4 * WAVE) {
-        float4 v[4];
-        int rr[4], cc[4];
+    for (int f0 = 0; f0 < tot; f0 += 16 * WAVE) {
+        float4 v[16];
+        int rr[16], cc[16];
 #pragma unroll
-        for (int u = 0; u < 4; u++) {
+        for (int u = 0; u < 16; u++) {
             const int f = f0 + u * WAVE + lane;
             rr[u] = f / dp4;
             cc[u] = f - rr[u] * dp4;
@@ -283,7 +300,7 @@ __global__ __launch_bounds__(64) void k_add_scatter_lds(Dev S, const float *__re
             if (f < tot) v[u] = reinterpret_cast<const float4 *>(x + (int64_t)src * S.d)[cc[u]];
         }
 #pragma unroll
-        for (int u = 0; u < 4; u++)
+        for (int u = 0; u < 16; u++)
             if (f0 + u * WAVE + lane < tot) srow[rr[u] * ld + cc[u]] = v[u];
     }
     __syncthreads();
@@ -326,6 +343,7 @@ __global__ __launch_bounds__(64) void k_add_scatter_lds(Dev S, const float *__re
         const int64_t u = ids[i];
         S.sids[g] = (uint32_t)u;
         S.att[u] = g;
+        if (S.bits) publish_slot(S, slab, slot);
     }
 }
 
@@ -350,8 +368,10 @@ __global__ __launch_bounds__(256) void k_rm_validate(Dev S, int n, const int64_t
     if (u < 0 || u >= S.id_capacity) fail_call(S.ctl, -3);
 }
 
+template <bool BLK>
 __global__ __launch_bounds__(256) void k_rm_mark(Dev S, int n, const int64_t *__restrict__ ids,
                                                  uint32_t *__restrict__ rec, int mode) {
+    extern __shared__ int32_t hist[];
     if (rm_skip(S, mode)) return;
     const int i = blockIdx.x * 256 + threadIdx.x;
     const int64_t u = i < n ? ids[i] : -1;
@@ -363,7 +383,7 @@ __global__ __launch_bounds__(256) void k_rm_mark(Dev S, int n, const int64_t *__
         S.sids[g] = INVALID;   // tombstone: this slot no longer holds a live entry
         l = S.sowner[g / (uint32_t)S.C];
     }
-    wave_agg_inc(S.l_m, l, hit);
+    list_agg_inc<BLK>(S.l_m, l, hit, hist, S.nlist, false);
     if (i < n) rec[i] = g;
 }
 
@@ -397,8 +417,10 @@ __global__ __launch_bounds__(1024) void k_rm_plan(Dev S, int64_t *n_removed, int
 
 // Holes: deleted positions below the new length n' of their list.  The h-th
 // hole of list l (in any order) is stored at seg[l_off[l] + h].
+template <bool BLK>
 __global__ __launch_bounds__(256) void k_rm_holes(Dev S, int n, const uint32_t *__restrict__ rec,
                                                   int32_t *__restrict__ seg, int mode) {
+    extern __shared__ int32_t hist[];
     if (rm_skip(S, mode)) return;
     const int i = blockIdx.x * 256 + threadIdx.x;
     const uint32_t g = i < n ? rec[i] : INVALID;
@@ -410,8 +432,18 @@ __global__ __launch_bounds__(256) void k_rm_holes(Dev S, int n, const uint32_t *
         l = S.sowner[slab];
         hole = S.sord[slab] * S.C + (int)(g % (uint32_t)S.C) < S.l_newlen[l];
     }
-    const int h = wave_agg_inc(S.l_h, l, hole);
+    const int h = list_agg_inc<BLK>(S.l_h, l, hole, hist, S.nlist, true);
     if (hole) seg[S.l_off[l] + h] = (int32_t)g;
+}
+
+// Tail-window entry -> list map for the move: entries l_off[l] .. +l_m[l]
+// belong to list l.  One wave per list.
+__global__ __launch_bounds__(256) void k_rm_expand(Dev S, int32_t *__restrict__ emap, int mode) {
+    if (rm_skip(S, mode)) return;
+    const int l = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (l >= S.nlist) return;
+    const int m = S.l_m[l], o = S.l_off[l];
+    for (int j = lane_id(); j < m; j += 64) emap[o + j] = l;
 }
 
 // The tail windows [n', n) of all lists with deletions, list after list, one
@@ -421,28 +453,21 @@ __global__ __launch_bounds__(256) void k_rm_holes(Dev S, int n, const uint32_t *
 // read consecutive slots, so each 16-byte dimension chunk of a wave's
 // survivors is one contiguous read; the holes they fill are scattered.
 template <bool HALF>
-__global__ __launch_bounds__(256) void k_rm_move(Dev S, int n, const int32_t *__restrict__ seg, int mode) {
+__global__ __launch_bounds__(256) void k_rm_move(Dev S, int n, const int32_t *__restrict__ seg,
+                                                 const int32_t *__restrict__ emap, int mode) {
     if (rm_skip(S, mode)) return;
     const int e = blockIdx.x * 256 + threadIdx.x;
     const int total = S.ctl[CTL_RMTOT];
     const bool active = e < total;
-    int l = 0;
-    if (active) {   // the last list whose window starts at or before e
-        int lo = 0, hi = S.nlist - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (S.l_off[mid] <= e)
-                lo = mid;
-            else
-                hi = mid - 1;
-        }
-        l = lo;
-    }
+    const int l = active ? emap[e] : 0;
     uint32_t src = 0, id = INVALID;
     if (active) {
         const int tp = S.l_newlen[l] + (e - S.l_off[l]);
         src = (uint32_t)slab_of(S, l, tp / S.C) * (uint32_t)S.C + (uint32_t)(tp % S.C);
         id = S.sids[src];
+        // compacting lazy deletes: the validity bit tells a dead slot (its id word is stale)
+        if (S.bits && !((S.bits[(int64_t)(src / S.C) * S.bw + ((src % S.C) >> 6)] >> ((src % S.C) & 63)) & 1ull))
+            id = INVALID;
     }
     const bool surv = id != INVALID;
     const int r = wave_agg_inc(S.l_s, l, surv);
@@ -452,12 +477,12 @@ __global__ __launch_bounds__(256) void k_rm_move(Dev S, int n, const int32_t *__
     const float4 *sp = S.data + ss * S.dp4 * S.C + sl;
     float4 *dp = S.data + ds * S.dp4 * S.C + dl;
     int c = 0;
-    for (; c + 8 <= S.dp4; c += 8) {
-        float4 v[8];
+    for (; c + 16 <= S.dp4; c += 16) {   // 16 chunks of the row in flight
+        float4 v[16];
 #pragma unroll
-        for (int j = 0; j < 8; j++) v[j] = sp[(int64_t)(c + j) * S.C];
+        for (int j = 0; j < 16; j++) v[j] = sp[(int64_t)(c + j) * S.C];
 #pragma unroll
-        for (int j = 0; j < 8; j++) dp[(int64_t)(c + j) * S.C] = v[j];
+        for (int j = 0; j < 16; j++) dp[(int64_t)(c + j) * S.C] = v[j];
     }
     for (; c < S.dp4; c++) dp[(int64_t)c * S.C] = sp[(int64_t)c * S.C];
     if (HALF) {
@@ -468,6 +493,8 @@ __global__ __launch_bounds__(256) void k_rm_move(Dev S, int n, const int32_t *__
     if (S.xnorm) S.xnorm[dst] = S.xnorm[src];
     S.sids[dst] = id;
     S.att[id] = dst;
+    if (S.bits)   // compaction of lazy deletes: the hole holds a live entry again
+        atomicOr((unsigned long long *)(S.bits + ds * S.bw + (dl >> 6)), 1ull << (dl & 63));
 }
 
 // Per list: new length, and the tail slabs (and table pages) past the new
@@ -498,17 +525,139 @@ __global__ __launch_bounds__(256) void k_rm_finalize(Dev S, int mode) {
         const int li = blockIdx.x * 256 + i;
         const int ord = s_nsn[i] + (s - s_es[i]);
         const int slab = slab_of(S, li, ord);
+        if (S.bits)   // validity words are reset before the slab goes back on the stack
+            for (int w = 0; w < S.bw; w++) S.bits[(int64_t)slab * S.bw + w] = 0;
         S.free_slabs[s_base[0] + s] = slab;
         S.sowner[slab] = -1;
     }
     __syncthreads();
     if (m > 0) {
+        if (S.bits && (nl % S.C) != 0) {
+            // the last kept slab: slots past the new length hold no entry
+            const int64_t slab = slab_of(S, l, nsn - 1);
+            for (int s = nl % S.C; s < S.C; s++)
+                S.bits[slab * S.bw + (s >> 6)] &= ~(1ull << (s & 63));
+        }
+        if (S.bits) S.l_dead[l] -= m;
         for (int j = 0; j < pgo - pgn; j++)
             S.free_pages[s_base[1] + ep + j] = S.dir[(int64_t)l * S.dir_cap + pgn + j];
         S.len[l] = nl;
         S.l_m[l] = 0;
     }
 }
+
+// ------------------------------------------------------------ lazy deletes
+
+__global__ void k_rm_lazy_begin(int32_t *ctl) {
+    if (threadIdx.x == 0) ctl[CTL_RMTOT] = 0;
+}
+
+// The paper's eviction (Alg. 4): the address-table exchange finds the slot in
+// O(1) and makes exactly one thread own the id; the atomic AND clears its
+// validity bit, and the old word shows the 1 -> 0 transition that counts the
+// removal (Theorem 3).  Nothing moves; the slot stays dead until compaction.
+template <bool BLK>
+__global__ __launch_bounds__(256) void k_rm_lazy(Dev S, int n, const int64_t *__restrict__ ids, int mode) {
+    extern __shared__ int32_t hist[];
+    if (rm_skip(S, mode == 1 ? 1 : 0)) return;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int64_t u = i < n ? ids[i] : -1;
+    const bool active = u >= 0 && u < S.id_capacity;
+    const uint32_t g = active ? atomicExch(&S.att[u], INVALID) : INVALID;
+    bool gone = false;
+    int l = 0;
+    if (g != INVALID) {
+        const int64_t slab = g / (uint32_t)S.C;
+        const int slot = (int)(g % (uint32_t)S.C);
+        const uint64_t bit = 1ull << (slot & 63);
+        const uint64_t old = __hip_atomic_fetch_and(S.bits + slab * S.bw + (slot >> 6), ~bit, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+        gone = (old & bit) != 0;
+        l = S.sowner[slab];
+    }
+    list_agg_inc<BLK>(S.l_dead, l, gone, hist, S.nlist, false);
+    const uint64_t gm = ballot(gone);
+    if (gm && lane_id() == __builtin_ctzll(gm)) atomicAdd(&S.ctl[CTL_RMTOT], (int)__builtin_popcountll(gm));
+}
+
+__global__ void k_rm_lazy_end(Dev S, int64_t *n_removed) {
+    if (threadIdx.x == 0) *n_removed = call_failed(S.ctl) ? 0 : S.ctl[CTL_RMTOT];
+}
+
+// ------------------------------------------------------------ compaction
+
+// One block.  List l is compacted when its dead slots are at least
+// frac * len (and > 0); lists in order take dead slots out of the budget, the
+// last one partly: m' of its dead slots are removed (n' = len - m'), the
+// others stay dead.  Then as k_rm_plan: tail-window offsets, new lengths.
+__global__ __launch_bounds__(1024) void k_cmp_plan(Dev S, float frac, int budget, int64_t *n_compacted) {
+    __shared__ int sbuf[16];
+    int carry = 0;
+    for (int base = 0; base < S.nlist; base += 1024) {
+        const int l = base + threadIdx.x;
+        int want = 0;
+        if (l < S.nlist) {
+            const int dead = S.l_dead[l];
+            want = (dead > 0 && (float)dead >= frac * (float)S.len[l]) ? dead : 0;
+        }
+        int tot;
+        const int ex = block_excl_scan<1024>(want, sbuf, &tot);
+        const int room = budget - carry - ex;
+        const int m = want < room ? want : (room > 0 ? room : 0);
+        int tot_m;
+        const int exm = block_excl_scan<1024>(m, sbuf, &tot_m);
+        if (l < S.nlist) {
+            S.l_m[l] = m;
+            S.l_off[l] = carry + exm;
+            S.l_newlen[l] = S.len[l] - m;
+            S.l_q[l] = 0;
+            S.l_s[l] = 0;
+            S.l_h[l] = 0;
+        }
+        carry += tot_m;
+    }
+    if (threadIdx.x == 0) {
+        S.ctl[CTL_RMTOT] = carry;
+        if (n_compacted) *n_compacted = carry;
+    }
+}
+
+// Dead slots in each compacted list's tail window [n', len): l_q[l].
+__global__ __launch_bounds__(256) void k_cmp_tail(Dev S, const int32_t *__restrict__ emap) {
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    const int total = S.ctl[CTL_RMTOT];
+    const bool active = e < total;
+    int l = 0;
+    bool dead = false;
+    if (active) {
+        l = emap[e];
+        const int tp = S.l_newlen[l] + (e - S.l_off[l]);
+        const int slab = slab_of(S, l, tp / S.C), slot = tp % S.C;
+        dead = !((S.bits[(int64_t)slab * S.bw + (slot >> 6)] >> (slot & 63)) & 1ull);
+    }
+    wave_agg_inc(S.l_q, l, dead);
+}
+
+// Holes: dead slots below n'.  A compacted list needs one per survivor of its
+// tail window (m' - tail dead); any that many of its dead slots will do, the
+// others stay dead.  One thread per slab.
+__global__ __launch_bounds__(256) void k_cmp_holes(Dev S, int32_t *__restrict__ seg) {
+    const int64_t slab = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (slab >= S.num_slabs) return;
+    const int l = S.sowner[slab];
+    if (l < 0 || S.l_m[l] == 0) return;
+    const int need = S.l_m[l] - S.l_q[l];
+    const int nl = S.l_newlen[l];
+    const int p0 = S.sord[slab] * S.C;
+    for (int s = 0; s < S.C && p0 + s < nl; s++) {
+        const uint32_t g = (uint32_t)slab * (uint32_t)S.C + (uint32_t)s;
+        if ((S.bits[slab * S.bw + (s >> 6)] >> (s & 63)) & 1ull) continue;   // live
+        const int h = atomicAdd(&S.l_h[l], 1);
+        if (h >= need) break;
+        seg[S.l_off[l] + h] = (int32_t)g;
+    }
+}
+
 
 __global__ __launch_bounds__(256) void k_get_rows(Dev S, int n, const int64_t *__restrict__ ids,
                                                   float *__restrict__ rows) {
@@ -557,7 +706,10 @@ __global__ __launch_bounds__(256) void k_pack(Dev S, const int32_t *__restrict__
         for (int t = 0; t < 4; t++)
             if (4 * c + t < S.d) out[4 * c + t] = ev[t];
     }
-    if (lane_id() == 0) ids[i] = S.sids[(int64_t)slab * S.C + slot];
+    if (lane_id() == 0) {
+        const bool live = !S.bits || ((S.bits[(int64_t)slab * S.bw + (slot >> 6)] >> (slot & 63)) & 1ull);
+        ids[i] = live ? S.sids[(int64_t)slab * S.C + slot] : INVALID;
+    }
 }
 
 // Last kernel of an add or remove call: the next call gets a new sequence number.
@@ -569,12 +721,23 @@ __global__ void k_call_end(int32_t *ctl) {
 
 static unsigned blocks(int64_t threads, int per = 256) { return (unsigned)((threads + per - 1) / per); }
 
+// Per-list LDS histograms when nlist ints fit in 64 KiB.
+static bool blk_hist(const Dev &S) { return S.nlist <= 16384; }
+static size_t hist_bytes(const Dev &S) { return blk_hist(S) ? (size_t)S.nlist * 4 : 0; }
+#define SIVF_LAUNCH_BLK(K, grid, st, S, ...)                                                                  \
+    do {                                                                                                     \
+        if (blk_hist(S))                                                                                     \
+            hipLaunchKernelGGL(K<true>, dim3(grid), dim3(256), hist_bytes(S), st, S, __VA_ARGS__);          \
+        else                                                                                                 \
+            hipLaunchKernelGGL(K<false>, dim3(grid), dim3(256), 0, st, S, __VA_ARGS__);                     \
+    } while (0)
+
 void launch_add_prepare(hipStream_t st, const Dev &S, int n, const int64_t *ids) {
     hipLaunchKernelGGL(k_add_prepare, dim3(blocks(n)), dim3(256), 0, st, S, n, ids);
 }
 
 void launch_add_count(hipStream_t st, const Dev &S, int n, const int64_t *ids, const Batch &B, int fresh_only) {
-    hipLaunchKernelGGL(k_add_count, dim3(blocks(n)), dim3(256), 0, st, S, n, ids, B.assign, B.rank, fresh_only);
+    SIVF_LAUNCH_BLK(k_add_count, blocks(n), st, S, n, ids, B.assign, B.rank, fresh_only);
 }
 
 void launch_add_admit(hipStream_t st, const Dev &S) {
@@ -605,14 +768,35 @@ void launch_add_cleanup(hipStream_t st, const Dev &S, int n, const int64_t *ids)
 
 void launch_remove(hipStream_t st, const Dev &S, int n, const int64_t *ids, int64_t *n_removed, const Batch &B, int mode) {
     if (mode == 0) hipLaunchKernelGGL(k_rm_validate, dim3(blocks(n)), dim3(256), 0, st, S, n, ids);
-    hipLaunchKernelGGL(k_rm_mark, dim3(blocks(n)), dim3(256), 0, st, S, n, ids, B.rec, mode);
+    SIVF_LAUNCH_BLK(k_rm_mark, blocks(n), st, S, n, ids, B.rec, mode);
     hipLaunchKernelGGL(k_rm_plan, dim3(1), dim3(1024), 0, st, S, n_removed, mode);
-    hipLaunchKernelGGL(k_rm_holes, dim3(blocks(n)), dim3(256), 0, st, S, n, B.rec, B.seg, mode);
+    SIVF_LAUNCH_BLK(k_rm_holes, blocks(n), st, S, n, B.rec, B.seg, mode);
+    hipLaunchKernelGGL(k_rm_expand, dim3(blocks(S.nlist, 4)), dim3(256), 0, st, S, B.inv, mode);
     if (S.storage != 0)
-        hipLaunchKernelGGL(k_rm_move<true>, dim3(blocks(n)), dim3(256), 0, st, S, n, B.seg, mode);
+        hipLaunchKernelGGL(k_rm_move<true>, dim3(blocks(n)), dim3(256), 0, st, S, n, B.seg, B.inv, mode);
     else
-        hipLaunchKernelGGL(k_rm_move<false>, dim3(blocks(n)), dim3(256), 0, st, S, n, B.seg, mode);
+        hipLaunchKernelGGL(k_rm_move<false>, dim3(blocks(n)), dim3(256), 0, st, S, n, B.seg, B.inv, mode);
     hipLaunchKernelGGL(k_rm_finalize, dim3(blocks(S.nlist)), dim3(256), 0, st, S, mode);
+}
+
+void launch_remove_lazy(hipStream_t st, const Dev &S, int n, const int64_t *ids, int64_t *n_removed, int mode) {
+    if (mode == 0) hipLaunchKernelGGL(k_rm_validate, dim3(blocks(n)), dim3(256), 0, st, S, n, ids);
+    if (mode != 1) hipLaunchKernelGGL(k_rm_lazy_begin, dim3(1), dim3(64), 0, st, S.ctl);
+    SIVF_LAUNCH_BLK(k_rm_lazy, blocks(n), st, S, n, ids, mode);
+    if (mode != 1 && n_removed) hipLaunchKernelGGL(k_rm_lazy_end, dim3(1), dim3(64), 0, st, S, n_removed);
+}
+
+void launch_compact(hipStream_t st, const Dev &S, float min_dead_fraction, int budget, int64_t *n_compacted,
+                    const Batch &B) {
+    hipLaunchKernelGGL(k_cmp_plan, dim3(1), dim3(1024), 0, st, S, min_dead_fraction, budget, n_compacted);
+    hipLaunchKernelGGL(k_rm_expand, dim3(blocks(S.nlist, 4)), dim3(256), 0, st, S, B.inv, 0);
+    hipLaunchKernelGGL(k_cmp_tail, dim3(blocks(budget)), dim3(256), 0, st, S, B.inv);
+    hipLaunchKernelGGL(k_cmp_holes, dim3(blocks(S.num_slabs)), dim3(256), 0, st, S, B.seg);
+    if (S.storage != 0)
+        hipLaunchKernelGGL(k_rm_move<true>, dim3(blocks(budget)), dim3(256), 0, st, S, budget, B.seg, B.inv, 0);
+    else
+        hipLaunchKernelGGL(k_rm_move<false>, dim3(blocks(budget)), dim3(256), 0, st, S, budget, B.seg, B.inv, 0);
+    hipLaunchKernelGGL(k_rm_finalize, dim3(blocks(S.nlist)), dim3(256), 0, st, S, 0);
 }
 
 void launch_call_end(hipStream_t st, const Dev &S) {

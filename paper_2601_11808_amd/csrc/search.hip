@@ -485,6 +485,8 @@ __device__ __forceinline__ uint32_t key_hi(float v) {
         }                                                                                        \
         const int slab = __shfl(wslab, (pc >> cs_) - wbase);                                     \
         const int slot = pc & cm_;                                                               \
+        /* lazy deletes: a slot whose validity bit is clear holds no entry */                    \
+        const bool live_ = valid && (!S.bits || ((valid_word(S, slab, slot) >> (slot & 63)) & 1ull)); \
         const float4 *xp = S.data + (int64_t)slab * dp4 * C + slot;                              \
         float acc[T];                                                                            \
         _Pragma("unroll") for (int t = 0; t < T; t++) acc[t] = 0.f;                              \
@@ -512,7 +514,7 @@ __device__ __forceinline__ uint32_t key_hi(float v) {
         }                                                                                        \
         const uint32_t id = S.sids[(int64_t)slab * C + slot];                                    \
         _Pragma("unroll") for (int t = 0; t < T; t++) {                                          \
-            if (t < nt) topk_offer(K, t, valid, key_hi<METRIC>(acc[t]), id, buf, skq, kcap);     \
+            if (t < nt) topk_offer(K, t, live_, key_hi<METRIC>(acc[t]), id, buf, skq, kcap);     \
         }                                                                                        \
     }                                                                                            \
     SIVF_ITEM_SLOT(T)                                                                            \
@@ -886,7 +888,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
         acc[3] = mma(a1);
         float vv[16];
         uint32_t pmask = 0;
-        const int lim = p1 - base;   // positions of this step inside the item (64 except at its end)
 #pragma unroll
         for (int rg = 0; rg < 4; rg++) {
             const float xs[4] = {xn4[rg].x, xn4[rg].y, xn4[rg].z, xn4[rg].w};
@@ -899,12 +900,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
             }
         }
         if (!live) pmask = 0;
-        if (lim < 64) {
+        const uint64_t vm = step_valid(S, base, p1, wslab, wbase, cs, cm);   // in range and (lazy deletes) live
+        if (vm != ~0ull) {
 #pragma unroll
             for (int rg = 0; rg < 4; rg++)
 #pragma unroll
                 for (int j = 0; j < 4; j++)
-                    if (16 * rg + 4 * kgrp + j >= lim) pmask &= ~(1u << (4 * rg + j));
+                    if (!((vm >> (16 * rg + 4 * kgrp + j)) & 1ull)) pmask &= ~(1u << (4 * rg + j));
         }
         if (ballot(pmask != 0)) {
             // offsets of this lane's candidates among the 4 lanes of its query
@@ -1188,7 +1190,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
         // distance space (L2: the distance; IP: minus the score): value v and
         // certified half-width e of every (slot, query) pair of this lane
         float vv[16], ee[16];
-        const int lim = p1 - base;   // positions of this step inside the item (64 except at its end)
+        const uint64_t vm = step_valid(S, base, p1, wslab, wbase, cs, cm);   // in range and (lazy deletes) live
 #pragma unroll
         for (int rg = 0; rg < 4; rg++) {
             const float xs[4] = {xn4[rg].x, xn4[rg].y, xn4[rg].z, xn4[rg].w};
@@ -1213,7 +1215,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
             for (int i = 0; i < 16; i++) {
                 float u = vv[i] + ee[i];
                 if (!(u <= __int_as_float(0x7F800000))) u = __int_as_float(0x7F800000);   // NaN: +inf
-                if (16 * (i >> 2) + 4 * kgrp + (i & 3) < lim) {
+                if ((vm >> (16 * (i >> 2) + 4 * kgrp + (i & 3))) & 1ull) {
                     nv++;
                     mn = fminf(mn, u);
                     mx = fmaxf(mx, u);
@@ -1233,7 +1235,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
 #pragma unroll
                 for (int i = 0; i < 16; i++) {
                     const float u = vv[i] + ee[i];
-                    c += (16 * (i >> 2) + 4 * kgrp + (i & 3) < lim && u <= mid) ? 1 : 0;
+                    c += (((vm >> (16 * (i >> 2) + 4 * kgrp + (i & 3))) & 1ull) && u <= mid) ? 1 : 0;
                 }
                 c += __shfl_xor(c, 16);
                 c += __shfl_xor(c, 32);
@@ -1246,12 +1248,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
 #pragma unroll
         for (int i = 0; i < 16; i++) pmask |= (!(vv[i] - ee[i] > thd) ? 1u : 0u) << i;
         if (!live) pmask = 0;
-        if (lim < 64) {
+        if (vm != ~0ull) {
 #pragma unroll
             for (int rg = 0; rg < 4; rg++)
 #pragma unroll
                 for (int j = 0; j < 4; j++)
-                    if (16 * rg + 4 * kgrp + j >= lim) pmask &= ~(1u << (4 * rg + j));
+                    if (!((vm >> (16 * rg + 4 * kgrp + j)) & 1ull)) pmask &= ~(1u << (4 * rg + j));
         }
         if (ballot(pmask != 0)) {
             // queue the passing (position, query) pairs in lane order

@@ -93,9 +93,10 @@ void launch_init_state(hipStream_t st, const Dev &S, const float *centroids) {
     fill(st, (int32_t *)S.att, S.id_capacity, -1);
     fill(st, S.mark, S.id_capacity, -1);
     fill(st, S.len, S.nlist, 0);
-    int32_t *lists[] = {S.l_acnt, S.l_prem, S.l_base, S.l_eoff, S.l_m, S.l_off, S.l_newlen,
-                        S.l_q, S.l_s, S.l_h, S.l_qc, S.l_qcs, S.l_qoff, S.l_snap, S.l_pbase, S.l_ioff};
+    int32_t *lists[] = {S.l_acnt, S.l_prem, S.l_base, S.l_eoff, S.l_m, S.l_off, S.l_newlen, S.l_q, S.l_s,
+                        S.l_h, S.l_qc, S.l_qcs, S.l_qoff, S.l_snap, S.l_pbase, S.l_ioff, S.l_dead};
     for (int32_t *p : lists) fill(st, p, S.nlist, 0);
+    if (S.bits) launch_fill_i64(st, (int64_t *)S.bits, S.num_slabs * S.bw, 0);   // no slot holds an entry
     hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(CTL_WORDS), 0, st, S.ctl, S.num_slabs, S.num_pages);
 }
 

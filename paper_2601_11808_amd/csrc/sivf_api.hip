@@ -26,6 +26,8 @@ constexpr int64_t COARSE_BYTES = 256ll << 20;   // scratch for approximate coars
 
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
+constexpr int NLISTS = 17;   // per-list scratch arrays
+
 int kcap_for(int k) { return k <= 16 ? 16 : (k <= 32 ? 32 : (k <= 64 ? 64 : 128)); }
 
 struct Layout {
@@ -35,7 +37,7 @@ struct Layout {
     size_t cent, cent_h, cn2, cnorm, cmax, data, sids, sowner, sord, free_slabs, free_pages, pages, dir, len, att, mark,
         ctl, lists, b_assign, b_rank, b_rec, b_seg, b_inv, dt, probes, pair_rank, list_pairs, item_list, item_tile,
         item_chunk, partials, hdata, xnorm, rr_dist, rr_lab, dt_s, srv_q, srv_k, srv_np, srv_dist, srv_lab,
-        srv_seg;
+        srv_seg, bits;
 };
 
 bool config_ok(const sivf_config *c) {
@@ -56,6 +58,8 @@ bool config_ok(const sivf_config *c) {
     if (c->max_k < 1 || c->max_k > 128) return false;
     if (c->max_nprobe < 1 || c->max_nprobe > 1024) return false;
     if ((int64_t)c->max_queries * c->max_nprobe >= (1ll << 31) / 64) return false;
+    if (c->delete_mode != SIVF_DELETE_COMPACT && c->delete_mode != SIVF_DELETE_LAZY) return false;
+    if (c->reserved != 0) return false;
     return true;
 }
 
@@ -95,7 +99,7 @@ Layout make_layout(const sivf_config *c) {
     L.att = take((size_t)c->id_capacity * 4);
     L.mark = take((size_t)c->id_capacity * 4);
     L.ctl = take(CTL_WORDS * 4);
-    L.lists = take((size_t)16 * nl * 4);
+    L.lists = take((size_t)NLISTS * nl * 4);
     L.b_assign = take((size_t)c->max_batch * 4);
     L.b_rank = take((size_t)c->max_batch * 4);
     L.b_rec = take((size_t)c->max_batch * 4);
@@ -125,6 +129,8 @@ Layout make_layout(const sivf_config *c) {
     L.srv_dist = take((size_t)c->max_queries * c->max_k * 4);
     L.srv_lab = take((size_t)c->max_queries * c->max_k * 8);
     L.srv_seg = take((size_t)c->max_queries * sizeof(SrvSeg));
+    // lazy deletes: one validity bit per slot, ceil(C / 64) words per slab
+    L.bits = take(c->delete_mode == SIVF_DELETE_LAZY ? (size_t)ns * ((C + 63) / 64) * 8 : 0);
     L.total = cur;
     return L;
 }
@@ -239,7 +245,10 @@ sivf_status do_add(sivf_index *ix, int64_t n, const float *x, const int64_t *ids
     coarse(ix, st, ix->dt, x, n, 1, nullptr, 1, ix->B.assign, 1, 1);
     launch_add_count(st, S, nn, ids, ix->B, fresh_only ? 1 : 0);
     launch_add_admit(st, S);
-    if (!fresh_only) launch_remove(st, S, nn, ids, nullptr, ix->B, 1);   // delete half of an upsert
+    if (!fresh_only) {   // delete half of an upsert
+        if (S.bits) launch_remove_lazy(st, S, nn, ids, nullptr, 1);
+        else launch_remove(st, S, nn, ids, nullptr, ix->B, 1);
+    }
     launch_add_alloc(st, S);
     launch_add_scatter(st, S, nn, x, ids, ix->B);
     launch_add_cleanup(st, S, nn, ids);
@@ -256,7 +265,8 @@ sivf_status do_remove(sivf_index *ix, int64_t n, const int64_t *ids, int64_t *n_
         return launched(ix);
     }
     const int ps = prof_begin(ix, SIVF_PROF_REMOVE, st);
-    launch_remove(st, ix->S, (int)n, ids, n_removed, ix->B, 0);
+    if (ix->S.bits) launch_remove_lazy(st, ix->S, (int)n, ids, n_removed, 0);
+    else launch_remove(st, ix->S, (int)n, ids, n_removed, ix->B, 0);
     launch_call_end(st, ix->S);
     prof_end(ix, SIVF_PROF_REMOVE, ps, st);
     return launched(ix);
@@ -362,9 +372,11 @@ sivf_status sivf_create(const sivf_config *cfg, const float *centroids, void *wo
     S.mark = (int32_t *)(w + L.mark);
     S.ctl = (int32_t *)(w + L.ctl);
     int32_t *lists = (int32_t *)(w + L.lists);
-    int32_t **lp[] = {&S.l_acnt, &S.l_prem, &S.l_base, &S.l_eoff, &S.l_m, &S.l_off, &S.l_newlen,
-                      &S.l_q, &S.l_s, &S.l_h, &S.l_qc, &S.l_qcs, &S.l_qoff, &S.l_snap, &S.l_pbase, &S.l_ioff};
-    for (int i = 0; i < 16; i++) *lp[i] = lists + (size_t)i * cfg->nlist;
+    int32_t **lp[NLISTS] = {&S.l_acnt, &S.l_prem, &S.l_base, &S.l_eoff, &S.l_m, &S.l_off, &S.l_newlen, &S.l_q, &S.l_s,
+                            &S.l_h, &S.l_qc, &S.l_qcs, &S.l_qoff, &S.l_snap, &S.l_pbase, &S.l_ioff, &S.l_dead};
+    for (int i = 0; i < NLISTS; i++) *lp[i] = lists + (size_t)i * cfg->nlist;
+    S.bw = (cfg->slab_capacity + 63) / 64;
+    S.bits = cfg->delete_mode == SIVF_DELETE_LAZY ? (uint64_t *)(w + L.bits) : nullptr;
     ix->B.assign = (int32_t *)(w + L.b_assign);
     ix->B.rank = (int32_t *)(w + L.b_rank);
     ix->B.rec = (uint32_t *)(w + L.b_rec);
@@ -600,6 +612,20 @@ sivf_status sivf_step(sivf_index *ix, const sivf_step_args *a, void *stream) {
     return enqueue_step(ix, a, st);
 }
 
+sivf_status sivf_compact(sivf_index *ix, float min_dead_fraction, int64_t *n_compacted, void *stream) {
+    if (!ix || !(min_dead_fraction >= 0.f && min_dead_fraction <= 1.f)) return SIVF_ERR_ARG;
+    if (ix->broken) return SIVF_ERR_STATE;
+    hipStream_t st = as_stream(stream);
+    ix->last = st;
+    if (!ix->S.bits) {
+        if (n_compacted) launch_fill_i64(st, n_compacted, 1, 0);
+        return launched(ix);
+    }
+    launch_compact(st, ix->S, min_dead_fraction, ix->cfg.max_batch, n_compacted, ix->B);
+    launch_call_end(st, ix->S);
+    return launched(ix);
+}
+
 sivf_status sivf_assign(sivf_index *ix, int64_t n, const float *x, int32_t *lists, void *stream) {
     if (!ix || n < 0 || (n > 0 && (!x || !lists))) return SIVF_ERR_ARG;
     if (ix->broken) return SIVF_ERR_STATE;
@@ -710,28 +736,37 @@ sivf_status sivf_sync(sivf_index *ix, sivf_status *device_status) {
     return SIVF_OK;
 }
 
-static sivf_status read_counts(sivf_index *ix, std::vector<int32_t> &len, int32_t *ctl) {
+static sivf_status read_counts(sivf_index *ix, std::vector<int32_t> &len, int32_t *ctl,
+                               std::vector<int32_t> *dead = nullptr) {
     len.resize(ix->cfg.nlist);
     if (!dev_ok(hipStreamSynchronize(ix->last))) return SIVF_ERR_DEVICE;
     if (!dev_ok(hipMemcpy(len.data(), ix->S.len, sizeof(int32_t) * len.size(), hipMemcpyDeviceToHost)))
         return SIVF_ERR_DEVICE;
+    if (dead) {
+        dead->assign(ix->cfg.nlist, 0);
+        if (ix->S.bits &&
+            !dev_ok(hipMemcpy(dead->data(), ix->S.l_dead, sizeof(int32_t) * dead->size(), hipMemcpyDeviceToHost)))
+            return SIVF_ERR_DEVICE;
+    }
     if (!dev_ok(hipMemcpy(ctl, ix->S.ctl, sizeof(int32_t) * CTL_WORDS, hipMemcpyDeviceToHost))) return SIVF_ERR_DEVICE;
     return SIVF_OK;
 }
 
 sivf_status sivf_dump_info_get(sivf_index *ix, sivf_dump_info *info) {
     if (!ix || !info) return SIVF_ERR_ARG;
-    std::vector<int32_t> len;
+    std::vector<int32_t> len, dead;
     int32_t ctl[CTL_WORDS];
-    sivf_status s = read_counts(ix, len, ctl);
+    sivf_status s = read_counts(ix, len, ctl, &dead);
     if (s != SIVF_OK) return s;
-    int64_t live = 0, used = 0;
+    int64_t pos = 0, nd = 0, used = 0;
     const int C = ix->cfg.slab_capacity;
-    for (int32_t v : len) {
-        live += v;
-        used += (v + C - 1) / C;
+    for (int l = 0; l < ix->cfg.nlist; l++) {
+        pos += len[l];
+        nd += dead[l];
+        used += (len[l] + C - 1) / C;
     }
-    info->live = live;
+    info->live = pos - nd;
+    info->positions = pos;
     info->used_slabs = used;
     info->free_slabs = ctl[CTL_SLAB_TOP];
     info->num_slabs = ix->cfg.num_slabs;
@@ -768,9 +803,14 @@ sivf_status sivf_dump(sivf_index *ix, int32_t *list_len, int32_t *list_slabs, in
         std::vector<uint32_t> sids;
         if (!d2h(dir.data(), S.dir, dir.size() * 4) || !d2h(pages.data(), S.pages, pages.size() * 4))
             return SIVF_ERR_DEVICE;
+        std::vector<uint64_t> bits;
         if (ids_by_list) {
             sids.resize((size_t)c.num_slabs * C);
             if (!d2h(sids.data(), S.sids, sids.size() * 4)) return SIVF_ERR_DEVICE;
+            if (S.bits) {
+                bits.resize((size_t)c.num_slabs * S.bw);
+                if (!d2h(bits.data(), S.bits, bits.size() * 8)) return SIVF_ERR_DEVICE;
+            }
         }
         int64_t so = 0, io = 0;
         for (int l = 0; l < c.nlist; l++) {
@@ -785,7 +825,8 @@ sivf_status sivf_dump(sivf_index *ix, int32_t *list_len, int32_t *list_slabs, in
                     const int cnt = (o == ns - 1) ? len[l] - o * C : C;
                     for (int t = 0; t < cnt; t++) {
                         const uint32_t v = sids[(size_t)slab * C + t];
-                        ids_by_list[io++] = v == INVALID ? -1 : (int64_t)v;
+                        const bool dead = S.bits && !((bits[(size_t)slab * S.bw + (t >> 6)] >> (t & 63)) & 1ull);
+                        ids_by_list[io++] = (v == INVALID || dead) ? -1 : (int64_t)v;
                     }
                 }
             }
@@ -1030,7 +1071,10 @@ sivf_status sivf_server_remove(sivf_server *s, int64_t n, const int64_t *ids, in
     server_reap(s);
     sivf_status st = server_dispatch(s);   // earlier searches go first
     if (st != SIVF_OK) return st;
-    if (s->any_search && !dev_ok(hipStreamWaitEvent(s->s_mut, s->last_search, 0))) return SIVF_ERR_DEVICE;
+    // a compacting delete moves entries that earlier searches may still read;
+    // a lazy delete only clears validity bits and overlaps them
+    if (!ix->S.bits && s->any_search && !dev_ok(hipStreamWaitEvent(s->s_mut, s->last_search, 0)))
+        return SIVF_ERR_DEVICE;
     if (!server_inputs(s, input_stream, s->s_mut)) return SIVF_ERR_DEVICE;
     st = do_remove(ix, n, ids, n_removed, s->s_mut);
     if (st != SIVF_OK) return st;
@@ -1163,16 +1207,18 @@ bool same_shape(const sivf_config &a, const sivf_config &b) {
 sivf_status sivf_save(sivf_index *ix, const char *path) {
     if (!ix || !path) return SIVF_ERR_ARG;
     if (ix->broken) return SIVF_ERR_STATE;
-    std::vector<int32_t> len;
+    std::vector<int32_t> len, dead;
     int32_t ctl[CTL_WORDS];
-    sivf_status s = read_counts(ix, len, ctl);
+    sivf_status s = read_counts(ix, len, ctl, &dead);
     if (s != SIVF_OK) return s;
     const sivf_config &c = ix->cfg;
-    std::vector<int32_t> off(c.nlist);
-    int64_t live = 0;
+    std::vector<int32_t> off(c.nlist), live_len(c.nlist);
+    int64_t positions = 0, live = 0;
     for (int l = 0; l < c.nlist; l++) {
-        off[l] = (int32_t)live;
-        live += len[l];
+        off[l] = (int32_t)positions;
+        positions += len[l];
+        live_len[l] = len[l] - dead[l];   // lazily deleted slots are not saved
+        live += live_len[l];
     }
     FILE *f = fopen(path, "wb");
     if (!f) return SIVF_ERR_ARG;
@@ -1192,24 +1238,40 @@ sivf_status sivf_save(sivf_index *ix, const char *path) {
     if (!dev_ok(hipMemcpy(cent.data(), ix->S.cent, cent.size() * 4, hipMemcpyDeviceToHost))) return SIVF_ERR_DEVICE;
     for (int l = 0; l < c.nlist; l++)
         if (!write_all(f, cent.data() + (size_t)l * dpad, (size_t)c.dim * 4)) return SIVF_ERR_ARG;
-    if (!write_all(f, len.data(), (size_t)c.nlist * 4)) return SIVF_ERR_ARG;
+    if (!write_all(f, live_len.data(), (size_t)c.nlist * 4)) return SIVF_ERR_ARG;
     // list offsets into the (idle) per-list scratch of removes, rows and ids into the insert coarse scratch
     hipStream_t st = ix->last;
     if (!dev_ok(hipMemcpy(ix->S.l_off, off.data(), (size_t)c.nlist * 4, hipMemcpyHostToDevice))) return SIVF_ERR_DEVICE;
     float *rows_d = ix->dt;
     uint32_t *ids_d = (uint32_t *)(rows_d + (size_t)rec * c.dim);
-    std::vector<float> rows((size_t)rec * c.dim);
-    std::vector<uint32_t> ids((size_t)rec);
-    for (int64_t e0 = 0; e0 < live; e0 += rec) {
-        const int n = (int)(live - e0 < rec ? live - e0 : rec);
+    std::vector<float> rows((size_t)rec * c.dim), orows((size_t)rec * c.dim);
+    std::vector<uint32_t> ids((size_t)rec), oids((size_t)rec);
+    int64_t nout = 0, written = 0;   // live entries waiting in orows / oids, and those already written
+    auto flush = [&](bool all) {
+        while (nout == rec || (all && nout > 0)) {
+            if (!write_all(f, oids.data(), (size_t)nout * 4) || !write_all(f, orows.data(), (size_t)nout * c.dim * 4))
+                return false;
+            written += nout;
+            nout = 0;
+        }
+        return true;
+    };
+    for (int64_t e0 = 0; e0 < positions; e0 += rec) {
+        const int n = (int)(positions - e0 < rec ? positions - e0 : rec);
         launch_pack(st, ix->S, ix->S.l_off, e0, n, rows_d, ids_d);
         if (!dev_ok(hipGetLastError()) || !dev_ok(hipStreamSynchronize(st))) return SIVF_ERR_DEVICE;
         if (!dev_ok(hipMemcpy(ids.data(), ids_d, (size_t)n * 4, hipMemcpyDeviceToHost)) ||
             !dev_ok(hipMemcpy(rows.data(), rows_d, (size_t)n * c.dim * 4, hipMemcpyDeviceToHost)))
             return SIVF_ERR_DEVICE;
-        if (!write_all(f, ids.data(), (size_t)n * 4) || !write_all(f, rows.data(), (size_t)n * c.dim * 4))
-            return SIVF_ERR_ARG;
+        for (int i = 0; i < n; i++) {
+            if (ids[i] == INVALID) continue;   // a dead slot
+            oids[nout] = ids[i];
+            memcpy(orows.data() + (size_t)nout * c.dim, rows.data() + (size_t)i * c.dim, (size_t)c.dim * 4);
+            nout++;
+            if (!flush(false)) return SIVF_ERR_ARG;
+        }
     }
+    if (!flush(true) || written != live) return written != live ? SIVF_ERR_STATE : SIVF_ERR_ARG;
     if (fflush(f) != 0) return SIVF_ERR_ARG;
     return SIVF_OK;
 }
@@ -1456,7 +1518,8 @@ sivf_status sivf_registry_remove(sivf_registry *r, int64_t n, const int64_t *ext
     }
     launch_reg_lookup(st, r->R, (int)n, ext_ids, r->slot, r->internal);
     // unmapped keys carry internal id -1, which the remove skips
-    launch_remove(st, ix->S, (int)n, r->internal, n_removed, ix->B, 2);
+    if (ix->S.bits) launch_remove_lazy(st, ix->S, (int)n, r->internal, n_removed, 2);
+    else launch_remove(st, ix->S, (int)n, r->internal, n_removed, ix->B, 2);
     launch_call_end(st, ix->S);
     launch_reg_release(st, r->R, ix->S, (int)n, ext_ids, r->slot, r->ctl);
     return launched(ix);

@@ -73,7 +73,34 @@ struct Dev {
     int32_t *l_snap;   // search: list lengths when the search was planned (it scans only these)
     int32_t *l_pbase;  // search: first partial-result slot of the list's (pair, chunk) results
     int32_t *l_ioff;   // search: first work item of the list
+    int32_t *l_dead;   // lazy deletes: dead slots of each list below its length
+    // Lazy deletes (NULL with compacting deletes): validity bit of every slot,
+    // bw = ceil(C / 64) words per slab; bit s % 64 of word s / 64 is slot s.
+    uint64_t *bits;
+    int bw;
 };
+
+// Validity word of slot `slot` of `slab` (lazy deletes), read with an atomic
+// load at agent scope: a delete running on another XCD at the same time is
+// seen as soon as its atomic AND is, not from a stale cached line.
+__device__ __forceinline__ uint64_t valid_word(const Dev &S, int64_t slab, int slot) {
+    return __hip_atomic_load(S.bits + slab * S.bw + (slot >> 6), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Validity of the 64 positions base .. base + 63 of a scan step (bit j:
+// position base + j is below p1 and, with lazy deletes, live).  wslab/wbase:
+// lane j holds the slab of ordinal wbase + j.  Every lane must call it.
+__device__ __forceinline__ uint64_t step_valid(const Dev &S, int base, int p1, int wslab, int wbase, int cs, int cm) {
+    const int lim = p1 - base;
+    const uint64_t inr = lim >= 64 ? ~0ull : ((1ull << (lim > 0 ? lim : 0)) - 1);
+    if (!S.bits) return inr;
+    const int p = base + (int)__lane_id();
+    const int pc = p < p1 ? p : p1 - 1;
+    const int slab = __shfl(wslab, (pc >> cs) - wbase);
+    const int slot = pc & cm;
+    const bool ok = p < p1 && ((valid_word(S, slab, slot) >> (slot & 63)) & 1ull);
+    return __ballot(ok);
+}
 
 __device__ __forceinline__ int slab_of(const Dev &S, int l, int ord) {
     int page = S.dir[(int64_t)l * S.dir_cap + ord / PAGE];
@@ -162,6 +189,44 @@ __device__ __forceinline__ int wave_agg_inc(int32_t *counters, int key, bool act
         act &= ~grp;
     }
     return result;
+}
+
+// Block-aggregated form of wave_agg_inc, one key per thread of a block of NT
+// threads: the block counts in an LDS histogram (hist, nkeys entries) first,
+// then each key present reserves its range with one device atomic, so a wave
+// whose lanes hit many different keys does not wait on one returning atomic
+// per key.  Returns each active thread's distinct old value (0 when
+// want_rank is false: the counts are only added).  Every thread of the block
+// must call it.
+template <int NT>
+__device__ __forceinline__ int block_agg_inc(int32_t *counters, int key, bool active, int32_t *hist, int nkeys,
+                                             bool want_rank) {
+    const int tid = threadIdx.x;
+    __syncthreads();   // a previous call's readers are done with hist
+    for (int k = tid; k < nkeys; k += NT) hist[k] = 0;
+    __syncthreads();
+    const int local = active ? atomicAdd(&hist[key], 1) : 0;
+    __syncthreads();
+    for (int k = tid; k < nkeys; k += NT) {
+        const int c = hist[k];
+        if (c > 0) {
+            if (want_rank)
+                hist[k] = atomicAdd(&counters[k], c);
+            else
+                atomicAdd(&counters[k], c);
+        }
+    }
+    __syncthreads();
+    return (active && want_rank) ? hist[key] + local : 0;
+}
+
+// Per-list counters of a mutation kernel: LDS histogram when it fits (BLK),
+// else wave aggregation.
+template <bool BLK>
+__device__ __forceinline__ int list_agg_inc(int32_t *counters, int key, bool active, int32_t *hist, int nkeys,
+                                            bool want_rank) {
+    if (BLK) return block_agg_inc<256>(counters, key, active, hist, nkeys, want_rank);
+    return wave_agg_inc(counters, key, active);
 }
 
 // Record the first data-dependent error of a call and stop its later kernels.

@@ -30,7 +30,8 @@ void launch_coarse_select(hipStream_t st, const float *dt, const float *X, int n
 
 // ---- mutation (mutate.hip)
 struct Batch {
-    int32_t *assign, *rank, *seg, *inv;   // inv: source row of each new entry, entry-major
+    int32_t *assign, *rank, *seg, *inv;   // inv: source row of each new entry, entry-major (adds);
+                                          // the list of each tail-window entry (removes)
     uint32_t *rec;
 };
 void launch_add_prepare(hipStream_t st, const Dev &S, int n, const int64_t *ids);
@@ -46,6 +47,12 @@ void launch_add_cleanup(hipStream_t st, const Dev &S, int n, const int64_t *ids)
 void launch_remove(hipStream_t st, const Dev &S, int n, const int64_t *ids, int64_t *n_removed,
                    const Batch &B, int mode);
 void launch_call_end(hipStream_t st, const Dev &S);
+// lazy deletes: clear validity bits (mode 0: a remove call, ids validated;
+// mode 1: the delete half of an upsert; mode 2: ids outside the range skipped)
+void launch_remove_lazy(hipStream_t st, const Dev &S, int n, const int64_t *ids, int64_t *n_removed, int mode);
+// compaction of lazily deleted slots: at most `budget` dead slots per call
+void launch_compact(hipStream_t st, const Dev &S, float min_dead_fraction, int budget, int64_t *n_compacted,
+                    const Batch &B);
 void launch_get_rows(hipStream_t st, const Dev &S, int n, const int64_t *ids, float *rows);
 // checkpoint: entries [e0, e0 + n) in list order (off = per-list first entry) -> rows and ids
 void launch_pack(hipStream_t st, const Dev &S, const int32_t *off, int64_t e0, int n, float *rows, uint32_t *ids);

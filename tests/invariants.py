@@ -15,7 +15,9 @@ import numpy as np
 INVALID = 0xFFFFFFFF
 
 
-def check_dump(d, C, num_slabs):
+def check_dump(d, C, num_slabs, lazy=False):
+    """lazy: slots deleted lazily (not yet compacted) read -1 inside the lists;
+    the address table must not point at them."""
     ln = d["list_len"].astype(np.int64)
     assert (ln >= 0).all()
     ns = (ln + C - 1) // C
@@ -33,17 +35,22 @@ def check_dump(d, C, num_slabs):
     assert (owner[slabs] == lst).all(), "slab owner mismatch"
     assert (ordn[slabs] == ordinal).all(), "slab ordinal mismatch"
     assert (owner[free] == -1).all(), "free slab still owned"
-    ids = d["ids_by_list"]
-    assert ids.shape[0] == ln.sum()
-    assert (ids >= 0).all(), "tombstone inside a live range"
+    ids_all = d["ids_by_list"]
+    assert ids_all.shape[0] == ln.sum()
+    live = ids_all >= 0
+    if not lazy:
+        assert live.all(), "tombstone inside a live range"
+    if "info" in d:
+        assert d["info"]["live"] == int(live.sum()), "live count != live slots"
+    ids = ids_all[live]
     assert np.unique(ids).shape[0] == ids.shape[0], "an id is stored twice"
     att = d["att"]
     valid = att != INVALID
     assert valid.sum() == ids.shape[0], "address table size != live"
     assert valid[ids].all(), "live id missing from the address table"
     # expected slot of each live entry
-    pos = np.arange(ids.shape[0]) - np.repeat(np.cumsum(ln) - ln, ln)
-    list_of_entry = np.repeat(np.arange(ln.shape[0]), ln)
+    pos = (np.arange(ids_all.shape[0]) - np.repeat(np.cumsum(ln) - ln, ln))[live]
+    list_of_entry = np.repeat(np.arange(ln.shape[0]), ln)[live]
     slab_base = np.cumsum(ns) - ns
     slab_of_entry = slabs[slab_base[list_of_entry] + pos // C]
     want = slab_of_entry * C + pos % C
@@ -52,9 +59,16 @@ def check_dump(d, C, num_slabs):
 
 
 def membership_of(d):
+    """{list: sorted live ids} of the non-empty lists (lazily deleted slots, -1, dropped)."""
     ln = d["list_len"].astype(np.int64)
     offs = np.concatenate([[0], np.cumsum(ln)])
-    return {l: np.sort(d["ids_by_list"][offs[l]:offs[l + 1]]) for l in range(ln.shape[0]) if ln[l] > 0}
+    out = {}
+    for l in range(ln.shape[0]):
+        v = d["ids_by_list"][offs[l]:offs[l + 1]]
+        v = v[v >= 0]
+        if v.shape[0]:
+            out[l] = np.sort(v)
+    return out
 
 
 def same_membership(a, b):

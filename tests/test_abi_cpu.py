@@ -38,9 +38,9 @@ def test_every_declared_symbol_is_exported(lib):
 
 def test_struct_layouts_match_header():
     # sizes follow from the field lists in include/sivf.h (natural alignment)
-    assert ct.sizeof(sivf.SivfConfig) == 6 * 4 + 2 * 8 + 4 * 4
+    assert ct.sizeof(sivf.SivfConfig) == 6 * 4 + 2 * 8 + 6 * 4
     assert ct.sizeof(sivf.SivfStepArgs) == 8 + 8 + 8 + 8 + 8 + 4 + 4 + 8 + 8 + 8 + 8 + 8 + 8 + 8
-    assert ct.sizeof(sivf.SivfDumpInfo) == 5 * 8 + 2 * 4
+    assert ct.sizeof(sivf.SivfDumpInfo) == 5 * 8 + 2 * 4 + 8
 
 
 def _cfg(**kw):
@@ -113,3 +113,17 @@ def test_dump_validator_rejects_corruption(corrupt):
         d["att"][9] = 3
     with pytest.raises(AssertionError):
         check_dump(d, C, ns)
+
+
+def test_dump_validator_lazy_slots():
+    """With lazy deletes a dead slot reads -1 inside its list: accepted only in
+    lazy mode, and only if the address table no longer points there."""
+    d, C, ns = _good_dump()
+    d["ids_by_list"][1] = -1           # id 7 deleted lazily: its slot stays in list 0
+    d["att"][7] = 0xFFFFFFFF
+    assert check_dump(d, C, ns, lazy=True)
+    with pytest.raises(AssertionError):
+        check_dump(d, C, ns)
+    d["att"][7] = 9                    # ... but still reachable through the address table
+    with pytest.raises(AssertionError):
+        check_dump(d, C, ns, lazy=True)
