@@ -857,6 +857,7 @@ def serve_main(a):
     done_t = np.zeros(len(reqs))
     sub_t = np.zeros(len(reqs))
     refused, refused_at = 0, -1
+    refused_s, refused_s_at = 0, -1
     i = 0
     start = time.perf_counter() + 0.05
     while True:
@@ -876,7 +877,12 @@ def serve_main(a):
                 queues["mut"].append((i, t))
             else:
                 t, _, _ = srv.search(pl[0], k, r.nprobe)
-                queues["search"].append((i, t))
+                if t is None:           # search slots full: retry once something completes
+                    if refused_s_at != i:
+                        refused_s += 1
+                        refused_s_at = i
+                else:
+                    queues["search"].append((i, t))
             if t is not None:
                 sub_t[i] = time.perf_counter() - start
                 i += 1
@@ -889,6 +895,7 @@ def serve_main(a):
         if i == len(reqs) and all(heads[kq] == len(queues[kq]) for kq in queues):
             break
     end = time.perf_counter() - start
+    nb_launch, nb_req = srv.batches()
     srv.close()
     assert ix.sync() == 0
     prof = ix.profile_read()
@@ -937,6 +944,8 @@ def serve_main(a):
         "insert_vec_per_s": round(n_ins / end, 1), "delete_ids_per_s": round(n_del / end, 1),
         "search_queries_per_s": round(nq_tot / end, 1),
         "inserts_refused_then_retried": refused,
+        "searches_refused_then_retried": refused_s,
+        "search_batches": {"launches": nb_launch, "requests": nb_req},
         # device time per request class (HIP events on the server's streams; searches and inserts overlap,
         # so the sums can exceed the wall time)
         "device_ms_mean": {kk: round(v[0] / max(v[1], 1), 3) for kk, v in prof.items()},

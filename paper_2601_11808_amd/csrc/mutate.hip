@@ -182,12 +182,20 @@ __global__ __launch_bounds__(256) void k_add_alloc(Dev S) {
 // Entry order of the new entries: entry l_eoff[l] + rank is list l's rank-th
 // new position; inv[entry] = its source row.
 __global__ __launch_bounds__(256) void k_add_inv(Dev S, int n, const int32_t *__restrict__ assign,
-                                                 const int32_t *__restrict__ rank, int32_t *__restrict__ inv) {
+                                                 const int32_t *__restrict__ rank, int32_t *__restrict__ inv,
+                                                 uint32_t *__restrict__ dstg) {
     if (call_failed(S.ctl)) return;
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
     const int r = rank[i];
-    if (r >= 0) inv[S.l_eoff[assign[i]] + r] = i;
+    if (r < 0) return;
+    // the entry's destination slot, resolved here (many rows in flight) so
+    // that the copy kernel starts from two independent loads
+    const int l = assign[i];
+    const int e = S.l_eoff[l] + r;
+    const int pos = S.l_base[l] + r;
+    inv[e] = i;
+    dstg[e] = (uint32_t)slab_of(S, l, pos / S.C) * (uint32_t)S.C + (uint32_t)(pos % S.C);
 }
 
 // One lane per new entry, in entry order: consecutive lanes fill consecutive
@@ -266,9 +274,8 @@ constexpr int SENT = 32;
 
 __global__ __launch_bounds__(64) void k_add_scatter_lds(Dev S, const float *__restrict__ x,
                                                          const int64_t *__restrict__ ids,
-                                                         const int32_t *__restrict__ assign,
-                                                         const int32_t *__restrict__ rank,
-                                                         const int32_t *__restrict__ inv) {
+                                                         const int32_t *__restrict__ inv,
+                                                         const uint32_t *__restrict__ dstg) {
     extern __shared__ __align__(16) float4 srow[];   // [SENT][dp4 + 1]
     if (call_failed(S.ctl)) return;
     const int lane = threadIdx.x;
@@ -281,10 +288,9 @@ __global__ __launch_bounds__(64) void k_add_scatter_lds(Dev S, const float *__re
     int i = 0, slab = 0, slot = 0;
     if (lane < cnt) {
         i = inv[e0 + lane];
-        const int l = assign[i];
-        const int pos = S.l_base[l] + rank[i];
-        slab = slab_of(S, l, pos / S.C);
-        slot = pos % S.C;
+        const uint32_t g = dstg[e0 + lane];
+        slab = (int)(g / (uint32_t)S.C);
+        slot = (int)(g % (uint32_t)S.C);
     }
     // rows into LDS: up to 16 chunks per lane in flight (all of a 128-dim batch)
     const int tot = cnt * dp4;
@@ -749,11 +755,12 @@ void launch_add_alloc(hipStream_t st, const Dev &S) {
 }
 
 void launch_add_scatter(hipStream_t st, const Dev &S, int n, const float *x, const int64_t *ids, const Batch &B) {
-    hipLaunchKernelGGL(k_add_inv, dim3(blocks(n)), dim3(256), 0, st, S, n, B.assign, B.rank, B.inv);
+    // B.rec (free during an add once its upsert deletes are done) takes each entry's destination slot
+    hipLaunchKernelGGL(k_add_inv, dim3(blocks(n)), dim3(256), 0, st, S, n, B.assign, B.rank, B.inv, B.rec);
     const bool vec = (S.d % 4 == 0) && (((uintptr_t)x & 15) == 0);
     if (vec && S.dp4 <= 64)
         hipLaunchKernelGGL(k_add_scatter_lds, dim3(blocks(n, SENT)), dim3(64),
-                           (size_t)SENT * (S.dp4 + 1) * sizeof(float4), st, S, x, ids, B.assign, B.rank, B.inv);
+                           (size_t)SENT * (S.dp4 + 1) * sizeof(float4), st, S, x, ids, B.inv, B.rec);
     else if (vec)
         hipLaunchKernelGGL(k_add_scatter<true>, dim3(blocks(n)), dim3(256), 0, st, S, x, ids, B.assign, B.rank,
                            B.inv);
