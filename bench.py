@@ -64,17 +64,27 @@ def fp32_scan_roofline(evals, d, scan_ms, tile, traffic=None):
     because packed FP32 is off, and is reported against the FP32 VALU peak on
     its 3d flops per evaluation.  The matrix-core accounting of the certified
     scan (2 * 4 * ceil(d / 4) flops per evaluation against the FP32 MFMA peak)
-    is kept beside it."""
+    is kept beside it.  Where consecutive tiles of one list re-read its chunk
+    from L2 / MALL (many queries on few long lists), the per-tile byte count
+    exceeds what HBM can deliver in the measured time: the scan is then
+    reported against the matrix-core peak, with the HBM model beside it."""
     exact_tf = evals * 3.0 * d / (scan_ms * 1e-3) / 1e12
     if tile == 16:
         per_eval = (4.0 * d + 4.0) / tile
         gbps = evals * per_eval / (scan_ms * 1e-3) / 1e9
         tf = evals * 2.0 * 4 * ((d + 3) // 4) / (scan_ms * 1e-3) / 1e12
-        roof = {"bound": "hbm", "kernel": "k_scan_cert", "achieved": round(gbps, 1), "peak": HBM_PEAK_GBPS,
-                "unit": "GB/s", "frac": round(gbps / HBM_PEAK_GBPS, 4),
-                "bytes_per_eval": per_eval, "algorithmic_bytes_per_launch": int(evals * per_eval),
-                "mfma": {"achieved_tflops": round(tf, 3), "peak_tflops": MFMA32_PEAK_TFLOPS,
-                         "frac": round(tf / MFMA32_PEAK_TFLOPS, 4), "flops_per_eval": 2 * 4 * ((d + 3) // 4)}}
+        hbm = {"bound": "hbm", "kernel": "k_scan_cert", "achieved": round(gbps, 1), "peak": HBM_PEAK_GBPS,
+               "unit": "GB/s", "frac": round(gbps / HBM_PEAK_GBPS, 4),
+               "bytes_per_eval": per_eval, "algorithmic_bytes_per_launch": int(evals * per_eval)}
+        mf = {"achieved_tflops": round(tf, 3), "peak_tflops": MFMA32_PEAK_TFLOPS,
+              "frac": round(tf / MFMA32_PEAK_TFLOPS, 4), "flops_per_eval": 2 * 4 * ((d + 3) // 4)}
+        if gbps <= HBM_PEAK_GBPS:
+            roof = dict(hbm, mfma=mf)
+        else:
+            roof = {"bound": "mfma", "kernel": "k_scan_cert", "achieved": mf["achieved_tflops"],
+                    "peak": MFMA32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": mf["frac"],
+                    "flops_per_eval": mf["flops_per_eval"],
+                    "hbm_model": dict(hbm, note="per-tile chunk reads exceed HBM peak: served from L2/MALL")}
     else:
         roof = {"bound": "alu", "kernel": "k_scan_sq", "achieved": round(exact_tf, 3),
                 "peak": round(ALU_PEAK_TFLOPS, 2), "unit": "TFLOP/s", "frac": round(exact_tf / ALU_PEAK_TFLOPS, 4),
@@ -667,9 +677,13 @@ def batched_main(a):
     kpq_d = torch.from_numpy(kpq).to(dev)
     npq_d = torch.from_numpy(npq).to(dev)
     t0 = time.perf_counter()
-    tile, sh, pers = ix.tune_search(qd, kmax, int(npq.max()), k_per_query=kpq_d, nprobe_per_query=npq_d)
-    log(f"[batched] autotuner: {tile} queries x 2^{sh} positions per work item, persistent={pers} "
-        f"({time.perf_counter() - t0:.1f} s)")
+    if a.schedule:
+        tile, sh, pers = (int(v) for v in a.schedule.split(","))
+        ix.set_search_schedule(tile, sh, pers)
+    else:
+        tile, sh, pers = ix.tune_search(qd, kmax, int(npq.max()), k_per_query=kpq_d, nprobe_per_query=npq_d)
+    log(f"[batched] schedule: {tile} queries x 2^{sh} positions per work item, persistent={pers} "
+        f"({'given' if a.schedule else 'autotuned'}, {time.perf_counter() - t0:.1f} s)")
     # per step: B fresh vectors in, B uniformly random live ids out
     rng = np.random.default_rng([w.seed, 3, 1])
     live = np.arange(N, dtype=np.int64)
@@ -734,8 +748,20 @@ def batched_main(a):
     probes = ix.probe(qd, np_max).cpu().numpy()
     probes = np.where(np.arange(np_max)[None, :] < npq[:, None], probes, -1)
     lens = ix.dump()["list_len"].astype(np.int64)
-    evals = int(lens[probes[probes >= 0]].sum())
+    ev_q = np.where(probes >= 0, lens[np.maximum(probes, 0)], 0).sum(axis=1)   # evaluations per query
+    evals = int(ev_q.sum())
     scan_ms = prof["scan"][0] / max(prof["scan"][1], 1)
+    deep_ms = prof["scan_deep"][0] / max(prof["scan_deep"][1], 1)
+    deep_sched = ix.search_schedule()[1]
+    if prof["scan_deep"][1] > 0:
+        # two passes: k <= 64 on the certified scan, k > 64 on the deep schedule
+        ev_s, ev_d = int(ev_q[kpq <= 64].sum()), int(ev_q[kpq > 64].sum())
+        passes = [dict(fp32_scan_roofline(ev_s, w.dim, scan_ms, tile), queries="k <= 64"),
+                  dict(fp32_scan_roofline(ev_d, w.dim, deep_ms, deep_sched[0]), queries="k > 64")]
+        roof = dict(passes[0] if scan_ms >= deep_ms else passes[1])
+        roof["passes"] = passes
+    else:
+        roof = fp32_scan_roofline(evals, w.dim, scan_ms, tile)
     sm, gsm = np.sort(np.array(step_ms)), np.sort(np.array(gsteps))
     se_ms = prof["search"][0] / max(prof["search"][1], 1)
     res = {
@@ -747,7 +773,9 @@ def batched_main(a):
         "config": {"workload": f"batched: N={N}, d={w.dim}, Zipf(1.1) over {w.nlist} clusters, nlist={w.nlist}, "
                                f"slab={C}, {nq} queries, nprobe U[8,128], k in {{1,10,100}}, +{B}/-{B} random",
                    "parallelism": "single GPU"},
-        "schedule": {"tile": tile, "chunk_positions": 1 << sh, "persistent_waves": bool(pers)},
+        "schedule": {"tile": tile, "chunk_positions": 1 << sh, "persistent_waves": bool(pers),
+                     "deep_pass": {"tile": deep_sched[0], "chunk_positions": 1 << deep_sched[1],
+                                   "persistent_waves": bool(deep_sched[2])}},
         "recall_at_10_k_ge_10": round(rec, 4),
         "search_qps": round(nq / (se_ms * 1e-3), 1),
         "p50_step_ms": round(float(np.percentile(sm, 50)), 3), "p99_step_ms": round(float(np.percentile(sm, 99)), 3),
@@ -755,7 +783,7 @@ def batched_main(a):
         "graph_p99_step_ms": round(float(np.percentile(gsm, 99)), 3),
         "device_ms": {kk: round(v[0] / max(v[1], 1), 4) for kk, v in prof.items()},
         "list_len": {"min": int(lens.min()), "median": int(np.median(lens)), "max": int(lens.max())},
-        "roofline": fp32_scan_roofline(evals, w.dim, scan_ms, tile),
+        "roofline": roof,
         "bulk_load_vec_per_s": round(N / load_s, 1),
     }
     print(json.dumps(res), flush=True)

@@ -151,13 +151,15 @@ sivf_status sivf_search(sivf_index *ix, int64_t nq, const float *q, int32_t k,
 /* Search schedule autotuner (for uneven batches: skewed list lengths,
  * per-query nprobe and k).  Runs sivf_search on this sample batch once per
  * candidate schedule -- queries per work item (fp32 storage: 8 and 4, and
- * 16 where the certified matrix-core scan applies: dim <= 256, max_k <= 64,
+ * 16 where the certified matrix-core scan applies: dim <= 256,
  * slab_capacity >= 4; the reduced-precision scan always takes 16) x
  * positions per work item (2^10
  * .. 2^17; longer lists are split into chunks scanned in parallel) x wave
  * schedule (one wave per work item, or resident waves pulling items from
  * per-XCD counters) -- times each with HIP events and keeps the fastest for
- * every later search of this index (and graphs captured afterwards).
+ * every later search of this index (and graphs captured afterwards).  When
+ * the certified scan wins and the batch asks for k > 64, the schedule of
+ * the k > 64 pass (sivf_set_deep_schedule) is tuned after it the same way.
  * Results do not depend on the schedule.  Arguments as sivf_search;
  * dist/labels receive the last run's results.  Blocks until done.  tile,
  * chunk_shift, persistent: host int32 or NULL, receive the chosen values. */
@@ -168,11 +170,26 @@ sivf_status sivf_tune_search(sivf_index *ix, int64_t nq, const float *q, int32_t
 /* Set the search schedule directly (e.g. one found earlier by
  * sivf_tune_search): tile = queries per work item (fp32 storage: 4, 8
  * when dim <= 1024, or 16 -- the certified matrix-core scan, identical
- * results -- when dim <= 256, max_k <= 64 and slab_capacity >= 4; reduced
+ * results -- when dim <= 256 and slab_capacity >= 4; reduced
  * precision: 16), 2^chunk_shift = positions per
  * work item (6..31), persistent = 0 (one wave per item) or 1 (resident
  * waves).  SIVF_ERR_ARG for other values.  Applies to later calls. */
 sivf_status sivf_set_search_schedule(sivf_index *ix, int32_t tile, int32_t chunk_shift, int32_t persistent);
+
+/* Schedule of the k > 64 pass (fp32 storage).  Under the certified scan
+ * (tile 16) a search whose k exceeds 64 runs in two passes over the same
+ * probes and the same snapshot of list lengths: the queries with k <= 64 on
+ * the certified scan with 64-key lists, then those with k > 64 on this
+ * schedule (tile 4 or 8: the VALU scan; 16: the certified scan with 128-key
+ * lists); without per-query k every query takes the second.  Arguments and
+ * errors as sivf_set_search_schedule (SIVF_ERR_ARG on reduced-precision
+ * indexes too); default 4 queries x 2^13 positions, resident waves.  Set by
+ * sivf_tune_search as well.  Results do not depend on it. */
+sivf_status sivf_set_deep_schedule(sivf_index *ix, int32_t tile, int32_t chunk_shift, int32_t persistent);
+
+/* The schedules in force: sched (host, 6 int32) receives tile, chunk_shift,
+ * persistent of the search schedule, then those of the k > 64 pass. */
+sivf_status sivf_get_search_schedule(const sivf_index *ix, int32_t *sched);
 
 /* One sliding-window step in the order of the paper's mixed loop
  * (Sec. 5.5: insert, then search, then delete).  Any part with a zero count
@@ -309,17 +326,20 @@ typedef enum {
     SIVF_PROF_REMOVE = 1,  /* a whole sivf_remove                            */
     SIVF_PROF_SEARCH = 2,  /* a whole sivf_search                            */
     SIVF_PROF_COARSE = 3,  /* probe selection of a search (MFMA + re-check)  */
-    SIVF_PROF_SCAN = 4,    /* the slab scan kernel of a search               */
-    SIVF_PROF_MERGE = 5,   /* the final top-k merge kernel of a search       */
-    SIVF_PROF_KINDS = 6
+    SIVF_PROF_SCAN = 4,    /* the slab scan kernel of a search (its first pass) */
+    SIVF_PROF_MERGE = 5,   /* the final top-k merge kernels of a search      */
+    SIVF_PROF_SCAN_DEEP = 6, /* the k > 64 pass's scan of a two-pass search  */
+    SIVF_PROF_KINDS = 7
 } sivf_prof_kind;
 
 /* Turn event recording on (on != 0) or off. */
 sivf_status sivf_profile_enable(sivf_index *ix, int on);
 
 /* Wait for the recorded work, then write the summed device milliseconds and
- * the number of timed intervals of each class (host arrays of
- * SIVF_PROF_KINDS entries, either may be NULL) and reset the sums. */
+ * the number of timed calls of each class (host arrays of SIVF_PROF_KINDS
+ * entries, either may be NULL) and reset the sums.  In a two-pass search
+ * (see sivf_set_deep_schedule) the first pass's scan counts as SCAN and the
+ * second's as SCAN_DEEP; the merges of both add to one MERGE call. */
 sivf_status sivf_profile_read(sivf_index *ix, double *total_ms, int64_t *count);
 
 /* Serving: a request loop over one index whose requests overlap on the GPU

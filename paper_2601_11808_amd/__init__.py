@@ -63,6 +63,8 @@ SIGNATURES = [
     ("sivf_tune_search", ct.c_int, [_P, _I64, _P, _I32, _P, _I32, _P, _P, _P, _P, ct.POINTER(_I32),
                                     ct.POINTER(_I32), ct.POINTER(_I32)]),
     ("sivf_set_search_schedule", ct.c_int, [_P, _I32, _I32, _I32]),
+    ("sivf_set_deep_schedule", ct.c_int, [_P, _I32, _I32, _I32]),
+    ("sivf_get_search_schedule", ct.c_int, [_P, _P]),
     ("sivf_step", ct.c_int, [_P, ct.POINTER(SivfStepArgs), _P]),
     ("sivf_graph_create", ct.c_int, [_P, ct.POINTER(SivfStepArgs), ct.POINTER(_P)]),
     ("sivf_graph_launch", ct.c_int, [_P, _P]),
@@ -285,6 +287,17 @@ class Index:
         _check(lib().sivf_set_search_schedule(self._h, tile, chunk_shift, int(persistent)),
                "sivf_set_search_schedule")
 
+    def set_deep_schedule(self, tile, chunk_shift, persistent):
+        """Schedule of the k > 64 pass of a certified-scan search."""
+        _check(lib().sivf_set_deep_schedule(self._h, tile, chunk_shift, int(persistent)),
+               "sivf_set_deep_schedule")
+
+    def search_schedule(self):
+        """((tile, chunk_shift, persistent), the same for the k > 64 pass)."""
+        v = (ct.c_int32 * 6)()
+        _check(lib().sivf_get_search_schedule(self._h, ct.cast(v, ct.c_void_p)), "sivf_get_search_schedule")
+        return (v[0], v[1], v[2]), (v[3], v[4], v[5])
+
     def step(self, x=None, add_ids=None, q=None, k=10, nprobe=1, remove_ids=None, stream=None, out=None,
              k_per_query=None, nprobe_per_query=None):
         """add -> search -> remove; returns (dist, labels, n_removed)."""
@@ -401,7 +414,7 @@ class Index:
         _check(lib().sivf_stats(self._h, ct.byref(a), ct.byref(b), ct.byref(c)), "sivf_stats")
         return {"live": a.value, "used_slabs": b.value, "free_slabs": c.value}
 
-    PROF_KINDS = ("add", "remove", "search", "coarse", "scan", "merge")
+    PROF_KINDS = ("add", "remove", "search", "coarse", "scan", "merge", "scan_deep")
 
     def profile(self, on=True):
         _check(lib().sivf_profile_enable(self._h, 1 if on else 0), "sivf_profile_enable")

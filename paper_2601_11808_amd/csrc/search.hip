@@ -24,11 +24,25 @@ namespace sivf {
 
 __device__ __forceinline__ int cdiv_s(int a, int b) { return (a + b - 1) / b; }
 
+// Whether query qi belongs to the pass of class c.
+__device__ __forceinline__ bool in_class(const KClass &c, int qi) {
+    if (c.lo < 0 && c.hi == 0x7FFFFFFF) return true;
+    int kq = c.kpq ? c.kpq[qi] : c.k;
+    kq = kq < 0 ? 0 : (kq > c.k ? c.k : kq);
+    return kq > c.lo && kq <= c.hi;
+}
+
+// List of pair p, or -1 when it probes nothing or its query is outside the pass.
+__device__ __forceinline__ int pair_list(const int32_t *probes, int p, const KClass &c) {
+    const int l = probes[p];
+    return (l >= 0 && in_class(c, p / c.np_stride)) ? l : -1;
+}
+
 __global__ __launch_bounds__(256) void k_inv_count(Dev S, int npairs, const int32_t *__restrict__ probes,
-                                                   int32_t *__restrict__ pair_rank) {
+                                                   int32_t *__restrict__ pair_rank, KClass cls) {
     const int p = blockIdx.x * 256 + threadIdx.x;
     const bool active = p < npairs;
-    const int l = active ? probes[p] : -1;
+    const int l = active ? pair_list(probes, p, cls) : -1;
     const bool act = l >= 0;
     const int r = act ? atomicAdd(&S.l_qc[l], 1) : 0;   // a wave's 64 pairs hit ~64 distinct lists
     if (active) pair_rank[p] = act ? r : -1;
@@ -41,7 +55,7 @@ __global__ __launch_bounds__(256) void k_inv_count(Dev S, int npairs, const int3
 // and adds that base.  Used when the histogram fits in 64 KiB.
 constexpr int INV_PB = 8192;
 __global__ __launch_bounds__(1024) void k_inv_count_lds(Dev S, int npairs, const int32_t *__restrict__ probes,
-                                                        int32_t *__restrict__ pair_rank) {
+                                                        int32_t *__restrict__ pair_rank, KClass cls) {
     extern __shared__ int32_t hist[];
     const int tid = threadIdx.x;
     const int64_t p0 = (int64_t)blockIdx.x * INV_PB;
@@ -49,7 +63,7 @@ __global__ __launch_bounds__(1024) void k_inv_count_lds(Dev S, int npairs, const
     for (int i = tid; i < S.nlist; i += 1024) hist[i] = 0;
     __syncthreads();
     for (int i = tid; i < n; i += 1024) {
-        const int l = probes[p0 + i];
+        const int l = pair_list(probes, (int)(p0 + i), cls);
         pair_rank[p0 + i] = l >= 0 ? atomicAdd(&hist[l], 1) : -1;
     }
     __syncthreads();
@@ -59,8 +73,8 @@ __global__ __launch_bounds__(1024) void k_inv_count_lds(Dev S, int npairs, const
     }
     __syncthreads();
     for (int i = tid; i < n; i += 1024) {
-        const int l = probes[p0 + i];
-        if (l >= 0) pair_rank[p0 + i] += hist[l];
+        const int r = pair_rank[p0 + i];
+        if (r >= 0) pair_rank[p0 + i] = r + hist[probes[p0 + i]];
     }
 }
 
@@ -90,7 +104,8 @@ __device__ __forceinline__ int list_chunks(int len, int sh) {
 }
 
 // One block plans the whole search:
-//  1. snapshot every list's length (the scan reads only these entries) and
+//  1. snapshot every list's length (the scan reads only these entries; a
+//     second pass of the same search keeps the first pass's snapshot) and
 //     lay out the (query, probe) pairs list by list;
 //  2. split lists into chunks of 2^sh positions, with the smallest sh >= sh0
 //     whose partial results (one per pair and chunk) and work items (one per
@@ -102,7 +117,7 @@ __device__ __forceinline__ int list_chunks(int len, int sh) {
 //     others finish long lists -- each at most xcd_cap items (the blocks an
 //     XCD receives in the dispatch schedule).
 __global__ __launch_bounds__(1024) void k_inv_plan(Dev S, int T, int sh0, int64_t slot_cap, int64_t item_cap,
-                                                   int xcd_cap) {
+                                                   int xcd_cap, int snap) {
     __shared__ int sbuf[16];
     __shared__ long long sred[32];
     __shared__ long long scost[16];
@@ -115,7 +130,7 @@ __global__ __launch_bounds__(1024) void k_inv_plan(Dev S, int T, int sh0, int64_
         int tp;
         const int ep = block_excl_scan<1024>(qc, sbuf, &tp);
         if (valid) {
-            S.l_snap[l] = S.len[l];
+            if (snap) S.l_snap[l] = S.len[l];
             S.l_qoff[l] = carry_p + ep;
             S.l_qcs[l] = qc;
             S.l_qc[l] = 0;
@@ -618,7 +633,7 @@ __global__ __launch_bounds__(256) void k_chunk_merge(Dev S, int npairs, const in
                                                      uint64_t *__restrict__ partials, int kcap) {
     const int p = blockIdx.x * 256 + threadIdx.x, lane = lane_id();
     const int sh = S.ctl[CTL_CHUNK];
-    const int l = p < npairs ? probes[p] : -1;
+    const int l = (p < npairs && pair_rank[p] >= 0) ? probes[p] : -1;   // pairs of this pass only
     const int nc = l >= 0 ? list_chunks(S.l_snap[l], sh) : 0;
     const int64_t slot = nc > 1 ? (int64_t)S.l_pbase[l] + (int64_t)pair_rank[p] * nc : 0;
     uint64_t mask = ballot(nc > 1);
@@ -654,11 +669,11 @@ __global__ __launch_bounds__(256) void k_merge(Dev S, int nq, int np_stride, con
                                                const int32_t *__restrict__ pair_rank,
                                                const uint64_t *__restrict__ partials, int kcap, int out_stride,
                                                int k, int kmul, const int32_t *__restrict__ kpq,
-                                               float *__restrict__ dist, int64_t *__restrict__ labels) {
+                                               float *__restrict__ dist, int64_t *__restrict__ labels, KClass cls) {
     __shared__ unsigned char heads[4][1024];
     const int w = threadIdx.x >> 6, lane = lane_id();
     const int qi = blockIdx.x * 4 + w;
-    if (qi >= nq) return;
+    if (qi >= nq || !in_class(cls, qi)) return;   // a query of another pass: its results come from that one
     const int sh = S.ctl[CTL_CHUNK];
     int kq = kpq ? kpq[qi] : k;
     kq = kq < 0 ? 0 : (kq > k ? k : kq);
@@ -900,14 +915,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
             }
         }
         if (!live) pmask = 0;
-        const uint64_t vm = step_valid(S, base, p1, wslab, wbase, cs, cm);   // in range and (lazy deletes) live
-        if (vm != ~0ull) {
-#pragma unroll
-            for (int rg = 0; rg < 4; rg++)
-#pragma unroll
-                for (int j = 0; j < 4; j++)
-                    if (!((vm >> (16 * rg + 4 * kgrp + j)) & 1ull)) pmask &= ~(1u << (4 * rg + j));
-        }
+        // in range and (lazy deletes) live
+        pmask &= lane_valid16(step_valid(S, base, p1, wslab, wbase, cs, cm), kgrp);
         if (ballot(pmask != 0)) {
             // offsets of this lane's candidates among the 4 lanes of its query
             const int np = __builtin_popcount(pmask);
@@ -1082,7 +1091,12 @@ __device__ __forceinline__ f32x4_t cert_mfma(const float4 (&a)[NB], const float4
 // in full rounds of 64 (the queue drains early when a query has no k-th value
 // yet, before the slab window moves, and at the end of the item).
 // Exact lists: KC keys per query sorted across KC lanes, 64 / KC queries per
-// register (KC = 16 for kcap 16, else 64).
+// register (KC = 16 for kcap 16, else 64).  KC = 128 (k up to 128): ranks
+// 0..63 stay in registers as for KC = 64; ranks 64..127 are kept only for
+// queries whose k exceeds 64, in the upper half of the query's own partial
+// slot (read and written back by the inserting lanes, each its own rank; an
+// LDS copy would cost the kernel a third of its resident waves); a key that
+// enters the low half pushes its largest key down into the high half.
 template <int METRIC, int NB, bool PERS, int KC>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_scan_cert(Dev S, const int32_t *__restrict__ item_list,
                                                   const int32_t *__restrict__ item_tile,
@@ -1139,10 +1153,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
     const bool live = qcol < nt && skq[qcol] > 0;
     float thr_f = METRIC == 0 ? from_ord(thr) : from_ord(~thr);
     // sorted exact lists: query t in register t / QPR, lanes KC (t % QPR) .. +KC-1
-    constexpr int QPR = 64 / KC, NR = MQ / QPR;
+    // (KC = 128: ranks 0..63 in register t, the rest in LDS)
+    constexpr int QPR = KC == 128 ? 1 : 64 / KC, NR = MQ / QPR;
     uint64_t top[NR];
 #pragma unroll
     for (int r = 0; r < NR; r++) top[r] = ~0ull;
+    uint32_t hset = 0;   // KC = 128: queries whose ranks 64..127 have been written to their slot
 
     const int nslab = (len + cm) >> cs;
     int wbase = -(1 << 30), wslab = 0;
@@ -1190,7 +1206,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
         // distance space (L2: the distance; IP: minus the score): value v and
         // certified half-width e of every (slot, query) pair of this lane
         float vv[16], ee[16];
-        const uint64_t vm = step_valid(S, base, p1, wslab, wbase, cs, cm);   // in range and (lazy deletes) live
+        // bit 4 rg + j: position 16 rg + 4 kgrp + j in range and (lazy deletes) live
+        const uint32_t vm = lane_valid16(step_valid(S, base, p1, wslab, wbase, cs, cm), kgrp);
 #pragma unroll
         for (int rg = 0; rg < 4; rg++) {
             const float xs[4] = {xn4[rg].x, xn4[rg].y, xn4[rg].z, xn4[rg].w};
@@ -1215,7 +1232,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
             for (int i = 0; i < 16; i++) {
                 float u = vv[i] + ee[i];
                 if (!(u <= __int_as_float(0x7F800000))) u = __int_as_float(0x7F800000);   // NaN: +inf
-                if ((vm >> (16 * (i >> 2) + 4 * kgrp + (i & 3))) & 1ull) {
+                if ((vm >> i) & 1u) {
                     nv++;
                     mn = fminf(mn, u);
                     mx = fmaxf(mx, u);
@@ -1235,7 +1252,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
 #pragma unroll
                 for (int i = 0; i < 16; i++) {
                     const float u = vv[i] + ee[i];
-                    c += (((vm >> (16 * (i >> 2) + 4 * kgrp + (i & 3))) & 1ull) && u <= mid) ? 1 : 0;
+                    c += (((vm >> i) & 1u) && u <= mid) ? 1 : 0;
                 }
                 c += __shfl_xor(c, 16);
                 c += __shfl_xor(c, 32);
@@ -1248,13 +1265,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
 #pragma unroll
         for (int i = 0; i < 16; i++) pmask |= (!(vv[i] - ee[i] > thd) ? 1u : 0u) << i;
         if (!live) pmask = 0;
-        if (vm != ~0ull) {
-#pragma unroll
-            for (int rg = 0; rg < 4; rg++)
-#pragma unroll
-                for (int j = 0; j < 4; j++)
-                    if (!((vm >> (16 * rg + 4 * kgrp + j)) & 1ull)) pmask &= ~(1u << (4 * rg + j));
-        }
+        pmask &= vm;
         if (ballot(pmask != 0)) {
             // queue the passing (position, query) pairs in lane order
             const int np = __builtin_popcount(pmask);
@@ -1297,14 +1308,45 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
                 for (int t2 = 0; t2 < MQ; t2++) {
                     uint64_t bm = ballot(act && t == t2);
                     if (bm) {
+                        const int kq = __builtin_amdgcn_readfirstlane(skq[t2]);   // > 0: only live queries have pairs
+                        uint64_t hi = ~0ull;      // KC = 128, k > 64: ranks 64..127
+                        uint64_t *hdst = nullptr;
+                        if constexpr (KC == 128) {
+                            if (kq > 64) {
+                                SIVF_ITEM_SLOT(MQ)
+                                hdst = partials + (slot0 + (int64_t)t2 * nc) * kcap + 64;
+                                if ((hset >> t2) & 1u) hi = hdst[lane];
+                                hset |= 1u << t2;
+                            }
+                        }
+                        // only keys below the query's current k-th key can change its k best
+                        uint64_t kth;
+                        if constexpr (KC == 128) kth = kq <= 64 ? readlane_u64(top[t2], kq - 1) : readlane_u64(hi, kq - 65);
+                        else kth = readlane_u64(top[t2 / QPR], KC * (t2 % QPR) + kq - 1);
+                        bm = ballot(act && t == t2 && key < kth);
                         while (bm) {
                             const int src = (int)__builtin_ctzll(bm);
                             bm &= bm - 1;
-                            top[t2 / QPR] = sorted_insert<KC>(top[t2 / QPR], readlane_u64(key, src), KC * (t2 % QPR));
+                            uint64_t c = readlane_u64(key, src);
+                            if constexpr (KC == 128) {
+                                // a key below the low half's largest enters it and pushes that one down
+                                const uint64_t lmax = readlane_u64(top[t2], 63);
+                                if (c < lmax) {
+                                    top[t2] = sorted_insert<64>(top[t2], c, 0);
+                                    c = lmax;
+                                }
+                                if (kq > 64) hi = sorted_insert<64>(hi, c, 0);
+                            } else {
+                                top[t2 / QPR] = sorted_insert<KC>(top[t2 / QPR], c, KC * (t2 % QPR));
+                            }
                         }
-                        const int kq = skq[t2];   // > 0: only live queries have pairs
-                        const uint32_t nthr =
-                            kq > 0 ? (uint32_t)(readlane_u64(top[t2 / QPR], KC * (t2 % QPR) + kq - 1) >> 32) : 0u;
+                        uint32_t nthr = 0u;
+                        if constexpr (KC == 128) {
+                            if (kq > 64) hdst[lane] = hi;
+                            nthr = (uint32_t)((kq <= 64 ? readlane_u64(top[t2], kq - 1) : readlane_u64(hi, kq - 65)) >> 32);
+                        } else {
+                            nthr = kq > 0 ? (uint32_t)(readlane_u64(top[t2 / QPR], KC * (t2 % QPR) + kq - 1) >> 32) : 0u;
+                        }
                         if (qcol == t2) {
                             thr = nthr;
                             thr_f = METRIC == 0 ? from_ord(thr) : from_ord(~thr);
@@ -1322,10 +1364,21 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
         __syncthreads();   // queue writes of this step before the next step's appends
     }
     SIVF_ITEM_SLOT(MQ)
+    if constexpr (KC == 128) {
 #pragma unroll
-    for (int t = 0; t < MQ; t++)
-        if (t < nt && (lane >> (KC == 64 ? 6 : 4)) == (KC == 64 ? 0 : t % QPR) && (lane & (KC - 1)) < kcap)
-            partials[(slot0 + (int64_t)t * nc) * kcap + (lane & (KC - 1))] = top[t / QPR];
+        for (int t = 0; t < MQ; t++) {
+            if (t < nt) {
+                uint64_t *dst = partials + (slot0 + (int64_t)t * nc) * kcap;
+                dst[lane] = top[t];
+                if (!((hset >> t) & 1u)) dst[64 + lane] = ~0ull;   // no rank 64..127 key yet
+            }
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < MQ; t++)
+            if (t < nt && (lane >> (KC == 64 ? 6 : 4)) == (KC == 64 ? 0 : t % QPR) && (lane & (KC - 1)) < kcap)
+                partials[(slot0 + (int64_t)t * nc) * kcap + (lane & (KC - 1))] = top[t / QPR];
+    }
     SIVF_ITEM_LOOP_END
 }
 
@@ -1478,25 +1531,26 @@ static void launch_scan_t(hipStream_t st, const Dev &S, const SearchBufs &W, con
     else launch_scan_p<T, WIDE, false>(st, S, W, q, np_stride, kcap, k, kpq, npairs);
 }
 
-void launch_search_plan(hipStream_t st, const Dev &S, const SearchBufs &W, int nq, int np_stride) {
+void launch_search_plan(hipStream_t st, const Dev &S, const SearchBufs &W, int nq, const KClass &cls, int snap) {
+    const int np_stride = cls.np_stride;
     const int npairs = nq * np_stride;
     const unsigned pb = (unsigned)((npairs + 255) / 256);
     const int T = search_tile(S);
     if (S.nlist <= 16384)
         hipLaunchKernelGGL(k_inv_count_lds, dim3((unsigned)((npairs + INV_PB - 1) / INV_PB)), dim3(1024),
-                           (size_t)S.nlist * 4, st, S, npairs, W.probes, W.pair_rank);
+                           (size_t)S.nlist * 4, st, S, npairs, W.probes, W.pair_rank, cls);
     else
-        hipLaunchKernelGGL(k_inv_count, dim3(pb), dim3(256), 0, st, S, npairs, W.probes, W.pair_rank);
+        hipLaunchKernelGGL(k_inv_count, dim3(pb), dim3(256), 0, st, S, npairs, W.probes, W.pair_rank, cls);
     const int64_t lim = item_limit(S, W, npairs);
     hipLaunchKernelGGL(k_inv_plan, dim3(1), dim3(1024), 0, st, S, T, S.chunk_shift, W.slot_cap, lim,
-                       (int)((lim + 7) / 8));
+                       (int)((lim + 7) / 8), snap);
     hipLaunchKernelGGL(k_inv_items, dim3((S.nlist + 3) / 4), dim3(256), 0, st, S, T, W.item_list, W.item_tile,
                        W.item_chunk);
     hipLaunchKernelGGL(k_inv_scatter, dim3(pb), dim3(256), 0, st, S, npairs, W.probes, W.pair_rank,
                        W.list_pairs);
 }
 
-bool cert_ok(int storage, int d, int C, int kcap) { return storage == 0 && d <= 256 && C >= 4 && kcap <= 64; }
+bool cert_ok(int storage, int d, int C, int kcap) { return storage == 0 && d <= 256 && C >= 4 && kcap <= 128; }
 
 template <int METRIC, int NB, int KC>
 static void launch_cert_nb(hipStream_t st, const Dev &S, const SearchBufs &W, const float *q, int np_stride,
@@ -1515,7 +1569,8 @@ template <int METRIC>
 static void launch_cert(hipStream_t st, const Dev &S, const SearchBufs &W, const float *q, int np_stride, int kcap,
                         int k, const int32_t *kpq, int npairs) {
     // blocks of 16 dimensions held as B operands (d <= 256)
-    // sorted lists of 16 keys (kcap 16: four queries per register) or 64 (kcap 32, 64)
+    // sorted lists of 16 keys (kcap 16: four queries per register), 64 (kcap 32, 64) or
+    // 128 (kcap 128: ranks 64..127 in the partial slot)
     const int nb = (S.d + 15) / 16;
 #define SIVF_CERT_NB(KC)                                                                                     \
     do {                                                                                                     \
@@ -1525,7 +1580,8 @@ static void launch_cert(hipStream_t st, const Dev &S, const SearchBufs &W, const
         else launch_cert_nb<METRIC, 16, KC>(st, S, W, q, np_stride, kcap, k, kpq, npairs);                   \
     } while (0)
     if (kcap <= 16) SIVF_CERT_NB(16);
-    else SIVF_CERT_NB(64);
+    else if (kcap <= 64) SIVF_CERT_NB(64);
+    else SIVF_CERT_NB(128);
 #undef SIVF_CERT_NB
 }
 
@@ -1547,9 +1603,10 @@ void launch_search_scan(hipStream_t st, const Dev &S, const SearchBufs &W, int n
     }
 }
 
-void launch_search_merge(hipStream_t st, const Dev &S, const SearchBufs &W, int nq, int np_stride, int kcap,
+void launch_search_merge(hipStream_t st, const Dev &S, const SearchBufs &W, int nq, const KClass &cls, int kcap,
                          int out_stride, int k, int kmul, const int32_t *k_per_query, float *dist,
                          int64_t *labels) {
+    const int np_stride = cls.np_stride;
     const int npairs = nq * np_stride;
     const unsigned pb = (unsigned)((npairs + 255) / 256);
     if (kcap > 64)
@@ -1559,7 +1616,7 @@ void launch_search_merge(hipStream_t st, const Dev &S, const SearchBufs &W, int 
         hipLaunchKernelGGL(k_chunk_merge<false>, dim3(pb), dim3(256), 0, st, S, npairs, W.probes, W.pair_rank,
                            W.partials, kcap);
     hipLaunchKernelGGL(k_merge, dim3((nq + 3) / 4), dim3(256), 0, st, S, nq, np_stride, W.probes, W.pair_rank,
-                       W.partials, kcap, out_stride, k, kmul, k_per_query, dist, labels);
+                       W.partials, kcap, out_stride, k, kmul, k_per_query, dist, labels, cls);
 }
 
 }  // namespace sivf

@@ -142,6 +142,7 @@ bool dev_ok(hipError_t e) { return e == hipSuccess; }
 // Event pairs recorded around one class of work while profiling is on.
 struct ProfClass {
     std::vector<hipEvent_t> start, stop;
+    std::vector<char> more;   // the interval continues the previous one's call (not counted again)
     size_t used = 0;
     double ms = 0.0;
     int64_t count = 0;
@@ -161,6 +162,8 @@ struct sivf_index {
     bool broken = false;
     bool prof = false;
     ProfClass pc[SIVF_PROF_KINDS];
+    // schedule of the k > 64 pass of a certified-scan search (tile, chunk shift, persistent)
+    int deep_tile = 4, deep_shift = 13, deep_pers = 1;
 };
 
 namespace {
@@ -182,14 +185,14 @@ bool prof_fold(sivf_index *ix, ProfClass &c) {
         float ms = 0.f;
         if (!dev_ok(hipEventElapsedTime(&ms, c.start[i], c.stop[i]))) return false;
         c.ms += ms;
-        c.count++;
+        if (!c.more[i]) c.count++;
     }
     c.used = 0;
     return true;
 }
 
 // Returns the slot of an interval whose start was recorded, or -1.
-int prof_begin(sivf_index *ix, int kind, hipStream_t st) {
+int prof_begin(sivf_index *ix, int kind, hipStream_t st, bool more = false) {
     if (!ix->prof) return -1;
     ProfClass &c = ix->pc[kind];
     if (c.used == 4096 && !prof_fold(ix, c)) return -1;
@@ -202,8 +205,10 @@ int prof_begin(sivf_index *ix, int kind, hipStream_t st) {
         }
         c.start.push_back(a);
         c.stop.push_back(b);
+        c.more.push_back(0);
     }
     if (!dev_ok(hipEventRecord(c.start[c.used], st))) return -1;
+    c.more[c.used] = more ? 1 : 0;
     return (int)c.used++;
 }
 
@@ -287,25 +292,57 @@ sivf_status do_search(sivf_index *ix, int64_t nq, const float *q, int32_t k, con
     const int pc = prof_begin(ix, SIVF_PROF_COARSE, st);
     coarse(ix, st, ix->dt_s, q, nq, npq ? 0 : stride, npq, stride, ix->W.probes, stride, 0);
     prof_end(ix, SIVF_PROF_COARSE, pc, st);
-    launch_search_plan(st, ix->S, ix->W, (int)nq, stride);   // records the list lengths it will scan
-    if (snapshot_taken && !dev_ok(hipEventRecord(snapshot_taken, st))) return SIVF_ERR_DEVICE;
-    const int pk = prof_begin(ix, SIVF_PROF_SCAN, st);
-    if (c.storage == SIVF_F32)
-        launch_search_scan(st, ix->S, ix->W, (int)nq, q, stride, ix->L.kcap, k, kpq);
-    else
+    if (c.storage != SIVF_F32) {
+        const KClass all = kclass_all(stride);
+        launch_search_plan(st, ix->S, ix->W, (int)nq, all, 1);   // records the list lengths it will scan
+        if (snapshot_taken && !dev_ok(hipEventRecord(snapshot_taken, st))) return SIVF_ERR_DEVICE;
+        const int pk = prof_begin(ix, SIVF_PROF_SCAN, st);
         launch_search_scan_mfma(st, ix->S, ix->W, (int)nq, q, stride, ix->L.kcap, k, c.rerank_factor, kpq);
-    prof_end(ix, SIVF_PROF_SCAN, pk, st);
-    const int pm = prof_begin(ix, SIVF_PROF_MERGE, st);
-    if (c.storage == SIVF_F32) {
-        launch_search_merge(st, ix->S, ix->W, (int)nq, stride, ix->L.kcap, k, k, 1, kpq, dist, labels);
-    } else {
+        prof_end(ix, SIVF_PROF_SCAN, pk, st);
         // approximate candidates, then the exact fp32 re-rank of R * k per query
+        const int pm = prof_begin(ix, SIVF_PROF_MERGE, st);
         const int kc = c.rerank_factor * k;
-        launch_search_merge(st, ix->S, ix->W, (int)nq, stride, ix->L.kcap, kc, k, c.rerank_factor, kpq,
+        launch_search_merge(st, ix->S, ix->W, (int)nq, all, ix->L.kcap, kc, k, c.rerank_factor, kpq,
                             ix->W.rr_dist, ix->W.rr_lab);
         launch_rerank(st, ix->S, (int)nq, q, kc, ix->W.rr_lab, k, c.rerank_factor, kpq, dist, labels);
+        prof_end(ix, SIVF_PROF_MERGE, pm, st);
+        prof_end(ix, SIVF_PROF_SEARCH, ps, st);
+        return launched(ix);
     }
-    prof_end(ix, SIVF_PROF_MERGE, pm, st);
+    // fp32: partial lists as wide as the call's k needs.  On the certified
+    // scan, queries with k > 64 form a pass of their own on the deep schedule
+    // (its lists of 128 keys cost the certified scan more than the VALU scan
+    // pays); the k <= 64 queries keep the certified scan with 64-key lists.
+    const int kw = kcap_for(k);
+    const bool split = ix->S.tile == 16 && kw > 64;
+    Dev Sd = ix->S;
+    Sd.tile = ix->deep_tile;
+    Sd.chunk_shift = ix->deep_shift;
+    Sd.persistent = ix->deep_pers;
+    struct Pass {
+        const Dev *S;
+        KClass cls;
+        int kw;
+    } passes[2];
+    int np = 0;
+    if (!split) {
+        passes[np++] = {&ix->S, kclass_all(stride), kw};
+    } else {
+        if (kpq) passes[np++] = {&ix->S, KClass{kpq, k, stride, -1, 64}, 64};
+        passes[np++] = {&Sd, kpq ? KClass{kpq, k, stride, 64, 0x7FFFFFFF} : kclass_all(stride), 128};
+    }
+    for (int i = 0; i < np; i++) {
+        const Pass &P = passes[i];
+        launch_search_plan(st, *P.S, ix->W, (int)nq, P.cls, i == 0 ? 1 : 0);
+        if (i == 0 && snapshot_taken && !dev_ok(hipEventRecord(snapshot_taken, st))) return SIVF_ERR_DEVICE;
+        const int sk = (split && P.S == &Sd) ? SIVF_PROF_SCAN_DEEP : SIVF_PROF_SCAN;
+        const int pk = prof_begin(ix, sk, st);
+        launch_search_scan(st, *P.S, ix->W, (int)nq, q, stride, P.kw, k, kpq);
+        prof_end(ix, sk, pk, st);
+        const int pm = prof_begin(ix, SIVF_PROF_MERGE, st, i > 0);
+        launch_search_merge(st, *P.S, ix->W, (int)nq, P.cls, P.kw, k, k, 1, kpq, dist, labels);
+        prof_end(ix, SIVF_PROF_MERGE, pm, st);
+    }
     prof_end(ix, SIVF_PROF_SEARCH, ps, st);
     return launched(ix);
 }
@@ -455,6 +492,14 @@ sivf_status sivf_search(sivf_index *ix, int64_t nq, const float *q, int32_t k, c
     return do_search(ix, nq, q, k, k_per_query, nprobe, nprobe_per_query, dist, labels, as_stream(stream));
 }
 
+// Tile of a schedule the index admits: fp32 slabs take 4, 8 (dim <= 1024) or
+// 16 (the certified scan, where it applies); reduced precision takes 16.
+static bool tile_ok(const sivf_index *ix, int tile) {
+    const bool reduced = ix->cfg.storage != SIVF_F32;
+    const bool cert = tile == 16 && cert_ok(ix->cfg.storage, ix->cfg.dim, ix->cfg.slab_capacity, ix->L.kcap);
+    return reduced ? tile == 16 : (tile == 4 || (tile == 8 && ix->cfg.dim <= 1024) || cert);
+}
+
 sivf_status sivf_tune_search(sivf_index *ix, int64_t nq, const float *q, int32_t k, const int32_t *k_per_query,
                              int32_t nprobe, const int32_t *nprobe_per_query, float *dist, int64_t *labels,
                              void *stream, int32_t *tile, int32_t *chunk_shift, int32_t *persistent) {
@@ -474,35 +519,61 @@ sivf_status sivf_tune_search(sivf_index *ix, int64_t nq, const float *q, int32_t
     }
     const bool prof = ix->prof;
     ix->prof = false;
+    sivf_status s = SIVF_OK;
+    // device time of two searches after a warm-up one (negative on failure)
+    auto timed = [&]() -> float {
+        s = do_search(ix, nq, q, k, k_per_query, nprobe, nprobe_per_query, dist, labels, st);
+        if (s != SIVF_OK) return -1.f;
+        if (!dev_ok(hipEventRecord(e0, st))) s = SIVF_ERR_DEVICE;
+        for (int r = 0; r < 2 && s == SIVF_OK; r++)
+            s = do_search(ix, nq, q, k, k_per_query, nprobe, nprobe_per_query, dist, labels, st);
+        float ms = 0.f;
+        if (s == SIVF_OK && (!dev_ok(hipEventRecord(e1, st)) || !dev_ok(hipEventSynchronize(e1)) ||
+                             !dev_ok(hipEventElapsedTime(&ms, e0, e1))))
+            s = SIVF_ERR_DEVICE;
+        return s == SIVF_OK ? ms : -1.f;
+    };
     int bt = ix->S.tile, bs = ix->S.chunk_shift, bp = ix->S.persistent;
     float best = -1.f;
-    sivf_status s = SIVF_OK;
-    for (int pm = 0; pm < 2; pm++)
-    for (int T : tiles) {
-        for (int sh = 10; sh <= 17 && s == SIVF_OK; sh++) {
-            ix->S.tile = T;
-            ix->S.chunk_shift = sh;
-            ix->S.persistent = pm;
-            s = do_search(ix, nq, q, k, k_per_query, nprobe, nprobe_per_query, dist, labels, st);   // warm-up
-            if (s != SIVF_OK) break;
-            if (!dev_ok(hipEventRecord(e0, st))) s = SIVF_ERR_DEVICE;
-            for (int r = 0; r < 2 && s == SIVF_OK; r++)
-                s = do_search(ix, nq, q, k, k_per_query, nprobe, nprobe_per_query, dist, labels, st);
-            float ms = 0.f;
-            if (s == SIVF_OK && (!dev_ok(hipEventRecord(e1, st)) || !dev_ok(hipEventSynchronize(e1)) ||
-                                 !dev_ok(hipEventElapsedTime(&ms, e0, e1))))
-                s = SIVF_ERR_DEVICE;
-            if (s == SIVF_OK && (best < 0.f || ms < best)) {
-                best = ms;
-                bt = T;
-                bs = sh;
-                bp = pm;
+    for (int pm = 0; pm < 2 && s == SIVF_OK; pm++)
+        for (int T : tiles)
+            for (int sh = 10; sh <= 17 && s == SIVF_OK; sh++) {
+                ix->S.tile = T;
+                ix->S.chunk_shift = sh;
+                ix->S.persistent = pm;
+                const float ms = timed();
+                if (ms >= 0.f && (best < 0.f || ms < best)) {
+                    best = ms;
+                    bt = T;
+                    bs = sh;
+                    bp = pm;
+                }
             }
-        }
-    }
     ix->S.tile = bt;
     ix->S.chunk_shift = bs;
     ix->S.persistent = bp;
+    // a certified-scan schedule runs queries with k > 64 as a pass of their own: tune its schedule too
+    if (s == SIVF_OK && ix->cfg.storage == SIVF_F32 && bt == 16 && kcap_for(k) > 64) {
+        int dt = ix->deep_tile, ds = ix->deep_shift, dp = ix->deep_pers;
+        float dbest = -1.f;
+        for (int pm = 0; pm < 2 && s == SIVF_OK; pm++)
+            for (int T : tiles)
+                for (int sh = 10; sh <= 17 && s == SIVF_OK; sh++) {
+                    ix->deep_tile = T;
+                    ix->deep_shift = sh;
+                    ix->deep_pers = pm;
+                    const float ms = timed();
+                    if (ms >= 0.f && (dbest < 0.f || ms < dbest)) {
+                        dbest = ms;
+                        dt = T;
+                        ds = sh;
+                        dp = pm;
+                    }
+                }
+        ix->deep_tile = dt;
+        ix->deep_shift = ds;
+        ix->deep_pers = dp;
+    }
     ix->prof = prof;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -514,13 +585,29 @@ sivf_status sivf_tune_search(sivf_index *ix, int64_t nq, const float *q, int32_t
 
 sivf_status sivf_set_search_schedule(sivf_index *ix, int32_t tile, int32_t chunk_shift, int32_t persistent) {
     if (!ix) return SIVF_ERR_ARG;
-    const bool reduced = ix->cfg.storage != SIVF_F32;
-    const bool cert = tile == 16 && cert_ok(ix->cfg.storage, ix->cfg.dim, ix->cfg.slab_capacity, ix->L.kcap);
-    if (reduced ? tile != 16 : (tile != 4 && (tile != 8 || ix->cfg.dim > 1024) && !cert)) return SIVF_ERR_ARG;
+    if (!tile_ok(ix, tile)) return SIVF_ERR_ARG;
     if (chunk_shift < 6 || chunk_shift > 31 || (persistent != 0 && persistent != 1)) return SIVF_ERR_ARG;
     ix->S.tile = tile;
     ix->S.chunk_shift = chunk_shift;
     ix->S.persistent = persistent;
+    return SIVF_OK;
+}
+
+sivf_status sivf_set_deep_schedule(sivf_index *ix, int32_t tile, int32_t chunk_shift, int32_t persistent) {
+    if (!ix) return SIVF_ERR_ARG;
+    if (ix->cfg.storage != SIVF_F32 || !tile_ok(ix, tile)) return SIVF_ERR_ARG;
+    if (chunk_shift < 6 || chunk_shift > 31 || (persistent != 0 && persistent != 1)) return SIVF_ERR_ARG;
+    ix->deep_tile = tile;
+    ix->deep_shift = chunk_shift;
+    ix->deep_pers = persistent;
+    return SIVF_OK;
+}
+
+sivf_status sivf_get_search_schedule(const sivf_index *ix, int32_t *sched) {
+    if (!ix || !sched) return SIVF_ERR_ARG;
+    const int32_t v[6] = {ix->S.tile, ix->S.chunk_shift, ix->S.persistent, ix->deep_tile, ix->deep_shift,
+                          ix->deep_pers};
+    for (int i = 0; i < 6; i++) sched[i] = v[i];
     return SIVF_OK;
 }
 

@@ -102,6 +102,13 @@ __device__ __forceinline__ uint64_t step_valid(const Dev &S, int base, int p1, i
     return __ballot(ok);
 }
 
+// The 16 bits of a step mask that a lane of the MFMA scans owns: bit 4 rg + j
+// is position 16 rg + 4 kgrp + j of the step (row group rg, lane group kgrp).
+__device__ __forceinline__ uint32_t lane_valid16(uint64_t vm, int kgrp) {
+    const uint64_t s = vm >> (4 * kgrp);
+    return (uint32_t)((s & 0xFull) | ((s >> 12) & 0xF0ull) | ((s >> 24) & 0xF00ull) | ((s >> 36) & 0xF000ull));
+}
+
 __device__ __forceinline__ int slab_of(const Dev &S, int l, int ord) {
     int page = S.dir[(int64_t)l * S.dir_cap + ord / PAGE];
     return S.pages[(int64_t)page * PAGE + ord % PAGE];

@@ -68,6 +68,16 @@ struct SearchBufs {
     float *rr_dist;      // reduced precision: approximate candidates per query
     int64_t *rr_lab;
 };
+// One pass of a search over the queries whose k, clamped to [0, k], lies in
+// (lo, hi]: its plan, scan and merge skip the other queries.  A search whose
+// per-query k straddles 64 on a certified-scan schedule runs two passes (k up
+// to 64 on the certified scan, the rest on the deep schedule) that share the
+// coarse probes and the list-length snapshot.
+struct KClass {
+    const int32_t *kpq;   // per-query k or null (every query asks for k)
+    int k, np_stride, lo, hi;
+};
+inline KClass kclass_all(int np_stride) { return KClass{nullptr, 0, np_stride, -1, 0x7FFFFFFF}; }
 int search_tile(const Dev &S);
 // Default queries per work item: 16 (reduced precision, or the certified
 // matrix-core scan where it applies), else 8 (4 past 1024 dimensions).
@@ -77,10 +87,12 @@ bool cert_ok(int storage, int d, int C, int kcap);
 // Default search chunk: 2^14 positions per work item (a list is split only
 // when the plan's buffers allow; into longer chunks otherwise).
 constexpr int DEFAULT_CHUNK_SHIFT = 14;
-void launch_search_plan(hipStream_t st, const Dev &S, const SearchBufs &W, int nq, int np_stride);
+// snap = 1: record every list's length (the scan reads only these entries);
+// snap = 0: keep the lengths an earlier pass of the same search recorded.
+void launch_search_plan(hipStream_t st, const Dev &S, const SearchBufs &W, int nq, const KClass &cls, int snap);
 void launch_search_scan(hipStream_t st, const Dev &S, const SearchBufs &W, int nq, const float *q, int np_stride,
                         int kcap, int k, const int32_t *k_per_query);
-void launch_search_merge(hipStream_t st, const Dev &S, const SearchBufs &W, int nq, int np_stride, int kcap,
+void launch_search_merge(hipStream_t st, const Dev &S, const SearchBufs &W, int nq, const KClass &cls, int kcap,
                          int out_stride, int k, int kmul, const int32_t *k_per_query, float *dist,
                          int64_t *labels);
 void launch_search_scan_mfma(hipStream_t st, const Dev &S, const SearchBufs &W, int nq, const float *q,

@@ -118,7 +118,7 @@ def test_cert_scan_split_lists(metric, mk):
 
 
 def test_cert_schedule_limits():
-    """Tile 16 on fp32 slabs needs d <= 256, max_k <= 64 and slabs of >= 4 slots."""
+    """Tile 16 on fp32 slabs needs d <= 256 and slabs of >= 4 slots (any max_k up to 128)."""
     rng = np.random.default_rng(5)
 
     def mk(d, max_k, C):
@@ -127,9 +127,110 @@ def test_cert_schedule_limits():
                           max_queries=16, max_k=max_k, max_nprobe=4)
 
     mk(256, 64, 4).set_search_schedule(16, 14, 0)
-    for d, max_k, C in [(257, 16, 64), (64, 65, 64), (64, 16, 2)]:
+    mk(64, 128, 64).set_search_schedule(16, 14, 0)
+    for d, max_k, C in [(257, 16, 64), (64, 16, 2)]:
         with pytest.raises(sivf.SivfError):
             mk(d, max_k, C).set_search_schedule(16, 14, 0)
+
+
+@pytest.mark.parametrize("metric", [0, 1])
+def test_cert_scan_k128_split_lists(metric):
+    """Lists of 128 keys (k = 100 and 128, per-query k): work items of 8 queries,
+    two registers per list; long lists split into chunks, both schedules; bit for
+    bit equal to the VALU scan and equal to the oracle."""
+    rng = np.random.default_rng([78, metric])
+    sizes = [20001, 9000, 999, 130, 3, 0]
+    d = 48
+    cent = (rng.standard_normal((len(sizes), d)) * 8).astype(np.float32)
+    x = np.concatenate([cent[l] + rng.standard_normal((s, d)) for l, s in enumerate(sizes) if s]).astype(np.float32)
+    x[500:600] = x[:100]                       # equal rows: ties on distance
+    ids = rng.permutation(x.shape[0]).astype(np.int64)
+    q = np.concatenate([(cent[rng.integers(0, len(sizes), 300)] + rng.standard_normal((300, d))),
+                        x[rng.integers(0, x.shape[0], 50)]]).astype(np.float32)
+    ix = sivf.Index(d, len(sizes), cent, metric=metric, slab_capacity=64, num_slabs=700, id_capacity=x.shape[0],
+                    max_batch=1 << 16, max_queries=q.shape[0], max_k=128, max_nprobe=6)
+    ref = oracle.OracleIndex(d, len(sizes), cent, metric, 64, 700, x.shape[0])
+    ix.add(x, ids)
+    assert ix.sync() == 0
+    assert ref.add(x, ids) == 0
+    for k, nprobe in [(100, 3), (128, 6), (65, 1)]:
+        st, rd, rl = ref.search(q, k, nprobe)
+        for sched in [(16, 10, 0), (16, 12, 1), (16, 17, 0)]:
+            gd, gl = _both(ix, q, k, nprobe, sched=sched)
+            compare_results(gd, gl, rd, rl)
+    kpq = rng.integers(0, 129, q.shape[0]).astype(np.int32)
+    npq = rng.integers(1, 7, q.shape[0]).astype(np.int32)
+    gd, gl = _both(ix, q, 128, 6, kpq, npq, sched=(16, 11, 1))
+    st, rd, rl = ref.search(q, 128, 6, k_per_query=kpq, nprobe_per_query=npq)
+    compare_results(gd, gl, rd, rl)
+    # after deletes (tail moves) the lists are read again
+    assert ix.remove(ids[::3]) is not None and ix.sync() == 0
+    assert ref.remove(ids[::3])[0] == 0
+    gd, gl = _both(ix, q, 100, 4, sched=(16, 12, 0))
+    st, rd, rl = ref.search(q, 100, 4)
+    compare_results(gd, gl, rd, rl)
+    say("  k = 100/128 certified scan: identical to the VALU scan and the oracle on split lists")
+
+
+@pytest.mark.parametrize("deep", [(4, 12, 1), (8, 10, 0), (16, 13, 1), (16, 11, 0)])
+def test_cert_two_pass_mixed_k(deep):
+    """A certified-scan search whose per-query k straddles 64 runs two passes
+    (k <= 64 certified, k > 64 on the deep schedule) over one snapshot: equal
+    to the oracle and to the single-pass VALU scan, for every deep schedule,
+    with k = 0 queries, k exactly 64 and 65, and lists split into chunks; the
+    profile counts each search once."""
+    rng = np.random.default_rng([79, deep[0], deep[1]])
+    sizes = [12000, 5000, 700, 65, 1, 0, 3000]
+    d = 40
+    cent = (rng.standard_normal((len(sizes), d)) * 6).astype(np.float32)
+    x = np.concatenate([cent[l] + rng.standard_normal((s, d)) for l, s in enumerate(sizes) if s]).astype(np.float32)
+    x[200:260] = x[:60]
+    ids = rng.permutation(x.shape[0]).astype(np.int64)
+    q = (cent[rng.integers(0, len(sizes), 400)] + rng.standard_normal((400, d))).astype(np.float32)
+    ix = sivf.Index(d, len(sizes), cent, metric=0, slab_capacity=32, num_slabs=900, id_capacity=x.shape[0],
+                    max_batch=1 << 15, max_queries=q.shape[0], max_k=128, max_nprobe=7)
+    ref = oracle.OracleIndex(d, len(sizes), cent, 0, 32, 900, x.shape[0])
+    ix.add(x, ids)
+    assert ix.sync() == 0
+    assert ref.add(x, ids) == 0
+    kpq = rng.choice([0, 1, 7, 16, 33, 64, 65, 100, 128], q.shape[0]).astype(np.int32)
+    npq = rng.integers(1, 8, q.shape[0]).astype(np.int32)
+    ix.set_deep_schedule(*deep)
+    assert ix.search_schedule()[1] == deep
+    st, rd, rl = ref.search(q, 128, 7, k_per_query=kpq, nprobe_per_query=npq)
+    gd, gl = _both(ix, q, 128, 7, kpq, npq, sched=(16, 12, 1))
+    compare_results(gd, gl, rd, rl)
+    # one k for all: k > 64 runs the deep pass alone, k <= 64 the certified scan alone
+    for k in (100, 40):
+        st, rd, rl = ref.search(q, k, 5)
+        gd, gl = _both(ix, q, k, 5, sched=(16, 10, 0))
+        compare_results(gd, gl, rd, rl)
+    ix.set_search_schedule(16, 12, 1)
+    ix.profile(True)
+    for _ in range(3):
+        ix.search(q, 128, 7, k_per_query=kpq, nprobe_per_query=npq)
+    assert ix.sync() == 0
+    prof = ix.profile_read()
+    ix.profile(False)
+    assert prof["search"][1] == 3 and prof["scan"][1] == 3 and prof["merge"][1] == 3, prof
+    assert prof["scan_deep"][1] == 3 and prof["scan_deep"][0] > 0, prof
+    say(f"  deep schedule {deep}: two-pass search identical to the oracle and the VALU scan")
+
+
+def test_deep_schedule_args():
+    rng = np.random.default_rng(80)
+    cent = rng.standard_normal((4, 32)).astype(np.float32)
+    ix = sivf.Index(32, 4, cent, slab_capacity=16, num_slabs=64, id_capacity=256, max_batch=256, max_queries=16,
+                    max_k=100, max_nprobe=4)
+    for bad in [(5, 12, 1), (16, 5, 0), (4, 12, 2)]:
+        with pytest.raises(sivf.SivfError):
+            ix.set_deep_schedule(*bad)
+    ix.set_deep_schedule(8, 14, 0)
+    assert ix.search_schedule()[1] == (8, 14, 0)
+    bx = sivf.Index(32, 4, cent, slab_capacity=16, num_slabs=64, id_capacity=256, max_batch=256, max_queries=16,
+                    max_k=10, max_nprobe=4, storage=sivf.BF16, rerank_factor=2)
+    with pytest.raises(sivf.SivfError):
+        bx.set_deep_schedule(4, 12, 1)
 
 
 def test_cert_random_configs():
