@@ -239,6 +239,86 @@ sivf_status sivf_graph_destroy(sivf_graph *g);
  * NULL) receives the number reclaimed; call again while it is positive. */
 sivf_status sivf_compact(sivf_index *ix, float min_dead_fraction, int64_t *n_compacted, void *stream);
 
+/* ---- Host tier: cold lists in host memory (the hierarchical storage the
+ * paper plans as future work, Sec. 6: cold slabs offloaded to host memory so
+ * that the window may outgrow device memory).
+ *
+ * A second slab pool, in the device pool's layout, whose rows and ids live in
+ * caller-provided pinned host memory (the GPU reads and writes it in place
+ * over the host link) and whose bookkeeping -- validity bits, slab directory,
+ * free stacks, per-list cold lengths and dead counts, per-list probe counts --
+ * lives in a caller-provided device buffer.  Offloading a list moves every
+ * position of it (live or dead) to the end of its cold segment and returns its
+ * device slabs to the pool; later inserts into the list go to device slabs as
+ * usual.  Results are unchanged: a search scans each probed list's cold
+ * segment too (the VALU scan, reading host memory; profile class
+ * SIVF_PROF_SCAN_COLD) and merges both; a delete of a cold entry clears its
+ * validity bit in the device-resident cold bitmap (Alg. 4 as for device
+ * slots); sivf_get_rows, sivf_save and the live count of sivf_stats include cold
+ * entries; sivf_dump shows the device pool only (sivf_tier_dump the rest).
+ * Requires fp32 storage and SIVF_DELETE_LAZY; host_slabs >= 1 with
+ * (num_slabs + host_slabs) * slab_capacity < 2^31.  The management calls
+ * (attach, offload, reclaim, maintain) wait for the index's stream and must
+ * not overlap other calls on the index. */
+
+/* Bytes of the two tier buffers for host_slabs cold slabs (SIVF_ERR_ARG if
+ * the index cannot take a tier). */
+sivf_status sivf_tier_bytes(const sivf_index *ix, int64_t host_slabs, size_t *host_bytes, size_t *dev_bytes);
+
+/* Attach an empty host tier (once per index).  host_buf: pinned host memory
+ * the device can address (hipHostMalloc), 256-byte aligned; dev_buf: device
+ * memory, 256-byte aligned; both owned by the caller and kept until
+ * sivf_destroy.  SIVF_ERR_ARG for other buffers or sizes, SIVF_ERR_STATE if
+ * a tier is already attached. */
+sivf_status sivf_tier_attach(sivf_index *ix, int64_t host_slabs, void *host_buf, size_t host_bytes, void *dev_buf,
+                             size_t dev_bytes, void *stream);
+
+/* Move the n lists in `lists` (host int32, distinct list ids) to the tier:
+ * every position of each goes to the end of its cold segment (dead slots stay
+ * dead) and its device slabs return to the pool.  *moved (host, or NULL) =
+ * positions moved.  SIVF_ERR_NOSPACE (nothing moved) if the cold pool lacks
+ * the slabs; SIVF_ERR_STATE without a tier.  Waits. */
+sivf_status sivf_tier_offload(sivf_index *ix, int32_t n, const int32_t *lists, int64_t *moved, void *stream);
+
+/* Release every cold segment with no live entry left (a sliding window's old
+ * entries die together); *released (host, or NULL) = positions released.
+ * Partly dead segments stay until they die.  Waits. */
+sivf_status sivf_tier_reclaim(sivf_index *ix, int64_t *released, void *stream);
+
+/* Counts of the tier (host int64 each, any may be NULL; zeros without a
+ * tier): live cold entries, cold positions, cold slabs in use, free cold
+ * slabs.  Waits. */
+sivf_status sivf_tier_stats(sivf_index *ix, int64_t *cold_live, int64_t *cold_positions, int64_t *cold_used_slabs,
+                            int64_t *cold_free_slabs);
+
+/* Host copy of the cold segments: cold_len[nlist] and, list after list in
+ * position order, each cold position's id (-1 for a dead slot) in
+ * cold_ids_by_list[sum of cold_len] (either may be NULL).  Waits. */
+sivf_status sivf_tier_dump(sivf_index *ix, int32_t *cold_len, int64_t *cold_ids_by_list);
+
+/* Per-list probe counts since the tier was attached (host int32[nlist]): a
+ * search's first pass adds each list's (query, probe) pairs, saturating.
+ * halve != 0 halves the stored counts after reading them (decay).  Waits. */
+sivf_status sivf_list_heat(sivf_index *ix, int32_t *heat, int halve);
+
+typedef struct {
+    int64_t compacted;            /* dead device slots reclaimed by compaction */
+    int64_t reclaimed;            /* cold positions released (dead segments) */
+    int64_t offloaded_positions;  /* positions moved to the tier */
+    int32_t offloaded_lists;      /* lists moved to the tier */
+    int32_t reserved;
+} sivf_maintain_report;
+
+/* Adaptive maintenance (the background compaction policy of Sec. 6), for an
+ * idle moment of the index: (1) with lazy deletes, sivf_compact at
+ * min_dead_fraction until a call reclaims nothing; (2) with a tier, release
+ * dead cold segments; (3) with a tier, while the device pool has fewer than
+ * min_free_slabs free slabs, offload non-empty lists in ascending probe count
+ * (at most max_offload lists), then halve the probe counts.  rep (host, or
+ * NULL) receives what was done.  Waits. */
+sivf_status sivf_maintain(sivf_index *ix, float min_dead_fraction, int64_t min_free_slabs, int32_t max_offload,
+                          sivf_maintain_report *rep, void *stream);
+
 /* Nearest list of each vector (the coarse assignment used by sivf_add).
  * x: device n x dim fp32; lists: device n int32.  n <= max(max_batch, max_queries). */
 sivf_status sivf_assign(sivf_index *ix, int64_t n, const float *x, int32_t *lists, void *stream);
@@ -286,13 +366,14 @@ sivf_status sivf_get_rows(sivf_index *ix, int64_t n, const int64_t *ids, float *
 sivf_status sivf_sync(sivf_index *ix, sivf_status *device_status);
 
 /* Counters (waits for the handle's last stream).  Any pointer may be NULL.
- * live = entries in all lists; used = slabs held by lists; free = slabs on the
- * free stack.  used + free = num_slabs. */
+ * live = entries in all lists (host-tier entries included); used = device
+ * slabs held by lists; free = slabs on the free stack.  used + free =
+ * num_slabs. */
 sivf_status sivf_stats(sivf_index *ix, int64_t *live, int64_t *used_slabs, int64_t *free_slabs);
 
 /* Sizes of the arrays sivf_dump fills (waits for the handle's last stream). */
 typedef struct {
-    int64_t live;        /* entries in all lists                         */
+    int64_t live;        /* entries in all lists' device slabs           */
     int64_t used_slabs;  /* sum over lists of ceil(len / C)              */
     int64_t free_slabs;  /* entries on the free stack                    */
     int64_t num_slabs;
@@ -329,7 +410,8 @@ typedef enum {
     SIVF_PROF_SCAN = 4,    /* the slab scan kernel of a search (its first pass) */
     SIVF_PROF_MERGE = 5,   /* the final top-k merge kernels of a search      */
     SIVF_PROF_SCAN_DEEP = 6, /* the k > 64 pass's scan of a two-pass search  */
-    SIVF_PROF_KINDS = 7
+    SIVF_PROF_SCAN_COLD = 7, /* the host-tier scan of a search               */
+    SIVF_PROF_KINDS = 8
 } sivf_prof_kind;
 
 /* Turn event recording on (on != 0) or off. */

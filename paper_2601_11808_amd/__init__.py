@@ -51,6 +51,11 @@ class SivfDumpInfo(ct.Structure):
                 ("nlist", ct.c_int32), ("slab_capacity", ct.c_int32), ("positions", ct.c_int64)]
 
 
+class SivfMaintainReport(ct.Structure):
+    _fields_ = [("compacted", ct.c_int64), ("reclaimed", ct.c_int64), ("offloaded_positions", ct.c_int64),
+                ("offloaded_lists", ct.c_int32), ("reserved", ct.c_int32)]
+
+
 # (name, restype, argtypes) of every exported entry point of include/sivf.h
 _P, _I32, _I64 = ct.c_void_p, ct.c_int32, ct.c_int64
 SIGNATURES = [
@@ -64,6 +69,14 @@ SIGNATURES = [
                                     ct.POINTER(_I32), ct.POINTER(_I32)]),
     ("sivf_set_search_schedule", ct.c_int, [_P, _I32, _I32, _I32]),
     ("sivf_set_deep_schedule", ct.c_int, [_P, _I32, _I32, _I32]),
+    ("sivf_tier_bytes", ct.c_int, [_P, _I64, ct.POINTER(ct.c_size_t), ct.POINTER(ct.c_size_t)]),
+    ("sivf_tier_attach", ct.c_int, [_P, _I64, _P, ct.c_size_t, _P, ct.c_size_t, _P]),
+    ("sivf_tier_offload", ct.c_int, [_P, _I32, _P, ct.POINTER(_I64), _P]),
+    ("sivf_tier_reclaim", ct.c_int, [_P, ct.POINTER(_I64), _P]),
+    ("sivf_tier_stats", ct.c_int, [_P, ct.POINTER(_I64), ct.POINTER(_I64), ct.POINTER(_I64), ct.POINTER(_I64)]),
+    ("sivf_tier_dump", ct.c_int, [_P, _P, _P]),
+    ("sivf_list_heat", ct.c_int, [_P, _P, ct.c_int]),
+    ("sivf_maintain", ct.c_int, [_P, ct.c_float, _I64, _I32, ct.POINTER(SivfMaintainReport), _P]),
     ("sivf_get_search_schedule", ct.c_int, [_P, _P]),
     ("sivf_step", ct.c_int, [_P, ct.POINTER(SivfStepArgs), _P]),
     ("sivf_graph_create", ct.c_int, [_P, ct.POINTER(SivfStepArgs), ct.POINTER(_P)]),
@@ -414,7 +427,7 @@ class Index:
         _check(lib().sivf_stats(self._h, ct.byref(a), ct.byref(b), ct.byref(c)), "sivf_stats")
         return {"live": a.value, "used_slabs": b.value, "free_slabs": c.value}
 
-    PROF_KINDS = ("add", "remove", "search", "coarse", "scan", "merge", "scan_deep")
+    PROF_KINDS = ("add", "remove", "search", "coarse", "scan", "merge", "scan_deep", "scan_cold")
 
     def profile(self, on=True):
         _check(lib().sivf_profile_enable(self._h, 1 if on else 0), "sivf_profile_enable")
@@ -448,16 +461,75 @@ class Index:
         return out
 
     def membership(self):
-        """{list id: sorted id array} for non-empty lists (from a dump)."""
+        """{list id: sorted id array} for non-empty lists (from a dump; with a
+        host tier, device and cold entries together)."""
         d = self.dump()
         offs = np.concatenate([[0], np.cumsum(d["list_len"].astype(np.int64))])
+        cold = self.tier_dump() if getattr(self, "_tier", None) is not None else None
+        if cold is not None:
+            coffs = np.concatenate([[0], np.cumsum(cold["cold_len"].astype(np.int64))])
         out = {}
         for l in range(self.nlist):
             v = d["ids_by_list"][offs[l]:offs[l + 1]]
+            if cold is not None:
+                v = np.concatenate([v, cold["cold_ids"][coffs[l]:coffs[l + 1]]])
             v = v[v >= 0]                      # lazily deleted slots read -1
             if v.shape[0]:
                 out[l] = np.sort(v)
         return out
+
+    # -- host tier -------------------------------------------------------
+    def tier_attach(self, host_slabs, stream=None):
+        """Attach a host tier of host_slabs cold slabs (pinned host memory for
+        rows and ids, a device buffer for the rest; see sivf_tier_attach)."""
+        torch = _torch()
+        hb, db = ct.c_size_t(), ct.c_size_t()
+        _check(lib().sivf_tier_bytes(self._h, int(host_slabs), ct.byref(hb), ct.byref(db)), "sivf_tier_bytes")
+        host = torch.empty(hb.value, dtype=torch.uint8, pin_memory=True)
+        dev = torch.empty(db.value, dtype=torch.uint8, device=self.device)
+        _check(lib().sivf_tier_attach(self._h, int(host_slabs), _ptr(host), hb.value, _ptr(dev), db.value,
+                                      self._stream(stream)), "sivf_tier_attach")
+        self._tier = (host, dev)
+
+    def tier_offload(self, lists, stream=None):
+        """Move whole lists to the host tier; returns the positions moved."""
+        arr = np.ascontiguousarray(np.asarray(lists, dtype=np.int32).reshape(-1))
+        moved = ct.c_int64()
+        _check(lib().sivf_tier_offload(self._h, arr.shape[0], arr.ctypes.data_as(ct.c_void_p), ct.byref(moved),
+                                       self._stream(stream)), "sivf_tier_offload")
+        return moved.value
+
+    def tier_reclaim(self, stream=None):
+        """Release dead cold segments; returns the positions released."""
+        n = ct.c_int64()
+        _check(lib().sivf_tier_reclaim(self._h, ct.byref(n), self._stream(stream)), "sivf_tier_reclaim")
+        return n.value
+
+    def tier_stats(self):
+        v = [ct.c_int64() for _ in range(4)]
+        _check(lib().sivf_tier_stats(self._h, *[ct.byref(x) for x in v]), "sivf_tier_stats")
+        return dict(zip(("cold_live", "cold_positions", "cold_used_slabs", "cold_free_slabs"), (x.value for x in v)))
+
+    def tier_dump(self):
+        """{"cold_len": int32[nlist], "cold_ids": int64 ids by list (-1: dead)}."""
+        clen = np.empty(self.nlist, np.int32)
+        _check(lib().sivf_tier_dump(self._h, clen.ctypes.data_as(ct.c_void_p), None), "sivf_tier_dump")
+        ids = np.empty(int(clen.astype(np.int64).sum()), np.int64)
+        _check(lib().sivf_tier_dump(self._h, None, ids.ctypes.data_as(ct.c_void_p)), "sivf_tier_dump")
+        return {"cold_len": clen, "cold_ids": ids}
+
+    def list_heat(self, halve=False):
+        h = np.empty(self.nlist, np.int32)
+        _check(lib().sivf_list_heat(self._h, h.ctypes.data_as(ct.c_void_p), 1 if halve else 0), "sivf_list_heat")
+        return h
+
+    def maintain(self, min_dead_fraction=0.0, min_free_slabs=0, max_offload=0, stream=None):
+        """Compaction, dead cold segments, and offload of the least probed
+        lists below a free-slab mark (see sivf_maintain); returns its report."""
+        r = SivfMaintainReport()
+        _check(lib().sivf_maintain(self._h, float(min_dead_fraction), int(min_free_slabs), int(max_offload),
+                                   ct.byref(r), self._stream(stream)), "sivf_maintain")
+        return {k: getattr(r, k) for k, _ in SivfMaintainReport._fields_ if k != "reserved"}
 
 
 def checkpoint_config(path):

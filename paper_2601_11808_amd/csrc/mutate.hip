@@ -81,7 +81,9 @@ __global__ __launch_bounds__(256) void k_add_count(Dev S, int n, const int64_t *
     if (active) rank[i] = win ? r : -1;
     const uint32_t g = win ? S.att[u] : INVALID;
     const bool live = g != INVALID;
-    const int lo = live ? S.sowner[g / (uint32_t)S.C] : 0;
+    // with compacting deletes only (the host tier, whose positions index no
+    // device slab, needs lazy deletes)
+    const int lo = (live && !S.bits) ? S.sowner[g / (uint32_t)S.C] : 0;
     // an upsert frees a position only with compacting deletes (a lazy delete leaves a dead slot)
     list_agg_inc<BLK>(S.l_prem, lo, live && !S.bits, hist, S.nlist, false);
     if (ballot(live) && lane_id() == 0) {
@@ -562,6 +564,8 @@ __global__ void k_rm_lazy_begin(int32_t *ctl) {
 // O(1) and makes exactly one thread own the id; the atomic AND clears its
 // validity bit, and the old word shows the 1 -> 0 transition that counts the
 // removal (Theorem 3).  Nothing moves; the slot stays dead until compaction.
+// An entry in the host tier loses its bit in the device-resident cold bitmap
+// the same way.
 template <bool BLK>
 __global__ __launch_bounds__(256) void k_rm_lazy(Dev S, int n, const int64_t *__restrict__ ids, int mode) {
     extern __shared__ int32_t hist[];
@@ -570,18 +574,21 @@ __global__ __launch_bounds__(256) void k_rm_lazy(Dev S, int n, const int64_t *__
     const int64_t u = i < n ? ids[i] : -1;
     const bool active = u >= 0 && u < S.id_capacity;
     const uint32_t g = active ? atomicExch(&S.att[u], INVALID) : INVALID;
-    bool gone = false;
+    bool gone = false, cold = false;
     int l = 0;
     if (g != INVALID) {
-        const int64_t slab = g / (uint32_t)S.C;
-        const int slot = (int)(g % (uint32_t)S.C);
+        cold = (g & COLD_BIT) != 0;
+        const uint32_t pos = g & ~COLD_BIT;
+        const int64_t slab = pos / (uint32_t)S.C;
+        const int slot = (int)(pos % (uint32_t)S.C);
         const uint64_t bit = 1ull << (slot & 63);
-        const uint64_t old = __hip_atomic_fetch_and(S.bits + slab * S.bw + (slot >> 6), ~bit, __ATOMIC_RELAXED,
-                                                    __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t old = __hip_atomic_fetch_and((cold ? S.cbits : S.bits) + slab * S.bw + (slot >> 6), ~bit,
+                                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         gone = (old & bit) != 0;
-        l = S.sowner[slab];
+        l = cold ? S.csowner[slab] : S.sowner[slab];
     }
-    list_agg_inc<BLK>(S.l_dead, l, gone, hist, S.nlist, false);
+    list_agg_inc<BLK>(S.l_dead, l, gone && !cold, hist, S.nlist, false);
+    if (gone && cold) atomicAdd(&S.cdead[l], 1);
     const uint64_t gm = ballot(gone);
     if (gm && lane_id() == __builtin_ctzll(gm)) atomicAdd(&S.ctl[CTL_RMTOT], (int)__builtin_popcountll(gm));
 }
@@ -677,7 +684,8 @@ __global__ __launch_bounds__(256) void k_get_rows(Dev S, int n, const int64_t *_
         for (int j = sub; j < S.d; j += 16) out[j] = __int_as_float(0x7FC00000);
         return;
     }
-    const float4 *src = S.data + (int64_t)(g / S.C) * S.dp4 * S.C + g % S.C;
+    const uint32_t pos = g & ~COLD_BIT;   // a host-tier entry reads its row from host memory
+    const float4 *src = ((g & COLD_BIT) ? S.cdata : S.data) + (int64_t)(pos / S.C) * S.dp4 * S.C + pos % S.C;
     for (int c = sub; c < S.dp4; c += 16) {
         const float4 v = src[(int64_t)c * S.C];
         const float e[4] = {v.x, v.y, v.z, v.w};
@@ -687,10 +695,11 @@ __global__ __launch_bounds__(256) void k_get_rows(Dev S, int n, const int64_t *_
 }
 
 // Checkpoint packing: entries [e0, e0 + n) of all lists in list order (list
-// l's entries are e in [off[l], off[l] + len[l]), positions ascending) ->
-// fp32 rows (d floats each) and ids.  One wave per entry.
-__global__ __launch_bounds__(256) void k_pack(Dev S, const int32_t *__restrict__ off, int64_t e0, int n,
-                                              float *__restrict__ rows, uint32_t *__restrict__ ids) {
+// l's entries are e in [off[l], off[l + 1]), positions ascending; with a host
+// tier (tier = 1) its cold segment, viewed as Sc, follows its len[l] device
+// positions) -> fp32 rows (d floats each) and ids.  One wave per entry.
+__global__ __launch_bounds__(256) void k_pack(Dev S, Dev Sc, int tier, const int32_t *__restrict__ off, int64_t e0,
+                                              int n, float *__restrict__ rows, uint32_t *__restrict__ ids) {
     const int i = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
     if (i >= n) return;
     const int64_t e = e0 + i;
@@ -702,9 +711,13 @@ __global__ __launch_bounds__(256) void k_pack(Dev S, const int32_t *__restrict__
         else
             hi = mid - 1;
     }
-    const int p = (int)(e - off[lo]);
-    const int slab = slab_of(S, lo, p / S.C), slot = p % S.C;
-    const float4 *src = S.data + (int64_t)slab * S.dp4 * S.C + slot;
+    int p = (int)(e - off[lo]);
+    const bool cold = tier && p >= S.len[lo];
+    if (cold) p -= S.len[lo];
+    const int slab = cold ? slab_of(Sc, lo, p / S.C) : slab_of(S, lo, p / S.C), slot = p % S.C;
+    const float4 *src = (cold ? Sc.data : S.data) + (int64_t)slab * S.dp4 * S.C + slot;
+    const uint64_t *bits = cold ? Sc.bits : S.bits;
+    const uint32_t *sids = cold ? Sc.sids : S.sids;
     float *out = rows + (int64_t)i * S.d;
     for (int c = lane_id(); c < S.dp4; c += 64) {
         const float4 v = src[(int64_t)c * S.C];
@@ -713,8 +726,77 @@ __global__ __launch_bounds__(256) void k_pack(Dev S, const int32_t *__restrict__
             if (4 * c + t < S.d) out[4 * c + t] = ev[t];
     }
     if (lane_id() == 0) {
-        const bool live = !S.bits || ((S.bits[(int64_t)slab * S.bw + (slot >> 6)] >> (slot & 63)) & 1ull);
-        ids[i] = live ? S.sids[(int64_t)slab * S.C + slot] : INVALID;
+        const bool live = !bits || ((bits[(int64_t)slab * S.bw + (slot >> 6)] >> (slot & 63)) & 1ull);
+        ids[i] = live ? sids[(int64_t)slab * S.C + slot] : INVALID;
+    }
+}
+
+// ------------------------------------------------------------ host tier
+//
+// The cold pool is a second slab pool in the device pool's layout, held in
+// pinned host memory (rows, ids) with its bookkeeping on the device; Sc is
+// the device struct viewing it (its per-list scratch arrays are the device
+// pool's).  Offloading a list moves every position of it to the end of the
+// list's cold segment: the add allocator on Sc gives the cold slabs, a copy
+// moves rows, ids and validity bits and points live ids' address-table
+// entries at their cold positions, and the remove finalizer releases the
+// list's device slabs.
+
+// One block: per offloaded list, its positions as the cold allocation and as
+// the device-pool release.
+__global__ __launch_bounds__(1024) void k_tier_plan(Dev S, Dev Sc, const int32_t *__restrict__ olist, int n) {
+    for (int i = threadIdx.x; i < n; i += 1024) {
+        const int l = olist[i];
+        const int cnt = S.len[l];
+        S.l_acnt[l] = cnt;              // new cold positions (the add allocator on the cold view)
+        S.l_m[l] = cnt;                 // every device position leaves (the remove finalizer)
+        Sc.l_dead[l] += S.l_dead[l];    // dead slots move along, still dead
+        S.l_dead[l] = cnt;              // the finalizer subtracts the positions it releases
+    }
+    if (threadIdx.x == 0) Sc.ctl[CTL_EBASE] = 0;
+}
+
+// Grid (ceil(longest / 256), lists): one thread per position of an offloaded
+// list; position p goes to cold position l_base[l] + p (after the segment's
+// earlier entries).  Runs before the device slabs are released.
+__global__ __launch_bounds__(256) void k_tier_copy(Dev S, Dev Sc, const int32_t *__restrict__ olist) {
+    const int l = olist[blockIdx.y];
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= S.len[l]) return;
+    const int C = S.C;
+    const int hs = slab_of(S, l, p / C), hsl = p % C;
+    const int cp = S.l_base[l] + p;
+    const int cs = slab_of(Sc, l, cp / C), csl = cp % C;
+    const float4 *src = S.data + (int64_t)hs * S.dp4 * C + hsl;
+    float4 *dst = Sc.data + (int64_t)cs * S.dp4 * C + csl;
+    for (int c = 0; c < S.dp4; c++) dst[(int64_t)c * C] = src[(int64_t)c * C];
+    const uint32_t id = S.sids[(int64_t)hs * C + hsl];
+    Sc.sids[(int64_t)cs * C + csl] = id;
+    if ((S.bits[(int64_t)hs * S.bw + (hsl >> 6)] >> (hsl & 63)) & 1ull) {   // live: its id now lives in the tier
+        atomicOr((unsigned long long *)(Sc.bits + (int64_t)cs * S.bw + (csl >> 6)), 1ull << (csl & 63));
+        S.att[id] = COLD_BIT | ((uint32_t)cs * (uint32_t)C + (uint32_t)csl);
+    }
+}
+
+// One block: cold segments with no live entry left leave whole (the remove
+// finalizer on the cold view releases their slabs); the number of released
+// positions goes to *n_out.
+__global__ __launch_bounds__(1024) void k_tier_reclaim_plan(Dev Sc, int64_t *n_out) {
+    __shared__ long long sred[16];
+    long long tot = 0;
+    for (int l = threadIdx.x; l < Sc.nlist; l += 1024) {
+        const int n = Sc.len[l];
+        const bool dead = n > 0 && Sc.l_dead[l] == n;
+        Sc.l_m[l] = dead ? n : 0;
+        tot += dead ? n : 0;
+    }
+    for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o);
+    if (lane_id() == 0) sred[threadIdx.x >> 6] = tot;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long t = 0;
+        for (int w = 0; w < 16; w++) t += sred[w];
+        *n_out = t;
     }
 }
 
@@ -810,8 +892,25 @@ void launch_call_end(hipStream_t st, const Dev &S) {
     hipLaunchKernelGGL(k_call_end, dim3(1), dim3(64), 0, st, S.ctl);
 }
 
-void launch_pack(hipStream_t st, const Dev &S, const int32_t *off, int64_t e0, int n, float *rows, uint32_t *ids) {
-    if (n > 0) hipLaunchKernelGGL(k_pack, dim3((n + 3) / 4), dim3(256), 0, st, S, off, e0, n, rows, ids);
+void launch_pack(hipStream_t st, const Dev &S, const Dev *Sc, const int32_t *off, int64_t e0, int n, float *rows,
+                 uint32_t *ids) {
+    if (n > 0)
+        hipLaunchKernelGGL(k_pack, dim3((n + 3) / 4), dim3(256), 0, st, S, Sc ? *Sc : S, Sc ? 1 : 0, off, e0, n,
+                           rows, ids);
+}
+
+void launch_tier_offload(hipStream_t st, const Dev &S, const Dev &Sc, const int32_t *olist, int n, int longest) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_tier_plan, dim3(1), dim3(1024), 0, st, S, Sc, olist, n);
+    hipLaunchKernelGGL(k_add_alloc, dim3(blocks(S.nlist)), dim3(256), 0, st, Sc);
+    if (longest > 0)
+        hipLaunchKernelGGL(k_tier_copy, dim3(blocks(longest), (unsigned)n), dim3(256), 0, st, S, Sc, olist);
+    hipLaunchKernelGGL(k_rm_finalize, dim3(blocks(S.nlist)), dim3(256), 0, st, S, 0);
+}
+
+void launch_tier_reclaim(hipStream_t st, const Dev &Sc, int64_t *n_out) {
+    hipLaunchKernelGGL(k_tier_reclaim_plan, dim3(1), dim3(1024), 0, st, Sc, n_out);
+    hipLaunchKernelGGL(k_rm_finalize, dim3(blocks(Sc.nlist)), dim3(256), 0, st, Sc, 0);
 }
 
 void launch_get_rows(hipStream_t st, const Dev &S, int n, const int64_t *ids, float *rows) {

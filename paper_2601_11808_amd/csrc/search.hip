@@ -117,7 +117,7 @@ __device__ __forceinline__ int list_chunks(int len, int sh) {
 //     others finish long lists -- each at most xcd_cap items (the blocks an
 //     XCD receives in the dispatch schedule).
 __global__ __launch_bounds__(1024) void k_inv_plan(Dev S, int T, int sh0, int64_t slot_cap, int64_t item_cap,
-                                                   int xcd_cap, int snap) {
+                                                   int xcd_cap, int snap, int32_t *__restrict__ heat) {
     __shared__ int sbuf[16];
     __shared__ long long sred[32];
     __shared__ long long scost[16];
@@ -131,6 +131,8 @@ __global__ __launch_bounds__(1024) void k_inv_plan(Dev S, int T, int sh0, int64_
         const int ep = block_excl_scan<1024>(qc, sbuf, &tp);
         if (valid) {
             if (snap) S.l_snap[l] = S.len[l];
+            // probe count per list (host tier: the coldest lists are offloaded first), saturating
+            if (heat && qc > 0) heat[l] = (int32_t)min((int64_t)heat[l] + qc, (int64_t)0x7FFFFFFF);
             S.l_qoff[l] = carry_p + ep;
             S.l_qcs[l] = qc;
             S.l_qc[l] = 0;
@@ -665,11 +667,16 @@ __global__ __launch_bounds__(256) void k_chunk_merge(Dev S, int npairs, const in
 // probe partial lists (each sorted, kcap long; a split list's chunks were
 // merged into its first slot).  k: the call's k; each query keeps kmul * (its
 // k) results, at most out_stride (the row stride of dist / labels, <= 128).
+// prior (or NULL): one more sorted source per query, prior_stride keys (~0
+// padded) -- the host tier's results; keys_out (or NULL): write the sorted
+// keys there (stride out_stride, ~0 padded) instead of dist / labels.
 __global__ __launch_bounds__(256) void k_merge(Dev S, int nq, int np_stride, const int32_t *__restrict__ probes,
                                                const int32_t *__restrict__ pair_rank,
                                                const uint64_t *__restrict__ partials, int kcap, int out_stride,
                                                int k, int kmul, const int32_t *__restrict__ kpq,
-                                               float *__restrict__ dist, int64_t *__restrict__ labels, KClass cls) {
+                                               float *__restrict__ dist, int64_t *__restrict__ labels, KClass cls,
+                                               const uint64_t *__restrict__ prior, int prior_stride,
+                                               uint64_t *__restrict__ keys_out) {
     __shared__ unsigned char heads[4][1024];
     const int w = threadIdx.x >> 6, lane = lane_id();
     const int qi = blockIdx.x * 4 + w;
@@ -700,12 +707,22 @@ __global__ __launch_bounds__(256) void k_merge(Dev S, int nq, int np_stride, con
         }
     }
     uint64_t res = ~0ull, res2 = ~0ull;   // result r sits in lane r (r < 64) or lane r - 64 of res2
+    const uint64_t *prow_k = prior ? prior + (int64_t)qi * prior_stride : nullptr;
+    int ph = 0;   // next key of the prior source (wave-uniform)
+    uint64_t pv = prow_k ? prow_k[0] : ~0ull;
     for (int r = 0; r < kq; r++) {
         uint64_t m = best;
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
             const uint64_t u = shfl_xor_u64(m, o);
             m = u < m ? u : m;
+        }
+        if (pv < m) {   // the prior source's head is smallest (keys are distinct)
+            if (lane == r) res = pv;
+            if (lane + 64 == r) res2 = pv;
+            ph++;
+            pv = ph < prior_stride ? prow_k[ph] : ~0ull;
+            continue;
         }
         if (m == ~0ull) break;
         if (lane == r) res = m;
@@ -728,7 +745,9 @@ __global__ __launch_bounds__(256) void k_merge(Dev S, int nq, int np_stride, con
         if (r < out_stride) {
             const uint64_t key = h ? res2 : res;
             const int64_t o = (int64_t)qi * out_stride + r;
-            if (r < kq && key != ~0ull) {
+            if (keys_out) {
+                keys_out[o] = r < kq ? key : ~0ull;
+            } else if (r < kq && key != ~0ull) {
                 dist[o] = key_value(key, S.metric);
                 labels[o] = (int64_t)(uint32_t)key;
             } else {
@@ -1531,7 +1550,8 @@ static void launch_scan_t(hipStream_t st, const Dev &S, const SearchBufs &W, con
     else launch_scan_p<T, WIDE, false>(st, S, W, q, np_stride, kcap, k, kpq, npairs);
 }
 
-void launch_search_plan(hipStream_t st, const Dev &S, const SearchBufs &W, int nq, const KClass &cls, int snap) {
+void launch_search_plan(hipStream_t st, const Dev &S, const SearchBufs &W, int nq, const KClass &cls, int snap,
+                        int32_t *heat) {
     const int np_stride = cls.np_stride;
     const int npairs = nq * np_stride;
     const unsigned pb = (unsigned)((npairs + 255) / 256);
@@ -1543,7 +1563,7 @@ void launch_search_plan(hipStream_t st, const Dev &S, const SearchBufs &W, int n
         hipLaunchKernelGGL(k_inv_count, dim3(pb), dim3(256), 0, st, S, npairs, W.probes, W.pair_rank, cls);
     const int64_t lim = item_limit(S, W, npairs);
     hipLaunchKernelGGL(k_inv_plan, dim3(1), dim3(1024), 0, st, S, T, S.chunk_shift, W.slot_cap, lim,
-                       (int)((lim + 7) / 8), snap);
+                       (int)((lim + 7) / 8), snap, heat);
     hipLaunchKernelGGL(k_inv_items, dim3((S.nlist + 3) / 4), dim3(256), 0, st, S, T, W.item_list, W.item_tile,
                        W.item_chunk);
     hipLaunchKernelGGL(k_inv_scatter, dim3(pb), dim3(256), 0, st, S, npairs, W.probes, W.pair_rank,
@@ -1605,7 +1625,7 @@ void launch_search_scan(hipStream_t st, const Dev &S, const SearchBufs &W, int n
 
 void launch_search_merge(hipStream_t st, const Dev &S, const SearchBufs &W, int nq, const KClass &cls, int kcap,
                          int out_stride, int k, int kmul, const int32_t *k_per_query, float *dist,
-                         int64_t *labels) {
+                         int64_t *labels, const uint64_t *prior, int prior_stride, uint64_t *keys_out) {
     const int np_stride = cls.np_stride;
     const int npairs = nq * np_stride;
     const unsigned pb = (unsigned)((npairs + 255) / 256);
@@ -1616,7 +1636,8 @@ void launch_search_merge(hipStream_t st, const Dev &S, const SearchBufs &W, int 
         hipLaunchKernelGGL(k_chunk_merge<false>, dim3(pb), dim3(256), 0, st, S, npairs, W.probes, W.pair_rank,
                            W.partials, kcap);
     hipLaunchKernelGGL(k_merge, dim3((nq + 3) / 4), dim3(256), 0, st, S, nq, np_stride, W.probes, W.pair_rank,
-                       W.partials, kcap, out_stride, k, kmul, k_per_query, dist, labels, cls);
+                       W.partials, kcap, out_stride, k, kmul, k_per_query, dist, labels, cls, prior, prior_stride,
+                       keys_out);
 }
 
 }  // namespace sivf

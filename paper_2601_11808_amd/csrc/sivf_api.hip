@@ -8,6 +8,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <deque>
 #include <mutex>
@@ -164,6 +165,17 @@ struct sivf_index {
     ProfClass pc[SIVF_PROF_KINDS];
     // schedule of the k > 64 pass of a certified-scan search (tile, chunk shift, persistent)
     int deep_tile = 4, deep_shift = 13, deep_pers = 1;
+    // host tier (slabs == 0: none): V views the cold pool; its rows and ids sit in
+    // caller-provided pinned host memory, the rest in a caller-provided device buffer
+    struct {
+        int64_t slabs = 0;
+        Dev V{};
+        int32_t *heat = nullptr;     // per-list probe counts (searches add theirs)
+        uint64_t *prior = nullptr;   // [max_queries][kcap] keys of a search's cold pass
+        int32_t *olist = nullptr;    // [nlist] lists of an offload
+        int64_t *nout = nullptr;     // positions released by a reclaim
+        int64_t positions = 0;       // cold positions held (0: searches skip the cold pass)
+    } tier;
 };
 
 namespace {
@@ -331,16 +343,33 @@ sivf_status do_search(sivf_index *ix, int64_t nq, const float *q, int32_t k, con
         if (kpq) passes[np++] = {&ix->S, KClass{kpq, k, stride, -1, 64}, 64};
         passes[np++] = {&Sd, kpq ? KClass{kpq, k, stride, 64, 0x7FFFFFFF} : kclass_all(stride), 128};
     }
+    // host tier first: the probed lists' cold segments, scanned in host memory
+    // by the VALU scan; their sorted keys join each query's merge below
+    const uint64_t *prior = nullptr;
+    if (ix->tier.slabs > 0 && ix->tier.positions > 0) {
+        Dev Sv = ix->tier.V;
+        Sv.tile = ix->S.tile == 16 ? (c.dim <= 1024 ? 8 : 4) : ix->S.tile;
+        Sv.chunk_shift = ix->S.chunk_shift;
+        Sv.persistent = ix->S.persistent;
+        const KClass all = kclass_all(stride);
+        launch_search_plan(st, Sv, ix->W, (int)nq, all, 1);
+        const int pk = prof_begin(ix, SIVF_PROF_SCAN_COLD, st);
+        launch_search_scan(st, Sv, ix->W, (int)nq, q, stride, kw, k, kpq);
+        prof_end(ix, SIVF_PROF_SCAN_COLD, pk, st);
+        launch_search_merge(st, Sv, ix->W, (int)nq, all, kw, kw, k, 1, kpq, nullptr, nullptr, nullptr, 0,
+                            ix->tier.prior);
+        prior = ix->tier.prior;
+    }
     for (int i = 0; i < np; i++) {
         const Pass &P = passes[i];
-        launch_search_plan(st, *P.S, ix->W, (int)nq, P.cls, i == 0 ? 1 : 0);
+        launch_search_plan(st, *P.S, ix->W, (int)nq, P.cls, i == 0 ? 1 : 0, i == 0 ? ix->tier.heat : nullptr);
         if (i == 0 && snapshot_taken && !dev_ok(hipEventRecord(snapshot_taken, st))) return SIVF_ERR_DEVICE;
         const int sk = (split && P.S == &Sd) ? SIVF_PROF_SCAN_DEEP : SIVF_PROF_SCAN;
         const int pk = prof_begin(ix, sk, st);
         launch_search_scan(st, *P.S, ix->W, (int)nq, q, stride, P.kw, k, kpq);
         prof_end(ix, sk, pk, st);
         const int pm = prof_begin(ix, SIVF_PROF_MERGE, st, i > 0);
-        launch_search_merge(st, *P.S, ix->W, (int)nq, P.cls, P.kw, k, k, 1, kpq, dist, labels);
+        launch_search_merge(st, *P.S, ix->W, (int)nq, P.cls, P.kw, k, k, 1, kpq, dist, labels, prior, kw);
         prof_end(ix, SIVF_PROF_MERGE, pm, st);
     }
     prof_end(ix, SIVF_PROF_SEARCH, ps, st);
@@ -867,7 +896,9 @@ sivf_status sivf_stats(sivf_index *ix, int64_t *live, int64_t *used_slabs, int64
     sivf_dump_info info;
     sivf_status s = sivf_dump_info_get(ix, &info);
     if (s != SIVF_OK) return s;
-    if (live) *live = info.live;
+    int64_t cold_live = 0;   // entries in the host tier count as live too
+    if (ix->tier.slabs > 0 && (s = sivf_tier_stats(ix, &cold_live, nullptr, nullptr, nullptr)) != SIVF_OK) return s;
+    if (live) *live = info.live + cold_live;
     if (used_slabs) *used_slabs = info.used_slabs;
     if (free_slabs) *free_slabs = info.free_slabs;
     return SIVF_OK;
@@ -924,6 +955,338 @@ sivf_status sivf_dump(sivf_index *ix, int32_t *list_len, int32_t *list_slabs, in
     if (slab_owner && !d2h(slab_owner, S.sowner, (size_t)c.num_slabs * 4)) return SIVF_ERR_DEVICE;
     if (slab_ordinal && !d2h(slab_ordinal, S.sord, (size_t)c.num_slabs * 4)) return SIVF_ERR_DEVICE;
     if (att && !d2h(att, S.att, (size_t)c.id_capacity * 4)) return SIVF_ERR_DEVICE;
+    return SIVF_OK;
+}
+
+// ------------------------------------------------------------------ host tier
+
+namespace {
+
+// Byte layout of a host tier: rows and ids in host memory, bookkeeping on the device.
+struct TierLayout {
+    int64_t num_pages, dir_cap;
+    size_t host_total, data, sids;
+    size_t dev_total, bits, sowner, sord, free_slabs, free_pages, pages, dir, len, dead, heat, ctl, prior, olist, nout;
+};
+
+TierLayout tier_layout(const sivf_index *ix, int64_t hs) {
+    TierLayout T{};
+    const sivf_config &c = ix->cfg;
+    const int64_t C = c.slab_capacity, nl = c.nlist;
+    T.dir_cap = (hs + PAGE - 1) / PAGE + 1;
+    T.num_pages = (hs + PAGE - 1) / PAGE + nl;
+    size_t cur = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = cur;
+        cur = align_up(cur + (bytes ? bytes : 1));
+        return o;
+    };
+    T.data = take((size_t)hs * ix->L.dp4 * C * 16);
+    T.sids = take((size_t)hs * C * 4);
+    T.host_total = cur;
+    cur = 0;
+    T.bits = take((size_t)hs * ix->S.bw * 8);
+    T.sowner = take((size_t)hs * 4);
+    T.sord = take((size_t)hs * 4);
+    T.free_slabs = take((size_t)hs * 4);
+    T.free_pages = take((size_t)T.num_pages * 4);
+    T.pages = take((size_t)T.num_pages * PAGE * 4);
+    T.dir = take((size_t)nl * T.dir_cap * 4);
+    T.len = take((size_t)nl * 4);
+    T.dead = take((size_t)nl * 4);
+    T.heat = take((size_t)nl * 4);
+    T.ctl = take(CTL_WORDS * 4);
+    T.prior = take((size_t)c.max_queries * ix->L.kcap * 8);
+    T.olist = take((size_t)nl * 4);
+    T.nout = take(8);
+    T.dev_total = cur;
+    return T;
+}
+
+// fp32 slabs with lazy deletes; cold positions fit the address table's 31 bits and all
+// positions of both pools fit the int32 list offsets of a checkpoint
+bool tier_cfg_ok(const sivf_index *ix, int64_t hs) {
+    return ix->cfg.storage == SIVF_F32 && ix->S.bits && hs >= 1 &&
+           (hs + ix->cfg.num_slabs) * (int64_t)ix->cfg.slab_capacity < (1ll << 31);
+}
+
+// Cold lengths, dead counts and the cold pool's free-slab count (waits).
+sivf_status tier_counts(sivf_index *ix, std::vector<int32_t> &clen, std::vector<int32_t> &cdead, int32_t *cfree) {
+    const Dev &V = ix->tier.V;
+    clen.resize(ix->cfg.nlist);
+    cdead.resize(ix->cfg.nlist);
+    if (!dev_ok(hipStreamSynchronize(ix->last)) ||
+        !dev_ok(hipMemcpy(clen.data(), V.len, clen.size() * 4, hipMemcpyDeviceToHost)) ||
+        !dev_ok(hipMemcpy(cdead.data(), V.l_dead, cdead.size() * 4, hipMemcpyDeviceToHost)) ||
+        (cfree && !dev_ok(hipMemcpy(cfree, V.ctl + CTL_SLAB_TOP, 4, hipMemcpyDeviceToHost))))
+        return SIVF_ERR_DEVICE;
+    int64_t pos = 0;
+    for (int32_t v : clen) pos += v;
+    ix->tier.positions = pos;
+    return SIVF_OK;
+}
+
+}  // namespace
+
+sivf_status sivf_tier_bytes(const sivf_index *ix, int64_t host_slabs, size_t *host_bytes, size_t *dev_bytes) {
+    if (!ix || !tier_cfg_ok(ix, host_slabs)) return SIVF_ERR_ARG;
+    const TierLayout T = tier_layout(ix, host_slabs);
+    if (host_bytes) *host_bytes = T.host_total;
+    if (dev_bytes) *dev_bytes = T.dev_total;
+    return SIVF_OK;
+}
+
+sivf_status sivf_tier_attach(sivf_index *ix, int64_t host_slabs, void *host_buf, size_t host_bytes, void *dev_buf,
+                             size_t dev_bytes, void *stream) {
+    if (!ix || !host_buf || !dev_buf || !tier_cfg_ok(ix, host_slabs)) return SIVF_ERR_ARG;
+    if (ix->broken || ix->tier.slabs > 0) return SIVF_ERR_STATE;
+    const TierLayout T = tier_layout(ix, host_slabs);
+    if (host_bytes < T.host_total || dev_bytes < T.dev_total || ((uintptr_t)host_buf % ALIGN) != 0 ||
+        ((uintptr_t)dev_buf % ALIGN) != 0)
+        return SIVF_ERR_ARG;
+    // the host buffer must be pinned host memory the device reads and writes
+    hipPointerAttribute_t a{};
+    if (!dev_ok(hipPointerGetAttributes(&a, host_buf)) || a.type != hipMemoryTypeHost || !a.devicePointer)
+        return SIVF_ERR_ARG;
+    hipStream_t st = as_stream(stream);
+    ix->last = st;
+    char *h = (char *)a.devicePointer, *w = (char *)dev_buf;
+    Dev V = ix->S;   // geometry, scratch and centroids shared; pool arrays replaced
+    V.num_slabs = host_slabs;
+    V.num_pages = T.num_pages;
+    V.dir_cap = T.dir_cap;
+    V.data = (float4 *)(h + T.data);
+    V.sids = (uint32_t *)(h + T.sids);
+    V.hdata = nullptr;
+    V.xnorm = nullptr;
+    V.bits = (uint64_t *)(w + T.bits);
+    V.sowner = (int32_t *)(w + T.sowner);
+    V.sord = (int32_t *)(w + T.sord);
+    V.free_slabs = (int32_t *)(w + T.free_slabs);
+    V.free_pages = (int32_t *)(w + T.free_pages);
+    V.pages = (int32_t *)(w + T.pages);
+    V.dir = (int32_t *)(w + T.dir);
+    V.len = (int32_t *)(w + T.len);
+    V.l_dead = (int32_t *)(w + T.dead);
+    V.ctl = (int32_t *)(w + T.ctl);
+    V.cdata = nullptr;
+    V.cbits = nullptr;
+    V.csowner = nullptr;
+    V.cdead = nullptr;
+    // an empty cold pool: every slab and page free (the device pool's initial state)
+    std::vector<int32_t> iota((size_t)(host_slabs > T.num_pages ? host_slabs : T.num_pages));
+    for (size_t i = 0; i < iota.size(); i++) iota[i] = (int32_t)i;
+    std::vector<int32_t> ctl(CTL_WORDS, 0);
+    ctl[CTL_GATE] = -1;
+    ctl[CTL_UPSERT] = -1;
+    ctl[CTL_SLAB_TOP] = (int32_t)host_slabs;
+    ctl[CTL_PAGE_TOP] = (int32_t)T.num_pages;
+    const int nl = ix->cfg.nlist;
+    if (!dev_ok(hipStreamSynchronize(st)) ||
+        !dev_ok(hipMemcpy(V.free_slabs, iota.data(), (size_t)host_slabs * 4, hipMemcpyHostToDevice)) ||
+        !dev_ok(hipMemcpy(V.free_pages, iota.data(), (size_t)T.num_pages * 4, hipMemcpyHostToDevice)) ||
+        !dev_ok(hipMemcpy(V.ctl, ctl.data(), CTL_WORDS * 4, hipMemcpyHostToDevice)))
+        return SIVF_ERR_DEVICE;
+    launch_fill_i64(st, (int64_t *)V.bits, host_slabs * V.bw, 0);
+    launch_fill_i32(st, V.sowner, host_slabs, -1);
+    launch_fill_i32(st, V.sord, host_slabs, 0);
+    launch_fill_i32(st, V.len, nl, 0);
+    launch_fill_i32(st, V.l_dead, nl, 0);
+    launch_fill_i32(st, (int32_t *)(w + T.heat), nl, 0);
+    if (!dev_ok(hipGetLastError()) || !dev_ok(hipStreamSynchronize(st))) return SIVF_ERR_DEVICE;
+    ix->tier.V = V;
+    ix->tier.slabs = host_slabs;
+    ix->tier.heat = (int32_t *)(w + T.heat);
+    ix->tier.prior = (uint64_t *)(w + T.prior);
+    ix->tier.olist = (int32_t *)(w + T.olist);
+    ix->tier.nout = (int64_t *)(w + T.nout);
+    ix->tier.positions = 0;
+    ix->S.cdata = V.data;
+    ix->S.cbits = V.bits;
+    ix->S.csowner = V.sowner;
+    ix->S.cdead = V.l_dead;
+    return SIVF_OK;
+}
+
+sivf_status sivf_tier_offload(sivf_index *ix, int32_t n, const int32_t *lists, int64_t *moved, void *stream) {
+    if (!ix || n < 0 || (n > 0 && !lists)) return SIVF_ERR_ARG;
+    if (ix->broken || ix->tier.slabs == 0) return SIVF_ERR_STATE;
+    const int nl = ix->cfg.nlist, C = ix->cfg.slab_capacity;
+    std::vector<char> seen(nl, 0);
+    for (int i = 0; i < n; i++) {
+        if (lists[i] < 0 || lists[i] >= nl || seen[lists[i]]) return SIVF_ERR_ARG;
+        seen[lists[i]] = 1;
+    }
+    ix->last = as_stream(stream);
+    std::vector<int32_t> len, dead, clen, cdead;
+    int32_t ctl[CTL_WORDS], cfree = 0;
+    sivf_status s = read_counts(ix, len, ctl, &dead);
+    if (s == SIVF_OK) s = tier_counts(ix, clen, cdead, &cfree);
+    if (s != SIVF_OK) return s;
+    if (ctl[CTL_GATE] == ctl[CTL_SEQ]) return SIVF_ERR_STATE;   // a failed call is still open
+    std::vector<int32_t> ol;
+    int64_t need = 0, pos = 0;
+    int longest = 0;
+    for (int i = 0; i < n; i++) {
+        const int l = lists[i];
+        if (len[l] == 0) continue;
+        ol.push_back(l);
+        need += (clen[l] + len[l] + C - 1) / C - (clen[l] + C - 1) / C;
+        pos += len[l];
+        longest = len[l] > longest ? len[l] : longest;
+    }
+    if (need > cfree) return SIVF_ERR_NOSPACE;   // nothing moved
+    if (moved) *moved = pos;
+    if (ol.empty()) return SIVF_OK;
+    hipStream_t st = ix->last;
+    if (!dev_ok(hipMemcpy(ix->tier.olist, ol.data(), ol.size() * 4, hipMemcpyHostToDevice))) return SIVF_ERR_DEVICE;
+    launch_tier_offload(st, ix->S, ix->tier.V, ix->tier.olist, (int)ol.size(), longest);
+    s = launched(ix);
+    if (s != SIVF_OK) return s;
+    return tier_counts(ix, clen, cdead, nullptr);
+}
+
+sivf_status sivf_tier_reclaim(sivf_index *ix, int64_t *released, void *stream) {
+    if (!ix) return SIVF_ERR_ARG;
+    if (ix->broken || ix->tier.slabs == 0) return SIVF_ERR_STATE;
+    hipStream_t st = as_stream(stream);
+    ix->last = st;
+    launch_tier_reclaim(st, ix->tier.V, ix->tier.nout);
+    sivf_status s = launched(ix);
+    if (s != SIVF_OK) return s;
+    int64_t r = 0;
+    if (!dev_ok(hipStreamSynchronize(st)) || !dev_ok(hipMemcpy(&r, ix->tier.nout, 8, hipMemcpyDeviceToHost)))
+        return SIVF_ERR_DEVICE;
+    if (released) *released = r;
+    std::vector<int32_t> clen, cdead;
+    return tier_counts(ix, clen, cdead, nullptr);
+}
+
+sivf_status sivf_tier_stats(sivf_index *ix, int64_t *cold_live, int64_t *cold_positions, int64_t *cold_used_slabs,
+                            int64_t *cold_free_slabs) {
+    if (!ix) return SIVF_ERR_ARG;
+    int64_t live = 0, pos = 0, used = 0;
+    int32_t cfree = 0;
+    if (ix->tier.slabs > 0) {
+        std::vector<int32_t> clen, cdead;
+        sivf_status s = tier_counts(ix, clen, cdead, &cfree);
+        if (s != SIVF_OK) return s;
+        const int C = ix->cfg.slab_capacity;
+        for (int l = 0; l < ix->cfg.nlist; l++) {
+            pos += clen[l];
+            live += clen[l] - cdead[l];
+            used += (clen[l] + C - 1) / C;
+        }
+    }
+    if (cold_live) *cold_live = live;
+    if (cold_positions) *cold_positions = pos;
+    if (cold_used_slabs) *cold_used_slabs = used;
+    if (cold_free_slabs) *cold_free_slabs = cfree;
+    return SIVF_OK;
+}
+
+sivf_status sivf_tier_dump(sivf_index *ix, int32_t *cold_len, int64_t *cold_ids_by_list) {
+    if (!ix) return SIVF_ERR_ARG;
+    if (ix->tier.slabs == 0) return SIVF_ERR_STATE;
+    std::vector<int32_t> clen, cdead;
+    sivf_status s = tier_counts(ix, clen, cdead, nullptr);
+    if (s != SIVF_OK) return s;
+    const Dev &V = ix->tier.V;
+    const int C = ix->cfg.slab_capacity, nl = ix->cfg.nlist;
+    if (cold_len) memcpy(cold_len, clen.data(), (size_t)nl * 4);
+    if (!cold_ids_by_list) return SIVF_OK;
+    std::vector<int32_t> dir((size_t)nl * V.dir_cap), pages((size_t)V.num_pages * PAGE);
+    std::vector<uint64_t> bits((size_t)V.num_slabs * V.bw);
+    std::vector<uint32_t> sids((size_t)V.num_slabs * C);
+    if (!dev_ok(hipMemcpy(dir.data(), V.dir, dir.size() * 4, hipMemcpyDeviceToHost)) ||
+        !dev_ok(hipMemcpy(pages.data(), V.pages, pages.size() * 4, hipMemcpyDeviceToHost)) ||
+        !dev_ok(hipMemcpy(bits.data(), V.bits, bits.size() * 8, hipMemcpyDeviceToHost)) ||
+        !dev_ok(hipMemcpy(sids.data(), V.sids, sids.size() * 4, hipMemcpyDeviceToHost)))
+        return SIVF_ERR_DEVICE;
+    int64_t io = 0;
+    for (int l = 0; l < nl; l++)
+        for (int p = 0; p < clen[l]; p++) {
+            const int o = p / C, t = p % C;
+            const int page = dir[(size_t)l * V.dir_cap + o / PAGE];
+            if (page < 0 || page >= V.num_pages) return SIVF_ERR_STATE;
+            const int slab = pages[(size_t)page * PAGE + o % PAGE];
+            if (slab < 0 || slab >= V.num_slabs) return SIVF_ERR_STATE;
+            const bool live = (bits[(size_t)slab * V.bw + (t >> 6)] >> (t & 63)) & 1ull;
+            cold_ids_by_list[io++] = live ? (int64_t)sids[(size_t)slab * C + t] : -1;
+        }
+    return SIVF_OK;
+}
+
+sivf_status sivf_list_heat(sivf_index *ix, int32_t *heat, int halve) {
+    if (!ix || !heat) return SIVF_ERR_ARG;
+    if (ix->tier.slabs == 0) return SIVF_ERR_STATE;
+    const int nl = ix->cfg.nlist;
+    if (!dev_ok(hipStreamSynchronize(ix->last)) ||
+        !dev_ok(hipMemcpy(heat, ix->tier.heat, (size_t)nl * 4, hipMemcpyDeviceToHost)))
+        return SIVF_ERR_DEVICE;
+    if (halve) {
+        std::vector<int32_t> h(heat, heat + nl);
+        for (int32_t &v : h) v >>= 1;
+        if (!dev_ok(hipMemcpy(ix->tier.heat, h.data(), (size_t)nl * 4, hipMemcpyHostToDevice))) return SIVF_ERR_DEVICE;
+    }
+    return SIVF_OK;
+}
+
+sivf_status sivf_maintain(sivf_index *ix, float min_dead_fraction, int64_t min_free_slabs, int32_t max_offload,
+                          sivf_maintain_report *rep, void *stream) {
+    if (!ix || !(min_dead_fraction >= 0.f && min_dead_fraction <= 1.f) || min_free_slabs < 0 || max_offload < 0)
+        return SIVF_ERR_ARG;
+    if (ix->broken) return SIVF_ERR_STATE;
+    sivf_maintain_report r{};
+    hipStream_t st = as_stream(stream);
+    ix->last = st;
+    const bool lazy = ix->S.bits != nullptr;
+    // 1. compaction of dead slots, max_batch per call, while it makes progress
+    if (lazy) {
+        for (int it = 0; it < 1024; it++) {
+            launch_compact(st, ix->S, min_dead_fraction, ix->cfg.max_batch, nullptr, ix->B);
+            launch_call_end(st, ix->S);
+            sivf_status s = launched(ix);
+            if (s != SIVF_OK) return s;
+            int32_t c = 0;   // the compaction plan leaves its count in the remove-total word
+            if (!dev_ok(hipStreamSynchronize(st)) ||
+                !dev_ok(hipMemcpy(&c, ix->S.ctl + CTL_RMTOT, 4, hipMemcpyDeviceToHost)))
+                return SIVF_ERR_DEVICE;
+            r.compacted += c;
+            if (c == 0) break;
+        }
+    }
+    if (ix->tier.slabs > 0) {
+        // 2. cold segments with no live entry left
+        sivf_status s = sivf_tier_reclaim(ix, &r.reclaimed, stream);
+        if (s != SIVF_OK) return s;
+        // 3. below the free-slab mark: offload the least probed lists, then halve the probe counts
+        std::vector<int32_t> len, dead;
+        int32_t ctl[CTL_WORDS];
+        s = read_counts(ix, len, ctl, &dead);
+        if (s != SIVF_OK) return s;
+        int64_t free_slabs = ctl[CTL_SLAB_TOP];
+        if (free_slabs < min_free_slabs && max_offload > 0) {
+            const int nl = ix->cfg.nlist, C = ix->cfg.slab_capacity;
+            std::vector<int32_t> heat(nl);
+            s = sivf_list_heat(ix, heat.data(), 1);
+            if (s != SIVF_OK) return s;
+            std::vector<int32_t> order;
+            for (int l = 0; l < nl; l++)
+                if (len[l] > 0) order.push_back(l);
+            std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return heat[a] < heat[b]; });
+            std::vector<int32_t> pick;
+            for (int l : order) {
+                if (free_slabs >= min_free_slabs || (int)pick.size() >= max_offload) break;
+                pick.push_back(l);
+                free_slabs += (len[l] + C - 1) / C;
+            }
+            s = sivf_tier_offload(ix, (int32_t)pick.size(), pick.data(), &r.offloaded_positions, stream);
+            if (s != SIVF_OK) return s;
+            r.offloaded_lists = (int32_t)pick.size();
+        }
+    }
+    if (rep) *rep = r;
     return SIVF_OK;
 }
 
@@ -1299,12 +1662,15 @@ sivf_status sivf_save(sivf_index *ix, const char *path) {
     sivf_status s = read_counts(ix, len, ctl, &dead);
     if (s != SIVF_OK) return s;
     const sivf_config &c = ix->cfg;
+    // with a host tier each list's cold segment follows its device positions
+    std::vector<int32_t> clen(c.nlist, 0), cdead(c.nlist, 0);
+    if (ix->tier.slabs > 0 && (s = tier_counts(ix, clen, cdead, nullptr)) != SIVF_OK) return s;
     std::vector<int32_t> off(c.nlist), live_len(c.nlist);
     int64_t positions = 0, live = 0;
     for (int l = 0; l < c.nlist; l++) {
         off[l] = (int32_t)positions;
-        positions += len[l];
-        live_len[l] = len[l] - dead[l];   // lazily deleted slots are not saved
+        positions += len[l] + clen[l];
+        live_len[l] = len[l] - dead[l] + clen[l] - cdead[l];   // lazily deleted slots are not saved
         live += live_len[l];
     }
     FILE *f = fopen(path, "wb");
@@ -1345,7 +1711,7 @@ sivf_status sivf_save(sivf_index *ix, const char *path) {
     };
     for (int64_t e0 = 0; e0 < positions; e0 += rec) {
         const int n = (int)(positions - e0 < rec ? positions - e0 : rec);
-        launch_pack(st, ix->S, ix->S.l_off, e0, n, rows_d, ids_d);
+        launch_pack(st, ix->S, ix->tier.slabs > 0 ? &ix->tier.V : nullptr, ix->S.l_off, e0, n, rows_d, ids_d);
         if (!dev_ok(hipGetLastError()) || !dev_ok(hipStreamSynchronize(st))) return SIVF_ERR_DEVICE;
         if (!dev_ok(hipMemcpy(ids.data(), ids_d, (size_t)n * 4, hipMemcpyDeviceToHost)) ||
             !dev_ok(hipMemcpy(rows.data(), rows_d, (size_t)n * c.dim * 4, hipMemcpyDeviceToHost)))

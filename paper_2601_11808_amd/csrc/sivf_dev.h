@@ -21,6 +21,9 @@
 namespace sivf {
 
 constexpr uint32_t INVALID = 0xFFFFFFFFu;   // empty address-table entry / tombstoned slot
+// Address-table flag of an entry in the host tier: the low 31 bits are its
+// position (slab * C + slot) in the cold pool.
+constexpr uint32_t COLD_BIT = 0x80000000u;
 constexpr int PAGE = 256;                   // slab ids per page of a list table
 constexpr int WAVE = 64;
 
@@ -78,6 +81,12 @@ struct Dev {
     // bw = ceil(C / 64) words per slab; bit s % 64 of word s / 64 is slot s.
     uint64_t *bits;
     int bw;
+    // Host tier (all NULL without one): rows of cold entries (pinned host
+    // memory), their validity bits, the owning list of each cold slab, and
+    // each list's dead cold slots.  Cold entries are deleted lazily.
+    const float4 *cdata;
+    uint64_t *cbits;
+    int32_t *csowner, *cdead;
 };
 
 // Validity word of slot `slot` of `slab` (lazy deletes), read with an atomic

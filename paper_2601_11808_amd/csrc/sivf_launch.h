@@ -54,8 +54,15 @@ void launch_remove_lazy(hipStream_t st, const Dev &S, int n, const int64_t *ids,
 void launch_compact(hipStream_t st, const Dev &S, float min_dead_fraction, int budget, int64_t *n_compacted,
                     const Batch &B);
 void launch_get_rows(hipStream_t st, const Dev &S, int n, const int64_t *ids, float *rows);
-// checkpoint: entries [e0, e0 + n) in list order (off = per-list first entry) -> rows and ids
-void launch_pack(hipStream_t st, const Dev &S, const int32_t *off, int64_t e0, int n, float *rows, uint32_t *ids);
+// checkpoint: entries [e0, e0 + n) in list order (off = per-list first entry) -> rows and ids; with a
+// host tier (Sc: the cold pool's view, else NULL) each list's cold segment follows its device positions
+void launch_pack(hipStream_t st, const Dev &S, const Dev *Sc, const int32_t *off, int64_t e0, int n, float *rows,
+                 uint32_t *ids);
+// host tier: move every position of the n lists in olist (device array) to the end of their cold
+// segments (longest: the most positions of one of them); lazy deletes only
+void launch_tier_offload(hipStream_t st, const Dev &S, const Dev &Sc, const int32_t *olist, int n, int longest);
+// host tier: release the cold segments with no live entry; *n_out (device) = positions released
+void launch_tier_reclaim(hipStream_t st, const Dev &Sc, int64_t *n_out);
 void launch_fill_i64(hipStream_t st, int64_t *p, int64_t n, int64_t v);
 void launch_fill_i32(hipStream_t st, int32_t *p, int64_t n, int32_t v);
 
@@ -89,12 +96,17 @@ bool cert_ok(int storage, int d, int C, int kcap);
 constexpr int DEFAULT_CHUNK_SHIFT = 14;
 // snap = 1: record every list's length (the scan reads only these entries);
 // snap = 0: keep the lengths an earlier pass of the same search recorded.
-void launch_search_plan(hipStream_t st, const Dev &S, const SearchBufs &W, int nq, const KClass &cls, int snap);
+// heat (or NULL): per-list probe counts to add this pass's pairs to
+void launch_search_plan(hipStream_t st, const Dev &S, const SearchBufs &W, int nq, const KClass &cls, int snap,
+                        int32_t *heat = nullptr);
 void launch_search_scan(hipStream_t st, const Dev &S, const SearchBufs &W, int nq, const float *q, int np_stride,
                         int kcap, int k, const int32_t *k_per_query);
+// prior (or NULL): per query, prior_stride sorted keys merged in as one more source;
+// keys_out (or NULL): sorted keys (stride out_stride) instead of dist / labels
 void launch_search_merge(hipStream_t st, const Dev &S, const SearchBufs &W, int nq, const KClass &cls, int kcap,
                          int out_stride, int k, int kmul, const int32_t *k_per_query, float *dist,
-                         int64_t *labels);
+                         int64_t *labels, const uint64_t *prior = nullptr, int prior_stride = 0,
+                         uint64_t *keys_out = nullptr);
 void launch_search_scan_mfma(hipStream_t st, const Dev &S, const SearchBufs &W, int nq, const float *q,
                              int np_stride, int kcap, int k, int kmul, const int32_t *k_per_query);
 void launch_rerank(hipStream_t st, const Dev &S, int nq, const float *q, int kc, const int64_t *cand, int k,

@@ -8,16 +8,19 @@ address table of Sec. 3.4 maps each live id to its slot):
     one list, and a held slab records its owner and ordinal;
   - used + free = pool size, and no slab is both free and held;
   - every live position holds a real id (no tombstone), each id once;
-  - the address table maps exactly the live ids, each to its own slot.
+  - the address table maps exactly the live ids, each to its own slot;
+  - with a host tier, entries flagged cold are exactly the live cold ids.
 """
 import numpy as np
 
 INVALID = 0xFFFFFFFF
+COLD_BIT = 0x80000000
 
 
-def check_dump(d, C, num_slabs, lazy=False):
+def check_dump(d, C, num_slabs, lazy=False, cold_ids=None):
     """lazy: slots deleted lazily (not yet compacted) read -1 inside the lists;
-    the address table must not point at them."""
+    the address table must not point at them.  cold_ids: the host tier's ids
+    by list (-1 for dead slots), or None without a tier."""
     ln = d["list_len"].astype(np.int64)
     assert (ln >= 0).all()
     ns = (ln + C - 1) // C
@@ -45,7 +48,15 @@ def check_dump(d, C, num_slabs, lazy=False):
     ids = ids_all[live]
     assert np.unique(ids).shape[0] == ids.shape[0], "an id is stored twice"
     att = d["att"]
-    valid = att != INVALID
+    cold = (att != INVALID) & ((att & COLD_BIT) != 0)
+    if cold_ids is None:
+        assert not cold.any(), "a cold address without a tier"
+    else:
+        cl = cold_ids[cold_ids >= 0]
+        assert np.unique(cl).shape[0] == cl.shape[0], "a cold id is stored twice"
+        assert np.intersect1d(cl, ids).shape[0] == 0, "an id is both cold and on the device"
+        assert np.array_equal(np.flatnonzero(cold), np.sort(cl)), "cold addresses != live cold ids"
+    valid = (att != INVALID) & ~cold
     assert valid.sum() == ids.shape[0], "address table size != live"
     assert valid[ids].all(), "live id missing from the address table"
     # expected slot of each live entry

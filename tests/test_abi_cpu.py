@@ -41,6 +41,7 @@ def test_struct_layouts_match_header():
     assert ct.sizeof(sivf.SivfConfig) == 6 * 4 + 2 * 8 + 6 * 4
     assert ct.sizeof(sivf.SivfStepArgs) == 8 + 8 + 8 + 8 + 8 + 4 + 4 + 8 + 8 + 8 + 8 + 8 + 8 + 8
     assert ct.sizeof(sivf.SivfDumpInfo) == 5 * 8 + 2 * 4 + 8
+    assert ct.sizeof(sivf.SivfMaintainReport) == 3 * 8 + 2 * 4
 
 
 def _cfg(**kw):
