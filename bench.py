@@ -106,7 +106,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="window",
-                    choices=["window", "tiny", "precision", "serve", "batched", "mutation"])
+                    choices=["window", "tiny", "precision", "serve", "batched", "mutation", "tier"])
     ap.add_argument("--serve-seconds", type=float, default=5.0, help="serve: length of the arrival stream")
     ap.add_argument("--serve-rate", type=float, default=2000.0, help="serve: Poisson arrival rate (req/s)")
     ap.add_argument("--serve-n", type=int, default=50_000_000, help="serve: steady-state window size")
@@ -384,6 +384,8 @@ def main():
         return batched_main(a)
     if a.workload == "mutation":
         return mutation_main(a)
+    if a.workload == "tier":
+        return tier_main(a)
     import torch
     import paper_2601_11808_amd as sivf
     import workloads
@@ -785,6 +787,96 @@ def batched_main(a):
         "list_len": {"min": int(lens.min()), "median": int(np.median(lens)), "max": int(lens.max())},
         "roofline": roof,
         "bulk_load_vec_per_s": round(N / load_s, 1),
+    }
+    print(json.dumps(res), flush=True)
+
+
+# PCIe 5.0 x16, one direction: the host link of an MI355X
+HOST_LINK_GBPS = 64.0
+
+
+def tier_main(a):
+    """Host tier on the window data: the odd lists move to pinned host memory.
+    Reports the offload rate and the window search with those lists scanned in
+    host memory, beside the same search with every list on the device (the
+    results must be identical)."""
+    import torch
+    import paper_2601_11808_amd as sivf
+    import workloads
+
+    if not os.path.exists(sivf.LIB_PATH):
+        raise SystemExit("libsivf.so is not built: run python -c 'import __graft_entry__ as g; g.build()'")
+    dev = torch.device("cuda:0")
+    w = workloads.window()
+    x, ids = w.base()
+    q = w.queries()
+    N, d = x.shape
+    nq, k, nprobe = q.shape[0], w.k, w.nprobe
+    num_slabs = int(1.15 * N / w.slab) + w.nlist
+    ix = sivf.Index(d, w.nlist, w.centroids, metric=w.metric, slab_capacity=w.slab, num_slabs=num_slabs,
+                    id_capacity=N, max_batch=65536, max_queries=nq, max_k=16, max_nprobe=nprobe,
+                    delete_mode=sivf.DELETE_LAZY, device="cuda:0")
+    xd, idd = torch.from_numpy(x).to(dev), torch.from_numpy(ids).to(dev)
+    for c in range(0, N, 65536):
+        ix.add(xd[c:c + 65536], idd[c:c + 65536])
+    assert ix.sync() == 0
+    ix.tier_attach(num_slabs)
+    qd = torch.from_numpy(q).to(dev)
+    sched = tuple(int(v) for v in a.schedule.split(",")) if a.schedule else (16, 16, 0)
+    ix.set_search_schedule(*sched)
+    reps = max(3, a.steps)
+
+    def timed_search():
+        for _ in range(a.warmup):
+            ix.search(qd, k, nprobe)
+        assert ix.sync() == 0
+        ix.profile_read()
+        ix.profile(True)
+        for _ in range(reps):
+            dist, lab = ix.search(qd, k, nprobe)
+        prof = ix.profile_read()
+        ix.profile(False)
+        assert ix.sync() == 0
+        return {kk: v[0] / max(v[1], 1) for kk, v in prof.items() if v[1] > 0}, dist, lab
+
+    hot, d_hot, l_hot = timed_search()
+    odd = np.arange(1, w.nlist, 2, dtype=np.int32)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    moved = ix.tier_offload(odd)
+    off_s = time.perf_counter() - t0
+    ts = ix.tier_stats()
+    cold, d_cold, l_cold = timed_search()
+    same = bool(torch.equal(l_hot, l_cold) and torch.equal(d_hot.view(torch.int32), d_cold.view(torch.int32)))
+    # link bytes of the cold scan: every probed cold segment crosses the host link at least once per
+    # search (rows and ids); re-reads by further query tiles are served from the GPU's caches
+    probes = ix.probe(qd, nprobe).cpu().numpy()
+    clen = ix.tier_dump()["cold_len"].astype(np.int64)
+    cold_evals = int(clen[probes[probes >= 0]].sum())
+    probed = np.zeros(w.nlist, bool)
+    probed[probes[probes >= 0]] = True
+    link_bytes = float(clen[probed].sum()) * (4.0 * d + 4.0)
+    scan_cold_ms = cold.get("scan_cold", 0.0)
+    res = {
+        "metric": "host tier: window search with half the lists in host memory; offload rate",
+        "value": round(nq / (cold["search"] * 1e-3), 1), "unit": "queries/s (half the lists cold)",
+        "n_gpus": 1, "steps": reps, "warmup": a.warmup, "ms_per_step": round(cold["search"], 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"tier: window data N={N}, d={d}, nlist={w.nlist}, slab={w.slab}, lazy deletes; "
+                               f"the {odd.shape[0]} odd lists offloaded; {nq} queries, nprobe {nprobe}, k {k}",
+                   "parallelism": "single GPU"},
+        "identical_results": same,
+        "offload": {"positions": moved, "seconds": round(off_s, 4), "positions_per_s": round(moved / off_s, 1),
+                    "link_GBps": round(moved * (4.0 * d + 4.0) / off_s / 1e9, 2)},
+        "tier_stats": ts,
+        "search_all_device_ms": {kk: round(v, 4) for kk, v in hot.items()},
+        "search_half_cold_ms": {kk: round(v, 4) for kk, v in cold.items()},
+        "cold_scan": {"bound": "host link", "evals_per_launch": cold_evals, "link_bytes": int(link_bytes),
+                      "achieved": round(link_bytes / (scan_cold_ms * 1e-3) / 1e9, 2) if scan_cold_ms else None,
+                      "peak": HOST_LINK_GBPS, "unit": "GB/s",
+                      "frac": round(link_bytes / (scan_cold_ms * 1e-3) / 1e9 / HOST_LINK_GBPS, 4) if scan_cold_ms
+                      else None,
+                      "note": "each probed cold segment's rows and ids cross the link once per search"},
     }
     print(json.dumps(res), flush=True)
 
