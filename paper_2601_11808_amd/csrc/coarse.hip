@@ -226,6 +226,147 @@ __global__ __launch_bounds__(256) void k_coarse_gemm(const float *__restrict__ X
     }
 }
 
+// Group minima of the insert path on bf16 MFMA, row-stationary (padded rows
+// of at most 128 dimensions): a block takes 128 rows -- rounded to bf16 once
+// and held in registers, wave w owning rows 32 w .. 32 w + 31 as two 16-row
+// operands per 32-dimension step -- and sweeps nct consecutive tiles of 128
+// centroids, each streamed through LDS (double buffer: the next tile's loads
+// are in flight while the current one feeds the MFMAs; one barrier per
+// tile).  Per tile each row gets its 8 group minima, out[r][g] as
+// k_coarse_gemm<., 1> writes them; |c|^2 comes from LDS (+inf past nlist),
+// and Dt = |x|^2 + (|c|^2 - 2 x.c) takes one fma per list.
+constexpr int HK = 128, HBLD = HK + 8;   // halves of a padded row; LDS row stride (halves)
+template <int METRIC>
+__global__ __launch_bounds__(256) void k_coarse_gmin_h(const float *__restrict__ X, int n, int d,
+                                                       const uint16_t *__restrict__ cent_h, int dpad,
+                                                       const float *__restrict__ cn2, int nlist,
+                                                       float *__restrict__ out, int ldo, int nct, int xcd_map,
+                                                       const int32_t *ctl, int gated) {
+    __shared__ __align__(16) uint16_t sB[2][GN * HBLD];
+    __shared__ __align__(16) float sC[2][GN];
+    if (gated && call_failed(ctl)) return;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int nrb = (n + GM - 1) / GM, ncb = (nlist + GN - 1) / GN, ncs = (ncb + nct - 1) / nct;
+    int rb, sg;
+    if (xcd_map) {   // each XCD owns a contiguous range of centroid segments (tiles stay in its L2)
+        const int per = (ncs + 7) >> 3, j = (int)(blockIdx.x >> 3);
+        sg = (int)(blockIdx.x & 7) * per + j / nrb;
+        rb = j % nrb;
+        if (sg >= ncs || j / nrb >= per) return;
+    } else {
+        rb = (int)blockIdx.x % nrb;
+        sg = (int)blockIdx.x / nrb;
+    }
+    const int r0 = rb * GM, t0 = sg * nct, t1 = min(t0 + nct, ncb);
+    // this lane's rows (16 i + lane % 16 of the wave's 32) as bf16 operands, and their |x|^2
+    uint4 a[2][4];
+    float sq[2];
+#pragma unroll
+    for (int i = 0; i < 2; i++) {
+        const int r = r0 + 32 * w + 16 * i + (lane & 15);
+        float part = 0.f;
+#pragma unroll
+        for (int ks = 0; ks < 4; ks++) {
+            const int k = 32 * ks + 8 * (lane >> 4);
+            float v[8];
+#pragma unroll
+            for (int e = 0; e < 8; e++) v[e] = (r < n && k + e < d) ? X[(int64_t)r * d + k + e] : 0.f;
+#pragma unroll
+            for (int e = 0; e < 8; e++) part = fmaf(v[e], v[e], part);
+            a[i][ks] = make_uint4(to_bf16_bits(v[0]) | (to_bf16_bits(v[1]) << 16),
+                                  to_bf16_bits(v[2]) | (to_bf16_bits(v[3]) << 16),
+                                  to_bf16_bits(v[4]) | (to_bf16_bits(v[5]) << 16),
+                                  to_bf16_bits(v[6]) | (to_bf16_bits(v[7]) << 16));
+        }
+        part += __shfl_xor(part, 16);
+        part += __shfl_xor(part, 32);
+        sq[i] = part;
+    }
+    // tile loader: thread t fills half t & 1 of centroid row t >> 1 (64 halves as 16 x 8 bytes)
+    const int lr = tid >> 1, lh = (tid & 1) * 64;
+    uint2 stg[16];
+    float stc = 0.f;
+    auto gload = [&](int t) {
+        const int c = t * GN + lr;
+#pragma unroll
+        for (int q = 0; q < 16; q++) {
+            const int k = lh + 4 * q;   // dpad is a multiple of 4: a 4-half chunk is all in or all out
+            stg[q] = (c < nlist && k < dpad) ? *reinterpret_cast<const uint2 *>(cent_h + (int64_t)c * dpad + k)
+                                             : make_uint2(0u, 0u);
+        }
+        if (tid < GN) {
+            const int cc = t * GN + tid;
+            stc = cc < nlist ? (METRIC == 0 ? cn2[cc] : 0.f) : __builtin_inff();
+        }
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < 16; q++) *reinterpret_cast<uint2 *>(&sB[buf][lr * HBLD + lh + 4 * q]) = stg[q];
+        if (tid < GN) sC[buf][tid] = stc;
+    };
+    gload(t0);
+    lstore(0);
+    __syncthreads();
+    const bool vec = (ldo & 3) == 0;
+    for (int t = t0; t < t1; t++) {
+        const int cur = (t - t0) & 1;
+        if (t + 1 < t1) gload(t + 1);
+        floatx4 acc[2][8];
+#pragma unroll
+        for (int i = 0; i < 2; i++)
+#pragma unroll
+            for (int j = 0; j < 8; j++) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < 4; ks++) {
+#pragma unroll
+            for (int j = 0; j < 8; j++) {
+                const uint4 b = *reinterpret_cast<const uint4 *>(
+                    &sB[cur][(16 * j + (lane & 15)) * HBLD + 32 * ks + 8 * (lane >> 4)]);
+#pragma unroll
+                for (int i = 0; i < 2; i++)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(cbf16x8, b),
+                                                                       __builtin_bit_cast(cbf16x8, a[i][ks]),
+                                                                       acc[i][j], 0, 0, 0);
+            }
+        }
+        // lane: row 16 i + lane % 16, lists 16 j + 4 (lane / 16) .. +3 of the tile
+#pragma unroll
+        for (int i = 0; i < 2; i++) {
+            float gm[8];
+#pragma unroll
+            for (int j = 0; j < 8; j++) {
+                const float4 c2 = *reinterpret_cast<const float4 *>(&sC[cur][16 * j + 4 * (lane >> 4)]);
+                const float cs[4] = {c2.x, c2.y, c2.z, c2.w};
+                float m = __builtin_inff();
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    // lists past nlist carry |c|^2 = +inf (IP: masked the same way)
+                    const float v = METRIC == 0 ? fmaf(-2.0f, acc[i][j][r], cs[r])
+                                                : (cs[r] == 0.f ? -acc[i][j][r] : __builtin_inff());
+                    m = fminf(m, v);   // a NaN counts as +inf
+                }
+                m = fminf(m, __shfl_xor(m, 16));
+                m = fminf(m, __shfl_xor(m, 32));
+                gm[j] = METRIC == 0 ? sq[i] + m : m;
+            }
+            const int gr = r0 + 32 * w + 16 * i + (lane & 15);
+            if ((lane >> 4) == 0 && gr < n) {
+                float *o = out + (int64_t)gr * ldo + t * (GN / GROUP);
+                if (vec && t * (GN / GROUP) + 8 <= ldo) {
+                    *reinterpret_cast<float4 *>(o) = make_float4(gm[0], gm[1], gm[2], gm[3]);
+                    *reinterpret_cast<float4 *>(o + 4) = make_float4(gm[4], gm[5], gm[6], gm[7]);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 8; j++)
+                        if (t * (GN / GROUP) + j < ldo) o[j] = gm[j];
+                }
+            }
+        }
+        if (t + 1 < t1) lstore(cur ^ 1);   // its last readers finished before the previous barrier
+        __syncthreads();
+    }
+}
+
 // Certified bound on |Dt - D| for a row of norm qn and a list of norm cn: the
 // FP32 arithmetic of the GEMM ((4d+16) 2^-24 (|x|+|c|)^2, IP: |x||c|, plus
 // an underflow term) and, with bf16 operands (bf = 1), their rounding:
@@ -524,7 +665,23 @@ void launch_coarse_assign(hipStream_t st, float *scratch, const float *X, int n,
                           int out_stride, const int32_t *ctl, int gated, int bf) {
     if (n <= 0) return;
     const int ldg = coarse_groups(nlist);
-    coarse_gemm_t<1>(st, X, n, d, cent, cent_h, dpad, cn2, nlist, metric, scratch, ldg, ctl, gated, bf);
+    if (bf && dpad <= HK) {
+        // row-stationary bf16 sweep: segments of nct centroid tiles, enough blocks to fill the chip
+        const int nrb = (n + GM - 1) / GM, ncb = (nlist + GN - 1) / GN;
+        int nct = (int)(((int64_t)nrb * ncb) / 2048);
+        nct = nct < 1 ? 1 : (nct > 16 ? 16 : nct);
+        const int ncs = (ncb + nct - 1) / nct;
+        const int xcd_map = ncs >= 8 ? 1 : 0;
+        const unsigned grid = xcd_map ? (unsigned)(8 * ((ncs + 7) / 8) * nrb) : (unsigned)(nrb * ncs);
+        if (metric == 0)
+            hipLaunchKernelGGL(k_coarse_gmin_h<0>, dim3(grid), dim3(256), 0, st, X, n, d, cent_h, dpad, cn2, nlist,
+                               scratch, ldg, nct, xcd_map, ctl, gated);
+        else
+            hipLaunchKernelGGL(k_coarse_gmin_h<1>, dim3(grid), dim3(256), 0, st, X, n, d, cent_h, dpad, cn2, nlist,
+                               scratch, ldg, nct, xcd_map, ctl, gated);
+    } else {
+        coarse_gemm_t<1>(st, X, n, d, cent, cent_h, dpad, cn2, nlist, metric, scratch, ldg, ctl, gated, bf);
+    }
     hipLaunchKernelGGL(k_coarse_argmin, dim3((n + 3) / 4), dim3(256), 0, st, scratch, ldg, X, n, d, cent, dpad,
                        cmax, nlist, metric, out, out_stride, ctl, gated, bf);
 }

@@ -235,10 +235,13 @@ void coarse(sivf_index *ix, hipStream_t st, float *dt, const float *x, int64_t n
     const Dev &S = ix->S;
     const int dpad = S.dp4 * 4;
     const int bf = S.storage != SIVF_F32;   // reduced-precision indexes run the coarse GEMM on bf16 MFMA
-    for (int64_t r0 = 0; r0 < n; r0 += ix->L.coarse_rows) {
-        const int nr = (int)((n - r0) < ix->L.coarse_rows ? (n - r0) : ix->L.coarse_rows);
+    // the nearest-list path keeps one minimum per group of 16 lists: 16 times the rows fit the scratch
+    const bool assign = m == 1 && !m_per_row && mmax == 1;
+    const int64_t chunk = assign ? (int64_t)ix->L.coarse_rows * S.nlist / coarse_groups(S.nlist) : ix->L.coarse_rows;
+    for (int64_t r0 = 0; r0 < n; r0 += chunk) {
+        const int nr = (int)((n - r0) < chunk ? (n - r0) : chunk);
         const float *xr = x + r0 * S.d;
-        if (m == 1 && !m_per_row && mmax == 1) {
+        if (assign) {
             launch_coarse_assign(st, dt, xr, nr, S.d, S.cent, S.cent_h, dpad, S.cn2, S.cmax, S.nlist, S.metric,
                                  out + r0 * out_stride, out_stride, S.ctl, gated, bf);
             continue;

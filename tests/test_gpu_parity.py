@@ -121,6 +121,28 @@ def test_assign_and_probe_exact_bf16_coarse(metric):
 
 
 @pytest.mark.parametrize("metric", [0, 1])
+def test_assign_bf16_large_batches(metric):
+    """Large insert batches on bf16-coarse indexes: blocks sweep many centroid
+    tiles (up to 16, double-buffered) and segments end on a ragged tile; sampled
+    rows equal the oracle's nearest list (the rows are independent)."""
+    w = workloads.serving(n_base=0)
+    rng = np.random.default_rng([13, metric])
+    for nlist, cent, n in [(16384, w.centroids, 40000), (4100, None, 30000)]:
+        if cent is None:
+            cent = (rng.standard_normal((nlist, 96)) * 3).astype(np.float32)
+            x = (cent[rng.integers(0, nlist, n)] + rng.standard_normal((n, 96))).astype(np.float32)
+            x[:50] = cent[:50]                              # exact centroid copies
+        else:
+            x = (w.means[rng.integers(0, nlist, n)] + 48 * rng.standard_normal((n, 128))).astype(np.float32)
+        ix = sivf.Index(x.shape[1], nlist, cent, metric=metric, slab_capacity=64, num_slabs=64, id_capacity=64,
+                        max_batch=n, max_queries=64, max_k=16, max_nprobe=8, storage=2, rerank_factor=4)
+        got = ix.assign(x).cpu().numpy()
+        sub = np.concatenate([np.arange(50), rng.choice(n, 1500, replace=False), np.arange(n - 50, n)])
+        np.testing.assert_array_equal(got[sub], oracle.assign(x[sub], cent, metric))
+        say(f"  bf16 coarse, {n} rows x {nlist} lists: {sub.shape[0]} sampled rows equal the oracle")
+
+
+@pytest.mark.parametrize("metric", [0, 1])
 def test_assign_many_lists_and_extremes(metric):
     """Nearest-list decisions at the serving shape (d=128, 16,384 lists), with
     a ragged last group of lists (4,100 lists), and at magnitudes where fp32
