@@ -227,17 +227,18 @@ __global__ __launch_bounds__(256) void k_coarse_gemm(const float *__restrict__ X
 }
 
 // Group minima of the insert path on bf16 MFMA, row-stationary (padded rows
-// of at most 128 dimensions): a block takes 128 rows -- rounded to bf16 once
-// and held in registers, wave w owning rows 32 w .. 32 w + 31 as two 16-row
-// operands per 32-dimension step -- and sweeps nct consecutive tiles of 128
+// of at most 128 dimensions): a block of 8 waves takes 256 rows -- rounded to
+// bf16 once and held in registers, wave w owning rows 32 w .. 32 w + 31 as two
+// 16-row operands per 32-dimension step -- and sweeps nct consecutive tiles of 128
 // centroids, each streamed through LDS (double buffer: the next tile's loads
 // are in flight while the current one feeds the MFMAs; one barrier per
 // tile).  Per tile each row gets its 8 group minima, out[r][g] as
 // k_coarse_gemm<., 1> writes them; |c|^2 comes from LDS (+inf past nlist),
 // and Dt = |x|^2 + (|c|^2 - 2 x.c) takes one fma per list.
 constexpr int HK = 128, HBLD = HK + 8;   // halves of a padded row; LDS row stride (halves)
+constexpr int HW = 8, HR = 32 * HW;      // waves per block, rows per block
 template <int METRIC>
-__global__ __launch_bounds__(256) void k_coarse_gmin_h(const float *__restrict__ X, int n, int d,
+__global__ __launch_bounds__(64 * HW) void k_coarse_gmin_h(const float *__restrict__ X, int n, int d,
                                                        const uint16_t *__restrict__ cent_h, int dpad,
                                                        const float *__restrict__ cn2, int nlist,
                                                        float *__restrict__ out, int ldo, int nct, int xcd_map,
@@ -246,7 +247,7 @@ __global__ __launch_bounds__(256) void k_coarse_gmin_h(const float *__restrict__
     __shared__ __align__(16) float sC[2][GN];
     if (gated && call_failed(ctl)) return;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int nrb = (n + GM - 1) / GM, ncb = (nlist + GN - 1) / GN, ncs = (ncb + nct - 1) / nct;
+    const int nrb = (n + HR - 1) / HR, ncb = (nlist + GN - 1) / GN, ncs = (ncb + nct - 1) / nct;
     int rb, sg;
     if (xcd_map) {   // each XCD owns a contiguous range of centroid segments (tiles stay in its L2)
         const int per = (ncs + 7) >> 3, j = (int)(blockIdx.x >> 3);
@@ -257,7 +258,7 @@ __global__ __launch_bounds__(256) void k_coarse_gmin_h(const float *__restrict__
         rb = (int)blockIdx.x % nrb;
         sg = (int)blockIdx.x / nrb;
     }
-    const int r0 = rb * GM, t0 = sg * nct, t1 = min(t0 + nct, ncb);
+    const int r0 = rb * HR, t0 = sg * nct, t1 = min(t0 + nct, ncb);
     // this lane's rows (16 i + lane % 16 of the wave's 32) as bf16 operands, and their |x|^2
     uint4 a[2][4];
     float sq[2];
@@ -282,17 +283,29 @@ __global__ __launch_bounds__(256) void k_coarse_gmin_h(const float *__restrict__
         part += __shfl_xor(part, 32);
         sq[i] = part;
     }
-    // tile loader: thread t fills half t & 1 of centroid row t >> 1 (64 halves as 16 x 8 bytes)
-    const int lr = tid >> 1, lh = (tid & 1) * 64;
-    uint2 stg[16];
+    // tile loader: thread t fills quarter t & 3 of centroid row t >> 2 (32 halves: 4 x 16 bytes when
+    // rows are 16-byte aligned, dpad % 8 == 0, else 8 x 8 bytes; dpad % 4 == 0, so a chunk is all in
+    // or all out)
+    const int lr = tid >> 2, lq = (tid & 3) * 32;
+    const bool v16 = (dpad & 7) == 0;
+    uint2 stg[8];
     float stc = 0.f;
     auto gload = [&](int t) {
         const int c = t * GN + lr;
+        const uint16_t *src = cent_h + (int64_t)c * dpad + lq;
+        if (v16) {
 #pragma unroll
-        for (int q = 0; q < 16; q++) {
-            const int k = lh + 4 * q;   // dpad is a multiple of 4: a 4-half chunk is all in or all out
-            stg[q] = (c < nlist && k < dpad) ? *reinterpret_cast<const uint2 *>(cent_h + (int64_t)c * dpad + k)
-                                             : make_uint2(0u, 0u);
+            for (int q = 0; q < 4; q++) {
+                const uint4 v = (c < nlist && lq + 8 * q < dpad) ? *reinterpret_cast<const uint4 *>(src + 8 * q)
+                                                                 : make_uint4(0u, 0u, 0u, 0u);
+                stg[2 * q] = make_uint2(v.x, v.y);
+                stg[2 * q + 1] = make_uint2(v.z, v.w);
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 8; q++)
+                stg[q] = (c < nlist && lq + 4 * q < dpad) ? *reinterpret_cast<const uint2 *>(src + 4 * q)
+                                                          : make_uint2(0u, 0u);
         }
         if (tid < GN) {
             const int cc = t * GN + tid;
@@ -301,7 +314,9 @@ __global__ __launch_bounds__(256) void k_coarse_gmin_h(const float *__restrict__
     };
     auto lstore = [&](int buf) {
 #pragma unroll
-        for (int q = 0; q < 16; q++) *reinterpret_cast<uint2 *>(&sB[buf][lr * HBLD + lh + 4 * q]) = stg[q];
+        for (int q = 0; q < 4; q++)
+            *reinterpret_cast<uint4 *>(&sB[buf][lr * HBLD + lq + 8 * q]) =
+                make_uint4(stg[2 * q].x, stg[2 * q].y, stg[2 * q + 1].x, stg[2 * q + 1].y);
         if (tid < GN) sC[buf][tid] = stc;
     };
     gload(t0);
@@ -667,17 +682,17 @@ void launch_coarse_assign(hipStream_t st, float *scratch, const float *X, int n,
     const int ldg = coarse_groups(nlist);
     if (bf && dpad <= HK) {
         // row-stationary bf16 sweep: segments of nct centroid tiles, enough blocks to fill the chip
-        const int nrb = (n + GM - 1) / GM, ncb = (nlist + GN - 1) / GN;
-        int nct = (int)(((int64_t)nrb * ncb) / 2048);
+        const int nrb = (n + HR - 1) / HR, ncb = (nlist + GN - 1) / GN;
+        int nct = (int)(((int64_t)nrb * ncb) / 1024);
         nct = nct < 1 ? 1 : (nct > 16 ? 16 : nct);
         const int ncs = (ncb + nct - 1) / nct;
         const int xcd_map = ncs >= 8 ? 1 : 0;
         const unsigned grid = xcd_map ? (unsigned)(8 * ((ncs + 7) / 8) * nrb) : (unsigned)(nrb * ncs);
         if (metric == 0)
-            hipLaunchKernelGGL(k_coarse_gmin_h<0>, dim3(grid), dim3(256), 0, st, X, n, d, cent_h, dpad, cn2, nlist,
+            hipLaunchKernelGGL(k_coarse_gmin_h<0>, dim3(grid), dim3(64 * HW), 0, st, X, n, d, cent_h, dpad, cn2, nlist,
                                scratch, ldg, nct, xcd_map, ctl, gated);
         else
-            hipLaunchKernelGGL(k_coarse_gmin_h<1>, dim3(grid), dim3(256), 0, st, X, n, d, cent_h, dpad, cn2, nlist,
+            hipLaunchKernelGGL(k_coarse_gmin_h<1>, dim3(grid), dim3(64 * HW), 0, st, X, n, d, cent_h, dpad, cn2, nlist,
                                scratch, ldg, nct, xcd_map, ctl, gated);
     } else {
         coarse_gemm_t<1>(st, X, n, d, cent, cent_h, dpad, cn2, nlist, metric, scratch, ldg, ctl, gated, bf);
