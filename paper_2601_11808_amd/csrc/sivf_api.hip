@@ -234,7 +234,9 @@ void coarse(sivf_index *ix, hipStream_t st, float *dt, const float *x, int64_t n
             int mmax, int32_t *out, int out_stride, int gated) {
     const Dev &S = ix->S;
     const int dpad = S.dp4 * 4;
-    const int bf = S.storage != SIVF_F32;   // reduced-precision indexes run the coarse GEMM on bf16 MFMA
+    // reduced-precision indexes assign inserts on bf16 MFMA; probes stay on FP32 MFMA: a probe batch
+    // is small, and the 64 times tighter bound leaves the exact re-check few candidates
+    const int bf = S.storage != SIVF_F32 && m == 1 && !m_per_row && mmax == 1;
     // the nearest-list path keeps one minimum per group of 16 lists: 16 times the rows fit the scratch
     const bool assign = m == 1 && !m_per_row && mmax == 1;
     const int64_t chunk = assign ? (int64_t)ix->L.coarse_rows * S.nlist / coarse_groups(S.nlist) : ix->L.coarse_rows;
