@@ -563,6 +563,156 @@ __global__ __launch_bounds__(256) void k_coarse_select(
     for (int p = tid; p < out_stride; p += 256) orow[p] = p < nk ? kl[p] : -1;
 }
 
+// The same selection for up to 2,048 lists and nprobe <= 64, one wave per
+// row and no block barrier: the row's approximate distances sit in registers
+// (lane l holds lists l + 64 i); tau, the m-th smallest, is found bit by bit
+// on their ordered keys (the key the radix select above finds); candidates
+// (the same test) are queued per wave in LDS and re-checked 64 at a time, each
+// batch merged into the row's best m -- sorted across the lanes by (exact
+// distance, list id) -- by a bitonic network.
+constexpr int SW_MAXL = 2048, SW_MAXM = 64, SW_Q = 128;
+
+__device__ __forceinline__ uint64_t ord64(double x) {
+    const uint64_t b = (uint64_t)__double_as_longlong(x + 0.0);   // -0 ranks as +0
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+__device__ __forceinline__ bool lex_less(uint64_t ka, int la, uint64_t kb, int lb) {
+    return ka < kb || (ka == kb && la < lb);
+}
+
+// One compare-exchange step over the 64 lanes (blocks of K lanes, partner
+// distance J) on (key, list) pairs; asc: the final order.
+template <int J>
+__device__ __forceinline__ void sel_step(uint64_t &k, int &l, int K, bool asc) {
+    const int lane = lane_id();
+    const uint64_t pk = xor_lane_u64<J>(k);
+    const int pl = (int)xor_lane<J>((uint32_t)l);
+    const bool up = ((lane & K) == 0) == asc;
+    const bool keep_min = ((lane & J) == 0) == up;
+    const bool p_less = lex_less(pk, pl, k, l);
+    if (keep_min == p_less) {   // take the partner's pair
+        k = pk;
+        l = pl;
+    }
+}
+
+// Half-cleaners J = 32 .. 1 of blocks of K lanes.
+__device__ __forceinline__ void sel_clean(uint64_t &k, int &l, int K, bool asc) {
+    if (K > 32) sel_step<32>(k, l, K, asc);
+    if (K > 16) sel_step<16>(k, l, K, asc);
+    if (K > 8) sel_step<8>(k, l, K, asc);
+    if (K > 4) sel_step<4>(k, l, K, asc);
+    if (K > 2) sel_step<2>(k, l, K, asc);
+    sel_step<1>(k, l, K, asc);
+}
+
+__device__ __forceinline__ void sel_sort64(uint64_t &k, int &l, bool asc) {
+#pragma unroll
+    for (int K = 2; K <= 64; K <<= 1) sel_clean(k, l, K, asc);
+}
+
+__global__ __launch_bounds__(256) void k_coarse_select_w(
+    const float *__restrict__ dt, const float *__restrict__ X, int n, int d, const float *__restrict__ cent,
+    int dpad, const double *__restrict__ cnorm, const double *__restrict__ cmax, int nlist, int metric,
+    int m_uniform, const int32_t *__restrict__ m_per_row, int mmax, int32_t *__restrict__ out,
+    int out_stride, const int32_t *ctl, int gated, int bf) {
+    extern __shared__ __align__(16) unsigned char smem[];   // per wave: the row (dpad floats), then the queue
+    if (gated && call_failed(ctl)) return;
+    const int lane = lane_id(), w = threadIdx.x >> 6;
+    const int row = blockIdx.x * 4 + w;
+    if (row >= n) return;   // whole waves only: this kernel has no block barrier
+    float *sx = reinterpret_cast<float *>(smem) + w * dpad;
+    int *qu = reinterpret_cast<int *>(reinterpret_cast<float *>(smem) + 4 * dpad) + w * SW_Q;
+    int m = m_per_row ? m_per_row[row] : m_uniform;
+    m = m < nlist ? m : nlist;
+    m = m < mmax ? m : mmax;
+    m = m < 1 ? 1 : m;
+    const float *xr = X + (int64_t)row * d;
+    double q2 = 0.0;
+    for (int j = lane; j < dpad; j += 64) {
+        const float v = j < d ? xr[j] : 0.f;
+        sx[j] = v;
+        q2 = __fma_rn((double)v, (double)v, q2);
+    }
+    for (int o = 32; o > 0; o >>= 1) q2 += __shfl_xor(q2, o);
+    const double qn = sqrt(q2) * (1.0 + 0x1p-50);
+    const double cm = *cmax;
+    const double emax = coarse_err(metric, d, bf, qn, cm);
+    const bool every = !(qn + cm < 0x1p60);
+    const float *drow = dt + (int64_t)row * nlist;
+    uint32_t key[SW_MAXL / 64];
+#pragma unroll
+    for (int i = 0; i < SW_MAXL / 64; i++) {
+        const int l = 64 * i + lane;
+        key[i] = l < nlist ? ord_bits(drow[l]) : 0xFFFFFFFFu;
+    }
+    // tau: the m-th smallest key, bit by bit (count(key < t) < m keeps bit b set); counts by ballot
+    const int ni = (nlist + 63) >> 6;
+    uint32_t t = 0;
+    for (int b = 31; b >= 0; b--) {
+        const uint32_t trial = t | (1u << b);
+        int c = 0;
+#pragma unroll
+        for (int i = 0; i < SW_MAXL / 64; i++)
+            if (i < ni) c += (int)__builtin_popcountll(ballot(key[i] < trial));
+        if (c < m) t = trial;
+    }
+    const double ub = (double)from_ord(t) + emax;
+    // the row's best m so far: rank r in lane r (empty: all ones)
+    uint64_t bk = ~0ull;
+    int bl = 0x7FFFFFFF;
+    int qn_ = 0;
+    auto batch = [&](int c) {   // re-check queue[0, c) (c <= 64) and merge it in
+        const int lc = lane < c ? qu[lane] : -1;
+        uint64_t k = ~0ull;
+        int l = 0x7FFFFFFF;
+        if (lc >= 0) {
+            k = ord64(canon_dist(sx, cent + (int64_t)lc * dpad, d, metric));
+            l = lc;
+        }
+        sel_sort64(k, l, false);   // descending: the element-wise minimum with bk is bitonic
+        if (lex_less(k, l, bk, bl)) {
+            bk = k;
+            bl = l;
+        }
+        sel_clean(bk, bl, 64, true);
+    };
+    // candidate test of every list first (all norm loads in flight together), then the queue
+    uint32_t cbits = 0;
+#pragma unroll
+    for (int i = 0; i < SW_MAXL / 64; i++) {
+        const int l = 64 * i + lane;
+        if (i < ni && l < nlist) {
+            const double dv = (double)from_ord(key[i]);
+            const double el = coarse_err(metric, d, bf, qn, cnorm[l]);
+            cbits |= (every || !(dv - el > ub)) ? (1u << i) : 0u;   // "not above": a NaN keeps the list
+        }
+    }
+    for (int i = 0; i < ni; i++) {
+        const int l = 64 * i + lane;
+        const bool isc = (cbits >> i) & 1u;
+        const uint64_t bm = ballot(isc);
+        if (bm) {
+            if (isc) qu[qn_ + (int)__builtin_popcountll(bm & lanemask_lt())] = l;
+            qn_ += (int)__builtin_popcountll(bm);
+            __builtin_amdgcn_wave_barrier();
+            if (qn_ >= 64) {
+                batch(64);
+                const int rest = qn_ - 64;
+                const int v = lane < rest ? qu[64 + lane] : 0;
+                __builtin_amdgcn_wave_barrier();
+                if (lane < rest) qu[lane] = v;
+                __builtin_amdgcn_wave_barrier();
+                qn_ = rest;
+            }
+        }
+    }
+    if (qn_ > 0) batch(qn_);
+    int32_t *orow = out + (int64_t)row * out_stride;
+    for (int p = lane; p < out_stride; p += 64) orow[p] = (p < m && bl != 0x7FFFFFFF) ? bl : -1;
+}
+
 // Nearest list per row (m = 1) from the group minima of k_coarse_gemm<.., 1>.
 // tau = the smallest approximate distance; every list whose certified
 // interval can reach below the best one lies in a group whose minimum is at
@@ -706,6 +856,13 @@ void launch_coarse_select(hipStream_t st, const float *dt, const float *X, int n
                           int m_uniform, const int32_t *m_per_row, int mmax, int32_t *out, int out_stride,
                           const int32_t *ctl, int gated, int bf) {
     if (n <= 0) return;
+    if (nlist <= SW_MAXL && mmax <= SW_MAXM) {
+        hipLaunchKernelGGL(k_coarse_select_w, dim3((n + 3) / 4), dim3(256),
+                           (size_t)4 * dpad * sizeof(float) + (size_t)4 * SW_Q * sizeof(int), st, dt, X, n, d, cent,
+                           dpad, cnorm, cmax, nlist, metric, m_uniform, m_per_row, mmax, out, out_stride, ctl, gated,
+                           bf);
+        return;
+    }
     hipLaunchKernelGGL(k_coarse_select, dim3(n), dim3(256), coarse_select_smem(dpad, mmax), st, dt, X, n, d,
                        cent, dpad, cnorm, cmax, nlist, metric, m_uniform, m_per_row, mmax, out, out_stride,
                        ctl, gated, bf);
