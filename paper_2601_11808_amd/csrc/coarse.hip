@@ -30,13 +30,49 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 constexpr int GM = 128, GN = 128, GK = 32, GLD = GM + 16;
 constexpr int GROUP = 16;   // lists per group minimum (insert path)
 
+// Smallest value m1 (at group position a) and second smallest m2 of a group
+// of 16 lists.  A lane pushes its 4 values, then the lanes holding the other
+// positions of the group (lane ^ 16, lane ^ 32) are merged in; both sides of an
+// exchange end with the same triple.  A NaN counts as +inf.  Equal smallest
+// values leave m2 == m1.
+__device__ __forceinline__ void min2_push(float &m1, float &m2, int &a, float v, int idx) {
+    if (v < m1) {
+        m2 = m1;
+        m1 = v;
+        a = idx;
+    } else if (v < m2) {
+        m2 = v;
+    }
+}
+__device__ __forceinline__ void min2_merge(float &m1, float &m2, int &a, float om1, float om2, int oa) {
+    if (om1 < m1 || (om1 == m1 && oa < a)) {
+        m2 = fminf(m1, om2);
+        m1 = om1;
+        a = oa;
+    } else {
+        m2 = fminf(m2, om1);
+    }
+}
+template <int J>
+__device__ __forceinline__ void min2_xor(float &m1, float &m2, int &a) {
+    const float om1 = __shfl_xor(m1, J), om2 = __shfl_xor(m2, J);
+    const int oa = __shfl_xor(a, J);
+    min2_merge(m1, m2, a, om1, om2, oa);
+}
+// The second smallest value rounded down to a multiple of 16 in the ordered
+// key space (so it never grows), with the position of the smallest in the
+// freed low bits.
+__device__ __forceinline__ uint32_t min2_pack(float m2, int a) { return (ord_bits(m2) & ~15u) | (uint32_t)a; }
+
 constexpr int HLD = GK + 8;  // bf16 operands: row-major LDS rows of 32 + 8 halves (80 bytes)
 
 typedef __bf16 cbf16x8 __attribute__((ext_vector_type(8)));
 
 // GMIN = 0: write Dt[r][l] for every list (out row stride ldo = nlist).
 // GMIN = 1: write only the minimum of each group of 16 consecutive lists,
-//           out[r][l / 16] (ldo = ceil(nlist / 16)); a NaN counts as +inf.
+//           out[r][l / 16] (ldo = ceil(nlist / 16)); a NaN counts as +inf;
+//           out2[r][l / 16] = min2_pack(second smallest, position of the
+//           smallest) of the same group.
 // BF = 1: both operands rounded to bf16 (round to nearest even) and
 //         multiplied on v_mfma_f32_16x16x32_bf16 (16 times the FP32 MFMA
 //         rate); |x|^2 and |c|^2 stay fp32 from the exact values.  The
@@ -46,8 +82,8 @@ __global__ __launch_bounds__(256) void k_coarse_gemm(const float *__restrict__ X
                                                      const float *__restrict__ cent,
                                                      const uint16_t *__restrict__ cent_h, int dpad,
                                                      const float *__restrict__ cn2, int nlist,
-                                                     float *__restrict__ out, int ldo, const int32_t *ctl,
-                                                     int gated, int xcd_map) {
+                                                     float *__restrict__ out, uint32_t *__restrict__ out2, int ldo,
+                                                     const int32_t *ctl, int gated, int xcd_map) {
     // fp32: k-major [GK][GLD] floats per operand; bf16: row-major [GM][HLD] halves per operand
     __shared__ __align__(16) float sbuf[2][BF ? (GM * HLD / 2) : (GK * GLD)];
     __shared__ float sqn[GM];
@@ -215,12 +251,17 @@ __global__ __launch_bounds__(256) void k_coarse_gemm(const float *__restrict__ X
                     }
                 }
             } else {
-                float m = __builtin_inff();
+                float m1 = __builtin_inff(), m2 = __builtin_inff();
+                int a = 0;
 #pragma unroll
-                for (int r = 0; r < 4; r++) m = (gcb + r < nlist && v[r] == v[r]) ? fminf(m, v[r]) : m;
-                m = fminf(m, __shfl_xor(m, 16));
-                m = fminf(m, __shfl_xor(m, 32));
-                if ((lane >> 4) == 0 && gr < n && gc0 < nlist) out[(int64_t)gr * ldo + gc0 / GROUP] = m;
+                for (int r = 0; r < 4; r++)
+                    if (gcb + r < nlist) min2_push(m1, m2, a, v[r], 4 * (lane >> 4) + r);
+                min2_xor<16>(m1, m2, a);
+                min2_xor<32>(m1, m2, a);
+                if ((lane >> 4) == 0 && gr < n && gc0 < nlist) {
+                    out[(int64_t)gr * ldo + gc0 / GROUP] = m1;
+                    out2[(int64_t)gr * ldo + gc0 / GROUP] = min2_pack(m2, a);
+                }
             }
         }
     }
@@ -232,8 +273,8 @@ __global__ __launch_bounds__(256) void k_coarse_gemm(const float *__restrict__ X
 // 16-row operands per 32-dimension step -- and sweeps nct consecutive tiles of 128
 // centroids, each streamed through LDS (double buffer: the next tile's loads
 // are in flight while the current one feeds the MFMAs; one barrier per
-// tile).  Per tile each row gets its 8 group minima, out[r][g] as
-// k_coarse_gemm<., 1> writes them; |c|^2 comes from LDS (+inf past nlist),
+// tile).  Per tile each row gets its 8 group minima, out[r][g] and out2[r][g]
+// as k_coarse_gemm<., 1> writes them; |c|^2 comes from LDS (+inf past nlist),
 // and Dt = |x|^2 + (|c|^2 - 2 x.c) takes one fma per list.
 constexpr int HK = 128, HBLD = HK + 8;   // halves of a padded row; LDS row stride (halves)
 constexpr int HW = 8, HR = 32 * HW;      // waves per block, rows per block
@@ -241,8 +282,8 @@ template <int METRIC>
 __global__ __launch_bounds__(64 * HW) void k_coarse_gmin_h(const float *__restrict__ X, int n, int d,
                                                        const uint16_t *__restrict__ cent_h, int dpad,
                                                        const float *__restrict__ cn2, int nlist,
-                                                       float *__restrict__ out, int ldo, int nct, int xcd_map,
-                                                       const int32_t *ctl, int gated) {
+                                                       float *__restrict__ out, uint32_t *__restrict__ out2, int ldo,
+                                                       int nct, int xcd_map, const int32_t *ctl, int gated) {
     __shared__ __align__(16) uint16_t sB[2][GN * HBLD];
     __shared__ __align__(16) float sC[2][GN];
     if (gated && call_failed(ctl)) return;
@@ -348,32 +389,42 @@ __global__ __launch_bounds__(64 * HW) void k_coarse_gmin_h(const float *__restri
 #pragma unroll
         for (int i = 0; i < 2; i++) {
             float gm[8];
+            uint32_t g2[8];
 #pragma unroll
             for (int j = 0; j < 8; j++) {
                 const float4 c2 = *reinterpret_cast<const float4 *>(&sC[cur][16 * j + 4 * (lane >> 4)]);
                 const float cs[4] = {c2.x, c2.y, c2.z, c2.w};
-                float m = __builtin_inff();
+                float m1 = __builtin_inff(), m2 = __builtin_inff();
+                int a = 0;
 #pragma unroll
                 for (int r = 0; r < 4; r++) {
                     // lists past nlist carry |c|^2 = +inf (IP: masked the same way)
                     const float v = METRIC == 0 ? fmaf(-2.0f, acc[i][j][r], cs[r])
                                                 : (cs[r] == 0.f ? -acc[i][j][r] : __builtin_inff());
-                    m = fminf(m, v);   // a NaN counts as +inf
+                    min2_push(m1, m2, a, v, 4 * (lane >> 4) + r);
                 }
-                m = fminf(m, __shfl_xor(m, 16));
-                m = fminf(m, __shfl_xor(m, 32));
-                gm[j] = METRIC == 0 ? sq[i] + m : m;
+                min2_xor<16>(m1, m2, a);
+                min2_xor<32>(m1, m2, a);
+                // adding |x|^2 is monotone: the order, and so the position, stay
+                gm[j] = METRIC == 0 ? sq[i] + m1 : m1;
+                g2[j] = min2_pack(METRIC == 0 ? sq[i] + m2 : m2, a);
             }
             const int gr = r0 + 32 * w + 16 * i + (lane & 15);
             if ((lane >> 4) == 0 && gr < n) {
                 float *o = out + (int64_t)gr * ldo + t * (GN / GROUP);
+                uint32_t *o2 = out2 + (int64_t)gr * ldo + t * (GN / GROUP);
                 if (vec && t * (GN / GROUP) + 8 <= ldo) {
                     *reinterpret_cast<float4 *>(o) = make_float4(gm[0], gm[1], gm[2], gm[3]);
                     *reinterpret_cast<float4 *>(o + 4) = make_float4(gm[4], gm[5], gm[6], gm[7]);
+                    *reinterpret_cast<uint4 *>(o2) = make_uint4(g2[0], g2[1], g2[2], g2[3]);
+                    *reinterpret_cast<uint4 *>(o2 + 4) = make_uint4(g2[4], g2[5], g2[6], g2[7]);
                 } else {
 #pragma unroll
                     for (int j = 0; j < 8; j++)
-                        if (t * (GN / GROUP) + j < ldo) o[j] = gm[j];
+                        if (t * (GN / GROUP) + j < ldo) {
+                            o[j] = gm[j];
+                            o2[j] = g2[j];
+                        }
                 }
             }
         }
@@ -717,10 +768,15 @@ __global__ __launch_bounds__(256) void k_coarse_select_w(
 // tau = the smallest approximate distance; every list whose certified
 // interval can reach below the best one lies in a group whose minimum is at
 // most tau + 2 max E, so those groups are re-checked exactly (canonical FP64
-// distance, ties to the lower list).  Rows with a non-finite coordinate get
-// -1 (the insert then fails); rows or centroids so large that fp32 squares
-// could overflow are re-checked against every list.  One wave per row.
-__global__ __launch_bounds__(256) void k_coarse_argmin(const float *__restrict__ gmin, int ldg,
+// distance, ties to the lower list).  When the second smallest approximate
+// distance of the row (the other groups' minima and the best group's second
+// value) exceeds tau + 2 max E, no other list can reach below the best one:
+// its canonical distance is smaller than every other list's, and it is taken
+// without a re-check.  Rows with a non-finite coordinate get -1 (the insert
+// then fails); rows or centroids so large that fp32 squares could overflow
+// are re-checked against every list.  One wave per row.
+__global__ __launch_bounds__(256) void k_coarse_argmin(const float *__restrict__ gmin,
+                                                       const uint32_t *__restrict__ gsec, int ldg,
                                                        const float *__restrict__ X, int n, int d,
                                                        const float *__restrict__ cent, int dpad,
                                                        const double *__restrict__ cmax, int nlist, int metric,
@@ -749,9 +805,25 @@ __global__ __launch_bounds__(256) void k_coarse_argmin(const float *__restrict__
     const double emax = coarse_err(metric, d, bf, qn, cm);
     const bool every = !(qn + cm < 0x1p60);
     const float *g = gmin + (int64_t)row * ldg;
-    float t = __builtin_inff();
-    for (int gi = lane; gi < ldg; gi += 64) t = fminf(t, g[gi]);
-    for (int o = 32; o > 0; o >>= 1) t = fminf(t, __shfl_xor(t, o));
+    // the smallest group minimum t (group tg) and the second smallest t2
+    float t = __builtin_inff(), t2 = __builtin_inff();
+    int tg = 0x7fffffff;
+    for (int gi = lane; gi < ldg; gi += 64) min2_push(t, t2, tg, g[gi], gi);
+    min2_xor<32>(t, t2, tg);
+    min2_xor<16>(t, t2, tg);
+    min2_xor<8>(t, t2, tg);
+    min2_xor<4>(t, t2, tg);
+    min2_xor<2>(t, t2, tg);
+    min2_xor<1>(t, t2, tg);
+    if (!every && tg < ldg) {
+        const uint32_t p = gsec[(int64_t)row * ldg + tg];
+        const float sec = fminf(t2, from_ord(p & ~15u));
+        const int l = tg * GROUP + (int)(p & 15u);
+        if ((double)sec - emax > (double)t + emax && l < nlist) {
+            if (lane == 0) out[(int64_t)row * out_stride] = l;
+            return;
+        }
+    }
     const double ub = (double)t + 2.0 * emax;
     double best = __builtin_inf();
     int bestl = 0x7fffffff;
@@ -795,15 +867,15 @@ size_t coarse_select_smem(int dpad, int mmax) {
 template <int GMIN>
 static void coarse_gemm_t(hipStream_t st, const float *X, int n, int d, const float *cent,
                           const uint16_t *cent_h, int dpad,
-                          const float *cn2, int nlist, int metric, float *out, int ldo, const int32_t *ctl,
-                          int gated, int bf) {
+                          const float *cn2, int nlist, int metric, float *out, uint32_t *out2, int ldo,
+                          const int32_t *ctl, int gated, int bf) {
     const int nrb = (n + GM - 1) / GM, ncb = (nlist + GN - 1) / GN;
     const int xcd_map = ncb >= 8 ? 1 : 0;   // fewer centroid blocks than XCDs: plain order
     const unsigned grid = xcd_map ? (unsigned)(8 * ((ncb + 7) / 8) * nrb) : (unsigned)(nrb * ncb);
     const bool vec = (d % 4 == 0) && (((uintptr_t)X & 15) == 0);
 #define SIVF_GEMM(M, V, B)                                                                                      \
     hipLaunchKernelGGL((k_coarse_gemm<M, GMIN, V, B>), dim3(grid), dim3(256), 0, st, X, n, d, cent, cent_h, dpad, \
-                       cn2, nlist, out, ldo, ctl, gated, xcd_map)
+                       cn2, nlist, out, out2, ldo, ctl, gated, xcd_map)
 #define SIVF_GEMM_B(M, V)                                                                                       \
     do {                                                                                                        \
         if (bf) SIVF_GEMM(M, V, 1); else SIVF_GEMM(M, V, 0);                                                    \
@@ -820,7 +892,7 @@ static void coarse_gemm_t(hipStream_t st, const float *X, int n, int d, const fl
 void launch_coarse_gemm(hipStream_t st, const float *X, int n, int d, const float *cent, const uint16_t *cent_h, int dpad,
                         const float *cn2, int nlist, int metric, float *out, const int32_t *ctl,
                         int gated, int bf) {
-    if (n > 0) coarse_gemm_t<0>(st, X, n, d, cent, cent_h, dpad, cn2, nlist, metric, out, nlist, ctl, gated, bf);
+    if (n > 0) coarse_gemm_t<0>(st, X, n, d, cent, cent_h, dpad, cn2, nlist, metric, out, nullptr, nlist, ctl, gated, bf);
 }
 
 int coarse_groups(int nlist) { return (nlist + GROUP - 1) / GROUP; }
@@ -830,6 +902,8 @@ void launch_coarse_assign(hipStream_t st, float *scratch, const float *X, int n,
                           int out_stride, const int32_t *ctl, int gated, int bf) {
     if (n <= 0) return;
     const int ldg = coarse_groups(nlist);
+    // group minima, then the packed second values (2 n ldg words of scratch)
+    uint32_t *gsec = reinterpret_cast<uint32_t *>(scratch + (int64_t)n * ldg);
     if (bf && dpad <= HK) {
         // row-stationary bf16 sweep: segments of nct centroid tiles, enough blocks to fill the chip
         const int nrb = (n + HR - 1) / HR, ncb = (nlist + GN - 1) / GN;
@@ -840,14 +914,14 @@ void launch_coarse_assign(hipStream_t st, float *scratch, const float *X, int n,
         const unsigned grid = xcd_map ? (unsigned)(8 * ((ncs + 7) / 8) * nrb) : (unsigned)(nrb * ncs);
         if (metric == 0)
             hipLaunchKernelGGL(k_coarse_gmin_h<0>, dim3(grid), dim3(64 * HW), 0, st, X, n, d, cent_h, dpad, cn2, nlist,
-                               scratch, ldg, nct, xcd_map, ctl, gated);
+                               scratch, gsec, ldg, nct, xcd_map, ctl, gated);
         else
             hipLaunchKernelGGL(k_coarse_gmin_h<1>, dim3(grid), dim3(64 * HW), 0, st, X, n, d, cent_h, dpad, cn2, nlist,
-                               scratch, ldg, nct, xcd_map, ctl, gated);
+                               scratch, gsec, ldg, nct, xcd_map, ctl, gated);
     } else {
-        coarse_gemm_t<1>(st, X, n, d, cent, cent_h, dpad, cn2, nlist, metric, scratch, ldg, ctl, gated, bf);
+        coarse_gemm_t<1>(st, X, n, d, cent, cent_h, dpad, cn2, nlist, metric, scratch, gsec, ldg, ctl, gated, bf);
     }
-    hipLaunchKernelGGL(k_coarse_argmin, dim3((n + 3) / 4), dim3(256), 0, st, scratch, ldg, X, n, d, cent, dpad,
+    hipLaunchKernelGGL(k_coarse_argmin, dim3((n + 3) / 4), dim3(256), 0, st, scratch, gsec, ldg, X, n, d, cent, dpad,
                        cmax, nlist, metric, out, out_stride, ctl, gated, bf);
 }
 

@@ -1036,10 +1036,15 @@ __device__ __forceinline__ void cert_load_a(float4 (&a)[NB], const float4 *__res
 template <int NB>
 __device__ __forceinline__ f32x4_t cert_mfma(const float4 (&a)[NB], const float4 *qrow, int kgrp, int dp4) {
     f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
+    // the next chunk's LDS read is in flight during this chunk's MFMAs
+    float4 nb = kgrp < dp4 ? qrow[kgrp] : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
     for (int b = 0; b < NB; b++) {
-        const int c = 4 * b + kgrp;
-        const float4 bv = c < dp4 ? qrow[c] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float4 bv = nb;
+        if (b + 1 < NB) {
+            const int c = 4 * b + 4 + kgrp;
+            nb = c < dp4 ? qrow[c] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
         acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[b].x, bv.x, acc, 0, 0, 0);
         acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[b].y, bv.y, acc, 0, 0, 0);
         acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[b].z, bv.z, acc, 0, 0, 0);
@@ -1153,6 +1158,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
     const int nslab = (len + cm) >> cs;
     int wbase = -(1 << 30), wslab = 0;
     int qn = 0;   // queued pairs (fewer than 64 carry over to the next step)
+    const bool one_slab = cs >= 6 && !(p0 & 63);   // steps never straddle slabs
     for (int base = p0; base < p1; base += 64) {
         const int last_ord = min(base + 63, p1 - 1) >> cs;
         if (last_ord >= wbase + 64) {
@@ -1160,29 +1166,40 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
             wslab = (wbase + lane < nslab) ? slab_of(S, l, wbase + lane) : 0;
         }
         // the 4 result rows of this lane in row group rg: positions base + 16 rg + 4 kgrp .. +3
-        int64_t g4[4];
-#pragma unroll
-        for (int rg = 0; rg < 4; rg++) {
-            const int p = base + 16 * rg + 4 * kgrp;
-            const int pc = p < p1 ? p : ((p1 - 1) & ~3);
-            g4[rg] = (int64_t)__shfl(wslab, (pc >> cs) - wbase) * C + (pc & cm);
-        }
-        float4 xn4[4];
-#pragma unroll
-        for (int rg = 0; rg < 4; rg++) xn4[rg] = *reinterpret_cast<const float4 *>(S.xnorm + g4[rg]);
         // A operands of row group rg: slot 16 rg + qcol, chunks 4 b + kgrp; two
         // row groups in flight (the loads of the next overlap this one's MFMAs).
         // Chunks past the row repeat its last chunk (their B lanes are zero and
         // stored values are finite); positions past the item read its last row
         // and are masked below.
+        int64_t g4[4];
         const float4 *xr[4];
+        if (one_slab) {
+            // the step's 64 positions lie in one slab: a scalar slab index
+            const int64_t sb = __builtin_amdgcn_readlane(wslab, (base >> cs) - wbase);
 #pragma unroll
-        for (int rg = 0; rg < 4; rg++) {
-            const int p = base + 16 * rg + qcol;
-            const int pc = p < p1 ? p : p1 - 1;
-            const int slab = __shfl(wslab, (pc >> cs) - wbase);
-            xr[rg] = S.data + (int64_t)slab * dp4 * C + (pc & cm);
+            for (int rg = 0; rg < 4; rg++) {
+                const int p = base + 16 * rg + 4 * kgrp, pr = base + 16 * rg + qcol;
+                g4[rg] = sb * C + ((p < p1 ? p : ((p1 - 1) & ~3)) & cm);
+                xr[rg] = S.data + sb * dp4 * C + ((pr < p1 ? pr : p1 - 1) & cm);
+            }
+        } else {
+#pragma unroll
+            for (int rg = 0; rg < 4; rg++) {
+                const int p = base + 16 * rg + 4 * kgrp;
+                const int pc = p < p1 ? p : ((p1 - 1) & ~3);
+                g4[rg] = (int64_t)__shfl(wslab, (pc >> cs) - wbase) * C + (pc & cm);
+            }
+#pragma unroll
+            for (int rg = 0; rg < 4; rg++) {
+                const int p = base + 16 * rg + qcol;
+                const int pc = p < p1 ? p : p1 - 1;
+                const int slab = __shfl(wslab, (pc >> cs) - wbase);
+                xr[rg] = S.data + (int64_t)slab * dp4 * C + (pc & cm);
+            }
         }
+        float4 xn4[4];
+#pragma unroll
+        for (int rg = 0; rg < 4; rg++) xn4[rg] = *reinterpret_cast<const float4 *>(S.xnorm + g4[rg]);
         f32x4_t acc[4];
         float4 a0[NB], a1[NB];
         cert_load_a<NB>(a0, xr[0], C, kgrp, dp4);
@@ -1259,14 +1276,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
         if (ballot(pmask != 0)) {
             // queue the passing (position, query) pairs in lane order
             const int np = __builtin_popcount(pmask);
-            int incl = np;
-#pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const int u = __shfl_up(incl, o);
-                if (lane >= o) incl += u;
-            }
+            const int incl = wave_incl_scan_dpp(np);
             int at = qn + incl - np;
-            qn += __shfl(incl, 63);
+            qn += __builtin_amdgcn_readlane(incl, 63);
             const int wpos = base - (wbase << cs);   // queued positions are relative to the slab window
             uint32_t m = pmask;
             while (m) {

@@ -84,7 +84,7 @@ Layout make_layout(const sivf_config *c) {
         return o;
     };
     L.cent = take((size_t)nl * L.dp4 * 16);
-    L.cent_h = take(c->storage != SIVF_F32 ? (size_t)nl * L.dp4 * 8 : 0);
+    L.cent_h = take((size_t)nl * L.dp4 * 8);   // bf16 centroids: insert assignment (every storage)
     L.cn2 = take((size_t)nl * 4);
     L.cnorm = take((size_t)nl * 8);
     L.cmax = take(8);
@@ -234,12 +234,15 @@ void coarse(sivf_index *ix, hipStream_t st, float *dt, const float *x, int64_t n
             int mmax, int32_t *out, int out_stride, int gated) {
     const Dev &S = ix->S;
     const int dpad = S.dp4 * 4;
-    // reduced-precision indexes assign inserts on bf16 MFMA; probes stay on FP32 MFMA: a probe batch
-    // is small, and the 64 times tighter bound leaves the exact re-check few candidates
-    const int bf = S.storage != SIVF_F32 && m == 1 && !m_per_row && mmax == 1;
-    // the nearest-list path keeps one minimum per group of 16 lists: 16 times the rows fit the scratch
+    // inserts are assigned on bf16 MFMA (every storage): the nearest list is almost always separated
+    // from the rest by more than the certified bound, and then needs no FP64 re-check; probes stay on
+    // FP32 MFMA: a probe batch is small, and the 64 times tighter bound leaves the exact re-check of
+    // nprobe lists few candidates
+    const int bf = m == 1 && !m_per_row && mmax == 1;
+    // the nearest-list path keeps two words per group of 16 lists: 8 times the rows fit the scratch
     const bool assign = m == 1 && !m_per_row && mmax == 1;
-    const int64_t chunk = assign ? (int64_t)ix->L.coarse_rows * S.nlist / coarse_groups(S.nlist) : ix->L.coarse_rows;
+    const int64_t chunk =
+        assign ? (int64_t)ix->L.coarse_rows * S.nlist / (2 * coarse_groups(S.nlist)) : ix->L.coarse_rows;
     for (int64_t r0 = 0; r0 < n; r0 += chunk) {
         const int nr = (int)((n - r0) < chunk ? (n - r0) : chunk);
         const float *xr = x + r0 * S.d;
@@ -426,7 +429,7 @@ sivf_status sivf_create(const sivf_config *cfg, const float *centroids, void *wo
     S.dir_cap = L.dir_cap;
     S.id_capacity = cfg->id_capacity;
     S.cent = (const float *)(w + L.cent);
-    S.cent_h = cfg->storage != SIVF_F32 ? (const uint16_t *)(w + L.cent_h) : nullptr;
+    S.cent_h = (const uint16_t *)(w + L.cent_h);
     S.cn2 = (const float *)(w + L.cn2);
     S.cnorm = (const double *)(w + L.cnorm);
     S.cmax = (const double *)(w + L.cmax);

@@ -296,6 +296,20 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
     return v;
 }
 
+// The same inclusive sum without LDS permutes: DPP row shifts build the sum
+// inside each row of 16 lanes, then each row adds the totals of the rows
+// before it (lanes 15, 31 and 47, read as scalars).  Every lane must call it.
+__device__ __forceinline__ int wave_incl_scan_dpp(int v) {
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, false);   // row_shr:1 (lane 0 of a row adds 0)
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, false);   // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, false);   // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, false);   // row_shr:8
+    const int r = lane_id() >> 4;
+    const int s0 = __builtin_amdgcn_readlane(v, 15), s1 = __builtin_amdgcn_readlane(v, 31),
+              s2 = __builtin_amdgcn_readlane(v, 47);
+    return v + (r >= 1 ? s0 : 0) + (r >= 2 ? s1 : 0) + (r >= 3 ? s2 : 0);
+}
+
 // Exclusive sum over a block of NT threads (NT multiple of 64, <= 1024);
 // *total receives the block sum.  Uses sbuf[NT/64] of shared memory.
 template <int NT>
