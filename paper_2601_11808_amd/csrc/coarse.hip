@@ -267,6 +267,21 @@ __global__ __launch_bounds__(256) void k_coarse_gemm(const float *__restrict__ X
     }
 }
 
+// Certified bound on |Dt - D| for a row of norm qn and a list of norm cn: the
+// FP32 arithmetic of the GEMM ((4d+16) 2^-24 (|x|+|c|)^2, IP: |x||c|, plus
+// an underflow term) and, with bf16 operands (bf = 1), their rounding:
+// |x.c - x~.c~| <= (2u + u^2)|x||c| with u = 2^-8 (Cauchy-Schwarz), counted
+// twice for L2's -2 x.c, plus the bf16 subnormal spacing.
+__device__ __forceinline__ double coarse_err(int metric, int d, int bf, double qn, double cn) {
+    const double coef = (4.0 * d + 16.0) * 0x1p-24;
+    double e = metric == 0 ? coef * (qn + cn) * (qn + cn) : coef * qn * cn;
+    if (bf) {
+        const double u = 0x1p-8, m = metric == 0 ? 2.0 : 1.0;
+        e += m * (2.0 * u + u * u) * 1.01 * qn * cn + m * 0x1p-132 * sqrt((double)d) * (qn + cn);
+    }
+    return e + (double)d * 0x1p-120;
+}
+
 // Group minima of the insert path on bf16 MFMA, row-stationary (padded rows
 // of at most 128 dimensions): a block of 8 waves takes 256 rows -- rounded to
 // bf16 once and held in registers, wave w owning rows 32 w .. 32 w + 31 as two
@@ -276,14 +291,26 @@ __global__ __launch_bounds__(256) void k_coarse_gemm(const float *__restrict__ X
 // tile).  Per tile each row gets its 8 group minima, out[r][g] and out2[r][g]
 // as k_coarse_gemm<., 1> writes them; |c|^2 comes from LDS (+inf past nlist),
 // and Dt = |x|^2 + (|c|^2 - 2 x.c) takes one fma per list.
+//
+// DEC (one segment holds every list): each lane also keeps, over all tiles, the
+// smallest and second smallest Dt of its rows among its own lists and the list
+// of the smallest; the 4 lanes of a row merge them at the end.  A row whose
+// second smallest Dt exceeds the smallest by more than twice the certified
+// bound (coarse_err with the row's FP64 norm and the largest centroid norm) has
+// its nearest list decided here, with the argmin kernel's test; the others get
+// ASSIGN_UNDECIDED in assign[] and only their group minima (out2 is not
+// written) for the argmin kernel's re-check.
 constexpr int HK = 128, HBLD = HK + 8;   // halves of a padded row; LDS row stride (halves)
 constexpr int HW = 8, HR = 32 * HW;      // waves per block, rows per block
-template <int METRIC>
+constexpr int32_t ASSIGN_UNDECIDED = -2;
+template <int METRIC, bool DEC>
 __global__ __launch_bounds__(64 * HW) void k_coarse_gmin_h(const float *__restrict__ X, int n, int d,
                                                        const uint16_t *__restrict__ cent_h, int dpad,
                                                        const float *__restrict__ cn2, int nlist,
                                                        float *__restrict__ out, uint32_t *__restrict__ out2, int ldo,
-                                                       int nct, int xcd_map, const int32_t *ctl, int gated) {
+                                                       int nct, int xcd_map, const double *__restrict__ cmax,
+                                                       int32_t *__restrict__ assign, int assign_stride,
+                                                       const int32_t *ctl, int gated) {
     __shared__ __align__(16) uint16_t sB[2][GN * HBLD];
     __shared__ __align__(16) float sC[2][GN];
     if (gated && call_failed(ctl)) return;
@@ -303,6 +330,8 @@ __global__ __launch_bounds__(64 * HW) void k_coarse_gmin_h(const float *__restri
     // this lane's rows (16 i + lane % 16 of the wave's 32) as bf16 operands, and their |x|^2
     uint4 a[2][4];
     float sq[2];
+    double q2[2] = {0.0, 0.0};   // DEC: FP64 |x|^2 for the bound
+    bool fin[2] = {true, true};
 #pragma unroll
     for (int i = 0; i < 2; i++) {
         const int r = r0 + 32 * w + 16 * i + (lane & 15);
@@ -315,6 +344,13 @@ __global__ __launch_bounds__(64 * HW) void k_coarse_gmin_h(const float *__restri
             for (int e = 0; e < 8; e++) v[e] = (r < n && k + e < d) ? X[(int64_t)r * d + k + e] : 0.f;
 #pragma unroll
             for (int e = 0; e < 8; e++) part = fmaf(v[e], v[e], part);
+            if (DEC) {
+#pragma unroll
+                for (int e = 0; e < 8; e++) {
+                    fin[i] = fin[i] && __builtin_isfinite(v[e]);
+                    q2[i] = __fma_rn((double)v[e], (double)v[e], q2[i]);
+                }
+            }
             a[i][ks] = make_uint4(to_bf16_bits(v[0]) | (to_bf16_bits(v[1]) << 16),
                                   to_bf16_bits(v[2]) | (to_bf16_bits(v[3]) << 16),
                                   to_bf16_bits(v[4]) | (to_bf16_bits(v[5]) << 16),
@@ -364,6 +400,9 @@ __global__ __launch_bounds__(64 * HW) void k_coarse_gmin_h(const float *__restri
     lstore(0);
     __syncthreads();
     const bool vec = (ldo & 3) == 0;
+    // DEC: per row i, this lane's smallest (b1, list ba) and second smallest b2 of |c|^2 - 2 x.c
+    float b1[2] = {__builtin_inff(), __builtin_inff()}, b2[2] = {__builtin_inff(), __builtin_inff()};
+    int ba[2] = {0, 0};
     for (int t = t0; t < t1; t++) {
         const int cur = (t - t0) & 1;
         if (t + 1 < t1) gload(t + 1);
@@ -401,13 +440,23 @@ __global__ __launch_bounds__(64 * HW) void k_coarse_gmin_h(const float *__restri
                     // lists past nlist carry |c|^2 = +inf (IP: masked the same way)
                     const float v = METRIC == 0 ? fmaf(-2.0f, acc[i][j][r], cs[r])
                                                 : (cs[r] == 0.f ? -acc[i][j][r] : __builtin_inff());
-                    min2_push(m1, m2, a, v, 4 * (lane >> 4) + r);
+                    if (DEC) {
+                        m1 = fminf(m1, v);   // a NaN counts as +inf
+                        min2_push(b1[i], b2[i], ba[i], v, t * GN + 16 * j + 4 * (lane >> 4) + r);
+                    } else {
+                        min2_push(m1, m2, a, v, 4 * (lane >> 4) + r);
+                    }
                 }
-                min2_xor<16>(m1, m2, a);
-                min2_xor<32>(m1, m2, a);
+                if (DEC) {
+                    m1 = fminf(m1, __shfl_xor(m1, 16));
+                    m1 = fminf(m1, __shfl_xor(m1, 32));
+                } else {
+                    min2_xor<16>(m1, m2, a);
+                    min2_xor<32>(m1, m2, a);
+                }
                 // adding |x|^2 is monotone: the order, and so the position, stay
                 gm[j] = METRIC == 0 ? sq[i] + m1 : m1;
-                g2[j] = min2_pack(METRIC == 0 ? sq[i] + m2 : m2, a);
+                g2[j] = DEC ? 0u : min2_pack(METRIC == 0 ? sq[i] + m2 : m2, a);
             }
             const int gr = r0 + 32 * w + 16 * i + (lane & 15);
             if ((lane >> 4) == 0 && gr < n) {
@@ -416,14 +465,16 @@ __global__ __launch_bounds__(64 * HW) void k_coarse_gmin_h(const float *__restri
                 if (vec && t * (GN / GROUP) + 8 <= ldo) {
                     *reinterpret_cast<float4 *>(o) = make_float4(gm[0], gm[1], gm[2], gm[3]);
                     *reinterpret_cast<float4 *>(o + 4) = make_float4(gm[4], gm[5], gm[6], gm[7]);
-                    *reinterpret_cast<uint4 *>(o2) = make_uint4(g2[0], g2[1], g2[2], g2[3]);
-                    *reinterpret_cast<uint4 *>(o2 + 4) = make_uint4(g2[4], g2[5], g2[6], g2[7]);
+                    if (!DEC) {
+                        *reinterpret_cast<uint4 *>(o2) = make_uint4(g2[0], g2[1], g2[2], g2[3]);
+                        *reinterpret_cast<uint4 *>(o2 + 4) = make_uint4(g2[4], g2[5], g2[6], g2[7]);
+                    }
                 } else {
 #pragma unroll
                     for (int j = 0; j < 8; j++)
                         if (t * (GN / GROUP) + j < ldo) {
                             o[j] = gm[j];
-                            o2[j] = g2[j];
+                            if (!DEC) o2[j] = g2[j];
                         }
                 }
             }
@@ -431,21 +482,29 @@ __global__ __launch_bounds__(64 * HW) void k_coarse_gmin_h(const float *__restri
         if (t + 1 < t1) lstore(cur ^ 1);   // its last readers finished before the previous barrier
         __syncthreads();
     }
-}
-
-// Certified bound on |Dt - D| for a row of norm qn and a list of norm cn: the
-// FP32 arithmetic of the GEMM ((4d+16) 2^-24 (|x|+|c|)^2, IP: |x||c|, plus
-// an underflow term) and, with bf16 operands (bf = 1), their rounding:
-// |x.c - x~.c~| <= (2u + u^2)|x||c| with u = 2^-8 (Cauchy-Schwarz), counted
-// twice for L2's -2 x.c, plus the bf16 subnormal spacing.
-__device__ __forceinline__ double coarse_err(int metric, int d, int bf, double qn, double cn) {
-    const double coef = (4.0 * d + 16.0) * 0x1p-24;
-    double e = metric == 0 ? coef * (qn + cn) * (qn + cn) : coef * qn * cn;
-    if (bf) {
-        const double u = 0x1p-8, m = metric == 0 ? 2.0 : 1.0;
-        e += m * (2.0 * u + u * u) * 1.01 * qn * cn + m * 0x1p-132 * sqrt((double)d) * (qn + cn);
+    if (DEC) {
+        const double cm = *cmax;
+#pragma unroll
+        for (int i = 0; i < 2; i++) {
+            min2_xor<16>(b1[i], b2[i], ba[i]);
+            min2_xor<32>(b1[i], b2[i], ba[i]);
+            double q = q2[i];
+            q += __shfl_xor(q, 16);
+            q += __shfl_xor(q, 32);
+            int fi = fin[i] ? 1 : 0;
+            fi &= __shfl_xor(fi, 16);
+            fi &= __shfl_xor(fi, 32);
+            const bool f = fi != 0;
+            const int gr = r0 + 32 * w + 16 * i + (lane & 15);
+            if ((lane >> 4) == 0 && gr < n) {
+                const double qn = sqrt(q) * (1.0 + 0x1p-50);
+                const double e = coarse_err(METRIC, d, 1, qn, cm);
+                const float d1 = METRIC == 0 ? sq[i] + b1[i] : b1[i], d2 = METRIC == 0 ? sq[i] + b2[i] : b2[i];
+                const bool ok = f && qn + cm < 0x1p60 && (double)d2 - e > (double)d1 + e && ba[i] < nlist;
+                assign[(int64_t)gr * assign_stride] = ok ? ba[i] : ASSIGN_UNDECIDED;
+            }
+        }
     }
-    return e + (double)d * 0x1p-120;
 }
 
 // Canonical FP64 coarse distance (sequential fma over ascending dimensions;
@@ -774,19 +833,16 @@ __global__ __launch_bounds__(256) void k_coarse_select_w(
 // its canonical distance is smaller than every other list's, and it is taken
 // without a re-check.  Rows with a non-finite coordinate get -1 (the insert
 // then fails); rows or centroids so large that fp32 squares could overflow
-// are re-checked against every list.  One wave per row.
-__global__ __launch_bounds__(256) void k_coarse_argmin(const float *__restrict__ gmin,
-                                                       const uint32_t *__restrict__ gsec, int ldg,
-                                                       const float *__restrict__ X, int n, int d,
-                                                       const float *__restrict__ cent, int dpad,
-                                                       const double *__restrict__ cmax, int nlist, int metric,
-                                                       int32_t *__restrict__ out, int out_stride,
-                                                       const int32_t *ctl, int gated, int bf) {
-    if (gated && call_failed(ctl)) return;
+// are re-checked against every list.  One wave per row (row wave-uniform: its
+// coordinates are read through the scalar cache).  Without gsec (rows the
+// group-minima kernel left undecided) the separation test is skipped.
+__device__ __forceinline__ void argmin_row(int row, const float *__restrict__ gmin,
+                                           const uint32_t *__restrict__ gsec, int ldg,
+                                           const float *__restrict__ X, int d,
+                                           const float *__restrict__ cent, int dpad,
+                                           const double *__restrict__ cmax, int nlist, int metric,
+                                           int32_t *__restrict__ out, int out_stride, int bf) {
     const int lane = threadIdx.x & 63;
-    // wave-uniform row: its coordinates are read through the scalar cache
-    const int row = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
-    if (row >= n) return;
     const float *xr = X + (int64_t)row * d;
     double q2 = 0.0;
     bool fin = true;
@@ -815,7 +871,7 @@ __global__ __launch_bounds__(256) void k_coarse_argmin(const float *__restrict__
     min2_xor<4>(t, t2, tg);
     min2_xor<2>(t, t2, tg);
     min2_xor<1>(t, t2, tg);
-    if (!every && tg < ldg) {
+    if (gsec && !every && tg < ldg) {
         const uint32_t p = gsec[(int64_t)row * ldg + tg];
         const float sec = fminf(t2, from_ord(p & ~15u));
         const int l = tg * GROUP + (int)(p & 15u);
@@ -857,6 +913,37 @@ __global__ __launch_bounds__(256) void k_coarse_argmin(const float *__restrict__
         }
     }
     if (lane == 0) out[(int64_t)row * out_stride] = bestl < nlist ? bestl : -1;
+}
+
+// all_rows: one wave per row.  Otherwise every wave takes chunks of AM_CHUNK
+// rows and re-checks only those marked ASSIGN_UNDECIDED (small chunks: the
+// re-checks, a latency chain each, spread over many waves).
+constexpr int AM_CHUNK = 16, AM_MAXB = 16384;
+__global__ __launch_bounds__(256) void k_coarse_argmin(const float *__restrict__ gmin,
+                                                       const uint32_t *__restrict__ gsec, int ldg,
+                                                       const float *__restrict__ X, int n, int d,
+                                                       const float *__restrict__ cent, int dpad,
+                                                       const double *__restrict__ cmax, int nlist, int metric,
+                                                       int32_t *__restrict__ out, int out_stride,
+                                                       const int32_t *ctl, int gated, int bf, int all_rows) {
+    if (gated && call_failed(ctl)) return;
+    const int wid = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (all_rows) {
+        const int row = __builtin_amdgcn_readfirstlane(wid);
+        if (row < n) argmin_row(row, gmin, gsec, ldg, X, d, cent, dpad, cmax, nlist, metric, out, out_stride, bf);
+        return;
+    }
+    const int nw = gridDim.x * 4, lane = threadIdx.x & 63;
+    for (int c0 = wid * AM_CHUNK; c0 < n; c0 += nw * AM_CHUNK) {
+        const int r = c0 + lane;
+        uint64_t m = ballot(lane < AM_CHUNK && r < n && out[(int64_t)r * out_stride] == ASSIGN_UNDECIDED);
+        while (m) {
+            const int b = __builtin_ctzll(m);
+            m &= m - 1;
+            argmin_row(__builtin_amdgcn_readfirstlane(c0 + b), gmin, nullptr, ldg, X, d, cent, dpad, cmax, nlist,
+                       metric, out, out_stride, bf);
+        }
+    }
 }
 
 size_t coarse_select_smem(int dpad, int mmax) {
@@ -904,6 +991,7 @@ void launch_coarse_assign(hipStream_t st, float *scratch, const float *X, int n,
     const int ldg = coarse_groups(nlist);
     // group minima, then the packed second values (2 n ldg words of scratch)
     uint32_t *gsec = reinterpret_cast<uint32_t *>(scratch + (int64_t)n * ldg);
+    bool decided = false;
     if (bf && dpad <= HK) {
         // row-stationary bf16 sweep: segments of nct centroid tiles, enough blocks to fill the chip
         const int nrb = (n + HR - 1) / HR, ncb = (nlist + GN - 1) / GN;
@@ -912,17 +1000,27 @@ void launch_coarse_assign(hipStream_t st, float *scratch, const float *X, int n,
         const int ncs = (ncb + nct - 1) / nct;
         const int xcd_map = ncs >= 8 ? 1 : 0;
         const unsigned grid = xcd_map ? (unsigned)(8 * ((ncs + 7) / 8) * nrb) : (unsigned)(nrb * ncs);
-        if (metric == 0)
-            hipLaunchKernelGGL(k_coarse_gmin_h<0>, dim3(grid), dim3(64 * HW), 0, st, X, n, d, cent_h, dpad, cn2, nlist,
-                               scratch, gsec, ldg, nct, xcd_map, ctl, gated);
-        else
-            hipLaunchKernelGGL(k_coarse_gmin_h<1>, dim3(grid), dim3(64 * HW), 0, st, X, n, d, cent_h, dpad, cn2, nlist,
-                               scratch, gsec, ldg, nct, xcd_map, ctl, gated);
+        decided = ncs == 1;   // one block sees every list of its rows
+#define SIVF_GMIN(M, DEC)                                                                                        \
+    hipLaunchKernelGGL((k_coarse_gmin_h<M, DEC>), dim3(grid), dim3(64 * HW), 0, st, X, n, d, cent_h, dpad, cn2,   \
+                       nlist, scratch, gsec, ldg, nct, xcd_map, cmax, out, out_stride, ctl, gated)
+        if (metric == 0) {
+            if (decided) SIVF_GMIN(0, true); else SIVF_GMIN(0, false);
+        } else {
+            if (decided) SIVF_GMIN(1, true); else SIVF_GMIN(1, false);
+        }
+#undef SIVF_GMIN
     } else {
         coarse_gemm_t<1>(st, X, n, d, cent, cent_h, dpad, cn2, nlist, metric, scratch, gsec, ldg, ctl, gated, bf);
     }
-    hipLaunchKernelGGL(k_coarse_argmin, dim3((n + 3) / 4), dim3(256), 0, st, scratch, gsec, ldg, X, n, d, cent, dpad,
-                       cmax, nlist, metric, out, out_stride, ctl, gated, bf);
+    if (decided) {
+        const int chunks = (n + AM_CHUNK - 1) / AM_CHUNK, nb = (chunks + 3) / 4;
+        hipLaunchKernelGGL(k_coarse_argmin, dim3(nb < AM_MAXB ? nb : AM_MAXB), dim3(256), 0, st, scratch, nullptr, ldg, X,
+                           n, d, cent, dpad, cmax, nlist, metric, out, out_stride, ctl, gated, bf, 0);
+    } else {
+        hipLaunchKernelGGL(k_coarse_argmin, dim3((n + 3) / 4), dim3(256), 0, st, scratch, gsec, ldg, X, n, d, cent,
+                           dpad, cmax, nlist, metric, out, out_stride, ctl, gated, bf, 1);
+    }
 }
 
 void launch_coarse_select(hipStream_t st, const float *dt, const float *X, int n, int d, const float *cent,

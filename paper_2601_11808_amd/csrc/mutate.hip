@@ -271,8 +271,10 @@ __global__ __launch_bounds__(256) void k_add_scatter(Dev S, const float *__restr
 // one wave per SENT consecutive new entries.  The wave first reads the
 // entries' source rows whole (consecutive lanes read consecutive chunks of a
 // row) into LDS, then writes chunk c of every entry (consecutive lanes,
-// consecutive slots), so reads and writes are both contiguous runs.
-constexpr int SENT = 32;
+// consecutive slots), so reads and writes are both contiguous runs.  16
+// entries per wave keep the staging area at 8.25 KiB (d = 128), so that many
+// waves per CU have loads in flight.
+constexpr int SENT = 16;
 
 __global__ __launch_bounds__(64) void k_add_scatter_lds(Dev S, const float *__restrict__ x,
                                                          const int64_t *__restrict__ ids,
@@ -294,31 +296,32 @@ __global__ __launch_bounds__(64) void k_add_scatter_lds(Dev S, const float *__re
         slab = (int)(g / (uint32_t)S.C);
         slot = (int)(g % (uint32_t)S.C);
     }
-    // rows into LDS: up to 16 chunks per lane in flight (all of a 128-dim batch)
+    // rows into LDS: 8 chunks per lane in flight (all of a 128-dim batch)
     const int tot = cnt * dp4;
-    for (int f0 = 0; f0 < tot; f0 += 16 * WAVE) {
-        float4 v[16];
-        int rr[16], cc[16];
+    for (int f0 = 0; f0 < tot; f0 += 8 * WAVE) {
+        float4 v[8];
 #pragma unroll
-        for (int u = 0; u < 16; u++) {
-            const int f = f0 + u * WAVE + lane;
-            rr[u] = f / dp4;
-            cc[u] = f - rr[u] * dp4;
-            const int src = __shfl(i, rr[u] < SENT ? rr[u] : 0);
-            if (f < tot) v[u] = reinterpret_cast<const float4 *>(x + (int64_t)src * S.d)[cc[u]];
+        for (int u = 0; u < 8; u++) {
+            const int f = min(f0 + u * WAVE + lane, tot - 1);   // past the end: re-read the last chunk
+            const int r = f / dp4;
+            const int src = __shfl(i, r);
+            v[u] = reinterpret_cast<const float4 *>(x + (int64_t)src * S.d)[f - r * dp4];
         }
 #pragma unroll
-        for (int u = 0; u < 16; u++)
-            if (f0 + u * WAVE + lane < tot) srow[rr[u] * ld + cc[u]] = v[u];
+        for (int u = 0; u < 8; u++) {
+            const int f = f0 + u * WAVE + lane;
+            const int r = f / dp4;
+            if (f < tot) srow[r * ld + (f - r * dp4)] = v[u];
+        }
     }
     __syncthreads();
-    // chunk c of entry e: lanes e + SENT * h take chunks h, h + 2, ...
+    // chunk c of entry e: lanes e + SENT * h take chunks h, h + WAVE / SENT, ...
     {
         const int e = lane % SENT, h = lane / SENT;
         const int sl = __shfl(slab, e), so = __shfl(slot, e);
         if (e < cnt) {
             float4 *dst = S.data + (int64_t)sl * dp4 * S.C + so;
-            for (int c = h; c < dp4; c += 2) dst[(int64_t)c * S.C] = srow[e * ld + c];
+            for (int c = h; c < dp4; c += WAVE / SENT) dst[(int64_t)c * S.C] = srow[e * ld + c];
         }
     }
     if (lane < cnt) {
