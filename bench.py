@@ -303,7 +303,7 @@ def bulk_mutation_leg(w, x, ids, reps=3):
         "insert": {"vectors": N, "ms": round(am, 4), "vec_per_s": round(N / (am * 1e-3), 1),
                    "algorithmic_bytes": ins_b, "GBps": round(ins_gbps, 1), "frac": round(ins_gbps / HBM_PEAK_GBPS, 4),
                    "bytes_per_vector": 8 * d + 8,
-                   "note": "the call includes the exact coarse assignment (FP32 MFMA GEMM + FP64 re-check)"},
+                   "note": "the call includes the exact coarse assignment (bf16 MFMA with the certified bound; FP64 re-check of the rows it leaves undecided)"},
         "delete": {"ids": N // 2, "ms": round(rmm, 4), "vec_per_s": round((N // 2) / (rmm * 1e-3), 1),
                    "algorithmic_bytes": del_b, "GBps": round(del_gbps, 1), "frac": round(del_gbps / HBM_PEAK_GBPS, 4),
                    "bytes_per_id": 4 + 2 * (4 * d + 4) + 8},

@@ -997,6 +997,8 @@ void launch_coarse_assign(hipStream_t st, float *scratch, const float *X, int n,
         const int nrb = (n + HR - 1) / HR, ncb = (nlist + GN - 1) / GN;
         int nct = (int)(((int64_t)nrb * ncb) / 1024);
         nct = nct < 1 ? 1 : (nct > 16 ? 16 : nct);
+        // a block per CU at least, and 16 tiles or fewer: one segment, so rows are decided in the sweep
+        if (nrb >= 256 && ncb <= 16) nct = ncb;
         const int ncs = (ncb + nct - 1) / nct;
         const int xcd_map = ncs >= 8 ? 1 : 0;
         const unsigned grid = xcd_map ? (unsigned)(8 * ((ncs + 7) / 8) * nrb) : (unsigned)(nrb * ncs);
