@@ -59,10 +59,12 @@ __device__ __forceinline__ void min2_xor(float &m1, float &m2, int &a) {
     const int oa = __shfl_xor(a, J);
     min2_merge(m1, m2, a, om1, om2, oa);
 }
-// The second smallest value rounded down to a multiple of 16 in the ordered
-// key space (so it never grows), with the position of the smallest in the
-// freed low bits.
-__device__ __forceinline__ uint32_t min2_pack(float m2, int a) { return (ord_bits(m2) & ~15u) | (uint32_t)a; }
+// The second smallest value rounded down to a multiple of 2^SEG_BITS in the
+// ordered key space (so it never grows: the relative change is below 2^-12),
+// with the position of the smallest (< 2^SEG_BITS) in the freed low bits.
+constexpr int SEG_BITS = 11;
+constexpr uint32_t SEG_MASK = (1u << SEG_BITS) - 1;
+__device__ __forceinline__ uint32_t min2_pack(float m2, int a) { return (ord_bits(m2) & ~SEG_MASK) | (uint32_t)a; }
 
 constexpr int HLD = GK + 8;  // bf16 operands: row-major LDS rows of 32 + 8 halves (80 bytes)
 
@@ -72,7 +74,7 @@ typedef __bf16 cbf16x8 __attribute__((ext_vector_type(8)));
 // GMIN = 1: write only the minimum of each group of 16 consecutive lists,
 //           out[r][l / 16] (ldo = ceil(nlist / 16)); a NaN counts as +inf;
 //           out2[r][l / 16] = min2_pack(second smallest, position of the
-//           smallest) of the same group.
+//           smallest) of the same group (here a segment is one group).
 // BF = 1: both operands rounded to bf16 (round to nearest even) and
 //         multiplied on v_mfma_f32_16x16x32_bf16 (16 times the FP32 MFMA
 //         rate); |x|^2 and |c|^2 stay fp32 from the exact values.  The
@@ -288,22 +290,28 @@ __device__ __forceinline__ double coarse_err(int metric, int d, int bf, double q
 // 16-row operands per 32-dimension step -- and sweeps nct consecutive tiles of 128
 // centroids, each streamed through LDS (double buffer: the next tile's loads
 // are in flight while the current one feeds the MFMAs; one barrier per
-// tile).  Per tile each row gets its 8 group minima, out[r][g] and out2[r][g]
-// as k_coarse_gemm<., 1> writes them; |c|^2 comes from LDS (+inf past nlist),
-// and Dt = |x|^2 + (|c|^2 - 2 x.c) takes one fma per list.
+// tile).  Per tile each row gets its 8 group minima, out[r][g] as
+// k_coarse_gemm<., 1> writes them; |c|^2 comes from LDS (+inf past nlist),
+// and Dt = |x|^2 + (|c|^2 - 2 x.c) takes one fma per list.  Each lane also
+// keeps, over the segment's tiles, the smallest and second smallest Dt of its
+// rows among its own lists and the position of the smallest; the 4 lanes of a
+// row merge them at the end, and out2[r][segment] = min2_pack(second
+// smallest, position in the segment).
 //
-// DEC (one segment holds every list): each lane also keeps, over all tiles, the
-// smallest and second smallest Dt of its rows among its own lists and the list
-// of the smallest; the 4 lanes of a row merge them at the end.  A row whose
-// second smallest Dt exceeds the smallest by more than twice the certified
-// bound (coarse_err with the row's FP64 norm and the largest centroid norm) has
-// its nearest list decided here, with the argmin kernel's test; the others get
-// ASSIGN_UNDECIDED in assign[] and only their group minima (out2 is not
-// written) for the argmin kernel's re-check.
+// MODE GM_PLAIN (more than 16 tiles of lists, where the tracking costs more
+// in this kernel than the re-checks it saves) writes only the group minima.
+// GM_SEG writes out2 as above.  GM_DEC (one segment holds every list): instead
+// of out2, a row whose second
+// smallest Dt exceeds the smallest by more than twice the certified bound
+// (coarse_err with the row's FP64 norm and the largest centroid norm) has its
+// nearest list decided here, with the argmin kernel's test; the others get
+// ASSIGN_UNDECIDED in assign[] and only their group minima for the argmin
+// kernel's re-check.
 constexpr int HK = 128, HBLD = HK + 8;   // halves of a padded row; LDS row stride (halves)
 constexpr int HW = 8, HR = 32 * HW;      // waves per block, rows per block
 constexpr int32_t ASSIGN_UNDECIDED = -2;
-template <int METRIC, bool DEC>
+constexpr int GM_PLAIN = 0, GM_SEG = 1, GM_DEC = 2;
+template <int METRIC, int MODE>
 __global__ __launch_bounds__(64 * HW) void k_coarse_gmin_h(const float *__restrict__ X, int n, int d,
                                                        const uint16_t *__restrict__ cent_h, int dpad,
                                                        const float *__restrict__ cn2, int nlist,
@@ -327,6 +335,7 @@ __global__ __launch_bounds__(64 * HW) void k_coarse_gmin_h(const float *__restri
         sg = (int)blockIdx.x / nrb;
     }
     const int r0 = rb * HR, t0 = sg * nct, t1 = min(t0 + nct, ncb);
+    constexpr bool DEC = MODE == GM_DEC, TRACK = MODE != GM_PLAIN;
     // this lane's rows (16 i + lane % 16 of the wave's 32) as bf16 operands, and their |x|^2
     uint4 a[2][4];
     float sq[2];
@@ -400,7 +409,7 @@ __global__ __launch_bounds__(64 * HW) void k_coarse_gmin_h(const float *__restri
     lstore(0);
     __syncthreads();
     const bool vec = (ldo & 3) == 0;
-    // DEC: per row i, this lane's smallest (b1, list ba) and second smallest b2 of |c|^2 - 2 x.c
+    // per row i, this lane's smallest (b1, at segment position ba) and second smallest b2 of |c|^2 - 2 x.c
     float b1[2] = {__builtin_inff(), __builtin_inff()}, b2[2] = {__builtin_inff(), __builtin_inff()};
     int ba[2] = {0, 0};
     for (int t = t0; t < t1; t++) {
@@ -428,59 +437,49 @@ __global__ __launch_bounds__(64 * HW) void k_coarse_gmin_h(const float *__restri
 #pragma unroll
         for (int i = 0; i < 2; i++) {
             float gm[8];
-            uint32_t g2[8];
 #pragma unroll
             for (int j = 0; j < 8; j++) {
                 const float4 c2 = *reinterpret_cast<const float4 *>(&sC[cur][16 * j + 4 * (lane >> 4)]);
                 const float cs[4] = {c2.x, c2.y, c2.z, c2.w};
-                float m1 = __builtin_inff(), m2 = __builtin_inff();
-                int a = 0;
+                float m1 = __builtin_inff();
 #pragma unroll
                 for (int r = 0; r < 4; r++) {
                     // lists past nlist carry |c|^2 = +inf (IP: masked the same way)
                     const float v = METRIC == 0 ? fmaf(-2.0f, acc[i][j][r], cs[r])
                                                 : (cs[r] == 0.f ? -acc[i][j][r] : __builtin_inff());
-                    if (DEC) {
-                        m1 = fminf(m1, v);   // a NaN counts as +inf
-                        min2_push(b1[i], b2[i], ba[i], v, t * GN + 16 * j + 4 * (lane >> 4) + r);
-                    } else {
-                        min2_push(m1, m2, a, v, 4 * (lane >> 4) + r);
-                    }
+                    m1 = fminf(m1, v);   // a NaN counts as +inf
+                    if (TRACK) min2_push(b1[i], b2[i], ba[i], v, (t - t0) * GN + 16 * j + 4 * (lane >> 4) + r);
                 }
-                if (DEC) {
-                    m1 = fminf(m1, __shfl_xor(m1, 16));
-                    m1 = fminf(m1, __shfl_xor(m1, 32));
-                } else {
-                    min2_xor<16>(m1, m2, a);
-                    min2_xor<32>(m1, m2, a);
-                }
-                // adding |x|^2 is monotone: the order, and so the position, stay
+                m1 = fminf(m1, __shfl_xor(m1, 16));
+                m1 = fminf(m1, __shfl_xor(m1, 32));
                 gm[j] = METRIC == 0 ? sq[i] + m1 : m1;
-                g2[j] = DEC ? 0u : min2_pack(METRIC == 0 ? sq[i] + m2 : m2, a);
             }
             const int gr = r0 + 32 * w + 16 * i + (lane & 15);
             if ((lane >> 4) == 0 && gr < n) {
                 float *o = out + (int64_t)gr * ldo + t * (GN / GROUP);
-                uint32_t *o2 = out2 + (int64_t)gr * ldo + t * (GN / GROUP);
                 if (vec && t * (GN / GROUP) + 8 <= ldo) {
                     *reinterpret_cast<float4 *>(o) = make_float4(gm[0], gm[1], gm[2], gm[3]);
                     *reinterpret_cast<float4 *>(o + 4) = make_float4(gm[4], gm[5], gm[6], gm[7]);
-                    if (!DEC) {
-                        *reinterpret_cast<uint4 *>(o2) = make_uint4(g2[0], g2[1], g2[2], g2[3]);
-                        *reinterpret_cast<uint4 *>(o2 + 4) = make_uint4(g2[4], g2[5], g2[6], g2[7]);
-                    }
                 } else {
 #pragma unroll
                     for (int j = 0; j < 8; j++)
-                        if (t * (GN / GROUP) + j < ldo) {
-                            o[j] = gm[j];
-                            if (!DEC) o2[j] = g2[j];
-                        }
+                        if (t * (GN / GROUP) + j < ldo) o[j] = gm[j];
                 }
             }
         }
         if (t + 1 < t1) lstore(cur ^ 1);   // its last readers finished before the previous barrier
         __syncthreads();
+    }
+    if (MODE == GM_SEG) {
+#pragma unroll
+        for (int i = 0; i < 2; i++) {
+            min2_xor<16>(b1[i], b2[i], ba[i]);
+            min2_xor<32>(b1[i], b2[i], ba[i]);
+            const int gr = r0 + 32 * w + 16 * i + (lane & 15);
+            // adding |x|^2 is monotone: the order, and so the position, stay
+            if ((lane >> 4) == 0 && gr < n)
+                out2[(int64_t)gr * ncs + sg] = min2_pack(METRIC == 0 ? sq[i] + b2[i] : b2[i], ba[i]);
+        }
     }
     if (DEC) {
         const double cm = *cmax;
@@ -837,7 +836,7 @@ __global__ __launch_bounds__(256) void k_coarse_select_w(
 // coordinates are read through the scalar cache).  Without gsec (rows the
 // group-minima kernel left undecided) the separation test is skipped.
 __device__ __forceinline__ void argmin_row(int row, const float *__restrict__ gmin,
-                                           const uint32_t *__restrict__ gsec, int ldg,
+                                           const uint32_t *__restrict__ gsec, int gps, int ldg,
                                            const float *__restrict__ X, int d,
                                            const float *__restrict__ cent, int dpad,
                                            const double *__restrict__ cmax, int nlist, int metric,
@@ -872,9 +871,12 @@ __device__ __forceinline__ void argmin_row(int row, const float *__restrict__ gm
     min2_xor<2>(t, t2, tg);
     min2_xor<1>(t, t2, tg);
     if (gsec && !every && tg < ldg) {
-        const uint32_t p = gsec[(int64_t)row * ldg + tg];
-        const float sec = fminf(t2, from_ord(p & ~15u));
-        const int l = tg * GROUP + (int)(p & 15u);
+        // segments of gps groups: the best group's segment gives the position of the smallest and
+        // its second smallest; t2 covers the lists of every other group
+        const int sg = tg / gps, nseg = (ldg + gps - 1) / gps;
+        const uint32_t p = gsec[(int64_t)row * nseg + sg];
+        const float sec = fminf(t2, from_ord(p & ~SEG_MASK));
+        const int l = sg * gps * GROUP + (int)(p & SEG_MASK);
         if ((double)sec - emax > (double)t + emax && l < nlist) {
             if (lane == 0) out[(int64_t)row * out_stride] = l;
             return;
@@ -920,7 +922,7 @@ __device__ __forceinline__ void argmin_row(int row, const float *__restrict__ gm
 // re-checks, a latency chain each, spread over many waves).
 constexpr int AM_CHUNK = 16, AM_MAXB = 16384;
 __global__ __launch_bounds__(256) void k_coarse_argmin(const float *__restrict__ gmin,
-                                                       const uint32_t *__restrict__ gsec, int ldg,
+                                                       const uint32_t *__restrict__ gsec, int gps, int ldg,
                                                        const float *__restrict__ X, int n, int d,
                                                        const float *__restrict__ cent, int dpad,
                                                        const double *__restrict__ cmax, int nlist, int metric,
@@ -930,7 +932,7 @@ __global__ __launch_bounds__(256) void k_coarse_argmin(const float *__restrict__
     const int wid = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (all_rows) {
         const int row = __builtin_amdgcn_readfirstlane(wid);
-        if (row < n) argmin_row(row, gmin, gsec, ldg, X, d, cent, dpad, cmax, nlist, metric, out, out_stride, bf);
+        if (row < n) argmin_row(row, gmin, gsec, gps, ldg, X, d, cent, dpad, cmax, nlist, metric, out, out_stride, bf);
         return;
     }
     const int nw = gridDim.x * 4, lane = threadIdx.x & 63;
@@ -940,8 +942,8 @@ __global__ __launch_bounds__(256) void k_coarse_argmin(const float *__restrict__
         while (m) {
             const int b = __builtin_ctzll(m);
             m &= m - 1;
-            argmin_row(__builtin_amdgcn_readfirstlane(c0 + b), gmin, nullptr, ldg, X, d, cent, dpad, cmax, nlist,
-                       metric, out, out_stride, bf);
+            argmin_row(__builtin_amdgcn_readfirstlane(c0 + b), gmin, nullptr, 1, ldg, X, d, cent, dpad, cmax,
+                       nlist, metric, out, out_stride, bf);
         }
     }
 }
@@ -992,6 +994,7 @@ void launch_coarse_assign(hipStream_t st, float *scratch, const float *X, int n,
     // group minima, then the packed second values (2 n ldg words of scratch)
     uint32_t *gsec = reinterpret_cast<uint32_t *>(scratch + (int64_t)n * ldg);
     bool decided = false;
+    int gps = 1;   // groups per segment of gsec
     if (bf && dpad <= HK) {
         // row-stationary bf16 sweep: segments of nct centroid tiles, enough blocks to fill the chip
         const int nrb = (n + HR - 1) / HR, ncb = (nlist + GN - 1) / GN;
@@ -1003,24 +1006,30 @@ void launch_coarse_assign(hipStream_t st, float *scratch, const float *X, int n,
         const int xcd_map = ncs >= 8 ? 1 : 0;
         const unsigned grid = xcd_map ? (unsigned)(8 * ((ncs + 7) / 8) * nrb) : (unsigned)(nrb * ncs);
         decided = ncs == 1;   // one block sees every list of its rows
-#define SIVF_GMIN(M, DEC)                                                                                        \
-    hipLaunchKernelGGL((k_coarse_gmin_h<M, DEC>), dim3(grid), dim3(64 * HW), 0, st, X, n, d, cent_h, dpad, cn2,   \
+        const int mode = decided ? GM_DEC : (ncb <= 16 ? GM_SEG : GM_PLAIN);
+        gps = nct * (GN / GROUP);
+        if (mode == GM_PLAIN) gsec = nullptr;
+#define SIVF_GMIN(M, MODE)                                                                                       \
+    hipLaunchKernelGGL((k_coarse_gmin_h<M, MODE>), dim3(grid), dim3(64 * HW), 0, st, X, n, d, cent_h, dpad, cn2,  \
                        nlist, scratch, gsec, ldg, nct, xcd_map, cmax, out, out_stride, ctl, gated)
-        if (metric == 0) {
-            if (decided) SIVF_GMIN(0, true); else SIVF_GMIN(0, false);
-        } else {
-            if (decided) SIVF_GMIN(1, true); else SIVF_GMIN(1, false);
-        }
+#define SIVF_GMIN_M(M)                                                                                           \
+    do {                                                                                                         \
+        if (mode == GM_DEC) SIVF_GMIN(M, GM_DEC);                                                                \
+        else if (mode == GM_SEG) SIVF_GMIN(M, GM_SEG);                                                           \
+        else SIVF_GMIN(M, GM_PLAIN);                                                                             \
+    } while (0)
+        if (metric == 0) SIVF_GMIN_M(0); else SIVF_GMIN_M(1);
+#undef SIVF_GMIN_M
 #undef SIVF_GMIN
     } else {
         coarse_gemm_t<1>(st, X, n, d, cent, cent_h, dpad, cn2, nlist, metric, scratch, gsec, ldg, ctl, gated, bf);
     }
     if (decided) {
         const int chunks = (n + AM_CHUNK - 1) / AM_CHUNK, nb = (chunks + 3) / 4;
-        hipLaunchKernelGGL(k_coarse_argmin, dim3(nb < AM_MAXB ? nb : AM_MAXB), dim3(256), 0, st, scratch, nullptr, ldg, X,
+        hipLaunchKernelGGL(k_coarse_argmin, dim3(nb < AM_MAXB ? nb : AM_MAXB), dim3(256), 0, st, scratch, nullptr, 1, ldg, X,
                            n, d, cent, dpad, cmax, nlist, metric, out, out_stride, ctl, gated, bf, 0);
     } else {
-        hipLaunchKernelGGL(k_coarse_argmin, dim3((n + 3) / 4), dim3(256), 0, st, scratch, gsec, ldg, X, n, d, cent,
+        hipLaunchKernelGGL(k_coarse_argmin, dim3((n + 3) / 4), dim3(256), 0, st, scratch, gsec, gps, ldg, X, n, d, cent,
                            dpad, cmax, nlist, metric, out, out_stride, ctl, gated, bf, 1);
     }
 }
