@@ -143,6 +143,28 @@ def test_assign_bf16_large_batches(metric):
 
 
 @pytest.mark.parametrize("metric", [0, 1])
+def test_assign_decided_in_sweep(metric):
+    """Batches of 65,536 rows or more over at most 2,048 lists: the bf16 sweep
+    sees every list of its rows, decides the rows whose nearest list is
+    separated by the certified bound and leaves the others to the FP64
+    re-check.  Exact ties (duplicate centroids), near-equidistant points,
+    centroid copies and rows too large for fp32 squares all equal the oracle,
+    as does a random sample of the rest; fp32 and bf16 storage."""
+    for d, nlist, n, storage in [(128, 1024, 70000, 0), (96, 2048, 66000, 0), (40, 1500, 80000, 1)]:
+        cent, x = _tie_data(d * 7 + nlist + metric, d, nlist, n)
+        x[-20:] = cent[:20] * np.float32(3e18)          # |x|^2 overflows fp32: every list re-checked
+        rng = np.random.default_rng([d, nlist, metric])
+        ix = sivf.Index(d, nlist, cent, metric=metric, slab_capacity=64, num_slabs=64, id_capacity=64,
+                        max_batch=n, max_queries=64, max_k=16, max_nprobe=8, storage=storage,
+                        rerank_factor=4 if storage else 0)
+        got = ix.assign(x).cpu().numpy()
+        sub = np.concatenate([np.arange(3000), np.arange(n // 3, n // 3 + 8),
+                              rng.choice(n, 2000, replace=False), np.arange(n - 20, n)])
+        np.testing.assert_array_equal(got[sub], oracle.assign(x[sub], cent, metric))
+        say(f"  {n} rows x {nlist} lists (d={d}, storage {storage}): {sub.shape[0]} rows equal the oracle")
+
+
+@pytest.mark.parametrize("metric", [0, 1])
 def test_assign_many_lists_and_extremes(metric):
     """Nearest-list decisions at the serving shape (d=128, 16,384 lists), with
     a ragged last group of lists (4,100 lists), and at magnitudes where fp32
