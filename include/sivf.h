@@ -337,7 +337,8 @@ sivf_status sivf_probe(sivf_index *ix, int64_t nq, const float *q, int32_t nprob
  * device shares it and leaves its contents behind (nothing in it needs to
  * start at zero), so calls that overlap on one device -- on two streams, or
  * from two threads -- race and must not be issued.  nq x nlist floats
- * (nq x ceil(nlist / 16) when nprobe == 1) must fit in 16 MiB and nq may not
+ * (when nprobe == 1: nq x ceil(nlist / 16) for more than 2,048 lists of at
+ * most 128 dimensions, else twice that) must fit in 16 MiB and nq may not
  * exceed max(max_batch, max_queries): larger requests return
  * SIVF_ERR_TOO_LARGE with nothing enqueued.  The calling thread's device may
  * differ from the index's; the kernels run on the stream given.  Allocates

@@ -986,6 +986,13 @@ void launch_coarse_gemm(hipStream_t st, const float *X, int n, int d, const floa
 
 int coarse_groups(int nlist) { return (nlist + GROUP - 1) / GROUP; }
 
+// Scratch words per (row, group) of the nearest-list path: the group minima,
+// plus room for the second-minimum words except in the plain bf16 sweep (more
+// than 16 tiles of lists).
+int coarse_assign_words(int nlist, int dpad) {
+    return (dpad <= HK && (nlist + GN - 1) / GN > 16) ? 1 : 2;
+}
+
 void launch_coarse_assign(hipStream_t st, float *scratch, const float *X, int n, int d, const float *cent,
                           const uint16_t *cent_h, int dpad, const float *cn2, const double *cmax, int nlist, int metric, int32_t *out,
                           int out_stride, const int32_t *ctl, int gated, int bf) {

@@ -239,10 +239,11 @@ void coarse(sivf_index *ix, hipStream_t st, float *dt, const float *x, int64_t n
     // FP32 MFMA: a probe batch is small, and the 64 times tighter bound leaves the exact re-check of
     // nprobe lists few candidates
     const int bf = m == 1 && !m_per_row && mmax == 1;
-    // the nearest-list path keeps two words per group of 16 lists: 8 times the rows fit the scratch
+    // the nearest-list path keeps one or two words per group of 16 lists: 8 or 16 times the rows fit
     const bool assign = m == 1 && !m_per_row && mmax == 1;
-    const int64_t chunk =
-        assign ? (int64_t)ix->L.coarse_rows * S.nlist / (2 * coarse_groups(S.nlist)) : ix->L.coarse_rows;
+    const int64_t chunk = assign ? (int64_t)ix->L.coarse_rows * S.nlist /
+                                       ((int64_t)coarse_assign_words(S.nlist, dpad) * coarse_groups(S.nlist))
+                                 : ix->L.coarse_rows;
     for (int64_t r0 = 0; r0 < n; r0 += chunk) {
         const int nr = (int)((n - r0) < chunk ? (n - r0) : chunk);
         const float *xr = x + r0 * S.d;
@@ -814,7 +815,10 @@ sivf_status sivf_probe_noalloc(sivf_index *ix, int64_t nq, const float *q, int32
     if (ix->broken) return SIVF_ERR_STATE;
     if (nprobe < 1 || nprobe > ix->cfg.max_nprobe) return SIVF_ERR_ARG;
     const int m = nprobe < ix->cfg.nlist ? nprobe : ix->cfg.nlist;
-    const int per_row = (m == 1 && nprobe == 1) ? coarse_groups(ix->cfg.nlist) : ix->cfg.nlist;
+    // nprobe 1 takes the nearest-list path: group minima, and second-minimum words where that path keeps them
+    const int per_row = (m == 1 && nprobe == 1)
+                            ? coarse_groups(ix->cfg.nlist) * coarse_assign_words(ix->cfg.nlist, ix->S.dp4 * 4)
+                            : ix->cfg.nlist;
     if ((size_t)nq * (size_t)per_row > NOALLOC_SCRATCH_FLOATS) return SIVF_ERR_TOO_LARGE;
     const int64_t cap = ix->cfg.max_batch > ix->cfg.max_queries ? ix->cfg.max_batch : ix->cfg.max_queries;
     if (nq > cap) return SIVF_ERR_TOO_LARGE;

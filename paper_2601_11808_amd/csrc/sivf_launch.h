@@ -20,6 +20,7 @@ void launch_coarse_gemm(hipStream_t st, const float *X, int n, int d, const floa
 // m = 1 (nearest list per row): group-minimum GEMM into scratch (n x
 // ceil(nlist / 16) floats), then the exact argmin; rows with a non-finite
 // coordinate get -1.
+int coarse_assign_words(int nlist, int dpad);
 void launch_coarse_assign(hipStream_t st, float *scratch, const float *X, int n, int d, const float *cent,
                           const uint16_t *cent_h, int dpad, const float *cn2, const double *cmax, int nlist, int metric, int32_t *out,
                           int out_stride, const int32_t *ctl, int gated, int bf);

@@ -40,3 +40,15 @@ def test_probe_noalloc_matches_probe(metric):
     q = rng.standard_normal((100, d)).astype(np.float32)
     np.testing.assert_array_equal(big.probe_noalloc(q, 9).cpu().numpy(), big.probe(q, 9).cpu().numpy())
     assert big.sync() == 0
+    # nprobe 1 (the nearest-list path) keeps two words per group of 16 lists at 1,000 lists: 63 groups,
+    # so 33,288 rows fill the 16 MiB; 40,000 rows are refused, 30,000 are served
+    wide = sivf.Index(d, nlist, cent, metric=metric, slab_capacity=64, num_slabs=64, id_capacity=64,
+                      max_batch=40000, max_queries=64, max_k=16, max_nprobe=64)
+    with pytest.raises(sivf.SivfError) as e:
+        wide.probe_noalloc(rng.standard_normal((40000, d)).astype(np.float32), 1)
+    assert e.value.status == sivf.ERR_TOO_LARGE
+    q = rng.standard_normal((30000, d)).astype(np.float32)
+    got = wide.probe_noalloc(q, 1).cpu().numpy()
+    np.testing.assert_array_equal(got, wide.probe(q, 1).cpu().numpy())
+    np.testing.assert_array_equal(got[:300], oracle.probe(q[:300], cent, 1, metric))
+    assert wide.sync() == 0
