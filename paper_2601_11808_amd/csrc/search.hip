@@ -839,6 +839,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
 
     const int nslab = (len + cm) >> cs;
     int wbase = -(1 << 30), wslab = 0;
+    const bool one_slab = cs >= 6 && !(p0 & 63);   // steps never straddle slabs
     for (int base = p0; base < p1; base += 64) {
         const int last_ord = min(base + 63, p1 - 1) >> cs;
         if (last_ord >= wbase + 64) {
@@ -846,30 +847,41 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
             wslab = (wbase + lane < nslab) ? slab_of(S, l, wbase + lane) : 0;
         }
         // the 4 result rows of this lane in row group rg are positions
-        // base + 16 rg + 4 kgrp .. +3: one slab (C >= 4), 16-byte aligned slots
+        // base + 16 rg + 4 kgrp .. +3: one slab (C >= 4), 16-byte aligned slots.
+        // A operands of row group rg: slot 16 rg + qcol, 8-dim chunks 4 kb + kgrp;
+        // two row groups in flight.  Chunks past the row repeat its last chunk
+        // (their B lanes are zero); positions past the item read its last row
+        // and are masked below.
         int64_t g4[4];
+        const uint4 *hr[4];
+        if (one_slab) {
+            // the step's 64 positions lie in one slab: a scalar slab index
+            const int64_t sb = __builtin_amdgcn_readlane(wslab, (base >> cs) - wbase);
 #pragma unroll
-        for (int rg = 0; rg < 4; rg++) {
-            const int p = base + 16 * rg + 4 * kgrp;
-            const int pc = p < p1 ? p : ((p1 - 1) & ~3);
-            g4[rg] = (int64_t)__shfl(wslab, (pc >> cs) - wbase) * C + (pc & cm);
+            for (int rg = 0; rg < 4; rg++) {
+                const int p = base + 16 * rg + 4 * kgrp, pr = base + 16 * rg + qcol;
+                g4[rg] = sb * C + ((p < p1 ? p : ((p1 - 1) & ~3)) & cm);
+                hr[rg] = S.hdata + sb * dp8 * C + ((pr < p1 ? pr : p1 - 1) & cm);
+            }
+        } else {
+#pragma unroll
+            for (int rg = 0; rg < 4; rg++) {
+                const int p = base + 16 * rg + 4 * kgrp;
+                const int pc = p < p1 ? p : ((p1 - 1) & ~3);
+                g4[rg] = (int64_t)__shfl(wslab, (pc >> cs) - wbase) * C + (pc & cm);
+            }
+#pragma unroll
+            for (int rg = 0; rg < 4; rg++) {
+                const int p = base + 16 * rg + qcol;
+                const int pc = p < p1 ? p : p1 - 1;
+                const int slab = __shfl(wslab, (pc >> cs) - wbase);
+                hr[rg] = S.hdata + (int64_t)slab * dp8 * C + (pc & cm);
+            }
         }
         float4 xn4[4] = {};
         if (METRIC == 0) {
 #pragma unroll
             for (int rg = 0; rg < 4; rg++) xn4[rg] = *reinterpret_cast<const float4 *>(S.xnorm + g4[rg]);
-        }
-        // A operands of row group rg: slot 16 rg + qcol, 8-dim chunks 4 kb + kgrp;
-        // two row groups in flight.  Chunks past the row repeat its last chunk
-        // (their B lanes are zero); positions past the item read its last row
-        // and are masked below.
-        const uint4 *hr[4];
-#pragma unroll
-        for (int rg = 0; rg < 4; rg++) {
-            const int p = base + 16 * rg + qcol;
-            const int pc = p < p1 ? p : p1 - 1;
-            const int slab = __shfl(wslab, (pc >> cs) - wbase);
-            hr[rg] = S.hdata + (int64_t)slab * dp8 * C + (pc & cm);
         }
         f32x4_t acc[4];
         uint4 a0[NKB], a1[NKB];
