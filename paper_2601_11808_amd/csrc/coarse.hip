@@ -300,13 +300,12 @@ __device__ __forceinline__ double coarse_err(int metric, int d, int bf, double q
 //
 // MODE GM_PLAIN (more than 16 tiles of lists, where the tracking costs more
 // in this kernel than the re-checks it saves) writes only the group minima.
-// GM_SEG writes out2 as above.  GM_DEC (one segment holds every list): instead
-// of out2, a row whose second
-// smallest Dt exceeds the smallest by more than twice the certified bound
-// (coarse_err with the row's FP64 norm and the largest centroid norm) has its
-// nearest list decided here, with the argmin kernel's test; the others get
-// ASSIGN_UNDECIDED in assign[] and only their group minima for the argmin
-// kernel's re-check.
+// GM_SEG writes out2 as above.  GM_DEC (one segment holds every list) writes
+// no out2: a row whose second smallest Dt exceeds the smallest by more than
+// twice the certified bound (coarse_err with the row's FP64 norm and the
+// largest centroid norm) has its nearest list decided here, with the argmin
+// kernel's test; the others get ASSIGN_UNDECIDED in assign[] and only their
+// group minima for the argmin kernel's re-check.
 constexpr int HK = 128, HBLD = HK + 8;   // halves of a padded row; LDS row stride (halves)
 constexpr int HW = 8, HR = 32 * HW;      // waves per block, rows per block
 constexpr int32_t ASSIGN_UNDECIDED = -2;
@@ -998,7 +997,8 @@ void launch_coarse_assign(hipStream_t st, float *scratch, const float *X, int n,
                           int out_stride, const int32_t *ctl, int gated, int bf) {
     if (n <= 0) return;
     const int ldg = coarse_groups(nlist);
-    // group minima, then the packed second values (2 n ldg words of scratch)
+    // group minima (n ldg words), then the packed second values (at most n ldg words; none in the
+    // plain sweep, see coarse_assign_words)
     uint32_t *gsec = reinterpret_cast<uint32_t *>(scratch + (int64_t)n * ldg);
     bool decided = false;
     int gps = 1;   // groups per segment of gsec
