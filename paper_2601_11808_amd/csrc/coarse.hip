@@ -440,14 +440,26 @@ __global__ __launch_bounds__(64 * HW) void k_coarse_gmin_h(const float *__restri
             for (int j = 0; j < 8; j++) {
                 const float4 c2 = *reinterpret_cast<const float4 *>(&sC[cur][16 * j + 4 * (lane >> 4)]);
                 const float cs[4] = {c2.x, c2.y, c2.z, c2.w};
-                float m1 = __builtin_inff();
+                float v[4];
 #pragma unroll
-                for (int r = 0; r < 4; r++) {
-                    // lists past nlist carry |c|^2 = +inf (IP: masked the same way)
-                    const float v = METRIC == 0 ? fmaf(-2.0f, acc[i][j][r], cs[r])
-                                                : (cs[r] == 0.f ? -acc[i][j][r] : __builtin_inff());
-                    m1 = fminf(m1, v);   // a NaN counts as +inf
-                    if (TRACK) min2_push(b1[i], b2[i], ba[i], v, (t - t0) * GN + 16 * j + 4 * (lane >> 4) + r);
+                for (int r = 0; r < 4; r++)   // lists past nlist carry |c|^2 = +inf (IP: masked the same way)
+                    v[r] = METRIC == 0 ? fmaf(-2.0f, acc[i][j][r], cs[r])
+                                       : (cs[r] == 0.f ? -acc[i][j][r] : __builtin_inff());
+                // smallest (at position qp) and second smallest of the 4 values by a min / max network;
+                // fminf / fmaxf drop a NaN, so a NaN counts as +inf or duplicates a value (never a
+                // smaller second value)
+                const float lo01 = fminf(v[0], v[1]), lo23 = fminf(v[2], v[3]);
+                float m1 = fminf(lo01, lo23);
+                if (TRACK) {
+                    const float hi01 = fmaxf(v[0], v[1]), hi23 = fmaxf(v[2], v[3]);
+                    const bool c23 = lo23 < lo01;
+                    const float qsec = fminf(fmaxf(lo01, lo23), fminf(hi01, hi23));
+                    const int qp = c23 ? (v[3] < v[2] ? 3 : 2) : (v[1] < v[0] ? 1 : 0);
+                    // merge into the running pair: the second smallest of {b1, b2, m1, qsec}
+                    const float nb2 = fminf(fmaxf(b1[i], m1), fminf(b2[i], qsec));
+                    if (m1 < b1[i]) ba[i] = (t - t0) * GN + 16 * j + 4 * (lane >> 4) + qp;
+                    b1[i] = fminf(b1[i], m1);
+                    b2[i] = nb2;
                 }
                 m1 = fminf(m1, __shfl_xor(m1, 16));
                 m1 = fminf(m1, __shfl_xor(m1, 32));
