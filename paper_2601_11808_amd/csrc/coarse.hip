@@ -302,8 +302,8 @@ __device__ __forceinline__ double coarse_err(int metric, int d, int bf, double q
 // in this kernel than the re-checks it saves) writes only the group minima.
 // GM_SEG writes out2 as above.  GM_DEC (one segment holds every list) writes
 // no out2: a row whose second smallest Dt exceeds the smallest by more than
-// twice the certified bound (coarse_err with the row's FP64 norm and the
-// largest centroid norm) has its nearest list decided here, with the argmin
+// twice the certified bound (coarse_err with an upper bound of the row's norm
+// and the largest centroid norm) has its nearest list decided here, with the argmin
 // kernel's test; the others get ASSIGN_UNDECIDED in assign[] and only their
 // group minima for the argmin kernel's re-check.
 constexpr int HK = 128, HBLD = HK + 8;   // halves of a padded row; LDS row stride (halves)
@@ -338,8 +338,6 @@ __global__ __launch_bounds__(64 * HW) void k_coarse_gmin_h(const float *__restri
     // this lane's rows (16 i + lane % 16 of the wave's 32) as bf16 operands, and their |x|^2
     uint4 a[2][4];
     float sq[2];
-    double q2[2] = {0.0, 0.0};   // DEC: FP64 |x|^2 for the bound
-    bool fin[2] = {true, true};
 #pragma unroll
     for (int i = 0; i < 2; i++) {
         const int r = r0 + 32 * w + 16 * i + (lane & 15);
@@ -352,13 +350,6 @@ __global__ __launch_bounds__(64 * HW) void k_coarse_gmin_h(const float *__restri
             for (int e = 0; e < 8; e++) v[e] = (r < n && k + e < d) ? X[(int64_t)r * d + k + e] : 0.f;
 #pragma unroll
             for (int e = 0; e < 8; e++) part = fmaf(v[e], v[e], part);
-            if (DEC) {
-#pragma unroll
-                for (int e = 0; e < 8; e++) {
-                    fin[i] = fin[i] && __builtin_isfinite(v[e]);
-                    q2[i] = __fma_rn((double)v[e], (double)v[e], q2[i]);
-                }
-            }
             a[i][ks] = make_uint4(to_bf16_bits(v[0]) | (to_bf16_bits(v[1]) << 16),
                                   to_bf16_bits(v[2]) | (to_bf16_bits(v[3]) << 16),
                                   to_bf16_bits(v[4]) | (to_bf16_bits(v[5]) << 16),
@@ -498,19 +489,15 @@ __global__ __launch_bounds__(64 * HW) void k_coarse_gmin_h(const float *__restri
         for (int i = 0; i < 2; i++) {
             min2_xor<16>(b1[i], b2[i], ba[i]);
             min2_xor<32>(b1[i], b2[i], ba[i]);
-            double q = q2[i];
-            q += __shfl_xor(q, 16);
-            q += __shfl_xor(q, 32);
-            int fi = fin[i] ? 1 : 0;
-            fi &= __shfl_xor(fi, 16);
-            fi &= __shfl_xor(fi, 32);
-            const bool f = fi != 0;
             const int gr = r0 + 32 * w + 16 * i + (lane & 15);
             if ((lane >> 4) == 0 && gr < n) {
-                const double qn = sqrt(q) * (1.0 + 0x1p-50);
+                // an upper bound on |x| from the fp32 sum of squares (d + 2 roundings of at most 2^-24
+                // relative each; the additive term covers squares flushed to zero); a non-finite
+                // coordinate makes it inf or NaN, and the row is left undecided
+                const double qn = sqrt((double)sq[i] * (1.0 + (d + 4) * 0x1p-23)) * (1.0 + 0x1p-50) + 0x1p-56;
                 const double e = coarse_err(METRIC, d, 1, qn, cm);
                 const float d1 = METRIC == 0 ? sq[i] + b1[i] : b1[i], d2 = METRIC == 0 ? sq[i] + b2[i] : b2[i];
-                const bool ok = f && qn + cm < 0x1p60 && (double)d2 - e > (double)d1 + e && ba[i] < nlist;
+                const bool ok = qn + cm < 0x1p60 && (double)d2 - e > (double)d1 + e && ba[i] < nlist;
                 assign[(int64_t)gr * assign_stride] = ok ? ba[i] : ASSIGN_UNDECIDED;
             }
         }
