@@ -794,7 +794,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
                                                   const int32_t *__restrict__ list_pairs,
                                                   const float *__restrict__ q, int np_stride, int kcap, int k,
                                                   int kmul, const int32_t *__restrict__ kpq,
-                                                  uint64_t *__restrict__ partials) {
+                                                  uint64_t *__restrict__ partials, uint32_t *__restrict__ gthr) {
     __shared__ uint64_t buf[MQ * MBUF];
     __shared__ int scnt[MQ], skq[MQ];
     const int lane = threadIdx.x, qcol = lane & 15, kgrp = lane >> 4;
@@ -808,7 +808,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
         scnt[lane] = 0;
     }
     // B operand: query qcol, dims 32 kb + 8 kgrp .. +8, rounded like the slabs
-    const float *qr = q + (int64_t)(pairs[qcol < nt ? qcol : 0] / np_stride) * d;
+    const int qg = pairs[qcol < nt ? qcol : 0] / np_stride;   // query of column qcol
+    const float *qr = q + (int64_t)qg * d;
     uint4 bq[NKB];
     float qn = 0.f;
 #pragma unroll
@@ -878,6 +879,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
                 hr[rg] = S.hdata + (int64_t)slab * dp8 * C + (pc & cm);
             }
         }
+        // the best R k-th key any work item has published for this query: a candidate behind it cannot
+        // enter the query's final list (those R k keys are real candidates), so it tightens the filter
+        const uint32_t pub = live ? __hip_atomic_load(gthr + qg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : ~0u;
         float4 xn4[4] = {};
         if (METRIC == 0) {
 #pragma unroll
@@ -903,6 +907,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
         load_a(a1, hr[3]);
         acc[2] = mma(a0);
         acc[3] = mma(a1);
+        if (pub < thr) {
+            thr = pub;
+            thr_f = METRIC == 0 ? from_ord(thr) : from_ord(~thr);
+        }
         float vv[16];
         uint32_t pmask = 0;
 #pragma unroll
@@ -960,6 +968,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
                 for (int t = 0; t < MQ; t++) {
                     if ((fm >> t) & 1ull) {
                         const uint32_t nthr = mfma_flush<MQ>(top, t, buf, scnt[t], skq[t], kcap);
+                        // publish a full list's R k-th key for the query's other work items
+                        if (lane == 0 && nthr != 0xFFFFFFFFu)
+                            __hip_atomic_fetch_min(gthr + __builtin_amdgcn_readlane(qg, t), nthr, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
                         if (qcol == t) {
                             thr = nthr;
                             thr_f = METRIC == 0 ? from_ord(thr) : from_ord(~thr);
@@ -1489,10 +1501,11 @@ void launch_search_scan_mfma(hipStream_t st, const Dev &S, const SearchBufs &W, 
     const int npairs = nq * np_stride;
     // k-blocks of 32 dimensions held as B operands: 2, 3, 4 or 8 (d <= 256)
     const int nkb = (S.d + 31) / 32;
+    launch_fill_i32(st, reinterpret_cast<int32_t *>(W.gthr), nq, -1);   // no key published yet
 #define SIVF_LAUNCH_MFMA_P(M, D, K, P)                                                                       \
     hipLaunchKernelGGL((k_scan_mfma<M, D, K, P>), dim3(scan_grid(k_scan_mfma<M, D, K, P>, S, W, npairs, 0)),    \
                        dim3(64), 0, st, S, W.item_list, W.item_tile, W.item_chunk, W.list_pairs, q, np_stride,  \
-                       kcap, k, kmul, k_per_query, W.partials)
+                       kcap, k, kmul, k_per_query, W.partials, W.gthr)
 #define SIVF_LAUNCH_MFMA(M, D, K)                                                                            \
     do {                                                                                                     \
         if (S.persistent) SIVF_LAUNCH_MFMA_P(M, D, K, true);                                                 \
