@@ -968,10 +968,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
                 for (int t = 0; t < MQ; t++) {
                     if ((fm >> t) & 1ull) {
                         const uint32_t nthr = mfma_flush<MQ>(top, t, buf, scnt[t], skq[t], kcap);
-                        // publish a full list's R k-th key for the query's other work items
+                        // publish a full list's R k-th key for the query's other work items (the query
+                        // index is read while the whole wave is active)
+                        const int qt = __builtin_amdgcn_readlane(qg, t);
                         if (lane == 0 && nthr != 0xFFFFFFFFu)
-                            __hip_atomic_fetch_min(gthr + __builtin_amdgcn_readlane(qg, t), nthr, __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_AGENT);
+                            __hip_atomic_fetch_min(gthr + qt, nthr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         if (qcol == t) {
                             thr = nthr;
                             thr_f = METRIC == 0 ? from_ord(thr) : from_ord(~thr);
@@ -1123,7 +1124,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
                                                   const int32_t *__restrict__ list_pairs,
                                                   const float *__restrict__ q, int np_stride, int kcap, int k,
                                                   const int32_t *__restrict__ kpq,
-                                                  uint64_t *__restrict__ partials) {
+                                                  uint64_t *__restrict__ partials, uint32_t *__restrict__ gthr) {
     extern __shared__ float4 sqr[];    // the tile's 16 query rows, zero-padded to dp4 chunks, stride dp4 + 1
     __shared__ uint32_t pq[64 * MQ + 64];   // queued passing pairs: window position << 4 | query
     __shared__ int skq[MQ];
@@ -1154,6 +1155,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
         sqr[t * qs + (j >> 2)] = v;
     }
     __syncthreads();
+    const int qg = pairs[qcol < nt ? qcol : 0] / np_stride;   // query of column qcol
     float qn2 = 0.f;   // |q|^2 of query qcol
 #pragma unroll
     for (int b = 0; b < NB; b++) {
@@ -1221,6 +1223,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
                 xr[rg] = S.data + (int64_t)slab * dp4 * C + (pc & cm);
             }
         }
+        // the best k-th key value any work item has published for this query: a pair behind it cannot
+        // enter the query's final k (those k keys are real candidates), so it serves as the threshold
+        const uint32_t pub = live ? __hip_atomic_load(gthr + qg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : ~0u;
         float4 xn4[4];
 #pragma unroll
         for (int rg = 0; rg < 4; rg++) xn4[rg] = *reinterpret_cast<const float4 *>(S.xnorm + g4[rg]);
@@ -1248,6 +1253,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
                 vv[4 * rg + j] = METRIC == 0 ? fmaf(-2.f, acc[rg][j], sq) : -acc[rg][j];
                 ee[4 * rg + j] = fmaf(e1, sq, e0);
             }
+        }
+        if (pub < thr) {
+            thr = pub;
+            thr_f = METRIC == 0 ? from_ord(thr) : from_ord(~thr);
         }
         // the query's k-th best value so far in distance space (NaN: none yet, all pass)
         float thd = METRIC == 0 ? thr_f : -thr_f;
@@ -1373,6 +1382,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
                         } else {
                             nthr = kq > 0 ? (uint32_t)(readlane_u64(top[t2 / QPR], KC * (t2 % QPR) + kq - 1) >> 32) : 0u;
                         }
+                        // publish a full list's k-th key value for the query's other work items (the
+                        // query index is read while the whole wave is active)
+                        const int qt = __builtin_amdgcn_readlane(qg, t2);
+                        if (lane == 0 && nthr != 0xFFFFFFFFu)
+                            __hip_atomic_fetch_min(gthr + qt, nthr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         if (qcol == t2) {
                             thr = nthr;
                             thr_f = METRIC == 0 ? from_ord(thr) : from_ord(~thr);
@@ -1587,7 +1601,7 @@ static void launch_cert_nb(hipStream_t st, const Dev &S, const SearchBufs &W, co
 #define SIVF_LAUNCH_CERT(P)                                                                                  \
     hipLaunchKernelGGL((k_scan_cert<METRIC, NB, P, KC>), dim3(scan_grid(k_scan_cert<METRIC, NB, P, KC>, S, W, npairs, smem)), \
                        dim3(64), smem, st, S, W.item_list, W.item_tile, W.item_chunk, W.list_pairs, q, np_stride, \
-                       kcap, k, kpq, W.partials)
+                       kcap, k, kpq, W.partials, W.gthr)
     if (S.persistent) SIVF_LAUNCH_CERT(true);
     else SIVF_LAUNCH_CERT(false);
 #undef SIVF_LAUNCH_CERT
@@ -1600,6 +1614,7 @@ static void launch_cert(hipStream_t st, const Dev &S, const SearchBufs &W, const
     // sorted lists of 16 keys (kcap 16: four queries per register), 64 (kcap 32, 64) or
     // 128 (kcap 128: ranks 64..127 in the partial slot)
     const int nb = (S.d + 15) / 16;
+    launch_fill_i32(st, reinterpret_cast<int32_t *>(W.gthr), npairs / np_stride, -1);   // no key published yet
 #define SIVF_CERT_NB(KC)                                                                                     \
     do {                                                                                                     \
         if (nb <= 2) launch_cert_nb<METRIC, 2, KC>(st, S, W, q, np_stride, kcap, k, kpq, npairs);            \

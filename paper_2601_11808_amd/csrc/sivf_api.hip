@@ -122,7 +122,7 @@ Layout make_layout(const sivf_config *c) {
     L.xnorm = take((reduced && c->metric == SIVF_L2) || !reduced ? (size_t)ns * C * 4 : 0);
     L.rr_dist = take(reduced ? (size_t)c->max_queries * L.kcap * 4 : 0);
     L.rr_lab = take(reduced ? (size_t)c->max_queries * L.kcap * 8 : 0);
-    L.gthr = take(reduced ? (size_t)c->max_queries * 4 : 0);
+    L.gthr = take((size_t)c->max_queries * 4);   // per-query shared thresholds of the MFMA scans
     // serving: one coalesced search batch (query rows, per-row k and nprobe,
     // results at stride max_k, one segment per request)
     L.srv_q = take((size_t)c->max_queries * c->dim * 4);
@@ -426,7 +426,7 @@ sivf_status sivf_create(const sivf_config *cfg, const float *centroids, void *wo
     S.xnorm = (cfg->storage == SIVF_F32 || cfg->metric == SIVF_L2) ? (float *)(w + L.xnorm) : nullptr;
     ix->W.rr_dist = cfg->storage != SIVF_F32 ? (float *)(w + L.rr_dist) : nullptr;
     ix->W.rr_lab = cfg->storage != SIVF_F32 ? (int64_t *)(w + L.rr_lab) : nullptr;
-    ix->W.gthr = cfg->storage != SIVF_F32 ? (uint32_t *)(w + L.gthr) : nullptr;
+    ix->W.gthr = (uint32_t *)(w + L.gthr);
     S.num_slabs = cfg->num_slabs;
     S.num_pages = L.num_pages;
     S.dir_cap = L.dir_cap;

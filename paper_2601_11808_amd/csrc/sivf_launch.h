@@ -75,7 +75,7 @@ struct SearchBufs {
     int64_t item_cap;    // entries of item_list / item_tile / item_chunk
     float *rr_dist;      // reduced precision: approximate candidates per query
     int64_t *rr_lab;
-    uint32_t *gthr;      // reduced precision: per query, the best published R k-th key (high word)
+    uint32_t *gthr;      // MFMA scans: per query, the best published k-th (R k-th) key's high word
 };
 // One pass of a search over the queries whose k, clamped to [0, k], lies in
 // (lo, hi]: its plan, scan and merge skip the other queries.  A search whose
