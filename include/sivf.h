@@ -183,7 +183,7 @@ sivf_status sivf_set_search_schedule(sivf_index *ix, int32_t tile, int32_t chunk
  * schedule (tile 4 or 8: the VALU scan; 16: the certified scan with 128-key
  * lists); without per-query k every query takes the second.  Arguments and
  * errors as sivf_set_search_schedule (SIVF_ERR_ARG on reduced-precision
- * indexes too); default 4 queries x 2^13 positions, resident waves.  Set by
+ * indexes too); default 16 queries x 2^14 positions, resident waves.  Set by
  * sivf_tune_search as well.  Results do not depend on it. */
 sivf_status sivf_set_deep_schedule(sivf_index *ix, int32_t tile, int32_t chunk_shift, int32_t persistent);
 

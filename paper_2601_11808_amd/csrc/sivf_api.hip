@@ -164,8 +164,9 @@ struct sivf_index {
     bool broken = false;
     bool prof = false;
     ProfClass pc[SIVF_PROF_KINDS];
-    // schedule of the k > 64 pass of a certified-scan search (tile, chunk shift, persistent)
-    int deep_tile = 4, deep_shift = 13, deep_pers = 1;
+    // schedule of the k > 64 pass of a certified-scan search (tile, chunk shift, persistent): by
+    // default the certified scan with 128-key lists
+    int deep_tile = 16, deep_shift = 14, deep_pers = 1;
     // host tier (slabs == 0: none): V views the cold pool; its rows and ids sit in
     // caller-provided pinned host memory, the rest in a caller-provided device buffer
     struct {
