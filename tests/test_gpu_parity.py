@@ -87,7 +87,9 @@ def _tie_data(seed, d, nlist, n):
 def test_assign_and_probe_exact(metric):
     """Coarse decisions equal the oracle's (FP64 canonical distance, ties to
     the smaller list id) on inputs full of near-ties and exact ties."""
-    for d, nlist in [(16, 64), (128, 1024), (7, 13)]:
+    # one-wave selection with 32 (up to 2,048 lists) and 64 (up to 4,096) distances per lane; 4,100 lists
+    # take the block selection
+    for d, nlist in [(16, 64), (128, 1024), (7, 13), (24, 3000), (40, 4096), (20, 4100)]:
         cent, x = _tie_data(d * 1000 + nlist, d, nlist, 6000)
         p = Pair(d, nlist, cent, metric=metric, max_batch=8192, max_nprobe=64)
         ga = p.gpu.assign(x).cpu().numpy()
