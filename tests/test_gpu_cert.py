@@ -172,6 +172,39 @@ def test_cert_scan_k128_split_lists(metric):
     say("  k = 100/128 certified scan: identical to the VALU scan and the oracle on split lists")
 
 
+@pytest.mark.parametrize("metric", [0, 1])
+def test_cert_ties_across_work_items(metric):
+    """Equal keys spread over every chunk of a split list: 300 distinct integer
+    rows, each stored 80 times at random positions under random ids, so a
+    query's k-th distance is shared by dozens of rows in different work items.
+    A work item may take another item's published k-th value as its threshold;
+    rows equal to it must still pass, so the k smallest ids of the tied rows
+    come out (the oracle's order), for k up to 64 and above 64, split and
+    whole-list schedules."""
+    rng = np.random.default_rng([81, metric])
+    d = 24
+    base = np.concatenate([rng.integers(-2, 3, (200, d)), 3 + rng.integers(-1, 2, (100, d))]).astype(np.float32)
+    x = np.repeat(base, 80, axis=0)[rng.permutation(base.shape[0] * 80)]
+    ids = rng.permutation(x.shape[0]).astype(np.int64)
+    cent = np.stack([np.zeros(d), np.full(d, 3.0), np.full(d, -3.0)]).astype(np.float32)
+    q = np.concatenate([rng.integers(-2, 4, (100, d)).astype(np.float32), base[rng.integers(0, 300, 50)]])
+    ix = sivf.Index(d, 3, cent, metric=metric, slab_capacity=64, num_slabs=420, id_capacity=x.shape[0],
+                    max_batch=1 << 15, max_queries=q.shape[0], max_k=128, max_nprobe=3)
+    ref = oracle.OracleIndex(d, 3, cent, metric, 64, 420, x.shape[0])
+    ix.add(x, ids)
+    assert ix.sync() == 0
+    assert ref.add(x, ids) == 0
+    for k, nprobe in [(10, 1), (64, 3), (100, 2), (128, 3)]:
+        st, rd, rl = ref.search(q, k, nprobe)
+        assert st == 0
+        for sched in [(16, 10, 0), (16, 10, 1), (16, 17, 0)]:
+            if k > 64:
+                ix.set_deep_schedule(*sched)
+            gd, gl = _both(ix, q, k, nprobe, sched=sched)
+            compare_results(gd, gl, rd, rl)
+    say(f"  metric={metric}: tied keys across work items resolved as the oracle does")
+
+
 @pytest.mark.parametrize("deep", [(4, 12, 1), (8, 10, 0), (16, 13, 1), (16, 11, 0)])
 def test_cert_two_pass_mixed_k(deep):
     """A certified-scan search whose per-query k straddles 64 runs two passes
